@@ -1,0 +1,375 @@
+"""Plain FP64 CPU oracle for DEANN's query path.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, obviously correct
+definition that the HIP path is checked against.  Only the test suite, the
+smoke check and the benchmark's CPU-baseline leg may import it; the product
+path never does, and it shares no code with the HIP library (the two meet only
+in the seeded inputs of the ``synth`` package).
+
+Everything is float64 NumPy with element-wise operations only (no BLAS GEMM),
+single-threaded.  Inputs are the float32 bytes the GPU receives, upcast
+exactly to float64.
+
+Paper: Karppa, Aumueller, Pagh, "DEANN: Speeding up Kernel-Density Estimation
+using Approximate Nearest Neighbor Search" (arXiv 2107.02736).
+
+Parity status of each function (what pins it in tests/test_oracle_*.py):
+  sq_dists, kernel_values, kde_exact  pinned: n=1 closed form, power-law
+      construction of Lemma 4 (exact values), h -> inf limit, KDE in [0,1],
+      exact rational brute force on tiny inputs, GEMM identity of App. F.
+  knn        pinned: exact rational brute force (fractions) incl. exact ties.
+  philox4x64_10  pinned: numpy's independent Philox4x64-10 and the SC'11 zero
+      known-answer vector.
+  sample_indices pinned: exhaustive rank->index enumeration on tiny n,
+      chi-square uniformity over X minus NN, no draw inside NN.
+  deann_estimate pinned: k=n gives kde_exact, unbiasedness over many seeds,
+      variance formula of random sampling with repetition, Bernoulli worst
+      case of App. D.
+  kde_grad / deann_grad pinned: central finite differences, n=1 closed form.
+  mean_shift pinned: n=1 lands on the point in one step; density never
+      decreases along exact Gaussian mean-shift steps.
+  bisect_h   pinned: monotonicity of KDE in h and the target tolerance.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+GAUSSIAN = 0
+EXPONENTIAL = 1
+
+_ROW_CHUNK = 1 << 15
+_U64 = (1 << 64) - 1
+
+
+# --------------------------------------------------------------------------
+# Distances and kernels (Eq. (1), Eq. (2), the exponential kernel of Sec. 1)
+# --------------------------------------------------------------------------
+
+def sq_dists(X: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Squared Euclidean distances ||x_i - y||^2 for every row of X, in FP64.
+
+    Direct differences (not the GEMM identity of App. F), row chunks to bound
+    memory.
+    """
+    y64 = np.asarray(y, dtype=np.float64)
+    out = np.empty(X.shape[0], dtype=np.float64)
+    for r0 in range(0, X.shape[0], _ROW_CHUNK):
+        diff = X[r0:r0 + _ROW_CHUNK].astype(np.float64) - y64
+        out[r0:r0 + _ROW_CHUNK] = np.einsum("ij,ij->i", diff, diff, optimize=False)
+    return out
+
+
+def kernel_values(d2: np.ndarray, h: float, kernel: int) -> np.ndarray:
+    """K_h as a function of the squared distance.
+
+    Gaussian (Eq. (2)): exp(-d^2 / (2 h^2)).  Exponential (Sec. 1):
+    exp(-d / h).  Both are unnormalised, so every value lies in [0, 1].
+    """
+    d2 = np.maximum(np.asarray(d2, dtype=np.float64), 0.0)
+    if kernel == GAUSSIAN:
+        return np.exp(-d2 / (2.0 * h * h))
+    if kernel == EXPONENTIAL:
+        return np.exp(-np.sqrt(d2) / h)
+    raise ValueError("unknown kernel")
+
+
+def kde_exact(X: np.ndarray, Y: np.ndarray, h: float, kernel: int) -> np.ndarray:
+    """Exact KDE of Eq. (1) for every query row: (1/n) sum_i K_h(x_i, y).
+
+    The sum over i is math.fsum (correctly rounded), so the only rounding left
+    is that of each distance and kernel value.
+    """
+    n = X.shape[0]
+    Y = np.atleast_2d(Y)
+    out = np.empty(Y.shape[0], dtype=np.float64)
+    for j in range(Y.shape[0]):
+        out[j] = math.fsum(kernel_values(sq_dists(X, Y[j]), h, kernel)) / n
+    return out
+
+
+# --------------------------------------------------------------------------
+# Exact k nearest neighbours (the black-box ANN of Algorithm 1, made exact)
+# --------------------------------------------------------------------------
+
+def _exact_sq_dist(x_row: np.ndarray, y: np.ndarray) -> Fraction:
+    """||x - y||^2 as an exact rational (every float32 value is dyadic)."""
+    s = Fraction(0)
+    for a, b in zip(x_row.tolist(), y.tolist()):
+        t = Fraction(a) - Fraction(b)
+        s += t * t
+    return s
+
+
+def knn(X: np.ndarray, y: np.ndarray, k: int) -> np.ndarray:
+    """Indices of the k nearest rows of X to y, sorted ascending by index.
+
+    The order is the lexicographic key (exact real ||x_i - y||^2, i): the
+    sequence of points sorted by distance (Sec. 2) with ties broken towards
+    the lower index.  Ranking is done in FP64; wherever the FP64 values near
+    the k-th place are too close for FP64 rounding to decide, those points
+    are compared again with exact rational arithmetic.
+    """
+    n, d = X.shape
+    if k <= 0:
+        return np.empty(0, dtype=np.int64)
+    if k >= n:
+        return np.arange(n, dtype=np.int64)
+    d2 = sq_dists(X, y)
+    order = np.lexsort((np.arange(n), d2))
+    dk = d2[order[k - 1]]
+    # Relative error of an FP64 sum of d squared differences (each difference
+    # of two float32 values is exact in FP64 within this range of magnitudes).
+    rel = 4.0 * (d + 2) * 2.0 ** -53
+    lo, hi = dk * (1.0 - rel), dk * (1.0 + rel)
+    if dk == 0.0:
+        lo, hi = -1.0, 0.0
+    sure = d2 < lo
+    band = np.nonzero((d2 >= lo) & (d2 <= hi))[0]
+    n_sure = int(sure.sum())
+    need = k - n_sure
+    if need == len(band):
+        chosen = band
+    else:
+        keyed = sorted(band.tolist(), key=lambda i: (_exact_sq_dist(X[i], y), i))
+        chosen = np.asarray(keyed[:need], dtype=np.int64)
+    res = np.concatenate([np.nonzero(sure)[0], chosen]).astype(np.int64)
+    res.sort()
+    assert res.size == k
+    return res
+
+
+# --------------------------------------------------------------------------
+# Counter-based random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw,
+# "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11)
+# --------------------------------------------------------------------------
+
+_PHILOX_M0 = 0xD2E7470EE14C6C93
+_PHILOX_M1 = 0xCA5A826395121157
+_PHILOX_W0 = 0x9E3779B97F4A7C15   # golden ratio
+_PHILOX_W1 = 0xBB67AE8584CAA73B   # sqrt(3) - 1
+
+
+def philox4x64_10(key: tuple[int, int], counter: tuple[int, int, int, int]) -> list[int]:
+    """One 4x64-bit Philox block with 10 rounds, in Python integers."""
+    k0, k1 = key[0] & _U64, key[1] & _U64
+    c0, c1, c2, c3 = (c & _U64 for c in counter)
+    for rnd in range(10):
+        if rnd:
+            k0 = (k0 + _PHILOX_W0) & _U64
+            k1 = (k1 + _PHILOX_W1) & _U64
+        p0 = _PHILOX_M0 * c0
+        p1 = _PHILOX_M1 * c2
+        c0, c1, c2, c3 = ((p1 >> 64) ^ c1 ^ k0, p1 & _U64, (p0 >> 64) ^ c3 ^ k1, p0 & _U64)
+    return [c0, c1, c2, c3]
+
+
+def sample_indices(n: int, nn_sorted: np.ndarray, m: int, seed: int, stream: int,
+                   word2: int = 0) -> np.ndarray:
+    """The m uniform draws, with repetition, from X2 = [n] minus NN (Algorithm 1).
+
+    Draw j uses u = word (j mod 4) of Philox4x64-10 with key (seed, 0) and
+    counter (j div 4, stream, word2, 0); the rank r = floor(u (n-k) / 2^64)
+    (multiply-shift, no rejection) selects the r-th smallest element of X2.
+    With NN sorted e_0 < ... < e_{k-1}, that element is r + #{t : e_t - t <= r}.
+    Returns int64 indices in draw order; all -1 when X2 is empty.
+    """
+    k = len(nn_sorted)
+    size2 = n - k
+    if m <= 0:
+        return np.empty(0, dtype=np.int64)
+    if size2 <= 0:
+        return np.full(m, -1, dtype=np.int64)
+    out = np.empty(m, dtype=np.int64)
+    block = None
+    for j in range(m):
+        if j % 4 == 0:
+            block = philox4x64_10((seed, 0), (j // 4, stream, word2, 0))
+        u = block[j % 4]
+        r = (u * size2) >> 64
+        out[j] = rank_to_index(nn_sorted, r)
+    return out
+
+
+def rank_to_index(nn_sorted, r: int) -> int:
+    """The r-th smallest (0-based) element of [n] minus the sorted set NN.
+
+    e_t - t counts the elements of X2 below e_t, so e_t lies below the answer
+    exactly when e_t - t <= r.
+    """
+    below = sum(1 for t, e in enumerate(nn_sorted) if int(e) - t <= r)
+    return r + below
+
+
+# --------------------------------------------------------------------------
+# DEANN estimate (Algorithm 1) and its extremes
+# --------------------------------------------------------------------------
+
+def deann_estimate(X: np.ndarray, y: np.ndarray, h: float, kernel: int, k: int, m: int,
+                   seed: int, stream: int, word2: int = 0, nn: np.ndarray | None = None):
+    """DEANN for one query.  Returns (estimate, nn_sorted, sample_idx).
+
+    X1 = the k nearest rows (exact k-NN unless ``nn`` is given), X2 = the rest,
+    Z1 = sum over X1 of K, S = m draws from X2, Z2 = sum over S of K, and the
+    estimate (k/n)(Z1/k) + ((n-k)/n)(Z2/m) written as (Z1 + ((n-k)/m) Z2)/n so
+    that k = 0 (plain random sampling) and m = 0 (far points dropped) need no
+    special case.  When k = n the estimate is the exact KDE and no draw is made.
+    """
+    n = X.shape[0]
+    if nn is None:
+        nn = knn(X, y, k)
+    nn = np.sort(np.asarray(nn, dtype=np.int64))
+    k = len(nn)
+    s_idx = sample_indices(n, nn, m, seed, stream, word2)
+    z1 = math.fsum(kernel_values(sq_dists(X[nn], y), h, kernel)) if k else 0.0
+    if m > 0 and n - k > 0:
+        z2 = math.fsum(kernel_values(sq_dists(X[s_idx], y), h, kernel))
+        est = (z1 + (n - k) / m * z2) / n
+    else:
+        est = z1 / n
+    return est, nn, s_idx
+
+
+# --------------------------------------------------------------------------
+# Gradients (derived from Eq. (1)-(2); the paper gives none)
+# --------------------------------------------------------------------------
+
+def _kernel_and_grads(Xs: np.ndarray, y: np.ndarray, h: float, kernel: int):
+    """K, dK/dy (rows) and dK/dh for the rows Xs against y, all FP64."""
+    y64 = np.asarray(y, dtype=np.float64)
+    diff = Xs.astype(np.float64) - y64            # x - y
+    d2 = np.einsum("ij,ij->i", diff, diff, optimize=False)
+    K = kernel_values(d2, h, kernel)
+    if kernel == GAUSSIAN:
+        w = K / (h * h)                           # dK/dy = K (x - y) / h^2
+        dh = K * d2 / h ** 3                      # dK/dh = K d^2 / h^3
+    else:
+        r = np.sqrt(d2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            w = np.where(r > 0.0, K / (h * r), 0.0)   # dK/dy = K (x - y) / (h r), 0 at r = 0
+        dh = K * r / (h * h)                      # dK/dh = K r / h^2
+    return K, w[:, None] * diff, dh
+
+
+def kde_grad(X: np.ndarray, y: np.ndarray, h: float, kernel: int):
+    """(KDE, dKDE/dy [d], dKDE/dh) of Eq. (1) for one query, summing all n rows."""
+    n, d = X.shape
+    gy = np.zeros(d, dtype=np.float64)
+    val, gh = [], []
+    for r0 in range(0, n, _ROW_CHUNK):
+        K, gK, dh = _kernel_and_grads(X[r0:r0 + _ROW_CHUNK], y, h, kernel)
+        val.append(K)
+        gh.append(dh)
+        gy += gK.sum(axis=0)
+    return (math.fsum(np.concatenate(val)) / n, gy / n, math.fsum(np.concatenate(gh)) / n)
+
+
+def deann_grad(X: np.ndarray, y: np.ndarray, h: float, kernel: int, nn: np.ndarray,
+               s_idx: np.ndarray, m: int):
+    """(estimate, d/dy, d/dh) of the DEANN estimate with the index sets held fixed.
+
+    The selected sets are piecewise constant in y and h, so this is the
+    derivative almost everywhere: the weights of Algorithm 1 (1 for X1,
+    (n-k)/m for each draw) times the kernel derivatives.
+    """
+    n = X.shape[0]
+    nn = np.asarray(nn, dtype=np.int64)
+    k = len(nn)
+    d = X.shape[1]
+    K1, g1, h1 = _kernel_and_grads(X[nn], y, h, kernel) if k else (
+        np.zeros(0), np.zeros((0, d)), np.zeros(0))
+    est, gy, gh = math.fsum(K1), g1.sum(axis=0), math.fsum(h1)
+    if m > 0 and n - k > 0:
+        c = (n - k) / m
+        K2, g2, h2 = _kernel_and_grads(X[np.asarray(s_idx, dtype=np.int64)], y, h, kernel)
+        est += c * math.fsum(K2)
+        gy = gy + c * g2.sum(axis=0)
+        gh += c * math.fsum(h2)
+    return est / n, gy / n, gh / n
+
+
+# --------------------------------------------------------------------------
+# Mean shift (an application of density gradients, Sec. 1) and bandwidth
+# selection by bisection (Sec. 5, "Bandwidth selection")
+# --------------------------------------------------------------------------
+
+def mean_shift_exact(X: np.ndarray, y: np.ndarray, h: float, steps: int) -> np.ndarray:
+    """Gaussian-kernel mean shift: y <- sum_i K_i x_i / sum_i K_i, repeated.
+
+    The point is kept in float32 between steps, as a query array would be.
+    """
+    y = np.asarray(y, dtype=np.float32).astype(np.float64)
+    for _ in range(steps):
+        num = np.zeros_like(y)
+        den = []
+        for r0 in range(0, X.shape[0], _ROW_CHUNK):
+            Xs = X[r0:r0 + _ROW_CHUNK].astype(np.float64)
+            diff = Xs - y
+            K = kernel_values(np.einsum("ij,ij->i", diff, diff, optimize=False), h, GAUSSIAN)
+            num += (K[:, None] * Xs).sum(axis=0)
+            den.append(K)
+        y = (num / math.fsum(np.concatenate(den))).astype(np.float32).astype(np.float64)
+    return y
+
+
+def mean_shift_deann(X: np.ndarray, y: np.ndarray, h: float, k: int, m: int, seed: int,
+                     stream: int, steps: int) -> np.ndarray:
+    """Mean shift with DEANN weights: NN rows weigh 1, each draw (n-k)/m.
+
+    Step t re-selects the k-NN of the current point and draws with counter
+    word 2 equal to t.  The point is kept in float32 between steps.
+    """
+    n = X.shape[0]
+    y = np.asarray(y, dtype=np.float32).astype(np.float64)
+    for t in range(steps):
+        y32 = y.astype(np.float32)
+        nn = knn(X, y32, k)
+        s_idx = sample_indices(n, nn, m, seed, stream, word2=t)
+        rows = [X[nn].astype(np.float64)]
+        wts = [np.ones(len(nn))]
+        if m > 0 and n - len(nn) > 0:
+            rows.append(X[s_idx].astype(np.float64))
+            wts.append(np.full(m, (n - len(nn)) / m))
+        R = np.concatenate(rows)
+        W = np.concatenate(wts)
+        diff = R - y32.astype(np.float64)
+        K = kernel_values(np.einsum("ij,ij->i", diff, diff, optimize=False), h, GAUSSIAN) * W
+        y = ((K[:, None] * R).sum(axis=0) / math.fsum(K)).astype(np.float32).astype(np.float64)
+    return y
+
+
+def pairwise_sq_dists(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """All squared distances [q, n] in FP64 (for bisection over a fixed query set)."""
+    Y = np.atleast_2d(Y)
+    return np.stack([sq_dists(X, y) for y in Y])
+
+
+def bisect_h(D2: np.ndarray, target: float, kernel: int, stat: str = "mean",
+             rel_tol: float = 0.01, max_iter: int = 200) -> float:
+    """Bandwidth h whose mean (or median) exact KDE over the queries is within
+    ``rel_tol`` relative of ``target``, by bisection on log h.
+
+    D2 holds the FP64 squared distances [q, n] of the query set.  The KDE is
+    non-decreasing in h for a radially decreasing kernel, which the bisection
+    relies on.
+    """
+    agg = np.mean if stat == "mean" else np.median
+
+    def value(h):
+        # a 1% target needs no correctly rounded sum: numpy's pairwise sum
+        return float(agg([kernel_values(row, h, kernel).sum() / row.size for row in D2]))
+
+    lo, hi = -20.0, 20.0
+    for _ in range(max_iter):
+        mid = 0.5 * (lo + hi)
+        h = math.exp(mid)
+        v = value(h)
+        if abs(v - target) <= rel_tol * target:
+            return h
+        if v < target:
+            lo = mid
+        else:
+            hi = mid
+    raise RuntimeError("bisection did not converge")

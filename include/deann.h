@@ -1,0 +1,135 @@
+/*
+ * deann.h - C ABI of the DEANN query path on one AMD Instinct MI355X (gfx950).
+ *
+ * Paper: M. Karppa, M. Aumueller, R. Pagh, "DEANN: Speeding up Kernel-Density
+ * Estimation using Approximate Nearest Neighbor Search", arXiv 2107.02736.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer, row-major and contiguous, owned
+ *    by the caller.  The library never frees, keeps or modifies X and Y.
+ *  - X[n, d] is the dataset, Y[q, d] the queries, both float32.
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL for the
+ *    default stream) and is asynchronous: outputs are valid once the stream has
+ *    been synchronised.  No call synchronises the stream.
+ *  - Scratch memory is supplied by the caller through (ws, ws_bytes); query the
+ *    required size with the matching *_workspace function.  Its contents on
+ *    entry are irrelevant.
+ *  - Arguments are validated on the host before anything is launched; a
+ *    violation returns DEANN_EINVAL (or DEANN_EWORKSPACE, DEANN_EUNSUPPORTED)
+ *    and writes nothing.  A HIP launch failure returns DEANN_EHIP.
+ *    deann_last_error() gives a message for the last non-OK status of the
+ *    calling thread.
+ *  - Calls that share a workspace must not overlap in time; calls with
+ *    separate workspaces on different streams are independent.
+ *  - Results are bitwise reproducible for identical inputs (no floating-point
+ *    atomics; every reduction has a fixed order).
+ */
+#ifndef DEANN_H
+#define DEANN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Kernels: Gaussian exp(-||x-y||^2 / (2 h^2)) (Eq. (2)) and exponential
+ * exp(-||x-y|| / h) (Sec. 1).  Both unnormalised, so the KDE lies in [0, 1]. */
+typedef enum { DEANN_GAUSSIAN = 0, DEANN_EXPONENTIAL = 1 } deann_kernel;
+
+/* Precision of the distance tiles on MFMA (FP32 accumulation in every case).
+ * Values that reach an estimate in deann_query are always recomputed exactly
+ * in FP64 from the float32 inputs, whatever the precision here. */
+typedef enum { DEANN_FP32 = 0, DEANN_BF16 = 1, DEANN_FP16 = 2 } deann_precision;
+
+typedef enum {
+  DEANN_OK = 0,
+  DEANN_EINVAL = 1,       /* invalid argument (size, pointer, h, k, m, enum) */
+  DEANN_EWORKSPACE = 2,   /* ws_bytes smaller than the queried size, or ws NULL */
+  DEANN_EHIP = 3,         /* a HIP launch failed */
+  DEANN_EUNSUPPORTED = 4  /* valid but outside what this build implements */
+} deann_status;
+
+/* ---------------------------------------------------------------------------
+ * Exact KDE, Eq. (1):  out[j] = (1/n) sum_i K_h(x_i, y_j).
+ *
+ * Distances use the identity ||x-y||^2 = ||x||^2 + ||y||^2 - 2<x,y> of App. F
+ * (with both sides centred on the column mean of X) and the kernel sum is
+ * fused into the MFMA tile; per-split sums are combined in FP64.
+ *   precision  DEANN_FP32, DEANN_BF16 or DEANN_FP16 operands of the GEMM.
+ *   out        [q] float64.
+ * Requirements: n >= 1, d >= 1, q >= 0 (q = 0 is a no-op), h finite and > 0,
+ * n and q < 2^31.
+ * ------------------------------------------------------------------------- */
+size_t kde_exact_workspace(int64_t n, int64_t q, int64_t d, int precision);
+int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+              int kernel, int precision, double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * DEANN estimate, Algorithm 1, with an exact k-NN in place of the ANN:
+ *   X1  = the k nearest rows of X to y (exact; ties to the lower index),
+ *   Z1  = sum over X1 of K_h,  S = m draws with repetition from X2 = X \ X1,
+ *   Z2  = sum over S of K_h,   out = (Z1 + ((n-k)/m) Z2) / n,
+ * which is (k/n) Z1/k + ((n-k)/n) Z2/m of Algorithm 1 line 6, valid also for
+ * k = 0 (random sampling) and m = 0 (far points dropped, biased).  With k = n
+ * the result is the exact KDE and no draw is made.
+ *
+ * Draw j of query i is word (j mod 4) of Philox4x64-10 (Salmon et al., SC'11)
+ * with key (seed, 0) and counter (j div 4, query_offset + i, word2, 0); the rank
+ * r = floor(u (n-k) / 2^64) selects the r-th smallest index of X2.  Splitting a
+ * query batch and passing query_offset reproduces the same draws.
+ *
+ *   precision   operand precision of the k-NN distance scan.  The neighbour set
+ *               is exact in every precision: candidates are ranked by a rigorous
+ *               lower bound and re-evaluated in FP64; a query whose candidate
+ *               set cannot be certified is rescanned.
+ *   out         [q] float64 estimates.
+ *   nn_idx      [q, k] int32, neighbour indices sorted ascending, or NULL.
+ *   sample_idx  [q, m] int32, drawn indices in draw order (-1 when X2 is
+ *               empty), or NULL.  Both are needed by deann_query_backward.
+ * Requirements: as kde_exact, plus 0 <= k <= n with k <= 1008 or k == n,
+ * m >= 0, n < 2^31.
+ * ------------------------------------------------------------------------- */
+size_t deann_query_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
+                             int precision);
+int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                int kernel, int64_t k, int64_t m, uint64_t seed, uint64_t query_offset,
+                uint64_t word2, int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint of deann_query with the index sets held fixed (the selection is
+ * piecewise constant in y and h, so this is the derivative almost everywhere):
+ *   grad_Y[j] = grad_out[j] * d out[j] / d y_j          [q, d] float32, or NULL
+ *   grad_h    = sum_j grad_out[j] * d out[j] / d h      [1] float64, or NULL
+ * Gaussian: dK/dy = K (x-y)/h^2, dK/dh = K r^2/h^3; exponential:
+ * dK/dy = K (x-y)/(h r) (0 at r = 0), dK/dh = K r/h^2, with r = ||x-y||.
+ * nn_idx and sample_idx are the outputs of the forward call with the same
+ * (n, k, m).  Rows are gathered again and distances recomputed in FP64.
+ * ------------------------------------------------------------------------- */
+size_t deann_query_backward_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m);
+int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                         double h, int kernel, int64_t k, int64_t m, const int32_t* nn_idx,
+                         const int32_t* sample_idx, const double* grad_out, float* grad_Y,
+                         double* grad_h, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint of kde_exact (FP32 operands only; d <= 128):
+ *   grad_Y[j] = grad_out[j] * (1/n) sum_i dK/dy (x_i, y_j),   [q, d] or NULL
+ *   grad_h    = sum_j grad_out[j] * (1/n) sum_i dK/dh,        [1] or NULL.
+ * The distance tiles are recomputed on MFMA, never stored.
+ * ------------------------------------------------------------------------- */
+size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d);
+int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                       int kernel, const double* grad_out, float* grad_Y, double* grad_h,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* deann_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEANN_H */

@@ -1,0 +1,11 @@
+"""DEANN's query path on AMD Instinct MI355X (gfx950): exact KDE, DEANN with an
+exact k-NN, and their adjoints, as hand-written HIP kernels behind a C ABI.
+
+The HIP library must be built (``python -m paper_2107_02736_amd.build``);
+there is no CPU fallback.
+"""
+from ._lib import DeannError, load as load_library  # noqa: F401
+from .api import (  # noqa: F401
+    kde_exact, deann_query, deann_query_backward, kde_exact_backward,
+)
+from .autograd import ExactKDE, DeannKDE, exact_kde, deann_kde, mean_shift, bisect_h  # noqa: F401

@@ -1,0 +1,77 @@
+"""ctypes binding of libdeann.so: argument marshalling only.
+
+Every computation happens in the HIP library; this module converts Python
+values into the C ABI declared in include/deann.h and raises on a non-OK status.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdeann.so")
+
+OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
+GAUSSIAN, EXPONENTIAL = 0, 1
+FP32, BF16, FP16 = 0, 1, 2
+
+EXPORTS = (
+    "kde_exact_workspace", "kde_exact",
+    "deann_query_workspace", "deann_query",
+    "deann_query_backward_workspace", "deann_query_backward",
+    "kde_exact_backward_workspace", "kde_exact_backward",
+    "deann_last_error",
+)
+
+
+class DeannError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"deann status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+_i64, _u64, _int, _dbl, _sz, _vp = (ctypes.c_int64, ctypes.c_uint64, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p)
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build the HIP library first "
+            "(python -m paper_2107_02736_amd.build)")
+    lib = ctypes.CDLL(path)
+    lib.deann_last_error.restype = ctypes.c_char_p
+    lib.deann_last_error.argtypes = []
+    lib.kde_exact_workspace.restype = _sz
+    lib.kde_exact_workspace.argtypes = [_i64, _i64, _i64, _int]
+    lib.kde_exact.restype = _int
+    lib.kde_exact.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _int, _vp, _vp, _sz, _vp]
+    lib.deann_query_workspace.restype = _sz
+    lib.deann_query_workspace.argtypes = [_i64, _i64, _i64, _i64, _i64, _int]
+    lib.deann_query.restype = _int
+    lib.deann_query.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64, _u64, _u64,
+                                _u64, _int, _vp, _vp, _vp, _vp, _sz, _vp]
+    lib.deann_query_backward_workspace.restype = _sz
+    lib.deann_query_backward_workspace.argtypes = [_i64, _i64, _i64, _i64, _i64]
+    lib.deann_query_backward.restype = _int
+    lib.deann_query_backward.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64, _vp,
+                                         _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    lib.kde_exact_backward_workspace.restype = _sz
+    lib.kde_exact_backward_workspace.argtypes = [_i64, _i64, _i64]
+    lib.kde_exact_backward.restype = _int
+    lib.kde_exact_backward.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _vp, _vp, _vp, _vp,
+                                       _sz, _vp]
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != OK:
+        msg = load().deann_last_error().decode(errors="replace")
+        raise DeannError(status, msg)

@@ -1,0 +1,125 @@
+"""Torch-facing wrappers of the C ABI (device memory and streams from PyTorch).
+
+Each function checks shapes and dtypes, allocates outputs and the workspace
+with torch, and calls the HIP library on torch's current stream.  No value is
+computed here.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+_KERNELS = {"gaussian": _lib.GAUSSIAN, "exponential": _lib.EXPONENTIAL}
+_PRECS = {"fp32": _lib.FP32, "bf16": _lib.BF16, "fp16": _lib.FP16}
+
+
+def kernel_id(kernel) -> int:
+    if isinstance(kernel, int):
+        return kernel
+    return _KERNELS[kernel]
+
+
+def precision_id(precision) -> int:
+    if isinstance(precision, int):
+        return precision
+    return _PRECS[precision]
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check_xy(X: torch.Tensor, Y: torch.Tensor):
+    if not (X.is_cuda and Y.is_cuda):
+        raise ValueError("X and Y must be device tensors (the HIP library has no CPU path)")
+    if X.dtype != torch.float32 or Y.dtype != torch.float32:
+        raise TypeError("X and Y must be float32")
+    if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+        raise ValueError("X must be [n, d] and Y [q, d]")
+    if not (X.is_contiguous() and Y.is_contiguous()):
+        raise ValueError("X and Y must be contiguous")
+    if X.device != Y.device:
+        raise ValueError("X and Y must be on the same device")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def kde_exact(X: torch.Tensor, Y: torch.Tensor, h: float, kernel="gaussian",
+              precision="fp32", out: torch.Tensor | None = None) -> torch.Tensor:
+    """Exact KDE of every query row (float64 [q])."""
+    _check_xy(X, Y)
+    lib = _lib.load()
+    n, d = X.shape
+    q = Y.shape[0]
+    p = precision_id(precision)
+    if out is None:
+        out = torch.empty(q, dtype=torch.float64, device=X.device)
+    ws = _workspace(lib.kde_exact_workspace(n, q, d, p), X.device)
+    _lib.check(lib.kde_exact(X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), p,
+                             out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(X.device)))
+    return out
+
+
+def deann_query(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int, kernel="gaussian",
+                seed: int = 0, query_offset: int = 0, word2: int = 0, precision="fp32",
+                return_indices: bool = True):
+    """DEANN estimate of every query: (out float64 [q], nn_idx int32 [q,k], sample_idx int32 [q,m])."""
+    _check_xy(X, Y)
+    lib = _lib.load()
+    n, d = X.shape
+    q = Y.shape[0]
+    p = precision_id(precision)
+    dev = X.device
+    out = torch.empty(q, dtype=torch.float64, device=dev)
+    nn = torch.empty((q, k), dtype=torch.int32, device=dev) if return_indices else None
+    sm = torch.empty((q, m), dtype=torch.int32, device=dev) if return_indices else None
+    ws = _workspace(lib.deann_query_workspace(n, q, d, k, m, p), dev)
+    _lib.check(lib.deann_query(X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel),
+                               int(k), int(m), int(seed), int(query_offset), int(word2), p,
+                               out.data_ptr(), _ptr(nn), _ptr(sm), ws.data_ptr(), ws.numel(),
+                               _stream(dev)))
+    return out, nn, sm
+
+
+def deann_query_backward(X, Y, h, k, m, nn_idx, sample_idx, grad_out, kernel="gaussian",
+                         need_grad_y: bool = True, need_grad_h: bool = True):
+    """(grad_Y float32 [q,d] or None, grad_h float64 [1] or None) of deann_query."""
+    _check_xy(X, Y)
+    lib = _lib.load()
+    n, d = X.shape
+    q = Y.shape[0]
+    dev = X.device
+    grad_out = grad_out.to(device=dev, dtype=torch.float64).contiguous()
+    gy = torch.empty((q, d), dtype=torch.float32, device=dev) if need_grad_y else None
+    gh = torch.empty(1, dtype=torch.float64, device=dev) if need_grad_h else None
+    ws = _workspace(lib.deann_query_backward_workspace(n, q, d, k, m), dev)
+    _lib.check(lib.deann_query_backward(
+        X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), int(k), int(m),
+        _ptr(nn_idx), _ptr(sample_idx), grad_out.data_ptr(), _ptr(gy), _ptr(gh), ws.data_ptr(),
+        ws.numel(), _stream(dev)))
+    return gy, gh
+
+
+def kde_exact_backward(X, Y, h, grad_out, kernel="gaussian", need_grad_y: bool = True,
+                       need_grad_h: bool = True):
+    """(grad_Y float32 [q,d] or None, grad_h float64 [1] or None) of kde_exact (FP32)."""
+    _check_xy(X, Y)
+    lib = _lib.load()
+    n, d = X.shape
+    q = Y.shape[0]
+    dev = X.device
+    grad_out = grad_out.to(device=dev, dtype=torch.float64).contiguous()
+    gy = torch.empty((q, d), dtype=torch.float32, device=dev) if need_grad_y else None
+    gh = torch.empty(1, dtype=torch.float64, device=dev) if need_grad_h else None
+    ws = _workspace(lib.kde_exact_backward_workspace(n, q, d), dev)
+    _lib.check(lib.kde_exact_backward(
+        X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), grad_out.data_ptr(),
+        _ptr(gy), _ptr(gh), ws.data_ptr(), ws.numel(), _stream(dev)))
+    return gy, gh

@@ -1,0 +1,354 @@
+// Adjoints of the KDE (derived from Eq. (1)-(2); the paper has no gradients).
+//
+// For one query y and one data row x at distance r = ||x - y||:
+//   Gaussian:    dK/dy = K (x - y) / h^2,        dK/dh = K r^2 / h^3
+//   exponential: dK/dy = K (x - y) / (h r),      dK/dh = K r / h^2   (dK/dy = 0 at r = 0)
+//
+// DEANN estimate (Algorithm 1, line 6): the index sets are held fixed (the
+// selection is piecewise constant in y and h), each neighbour weighs 1 and each
+// draw (n-k)/m, all over n.  The rows are gathered again and the distances
+// recomputed in FP64; nothing from the forward pass is stored but the indices.
+//
+// Exact KDE: the distance tile is recomputed on MFMA as S^T = X~ Y~^T so that
+// the weights W = dK/dy-scale land in registers exactly in the A-operand layout
+// of a second MFMA product G = W X~ (k dimension = data rows).  Then
+// dKDE/dy = (G - y~ rowsum(W)) / n in the centred coordinates.
+#include "common.h"
+#include "kernels.h"
+
+namespace deann {
+
+// ---------------------------------------------------------------------------
+// DEANN backward: one workgroup per query
+// ---------------------------------------------------------------------------
+constexpr int BWD_CHUNK = 512;
+constexpr int BWD_MAX_COORD_PER_THREAD = 8;   // d <= 2048
+
+__global__ void __launch_bounds__(WG)
+deann_backward_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
+                      int64_t d, double h, int kern, int64_t k, int64_t m,
+                      const int32_t* __restrict__ nn, const int32_t* __restrict__ samp,
+                      const double* __restrict__ grad_out, float* __restrict__ grad_Y,
+                      double* __restrict__ gh_part) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  double* wc = reinterpret_cast<double*>(smem);          // BWD_CHUNK
+  double* hh = wc + BWD_CHUNK;                            // BWD_CHUNK
+  int32_t* rid = reinterpret_cast<int32_t*>(hh + BWD_CHUNK);   // BWD_CHUNK
+  float* ys = reinterpret_cast<float*>(rid + BWD_CHUNK);        // d
+  const int64_t qi = blockIdx.x;
+  const int64_t size2 = n - k;
+  const int64_t ms = (size2 > 0) ? m : 0;
+  const int64_t R = k + ms;
+  const double csamp = ms > 0 ? (double)size2 / (double)m : 0.0;
+  for (int64_t t = threadIdx.x; t < d; t += WG) ys[t] = Y[qi * d + t];
+  double acc[BWD_MAX_COORD_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < BWD_MAX_COORD_PER_THREAD; ++u) acc[u] = 0.0;
+  double hsum = 0.0;   // thread 0
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  const double inv_h2 = 1.0 / (h * h);
+  __syncthreads();
+  for (int64_t r0 = 0; r0 < R; r0 += BWD_CHUNK) {
+    const int cnt = (int)(R - r0 < BWD_CHUNK ? R - r0 : BWD_CHUNK);
+    for (int jj = g; jj < cnt; jj += WG / 16) {
+      const int64_t j = r0 + jj;
+      const int32_t row = j < k ? nn[qi * k + j] : samp[qi * m + (j - k)];
+      const double c = j < k ? 1.0 : csamp;
+      const float* xr = X + (int64_t)row * d;
+      double s = 0.0;
+      for (int64_t t = l16; t < d; t += 16) {
+        const double df = (double)xr[t] - (double)ys[t];
+        s = __builtin_fma(df, df, s);
+      }
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      s += __shfl_xor(s, 8, 64);
+      if (l16 == 0) {
+        double w, dh;
+        if (kern == KERNEL_GAUSSIAN) {
+          const double K = exp(-0.5 * s * inv_h2);
+          w = K * inv_h2;
+          dh = K * s * inv_h2 / h;
+        } else {
+          const double r = sqrt(s);
+          const double K = exp(-r / h);
+          w = r > 0.0 ? K / (h * r) : 0.0;
+          dh = K * r * inv_h2;
+        }
+        wc[jj] = c * w;
+        hh[jj] = c * dh;
+        rid[jj] = row;
+      }
+    }
+    __syncthreads();
+    // coordinates owned by this thread, rows in fixed order
+    for (int jj = 0; jj < cnt; ++jj) {
+      const float* xr = X + (int64_t)rid[jj] * d;
+      const double w = wc[jj];
+#pragma unroll
+      for (int u = 0; u < BWD_MAX_COORD_PER_THREAD; ++u) {
+        const int64_t t = threadIdx.x + (int64_t)u * WG;
+        if (t < d) acc[u] = __builtin_fma(w, (double)xr[t] - (double)ys[t], acc[u]);
+      }
+    }
+    if (threadIdx.x == 0)
+      for (int jj = 0; jj < cnt; ++jj) hsum += hh[jj];
+    __syncthreads();
+  }
+  const double go = grad_out[qi];
+  const double scale = go / (double)n;
+  if (grad_Y) {
+#pragma unroll
+    for (int u = 0; u < BWD_MAX_COORD_PER_THREAD; ++u) {
+      const int64_t t = threadIdx.x + (int64_t)u * WG;
+      if (t < d) grad_Y[qi * d + t] = (float)(scale * acc[u]);
+    }
+  }
+  if (threadIdx.x == 0 && gh_part) gh_part[qi] = scale * hsum;
+}
+
+// Fixed-order sum of q per-query terms into one scalar (single workgroup).
+__global__ void __launch_bounds__(WG) sum_scalar_kernel(const double* __restrict__ v, int64_t q,
+                                                        double* __restrict__ out) {
+  __shared__ double red[WG];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < q; i += WG) s += v[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = WG / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
+                                 double h, int kern, int64_t k, int64_t m, const int32_t* nn,
+                                 const int32_t* samp, const double* grad_out, float* grad_Y,
+                                 double* gh_part, double* grad_h, hipStream_t s) {
+  if (q == 0) return hipSuccess;
+  const size_t sm = BWD_CHUNK * (8 + 8 + 4) + d * 4 + 16;
+  deann_backward_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(X, Y, n, d, h, kern, k, m, nn,
+                                                                samp, grad_out, grad_Y, gh_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !grad_h) return e;
+  sum_scalar_kernel<<<dim3(1), dim3(WG), 0, s>>>(gh_part, q, grad_h);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exact-KDE backward on MFMA (FP32 operands, padded d <= 128)
+// ---------------------------------------------------------------------------
+template <int KERN, int TB>   // TB = padded d / 16
+__global__ void __launch_bounds__(WG, 1)
+kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
+                    double* __restrict__ gy_part, double* __restrict__ rw_part,
+                    double* __restrict__ gh_part, int64_t grid) {
+  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
+  const int64_t V = xcd_virtual_id(blockIdx.x, grid);
+  if (V >= p.qtiles * p.splits) return;
+  const int64_t split = V / p.qtiles, qt = V % p.qtiles;
+  const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wi = wave >> 1, wq = wave & 1;   // data-row half, query half
+  constexpr int DP = TB * 16;
+  constexpr int XS = DP + 4;                 // LDS row stride (floats) of the data tile
+
+  float yn[4];
+#pragma unroll
+  for (int bq = 0; bq < 4; ++bq) yn[bq] = p.ynorm[qt * BQ + wq * 64 + bq * 16 + (lane & 15)];
+  f32x4 gacc[4][TB];
+#pragma unroll
+  for (int bq = 0; bq < 4; ++bq)
+#pragma unroll
+    for (int tb = 0; tb < TB; ++tb) gacc[bq][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double rws[4], dhs[4];
+#pragma unroll
+  for (int bq = 0; bq < 4; ++bq) { rws[bq] = 0.0; dhs[bq] = 0.0; }
+
+  const char* yq = p.Ys + qt * BQ * p.ld_bytes;
+  float* xt = reinterpret_cast<float*>(lds);
+  for (int64_t t = t0; t < t1; ++t) {
+    const char* xg = p.Xs + t * BN * p.ld_bytes;
+    f32x4 acc[4][4];   // [bi][bq]: rows = data, cols = queries
+    tile_dot<float>(acc, xg, yq, p.ld_bytes, p.nchunks, lds, wi, wq, lane);
+    // weights in place
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = t * BN + wi * 64 + bi * 16 + 4 * (lane >> 4) + r;
+        const bool valid = row < p.n;
+        const float xn = p.xnorm[row];
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq) {
+          const float s = acc[bi][bq][r];
+          const float d2 = fmaxf(0.f, __builtin_fmaf(-2.f, s, xn + yn[bq]));
+          float w, dh;
+          if (KERN == KERNEL_GAUSSIAN) {
+            const float K = __builtin_amdgcn_exp2f(-L * d2);
+            w = K * inv_h2;
+            dh = K * d2 * inv_h2 * inv_h;
+          } else {
+            const float rr = __builtin_sqrtf(d2);
+            const float K = __builtin_amdgcn_exp2f(-L * rr);
+            w = rr > 0.f ? K * inv_h / rr : 0.f;
+            dh = K * rr * inv_h2;
+          }
+          w = valid ? w : 0.f;
+          dh = valid ? dh : 0.f;
+          acc[bi][bq][r] = w;
+          rws[bq] += (double)w;
+          dhs[bq] += (double)dh;
+        }
+      }
+    }
+    // full data tile (all padded coordinates) into LDS
+    for (int v = threadIdx.x; v < BN * DP / 4; v += WG) {
+      const int row = v / (DP / 4), c4 = v % (DP / 4);
+      const f32x4 val = *reinterpret_cast<const f32x4*>(xg + row * p.ld_bytes + c4 * 16);
+      float* dst = xt + row * XS + c4 * 4;
+      dst[0] = val[0]; dst[1] = val[1]; dst[2] = val[2]; dst[3] = val[3];
+    }
+    __syncthreads();
+    // G[q][t] += sum_i W[q][i] x~[i][t]
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+#pragma unroll
+      for (int tb = 0; tb < TB; ++tb) {
+        float b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          b[j] = xt[(wi * 64 + bi * 16 + 4 * (lane >> 4) + j) * XS + tb * 16 + (lane & 15)];
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            gacc[bq][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[bi][bq][j], b[j],
+                                                                 gacc[bq][tb], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+  // combine the two data-row halves: wave (1, wq) hands over to wave (0, wq)
+  float* red = reinterpret_cast<float*>(lds);   // [2][64][DP]
+  double* redd = reinterpret_cast<double*>(lds + 2 * 64 * DP * 4);   // [2][2][64]
+#pragma unroll
+  for (int bq = 0; bq < 4; ++bq) {
+    double a = rws[bq], bb = dhs[bq];
+    a += __shfl_xor(a, 16, 64);
+    a += __shfl_xor(a, 32, 64);
+    bb += __shfl_xor(bb, 16, 64);
+    bb += __shfl_xor(bb, 32, 64);
+    rws[bq] = a;
+    dhs[bq] = bb;
+  }
+  if (wi == 1) {
+#pragma unroll
+    for (int bq = 0; bq < 4; ++bq)
+#pragma unroll
+      for (int tb = 0; tb < TB; ++tb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          red[(wq * 64 + bq * 16 + 4 * (lane >> 4) + r) * DP + tb * 16 + (lane & 15)] =
+              gacc[bq][tb][r];
+    if (lane < 16)
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) {
+        redd[(0 * 2 + wq) * 64 + bq * 16 + lane] = rws[bq];
+        redd[(1 * 2 + wq) * 64 + bq * 16 + lane] = dhs[bq];
+      }
+  }
+  __syncthreads();
+  if (wi == 0) {
+    const int64_t qbase = split * p.qp + qt * BQ + wq * 64;
+#pragma unroll
+    for (int bq = 0; bq < 4; ++bq)
+#pragma unroll
+      for (int tb = 0; tb < TB; ++tb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ql = bq * 16 + 4 * (lane >> 4) + r;
+          const int col = tb * 16 + (lane & 15);
+          gy_part[(qbase + ql) * DP + col] =
+              (double)gacc[bq][tb][r] + (double)red[(wq * 64 + ql) * DP + col];
+        }
+    if (lane < 16)
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) {
+        rw_part[qbase + bq * 16 + lane] = rws[bq] + redd[(0 * 2 + wq) * 64 + bq * 16 + lane];
+        gh_part[qbase + bq * 16 + lane] = dhs[bq] + redd[(1 * 2 + wq) * 64 + bq * 16 + lane];
+      }
+  }
+}
+
+// grad_Y[q] = g_q / n * (sum_s G_s[q] - y~_q sum_s rowsum_s[q]);  per-query h term.
+__global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
+                                           const double* __restrict__ rw_part,
+                                           const double* __restrict__ gh_part,
+                                           const float* __restrict__ Ys, int64_t splits,
+                                           int64_t qp, int64_t q, int64_t d, int64_t dp,
+                                           double inv_n, const double* __restrict__ grad_out,
+                                           float* __restrict__ grad_Y, double* __restrict__ ghq) {
+  const int64_t qi = blockIdx.x;
+  __shared__ double rw_s;
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int64_t s = 0; s < splits; ++s) { a += rw_part[s * qp + qi]; b += gh_part[s * qp + qi]; }
+    rw_s = a;
+    if (ghq) ghq[qi] = grad_out[qi] * b * inv_n;
+  }
+  __syncthreads();
+  if (!grad_Y) return;
+  const double sc = grad_out[qi] * inv_n;
+  for (int64_t t = threadIdx.x; t < d; t += blockDim.x) {
+    double g = 0.0;
+    for (int64_t s = 0; s < splits; ++s) g += gy_part[(s * qp + qi) * dp + t];
+    grad_Y[qi * d + t] = (float)(sc * (g - (double)Ys[qi * dp + t] * rw_s));
+  }
+}
+
+template <int KERN>
+static hipError_t launch_kde_bwd_k(const TileProblem& p, int TB, float L, float inv_h,
+                                   float inv_h2, double* gy, double* rw, double* gh,
+                                   hipStream_t s) {
+  const int64_t grid = round_up(p.qtiles * p.splits, 8);
+  const dim3 g((unsigned)grid), b(WG);
+  switch (TB) {
+    case 2: kde_backward_kernel<KERN, 2><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh, grid); break;
+    case 4: kde_backward_kernel<KERN, 4><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh, grid); break;
+    case 6: kde_backward_kernel<KERN, 6><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh, grid); break;
+    default: kde_backward_kernel<KERN, 8><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh, grid); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, double h, int kern,
+                               const double* grad_out, double* gy_part, double* gh_part,
+                               float* grad_Y, double* grad_h, hipStream_t s) {
+  (void)Y;
+  const int64_t dp = p.ld_bytes / 4;
+  const int TB = (int)(dp / 16);
+  const double log2e = 1.4426950408889634;
+  const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
+  double* rw_part = gh_part + p.splits * p.qp;   // layout: gh [splits][qp], rw [splits][qp], ghq [q]
+  double* ghq = rw_part + p.splits * p.qp;
+  hipError_t e = (kern == KERNEL_GAUSSIAN)
+                     ? launch_kde_bwd_k<KERNEL_GAUSSIAN>(p, TB, L, (float)(1.0 / h),
+                                                         (float)(1.0 / (h * h)), gy_part, rw_part,
+                                                         gh_part, s)
+                     : launch_kde_bwd_k<KERNEL_EXPONENTIAL>(p, TB, L, (float)(1.0 / h),
+                                                            (float)(1.0 / (h * h)), gy_part,
+                                                            rw_part, gh_part, s);
+  if (e != hipSuccess) return e;
+  kde_backward_reduce_kernel<<<dim3((unsigned)p.q), dim3(128), 0, s>>>(
+      gy_part, rw_part, gh_part, reinterpret_cast<const float*>(p.Ys), p.splits, p.qp, p.q, d, dp,
+      1.0 / (double)p.n, grad_out, grad_Y, ghq);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!grad_h) return hipSuccess;
+  sum_scalar_kernel<<<dim3(1), dim3(WG), 0, s>>>(ghq, p.q, grad_h);
+  return hipGetLastError();
+}
+
+}  // namespace deann

@@ -1,0 +1,202 @@
+// Shared device helpers for the DEANN HIP library (gfx950 / CDNA4).
+//
+// Tiles: a workgroup of 256 threads (4 wave64) owns a BQ x BN block of
+// (query, data-row) pairs.  Both operands are staged through LDS in k-chunks
+// of DK elements; each wave owns a 64 x 64 quarter and issues 16 x 16 MFMA
+// blocks (v_mfma_f32_16x16x4_f32 for FP32 operands, v_mfma_f32_16x16x32_{bf16,f16}
+// for 16-bit operands), accumulating in FP32.
+//
+// Operand layout convention (identical for A = query rows and B = data rows):
+// a k-group is 64 bytes of a row.  Lane l of a wave reads the 16 bytes at
+// offset 16*(l/16) of the k-group of row (l%16).  For FP32 those 4 floats feed
+// 4 successive 16x16x4 MFMAs; for 16-bit types the 8 values feed one 16x16x32
+// MFMA.  The k order inside a group is thereby permuted, identically for both
+// operands, which leaves every dot product unchanged.
+//
+// Accumulator layout of a 16x16 block: lane l, register r holds
+// row 4*(l/16) + r, column l%16.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace deann {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int WG = 256;          // threads per workgroup
+constexpr int BQ = 128;          // queries per tile
+constexpr int BN = 128;          // data rows per tile
+constexpr int KG_BYTES = 64;     // bytes of a row per k-group
+constexpr int CHUNK_BYTES = 128; // bytes of a row per LDS k-chunk (2 k-groups)
+constexpr int ROW_PAD = 16;      // LDS row padding in bytes
+constexpr int LDS_ROW = CHUNK_BYTES + ROW_PAD;
+constexpr int TILE_LDS = BQ * LDS_ROW;   // one operand chunk in LDS (bytes)
+
+enum : int { KERNEL_GAUSSIAN = 0, KERNEL_EXPONENTIAL = 1 };
+enum : int { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2 };
+
+template <typename T> struct elem_of;
+template <> struct elem_of<float> { static constexpr int bytes = 4; };
+template <> struct elem_of<__bf16> { static constexpr int bytes = 2; };
+template <> struct elem_of<_Float16> { static constexpr int bytes = 2; };
+
+// Elements per padded row unit: every scan operand row is padded with zeros
+// to a multiple of CHUNK_BYTES so that tile loads need no k masking.
+template <typename T>
+__host__ __device__ constexpr int64_t padded_dim(int64_t d) {
+  const int64_t per = CHUNK_BYTES / elem_of<T>::bytes;
+  return (d + per - 1) / per * per;
+}
+
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// MFMA on one 64-byte k-group: acc += A(16 x kgroup) * B(kgroup x 16)^T
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ f32x4 mfma_kgroup(u32x4 a, u32x4 b, f32x4 acc);
+
+template <>
+__device__ __forceinline__ f32x4 mfma_kgroup<float>(u32x4 a, u32x4 b, f32x4 acc) {
+  // element-wise reinterpretation (a bit_cast of a vector element would
+  // reinterpret the whole vector's first bytes)
+  const uint32_t a0 = a.x, a1 = a.y, a2 = a.z, a3 = a.w;
+  const uint32_t b0 = b.x, b1 = b.y, b2 = b.z, b3 = b.w;
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a0), __uint_as_float(b0), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a1), __uint_as_float(b1), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a2), __uint_as_float(b2), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a3), __uint_as_float(b3), acc, 0, 0, 0);
+  return acc;
+}
+
+template <>
+__device__ __forceinline__ f32x4 mfma_kgroup<__bf16>(u32x4 a, u32x4 b, f32x4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ f32x4 mfma_kgroup<_Float16>(u32x4 a, u32x4 b, f32x4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                __builtin_bit_cast(f16x8, b), acc, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Global -> register -> LDS staging of one k-chunk (CHUNK_BYTES per row) of a
+// 128-row tile.  Rows are padded in global memory (row stride `ld_bytes`, a
+// multiple of CHUNK_BYTES) and the row count is padded to a multiple of 128,
+// so every load is in bounds and 16-byte aligned.
+// ---------------------------------------------------------------------------
+constexpr int CHUNK_VECS = BQ * CHUNK_BYTES / 16 / WG;   // 16-byte loads per thread (= 4)
+
+struct ChunkRegs { u32x4 v[CHUNK_VECS]; };
+
+__device__ __forceinline__ void load_chunk(ChunkRegs& r, const char* __restrict__ base,
+                                           int64_t ld_bytes, int64_t kbyte) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < CHUNK_VECS; ++i) {
+    const int v = t + i * WG;                 // vector id within the tile chunk
+    const int row = v / (CHUNK_BYTES / 16);
+    const int col = v % (CHUNK_BYTES / 16);
+    r.v[i] = *reinterpret_cast<const u32x4*>(base + row * ld_bytes + kbyte + col * 16);
+  }
+}
+
+__device__ __forceinline__ void store_chunk(const ChunkRegs& r, char* lds) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < CHUNK_VECS; ++i) {
+    const int v = t + i * WG;
+    const int row = v / (CHUNK_BYTES / 16);
+    const int col = v % (CHUNK_BYTES / 16);
+    *reinterpret_cast<u32x4*>(lds + row * LDS_ROW + col * 16) = r.v[i];
+  }
+}
+
+// Fragment of 16 rows starting at `row0` for k-group `kg` of the LDS chunk.
+__device__ __forceinline__ u32x4 lds_frag(const char* lds, int row0, int kg, int lane) {
+  return *reinterpret_cast<const u32x4*>(lds + (row0 + (lane & 15)) * LDS_ROW + kg * KG_BYTES +
+                                         (lane >> 4) * 16);
+}
+
+// Accumulate the wave's 64 x 64 quarter over one LDS chunk.
+// qa: LDS chunk of the query tile, xa: LDS chunk of the data tile.
+template <typename T>
+__device__ __forceinline__ void mfma_chunk(f32x4 (&acc)[4][4], const char* qa, const char* xa,
+                                           int wq, int wn, int lane) {
+#pragma unroll
+  for (int kg = 0; kg < CHUNK_BYTES / KG_BYTES; ++kg) {
+    u32x4 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = lds_frag(qa, wq * 64 + i * 16, kg, lane);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = lds_frag(xa, wn * 64 + j * 16, kg, lane);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = mfma_kgroup<T>(a[i], b[j], acc[i][j]);
+  }
+}
+
+// Full d-loop for one (query tile, data tile) pair with LDS double buffering.
+// lds must hold 4 * TILE_LDS bytes: [q0 | x0 | q1 | x1].
+template <typename T>
+__device__ __forceinline__ void tile_dot(f32x4 (&acc)[4][4], const char* __restrict__ yq,
+                                         const char* __restrict__ xt, int64_t ld_bytes,
+                                         int nchunks, char* lds, int wq, int wn, int lane) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  ChunkRegs rq, rx;
+  load_chunk(rq, yq, ld_bytes, 0);
+  load_chunk(rx, xt, ld_bytes, 0);
+  __syncthreads();   // previous users of the LDS buffers are done
+  store_chunk(rq, lds);
+  store_chunk(rx, lds + TILE_LDS);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int cur = c & 1;
+    char* qa = lds + cur * 2 * TILE_LDS;
+    char* xa = qa + TILE_LDS;
+    const bool more = c + 1 < nchunks;
+    if (more) {
+      load_chunk(rq, yq, ld_bytes, (int64_t)(c + 1) * CHUNK_BYTES);
+      load_chunk(rx, xt, ld_bytes, (int64_t)(c + 1) * CHUNK_BYTES);
+    }
+    mfma_chunk<T>(acc, qa, xa, wq, wn, lane);
+    if (more) {
+      char* qn = lds + (cur ^ 1) * 2 * TILE_LDS;
+      store_chunk(rq, qn);
+      store_chunk(rx, qn + TILE_LDS);
+    }
+    __syncthreads();
+  }
+}
+
+// XCD-aware placement: workgroups are dispatched round-robin over the 8 XCDs.
+// Map the hardware id so that each XCD receives a contiguous range of virtual
+// ids; consecutive virtual ids share the same data split (and hence the same
+// data tiles in that XCD's L2) and differ in their query tile.
+__device__ __forceinline__ int64_t xcd_virtual_id(int64_t hw, int64_t grid) {
+  const int64_t per = grid / 8;   // grid is a multiple of 8
+  return (hw % 8) * per + hw / 8;
+}
+
+// Order-preserving map float -> uint32 (total order matching <, -0 < +0).
+__device__ __forceinline__ uint32_t float_key(float f) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float key_float(uint32_t k) {
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return __builtin_bit_cast(float, b);
+}
+
+}  // namespace deann

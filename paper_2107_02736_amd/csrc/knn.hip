@@ -1,0 +1,586 @@
+// Exact k nearest neighbours: the ANN black box of Algorithm 1 (line 2)
+// replaced by an exact brute-force search whose result equals the sequence of
+// points sorted by distance (Sec. 2) with ties broken towards the lower index.
+//
+// 1. scan     : the MFMA distance tile of the prepared (possibly BF16/FP16)
+//               operands gives a key per pair that provably never exceeds
+//               ||x~ - y~||^2.  Each (split, query) keeps the K1 smallest keys
+//               in a global list (threshold in LDS, append on accept,
+//               workgroup bitonic compaction when the list runs full).
+// 2. refine   : per query, the K1 smallest keys over all splits are re-evaluated
+//               exactly (FP64 direct differences, double-double for near ties),
+//               sorted by (d^2, index); the first k are the candidates.  A
+//               certificate checks that every excluded point is provably farther
+//               than the k-th candidate: sqrt(T) - E - e_y > d_k, with T the K1-th
+//               key and E, e_y bounds of the rounding of the rows.
+// 3. collect  : queries failing the certificate rescan and gather every point
+//               whose key admits a distance <= d_k; refine2 then sorts that set.
+// 4. exhaustive: a query whose second-pass set overflowed is scanned with exact
+//               FP64 distances by one workgroup (rare fallback).
+#include "common.h"
+#include "kernels.h"
+
+namespace deann {
+
+constexpr int SORT_CAP = 4096;   // entries of the workgroup LDS sorts
+constexpr int K_MAX = 1024;      // largest K1 (and hence k) the refine kernels take
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+// Workgroup bitonic sort of N (power of two) packed uint64 keys, ascending.
+__device__ void block_sort_u64(uint64_t* a, int N) {
+  for (int kk = 2; kk <= N; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = a[i], y = a[ixj];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) { a[i] = y; a[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Workgroup bitonic sort of N pairs (key, idx) ascending by (key, idx).
+__device__ void block_sort_pairs(uint64_t* key, uint32_t* idx, int N) {
+  for (int kk = 2; kk <= N; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = key[i], b = key[ixj];
+          const uint32_t ia = idx[i], ib = idx[ixj];
+          const bool gt = a > b || (a == b && ia > ib);
+          const bool up = (i & kk) == 0;
+          if (gt == up) { key[i] = b; key[ixj] = a; idx[i] = ib; idx[ixj] = ia; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Exact FP64 squared distance of row `row` of X to the query held in LDS,
+// computed by a group of 16 consecutive lanes (all 16 get the result).
+__device__ __forceinline__ double group16_d2(const float* __restrict__ X, int64_t row, int64_t d,
+                                             const float* ys, int l16) {
+  const float* xr = X + row * d;
+  double s = 0.0;
+  for (int64_t t = l16; t < d; t += 16) {
+    const double df = (double)xr[t] - (double)ys[t];
+    s = __builtin_fma(df, df, s);
+  }
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  s += __shfl_xor(s, 4, 64);
+  s += __shfl_xor(s, 8, 64);
+  return s;
+}
+
+// ||x - y||^2 as an unevaluated double-double sum (error-free squares and
+// two-sum accumulation); used only to order near ties.
+__device__ void dd_d2(const float* __restrict__ xr, const float* ys, int64_t d, double& hi,
+                      double& lo) {
+  double s = 0.0, c = 0.0;
+  for (int64_t t = 0; t < d; ++t) {
+    const double df = (double)xr[t] - (double)ys[t];
+    const double p = df * df;
+    const double pe = __builtin_fma(df, df, -p);
+    // two-sum s + p
+    const double t1 = s + p;
+    const double bp = t1 - s;
+    const double e1 = (s - (t1 - bp)) + (p - bp);
+    s = t1;
+    c += e1 + pe;
+  }
+  hi = s + c;
+  lo = c - (hi - s);
+}
+
+__device__ __forceinline__ double kernel_value(double d2, double h, int kern) {
+  if (kern == KERNEL_GAUSSIAN) return exp(-d2 / (2.0 * h * h));
+  return exp(-sqrt(d2) / h);
+}
+
+// Reorders the entries of [a, b] (inclusive; near-tied in FP64) by their
+// double-double distance, then index.  Single thread, tiny ranges.
+__device__ void resolve_band(uint64_t* key, uint32_t* idx, int a, int b, const float* X,
+                             int64_t d, const float* ys) {
+  constexpr int MAXB = 32;
+  double hi[MAXB], lo[MAXB];
+  uint32_t id[MAXB];
+  const int cnt = b - a + 1;
+  for (int i = 0; i < cnt; ++i) {
+    id[i] = idx[a + i];
+    dd_d2(X + (int64_t)id[i] * d, ys, d, hi[i], lo[i]);
+  }
+  for (int i = 1; i < cnt; ++i) {   // insertion sort by (hi, lo, id)
+    const double h0 = hi[i], l0 = lo[i];
+    const uint32_t i0 = id[i];
+    int j = i - 1;
+    while (j >= 0 && (hi[j] > h0 || (hi[j] == h0 && (lo[j] > l0 || (lo[j] == l0 && id[j] > i0))))) {
+      hi[j + 1] = hi[j]; lo[j + 1] = lo[j]; id[j + 1] = id[j];
+      --j;
+    }
+    hi[j + 1] = h0; lo[j + 1] = l0; id[j + 1] = i0;
+  }
+  for (int i = 0; i < cnt; ++i) {
+    idx[a + i] = id[i];
+    key[a + i] = __builtin_bit_cast(uint64_t, hi[i]);
+  }
+}
+
+// Relative error bound of the FP64 direct squared distance.
+__device__ __forceinline__ double fp64_rel(int64_t d) { return 4.0 * (double)(d + 2) * 0x1p-53; }
+
+// After a (d^2 bits, index) sort of `cnt` exact candidates: fix the order of
+// entries whose FP64 distances are too close to the k-th to be trusted.
+__device__ void fix_boundary(uint64_t* key, uint32_t* idx, int cnt, int k, const float* X,
+                             int64_t d, const float* ys) {
+  if (threadIdx.x == 0 && k < cnt && k > 0) {
+    const double D = __builtin_bit_cast(double, key[k - 1]);
+    const double rel = fp64_rel(d);
+    const double lo = D * (1.0 - rel), hi = D * (1.0 + rel);
+    int a = k - 1, b = k - 1;
+    while (a > 0 && __builtin_bit_cast(double, key[a - 1]) >= lo) --a;
+    while (b + 1 < cnt && __builtin_bit_cast(double, key[b + 1]) <= hi) ++b;
+    if (b > k - 1) {
+      if (b - a + 1 > 32) { a = (k - 16 > a) ? k - 16 : a; b = (a + 31 < b) ? a + 31 : b; }
+      resolve_band(key, idx, a, b, X, d, ys);
+    }
+  }
+  __syncthreads();
+}
+
+// Neighbour list sorted by index, Z1 = sum of kernel values over it.
+__device__ void emit_neighbours(const uint64_t* key, uint32_t* idx, uint32_t* tmp, int k,
+                                double h, int kern, int32_t* nn_row, int32_t* nn_out_row,
+                                double* z1_out, double* red) {
+  // Z1 in the fixed (distance, index) order: per-thread strided partials, then a tree.
+  double s = 0.0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x)
+    s += kernel_value(__builtin_bit_cast(double, key[i]), h, kern);
+  red[threadIdx.x] = s;
+  const int N = next_pow2(k);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) tmp[i] = i < k ? idx[i] : 0xffffffffu;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  // sort the k indices ascending (bitonic on 32-bit values)
+  for (int kk = 2; kk <= N; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint32_t a = tmp[i], b = tmp[ixj];
+          if ((a > b) == ((i & kk) == 0)) { tmp[i] = b; tmp[ixj] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    nn_row[i] = (int32_t)tmp[i];
+    if (nn_out_row) nn_out_row[i] = (int32_t)tmp[i];
+  }
+  if (threadIdx.x == 0) *z1_out = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// 1. scan
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(WG, 2)
+knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt,
+                int cap1, int K1, int64_t grid) {
+  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
+  __shared__ float thr[BQ];
+  __shared__ int cnt[BQ];
+  __shared__ int need[BQ];
+  const int64_t V = xcd_virtual_id(blockIdx.x, grid);
+  if (V >= p.qtiles * p.splits) return;
+  const int64_t split = V / p.qtiles, qt = V % p.qtiles;
+  const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wq = wave >> 1, wn = wave & 1;
+  if (threadIdx.x < BQ) { thr[threadIdx.x] = __builtin_inff(); cnt[threadIdx.x] = 0; }
+  uint64_t* lists = cand + (split * p.qp + qt * BQ) * (int64_t)cap1;
+
+  float yk[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) yk[i][r] = p.yknorm[qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r];
+
+  const char* yq = p.Ys + qt * BQ * p.ld_bytes;
+  const int limit = cap1 - BN;   // a list above this could overflow in the next tile
+  for (int64_t t = t0; t <= t1; ++t) {
+    const bool last = (t == t1);
+    if (!last) {
+      f32x4 acc[4][4];
+      tile_dot<T>(acc, yq, p.Xs + t * BN * p.ld_bytes, p.ld_bytes, p.nchunks, lds, wq, wn, lane);
+      float th[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) th[i][r] = thr[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
+        const bool valid = col < p.n;
+        const float xk = p.xknorm[col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk[i][r] + xk);
+            if (valid && key < th[i][r]) {
+              const int ql = wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+              const int slot = atomicAdd(&cnt[ql], 1);
+              lists[(int64_t)ql * cap1 + slot] =
+                  ((uint64_t)float_key(key) << 32) | (uint64_t)(uint32_t)col;
+            }
+          }
+      }
+    }
+    __syncthreads();
+    // compaction of lists that might overflow (or, at the end, of every list above K1)
+    const int lim = last ? K1 : limit;
+    if (threadIdx.x < BQ) need[threadIdx.x] = cnt[threadIdx.x] > lim;
+    __syncthreads();
+    uint64_t* buf = reinterpret_cast<uint64_t*>(lds);
+    for (int ql = 0; ql < BQ; ++ql) {
+      if (!need[ql]) continue;
+      const int c = cnt[ql];
+      const int N = next_pow2(c);
+      uint64_t* lst = lists + (int64_t)ql * cap1;
+      for (int i = threadIdx.x; i < N; i += WG) buf[i] = i < c ? lst[i] : ~0ull;
+      __syncthreads();
+      block_sort_u64(buf, N);
+      for (int i = threadIdx.x; i < K1; i += WG) lst[i] = buf[i];
+      if (threadIdx.x == 0) {
+        cnt[ql] = K1;
+        thr[ql] = key_float((uint32_t)(buf[K1 - 1] >> 32));
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x < BQ) cand_cnt[split * p.qp + qt * BQ + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// 2. merge + exact refine + certificate (one workgroup per query)
+// ---------------------------------------------------------------------------
+struct RefineArgs {
+  const float* X;
+  const float* Y;
+  int64_t n, q, d, k, qp, splits;
+  double h;
+  int kern;
+};
+
+__global__ void __launch_bounds__(WG)
+knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  uint64_t* buf = reinterpret_cast<uint64_t*>(smem);                  // SORT_CAP
+  uint64_t* dkey = buf + SORT_CAP;                                     // K_MAX
+  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + K_MAX);         // K_MAX
+  uint32_t* tmp = didx + K_MAX;                                        // K_MAX
+  double* red = reinterpret_cast<double*>(tmp + K_MAX);               // WG
+  float* ys = reinterpret_cast<float*>(red + WG);                      // d
+  __shared__ int fill_s;
+  const int64_t qi = blockIdx.x;
+  const int K1 = (int)b.K1;
+  for (int64_t t = threadIdx.x; t < a.d; t += WG) ys[t] = a.Y[qi * a.d + t];
+  if (threadIdx.x == 0) fill_s = 0;
+  __syncthreads();
+  // gather the split lists, keeping the K1 smallest keys
+  int64_t seen = 0;
+  for (int64_t s = 0; s < a.splits; ++s) {
+    const int c = b.cand_cnt[s * a.qp + qi];
+    const int f = fill_s;
+    const uint64_t* lst = b.cand + (s * a.qp + qi) * b.cap1;
+    for (int i = threadIdx.x; i < c; i += WG) buf[f + i] = lst[i];
+    seen += c;
+    __syncthreads();
+    if (threadIdx.x == 0) fill_s = f + c;
+    __syncthreads();
+    const bool flush = (fill_s + K1 > SORT_CAP) || (s + 1 == a.splits);
+    if (flush && fill_s > K1) {
+      const int F = fill_s;
+      for (int i = F + threadIdx.x; i < SORT_CAP; i += WG) buf[i] = ~0ull;
+      __syncthreads();
+      block_sort_u64(buf, SORT_CAP);
+      if (threadIdx.x == 0) fill_s = K1;
+      __syncthreads();
+    }
+  }
+  const int C = fill_s;            // candidates (<= K1)
+  // all points were candidates iff no list ever dropped anything
+  const bool complete = (seen == a.n) && (C == a.n);
+  const float Tkey = (C == K1) ? key_float((uint32_t)(buf[K1 - 1] >> 32)) : __builtin_inff();
+  // exact FP64 distances
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  for (int c = g; c < C; c += WG / 16) {
+    const uint32_t id = (uint32_t)(buf[c] & 0xffffffffu);
+    const double d2 = group16_d2(a.X, id, a.d, ys, l16);
+    if (l16 == 0) { dkey[c] = __builtin_bit_cast(uint64_t, d2); didx[c] = id; }
+  }
+  const int N = next_pow2(C > 1 ? C : 2);
+  for (int i = C + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
+  __syncthreads();
+  block_sort_pairs(dkey, didx, N);
+  const int k = (int)a.k;
+  fix_boundary(dkey, didx, C, k, a.X, a.d, ys);
+  bool ok = complete;
+  if (!ok && C >= k) {
+    const double Dk = __builtin_bit_cast(double, dkey[k - 1]) * (1.0 + fp64_rel(a.d));
+    const double E = (double)__builtin_bit_cast(float, *b.xerr_max);
+    const double ey = (double)b.yerr[qi];
+    const double lhs = sqrt((double)fmaxf(Tkey, 0.f)) - E - ey;
+    ok = lhs > 0.0 && lhs * lhs > Dk * (1.0 + 1e-14);
+    if (!ok) {
+      if (threadIdx.x == 0) {
+        const double r = (sqrt(Dk) + E + ey) * (1.0 + 1e-6);
+        b.thr2[qi] = (float)(r * r * (1.0 + 1e-6));
+        b.status[qi] = 1;
+        b.cand2_cnt[qi] = 0;
+        b.flags[qi / BQ] = 1;
+      }
+      return;
+    }
+  }
+  if (!ok) {   // fewer candidates than k cannot happen for k <= n; treat as exhaustive
+    if (threadIdx.x == 0) { b.status[qi] = 2; b.flags[qi / BQ] = 1; }
+    return;
+  }
+  if (threadIdx.x == 0) b.status[qi] = 0;
+  emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
+                  nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
+}
+
+// ---------------------------------------------------------------------------
+// 3. second pass: collect every point whose key admits distance <= d_k
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(WG, 2)
+knn_collect_kernel(TileProblem p, KnnBuffers b, int64_t grid) {
+  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
+  const int64_t V = xcd_virtual_id(blockIdx.x, grid);
+  if (V >= p.qtiles * p.splits) return;
+  const int64_t split = V / p.qtiles, qt = V % p.qtiles;
+  if (b.flags[qt] == 0) return;
+  const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wq = wave >> 1, wn = wave & 1;
+  float yk[4][4], th[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+      yk[i][r] = p.yknorm[row];
+      th[i][r] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
+    }
+  const char* yq = p.Ys + qt * BQ * p.ld_bytes;
+  for (int64_t t = t0; t < t1; ++t) {
+    f32x4 acc[4][4];
+    tile_dot<T>(acc, yq, p.Xs + t * BN * p.ld_bytes, p.ld_bytes, p.nchunks, lds, wq, wn, lane);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
+      const bool valid = col < p.n;
+      const float xk = p.xknorm[col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk[i][r] + xk);
+          if (valid && key <= th[i][r]) {
+            const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+            const int slot = atomicAdd(&b.cand2_cnt[row], 1);
+            if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = (uint64_t)col;
+          }
+        }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(WG)
+knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  uint64_t* dkey = reinterpret_cast<uint64_t*>(smem);                // SORT_CAP
+  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + SORT_CAP);      // SORT_CAP
+  uint32_t* tmp = didx + SORT_CAP;                                     // K_MAX
+  double* red = reinterpret_cast<double*>(tmp + K_MAX);               // WG
+  float* ys = reinterpret_cast<float*>(red + WG);                      // d
+  const int64_t qi = blockIdx.x;
+  if (b.status[qi] != 1) return;
+  const int C = b.cand2_cnt[qi];
+  if (C > b.cap2 || C > SORT_CAP) {
+    if (threadIdx.x == 0) b.status[qi] = 2;
+    return;
+  }
+  for (int64_t t = threadIdx.x; t < a.d; t += WG) ys[t] = a.Y[qi * a.d + t];
+  __syncthreads();
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  for (int c = g; c < C; c += WG / 16) {
+    const uint32_t id = (uint32_t)b.cand2[qi * b.cap2 + c];
+    const double d2 = group16_d2(a.X, id, a.d, ys, l16);
+    if (l16 == 0) { dkey[c] = __builtin_bit_cast(uint64_t, d2); didx[c] = id; }
+  }
+  const int N = next_pow2(C > 1 ? C : 2);
+  for (int i = C + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
+  __syncthreads();
+  block_sort_pairs(dkey, didx, N);
+  const int k = (int)a.k;
+  fix_boundary(dkey, didx, C, k, a.X, a.d, ys);
+  if (threadIdx.x == 0) b.status[qi] = 0;
+  emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
+                  nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
+}
+
+// ---------------------------------------------------------------------------
+// 4. exhaustive exact scan for the rare overflow (one workgroup per query)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG)
+knn_exhaustive_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  uint64_t* dkey = reinterpret_cast<uint64_t*>(smem);
+  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + SORT_CAP);
+  uint32_t* tmp = didx + SORT_CAP;
+  double* red = reinterpret_cast<double*>(tmp + K_MAX);
+  float* ys = reinterpret_cast<float*>(red + WG);
+  __shared__ int fill_s;
+  const int64_t qi = blockIdx.x;
+  if (b.status[qi] != 2) return;
+  const int k = (int)a.k;
+  for (int64_t t = threadIdx.x; t < a.d; t += WG) ys[t] = a.Y[qi * a.d + t];
+  if (threadIdx.x == 0) fill_s = 0;
+  __syncthreads();
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  // keep a margin beyond k so that near ties at the k-th place can be re-ordered
+  const int kkeep = k + 32 < SORT_CAP / 2 ? k + 32 : SORT_CAP / 2;
+  const int chunk = SORT_CAP - kkeep;        // rows examined between sorts
+  uint64_t kth_key = ~0ull;
+  uint32_t kth_idx = 0xffffffffu;
+  for (int64_t r0 = 0; r0 < a.n; r0 += chunk) {
+    const int64_t r1 = r0 + chunk < a.n ? r0 + chunk : a.n;
+    for (int64_t r = r0 + g; r < r1; r += WG / 16) {
+      const double d2 = group16_d2(a.X, r, a.d, ys, l16);
+      const uint64_t kb = __builtin_bit_cast(uint64_t, d2);
+      if (l16 == 0 && (kb < kth_key || (kb == kth_key && (uint32_t)r < kth_idx))) {
+        const int slot = atomicAdd(&fill_s, 1);
+        dkey[slot] = kb;
+        didx[slot] = (uint32_t)r;
+      }
+    }
+    __syncthreads();
+    const int F = fill_s;
+    for (int i = F + threadIdx.x; i < SORT_CAP; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
+    __syncthreads();
+    block_sort_pairs(dkey, didx, SORT_CAP);
+    if (F >= kkeep) { kth_key = dkey[kkeep - 1]; kth_idx = didx[kkeep - 1]; }
+    __syncthreads();
+    if (threadIdx.x == 0) fill_s = F < kkeep ? F : kkeep;
+    __syncthreads();
+  }
+  fix_boundary(dkey, didx, fill_s, k, a.X, a.d, ys);
+  if (threadIdx.x == 0) b.status[qi] = 0;
+  emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
+                  nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
+}
+
+// ---------------------------------------------------------------------------
+// k = n: every row is a neighbour; Z1 is the exact FP64 kernel sum
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG)
+knn_all_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n, int64_t d,
+               double h, int kern, int32_t* __restrict__ nn, double* __restrict__ z1) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  double* red = reinterpret_cast<double*>(smem);   // WG / 16
+  float* ys = reinterpret_cast<float*>(red + WG / 16);
+  const int64_t qi = blockIdx.x;
+  for (int64_t t = threadIdx.x; t < d; t += WG) ys[t] = Y[qi * d + t];
+  for (int64_t i = threadIdx.x; i < n; i += WG) nn[qi * n + i] = (int32_t)i;
+  __syncthreads();
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  double s = 0.0;
+  for (int64_t r = g; r < n; r += WG / 16) s += kernel_value(group16_d2(X, r, d, ys, l16), h, kern);
+  if (l16 == 0) red[g] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < WG / 16; ++i) t += red[i];
+    z1[qi] = t;
+  }
+}
+
+hipError_t launch_knn_all(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
+                          double h, int kern, int32_t* nn, double* z1, hipStream_t s) {
+  if (q == 0) return hipSuccess;
+  const size_t sm = (WG / 16) * 8 + d * 4 + 16;
+  knn_all_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(X, Y, n, d, h, kern, nn, z1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// host launch
+// ---------------------------------------------------------------------------
+template <typename T>
+static hipError_t launch_tiles(const TileProblem& p, const KnnBuffers& b, bool collect,
+                               hipStream_t s) {
+  const int64_t grid = round_up(p.qtiles * p.splits, 8);
+  if (!collect)
+    knn_scan_kernel<T><<<dim3((unsigned)grid), dim3(WG), 0, s>>>(p, b.cand, b.cand_cnt,
+                                                                 (int)b.cap1, (int)b.K1, grid);
+  else
+    knn_collect_kernel<T><<<dim3((unsigned)grid), dim3(WG), 0, s>>>(p, b, grid);
+  return hipGetLastError();
+}
+
+static hipError_t launch_tiles_prec(int prec, const TileProblem& p, const KnnBuffers& b,
+                                    bool collect, hipStream_t s) {
+  switch (prec) {
+    case PREC_FP32: return launch_tiles<float>(p, b, collect, s);
+    case PREC_BF16: return launch_tiles<__bf16>(p, b, collect, s);
+    default: return launch_tiles<_Float16>(p, b, collect, s);
+  }
+}
+
+hipError_t launch_knn(int prec, const TileProblem& p, const KnnBuffers& b, const float* X,
+                      const float* Y, int64_t d, int64_t k, double h, int kern, int32_t* nn_out,
+                      hipStream_t s) {
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(b.flags), p.qtiles, 0u, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_u32(reinterpret_cast<uint32_t*>(b.status), p.q, 0u, s);
+  if (e != hipSuccess) return e;
+  e = launch_tiles_prec(prec, p, b, false, s);
+  if (e != hipSuccess) return e;
+  RefineArgs a{X, Y, p.n, p.q, d, k, p.qp, p.splits, h, kern};
+  const size_t sm1 = SORT_CAP * 8 + K_MAX * (8 + 4 + 4) + WG * 8 + d * 4;
+  knn_refine_kernel<<<dim3((unsigned)p.q), dim3(WG), sm1, s>>>(a, b, nn_out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  e = launch_tiles_prec(prec, p, b, true, s);
+  if (e != hipSuccess) return e;
+  const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + d * 4;
+  knn_refine2_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, b, nn_out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  knn_exhaustive_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, b, nn_out);
+  return hipGetLastError();
+}
+
+}  // namespace deann

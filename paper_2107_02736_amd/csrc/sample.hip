@@ -1,0 +1,137 @@
+// Random-sampling part of DEANN (Algorithm 1, lines 3-6): m uniform draws
+// with repetition from X2 = X minus the k neighbours, the exact kernel sum over
+// the drawn rows, and the combined estimate (Z1 + ((n-k)/m) Z2) / n.
+//
+// Draw j of query i uses word (j mod 4) of Philox4x64-10 (Salmon et al., SC'11)
+// with key (seed, 0) and counter (j div 4, query_offset + i, word2, 0).  The
+// rank r = floor(u (n - k) / 2^64) picks the r-th smallest element of X2, found
+// as r + #{t : nn_t - t <= r} over the neighbours sorted by index.  All of it is
+// integer arithmetic, so the drawn indices are bit-reproducible.
+//
+// The gather reads each drawn row once with 16 lanes per row (64-byte
+// coalesced segments) and evaluates ||x - y||^2 directly in FP64.
+#include "common.h"
+#include "kernels.h"
+
+namespace deann {
+
+struct Philox4x64 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ Philox4x64 philox4x64_10(uint64_t k0, uint64_t k1, uint64_t c0,
+                                                    uint64_t c1, uint64_t c2, uint64_t c3) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  Philox4x64 o;
+  o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+  return o;
+}
+
+constexpr int DRAW_CHUNK = 1024;   // draws handled per pass through LDS
+
+__device__ __forceinline__ double kval(double d2, double h, int kern) {
+  if (kern == KERNEL_GAUSSIAN) return exp(-d2 / (2.0 * h * h));
+  return exp(-sqrt(d2) / h);
+}
+
+__global__ void __launch_bounds__(WG)
+deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
+                    int64_t d, double h, int kern, int64_t k, int64_t m, uint64_t seed,
+                    uint64_t query_offset, uint64_t word2, const int32_t* __restrict__ nn_sorted,
+                    const double* __restrict__ z1, double* __restrict__ out,
+                    int32_t* __restrict__ sample_idx) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  double* kv = reinterpret_cast<double*>(smem);                    // DRAW_CHUNK
+  int32_t* sidx = reinterpret_cast<int32_t*>(kv + DRAW_CHUNK);     // DRAW_CHUNK
+  int32_t* gaps = sidx + DRAW_CHUNK;                               // k
+  float* ys = reinterpret_cast<float*>(gaps + k);                  // d
+  const int64_t qi = blockIdx.x;
+  const uint64_t size2 = (uint64_t)(n - k);
+  const double zz1 = k > 0 ? z1[qi] : 0.0;
+  if (m == 0 || size2 == 0) {
+    if (sample_idx)
+      for (int64_t j = threadIdx.x; j < m; j += WG) sample_idx[qi * m + j] = -1;
+    if (threadIdx.x == 0) out[qi] = zz1 / (double)n;
+    return;
+  }
+  for (int64_t t = threadIdx.x; t < k; t += WG) gaps[t] = nn_sorted[qi * k + t] - (int32_t)t;
+  for (int64_t t = threadIdx.x; t < d; t += WG) ys[t] = Y[qi * d + t];
+  __syncthreads();
+  const uint64_t stream = query_offset + (uint64_t)qi;
+  double total = 0.0;   // meaningful in thread 0
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  for (int64_t j0 = 0; j0 < m; j0 += DRAW_CHUNK) {
+    const int cnt = (int)(m - j0 < DRAW_CHUNK ? m - j0 : DRAW_CHUNK);
+    // draws: each thread makes one Philox block = 4 consecutive draws
+    for (int b = threadIdx.x; b * 4 < cnt; b += WG) {
+      const int64_t jb = (j0 >> 2) + b;     // j0 is a multiple of 4
+      const Philox4x64 blk = philox4x64_10(seed, 0, (uint64_t)jb, stream, word2, 0);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int jj = b * 4 + w;
+        if (jj < cnt) {
+          const uint64_t r = __umul64hi(blk.v[w], size2);
+          // #{t : gaps[t] <= r}: gaps is non-decreasing
+          int lo = 0, hi = (int)k;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((uint64_t)(int64_t)gaps[mid] <= r) lo = mid + 1; else hi = mid;
+          }
+          const int32_t idx = (int32_t)(r + (uint64_t)lo);
+          sidx[jj] = idx;
+          if (sample_idx) sample_idx[qi * m + j0 + jj] = idx;
+        }
+      }
+    }
+    __syncthreads();
+    // gather and evaluate: 16 lanes per drawn row
+    for (int jj = g; jj < cnt; jj += WG / 16) {
+      const float* xr = X + (int64_t)sidx[jj] * d;
+      double s = 0.0;
+      for (int64_t t = l16; t < d; t += 16) {
+        const double df = (double)xr[t] - (double)ys[t];
+        s = __builtin_fma(df, df, s);
+      }
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      s += __shfl_xor(s, 8, 64);
+      if (l16 == 0) kv[jj] = kval(s, h, kern);
+    }
+    __syncthreads();
+    // fixed-order reduction of the chunk
+    double* red = kv;   // reuse in place: tree over DRAW_CHUNK slots
+    for (int i = cnt + threadIdx.x; i < DRAW_CHUNK; i += WG) red[i] = 0.0;
+    __syncthreads();
+    for (int w = DRAW_CHUNK / 2; w > 0; w >>= 1) {
+      for (int i = threadIdx.x; i < w; i += WG) red[i] += red[i + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) total += red[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[qi] = (zz1 + (double)size2 / (double)m * total) / (double)n;
+}
+
+hipError_t launch_sample(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
+                         double h, int kern, int64_t k, int64_t m, uint64_t seed,
+                         uint64_t query_offset, uint64_t word2, const int32_t* nn_sorted,
+                         const double* z1, double* out, int32_t* sample_idx, hipStream_t s) {
+  if (q == 0) return hipSuccess;
+  const size_t sm = DRAW_CHUNK * (8 + 4) + k * 4 + d * 4 + 16;
+  deann_sample_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(X, Y, n, d, h, kern, k, m, seed,
+                                                              query_offset, word2, nn_sorted, z1,
+                                                              out, sample_idx);
+  return hipGetLastError();
+}
+
+}  // namespace deann

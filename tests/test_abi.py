@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+entry point, and rejects invalid arguments before launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2107_02736_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "deann.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b([a-z_]+)\s*\(", text)) - {"if", "sizeof"}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libdeann.so not built")
+    return _lib.load()
+
+
+def test_header_and_exports_agree(lib):
+    declared = _declared()
+    assert declared == set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+def _kde(lib, n=10, q=4, d=3, h=1.0, kernel=0, prec=0, out=FAKE, ws=FAKE, wsb=1 << 30, X=FAKE):
+    return lib.kde_exact(X, n, FAKE, q, d, h, kernel, prec, out, ws, wsb, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=0), _lib.EINVAL), (dict(d=0), _lib.EINVAL), (dict(q=-1), _lib.EINVAL),
+    (dict(h=0.0), _lib.EINVAL), (dict(h=float("nan")), _lib.EINVAL),
+    (dict(h=float("inf")), _lib.EINVAL), (dict(kernel=7), _lib.EINVAL),
+    (dict(prec=9), _lib.EINVAL), (dict(out=None), _lib.EINVAL), (dict(X=None), _lib.EINVAL),
+    (dict(n=1 << 31), _lib.EINVAL), (dict(ws=None), _lib.EWORKSPACE), (dict(wsb=16), _lib.EWORKSPACE),
+])
+def test_kde_exact_validation(lib, kw, status):
+    assert _kde(lib, **kw) == status
+    assert lib.deann_last_error().decode()
+
+
+def test_q_zero_is_a_noop(lib):
+    assert _kde(lib, q=0, out=None, ws=None, wsb=0) == _lib.OK
+
+
+def _dq(lib, n=100, q=4, d=3, h=1.0, kernel=0, k=5, m=10, prec=0, ws=FAKE, wsb=1 << 34):
+    return lib.deann_query(FAKE, n, FAKE, q, d, h, kernel, k, m, 0, 0, 0, prec, FAKE, FAKE, FAKE,
+                           ws, wsb, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(k=-1), _lib.EINVAL), (dict(k=101), _lib.EINVAL), (dict(m=-1), _lib.EINVAL),
+    (dict(n=5000, k=2000), _lib.EUNSUPPORTED), (dict(prec=3), _lib.EINVAL),
+    (dict(wsb=8), _lib.EWORKSPACE), (dict(h=-2.0), _lib.EINVAL),
+])
+def test_deann_query_validation(lib, kw, status):
+    assert _dq(lib, **kw) == status
+
+
+def test_backward_validation(lib):
+    # grad_out missing
+    st = lib.deann_query_backward(FAKE, 100, FAKE, 4, 3, 1.0, 0, 5, 10, FAKE, FAKE, None, FAKE,
+                                  FAKE, FAKE, 1 << 20, None)
+    assert st == _lib.EINVAL
+    # exact backward beyond d = 128
+    st = lib.kde_exact_backward(FAKE, 100, FAKE, 4, 200, 1.0, 0, FAKE, FAKE, FAKE, FAKE, 1 << 30,
+                                None)
+    assert st == _lib.EUNSUPPORTED
+
+
+def test_workspace_sizes_grow(lib):
+    a = lib.kde_exact_workspace(10_000, 1_000, 16, 0)
+    b = lib.kde_exact_workspace(1_000_000, 10_000, 128, 0)
+    assert 0 < a < b
+    assert lib.deann_query_workspace(10_000, 1_000, 16, 50, 500, 1) > 0
+    assert lib.kde_exact_workspace(0, 1, 1, 0) == 0

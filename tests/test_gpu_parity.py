@@ -1,0 +1,290 @@
+"""Parity of the HIP path with the FP64 oracle on the small mixture workload
+(n = 10,000, d = 16, q = 1,000, k = 50, m = 500) and on edge shapes."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import GAUSSIAN, EXPONENTIAL
+
+from .gpu_common import bandwidth, device, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+KNAME = {GAUSSIAN: "gaussian", EXPONENTIAL: "exponential"}
+WL = "mix10_n1e4_d16"
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+@pytest.fixture(scope="module")
+def c1(dev):
+    spec, X, Y = synth.workload(WL)
+    return X, Y, to_dev(X, dev), to_dev(Y, dev)
+
+
+@pytest.fixture(scope="module")
+def c1_exact():
+    spec, X, Y = synth.workload(WL)
+    return {kern: oracle.kde_exact(X, Y, bandwidth(WL, KNAME[kern]), kern)
+            for kern in (GAUSSIAN, EXPONENTIAL)}
+
+
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_exact_kde_fp32_within_1e5(c1, c1_exact, kern):
+    import paper_2107_02736_amd as dk
+    X, Y, Xd, Yd = c1
+    h = bandwidth(WL, KNAME[kern])
+    got = dk.kde_exact(Xd, Yd, h, KNAME[kern], "fp32").cpu().numpy()
+    err, excluded = rel_err(got, c1_exact[kern])
+    print(f"exact fp32 {KNAME[kern]}: max rel {err.max():.3e} mean {err.mean():.3e} excluded {excluded}")
+    assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_exact_kde_low_precision_bound(c1, c1_exact, kern, prec):
+    # Stated bound for 16-bit GEMM operands (8- or 11-bit significands):
+    # mean relative error <= 1% at the workload bandwidth.
+    import paper_2107_02736_amd as dk
+    X, Y, Xd, Yd = c1
+    h = bandwidth(WL, KNAME[kern])
+    got = dk.kde_exact(Xd, Yd, h, KNAME[kern], prec).cpu().numpy()
+    err, _ = rel_err(got, c1_exact[kern])
+    print(f"exact {prec} {KNAME[kern]}: max rel {err.max():.3e} mean {err.mean():.3e}")
+    assert err.mean() <= (1e-2 if prec == "bf16" else 2e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_knn_bit_exact(c1, prec):
+    import paper_2107_02736_amd as dk
+    X, Y, Xd, Yd = c1
+    k = 50
+    _, nn, _ = dk.deann_query(Xd, Yd, 2.0, k, 0, "gaussian", precision=prec)
+    nn = nn.cpu().numpy()
+    for j in range(0, Y.shape[0], 3):
+        assert np.array_equal(nn[j], oracle.knn(X, Y[j], k)), f"query {j}"
+
+
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_deann_estimate_and_samples(c1, kern):
+    import paper_2107_02736_amd as dk
+    X, Y, Xd, Yd = c1
+    h = bandwidth(WL, KNAME[kern])
+    k, m, seed = 50, 500, 0
+    out, nn, sm = dk.deann_query(Xd, Yd, h, k, m, KNAME[kern], seed=seed)
+    out, nn, sm = out.cpu().numpy(), nn.cpu().numpy(), sm.cpu().numpy()
+    for j in range(0, Y.shape[0], 10):
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, kern, k, m, seed, j)
+        assert np.array_equal(nn[j], nn_ref)
+        assert np.array_equal(sm[j], s_ref)
+        assert abs(out[j] - est) <= 1e-12 * est + 1e-300
+
+
+def test_query_offset_reproduces_batch(c1):
+    import paper_2107_02736_amd as dk
+    X, Y, Xd, Yd = c1
+    a = dk.deann_query(Xd, Yd[:300], 2.4, 50, 500, seed=9)
+    b1 = dk.deann_query(Xd, Yd[:120].contiguous(), 2.4, 50, 500, seed=9)
+    b2 = dk.deann_query(Xd, Yd[120:300].contiguous(), 2.4, 50, 500, seed=9, query_offset=120)
+    for i in range(3):
+        full = a[i].cpu()
+        split = np.concatenate([b1[i].cpu().numpy(), b2[i].cpu().numpy()])
+        assert np.array_equal(full.numpy(), split)
+
+
+def test_determinism(c1):
+    import paper_2107_02736_amd as dk
+    X, Y, Xd, Yd = c1
+    for prec in ("fp32", "bf16"):
+        r1 = dk.deann_query(Xd, Yd, 2.4, 50, 500, seed=3, precision=prec)
+        r2 = dk.deann_query(Xd, Yd, 2.4, 50, 500, seed=3, precision=prec)
+        for a, b in zip(r1, r2):
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+        e1 = dk.kde_exact(Xd, Yd, 2.4, "gaussian", prec).cpu().numpy()
+        e2 = dk.kde_exact(Xd, Yd, 2.4, "gaussian", prec).cpu().numpy()
+        assert np.array_equal(e1, e2)
+
+
+# --------------------------------------------------------------------------
+# edge shapes and degenerate parameters
+# --------------------------------------------------------------------------
+
+def _small(n, q, d, seed=0):
+    rng = np.random.default_rng(seed)
+    cen = rng.uniform(-3, 3, size=(5, d))
+    X = (cen[rng.integers(0, 5, n)] + rng.normal(size=(n, d))).astype(np.float32)
+    Y = (cen[rng.integers(0, 5, q)] + rng.normal(size=(q, d))).astype(np.float32)
+    return X, Y
+
+
+@pytest.mark.parametrize("n,q,d", [(1000, 37, 9), (129, 1, 3), (1, 5, 2), (300, 130, 33),
+                                   (2500, 64, 64)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_edge_shapes_exact_and_knn(dev, n, q, d, prec):
+    import paper_2107_02736_amd as dk
+    X, Y = _small(n, q, d, seed=n + d)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h = 1.5
+    ref = oracle.kde_exact(X, Y, h, GAUSSIAN)
+    got = dk.kde_exact(Xd, Yd, h, "gaussian", prec).cpu().numpy()
+    err, _ = rel_err(got, ref)
+    assert err.max() <= (1e-5 if prec == "fp32" else 5e-2)
+    k = min(n, 7)
+    m = 11
+    out, nn, sm = dk.deann_query(Xd, Yd, h, k, m, precision=prec, seed=1)
+    out, nn, sm = out.cpu().numpy(), nn.cpu().numpy(), sm.cpu().numpy()
+    for j in range(q):
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, GAUSSIAN, k, m, 1, j)
+        assert np.array_equal(nn[j], nn_ref)
+        assert np.array_equal(sm[j], s_ref)
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
+
+
+@pytest.mark.parametrize("k,m", [(0, 40), (10, 0), (0, 0), (400, 50), (395, 3000), (1, 1)])
+def test_degenerate_k_m(dev, k, m):
+    import paper_2107_02736_amd as dk
+    X, Y = _small(400, 20, 5, seed=4)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h = 1.1
+    out, nn, sm = dk.deann_query(Xd, Yd, h, k, m, "exponential", seed=2)
+    out, nn, sm = out.cpu().numpy(), nn.cpu().numpy(), sm.cpu().numpy()
+    for j in range(20):
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, EXPONENTIAL, k, m, 2, j)
+        assert np.array_equal(nn[j], nn_ref)
+        assert np.array_equal(sm[j], s_ref)
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
+    if k == 400:   # k = n is the exact KDE
+        ref = oracle.kde_exact(X, Y, h, EXPONENTIAL)
+        assert np.allclose(out, ref, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_knn_exact_ties_and_duplicates(dev, prec):
+    # integer lattice data: many exactly equal distances, duplicate rows
+    import paper_2107_02736_amd as dk
+    rng = np.random.default_rng(12)
+    X = rng.integers(-2, 3, size=(700, 3)).astype(np.float32)
+    Y = rng.integers(-2, 3, size=(30, 3)).astype(np.float32)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    for k in (1, 9, 40):
+        _, nn, _ = dk.deann_query(Xd, Yd, 1.0, k, 0, precision=prec)
+        nn = nn.cpu().numpy()
+        for j in range(30):
+            assert np.array_equal(nn[j], oracle.knn(X, Y[j], k)), (k, j)
+
+
+def test_extreme_bandwidths(dev):
+    import paper_2107_02736_amd as dk
+    X, Y = _small(500, 8, 4, seed=2)
+    Y[0] = X[17]
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    big = dk.kde_exact(Xd, Yd, 1e6, "gaussian").cpu().numpy()
+    assert np.allclose(big, 1.0, rtol=1e-6)
+    tiny = dk.kde_exact(Xd, Yd, 1e-4, "gaussian").cpu().numpy()
+    assert tiny[0] == pytest.approx(1.0 / 500, rel=1e-6)
+    out, _, _ = dk.deann_query(Xd, Yd, 1e-4, 3, 10, seed=0)
+    assert out.cpu().numpy()[0] == pytest.approx(1.0 / 500, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# adjoints
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_deann_backward_vs_oracle(dev, kern):
+    import paper_2107_02736_amd as dk
+    X, Y = _small(3000, 40, 12, seed=7)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h, k, m = 1.3, 16, 100
+    out, nn, sm = dk.deann_query(Xd, Yd, h, k, m, KNAME[kern], seed=4)
+    g = np.linspace(0.5, 1.5, 40)
+    gy, gh = dk.deann_query_backward(Xd, Yd, h, k, m, nn, sm, to_dev(g, dev), KNAME[kern])
+    gy, gh = gy.cpu().numpy(), float(gh.cpu().numpy()[0])
+    nn, sm = nn.cpu().numpy(), sm.cpu().numpy()
+    gh_ref = 0.0
+    for j in range(40):
+        _, gy_ref, ghj = oracle.deann_grad(X, Y[j], h, kern, nn[j], sm[j], m)
+        assert np.linalg.norm(gy[j] - g[j] * gy_ref) <= 1e-6 * np.linalg.norm(g[j] * gy_ref) + 1e-30
+        gh_ref += g[j] * ghj
+    assert gh == pytest.approx(gh_ref, rel=1e-10)
+
+
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_exact_backward_vs_oracle(dev, kern):
+    import paper_2107_02736_amd as dk
+    X, Y = _small(6000, 70, 64, seed=9)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h = 6.0
+    g = np.linspace(1.0, 2.0, 70)
+    gy, gh = dk.kde_exact_backward(Xd, Yd, h, to_dev(g, dev), KNAME[kern])
+    gy, gh = gy.cpu().numpy(), float(gh.cpu().numpy()[0])
+    gh_ref, gh_scale = 0.0, 0.0
+    for j in range(70):
+        mu, gy_ref, ghj = oracle.kde_grad(X, Y[j].astype(np.float64), h, kern)
+        d2 = oracle.sq_dists(X, Y[j])
+        K = oracle.kernel_values(d2, h, kern)
+        r = np.sqrt(d2)
+        # normwise scale: the sum of the magnitudes of the terms of the gradient
+        if kern == GAUSSIAN:
+            scale = (K * r).sum() / (X.shape[0] * h * h)
+        else:
+            scale = K.sum() / (X.shape[0] * h)
+        assert np.linalg.norm(gy[j] - g[j] * gy_ref) <= 1e-4 * g[j] * scale
+        gh_ref += g[j] * ghj
+        gh_scale += g[j] * abs(ghj)
+    assert abs(gh - gh_ref) <= 1e-4 * gh_scale
+
+
+def test_autograd_matches_finite_differences(dev):
+    # DEANN with the index sets fixed: central differences of the GPU forward.
+    import torch
+
+    import paper_2107_02736_amd as dk
+    X, Y = _small(2000, 6, 8, seed=3)
+    Xd = to_dev(X, dev)
+    h, k, m = 1.2, 12, 64
+    Yr = to_dev(Y, dev).requires_grad_(True)
+    hr = torch.tensor(h, dtype=torch.float64, requires_grad=True)
+    out = dk.deann_kde(Yr, hr, Xd, k, m, seed=8)
+    out.sum().backward()
+    gy = Yr.grad.cpu().numpy()
+    nn0 = dk.deann_query(Xd, to_dev(Y, dev), h, k, m, seed=8)[1].cpu().numpy()
+    checked = 0
+    for j in range(6):
+        for t in range(8):
+            step = 1e-3 * h
+            yp, ym = Y.copy(), Y.copy()
+            yp[j, t] += step
+            ym[j, t] -= step
+            dp = float(yp[j, t]) - float(Y[j, t])
+            dm = float(Y[j, t]) - float(ym[j, t])
+            rp = dk.deann_query(Xd, to_dev(yp, dev), h, k, m, seed=8)
+            rm = dk.deann_query(Xd, to_dev(ym, dev), h, k, m, seed=8)
+            if not (np.array_equal(rp[1].cpu().numpy()[j], nn0[j])
+                    and np.array_equal(rm[1].cpu().numpy()[j], nn0[j])):
+                continue   # the neighbour set moved: the estimate jumps there
+            fd = (rp[0].cpu().numpy()[j] - rm[0].cpu().numpy()[j]) / (dp + dm)
+            assert gy[j, t] == pytest.approx(fd, rel=2e-3, abs=1e-6 * abs(out[j].item()) / h)
+            checked += 1
+    assert checked >= 40
+    fp = dk.deann_query(Xd, to_dev(Y, dev), h * (1 + 1e-4), k, m, seed=8)[0].cpu().numpy().sum()
+    fm = dk.deann_query(Xd, to_dev(Y, dev), h * (1 - 1e-4), k, m, seed=8)[0].cpu().numpy().sum()
+    assert hr.grad.item() == pytest.approx((fp - fm) / (2e-4 * h), rel=1e-4)
+
+
+def test_mean_shift_matches_oracle(dev):
+    import paper_2107_02736_amd as dk
+    X, Y = _small(3000, 5, 6, seed=11)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h = 1.0
+    ye = dk.mean_shift(Xd, Yd, h, 5, "exact").cpu().numpy()
+    yd = dk.mean_shift(Xd, Yd, h, 5, "deann", k=20, m=100, seed=1).cpu().numpy()
+    for j in range(5):
+        ref_e = oracle.mean_shift_exact(X, Y[j], h, 5)
+        assert np.allclose(ye[j], ref_e, rtol=1e-4, atol=1e-4)
+        ref_d = oracle.mean_shift_deann(X, Y[j], h, 20, 100, 1, j, 5)
+        assert np.allclose(yd[j], ref_d, rtol=1e-4, atol=1e-4)

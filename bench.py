@@ -1,0 +1,220 @@
+"""Benchmark of DEANN's query path on one MI355X.
+
+One step = the whole hot path over one batch of queries:
+  exact KDE (FP32 MFMA tiles, FP64 reduction)             kde_exact
+  DEANN estimate with the BF16 scan + FP64 refinement      deann_query
+  DEANN adjoint (d/dy, d/dh)                               deann_query_backward
+  exact-KDE adjoint (d/dy, d/dh), tiles recomputed         kde_exact_backward
+on the synthetic 100-cluster mixture with n = 1,000,000, d = 128 and
+q = 10,000 queries, Gaussian kernel, k = 100, m = 1,000.  Inputs are resident
+in HBM before the timed region.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("queries/s at ≤1% rel KDE err, BF16+refine vs FP32; exact KDE % MFMA peak")
+WORKLOAD = "mix100_n1e6_d128"
+K_NN, M_SAMPLES, KERNEL = 100, 1000, "gaussian"
+PEAK_FP32_MFMA = 157.3e12     # dense FP32 matrix, MI355X
+PEAK_BF16_MFMA = 2.5e15
+PEAK_HBM = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=6, help="queries in the oracle sample")
+    return ap.parse_args()
+
+
+def bandwidth(workload, kernel):
+    with open(os.path.join(ROOT, "tests", "golden", "bandwidths.json")) as f:
+        return float(json.load(f)[workload][kernel]["h"])
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the query path needs no communication "
+              "(queries shard with query_offset); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2107_02736_amd as dk
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    spec, X, Y = synth.workload(args.workload)
+    h = bandwidth(args.workload, KERNEL)
+    n, d = X.shape
+    q = Y.shape[0]
+    Xd = torch.from_numpy(X).to(dev)
+    Yd = torch.from_numpy(Y).to(dev)
+    gout = torch.ones(q, dtype=torch.float64, device=dev)
+    print(f"# data {time.time() - t0:.1f}s  n={n} d={d} q={q} h={h:.6g}", file=sys.stderr,
+          flush=True)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    comp = {"kde_exact_fp32": [], "deann_bf16": [], "deann_backward": [], "kde_exact_backward": []}
+
+    def step(record):
+        e = [ev() for _ in range(5)]
+        e[0].record()
+        mu = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32")
+        e[1].record()
+        est, nn, sm = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16")
+        e[2].record()
+        gy, gh = dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn, sm, gout, KERNEL)
+        e[3].record()
+        gye, ghe = dk.kde_exact_backward(Xd, Yd, h, gout, KERNEL)
+        e[4].record()
+        if record is not None:
+            record.append(e)
+        return mu, est, nn, sm, gy, gh, gye, ghe
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    events = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        res = step(events)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    names = list(comp)
+    for e in events:
+        for i, name in enumerate(names):
+            comp[name].append(e[i].elapsed_time(e[i + 1]))
+    ms_step = wall * 1e3 / args.steps
+    comp_ms = {k: float(np.mean(v)) for k, v in comp.items()}
+    mu, est, nn, sm, gy, gh, gye, ghe = res
+
+    # FP32-scan DEANN for the BF16+refine vs FP32 comparison (same seed)
+    for _ in range(max(1, args.warmup)):
+        est32, nn32, sm32 = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
+                                           precision="fp32")
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    reps = max(2, args.steps // 2)
+    a.record()
+    for _ in range(reps):
+        est32, nn32, sm32 = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
+                                           precision="fp32")
+    b.record()
+    torch.cuda.synchronize()
+    ms_deann32 = a.elapsed_time(b) / reps
+
+    mu_h = mu.cpu().numpy()
+    est_h, est32_h = est.cpu().numpy(), est32.cpu().numpy()
+    same_idx = bool(torch.equal(nn, nn32) and torch.equal(sm, sm32))
+    keep = mu_h >= 1e-16
+    rel_bf16_vs_fp32 = float(np.max(np.abs(est_h - est32_h)[keep] / est32_h[keep])) if keep.any() else 0.0
+    rel_deann_vs_exact = np.abs(est_h[keep] - mu_h[keep]) / mu_h[keep]
+
+    flops_exact = 2.0 * n * d * q
+    roof_achieved = flops_exact / (comp_ms["kde_exact_fp32"] * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": q / (ms_step * 1e-3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 scan + f32 exact tiles + f64 refine/reductions",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "q": q, "kernel": KERNEL, "h": h,
+                   "k": K_NN, "m": M_SAMPLES, "deann_scan": "bf16", "exact": "fp32"},
+        "roofline": {"bound": "mfma", "kernel": "kde_tile_kernel<float,gaussian>",
+                     "achieved": roof_achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                     "unit": "TFLOP/s", "frac": roof_achieved / PEAK_FP32_MFMA, "traffic": None,
+                     "flops_per_launch": flops_exact,
+                     "note": "achieved over the whole kde_exact call (prep + tiles + reduction)"},
+        "components_ms": comp_ms,
+        "queries_per_s": {
+            "step": q / (ms_step * 1e-3),
+            "deann_bf16_refine": q / (comp_ms["deann_bf16"] * 1e-3),
+            "deann_fp32": q / (ms_deann32 * 1e-3),
+            "kde_exact_fp32": q / (comp_ms["kde_exact_fp32"] * 1e-3),
+            "deann_backward": q / (comp_ms["deann_backward"] * 1e-3),
+            "kde_exact_backward": q / (comp_ms["kde_exact_backward"] * 1e-3),
+        },
+        "accuracy": {
+            "deann_bf16_vs_fp32_same_indices": same_idx,
+            "deann_bf16_vs_fp32_max_rel": rel_bf16_vs_fp32,
+            "deann_vs_exact_mean_rel": float(rel_deann_vs_exact.mean()) if keep.any() else None,
+            "deann_vs_exact_median_rel": float(np.median(rel_deann_vs_exact)) if keep.any() else None,
+            "queries_below_1e-16": int((~keep).sum()),
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["parity_sample"] = cpu_baseline(
+            X, Y, h, args.cpu_sample, mu_h, est_h, nn.cpu().numpy(), sm.cpu().numpy(),
+            gy.cpu().numpy())
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu):
+    """The FP64 oracle timed on the host for a few queries of the same workload,
+    doing the same per-query work as one step; also checks those queries."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    sub = synth.query_subset(Y.shape[0], size, seed=11)
+    t0 = time.perf_counter()
+    rel_exact, rel_deann, nn_ok, sm_ok, rel_gy = [], [], True, True, []
+    for j in sub:
+        mu = oracle.kde_exact(X, Y[j:j + 1], h, oracle.GAUSSIAN)[0]
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, oracle.GAUSSIAN, K_NN, M_SAMPLES,
+                                                   0, int(j))
+        _, gy_ref, _ = oracle.deann_grad(X, Y[j], h, oracle.GAUSSIAN, nn_ref, s_ref, M_SAMPLES)
+        oracle.kde_grad(X, Y[j], h, oracle.GAUSSIAN)
+        if mu >= 1e-16:
+            rel_exact.append(abs(mu_gpu[j] - mu) / mu)
+            rel_deann.append(abs(est_gpu[j] - est) / est)
+        nn_ok &= bool(np.array_equal(nn_gpu[j], nn_ref))
+        sm_ok &= bool(np.array_equal(sm_gpu[j], s_ref))
+        nrm = np.linalg.norm(gy_ref)
+        if nrm > 0:
+            rel_gy.append(float(np.linalg.norm(gy_gpu[j] - gy_ref) / nrm))
+    dt = time.perf_counter() - t0
+    base = {"value": len(sub) / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sub)} queries of the same workload, full step per query "
+                      "(exact KDE, DEANN, both adjoints), FP64 NumPy, single thread",
+            "seconds": dt}
+    par = {"queries": [int(j) for j in sub], "nn_equal": nn_ok, "samples_equal": sm_ok,
+           "exact_fp32_max_rel": max(rel_exact) if rel_exact else None,
+           "deann_max_rel": max(rel_deann) if rel_deann else None,
+           "deann_grad_y_max_rel": max(rel_gy) if rel_gy else None}
+    return base, par
+
+
+if __name__ == "__main__":
+    main()

@@ -89,7 +89,7 @@ int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, d
  *   nn_idx      [q, k] int32, neighbour indices sorted ascending, or NULL.
  *   sample_idx  [q, m] int32, drawn indices in draw order (-1 when X2 is
  *               empty), or NULL.  Both are needed by deann_query_backward.
- * Requirements: as kde_exact, plus 0 <= k <= n with k <= 1008 or k == n,
+ * Requirements: as kde_exact, plus 0 <= k <= n with k <= 496 or k == n,
  * m >= 0, n < 2^31.
  * ------------------------------------------------------------------------- */
 size_t deann_query_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,

@@ -34,7 +34,7 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 constexpr int64_t kAlign = 256;
-constexpr int64_t kMaxK = 1008;            // k limit of the candidate-list kernels
+constexpr int64_t kMaxK = 496;             // k limit of the candidate-list kernels (K1 <= 512)
 constexpr int64_t kCenterRows = 256;       // row slices of the column-mean reduction
 constexpr int64_t kSortCap = 4096;         // second-pass candidate capacity per query
 
@@ -64,9 +64,11 @@ struct Prep {
   float* c;
   double* cpart;
   char* Xs;
-  float *xnorm, *xknorm, *xerr;
+  double* xnorm;
+  float *xknorm, *xerr;
   char* Ys;
-  float *ynorm, *yknorm, *yerr;
+  double* ynorm;
+  float *yknorm, *yerr;
   uint32_t* err_max;
   int64_t dp, np, qp;
 };
@@ -80,11 +82,11 @@ Prep carve_prep(Carve& cv, int64_t n, int64_t q, int64_t d, int prec) {
   p.c = cv.take<float>(d);
   p.cpart = cv.take<double>(kCenterRows * d);
   p.Xs = cv.take<char>(p.np * p.dp * es);
-  p.xnorm = cv.take<float>(p.np);
+  p.xnorm = cv.take<double>(p.np);
   p.xknorm = cv.take<float>(p.np);
   p.xerr = cv.take<float>(p.np);
   p.Ys = cv.take<char>(p.qp * p.dp * es);
-  p.ynorm = cv.take<float>(p.qp);
+  p.ynorm = cv.take<double>(p.qp);
   p.yknorm = cv.take<float>(p.qp);
   p.yerr = cv.take<float>(p.qp);
   p.err_max = cv.take<uint32_t>(2);
@@ -159,7 +161,8 @@ int check_common(const float* X, int64_t n, const float* Y, int64_t q, int64_t d
 
 // ---- per-path workspace plans -------------------------------------------------
 constexpr int64_t kKdeSplitTarget = 4096;
-constexpr int64_t kKnnSplitTarget = 2048;
+constexpr int64_t kKnnSplitTarget = 512;     // selection scan: about one wave of workgroups
+constexpr int64_t kCollectSplitTarget = 4096;
 
 struct KdePlan {
   Prep prep;
@@ -201,7 +204,9 @@ DeannPlan plan_deann(void* ws, int64_t n, int64_t q, int64_t d, int64_t k, int p
   const int64_t splits = choose_splits(qtiles, ntiles, kKnnSplitTarget);
   KnnBuffers& b = P.kb;
   b.K1 = knn_K1(k);
-  b.cap1 = 4 * b.K1 > 512 ? 4 * b.K1 : 512;
+  // a list must hold K1 kept entries plus one tile (BN) of new ones
+  b.cap1 = 256;
+  while (b.cap1 < 2 * b.K1 + BN) b.cap1 <<= 1;
   b.cand = cv.take<uint64_t>(splits * P.prep.qp * b.cap1);
   b.cand_cnt = cv.take<int32_t>(splits * P.prep.qp);
   P.nn_internal = cv.take<int32_t>(q * (k > 0 ? k : 1));
@@ -310,7 +315,8 @@ int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
     e = run_prep(P.prep, X, n, Y, q, d, precision, s);
     if (e != hipSuccess) return hip_fail(e, "prep");
     TileProblem tp = make_problem(P.prep, n, q, precision, kKnnSplitTarget);
-    e = launch_knn(precision, tp, P.kb, X, Y, d, k, h, kernel, nullptr, s);
+    TileProblem tc = make_problem(P.prep, n, q, precision, kCollectSplitTarget);
+    e = launch_knn(precision, tp, tc, P.kb, X, Y, d, k, h, kernel, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "knn");
   }
   e = launch_sample(X, Y, n, q, d, h, kernel, k, m, seed, query_offset, word2, P.kb.nn_work,

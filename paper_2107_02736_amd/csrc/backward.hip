@@ -155,7 +155,7 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
   constexpr int DP = TB * 16;
   constexpr int XS = DP + 4;                 // LDS row stride (floats) of the data tile
 
-  float yn[4];
+  double yn[4];
 #pragma unroll
   for (int bq = 0; bq < 4; ++bq) yn[bq] = p.ynorm[qt * BQ + wq * 64 + bq * 16 + (lane & 15)];
   f32x4 gacc[4][TB];
@@ -180,11 +180,11 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
       for (int r = 0; r < 4; ++r) {
         const int64_t row = t * BN + wi * 64 + bi * 16 + 4 * (lane >> 4) + r;
         const bool valid = row < p.n;
-        const float xn = p.xnorm[row];
+        const double xn = p.xnorm[row];
 #pragma unroll
         for (int bq = 0; bq < 4; ++bq) {
-          const float s = acc[bi][bq][r];
-          const float d2 = fmaxf(0.f, __builtin_fmaf(-2.f, s, xn + yn[bq]));
+          const double s = (double)acc[bi][bq][r];
+          const float d2 = fmaxf(0.f, (float)__builtin_fma(-2.0, s, xn + yn[bq]));
           float w, dh;
           if (KERN == KERNEL_GAUSSIAN) {
             const float K = __builtin_amdgcn_exp2f(-L * d2);

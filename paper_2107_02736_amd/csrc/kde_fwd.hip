@@ -16,26 +16,22 @@ namespace deann {
 template <typename T, int KERN>
 __global__ void __launch_bounds__(WG, 2)
 kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_t ld_bytes,
-                int nchunks, const float* __restrict__ ynorm, const float* __restrict__ xnorm,
-                int64_t n, int64_t qtiles, int64_t splits, int64_t ntiles, float L,
+                int nchunks, const double* __restrict__ ynorm, const double* __restrict__ xnorm,
+                int64_t n, int64_t qtiles, int64_t splits, int64_t ntiles, double L,
                 double* __restrict__ partial, int64_t qp, int64_t grid) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
+  __shared__ double yns[BQ];
   const int64_t V = xcd_virtual_id(blockIdx.x, grid);
   if (V >= qtiles * splits) return;
   const int64_t split = V / qtiles, qt = V % qtiles;
   const int64_t t0 = split * ntiles / splits, t1 = (split + 1) * ntiles / splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
+  const float Lf = (float)L;
 
-  // query-side constants of this lane's 16 rows
-  float yb[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float yn = ynorm[qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r];
-      yb[i][r] = (KERN == KERNEL_GAUSSIAN) ? -L * yn : yn;
-    }
+  // query norms of the tile, kept in FP64: the norm + norm - 2 dot
+  // combination is where the GEMM form cancels
+  if (threadIdx.x < BQ) yns[threadIdx.x] = ynorm[qt * BQ + threadIdx.x];
   double sum[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -46,38 +42,34 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
   for (int64_t t = t0; t < t1; ++t) {
     f32x4 acc[4][4];
     tile_dot<T>(acc, yq, Xs + t * BN * ld_bytes, ld_bytes, nchunks, lds, wq, wn, lane);
-    float part[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) part[i][r] = 0.f;
+    double xn[4];
+    bool valid[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-      const bool valid = col < n;
-      const float xn = xnorm[col];
-      const float xb = (KERN == KERNEL_GAUSSIAN) ? -L * xn : xn;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float s = acc[i][j][r];
-          float kv;
-          if (KERN == KERNEL_GAUSSIAN) {
-            // -d^2 / (2 h^2) in log2 units, clamped at d^2 >= 0
-            const float arg = fminf(0.f, __builtin_fmaf(2.f * L, s, yb[i][r] + xb));
-            kv = __builtin_amdgcn_exp2f(arg);
-          } else {
-            const float d2 = fmaxf(0.f, __builtin_fmaf(-2.f, s, yb[i][r] + xb));
-            kv = __builtin_amdgcn_exp2f(-L * __builtin_sqrtf(d2));
-          }
-          part[i][r] += valid ? kv : 0.f;
-        }
+      valid[j] = col < n;
+      xn[j] = xnorm[col];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sum[i][r] += (double)part[i][r];
+      for (int r = 0; r < 4; ++r) {
+        const double yn = yns[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
+        float part = 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double d2d = __builtin_fma(-2.0, (double)acc[i][j][r], yn + xn[j]);
+          const float d2 = fmaxf(0.f, (float)d2d);
+          float kv;
+          if (KERN == KERNEL_GAUSSIAN)
+            kv = __builtin_amdgcn_exp2f(-Lf * d2);   // exp(-d^2 / (2 h^2))
+          else
+            kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));   // exp(-d / h)
+          part += valid[j] ? kv : 0.f;
+        }
+        sum[i][r] += (double)part;
+      }
+    }
   }
 
   // reduce over the 16 lanes that share rows, then over the two column waves
@@ -115,7 +107,7 @@ __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t sp
 }
 
 template <typename T>
-static hipError_t launch_kde_t(const TileProblem& p, int kern, float L, double* partial,
+static hipError_t launch_kde_t(const TileProblem& p, int kern, double L, double* partial,
                                hipStream_t s) {
   const int64_t work = p.qtiles * p.splits;
   const int64_t grid = round_up(work, 8);
@@ -133,7 +125,7 @@ static hipError_t launch_kde_t(const TileProblem& p, int kern, float L, double* 
 hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, double* partial,
                             double* out, hipStream_t s) {
   const double log2e = 1.4426950408889634;
-  const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
+  const double L = kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h;
   hipError_t e;
   switch (prec) {
     case PREC_FP32: e = launch_kde_t<float>(p, kern, L, partial, s); break;

@@ -12,8 +12,8 @@ struct TileProblem {
   const char* Xs;        // prepared data     [np][dp]
   int64_t ld_bytes;      // row stride of Ys and Xs in bytes (multiple of 128)
   int nchunks;           // ld_bytes / 128
-  const float* ynorm;    // ||y~||^2          [qp]
-  const float* xnorm;    // ||x~||^2          [np]
+  const double* ynorm;   // ||y~||^2          [qp]
+  const double* xnorm;   // ||x~||^2          [np]
   const float* yknorm;   // scaled norms for lower-bound keys [qp]
   const float* xknorm;   //                                   [np]
   int64_t n, q;          // true sizes
@@ -26,7 +26,7 @@ hipError_t launch_center(const float* X, int64_t n, int64_t d, double* part, int
                          hipStream_t s);
 hipError_t launch_prep_rows_prec(int prec, const float* src, int64_t rows, int64_t rows_padded,
                                  int64_t d, int64_t dp, const float* c, double a_scale, void* dst,
-                                 float* norm, float* knorm, float* err, uint32_t* err_max,
+                                 double* norm, float* knorm, float* err, uint32_t* err_max,
                                  hipStream_t s);
 
 hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, double* partial,
@@ -36,7 +36,7 @@ hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, 
 struct KnnBuffers {
   uint64_t* cand;        // [splits][qp][cap1] packed (key, index), scan lists
   int32_t* cand_cnt;     // [splits][qp]
-  int64_t cap1;          // list capacity per (split, query) = K1 + pending
+  int64_t cap1;          // list capacity per (split, query): 256, 512, 1024 or 2048
   int64_t K1;            // kept per list
   int32_t* nn_work;      // [q][k] neighbours sorted by index (internal copy)
   double* z1;            // [q] sum of kernel values over the neighbours
@@ -50,9 +50,10 @@ struct KnnBuffers {
   const uint32_t* xerr_max;
 };
 
-hipError_t launch_knn(int prec, const TileProblem& p, const KnnBuffers& b, const float* X,
-                      const float* Y, int64_t d, int64_t k, double h, int kern, int32_t* nn_out,
-                      hipStream_t s);
+// p: geometry of the selection scan, pc: of the second-pass collect (more splits)
+hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, const KnnBuffers& b,
+                      const float* X, const float* Y, int64_t d, int64_t k, double h, int kern,
+                      int32_t* nn_out, hipStream_t s);
 
 hipError_t launch_knn_all(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                           double h, int kern, int32_t* nn, double* z1, hipStream_t s);

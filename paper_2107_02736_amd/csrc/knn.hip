@@ -71,6 +71,44 @@ __device__ __forceinline__ int next_pow2(int v) {
   return p;
 }
 
+// Bitonic sort of 64*EPL packed keys held in registers by one wave, ascending;
+// element e = lane * EPL + r.  Partners within a lane are swapped in
+// registers, across lanes exchanged with shuffles; no LDS, no barrier.
+template <int EPL>
+__device__ __forceinline__ void wave_sort_u64(uint64_t (&v)[EPL], int lane) {
+  constexpr int N = 64 * EPL;
+#pragma unroll
+  for (int kk = 2; kk <= N; kk <<= 1) {
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j < EPL) {
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+          if ((r & j) == 0) {
+            const int e = lane * EPL + r;
+            const bool up = (e & kk) == 0;
+            const uint64_t a = v[r], b = v[r ^ j];
+            const bool sw = (a > b) == up;
+            v[r] = sw ? b : a;
+            v[r ^ j] = sw ? a : b;
+          }
+        }
+      } else {
+        const int lj = j / EPL;
+        const bool lower = (lane & lj) == 0;
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+          const int e = lane * EPL + r;
+          const bool up = (e & kk) == 0;
+          const uint64_t o = __shfl_xor(v[r], lj, 64);
+          const uint64_t mn = v[r] < o ? v[r] : o, mx = v[r] < o ? o : v[r];
+          v[r] = (lower == up) ? mn : mx;
+        }
+      }
+    }
+  }
+}
+
 // Exact FP64 squared distance of row `row` of X to the query held in LDS,
 // computed by a group of 16 consecutive lanes (all 16 get the result).
 __device__ __forceinline__ double group16_d2(const float* __restrict__ X, int64_t row, int64_t d,
@@ -202,14 +240,14 @@ __device__ void emit_neighbours(const uint64_t* key, uint32_t* idx, uint32_t* tm
 // ---------------------------------------------------------------------------
 // 1. scan
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int EPL>   // list capacity = 64 * EPL
 __global__ void __launch_bounds__(WG, 2)
 knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt,
-                int cap1, int K1, int64_t grid) {
+                int K1, int64_t grid) {
+  constexpr int cap1 = 64 * EPL;
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
   __shared__ float thr[BQ];
   __shared__ int cnt[BQ];
-  __shared__ int need[BQ];
   const int64_t V = xcd_virtual_id(blockIdx.x, grid);
   if (V >= p.qtiles * p.splits) return;
   const int64_t split = V / p.qtiles, qt = V % p.qtiles;
@@ -257,26 +295,32 @@ knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
       }
     }
     __syncthreads();
-    // compaction of lists that might overflow (or, at the end, of every list above K1)
+    // compaction of lists that might overflow (or, at the end, of every list
+    // above K1): each wave sorts its own queries' lists in registers
     const int lim = last ? K1 : limit;
-    if (threadIdx.x < BQ) need[threadIdx.x] = cnt[threadIdx.x] > lim;
-    __syncthreads();
-    uint64_t* buf = reinterpret_cast<uint64_t*>(lds);
-    for (int ql = 0; ql < BQ; ++ql) {
-      if (!need[ql]) continue;
+    for (int ql = wave; ql < BQ; ql += WG / 64) {
       const int c = cnt[ql];
-      const int N = next_pow2(c);
+      if (c <= lim) continue;
       uint64_t* lst = lists + (int64_t)ql * cap1;
-      for (int i = threadIdx.x; i < N; i += WG) buf[i] = i < c ? lst[i] : ~0ull;
-      __syncthreads();
-      block_sort_u64(buf, N);
-      for (int i = threadIdx.x; i < K1; i += WG) lst[i] = buf[i];
-      if (threadIdx.x == 0) {
-        cnt[ql] = K1;
-        thr[ql] = key_float((uint32_t)(buf[K1 - 1] >> 32));
+      uint64_t v[EPL];
+#pragma unroll
+      for (int r = 0; r < EPL; ++r) {
+        const int e = lane * EPL + r;
+        v[r] = e < c ? lst[e] : ~0ull;
       }
-      __syncthreads();
+      wave_sort_u64<EPL>(v, lane);
+#pragma unroll
+      for (int r = 0; r < EPL; ++r) {
+        const int e = lane * EPL + r;
+        if (e < K1) lst[e] = v[r];
+      }
+      const uint64_t kth = __shfl(v[(K1 - 1) % EPL], (K1 - 1) / EPL, 64);
+      if (lane == 0) {
+        cnt[ql] = K1;
+        thr[ql] = key_float((uint32_t)(kth >> 32));
+      }
     }
+    __syncthreads();
   }
   if (threadIdx.x < BQ) cand_cnt[split * p.qp + qt * BQ + threadIdx.x] = cnt[threadIdx.x];
 }
@@ -544,11 +588,17 @@ template <typename T>
 static hipError_t launch_tiles(const TileProblem& p, const KnnBuffers& b, bool collect,
                                hipStream_t s) {
   const int64_t grid = round_up(p.qtiles * p.splits, 8);
-  if (!collect)
-    knn_scan_kernel<T><<<dim3((unsigned)grid), dim3(WG), 0, s>>>(p, b.cand, b.cand_cnt,
-                                                                 (int)b.cap1, (int)b.K1, grid);
-  else
-    knn_collect_kernel<T><<<dim3((unsigned)grid), dim3(WG), 0, s>>>(p, b, grid);
+  const dim3 g((unsigned)grid), blk(WG);
+  if (collect) {
+    knn_collect_kernel<T><<<g, blk, 0, s>>>(p, b, grid);
+  } else {
+    switch (b.cap1) {
+      case 256: knn_scan_kernel<T, 4><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1, grid); break;
+      case 512: knn_scan_kernel<T, 8><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1, grid); break;
+      case 1024: knn_scan_kernel<T, 16><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1, grid); break;
+      default: knn_scan_kernel<T, 32><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1, grid); break;
+    }
+  }
   return hipGetLastError();
 }
 
@@ -561,9 +611,9 @@ static hipError_t launch_tiles_prec(int prec, const TileProblem& p, const KnnBuf
   }
 }
 
-hipError_t launch_knn(int prec, const TileProblem& p, const KnnBuffers& b, const float* X,
-                      const float* Y, int64_t d, int64_t k, double h, int kern, int32_t* nn_out,
-                      hipStream_t s) {
+hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, const KnnBuffers& b,
+                      const float* X, const float* Y, int64_t d, int64_t k, double h, int kern,
+                      int32_t* nn_out, hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(b.flags), p.qtiles, 0u, s);
   if (e != hipSuccess) return e;
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(b.status), p.q, 0u, s);
@@ -574,7 +624,7 @@ hipError_t launch_knn(int prec, const TileProblem& p, const KnnBuffers& b, const
   const size_t sm1 = SORT_CAP * 8 + K_MAX * (8 + 4 + 4) + WG * 8 + d * 4;
   knn_refine_kernel<<<dim3((unsigned)p.q), dim3(WG), sm1, s>>>(a, b, nn_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  e = launch_tiles_prec(prec, p, b, true, s);
+  e = launch_tiles_prec(prec, pc, b, true, s);
   if (e != hipSuccess) return e;
   const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + d * 4;
   knn_refine2_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, b, nn_out);

@@ -4,13 +4,15 @@
 // c the column mean of X (the KDE is translation invariant), stored in the
 // scan precision T with rows zero-padded to a multiple of 128 bytes.  Per row
 // we keep
-//   norm  = ||x~||^2 (FP64 accumulation, rounded to FP32),
+//   norm  = ||x~||^2 (FP64),
 //   knorm = ||x~||^2 (1 - a): scaled so that knorm_x + knorm_y - 2 x~.y~, as
 //           computed in FP32, never exceeds the exact ||x~ - y~||^2,
 //   err   = an upper bound of ||x~ - (x - c)||, the rounding of the row.
 // Hence for every pair ||x - y|| >= sqrt(max(key, 0)) - err_x - err_y.
 #include "common.h"
 #include "kernels.h"
+
+#include <algorithm>
 
 namespace deann {
 
@@ -59,7 +61,7 @@ template <typename T>
 __global__ void __launch_bounds__(WG) prep_rows_kernel(const float* __restrict__ src, int64_t rows,
                                                        int64_t rows_padded, int64_t d, int64_t dp,
                                                        const float* __restrict__ c, double a_scale,
-                                                       T* __restrict__ dst, float* __restrict__ norm,
+                                                       T* __restrict__ dst, double* __restrict__ norm,
                                                        float* __restrict__ knorm,
                                                        float* __restrict__ err,
                                                        uint32_t* __restrict__ err_max) {
@@ -69,7 +71,7 @@ __global__ void __launch_bounds__(WG) prep_rows_kernel(const float* __restrict__
   T* out = dst + row * dp;
   if (row >= rows) {
     for (int64_t t = lane; t < dp; t += 64) out[t] = to_elem<T>(0.f);
-    if (lane == 0) { norm[row] = 0.f; knorm[row] = 0.f; err[row] = 0.f; }
+    if (lane == 0) { norm[row] = 0.0; knorm[row] = 0.f; err[row] = 0.f; }
     return;
   }
   const float* in = src + row * d;
@@ -91,24 +93,44 @@ __global__ void __launch_bounds__(WG) prep_rows_kernel(const float* __restrict__
   nn = wave_sum(nn);
   ee = wave_sum(ee);
   if (lane == 0) {
-    norm[row] = (float)nn;
+    norm[row] = nn;
     // round the scaled norm down and the error bound up
     knorm[row] = (float)(nn * (1.0 - a_scale));
     // FP32 rounding is below 6e-8 relative, so the 1e-6 margin keeps e an upper bound
-    const float e = (float)(sqrt(ee) * (1.0 + 1e-6));
-    err[row] = e;
-    if (err_max) atomicMax(err_max, __builtin_bit_cast(uint32_t, e));
+    err[row] = (float)(sqrt(ee) * (1.0 + 1e-6));
+  }
+}
+
+// Largest error bound over the rows: block maxima, one atomic per block
+// (non-negative floats order like their bit patterns).
+__global__ void __launch_bounds__(WG) max_u32_kernel(const float* __restrict__ v, int64_t count,
+                                                     uint32_t* __restrict__ out) {
+  __shared__ uint32_t red[WG / 64];
+  uint32_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < count; i += (int64_t)gridDim.x * WG)
+    m = max(m, __builtin_bit_cast(uint32_t, v[i]));
+  for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = red[0];
+    for (int w = 1; w < WG / 64; ++w) r = max(r, red[w]);
+    atomicMax(out, r);
   }
 }
 
 template <typename T>
 hipError_t launch_prep_rows(const float* src, int64_t rows, int64_t rows_padded, int64_t d,
-                            int64_t dp, const float* c, double a_scale, void* dst, float* norm,
+                            int64_t dp, const float* c, double a_scale, void* dst, double* norm,
                             float* knorm, float* err, uint32_t* err_max, hipStream_t s) {
   const int64_t blocks = ceil_div(rows_padded, WG / 64);
   prep_rows_kernel<T><<<dim3((unsigned)blocks), dim3(WG), 0, s>>>(
       src, rows, rows_padded, d, dp, c, a_scale, reinterpret_cast<T*>(dst), norm, knorm, err,
       err_max);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !err_max) return e;
+  const int64_t mb = std::min<int64_t>(1024, ceil_div(rows, WG));
+  max_u32_kernel<<<dim3((unsigned)mb), dim3(WG), 0, s>>>(err, rows, err_max);
   return hipGetLastError();
 }
 
@@ -136,7 +158,7 @@ hipError_t launch_center(const float* X, int64_t n, int64_t d, double* part, int
 
 hipError_t launch_prep_rows_prec(int prec, const float* src, int64_t rows, int64_t rows_padded,
                                  int64_t d, int64_t dp, const float* c, double a_scale, void* dst,
-                                 float* norm, float* knorm, float* err, uint32_t* err_max,
+                                 double* norm, float* knorm, float* err, uint32_t* err_max,
                                  hipStream_t s) {
   switch (prec) {
     case PREC_FP32:

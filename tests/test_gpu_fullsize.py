@@ -1,0 +1,80 @@
+"""Full-size parity in the benchmark's launch configuration: the 100-cluster
+mixture with n = 1,000,000, d = 128, q = 10,000 (k = 100, m = 1,000) and the
+differentiation workload n = 500,000, d = 64, q = 4,096.  Sampled queries are
+checked against the oracle one by one; properties that hold at any size are
+checked on every query."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import GAUSSIAN, EXPONENTIAL
+
+from .gpu_common import bandwidth, device, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+WL = "mix100_n1e6_d128"
+KNAME = {GAUSSIAN: "gaussian", EXPONENTIAL: "exponential"}
+
+
+@pytest.fixture(scope="module")
+def big():
+    dev = device()
+    spec, X, Y = synth.workload(WL)
+    return X, Y, to_dev(X, dev), to_dev(Y, dev)
+
+
+def _check_indices(nn, sm, n, k):
+    # sorted, distinct, in range; draws in range and outside the neighbour set
+    assert nn.min() >= 0 and nn.max() < n
+    assert np.all(np.diff(nn, axis=1) > 0)
+    assert sm.min() >= 0 and sm.max() < n
+    for j in range(0, nn.shape[0], 97):
+        assert not np.isin(sm[j], nn[j]).any()
+
+
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_fullsize_deann_and_exact(big, kern):
+    import paper_2107_02736_amd as dk
+    X, Y, Xd, Yd = big
+    h = bandwidth(WL, KNAME[kern])
+    k, m = 100, 1000
+    mu = dk.kde_exact(Xd, Yd, h, KNAME[kern], "fp32").cpu().numpy()
+    res = {p: dk.deann_query(Xd, Yd, h, k, m, KNAME[kern], seed=0, precision=p)
+           for p in ("bf16", "fp32")}
+    out, nn, sm = (t.cpu().numpy() for t in res["bf16"])
+    out32, nn32, sm32 = (t.cpu().numpy() for t in res["fp32"])
+    # BF16 scan + refinement reproduces the FP32 result exactly
+    assert np.array_equal(nn, nn32) and np.array_equal(sm, sm32)
+    assert np.array_equal(out, out32)
+    assert np.all((mu >= 0) & (mu <= 1)) and np.all(out >= 0)
+    _check_indices(nn, sm, X.shape[0], k)
+    for j in synth.query_subset(Y.shape[0], 5, seed=3):
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, kern, k, m, 0, int(j))
+        assert np.array_equal(nn[j], nn_ref), j
+        assert np.array_equal(sm[j], s_ref), j
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
+        ref = oracle.kde_exact(X, Y[j:j + 1], h, kern)[0]
+        if ref >= 1e-16:
+            print(f"query {j}: exact fp32 rel err {abs(mu[j] - ref) / ref:.2e}")
+            assert abs(mu[j] - ref) <= 1e-5 * ref
+
+
+def test_fullsize_exact_backward():
+    import paper_2107_02736_amd as dk
+    dev = device()
+    wl = "mix50_n5e5_d64"
+    spec, X, Y = synth.workload(wl)
+    h = bandwidth(wl, "gaussian")
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    g = np.ones(Y.shape[0])
+    gy, gh = dk.kde_exact_backward(Xd, Yd, h, to_dev(g, dev), "gaussian")
+    gy = gy.cpu().numpy()
+    assert np.all(np.isfinite(gy))
+    for j in synth.query_subset(Y.shape[0], 3, seed=5):
+        _, gy_ref, _ = oracle.kde_grad(X, Y[j].astype(np.float64), h, GAUSSIAN)
+        d2 = oracle.sq_dists(X, Y[j])
+        K = oracle.kernel_values(d2, h, GAUSSIAN)
+        scale = (K * np.sqrt(d2)).sum() / (X.shape[0] * h * h)
+        assert np.linalg.norm(gy[j] - gy_ref) <= 1e-4 * scale

@@ -162,7 +162,7 @@ int check_common(const float* X, int64_t n, const float* Y, int64_t q, int64_t d
 // ---- per-path workspace plans -------------------------------------------------
 constexpr int64_t kKdeSplitTarget = 4096;
 constexpr int64_t kKnnSplitTarget = 512;     // selection scan: about one wave of workgroups
-constexpr int64_t kCollectSplitTarget = 4096;
+constexpr int64_t kCollectSplitTarget = 4096;  // candidate and collect passes
 
 struct KdePlan {
   Prep prep;
@@ -207,8 +207,11 @@ DeannPlan plan_deann(void* ws, int64_t n, int64_t q, int64_t d, int64_t k, int p
   // a list must hold K1 kept entries plus one tile (BN) of new ones
   b.cap1 = 256;
   while (b.cap1 < 2 * b.K1 + BN) b.cap1 <<= 1;
-  b.cand = cv.take<uint64_t>(splits * P.prep.qp * b.cap1);
-  b.cand_cnt = cv.take<int32_t>(splits * P.prep.qp);
+  // list scan (FP32) or one candidate per cell of the collect geometry (16-bit)
+  const int64_t splits_c = choose_splits(qtiles, ntiles, kCollectSplitTarget);
+  const int64_t lists = prec == DEANN_FP32 ? splits * b.cap1 : splits_c * 32;
+  b.cand = cv.take<uint64_t>(P.prep.qp * lists);
+  b.cand_cnt = cv.take<int32_t>((splits > splits_c ? splits : splits_c) * P.prep.qp);
   P.nn_internal = cv.take<int32_t>(q * (k > 0 ? k : 1));
   b.z1 = cv.take<double>(q > 0 ? q : 1);
   b.thr2 = cv.take<float>(q > 0 ? q : 1);

@@ -108,6 +108,106 @@ deann_backward_kernel(const float* __restrict__ X, const float* __restrict__ Y, 
   if (threadIdx.x == 0 && gh_part) gh_part[qi] = scale * hsum;
 }
 
+// Register-resident variant for d % 4 == 0 and d <= 64 * U: a group of 16
+// lanes gathers a row once (float4 loads, 256 contiguous bytes per group and
+// step), reduces ||x - y||^2 with shuffles, and accumulates w (x - y) into its
+// own FP64 coordinates; the 16 group partials are summed in a fixed order.
+template <int U>
+__global__ void __launch_bounds__(WG)
+deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
+                          int64_t d, double h, int kern, int64_t k, int64_t m,
+                          const int32_t* __restrict__ nn, const int32_t* __restrict__ samp,
+                          const double* __restrict__ grad_out, float* __restrict__ grad_Y,
+                          double* __restrict__ gh_part) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  double* part = reinterpret_cast<double*>(smem);   // [16][d]
+  double* hpart = part + 16 * d;                    // [16]
+  const int64_t qi = blockIdx.x;
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  const int64_t size2 = n - k;
+  const int64_t ms = (size2 > 0) ? m : 0;
+  const int64_t R = k + ms;
+  const double csamp = ms > 0 ? (double)size2 / (double)m : 0.0;
+  const double inv_h2 = 1.0 / (h * h);
+  // this lane's coordinates: 4 * l16 + 64 * u + {0..3}
+  float yv[U][4];
+  double acc[U][4];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t t = 4 * l16 + 64 * u + c;
+      yv[u][c] = t < d ? Y[qi * d + t] : 0.f;
+      acc[u][c] = 0.0;
+    }
+  double hs = 0.0;
+  for (int64_t j = g; j < R; j += WG / 16) {
+    const int32_t row = j < k ? nn[qi * k + j] : samp[qi * m + (j - k)];
+    const float* xr = X + (int64_t)row * d;
+    float xv[U][4];
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t t = 4 * l16 + 64 * u;
+      if (t < d) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(xr + t);
+        xv[u][0] = v[0]; xv[u][1] = v[1]; xv[u][2] = v[2]; xv[u][3] = v[3];
+      } else {
+        xv[u][0] = xv[u][1] = xv[u][2] = xv[u][3] = 0.f;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double df = (double)xv[u][c] - (double)yv[u][c];
+        s = __builtin_fma(df, df, s);
+      }
+    }
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    s += __shfl_xor(s, 8, 64);
+    const double c = j < k ? 1.0 : csamp;
+    double w, dh;
+    if (kern == KERNEL_GAUSSIAN) {
+      const double K = exp(-0.5 * s * inv_h2);
+      w = K * inv_h2;
+      dh = K * s * inv_h2 / h;
+    } else {
+      const double r = sqrt(s);
+      const double K = exp(-r / h);
+      w = r > 0.0 ? K / (h * r) : 0.0;
+      dh = K * r * inv_h2;
+    }
+    w *= c;
+    hs += c * dh;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+        acc[u][cc] = __builtin_fma(w, (double)xv[u][cc] - (double)yv[u][cc], acc[u][cc]);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t t = 4 * l16 + 64 * u + c;
+      if (t < d) part[g * d + t] = acc[u][c];
+    }
+  if (l16 == 0) hpart[g] = hs;
+  __syncthreads();
+  const double scale = grad_out[qi] / (double)n;
+  if (grad_Y)
+    for (int64_t t = threadIdx.x; t < d; t += WG) {
+      double v = 0.0;
+      for (int gg = 0; gg < WG / 16; ++gg) v += part[gg * d + t];
+      grad_Y[qi * d + t] = (float)(scale * v);
+    }
+  if (threadIdx.x == 0 && gh_part) {
+    double v = 0.0;
+    for (int gg = 0; gg < WG / 16; ++gg) v += hpart[gg];
+    gh_part[qi] = scale * v;
+  }
+}
+
 // Fixed-order sum of q per-query terms into one scalar (single workgroup).
 __global__ void __launch_bounds__(WG) sum_scalar_kernel(const double* __restrict__ v, int64_t q,
                                                         double* __restrict__ out) {
@@ -128,9 +228,23 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
                                  const int32_t* samp, const double* grad_out, float* grad_Y,
                                  double* gh_part, double* grad_h, hipStream_t s) {
   if (q == 0) return hipSuccess;
-  const size_t sm = BWD_CHUNK * (8 + 8 + 4) + d * 4 + 16;
-  deann_backward_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(X, Y, n, d, h, kern, k, m, nn,
-                                                                samp, grad_out, grad_Y, gh_part);
+  const bool vec = (d % 4 == 0) && d <= 256 &&
+                   (reinterpret_cast<uintptr_t>(X) % 16 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
+  if (vec) {
+    const size_t sm = (16 * d + 16) * 8;
+    const int U = (int)((d + 63) / 64);
+    const dim3 g((unsigned)q), b(WG);
+    switch (U) {
+      case 1: deann_backward_vec_kernel<1><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+      case 2: deann_backward_vec_kernel<2><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+      case 3: deann_backward_vec_kernel<3><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+      default: deann_backward_vec_kernel<4><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+    }
+  } else {
+    const size_t sm = BWD_CHUNK * (8 + 8 + 4) + d * 4 + 16;
+    deann_backward_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(X, Y, n, d, h, kern, k, m, nn,
+                                                                  samp, grad_out, grad_Y, gh_part);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !grad_h) return e;
   sum_scalar_kernel<<<dim3(1), dim3(WG), 0, s>>>(gh_part, q, grad_h);

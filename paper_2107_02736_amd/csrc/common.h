@@ -180,6 +180,58 @@ __device__ __forceinline__ void tile_dot(f32x4 (&acc)[4][4], const char* __restr
   }
 }
 
+// Streamed sweep over data tiles [t0, t1) against one query tile.  The chunk
+// sequence is continuous across tiles: the registers always hold the next
+// chunk (of this tile or of the next one) while the current one is multiplied,
+// so global latency is hidden behind the MFMAs and the epilogue.  One barrier
+// per chunk: a buffer is refilled two chunks after it was last read, and every
+// wave has passed the barrier in between.  Usage:
+//   StreamState st;  stream_start(st, ...);
+//   for (t = t0; t < t1; ++t) { stream_tile<T>(acc, st, ..., t, ...); epilogue; }
+//   __syncthreads();   // before reusing the staging area
+// The epilogue may use LDS outside the 4 * TILE_LDS staging area.
+struct StreamState {
+  ChunkRegs rq, rx;
+  int buf;
+};
+
+__device__ __forceinline__ void stream_start(StreamState& st, const char* __restrict__ yq,
+                                             const char* __restrict__ Xs, int64_t ld_bytes,
+                                             int64_t t0) {
+  load_chunk(st.rq, yq, ld_bytes, 0);
+  load_chunk(st.rx, Xs + t0 * BN * ld_bytes, ld_bytes, 0);
+  st.buf = 0;
+  __syncthreads();   // previous users of the staging area are done
+}
+
+template <typename T>
+__device__ __forceinline__ void stream_tile(f32x4 (&acc)[4][4], StreamState& st,
+                                            const char* __restrict__ yq,
+                                            const char* __restrict__ Xs, int64_t ld_bytes,
+                                            int nchunks, int64_t t, int64_t t1, char* lds,
+                                            int wq, int wn, int lane) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < nchunks; ++c) {
+    char* qa = lds + st.buf * 2 * TILE_LDS;
+    char* xa = qa + TILE_LDS;
+    store_chunk(st.rq, qa);
+    store_chunk(st.rx, xa);
+    __syncthreads();
+    int nc = c + 1;
+    int64_t nt = t;
+    if (nc == nchunks) { nc = 0; nt = t + 1; }
+    if (nt < t1) {
+      load_chunk(st.rq, yq, ld_bytes, (int64_t)nc * CHUNK_BYTES);
+      load_chunk(st.rx, Xs + nt * BN * ld_bytes, ld_bytes, (int64_t)nc * CHUNK_BYTES);
+    }
+    mfma_chunk<T>(acc, qa, xa, wq, wn, lane);
+    st.buf ^= 1;
+  }
+}
+
 // XCD-aware placement: workgroups are dispatched round-robin over the 8 XCDs.
 // Map the hardware id so that each XCD receives a contiguous range of virtual
 // ids; consecutive virtual ids share the same data split (and hence the same

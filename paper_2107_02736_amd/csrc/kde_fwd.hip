@@ -39,9 +39,11 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
     for (int r = 0; r < 4; ++r) sum[i][r] = 0.0;
 
   const char* yq = Ys + qt * BQ * ld_bytes;
+  StreamState st;
+  if (t0 < t1) stream_start(st, yq, Xs, ld_bytes, t0);
   for (int64_t t = t0; t < t1; ++t) {
     f32x4 acc[4][4];
-    tile_dot<T>(acc, yq, Xs + t * BN * ld_bytes, ld_bytes, nchunks, lds, wq, wn, lane);
+    stream_tile<T>(acc, st, yq, Xs, ld_bytes, nchunks, t, t1, lds, wq, wn, lane);
     double xn[4];
     bool valid[4];
 #pragma unroll
@@ -71,6 +73,7 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       }
     }
   }
+  __syncthreads();
 
   // reduce over the 16 lanes that share rows, then over the two column waves
 #pragma unroll
@@ -84,7 +87,6 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       v += __shfl_xor(v, 8, 64);
       sum[i][r] = v;
     }
-  __syncthreads();
   double* red = reinterpret_cast<double*>(lds);   // [2][BQ]
   if ((lane & 15) == 0) {
 #pragma unroll

@@ -240,6 +240,41 @@ __device__ void emit_neighbours(const uint64_t* key, uint32_t* idx, uint32_t* tm
 // ---------------------------------------------------------------------------
 // 1. scan
 // ---------------------------------------------------------------------------
+
+// Lists holding more than `lim` entries are cut to their K1 smallest keys;
+// each wave sorts its own queries' lists in registers.  Whole block calls.
+template <int EPL>
+__device__ __forceinline__ void compact_lists(uint64_t* __restrict__ lists, int* cnt, float* thr,
+                                              int lim, int K1, int wave, int lane) {
+  constexpr int cap1 = 64 * EPL;
+  for (int ql = wave; ql < BQ; ql += WG / 64) {
+    const int c = cnt[ql];
+    if (c <= lim) continue;
+    uint64_t* lst = lists + (int64_t)ql * cap1;
+    uint64_t v[EPL];
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) {
+      const int e = lane * EPL + r;
+      v[r] = e < c ? lst[e] : ~0ull;
+    }
+    wave_sort_u64<EPL>(v, lane);
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) {
+      const int e = lane * EPL + r;
+      if (e < K1) lst[e] = v[r];
+    }
+    uint64_t mine = 0;   // static register indexing only
+#pragma unroll
+    for (int r = 0; r < EPL; ++r)
+      if (r == (K1 - 1) % EPL) mine = v[r];
+    const uint64_t kth = __shfl(mine, (K1 - 1) / EPL, 64);
+    if (lane == 0) {
+      cnt[ql] = K1;
+      thr[ql] = key_float((uint32_t)(kth >> 32));
+    }
+  }
+  __syncthreads();
+}
 template <typename T, int EPL>   // list capacity = 64 * EPL
 __global__ void __launch_bounds__(WG, 2)
 knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt,
@@ -247,6 +282,7 @@ knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
   constexpr int cap1 = 64 * EPL;
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
   __shared__ float thr[BQ];
+  __shared__ float yks[BQ];
   __shared__ int cnt[BQ];
   const int64_t V = xcd_virtual_id(blockIdx.x, grid);
   if (V >= p.qtiles * p.splits) return;
@@ -254,75 +290,113 @@ knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
-  if (threadIdx.x < BQ) { thr[threadIdx.x] = __builtin_inff(); cnt[threadIdx.x] = 0; }
+  if (threadIdx.x < BQ) {
+    thr[threadIdx.x] = __builtin_inff();
+    cnt[threadIdx.x] = 0;
+    yks[threadIdx.x] = p.yknorm[qt * BQ + threadIdx.x];
+  }
   uint64_t* lists = cand + (split * p.qp + qt * BQ) * (int64_t)cap1;
-
-  float yk[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) yk[i][r] = p.yknorm[qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r];
 
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
   const int limit = cap1 - BN;   // a list above this could overflow in the next tile
-  for (int64_t t = t0; t <= t1; ++t) {
-    const bool last = (t == t1);
-    if (!last) {
-      f32x4 acc[4][4];
-      tile_dot<T>(acc, yq, p.Xs + t * BN * p.ld_bytes, p.ld_bytes, p.nchunks, lds, wq, wn, lane);
-      float th[4][4];
+
+  __syncthreads();   // thr / cnt initialised
+  StreamState st;
+  if (t0 < t1) stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    f32x4 acc[4][4];
+    stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
+    float xk[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
+      xk[j] = col < p.n ? p.xknorm[col] : __builtin_inff();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ql = wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const float yk = yks[ql], th = thr[ql];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]);
+          if (key < th) {
+            const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
+            const int slot = atomicAdd(&cnt[ql], 1);
+            lists[(int64_t)ql * cap1 + slot] =
+                ((uint64_t)float_key(key) << 32) | (uint64_t)(uint32_t)col;
+          }
+        }
+      }
+    __syncthreads();
+    compact_lists<EPL>(lists, cnt, thr, limit, K1, wave, lane);
+  }
+  compact_lists<EPL>(lists, cnt, thr, K1, K1, wave, lane);
+  if (threadIdx.x < BQ) cand_cnt[split * p.qp + qt * BQ + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// 1'. candidate pass for 16-bit scans: every lane keeps, for each of its 16
+//     queries, the smallest key among the data columns it sees (one "cell" =
+//     one lane column of one wave, per split).  No list traffic at all; the
+//     candidates only seed the exact distance d_k of the second pass, which is
+//     what certifies the result.
+// ---------------------------------------------------------------------------
+constexpr int CELLS = 32;   // cells per (split, query): 16 lane columns x 2 waves
+
+template <typename T>
+__global__ void __launch_bounds__(WG, 2)
+knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt,
+                int64_t grid) {
+  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
+  __shared__ float yks[BQ];
+  const int64_t V = xcd_virtual_id(blockIdx.x, grid);
+  if (V >= p.qtiles * p.splits) return;
+  const int64_t split = V / p.qtiles, qt = V % p.qtiles;
+  const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wq = wave >> 1, wn = wave & 1;
+  if (threadIdx.x < BQ) yks[threadIdx.x] = p.yknorm[qt * BQ + threadIdx.x];
+  float best[4][4];
+  uint32_t bidx[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { best[i][r] = __builtin_inff(); bidx[i][r] = 0xffffffffu; }
+  const char* yq = p.Ys + qt * BQ * p.ld_bytes;
+  StreamState st;
+  if (t0 < t1) stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    f32x4 acc[4][4];
+    stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
+      const float xk = col < p.n ? p.xknorm[col] : __builtin_inff();
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) th[i][r] = thr[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-        const bool valid = col < p.n;
-        const float xk = p.xknorm[col];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk[i][r] + xk);
-            if (valid && key < th[i][r]) {
-              const int ql = wq * 64 + i * 16 + 4 * (lane >> 4) + r;
-              const int slot = atomicAdd(&cnt[ql], 1);
-              lists[(int64_t)ql * cap1 + slot] =
-                  ((uint64_t)float_key(key) << 32) | (uint64_t)(uint32_t)col;
-            }
-          }
-      }
+        for (int r = 0; r < 4; ++r) {
+          const float key =
+              __builtin_fmaf(-2.f, acc[i][j][r], yks[wq * 64 + i * 16 + 4 * (lane >> 4) + r] + xk);
+          const bool better = key < best[i][r];
+          best[i][r] = better ? key : best[i][r];
+          bidx[i][r] = better ? (uint32_t)col : bidx[i][r];
+        }
     }
-    __syncthreads();
-    // compaction of lists that might overflow (or, at the end, of every list
-    // above K1): each wave sorts its own queries' lists in registers
-    const int lim = last ? K1 : limit;
-    for (int ql = wave; ql < BQ; ql += WG / 64) {
-      const int c = cnt[ql];
-      if (c <= lim) continue;
-      uint64_t* lst = lists + (int64_t)ql * cap1;
-      uint64_t v[EPL];
-#pragma unroll
-      for (int r = 0; r < EPL; ++r) {
-        const int e = lane * EPL + r;
-        v[r] = e < c ? lst[e] : ~0ull;
-      }
-      wave_sort_u64<EPL>(v, lane);
-#pragma unroll
-      for (int r = 0; r < EPL; ++r) {
-        const int e = lane * EPL + r;
-        if (e < K1) lst[e] = v[r];
-      }
-      const uint64_t kth = __shfl(v[(K1 - 1) % EPL], (K1 - 1) / EPL, 64);
-      if (lane == 0) {
-        cnt[ql] = K1;
-        thr[ql] = key_float((uint32_t)(kth >> 32));
-      }
-    }
-    __syncthreads();
   }
-  if (threadIdx.x < BQ) cand_cnt[split * p.qp + qt * BQ + threadIdx.x] = cnt[threadIdx.x];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+      const uint64_t v = bidx[i][r] == 0xffffffffu
+                             ? ~0ull
+                             : ((uint64_t)float_key(best[i][r]) << 32) | (uint64_t)bidx[i][r];
+      cand[(split * p.qp + row) * CELLS + wn * 16 + (lane & 15)] = v;
+    }
+  if (threadIdx.x < BQ) cand_cnt[split * p.qp + qt * BQ + threadIdx.x] = CELLS;
 }
 
 // ---------------------------------------------------------------------------
@@ -334,6 +408,7 @@ struct RefineArgs {
   int64_t n, q, d, k, qp, splits;
   double h;
   int kern;
+  int approx;   // candidates come from the cell pass: no certificate, always collect
 };
 
 __global__ void __launch_bounds__(WG)
@@ -355,15 +430,17 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   int64_t seen = 0;
   for (int64_t s = 0; s < a.splits; ++s) {
     const int c = b.cand_cnt[s * a.qp + qi];
-    const int f = fill_s;
     const uint64_t* lst = b.cand + (s * a.qp + qi) * b.cap1;
-    for (int i = threadIdx.x; i < c; i += WG) buf[f + i] = lst[i];
     seen += c;
     __syncthreads();
-    if (threadIdx.x == 0) fill_s = f + c;
+    // append the list, dropping empty cells (order inside buf is irrelevant)
+    for (int i = threadIdx.x; i < c; i += WG) {
+      const uint64_t v = lst[i];
+      if (v != ~0ull) buf[atomicAdd(&fill_s, 1)] = v;
+    }
     __syncthreads();
     const bool flush = (fill_s + K1 > SORT_CAP) || (s + 1 == a.splits);
-    if (flush && fill_s > K1) {
+    if (flush && fill_s >= K1) {   // sorted whenever the K1-th key is used
       const int F = fill_s;
       for (int i = F + threadIdx.x; i < SORT_CAP; i += WG) buf[i] = ~0ull;
       __syncthreads();
@@ -374,7 +451,7 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   }
   const int C = fill_s;            // candidates (<= K1)
   // all points were candidates iff no list ever dropped anything
-  const bool complete = (seen == a.n) && (C == a.n);
+  const bool complete = !a.approx && (seen == a.n) && (C == a.n);
   const float Tkey = (C == K1) ? key_float((uint32_t)(buf[K1 - 1] >> 32)) : __builtin_inff();
   // exact FP64 distances
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
@@ -390,12 +467,22 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   const int k = (int)a.k;
   fix_boundary(dkey, didx, C, k, a.X, a.d, ys);
   bool ok = complete;
+  if (!ok && C < k) {
+    // too few candidates to bound d_k: the second pass collects every point
+    if (threadIdx.x == 0) {
+      b.thr2[qi] = __builtin_inff();
+      b.status[qi] = 1;
+      b.cand2_cnt[qi] = 0;
+      b.flags[qi / BQ] = 1;
+    }
+    return;
+  }
   if (!ok && C >= k) {
     const double Dk = __builtin_bit_cast(double, dkey[k - 1]) * (1.0 + fp64_rel(a.d));
     const double E = (double)__builtin_bit_cast(float, *b.xerr_max);
     const double ey = (double)b.yerr[qi];
     const double lhs = sqrt((double)fmaxf(Tkey, 0.f)) - E - ey;
-    ok = lhs > 0.0 && lhs * lhs > Dk * (1.0 + 1e-14);
+    ok = !a.approx && lhs > 0.0 && lhs * lhs > Dk * (1.0 + 1e-14);
     if (!ok) {
       if (threadIdx.x == 0) {
         const double r = (sqrt(Dk) + E + ey) * (1.0 + 1e-6);
@@ -440,20 +527,21 @@ knn_collect_kernel(TileProblem p, KnnBuffers b, int64_t grid) {
       th[i][r] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
     }
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
+  StreamState st;
+  if (t0 < t1) stream_start(st, yq, p.Xs, p.ld_bytes, t0);
   for (int64_t t = t0; t < t1; ++t) {
     f32x4 acc[4][4];
-    tile_dot<T>(acc, yq, p.Xs + t * BN * p.ld_bytes, p.ld_bytes, p.nchunks, lds, wq, wn, lane);
+    stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-      const bool valid = col < p.n;
-      const float xk = p.xknorm[col];
+      const float xk = col < p.n ? p.xknorm[col] : __builtin_inff();
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk[i][r] + xk);
-          if (valid && key <= th[i][r]) {
+          if (key <= th[i][r]) {
             const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
             const int slot = atomicAdd(&b.cand2_cnt[row], 1);
             if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = (uint64_t)col;
@@ -618,18 +706,34 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
   if (e != hipSuccess) return e;
   e = launch_fill_u32(reinterpret_cast<uint32_t*>(b.status), p.q, 0u, s);
   if (e != hipSuccess) return e;
-  e = launch_tiles_prec(prec, p, b, false, s);
-  if (e != hipSuccess) return e;
-  RefineArgs a{X, Y, p.n, p.q, d, k, p.qp, p.splits, h, kern};
+  const bool approx = prec != PREC_FP32;
+  KnnBuffers bb = b;
+  RefineArgs a{X, Y, p.n, p.q, d, k, p.qp, p.splits, h, kern, 0};
+  if (approx) {
+    // 16-bit scans: cheap cell candidates, then the certified second pass
+    const int64_t grid = round_up(pc.qtiles * pc.splits, 8);
+    const dim3 g((unsigned)grid), blk(WG);
+    switch (prec) {
+      case PREC_BF16: knn_cand_kernel<__bf16><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt, grid); break;
+      default: knn_cand_kernel<_Float16><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt, grid); break;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    bb.cap1 = CELLS;
+    a.splits = pc.splits;
+    a.approx = 1;
+  } else {
+    e = launch_tiles_prec(prec, p, b, false, s);
+    if (e != hipSuccess) return e;
+  }
   const size_t sm1 = SORT_CAP * 8 + K_MAX * (8 + 4 + 4) + WG * 8 + d * 4;
-  knn_refine_kernel<<<dim3((unsigned)p.q), dim3(WG), sm1, s>>>(a, b, nn_out);
+  knn_refine_kernel<<<dim3((unsigned)p.q), dim3(WG), sm1, s>>>(a, bb, nn_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   e = launch_tiles_prec(prec, pc, b, true, s);
   if (e != hipSuccess) return e;
   const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + d * 4;
-  knn_refine2_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, b, nn_out);
+  knn_refine2_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, bb, nn_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  knn_exhaustive_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, b, nn_out);
+  knn_exhaustive_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, bb, nn_out);
   return hipGetLastError();
 }
 

@@ -39,7 +39,22 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6, help="queries in the oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a device-to-device copy of 1 GiB (counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy of known size: 1 GiB read + 1 GiB written per launch, three
+    launches.  Its FETCH_SIZE / WRITE_SIZE counters scale the hot kernels'."""
+    import torch
+    dev = torch.device("cuda:0")
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 3}))
 
 
 def bandwidth(workload, kernel):
@@ -49,6 +64,9 @@ def bandwidth(workload, kernel):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the query path needs no communication "
               "(queries shard with query_offset); run with --gpus 1", file=sys.stderr)

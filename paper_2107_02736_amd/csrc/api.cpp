@@ -125,6 +125,7 @@ TileProblem make_problem(const Prep& p, int64_t n, int64_t q, int prec, int64_t 
   t.qtiles = p.qp / BQ;
   t.ntiles = p.np / BN;
   t.splits = choose_splits(t.qtiles, t.ntiles, splits_target);
+  t.map = make_tile_map(t.qtiles, t.splits);
   return t;
 }
 

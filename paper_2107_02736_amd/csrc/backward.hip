@@ -254,51 +254,121 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
 // ---------------------------------------------------------------------------
 // Exact-KDE backward on MFMA (FP32 operands, padded d <= 128)
 // ---------------------------------------------------------------------------
-template <int KERN, int TB>   // TB = padded d / 16
-__global__ void __launch_bounds__(WG, 1)
+// 512 threads (8 waves, two per SIMD so that one wave's epilogue overlaps the
+// other's MFMAs).  First product: wave (wi, wq) computes S^T for data rows
+// wi*32..+32 and queries wq*64..+64 and turns it into the weights W, which go
+// to LDS as W[q][i].  Second product: wave (wq, wt) accumulates
+// G[q][t] = sum_i W[q][i] x~[i][t] for queries wq*64..+64 and coordinates
+// wt*DP/4..+DP/4 over all 128 rows of the tile, so no cross-wave sum of G is
+// needed.
+constexpr int BWG = 512;
+constexpr int BCV = BQ * CHUNK_BYTES / 16 / BWG;   // 16-byte chunk loads per thread (= 2)
+
+__device__ __forceinline__ void bload(u32x4 (&r)[BCV], const char* __restrict__ base,
+                                      int64_t ld_bytes, int64_t kbyte) {
+#pragma unroll
+  for (int i = 0; i < BCV; ++i) {
+    const int v = threadIdx.x + i * BWG;
+    r[i] = *reinterpret_cast<const u32x4*>(base + (v / 8) * ld_bytes + kbyte + (v % 8) * 16);
+  }
+}
+
+__device__ __forceinline__ void bstore(const u32x4 (&r)[BCV], char* lds) {
+#pragma unroll
+  for (int i = 0; i < BCV; ++i) {
+    const int v = threadIdx.x + i * BWG;
+    *reinterpret_cast<u32x4*>(lds + (v / 8) * LDS_ROW + (v % 8) * 16) = r[i];
+  }
+}
+
+template <int KERN, int TB>   // TB = padded d / 16, a multiple of 4 here... or 2, 6
+__global__ void __launch_bounds__(BWG, 1)
 kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
                     double* __restrict__ gy_part, double* __restrict__ rw_part,
-                    double* __restrict__ gh_part, int64_t grid) {
-  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
-  const int64_t V = xcd_virtual_id(blockIdx.x, grid);
-  if (V >= p.qtiles * p.splits) return;
-  const int64_t split = V / p.qtiles, qt = V % p.qtiles;
+                    double* __restrict__ gh_part) {
+  constexpr int DP = TB * 16;
+  constexpr int XTS = BN + 4;          // row stride (floats) of the transposed data tile
+  constexpr int WS = BN + 4;           // row stride (floats) of W[q][i]
+  constexpr int TBW = (TB + 3) / 4;    // coordinate blocks per wave in the second product
+  static_assert(BQ * WS * 4 <= 4 * TILE_LDS, "W must fit in the staging area");
+  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];   // staging, then W
+  __shared__ __attribute__((aligned(16))) float xt[DP * XTS];       // x~ tile as [t][i]
+  __shared__ double yns[BQ];
+  __shared__ double rsum[2][4][BQ];   // [rowsum of W | dK/dh sum][wi][query]
+  int64_t qt, split;
+  if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wi = wave >> 1, wq = wave & 1;   // data-row half, query half
-  constexpr int DP = TB * 16;
-  constexpr int XS = DP + 4;                 // LDS row stride (floats) of the data tile
+  const int wi = wave >> 1, wq = wave & 1;   // first product
+  const int wt = wave >> 1;                  // second product: coordinate quarter
+  if (threadIdx.x < BQ) yns[threadIdx.x] = p.ynorm[qt * BQ + threadIdx.x];
+  float* W = reinterpret_cast<float*>(lds);
 
-  double yn[4];
-#pragma unroll
-  for (int bq = 0; bq < 4; ++bq) yn[bq] = p.ynorm[qt * BQ + wq * 64 + bq * 16 + (lane & 15)];
-  f32x4 gacc[4][TB];
+  f32x4 gacc[4][TBW];
 #pragma unroll
   for (int bq = 0; bq < 4; ++bq)
 #pragma unroll
-    for (int tb = 0; tb < TB; ++tb) gacc[bq][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tb = 0; tb < TBW; ++tb) gacc[bq][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
   double rws[4], dhs[4];
 #pragma unroll
   for (int bq = 0; bq < 4; ++bq) { rws[bq] = 0.0; dhs[bq] = 0.0; }
 
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
-  float* xt = reinterpret_cast<float*>(lds);
+  u32x4 ry[BCV], rx[BCV];
+  int buf = 0;
+  if (t0 < t1) {
+    bload(ry, yq, p.ld_bytes, 0);
+    bload(rx, p.Xs + t0 * BN * p.ld_bytes, p.ld_bytes, 0);
+  }
+  __syncthreads();
   for (int64_t t = t0; t < t1; ++t) {
     const char* xg = p.Xs + t * BN * p.ld_bytes;
-    f32x4 acc[4][4];   // [bi][bq]: rows = data, cols = queries
-    tile_dot<float>(acc, xg, yq, p.ld_bytes, p.nchunks, lds, wi, wq, lane);
-    // weights in place
+    f32x4 acc[2][4];   // [bi][bq]: rows = data, columns = queries
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) acc[bi][bq] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < p.nchunks; ++c) {
+      char* qa = lds + buf * 2 * TILE_LDS;
+      char* xa = qa + TILE_LDS;
+      bstore(ry, qa);
+      bstore(rx, xa);
+      __syncthreads();
+      int nc = c + 1;
+      int64_t nt = t;
+      if (nc == p.nchunks) { nc = 0; nt = t + 1; }
+      if (nt < t1) {
+        bload(ry, yq, p.ld_bytes, (int64_t)nc * CHUNK_BYTES);
+        bload(rx, p.Xs + nt * BN * p.ld_bytes, p.ld_bytes, (int64_t)nc * CHUNK_BYTES);
+      }
+#pragma unroll
+      for (int kg = 0; kg < CHUNK_BYTES / KG_BYTES; ++kg) {
+        u32x4 a[2], b[4];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) a[bi] = lds_frag(xa, wi * 32 + bi * 16, kg, lane);
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq) b[bq] = lds_frag(qa, wq * 64 + bq * 16, kg, lane);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bq = 0; bq < 4; ++bq) acc[bi][bq] = mfma_kgroup<float>(a[bi], b[bq], acc[bi][bq]);
+      }
+      buf ^= 1;
+    }
+    // weights; per-tile FP32 row sums folded into FP64
+    float rw32[4] = {0.f, 0.f, 0.f, 0.f}, dh32[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = t * BN + wi * 64 + bi * 16 + 4 * (lane >> 4) + r;
+        const int64_t row = t * BN + wi * 32 + bi * 16 + 4 * (lane >> 4) + r;
         const bool valid = row < p.n;
         const double xn = p.xnorm[row];
 #pragma unroll
         for (int bq = 0; bq < 4; ++bq) {
           const double s = (double)acc[bi][bq][r];
-          const float d2 = fmaxf(0.f, (float)__builtin_fma(-2.0, s, xn + yn[bq]));
+          const float d2 = fmaxf(0.f, (float)__builtin_fma(
+              -2.0, s, xn + yns[wq * 64 + bq * 16 + (lane & 15)]));
           float w, dh;
           if (KERN == KERNEL_GAUSSIAN) {
             const float K = __builtin_amdgcn_exp2f(-L * d2);
@@ -313,41 +383,60 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
           w = valid ? w : 0.f;
           dh = valid ? dh : 0.f;
           acc[bi][bq][r] = w;
-          rws[bq] += (double)w;
-          dhs[bq] += (double)dh;
+          rw32[bq] += w;
+          dh32[bq] += dh;
         }
       }
     }
-    // full data tile (all padded coordinates) into LDS
-    for (int v = threadIdx.x; v < BN * DP / 4; v += WG) {
-      const int row = v / (DP / 4), c4 = v % (DP / 4);
-      const f32x4 val = *reinterpret_cast<const f32x4*>(xg + row * p.ld_bytes + c4 * 16);
-      float* dst = xt + row * XS + c4 * 4;
-      dst[0] = val[0]; dst[1] = val[1]; dst[2] = val[2]; dst[3] = val[3];
+#pragma unroll
+    for (int bq = 0; bq < 4; ++bq) { rws[bq] += (double)rw32[bq]; dhs[bq] += (double)dh32[bq]; }
+    __syncthreads();   // the staging area (now W) and xt are free
+    // W[q][i]: lane holds 4 consecutive i of one q per block
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq)
+        *reinterpret_cast<f32x4*>(&W[(wq * 64 + bq * 16 + (lane & 15)) * WS + wi * 32 + bi * 16 +
+                                     4 * (lane >> 4)]) = acc[bi][bq];
+    // data tile, transposed: 4 x 4 blocks, 16-byte loads and stores
+    for (int blk = threadIdx.x; blk < (BN / 4) * (DP / 4); blk += BWG) {
+      const int ib = blk % (BN / 4), tbk = blk / (BN / 4);
+      f32x4 v[4];
+#pragma unroll
+      for (int a4 = 0; a4 < 4; ++a4)
+        v[a4] = *reinterpret_cast<const f32x4*>(xg + (int64_t)(4 * ib + a4) * p.ld_bytes + tbk * 16);
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4)
+        *reinterpret_cast<f32x4*>(&xt[(4 * tbk + c4) * XTS + 4 * ib]) =
+            f32x4{v[0][c4], v[1][c4], v[2][c4], v[3][c4]};
     }
     __syncthreads();
-    // G[q][t] += sum_i W[q][i] x~[i][t]
+    // G[q][t] += sum_i W[q][i] x~[i][t] over the tile's 128 rows
+#pragma unroll 2
+    for (int kb = 0; kb < BN / 16; ++kb) {
+      f32x4 a[4];
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
+      for (int bq = 0; bq < 4; ++bq)
+        a[bq] = *reinterpret_cast<const f32x4*>(
+            &W[(wq * 64 + bq * 16 + (lane & 15)) * WS + kb * 16 + 4 * (lane >> 4)]);
 #pragma unroll
-      for (int tb = 0; tb < TB; ++tb) {
-        float b[4];
+      for (int tb = 0; tb < TBW; ++tb) {
+        const int tcol = (wt * TBW + tb) * 16;
+        if (tcol < DP) {
+          const f32x4 b = *reinterpret_cast<const f32x4*>(
+              &xt[(tcol + (lane & 15)) * XTS + kb * 16 + 4 * (lane >> 4)]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          b[j] = xt[(wi * 64 + bi * 16 + 4 * (lane >> 4) + j) * XS + tb * 16 + (lane & 15)];
+          for (int bq = 0; bq < 4; ++bq)
 #pragma unroll
-        for (int bq = 0; bq < 4; ++bq)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            gacc[bq][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acc[bi][bq][j], b[j],
-                                                                 gacc[bq][tb], 0, 0, 0);
+            for (int j = 0; j < 4; ++j)
+              gacc[bq][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bq][j], b[j], gacc[bq][tb],
+                                                                   0, 0, 0);
+        }
       }
     }
+    __syncthreads();   // W (staging) and xt are reused by the next tile
   }
-  __syncthreads();
-  // combine the two data-row halves: wave (1, wq) hands over to wave (0, wq)
-  float* red = reinterpret_cast<float*>(lds);   // [2][64][DP]
-  double* redd = reinterpret_cast<double*>(lds + 2 * 64 * DP * 4);   // [2][2][64]
+  // row sums: lanes sharing a query column, then the four wi waves (fixed order)
 #pragma unroll
   for (int bq = 0; bq < 4; ++bq) {
     double a = rws[bq], bb = dhs[bq];
@@ -355,45 +444,29 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
     a += __shfl_xor(a, 32, 64);
     bb += __shfl_xor(bb, 16, 64);
     bb += __shfl_xor(bb, 32, 64);
-    rws[bq] = a;
-    dhs[bq] = bb;
-  }
-  if (wi == 1) {
-#pragma unroll
-    for (int bq = 0; bq < 4; ++bq)
-#pragma unroll
-      for (int tb = 0; tb < TB; ++tb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          red[(wq * 64 + bq * 16 + 4 * (lane >> 4) + r) * DP + tb * 16 + (lane & 15)] =
-              gacc[bq][tb][r];
-    if (lane < 16)
-#pragma unroll
-      for (int bq = 0; bq < 4; ++bq) {
-        redd[(0 * 2 + wq) * 64 + bq * 16 + lane] = rws[bq];
-        redd[(1 * 2 + wq) * 64 + bq * 16 + lane] = dhs[bq];
-      }
+    if (lane < 16) {
+      rsum[0][wi][wq * 64 + bq * 16 + lane] = a;
+      rsum[1][wi][wq * 64 + bq * 16 + lane] = bb;
+    }
   }
   __syncthreads();
-  if (wi == 0) {
-    const int64_t qbase = split * p.qp + qt * BQ + wq * 64;
+  const int64_t qbase = split * p.qp + qt * BQ;
 #pragma unroll
-    for (int bq = 0; bq < 4; ++bq)
+  for (int bq = 0; bq < 4; ++bq)
 #pragma unroll
-      for (int tb = 0; tb < TB; ++tb)
+    for (int tb = 0; tb < TBW; ++tb) {
+      const int tcol = (wt * TBW + tb) * 16;
+      if (tcol < DP)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int ql = bq * 16 + 4 * (lane >> 4) + r;
-          const int col = tb * 16 + (lane & 15);
-          gy_part[(qbase + ql) * DP + col] =
-              (double)gacc[bq][tb][r] + (double)red[(wq * 64 + ql) * DP + col];
+          const int ql = wq * 64 + bq * 16 + 4 * (lane >> 4) + r;
+          gy_part[(qbase + ql) * DP + tcol + (lane & 15)] = (double)gacc[bq][tb][r];
         }
-    if (lane < 16)
-#pragma unroll
-      for (int bq = 0; bq < 4; ++bq) {
-        rw_part[qbase + bq * 16 + lane] = rws[bq] + redd[(0 * 2 + wq) * 64 + bq * 16 + lane];
-        gh_part[qbase + bq * 16 + lane] = dhs[bq] + redd[(1 * 2 + wq) * 64 + bq * 16 + lane];
-      }
+    }
+  if (threadIdx.x < BQ) {
+    const int ql = threadIdx.x;
+    rw_part[qbase + ql] = (rsum[0][0][ql] + rsum[0][1][ql]) + (rsum[0][2][ql] + rsum[0][3][ql]);
+    gh_part[qbase + ql] = (rsum[1][0][ql] + rsum[1][1][ql]) + (rsum[1][2][ql] + rsum[1][3][ql]);
   }
 }
 
@@ -427,13 +500,12 @@ template <int KERN>
 static hipError_t launch_kde_bwd_k(const TileProblem& p, int TB, float L, float inv_h,
                                    float inv_h2, double* gy, double* rw, double* gh,
                                    hipStream_t s) {
-  const int64_t grid = round_up(p.qtiles * p.splits, 8);
-  const dim3 g((unsigned)grid), b(WG);
+  const dim3 g((unsigned)p.map.grid), b(BWG);
   switch (TB) {
-    case 2: kde_backward_kernel<KERN, 2><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh, grid); break;
-    case 4: kde_backward_kernel<KERN, 4><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh, grid); break;
-    case 6: kde_backward_kernel<KERN, 6><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh, grid); break;
-    default: kde_backward_kernel<KERN, 8><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh, grid); break;
+    case 2: kde_backward_kernel<KERN, 2><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh); break;
+    case 4: kde_backward_kernel<KERN, 4><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh); break;
+    case 6: kde_backward_kernel<KERN, 6><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh); break;
+    default: kde_backward_kernel<KERN, 8><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh); break;
   }
   return hipGetLastError();
 }

@@ -204,7 +204,9 @@ __device__ __forceinline__ void stream_start(StreamState& st, const char* __rest
   __syncthreads();   // previous users of the staging area are done
 }
 
-template <typename T>
+// SWAP = false: acc rows are queries (wq), columns data rows (wn).
+// SWAP = true : acc rows are data rows (wq), columns queries (wn), i.e. S^T.
+template <typename T, bool SWAP = false>
 __device__ __forceinline__ void stream_tile(f32x4 (&acc)[4][4], StreamState& st,
                                             const char* __restrict__ yq,
                                             const char* __restrict__ Xs, int64_t ld_bytes,
@@ -227,18 +229,36 @@ __device__ __forceinline__ void stream_tile(f32x4 (&acc)[4][4], StreamState& st,
       load_chunk(st.rq, yq, ld_bytes, (int64_t)nc * CHUNK_BYTES);
       load_chunk(st.rx, Xs + nt * BN * ld_bytes, ld_bytes, (int64_t)nc * CHUNK_BYTES);
     }
-    mfma_chunk<T>(acc, qa, xa, wq, wn, lane);
+    if (SWAP)
+      mfma_chunk<T>(acc, xa, qa, wq, wn, lane);
+    else
+      mfma_chunk<T>(acc, qa, xa, wq, wn, lane);
     st.buf ^= 1;
   }
 }
 
-// XCD-aware placement: workgroups are dispatched round-robin over the 8 XCDs.
-// Map the hardware id so that each XCD receives a contiguous range of virtual
-// ids; consecutive virtual ids share the same data split (and hence the same
-// data tiles in that XCD's L2) and differ in their query tile.
-__device__ __forceinline__ int64_t xcd_virtual_id(int64_t hw, int64_t grid) {
-  const int64_t per = grid / 8;   // grid is a multiple of 8
-  return (hw % 8) * per + hw / 8;
+// XCD-aware placement.  Workgroups are dispatched round-robin over the 8 XCDs,
+// so hardware id hw runs on XCD hw % 8 as its (hw / 8)-th workgroup.  Each XCD
+// receives a contiguous eighth of the (split-major) work items, so the
+// workgroups an XCD holds at a time share one data split -- the same data
+// tiles, read once into that XCD's L2 -- and differ in their query tile.
+// Returns false for the padding items beyond qtiles * splits.
+struct TileMap {
+  int64_t grid;     // launched workgroups: qtiles * splits rounded up to 8
+};
+
+__device__ __forceinline__ bool map_tile(int64_t hw, const TileMap& m, int64_t qtiles,
+                                         int64_t splits, int64_t& qt, int64_t& split) {
+  const int64_t v = (hw % 8) * (m.grid / 8) + hw / 8;
+  split = v / qtiles;
+  qt = v % qtiles;
+  return split < splits;
+}
+
+inline TileMap make_tile_map(int64_t qtiles, int64_t splits) {
+  TileMap m;
+  m.grid = (qtiles * splits + 7) / 8 * 8;
+  return m;
 }
 
 // Order-preserving map float -> uint32 (total order matching <, -0 < +0).

@@ -18,12 +18,11 @@ __global__ void __launch_bounds__(WG, 2)
 kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_t ld_bytes,
                 int nchunks, const double* __restrict__ ynorm, const double* __restrict__ xnorm,
                 int64_t n, int64_t qtiles, int64_t splits, int64_t ntiles, double L,
-                double* __restrict__ partial, int64_t qp, int64_t grid) {
+                double* __restrict__ partial, int64_t qp, TileMap map) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
   __shared__ double yns[BQ];
-  const int64_t V = xcd_virtual_id(blockIdx.x, grid);
-  if (V >= qtiles * splits) return;
-  const int64_t split = V / qtiles, qt = V % qtiles;
+  int64_t qt, split;
+  if (!map_tile(blockIdx.x, map, qtiles, splits, qt, split)) return;
   const int64_t t0 = split * ntiles / splits, t1 = (split + 1) * ntiles / splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
@@ -111,16 +110,15 @@ __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t sp
 template <typename T>
 static hipError_t launch_kde_t(const TileProblem& p, int kern, double L, double* partial,
                                hipStream_t s) {
-  const int64_t work = p.qtiles * p.splits;
-  const int64_t grid = round_up(work, 8);
+  const dim3 g((unsigned)p.map.grid), b(WG);
   if (kern == KERNEL_GAUSSIAN)
-    kde_tile_kernel<T, KERNEL_GAUSSIAN><<<dim3((unsigned)grid), dim3(WG), 0, s>>>(
+    kde_tile_kernel<T, KERNEL_GAUSSIAN><<<g, b, 0, s>>>(
         p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
-        partial, p.qp, grid);
+        partial, p.qp, p.map);
   else
-    kde_tile_kernel<T, KERNEL_EXPONENTIAL><<<dim3((unsigned)grid), dim3(WG), 0, s>>>(
+    kde_tile_kernel<T, KERNEL_EXPONENTIAL><<<g, b, 0, s>>>(
         p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
-        partial, p.qp, grid);
+        partial, p.qp, p.map);
   return hipGetLastError();
 }
 

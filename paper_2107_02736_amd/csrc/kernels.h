@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.h"
+
 namespace deann {
 
 // Geometry of one (queries x data) tile sweep over the prepared operands.
@@ -19,6 +21,7 @@ struct TileProblem {
   int64_t n, q;          // true sizes
   int64_t np, qp;        // padded to multiples of 128
   int64_t qtiles, ntiles, splits;
+  TileMap map;           // workgroup -> (query tile, split), see common.h
 };
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);

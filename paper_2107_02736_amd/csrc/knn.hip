@@ -278,15 +278,14 @@ __device__ __forceinline__ void compact_lists(uint64_t* __restrict__ lists, int*
 template <typename T, int EPL>   // list capacity = 64 * EPL
 __global__ void __launch_bounds__(WG, 2)
 knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt,
-                int K1, int64_t grid) {
+                int K1) {
   constexpr int cap1 = 64 * EPL;
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
   __shared__ float thr[BQ];
   __shared__ float yks[BQ];
   __shared__ int cnt[BQ];
-  const int64_t V = xcd_virtual_id(blockIdx.x, grid);
-  if (V >= p.qtiles * p.splits) return;
-  const int64_t split = V / p.qtiles, qt = V % p.qtiles;
+  int64_t qt, split;
+  if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
@@ -347,13 +346,11 @@ constexpr int CELLS = 32;   // cells per (split, query): 16 lane columns x 2 wav
 
 template <typename T>
 __global__ void __launch_bounds__(WG, 2)
-knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt,
-                int64_t grid) {
+knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
   __shared__ float yks[BQ];
-  const int64_t V = xcd_virtual_id(blockIdx.x, grid);
-  if (V >= p.qtiles * p.splits) return;
-  const int64_t split = V / p.qtiles, qt = V % p.qtiles;
+  int64_t qt, split;
+  if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
@@ -508,11 +505,10 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(WG, 2)
-knn_collect_kernel(TileProblem p, KnnBuffers b, int64_t grid) {
+knn_collect_kernel(TileProblem p, KnnBuffers b) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
-  const int64_t V = xcd_virtual_id(blockIdx.x, grid);
-  if (V >= p.qtiles * p.splits) return;
-  const int64_t split = V / p.qtiles, qt = V % p.qtiles;
+  int64_t qt, split;
+  if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
   if (b.flags[qt] == 0) return;
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -675,16 +671,15 @@ hipError_t launch_knn_all(const float* X, const float* Y, int64_t n, int64_t q, 
 template <typename T>
 static hipError_t launch_tiles(const TileProblem& p, const KnnBuffers& b, bool collect,
                                hipStream_t s) {
-  const int64_t grid = round_up(p.qtiles * p.splits, 8);
-  const dim3 g((unsigned)grid), blk(WG);
+  const dim3 g((unsigned)p.map.grid), blk(WG);
   if (collect) {
-    knn_collect_kernel<T><<<g, blk, 0, s>>>(p, b, grid);
+    knn_collect_kernel<T><<<g, blk, 0, s>>>(p, b);
   } else {
     switch (b.cap1) {
-      case 256: knn_scan_kernel<T, 4><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1, grid); break;
-      case 512: knn_scan_kernel<T, 8><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1, grid); break;
-      case 1024: knn_scan_kernel<T, 16><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1, grid); break;
-      default: knn_scan_kernel<T, 32><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1, grid); break;
+      case 256: knn_scan_kernel<T, 4><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1); break;
+      case 512: knn_scan_kernel<T, 8><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1); break;
+      case 1024: knn_scan_kernel<T, 16><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1); break;
+      default: knn_scan_kernel<T, 32><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1); break;
     }
   }
   return hipGetLastError();
@@ -711,11 +706,10 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
   RefineArgs a{X, Y, p.n, p.q, d, k, p.qp, p.splits, h, kern, 0};
   if (approx) {
     // 16-bit scans: cheap cell candidates, then the certified second pass
-    const int64_t grid = round_up(pc.qtiles * pc.splits, 8);
-    const dim3 g((unsigned)grid), blk(WG);
+    const dim3 g((unsigned)pc.map.grid), blk(WG);
     switch (prec) {
-      case PREC_BF16: knn_cand_kernel<__bf16><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt, grid); break;
-      default: knn_cand_kernel<_Float16><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt, grid); break;
+      case PREC_BF16: knn_cand_kernel<__bf16><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt); break;
+      default: knn_cand_kernel<_Float16><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt); break;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     bb.cap1 = CELLS;

@@ -25,7 +25,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("queries/s at ≤1% rel KDE err, BF16+refine vs FP32; exact KDE % MFMA peak")
 WORKLOAD = "mix100_n1e6_d128"
-K_NN, M_SAMPLES, KERNEL = 100, 1000, "gaussian"
+KERNEL = "gaussian"
+# (k, m) per workload; the default line is the 100-cluster mixture, the others
+# are for separate runs with --workload
+KM = {"mix100_n1e6_d128": (100, 1000), "mix10_n1e4_d16": (50, 500),
+      "mix50_n5e5_d64": (64, 512), "mix200_n1e6_d960": (200, 2000)}
 PEAK_FP32_MFMA = 157.3e12     # dense FP32 matrix, MI355X
 PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8.0e12
@@ -57,6 +61,36 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 3}))
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "counters_mix100_n1e6_d128.json")
+
+
+def kernel_sources_sha(names):
+    import hashlib
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_2107_02736_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs, scaled by the same counters for a copy of known size; None
+    when the kernel's sources changed after the counters were taken."""
+    try:
+        with open(COUNTERS) as f:
+            rec = json.load(f)
+        k = rec["kernels"][kernel]
+        if kernel_sources_sha(k["sources"]) != k["sources_sha256"]:
+            return None
+        cal = rec["copy_calibration"]
+        fetch = k["FETCH_SIZE_kb"] * cal["bytes_per_launch"] / cal["FETCH_SIZE_kb"]
+        write = k["WRITE_SIZE_kb"] * cal["bytes_per_launch"] / cal["WRITE_SIZE_kb"]
+        return fetch + write
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def bandwidth(workload, kernel):
     with open(os.path.join(ROOT, "tests", "golden", "bandwidths.json")) as f:
         return float(json.load(f)[workload][kernel]["h"])
@@ -82,7 +116,9 @@ def main():
     t0 = time.time()
     spec, X, Y = synth.workload(args.workload)
     h = bandwidth(args.workload, KERNEL)
+    K_NN, M_SAMPLES = KM[args.workload]
     n, d = X.shape
+    exact_bwd = d <= 128     # kde_exact_backward supports d <= 128
     q = Y.shape[0]
     Xd = torch.from_numpy(X).to(dev)
     Yd = torch.from_numpy(Y).to(dev)
@@ -104,7 +140,7 @@ def main():
         e[2].record()
         gy, gh = dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn, sm, gout, KERNEL)
         e[3].record()
-        gye, ghe = dk.kde_exact_backward(Xd, Yd, h, gout, KERNEL)
+        gye, ghe = dk.kde_exact_backward(Xd, Yd, h, gout, KERNEL) if exact_bwd else (None, None)
         e[4].record()
         if record is not None:
             record.append(e)
@@ -114,12 +150,16 @@ def main():
         step(None)
     torch.cuda.synchronize()
     events = []
+    dk.kernel_timing(args.steps)     # events around the dense tile kernels
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         res = step(events)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    tile_ms = dk.kernel_times("kde_exact")
+    bwd_tile_ms = dk.kernel_times("kde_exact_backward")
+    dk.kernel_timing(0)
     names = list(comp)
     for e in events:
         for i, name in enumerate(names):
@@ -151,7 +191,8 @@ def main():
     rel_deann_vs_exact = np.abs(est_h[keep] - mu_h[keep]) / mu_h[keep]
 
     flops_exact = 2.0 * n * d * q
-    roof_achieved = flops_exact / (comp_ms["kde_exact_fp32"] * 1e-3)
+    tile_avg_ms = float(np.mean(tile_ms))
+    roof_achieved = flops_exact / (tile_avg_ms * 1e-3)
     out = {
         "metric": METRIC,
         "value": q / (ms_step * 1e-3),
@@ -166,12 +207,22 @@ def main():
         "dtype": "bf16 scan + f32 exact tiles + f64 refine/reductions",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "q": q, "kernel": KERNEL, "h": h,
-                   "k": K_NN, "m": M_SAMPLES, "deann_scan": "bf16", "exact": "fp32"},
+                   "k": K_NN, "m": M_SAMPLES, "deann_scan": "bf16", "exact": "fp32",
+                   "exact_backward_in_step": exact_bwd},
         "roofline": {"bound": "mfma", "kernel": "kde_tile_kernel<float,gaussian>",
                      "achieved": roof_achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": roof_achieved / PEAK_FP32_MFMA, "traffic": None,
-                     "flops_per_launch": flops_exact,
-                     "note": "achieved over the whole kde_exact call (prep + tiles + reduction)"},
+                     "unit": "TFLOP/s", "frac": roof_achieved / PEAK_FP32_MFMA,
+                     "traffic": measured_traffic("kde_tile_kernel<float,gaussian>"),
+                     "flops_per_launch": flops_exact, "kernel_avg_ms": tile_avg_ms,
+                     "launches_timed": len(tile_ms),
+                     "note": "2*n*d*q flops per launch / the tile kernel's own duration "
+                             "(HIP events recorded by the library around it on its stream)"},
+        "roofline_exact_backward": None if not bwd_tile_ms else {
+            "bound": "mfma", "kernel": "kde_backward_kernel<gaussian>",
+            "achieved": 4.0 * n * d * q / (float(np.mean(bwd_tile_ms)) * 1e-3) / 1e12,
+            "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+            "frac": 4.0 * n * d * q / (float(np.mean(bwd_tile_ms)) * 1e-3) / PEAK_FP32_MFMA,
+            "flops_per_launch": 4.0 * n * d * q, "kernel_avg_ms": float(np.mean(bwd_tile_ms))},
         "components_ms": comp_ms,
         "queries_per_s": {
             "step": q / (ms_step * 1e-3),
@@ -179,7 +230,8 @@ def main():
             "deann_fp32": q / (ms_deann32 * 1e-3),
             "kde_exact_fp32": q / (comp_ms["kde_exact_fp32"] * 1e-3),
             "deann_backward": q / (comp_ms["deann_backward"] * 1e-3),
-            "kde_exact_backward": q / (comp_ms["kde_exact_backward"] * 1e-3),
+            "kde_exact_backward": (q / (comp_ms["kde_exact_backward"] * 1e-3)
+                                   if exact_bwd else None),
         },
         "accuracy": {
             "deann_bf16_vs_fp32_same_indices": same_idx,
@@ -193,11 +245,12 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity_sample"] = cpu_baseline(
             X, Y, h, args.cpu_sample, mu_h, est_h, nn.cpu().numpy(), sm.cpu().numpy(),
-            gy.cpu().numpy())
+            gy.cpu().numpy(), K_NN, M_SAMPLES, exact_bwd)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu):
+def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu, K_NN, M_SAMPLES,
+                 exact_bwd):
     """The FP64 oracle timed on the host for a few queries of the same workload,
     doing the same per-query work as one step; also checks those queries."""
     import numpy as np
@@ -213,7 +266,8 @@ def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu):
         est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, oracle.GAUSSIAN, K_NN, M_SAMPLES,
                                                    0, int(j))
         _, gy_ref, _ = oracle.deann_grad(X, Y[j], h, oracle.GAUSSIAN, nn_ref, s_ref, M_SAMPLES)
-        oracle.kde_grad(X, Y[j], h, oracle.GAUSSIAN)
+        if exact_bwd:
+            oracle.kde_grad(X, Y[j], h, oracle.GAUSSIAN)
         if mu >= 1e-16:
             rel_exact.append(abs(mu_gpu[j] - mu) / mu)
             rel_deann.append(abs(est_gpu[j] - est) / est)

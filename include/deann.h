@@ -129,6 +129,21 @@ int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int
 /* Message for the last non-OK status returned on the calling thread. */
 const char* deann_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing, for measurement tools only (no effect on any result).
+ * deann_kernel_timing(capacity): capacity in [1, 4096] makes the calling thread
+ * record a pair of HIP events on the call's stream around the dense tile
+ * kernel of each following call, for up to `capacity` calls per site:
+ *   site 0 = kde_exact, site 1 = kde_exact_backward.
+ * Recording happens only while a site has unread slots left.  capacity = 0
+ * stops and releases the events (also done before a new capacity is set).
+ * deann_kernel_times(site, ms, max_count): waits for the recorded events,
+ * writes up to max_count durations in milliseconds to the host array ms (in
+ * call order), frees the site's slots and returns the count, or -1 on error.
+ * ------------------------------------------------------------------------- */
+int deann_kernel_timing(int capacity);
+int deann_kernel_times(int site, float* ms, int max_count);
+
 #ifdef __cplusplus
 }
 #endif

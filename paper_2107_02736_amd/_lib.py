@@ -21,6 +21,7 @@ EXPORTS = (
     "deann_query_backward_workspace", "deann_query_backward",
     "kde_exact_backward_workspace", "kde_exact_backward",
     "deann_last_error",
+    "deann_kernel_timing", "deann_kernel_times",
 )
 
 
@@ -67,6 +68,10 @@ def load(path: str = LIB_PATH):
     lib.kde_exact_backward.restype = _int
     lib.kde_exact_backward.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _vp, _vp, _vp, _vp,
                                        _sz, _vp]
+    lib.deann_kernel_timing.restype = _int
+    lib.deann_kernel_timing.argtypes = [_int]
+    lib.deann_kernel_times.restype = _int
+    lib.deann_kernel_times.argtypes = [_int, ctypes.POINTER(ctypes.c_float), _int]
     _lib = lib
     return lib
 

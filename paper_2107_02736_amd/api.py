@@ -123,3 +123,23 @@ def kde_exact_backward(X, Y, h, grad_out, kernel="gaussian", need_grad_y: bool =
         X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), grad_out.data_ptr(),
         _ptr(gy), _ptr(gh), ws.data_ptr(), ws.numel(), _stream(dev)))
     return gy, gh
+
+
+TIMING_SITES = {"kde_exact": 0, "kde_exact_backward": 1}
+
+
+def kernel_timing(capacity: int) -> None:
+    """Record HIP events around the dense tile kernel of the next `capacity`
+    kde_exact / kde_exact_backward calls on this thread (0 stops)."""
+    _lib.check(_lib.load().deann_kernel_timing(int(capacity)))
+
+
+def kernel_times(site: str, max_count: int = 4096) -> list:
+    """Durations in ms of the recorded tile kernels of `site`, in call order
+    (waits for them); frees the slots."""
+    import ctypes
+    buf = (ctypes.c_float * max_count)()
+    n = _lib.load().deann_kernel_times(TIMING_SITES[site], buf, max_count)
+    if n < 0:
+        _lib.check(_lib.EHIP)
+    return [float(buf[i]) for i in range(n)]

@@ -33,6 +33,37 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(DEANN_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Per-thread event pairs around the dense tile kernels (measurement only).
+constexpr int kTimingSites = 2;   // 0: kde_exact tiles, 1: kde_exact_backward tiles
+struct KernelTimer {
+  int cap = 0;
+  int used[kTimingSites] = {0, 0};
+  hipEvent_t* ev[kTimingSites] = {nullptr, nullptr};   // [cap][2] per site
+};
+thread_local KernelTimer g_timer;
+
+void timer_release() {
+  for (int s = 0; s < kTimingSites; ++s) {
+    if (g_timer.ev[s])
+      for (int i = 0; i < 2 * g_timer.cap; ++i)
+        if (g_timer.ev[s][i]) (void)hipEventDestroy(g_timer.ev[s][i]);
+    delete[] g_timer.ev[s];
+    g_timer.ev[s] = nullptr;
+    g_timer.used[s] = 0;
+  }
+  g_timer.cap = 0;
+}
+
+TimingHook timer_hook(int site) {
+  TimingHook th;
+  if (g_timer.cap > 0 && g_timer.used[site] < g_timer.cap) {
+    const int i = g_timer.used[site]++;
+    th.start = g_timer.ev[site][2 * i];
+    th.stop = g_timer.ev[site][2 * i + 1];
+  }
+  return th;
+}
+
 constexpr int64_t kAlign = 256;
 constexpr int64_t kMaxK = 496;             // k limit of the candidate-list kernels (K1 <= 512)
 constexpr int64_t kCenterRows = 256;       // row slices of the column-mean reduction
@@ -258,6 +289,45 @@ extern "C" {
 
 const char* deann_last_error(void) { return g_last_error.c_str(); }
 
+int deann_kernel_timing(int capacity) {
+  if (capacity < 0 || capacity > 4096)
+    return fail(DEANN_EINVAL, "timing capacity must be in [0, 4096] (got %d)", capacity);
+  timer_release();
+  if (capacity == 0) return DEANN_OK;
+  for (int s = 0; s < kTimingSites; ++s) {
+    g_timer.ev[s] = new hipEvent_t[2 * capacity]();
+    g_timer.cap = capacity;
+    for (int i = 0; i < 2 * capacity; ++i) {
+      const hipError_t e = hipEventCreate(&g_timer.ev[s][i]);
+      if (e != hipSuccess) {
+        g_timer.ev[s][i] = nullptr;
+        timer_release();
+        return hip_fail(e, "hipEventCreate");
+      }
+    }
+  }
+  return DEANN_OK;
+}
+
+int deann_kernel_times(int site, float* ms, int max_count) {
+  if (site < 0 || site >= kTimingSites || (!ms && max_count > 0) || max_count < 0) {
+    fail(DEANN_EINVAL, "bad timing site or buffer");
+    return -1;
+  }
+  const int n = g_timer.used[site] < max_count ? g_timer.used[site] : max_count;
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = hipEventSynchronize(g_timer.ev[site][2 * i + 1]);
+    if (e == hipSuccess)
+      e = hipEventElapsedTime(&ms[i], g_timer.ev[site][2 * i], g_timer.ev[site][2 * i + 1]);
+    if (e != hipSuccess) {
+      hip_fail(e, "kernel timing");
+      return -1;
+    }
+  }
+  g_timer.used[site] = 0;
+  return n;
+}
+
 size_t kde_exact_workspace(int64_t n, int64_t q, int64_t d, int precision) {
   if (n < 1 || d < 1 || q < 0 || bad_prec(precision)) return 0;
   return (size_t)plan_kde(nullptr, n, q, d, precision).bytes;
@@ -278,7 +348,7 @@ int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, d
   hipError_t e = run_prep(P.prep, X, n, Y, q, d, precision, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tp = make_problem(P.prep, n, q, precision, kKdeSplitTarget);
-  e = launch_kde_exact(precision, tp, kernel, h, P.partial, out, s);
+  e = launch_kde_exact(precision, tp, kernel, h, P.partial, out, s, timer_hook(0));
   if (e != hipSuccess) return hip_fail(e, "kde_exact");
   return DEANN_OK;
 }
@@ -383,7 +453,8 @@ int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int
   hipError_t e = run_prep(P.prep, X, n, Y, q, d, DEANN_FP32, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, kKdeSplitTarget);
-  e = launch_kde_backward(tp, Y, d, h, kernel, grad_out, P.gy_part, P.gh_part, grad_Y, grad_h, s);
+  e = launch_kde_backward(tp, Y, d, h, kernel, grad_out, P.gy_part, P.gh_part, grad_Y, grad_h, s,
+                          timer_hook(1));
   if (e != hipSuccess) return hip_fail(e, "kde backward");
   return DEANN_OK;
 }

@@ -322,7 +322,6 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
   }
   __syncthreads();
   for (int64_t t = t0; t < t1; ++t) {
-    const char* xg = p.Xs + t * BN * p.ld_bytes;
     f32x4 acc[2][4];   // [bi][bq]: rows = data, columns = queries
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -333,6 +332,14 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
       char* xa = qa + TILE_LDS;
       bstore(ry, qa);
       bstore(rx, xa);
+      // the same data chunk, transposed into xt[t][i] for the second product
+#pragma unroll
+      for (int i = 0; i < BCV; ++i) {
+        const int v = threadIdx.x + i * BWG;
+        const int t4 = c * (CHUNK_BYTES / 4) + (v % 8) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xt[(t4 + j) * XTS + v / 8] = __uint_as_float(rx[i][j]);
+      }
       __syncthreads();
       int nc = c + 1;
       int64_t nt = t;
@@ -390,7 +397,7 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
     }
 #pragma unroll
     for (int bq = 0; bq < 4; ++bq) { rws[bq] += (double)rw32[bq]; dhs[bq] += (double)dh32[bq]; }
-    __syncthreads();   // the staging area (now W) and xt are free
+    __syncthreads();   // the staging area (now W) is free
     // W[q][i]: lane holds 4 consecutive i of one q per block
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -398,18 +405,6 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
       for (int bq = 0; bq < 4; ++bq)
         *reinterpret_cast<f32x4*>(&W[(wq * 64 + bq * 16 + (lane & 15)) * WS + wi * 32 + bi * 16 +
                                      4 * (lane >> 4)]) = acc[bi][bq];
-    // data tile, transposed: 4 x 4 blocks, 16-byte loads and stores
-    for (int blk = threadIdx.x; blk < (BN / 4) * (DP / 4); blk += BWG) {
-      const int ib = blk % (BN / 4), tbk = blk / (BN / 4);
-      f32x4 v[4];
-#pragma unroll
-      for (int a4 = 0; a4 < 4; ++a4)
-        v[a4] = *reinterpret_cast<const f32x4*>(xg + (int64_t)(4 * ib + a4) * p.ld_bytes + tbk * 16);
-#pragma unroll
-      for (int c4 = 0; c4 < 4; ++c4)
-        *reinterpret_cast<f32x4*>(&xt[(4 * tbk + c4) * XTS + 4 * ib]) =
-            f32x4{v[0][c4], v[1][c4], v[2][c4], v[3][c4]};
-    }
     __syncthreads();
     // G[q][t] += sum_i W[q][i] x~[i][t] over the tile's 128 rows
 #pragma unroll 2
@@ -512,7 +507,7 @@ static hipError_t launch_kde_bwd_k(const TileProblem& p, int TB, float L, float 
 
 hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, double h, int kern,
                                const double* grad_out, double* gy_part, double* gh_part,
-                               float* grad_Y, double* grad_h, hipStream_t s) {
+                               float* grad_Y, double* grad_h, hipStream_t s, TimingHook th) {
   (void)Y;
   const int64_t dp = p.ld_bytes / 4;
   const int TB = (int)(dp / 16);
@@ -520,7 +515,9 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, 
   const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
   double* rw_part = gh_part + p.splits * p.qp;   // layout: gh [splits][qp], rw [splits][qp], ghq [q]
   double* ghq = rw_part + p.splits * p.qp;
-  hipError_t e = (kern == KERNEL_GAUSSIAN)
+  hipError_t e;
+  if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
+  e = (kern == KERNEL_GAUSSIAN)
                      ? launch_kde_bwd_k<KERNEL_GAUSSIAN>(p, TB, L, (float)(1.0 / h),
                                                          (float)(1.0 / (h * h)), gy_part, rw_part,
                                                          gh_part, s)
@@ -528,6 +525,7 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, 
                                                             (float)(1.0 / (h * h)), gy_part,
                                                             rw_part, gh_part, s);
   if (e != hipSuccess) return e;
+  if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
   kde_backward_reduce_kernel<<<dim3((unsigned)p.q), dim3(128), 0, s>>>(
       gy_part, rw_part, gh_part, reinterpret_cast<const float*>(p.Ys), p.splits, p.qp, p.q, d, dp,
       1.0 / (double)p.n, grad_out, grad_Y, ghq);

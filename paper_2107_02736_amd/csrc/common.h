@@ -237,6 +237,94 @@ __device__ __forceinline__ void stream_tile(f32x4 (&acc)[4][4], StreamState& st,
   }
 }
 
+// Query-stationary sweep for 16-bit operands with at most 256 bytes per row
+// (d <= 128): each wave keeps its 64 query rows' A fragments in registers for
+// the whole kernel, and only the data tiles stream through LDS, a whole tile
+// (all NKG 64-byte k-groups of 128 rows) per barrier.  Halves the LDS and L2
+// traffic of tile_stream and removes the query-tile reloads.
+template <int NKG>
+struct XStream {
+  static constexpr int ROWB = NKG * KG_BYTES;          // bytes of a row
+  static constexpr int LROW = ROWB + ROW_PAD;          // LDS row stride
+  static constexpr int VEC = BN * ROWB / 16 / WG;      // 16-byte loads per thread
+  static constexpr int BUF = BN * LROW;                // one buffer (bytes)
+  u32x4 r[VEC];
+  int buf;
+};
+
+template <int NKG>
+__device__ __forceinline__ void xs_load(XStream<NKG>& st, const char* __restrict__ xt,
+                                        int64_t ld_bytes) {
+#pragma unroll
+  for (int i = 0; i < XStream<NKG>::VEC; ++i) {
+    const int v = threadIdx.x + i * WG;
+    const int row = v / (XStream<NKG>::ROWB / 16), col = v % (XStream<NKG>::ROWB / 16);
+    st.r[i] = *reinterpret_cast<const u32x4*>(xt + row * ld_bytes + col * 16);
+  }
+}
+
+template <int NKG>
+__device__ __forceinline__ void xs_store(const XStream<NKG>& st, char* lds) {
+#pragma unroll
+  for (int i = 0; i < XStream<NKG>::VEC; ++i) {
+    const int v = threadIdx.x + i * WG;
+    const int row = v / (XStream<NKG>::ROWB / 16), col = v % (XStream<NKG>::ROWB / 16);
+    *reinterpret_cast<u32x4*>(lds + row * XStream<NKG>::LROW + col * 16) = st.r[i];
+  }
+}
+
+// A fragments of the wave's 64 query rows, all k-groups, straight from global.
+template <int NKG>
+__device__ __forceinline__ void yreg_load(u32x4 (&yf)[4][NKG], const char* __restrict__ yq,
+                                          int64_t ld_bytes, int wq, int lane) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int g = 0; g < NKG; ++g)
+      yf[i][g] = *reinterpret_cast<const u32x4*>(yq + (wq * 64 + i * 16 + (lane & 15)) * ld_bytes +
+                                                  g * KG_BYTES + (lane >> 4) * 16);
+}
+
+// One data tile t (data already prefetched in st): store, barrier, prefetch
+// tile t + 1 if any, multiply.  lds holds 2 * XStream<NKG>::BUF bytes.
+template <typename T, int NKG>
+__device__ __forceinline__ void yreg_tile(f32x4 (&acc)[4][4], XStream<NKG>& st,
+                                          const u32x4 (&yf)[4][NKG], const char* __restrict__ Xs,
+                                          int64_t ld_bytes, int64_t t, int64_t t1, char* lds,
+                                          int wn, int lane) {
+  char* xa = lds + st.buf * XStream<NKG>::BUF;
+  xs_store(st, xa);
+  __syncthreads();
+  if (t + 1 < t1) xs_load(st, Xs + (t + 1) * BN * ld_bytes, ld_bytes);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int g = 0; g < NKG; ++g) {
+    u32x4 b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *reinterpret_cast<const u32x4*>(xa + (wn * 64 + j * 16 + (lane & 15)) * XStream<NKG>::LROW +
+                                             g * KG_BYTES + (lane >> 4) * 16);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = mfma_kgroup<T>(yf[i][g], b[j], acc[i][j]);
+  }
+  st.buf ^= 1;
+}
+
+// k-groups of the query-stationary engine for this operand type and row size,
+// or 0 for the generic stream.  Only 128-byte rows (16-bit operands, d <= 64)
+// use it: with 256-byte rows the resident query fragments no longer fit two
+// workgroups per CU and the generic stream is faster.
+template <typename T>
+inline int query_stationary_kgroups(int64_t ld_bytes) {
+  if (elem_of<T>::bytes != 2 || ld_bytes != 2 * KG_BYTES) return 0;
+  return 2;
+}
+
 // XCD-aware placement.  Workgroups are dispatched round-robin over the 8 XCDs,
 // so hardware id hw runs on XCD hw % 8 as its (hw / 8)-th workgroup.  Each XCD
 // receives a contiguous eighth of the (split-major) work items, so the

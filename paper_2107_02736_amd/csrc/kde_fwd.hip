@@ -13,7 +13,7 @@
 
 namespace deann {
 
-template <typename T, int KERN>
+template <typename T, int KERN, int NKG>   // NKG > 0: query-stationary engine
 __global__ void __launch_bounds__(WG, 2)
 kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_t ld_bytes,
                 int nchunks, const double* __restrict__ ynorm, const double* __restrict__ xnorm,
@@ -38,11 +38,25 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
     for (int r = 0; r < 4; ++r) sum[i][r] = 0.0;
 
   const char* yq = Ys + qt * BQ * ld_bytes;
+  constexpr int NK = NKG > 0 ? NKG : 1;
   StreamState st;
-  if (t0 < t1) stream_start(st, yq, Xs, ld_bytes, t0);
+  XStream<NK> xs;
+  u32x4 yf[4][NK];
+  if (t0 < t1) {
+    if constexpr (NKG == 0) {
+      stream_start(st, yq, Xs, ld_bytes, t0);
+    } else {
+      yreg_load<NK>(yf, yq, ld_bytes, wq, lane);
+      xs_load(xs, Xs + t0 * BN * ld_bytes, ld_bytes);
+      xs.buf = 0;
+    }
+  }
   for (int64_t t = t0; t < t1; ++t) {
     f32x4 acc[4][4];
-    stream_tile<T>(acc, st, yq, Xs, ld_bytes, nchunks, t, t1, lds, wq, wn, lane);
+    if constexpr (NKG == 0)
+      stream_tile<T>(acc, st, yq, Xs, ld_bytes, nchunks, t, t1, lds, wq, wn, lane);
+    else
+      yreg_tile<T, NK>(acc, xs, yf, Xs, ld_bytes, t, t1, lds, wn, lane);
     double xn[4];
     bool valid[4];
 #pragma unroll
@@ -107,32 +121,45 @@ __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t sp
   out[i] = s * inv_n;
 }
 
+template <typename T, int KERN, int NKG>
+static void launch_kde_k(const TileProblem& p, double L, double* partial, hipStream_t s) {
+  kde_tile_kernel<T, KERN, NKG><<<dim3((unsigned)p.map.grid), dim3(WG), 0, s>>>(
+      p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
+      partial, p.qp, p.map);
+}
+
+template <typename T, int KERN>
+static void launch_kde_n(const TileProblem& p, double L, double* partial, hipStream_t s) {
+  if constexpr (elem_of<T>::bytes == 2) {
+    const int nkg = query_stationary_kgroups<T>(p.ld_bytes);
+    if (nkg == 2) return launch_kde_k<T, KERN, 2>(p, L, partial, s);
+  }
+  launch_kde_k<T, KERN, 0>(p, L, partial, s);
+}
+
 template <typename T>
 static hipError_t launch_kde_t(const TileProblem& p, int kern, double L, double* partial,
                                hipStream_t s) {
-  const dim3 g((unsigned)p.map.grid), b(WG);
   if (kern == KERNEL_GAUSSIAN)
-    kde_tile_kernel<T, KERNEL_GAUSSIAN><<<g, b, 0, s>>>(
-        p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
-        partial, p.qp, p.map);
+    launch_kde_n<T, KERNEL_GAUSSIAN>(p, L, partial, s);
   else
-    kde_tile_kernel<T, KERNEL_EXPONENTIAL><<<g, b, 0, s>>>(
-        p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
-        partial, p.qp, p.map);
+    launch_kde_n<T, KERNEL_EXPONENTIAL>(p, L, partial, s);
   return hipGetLastError();
 }
 
 hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, double* partial,
-                            double* out, hipStream_t s) {
+                            double* out, hipStream_t s, TimingHook th) {
   const double log2e = 1.4426950408889634;
   const double L = kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h;
   hipError_t e;
+  if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
   switch (prec) {
     case PREC_FP32: e = launch_kde_t<float>(p, kern, L, partial, s); break;
     case PREC_BF16: e = launch_kde_t<__bf16>(p, kern, L, partial, s); break;
     default: e = launch_kde_t<_Float16>(p, kern, L, partial, s); break;
   }
   if (e != hipSuccess) return e;
+  if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
   kde_reduce_kernel<<<dim3((unsigned)ceil_div(p.q, 256)), dim3(256), 0, s>>>(
       partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, out);
   return hipGetLastError();

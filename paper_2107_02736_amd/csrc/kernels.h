@@ -32,8 +32,13 @@ hipError_t launch_prep_rows_prec(int prec, const float* src, int64_t rows, int64
                                  double* norm, float* knorm, float* err, uint32_t* err_max,
                                  hipStream_t s);
 
+// Optional pair of events recorded around a dense tile kernel (both null: none).
+struct TimingHook {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, double* partial,
-                            double* out, hipStream_t s);
+                            double* out, hipStream_t s, TimingHook th = {});
 
 // ---- exact k nearest neighbours -------------------------------------------
 struct KnnBuffers {
@@ -75,6 +80,6 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
 
 hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, double h, int kern,
                                const double* grad_out, double* gy_part, double* gh_part,
-                               float* grad_Y, double* grad_h, hipStream_t s);
+                               float* grad_Y, double* grad_h, hipStream_t s, TimingHook th = {});
 
 }  // namespace deann

@@ -344,7 +344,7 @@ knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
 // ---------------------------------------------------------------------------
 constexpr int CELLS = 32;   // cells per (split, query): 16 lane columns x 2 waves
 
-template <typename T>
+template <typename T, int NKG>
 __global__ void __launch_bounds__(WG, 2)
 knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
@@ -362,11 +362,25 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
 #pragma unroll
     for (int r = 0; r < 4; ++r) { best[i][r] = __builtin_inff(); bidx[i][r] = 0xffffffffu; }
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
+  constexpr int NK = NKG > 0 ? NKG : 1;
   StreamState st;
-  if (t0 < t1) stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+  XStream<NK> xs;
+  u32x4 yf[4][NK];
+  if (t0 < t1) {
+    if constexpr (NKG == 0) {
+      stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+    } else {
+      yreg_load<NK>(yf, yq, p.ld_bytes, wq, lane);
+      xs_load(xs, p.Xs + t0 * BN * p.ld_bytes, p.ld_bytes);
+      xs.buf = 0;
+    }
+  }
   for (int64_t t = t0; t < t1; ++t) {
     f32x4 acc[4][4];
-    stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
+    if constexpr (NKG == 0)
+      stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
+    else
+      yreg_tile<T, NK>(acc, xs, yf, p.Xs, p.ld_bytes, t, t1, lds, wn, lane);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
@@ -503,7 +517,7 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
 // ---------------------------------------------------------------------------
 // 3. second pass: collect every point whose key admits distance <= d_k
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NKG>
 __global__ void __launch_bounds__(WG, 2)
 knn_collect_kernel(TileProblem p, KnnBuffers b) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
@@ -523,11 +537,25 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
       th[i][r] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
     }
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
+  constexpr int NK = NKG > 0 ? NKG : 1;
   StreamState st;
-  if (t0 < t1) stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+  XStream<NK> xs;
+  u32x4 yf[4][NK];
+  if (t0 < t1) {
+    if constexpr (NKG == 0) {
+      stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+    } else {
+      yreg_load<NK>(yf, yq, p.ld_bytes, wq, lane);
+      xs_load(xs, p.Xs + t0 * BN * p.ld_bytes, p.ld_bytes);
+      xs.buf = 0;
+    }
+  }
   for (int64_t t = t0; t < t1; ++t) {
     f32x4 acc[4][4];
-    stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
+    if constexpr (NKG == 0)
+      stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
+    else
+      yreg_tile<T, NK>(acc, xs, yf, p.Xs, p.ld_bytes, t, t1, lds, wn, lane);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
@@ -673,7 +701,13 @@ static hipError_t launch_tiles(const TileProblem& p, const KnnBuffers& b, bool c
                                hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), blk(WG);
   if (collect) {
-    knn_collect_kernel<T><<<g, blk, 0, s>>>(p, b);
+    const int nkg = query_stationary_kgroups<T>(p.ld_bytes);
+    if constexpr (elem_of<T>::bytes == 2) {
+      if (nkg == 2) knn_collect_kernel<T, 2><<<g, blk, 0, s>>>(p, b);
+      else knn_collect_kernel<T, 0><<<g, blk, 0, s>>>(p, b);
+    } else {
+      knn_collect_kernel<T, 0><<<g, blk, 0, s>>>(p, b);
+    }
   } else {
     switch (b.cap1) {
       case 256: knn_scan_kernel<T, 4><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1); break;
@@ -707,9 +741,13 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
   if (approx) {
     // 16-bit scans: cheap cell candidates, then the certified second pass
     const dim3 g((unsigned)pc.map.grid), blk(WG);
-    switch (prec) {
-      case PREC_BF16: knn_cand_kernel<__bf16><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt); break;
-      default: knn_cand_kernel<_Float16><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt); break;
+    const int nkg = query_stationary_kgroups<__bf16>(pc.ld_bytes);
+    if (prec == PREC_BF16) {
+      if (nkg == 2) knn_cand_kernel<__bf16, 2><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
+      else knn_cand_kernel<__bf16, 0><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
+    } else {
+      if (nkg == 2) knn_cand_kernel<_Float16, 2><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
+      else knn_cand_kernel<_Float16, 0><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     bb.cap1 = CELLS;

@@ -279,7 +279,8 @@ def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu, K_NN, M
     dt = time.perf_counter() - t0
     base = {"value": len(sub) / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(sub)} queries of the same workload, full step per query "
-                      "(exact KDE, DEANN, both adjoints), FP64 NumPy, single thread",
+                      "(exact KDE, DEANN, DEANN adjoint" + (", exact adjoint" if exact_bwd else "")
+                      + "), FP64 NumPy, single thread",
             "seconds": dt}
     par = {"queries": [int(j) for j in sub], "nn_equal": nn_ok, "samples_equal": sm_ok,
            "exact_fp32_max_rel": max(rel_exact) if rel_exact else None,

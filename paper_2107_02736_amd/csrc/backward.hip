@@ -283,8 +283,8 @@ __device__ __forceinline__ void bstore(const u32x4 (&r)[BCV], char* lds) {
 
 template <int KERN, int TB>   // TB = padded d / 16, a multiple of 4 here... or 2, 6
 __global__ void __launch_bounds__(BWG, 1)
-kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
-                    double* __restrict__ gy_part, double* __restrict__ rw_part,
+kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
+                    double* __restrict__ rw_part,
                     double* __restrict__ gh_part) {
   constexpr int DP = TB * 16;
   constexpr int XTS = BN + 4;          // row stride (floats) of the transposed data tile
@@ -293,7 +293,6 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
   static_assert(BQ * WS * 4 <= 4 * TILE_LDS, "W must fit in the staging area");
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];   // staging, then W
   __shared__ __attribute__((aligned(16))) float xt[DP * XTS];       // x~ tile as [t][i]
-  __shared__ double yns[BQ];
   __shared__ double rsum[2][4][BQ];   // [rowsum of W | dK/dh sum][wi][query]
   int64_t qt, split;
   if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
@@ -301,7 +300,13 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wi = wave >> 1, wq = wave & 1;   // first product
   const int wt = wave >> 1;                  // second product: coordinate quarter
-  if (threadIdx.x < BQ) yns[threadIdx.x] = p.ynorm[qt * BQ + threadIdx.x];
+  // per-query terms of the exponent (as in the forward tiles)
+  float yv[4];
+#pragma unroll
+  for (int bq = 0; bq < 4; ++bq) {
+    const double yn = p.ynorm[qt * BQ + wq * 64 + bq * 16 + (lane & 15)];
+    yv[bq] = KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * yn) : (float)yn;
+  }
   float* W = reinterpret_cast<float*>(lds);
 
   f32x4 gacc[4][TBW];
@@ -362,33 +367,35 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
       }
       buf ^= 1;
     }
-    // weights; per-tile FP32 row sums folded into FP64
+    // weights in FP32 (the same exponent arithmetic as the forward tiles; the
+    // constant factors 1/h^2, 1/h, -1/L and the Gaussian query factor are
+    // applied per query by the reduction); per-tile FP32 row sums folded into FP64
     float rw32[4] = {0.f, 0.f, 0.f, 0.f}, dh32[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = t * BN + wi * 32 + bi * 16 + 4 * (lane >> 4) + r;
-        const bool valid = row < p.n;
         const double xn = p.xnorm[row];
+        // padding rows: a huge finite term, so that K = 0 and K * d^2 = 0
+        const float xv = row < p.n ? (KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * xn) : (float)xn)
+                                   : (KERN == KERNEL_GAUSSIAN ? -1e30f : 1e30f);
 #pragma unroll
         for (int bq = 0; bq < 4; ++bq) {
-          const double s = (double)acc[bi][bq][r];
-          const float d2 = fmaxf(0.f, (float)__builtin_fma(
-              -2.0, s, xn + yns[wq * 64 + bq * 16 + (lane & 15)]));
+          const float s = acc[bi][bq][r];
           float w, dh;
           if (KERN == KERNEL_GAUSSIAN) {
-            const float K = __builtin_amdgcn_exp2f(-L * d2);
-            w = K * inv_h2;
-            dh = K * d2 * inv_h2 * inv_h;
+            const float a = fminf(__builtin_fmaf(2.f * L, s, yv[bq] + xv), 0.f);   // -L d^2
+            const float K = __builtin_amdgcn_exp2f(a);
+            w = K;
+            dh = K * a;
           } else {
+            const float d2 = fmaxf(__builtin_fmaf(-2.f, s, yv[bq] + xv), 0.f);
             const float rr = __builtin_sqrtf(d2);
             const float K = __builtin_amdgcn_exp2f(-L * rr);
-            w = rr > 0.f ? K * inv_h / rr : 0.f;
-            dh = K * rr * inv_h2;
+            w = rr > 0.f ? K * __builtin_amdgcn_rcpf(rr) : 0.f;
+            dh = K * rr;
           }
-          w = valid ? w : 0.f;
-          dh = valid ? dh : 0.f;
           acc[bi][bq][r] = w;
           rw32[bq] += w;
           dh32[bq] += dh;
@@ -465,25 +472,36 @@ kde_backward_kernel(TileProblem p, float L, float inv_h, float inv_h2,
   }
 }
 
-// grad_Y[q] = g_q / n * (sum_s G_s[q] - y~_q sum_s rowsum_s[q]);  per-query h term.
+// grad_Y[q] = g_q / n * c_y * f_q * (sum_s G_s[q] - y~_q sum_s rowsum_s[q]) and the
+// per-query h term g_q / n * c_h * f_q * sum_s dh_s[q], where c_y, c_h are the
+// constant factors left out of the tile weights and f_q is the Gaussian query
+// factor 2^(rounding remainder of -L ||y||^2) (1 for the exponential kernel).
 __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
                                            const double* __restrict__ rw_part,
                                            const double* __restrict__ gh_part,
                                            const float* __restrict__ Ys, int64_t splits,
                                            int64_t qp, int64_t q, int64_t d, int64_t dp,
-                                           double inv_n, const double* __restrict__ grad_out,
+                                           double inv_n, const double* __restrict__ ynorm,
+                                           float L, int kern, double c_y, double c_h,
+                                           const double* __restrict__ grad_out,
                                            float* __restrict__ grad_Y, double* __restrict__ ghq) {
   const int64_t qi = blockIdx.x;
-  __shared__ double rw_s;
+  __shared__ double rw_s, f_s;
   if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
     for (int64_t s = 0; s < splits; ++s) { a += rw_part[s * qp + qi]; b += gh_part[s * qp + qi]; }
+    double f = 1.0;
+    if (kern == KERNEL_GAUSSIAN) {
+      const double e = -(double)L * ynorm[qi];
+      f = exp2(e - (double)(float)e);
+    }
     rw_s = a;
-    if (ghq) ghq[qi] = grad_out[qi] * b * inv_n;
+    f_s = f;
+    if (ghq) ghq[qi] = grad_out[qi] * inv_n * c_h * f * b;
   }
   __syncthreads();
   if (!grad_Y) return;
-  const double sc = grad_out[qi] * inv_n;
+  const double sc = grad_out[qi] * inv_n * c_y * f_s;
   for (int64_t t = threadIdx.x; t < d; t += blockDim.x) {
     double g = 0.0;
     for (int64_t s = 0; s < splits; ++s) g += gy_part[(s * qp + qi) * dp + t];
@@ -492,15 +510,14 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
 }
 
 template <int KERN>
-static hipError_t launch_kde_bwd_k(const TileProblem& p, int TB, float L, float inv_h,
-                                   float inv_h2, double* gy, double* rw, double* gh,
-                                   hipStream_t s) {
+static hipError_t launch_kde_bwd_k(const TileProblem& p, int TB, float L, double* gy, double* rw,
+                                   double* gh, hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), b(BWG);
   switch (TB) {
-    case 2: kde_backward_kernel<KERN, 2><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh); break;
-    case 4: kde_backward_kernel<KERN, 4><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh); break;
-    case 6: kde_backward_kernel<KERN, 6><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh); break;
-    default: kde_backward_kernel<KERN, 8><<<g, b, 0, s>>>(p, L, inv_h, inv_h2, gy, rw, gh); break;
+    case 2: kde_backward_kernel<KERN, 2><<<g, b, 0, s>>>(p, L, gy, rw, gh); break;
+    case 4: kde_backward_kernel<KERN, 4><<<g, b, 0, s>>>(p, L, gy, rw, gh); break;
+    case 6: kde_backward_kernel<KERN, 6><<<g, b, 0, s>>>(p, L, gy, rw, gh); break;
+    default: kde_backward_kernel<KERN, 8><<<g, b, 0, s>>>(p, L, gy, rw, gh); break;
   }
   return hipGetLastError();
 }
@@ -518,17 +535,16 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, 
   hipError_t e;
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
   e = (kern == KERNEL_GAUSSIAN)
-                     ? launch_kde_bwd_k<KERNEL_GAUSSIAN>(p, TB, L, (float)(1.0 / h),
-                                                         (float)(1.0 / (h * h)), gy_part, rw_part,
-                                                         gh_part, s)
-                     : launch_kde_bwd_k<KERNEL_EXPONENTIAL>(p, TB, L, (float)(1.0 / h),
-                                                            (float)(1.0 / (h * h)), gy_part,
-                                                            rw_part, gh_part, s);
+          ? launch_kde_bwd_k<KERNEL_GAUSSIAN>(p, TB, L, gy_part, rw_part, gh_part, s)
+          : launch_kde_bwd_k<KERNEL_EXPONENTIAL>(p, TB, L, gy_part, rw_part, gh_part, s);
   if (e != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
+  // Gaussian: weights K, dh terms K * (-L d^2); exponential: weights K / r, dh terms K r
+  const double c_y = kern == KERNEL_GAUSSIAN ? 1.0 / (h * h) : 1.0 / h;
+  const double c_h = kern == KERNEL_GAUSSIAN ? -1.0 / (h * h * h * (double)L) : 1.0 / (h * h);
   kde_backward_reduce_kernel<<<dim3((unsigned)p.q), dim3(128), 0, s>>>(
       gy_part, rw_part, gh_part, reinterpret_cast<const float*>(p.Ys), p.splits, p.qp, p.q, d, dp,
-      1.0 / (double)p.n, grad_out, grad_Y, ghq);
+      1.0 / (double)p.n, p.ynorm, L, kern, c_y, c_h, grad_out, grad_Y, ghq);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!grad_h) return hipSuccess;
   sum_scalar_kernel<<<dim3(1), dim3(WG), 0, s>>>(ghq, p.q, grad_h);

@@ -1,6 +1,7 @@
 """Full-size parity in the benchmark's launch configuration: the 100-cluster
 mixture with n = 1,000,000, d = 128, q = 10,000 (k = 100, m = 1,000) and the
-differentiation workload n = 500,000, d = 64, q = 4,096.  Sampled queries are
+differentiation workload n = 500,000, d = 64, q = 4,096, and the large
+high-dimensional workload n = 1,000,000, d = 960, q = 10,000.  Sampled queries are
 checked against the oracle one by one; properties that hold at any size are
 checked on every query."""
 import numpy as np
@@ -78,3 +79,41 @@ def test_fullsize_exact_backward():
         K = oracle.kernel_values(d2, h, GAUSSIAN)
         scale = (K * np.sqrt(d2)).sum() / (X.shape[0] * h * h)
         assert np.linalg.norm(gy[j] - gy_ref) <= 1e-4 * scale
+
+
+def test_fullsize_d960_bf16_refine():
+    """Large high-dimensional workload (200-cluster mixture through |.|,
+    n = 1,000,000, d = 960, q = 10,000, k = 200, m = 2,000): the BF16 scan
+    with refinement gives the FP32 scan's result exactly; sampled queries and
+    the DEANN adjoint against the oracle."""
+    import paper_2107_02736_amd as dk
+    dev = device()
+    wl = "mix200_n1e6_d960"
+    spec, X, Y = synth.workload(wl)
+    h = bandwidth(wl, "gaussian")
+    k, m = 200, 2000
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    mu = dk.kde_exact(Xd, Yd, h, "gaussian", "fp32").cpu().numpy()
+    res = {p: dk.deann_query(Xd, Yd, h, k, m, "gaussian", seed=0, precision=p)
+           for p in ("bf16", "fp32")}
+    out, nn, sm = (t.cpu().numpy() for t in res["bf16"])
+    out32, nn32, sm32 = (t.cpu().numpy() for t in res["fp32"])
+    assert np.array_equal(nn, nn32) and np.array_equal(sm, sm32)
+    assert np.array_equal(out, out32)
+    assert np.all((mu >= 0) & (mu <= 1)) and np.all(out >= 0)
+    _check_indices(nn, sm, X.shape[0], k)
+    g = np.linspace(0.5, 1.5, Y.shape[0])
+    gy, gh = dk.deann_query_backward(Xd, Yd, h, k, m, res["bf16"][1], res["bf16"][2],
+                                     to_dev(g, dev), "gaussian")
+    gy = gy.cpu().numpy()
+    for j in synth.query_subset(Y.shape[0], 2, seed=13):
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, GAUSSIAN, k, m, 0, int(j))
+        assert np.array_equal(nn[j], nn_ref), j
+        assert np.array_equal(sm[j], s_ref), j
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
+        ref = oracle.kde_exact(X, Y[j:j + 1], h, GAUSSIAN)[0]
+        print(f"query {j}: exact {ref:.4e}, fp32 rel err {abs(mu[j] - ref) / ref:.2e}, "
+              f"DEANN rel err {abs(out[j] - ref) / ref:.2e}")
+        assert abs(mu[j] - ref) <= 1e-5 * ref
+        _, gy_ref, _ = oracle.deann_grad(X, Y[j], h, GAUSSIAN, nn_ref, s_ref, m)
+        assert np.linalg.norm(gy[j] - g[j] * gy_ref) <= 1e-6 * np.linalg.norm(g[j] * gy_ref)

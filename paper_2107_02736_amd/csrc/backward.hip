@@ -281,7 +281,13 @@ __device__ __forceinline__ void bstore(const u32x4 (&r)[BCV], char* lds) {
   }
 }
 
-template <int KERN, int TB>   // TB = padded d / 16, a multiple of 4 here... or 2, 6
+// Column of element (t, i) within row t of the transposed tile: groups of four
+// consecutive i stay contiguous (16-byte reads in the second product) and are
+// XOR-permuted by bits 3..4 of t, so that the transposed 4-byte writes of one
+// wave (8 coordinates x 8 rows) spread over all banks.
+__device__ __forceinline__ int xt_col(int t, int i) { return i ^ (((t >> 3) & 3) << 2); }
+
+template <int KERN, int TB>   // TB = padded d / 16: 2, 4, 6 or 8
 __global__ void __launch_bounds__(BWG, 1)
 kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
                     double* __restrict__ rw_part,
@@ -343,7 +349,8 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
         const int v = threadIdx.x + i * BWG;
         const int t4 = c * (CHUNK_BYTES / 4) + (v % 8) * 4;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) xt[(t4 + j) * XTS + v / 8] = __uint_as_float(rx[i][j]);
+        for (int j = 0; j < 4; ++j)
+          xt[(t4 + j) * XTS + xt_col(t4 + j, v / 8)] = __uint_as_float(rx[i][j]);
       }
       __syncthreads();
       int nc = c + 1;
@@ -353,6 +360,7 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
         bload(ry, yq, p.ld_bytes, (int64_t)nc * CHUNK_BYTES);
         bload(rx, p.Xs + nt * BN * p.ld_bytes, p.ld_bytes, (int64_t)nc * CHUNK_BYTES);
       }
+      __builtin_amdgcn_s_setprio(1);   // favour the wave issuing MFMAs
 #pragma unroll
       for (int kg = 0; kg < CHUNK_BYTES / KG_BYTES; ++kg) {
         u32x4 a[2], b[4];
@@ -365,6 +373,7 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
 #pragma unroll
           for (int bq = 0; bq < 4; ++bq) acc[bi][bq] = mfma_kgroup<float>(a[bi], b[bq], acc[bi][bq]);
       }
+      __builtin_amdgcn_s_setprio(0);
       buf ^= 1;
     }
     // weights in FP32 (the same exponent arithmetic as the forward tiles; the
@@ -426,7 +435,7 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
         const int tcol = (wt * TBW + tb) * 16;
         if (tcol < DP) {
           const f32x4 b = *reinterpret_cast<const f32x4*>(
-              &xt[(tcol + (lane & 15)) * XTS + kb * 16 + 4 * (lane >> 4)]);
+              &xt[(tcol + (lane & 15)) * XTS + xt_col(tcol + (lane & 15), kb * 16 + 4 * (lane >> 4))]);
 #pragma unroll
           for (int bq = 0; bq < 4; ++bq)
 #pragma unroll

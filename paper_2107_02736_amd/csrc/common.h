@@ -229,10 +229,12 @@ __device__ __forceinline__ void stream_tile(f32x4 (&acc)[4][4], StreamState& st,
       load_chunk(st.rq, yq, ld_bytes, (int64_t)nc * CHUNK_BYTES);
       load_chunk(st.rx, Xs + nt * BN * ld_bytes, ld_bytes, (int64_t)nc * CHUNK_BYTES);
     }
+    __builtin_amdgcn_s_setprio(1);   // favour the wave issuing MFMAs
     if (SWAP)
       mfma_chunk<T>(acc, xa, qa, wq, wn, lane);
     else
       mfma_chunk<T>(acc, qa, xa, wq, wn, lane);
+    __builtin_amdgcn_s_setprio(0);
     st.buf ^= 1;
   }
 }

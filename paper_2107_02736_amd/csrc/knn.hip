@@ -348,19 +348,26 @@ template <typename T, int NKG>
 __global__ void __launch_bounds__(WG, 2)
 knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
-  __shared__ float yks[BQ];
   int64_t qt, split;
   if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
+  // Per (query, cell): the smallest key seen, with the column block j (0..3)
+  // packed into its two low mantissa bits so that one min tracks both, and
+  // the tile it came from.  The packing perturbs keys by at most 3 ulp; the
+  // candidates only seed the second pass, which alone decides the result.
+  __shared__ float yks[BQ];
   if (threadIdx.x < BQ) yks[threadIdx.x] = p.yknorm[qt * BQ + threadIdx.x];
   float best[4][4];
-  uint32_t bidx[4][4];
+  int32_t btile[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) { best[i][r] = __builtin_inff(); bidx[i][r] = 0xffffffffu; }
+    for (int r = 0; r < 4; ++r) {
+      best[i][r] = __builtin_inff();
+      btile[i][r] = -1;
+    }
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
   constexpr int NK = NKG > 0 ? NKG : 1;
   StreamState st;
@@ -381,30 +388,38 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
       stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
     else
       yreg_tile<T, NK>(acc, xs, yf, p.Xs, p.ld_bytes, t, t1, lds, wn, lane);
+    float xk[4];   // padding columns: a huge finite key (never NaN after packing)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-      const float xk = col < p.n ? p.xknorm[col] : __builtin_inff();
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float key =
-              __builtin_fmaf(-2.f, acc[i][j][r], yks[wq * 64 + i * 16 + 4 * (lane >> 4) + r] + xk);
-          const bool better = key < best[i][r];
-          best[i][r] = better ? key : best[i][r];
-          bidx[i][r] = better ? (uint32_t)col : bidx[i][r];
-        }
+      xk[j] = col < p.n ? p.xknorm[col] : 3.0e38f;
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float yk = yks[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
+        float m = __builtin_inff();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]);
+          m = fminf(m, __uint_as_float((__float_as_uint(key) & ~3u) | (uint32_t)j));
+        }
+        const bool better = m < best[i][r];
+        best[i][r] = better ? m : best[i][r];
+        btile[i][r] = better ? (int32_t)t : btile[i][r];
+      }
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
-      const uint64_t v = bidx[i][r] == 0xffffffffu
+      const int64_t col = (int64_t)btile[i][r] * BN + wn * 64 +
+                          (int64_t)(__float_as_uint(best[i][r]) & 3u) * 16 + (lane & 15);
+      const uint64_t v = (btile[i][r] < 0 || col >= p.n)
                              ? ~0ull
-                             : ((uint64_t)float_key(best[i][r]) << 32) | (uint64_t)bidx[i][r];
+                             : ((uint64_t)float_key(best[i][r]) << 32) | (uint64_t)col;
       cand[(split * p.qp + row) * CELLS + wn * 16 + (lane & 15)] = v;
     }
   if (threadIdx.x < BQ) cand_cnt[split * p.qp + qt * BQ + threadIdx.x] = CELLS;
@@ -556,21 +571,39 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
       stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
     else
       yreg_tile<T, NK>(acc, xs, yf, p.Xs, p.ld_bytes, t, t1, lds, wn, lane);
+    // fl(key - th) <= 0 exactly when key <= th; padding columns (infinite
+    // key) and queries without a second pass (th = -inf) never hit
+    float xk[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-      const float xk = col < p.n ? p.xknorm[col] : __builtin_inff();
+      xk[j] = col < p.n ? p.xknorm[col] : __builtin_inff();
+    }
+    float m = __builtin_inff();
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk[i][r] + xk);
-          if (key <= th[i][r]) {
-            const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
-            const int slot = atomicAdd(&b.cand2_cnt[row], 1);
-            if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = (uint64_t)col;
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          m = fminf(m, __builtin_fmaf(-2.f, acc[i][j][r], yk[i][r] + xk[j]) - th[i][r]);
+    if (m <= 0.f) {   // rare: append the hits of this lane
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
+        if (col >= p.n) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk[i][r] + xk[j]);
+            if (key <= th[i][r]) {
+              const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+              const int slot = atomicAdd(&b.cand2_cnt[row], 1);
+              if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = (uint64_t)col;
+            }
           }
-        }
+      }
     }
   }
 }

@@ -176,6 +176,26 @@ def test_degenerate_k_m(dev, k, m):
         assert np.allclose(out, ref, rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("n,k", [(129, 100), (129, 128), (300, 120), (700, 250)])
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_knn_more_neighbours_than_cells(dev, n, k, prec):
+    # k above the number of 16-bit candidate cells (32 per data split): the
+    # second pass runs with an infinite threshold and must still skip the
+    # padding columns of the last data tile
+    import paper_2107_02736_amd as dk
+    X, Y = _small(n, 9, 5, seed=n + k)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h, m = 1.4, 37
+    out, nn, sm = (t.cpu().numpy() for t in dk.deann_query(Xd, Yd, h, k, m, "gaussian", seed=5,
+                                                            precision=prec))
+    assert nn.max() < n and sm.max() < n
+    for j in range(Y.shape[0]):
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, GAUSSIAN, k, m, 5, j)
+        assert np.array_equal(nn[j], nn_ref), j
+        assert np.array_equal(sm[j], s_ref), j
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_knn_exact_ties_and_duplicates(dev, prec):
     # integer lattice data: many exactly equal distances, duplicate rows

@@ -66,7 +66,7 @@ TimingHook timer_hook(int site) {
 
 constexpr int64_t kAlign = 256;
 constexpr int64_t kMaxK = 496;             // k limit of the candidate-list kernels (K1 <= 512)
-constexpr int64_t kCenterRows = 256;       // row slices of the column-mean reduction
+constexpr int64_t kCenterRows = 2048;      // row slices of the column-mean reduction
 constexpr int64_t kSortCap = 4096;         // second-pass candidate capacity per query
 
 int64_t elem_bytes(int prec) { return prec == DEANN_FP32 ? 4 : 2; }

@@ -468,9 +468,10 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
     const bool flush = (fill_s + K1 > SORT_CAP) || (s + 1 == a.splits);
     if (flush && fill_s >= K1) {   // sorted whenever the K1-th key is used
       const int F = fill_s;
-      for (int i = F + threadIdx.x; i < SORT_CAP; i += WG) buf[i] = ~0ull;
+      const int N = next_pow2(F);   // <= SORT_CAP
+      for (int i = F + threadIdx.x; i < N; i += WG) buf[i] = ~0ull;
       __syncthreads();
-      block_sort_u64(buf, SORT_CAP);
+      block_sort_u64(buf, N);
       if (threadIdx.x == 0) fill_s = K1;
       __syncthreads();
     }

@@ -25,22 +25,40 @@ __global__ void __launch_bounds__(WG) center_partial_kernel(const float* __restr
   const int64_t col = (int64_t)blockIdx.x * 64 + tx;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per;
   const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
-  double s = 0.0;
-  if (col < d)
-    for (int64_t r = r0 + ty; r < r1; r += 4) s += (double)X[r * d + col];
-  red[threadIdx.x] = s;
+  // four independent accumulators (rows r, r+4, r+8, r+12 of each step of 16),
+  // combined in a fixed order
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (col < d) {
+    int64_t r = r0 + ty;
+    for (; r + 12 < r1; r += 16) {
+      s0 += (double)X[r * d + col];
+      s1 += (double)X[(r + 4) * d + col];
+      s2 += (double)X[(r + 8) * d + col];
+      s3 += (double)X[(r + 12) * d + col];
+    }
+    for (; r < r1; r += 4) s0 += (double)X[r * d + col];
+  }
+  red[threadIdx.x] = (s0 + s1) + (s2 + s3);
   __syncthreads();
   if (ty == 0 && col < d)
     part[(int64_t)blockIdx.y * d + col] = ((red[tx] + red[tx + 64]) + red[tx + 128]) + red[tx + 192];
 }
 
-__global__ void center_finalize_kernel(const double* __restrict__ part, int64_t R, int64_t n,
-                                       int64_t d, float* __restrict__ c) {
-  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= d) return;
+// One workgroup per column: strided partial sums, then a fixed-order tree.
+__global__ void __launch_bounds__(WG) center_finalize_kernel(const double* __restrict__ part,
+                                                             int64_t R, int64_t n, int64_t d,
+                                                             float* __restrict__ c) {
+  __shared__ double red[WG];
+  const int64_t col = blockIdx.x;
   double s = 0.0;
-  for (int64_t r = 0; r < R; ++r) s += part[r * d + col];
-  c[col] = (float)(s / (double)n);
+  for (int64_t r = threadIdx.x; r < R; r += WG) s += part[r * d + col];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = WG / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c[col] = (float)(red[0] / (double)n);
 }
 
 template <typename T>
@@ -152,7 +170,7 @@ hipError_t launch_center(const float* X, int64_t n, int64_t d, double* part, int
       X, n, d, rows_per, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  center_finalize_kernel<<<dim3((unsigned)ceil_div(d, 256)), dim3(256), 0, s>>>(part, R, n, d, c);
+  center_finalize_kernel<<<dim3((unsigned)d), dim3(WG), 0, s>>>(part, R, n, d, c);
   return hipGetLastError();
 }
 

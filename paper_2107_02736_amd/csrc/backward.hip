@@ -332,7 +332,16 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
     bload(rx, p.Xs + t0 * BN * p.ld_bytes, p.ld_bytes, 0);
   }
   __syncthreads();
+  // data norms one tile ahead, one per thread, staged in LDS when the tile
+  // starts (published by the chunk barriers; xnorm covers the padded rows)
+  __shared__ double xns[2][BN];
+  double xn_reg = (threadIdx.x < BN && t0 < t1) ? p.xnorm[t0 * BN + threadIdx.x] : 0.0;
   for (int64_t t = t0; t < t1; ++t) {
+    const int nb = (int)((t - t0) & 1);
+    if (threadIdx.x < BN) {
+      xns[nb][threadIdx.x] = xn_reg;
+      if (t + 1 < t1) xn_reg = p.xnorm[(t + 1) * BN + threadIdx.x];
+    }
     f32x4 acc[2][4];   // [bi][bq]: rows = data, columns = queries
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -385,7 +394,7 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = t * BN + wi * 32 + bi * 16 + 4 * (lane >> 4) + r;
-        const double xn = p.xnorm[row];
+        const double xn = xns[nb][wi * 32 + bi * 16 + 4 * (lane >> 4) + r];
         // padding rows: a huge finite term, so that K = 0 and K * d^2 = 0
         const float xv = row < p.n ? (KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * xn) : (float)xn)
                                    : (KERN == KERNEL_GAUSSIAN ? -1e30f : 1e30f);

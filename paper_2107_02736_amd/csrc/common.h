@@ -239,6 +239,70 @@ __device__ __forceinline__ void stream_tile(f32x4 (&acc)[4][4], StreamState& st,
   }
 }
 
+// Query tile resident in LDS, data chunks two steps ahead, for rows of exactly
+// 256 bytes (16-bit operands with 64 < d <= 128: two chunks per tile).  The
+// query tile is copied to LDS once per workgroup; per chunk only the data
+// chunk is stored, and the registers of chunk c are refilled with chunk c of
+// the next tile right after the barrier, so a load has a whole tile (both
+// chunks and the epilogue) to arrive.  LDS: QL_Y_BYTES + 2 * TILE_LDS bytes.
+// Usage as stream_tile: ql_start once, ql_tile per data tile, __syncthreads()
+// before reusing the staging area.
+constexpr int QL_ROWB = 2 * CHUNK_BYTES;
+constexpr int QL_YROW = QL_ROWB + ROW_PAD;
+constexpr int QL_Y_BYTES = BQ * QL_YROW;
+
+struct QlState {
+  ChunkRegs rx[2];
+};
+
+__device__ __forceinline__ void ql_start(QlState& st, const char* __restrict__ yq,
+                                         const char* __restrict__ Xs, int64_t t0, char* lds) {
+  __syncthreads();   // previous users of the staging area are done
+  constexpr int VECS = BQ * QL_ROWB / 16;
+#pragma unroll
+  for (int i = 0; i < VECS / WG; ++i) {
+    const int v = threadIdx.x + i * WG;
+    const int row = v / (QL_ROWB / 16), col = v % (QL_ROWB / 16);
+    *reinterpret_cast<u32x4*>(lds + row * QL_YROW + col * 16) =
+        *reinterpret_cast<const u32x4*>(yq + row * QL_ROWB + col * 16);
+  }
+  load_chunk(st.rx[0], Xs + t0 * BN * QL_ROWB, QL_ROWB, 0);
+  load_chunk(st.rx[1], Xs + t0 * BN * QL_ROWB, QL_ROWB, CHUNK_BYTES);
+}
+
+template <typename T>
+__device__ __forceinline__ void ql_tile(f32x4 (&acc)[4][4], QlState& st,
+                                        const char* __restrict__ Xs, int64_t t, int64_t t1,
+                                        char* lds, int wq, int wn, int lane) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    char* xa = lds + QL_Y_BYTES + c * TILE_LDS;
+    store_chunk(st.rx[c], xa);
+    __syncthreads();
+    if (t + 1 < t1) load_chunk(st.rx[c], Xs + (t + 1) * BN * QL_ROWB, QL_ROWB, c * CHUNK_BYTES);
+    __builtin_amdgcn_s_setprio(1);   // favour the wave issuing MFMAs
+#pragma unroll
+    for (int kg = 0; kg < CHUNK_BYTES / KG_BYTES; ++kg) {
+      u32x4 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[i] = *reinterpret_cast<const u32x4*>(lds + (wq * 64 + i * 16 + (lane & 15)) * QL_YROW +
+                                               c * CHUNK_BYTES + kg * KG_BYTES + (lane >> 4) * 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = lds_frag(xa, wn * 64 + j * 16, kg, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma_kgroup<T>(a[i], b[j], acc[i][j]);
+    }
+    __builtin_amdgcn_s_setprio(0);
+  }
+}
+
 // Query-stationary sweep for 16-bit operands with at most 256 bytes per row
 // (d <= 128): each wave keeps its 64 query rows' A fragments in registers for
 // the whole kernel, and only the data tiles stream through LDS, a whole tile
@@ -317,14 +381,16 @@ __device__ __forceinline__ void yreg_tile(f32x4 (&acc)[4][4], XStream<NKG>& st,
   st.buf ^= 1;
 }
 
-// k-groups of the query-stationary engine for this operand type and row size,
-// or 0 for the generic stream.  Only 128-byte rows (16-bit operands, d <= 64)
-// use it: with 256-byte rows the resident query fragments no longer fit two
-// workgroups per CU and the generic stream is faster.
+// Engine for a tile kernel: 2 = query fragments in registers (16-bit rows of
+// 128 bytes, d <= 64); 1 = query tile in LDS (16-bit rows of 256 bytes,
+// 64 < d <= 128); 0 = generic stream.  Query fragments in registers for 256-byte
+// rows would not leave room for two workgroups per CU.
 template <typename T>
-inline int query_stationary_kgroups(int64_t ld_bytes) {
-  if (elem_of<T>::bytes != 2 || ld_bytes != 2 * KG_BYTES) return 0;
-  return 2;
+inline int tile_engine(int64_t ld_bytes) {
+  if (elem_of<T>::bytes != 2) return 0;
+  if (ld_bytes == 2 * KG_BYTES) return 2;
+  if (ld_bytes == QL_ROWB) return 1;
+  return 0;
 }
 
 // XCD-aware placement.  Workgroups are dispatched round-robin over the 8 XCDs,

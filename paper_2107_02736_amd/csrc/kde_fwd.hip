@@ -22,7 +22,7 @@
 
 namespace deann {
 
-template <typename T, int KERN, int NKG>   // NKG > 0: query-stationary engine
+template <typename T, int KERN, int ENG>   // ENG: see tile_engine
 __global__ void __launch_bounds__(WG, 2)
 kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_t ld_bytes,
                 int nchunks, const double* __restrict__ ynorm, const double* __restrict__ xnorm,
@@ -52,23 +52,39 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
     for (int r = 0; r < 4; ++r) sum[i][r] = 0.0;
 
   const char* yq = Ys + qt * BQ * ld_bytes;
-  constexpr int NK = NKG > 0 ? NKG : 1;
+  constexpr int NK = 2;   // k-groups of the register-resident engine
   StreamState st;
   XStream<NK> xs;
   u32x4 yf[4][NK];
+  QlState ql;
   if (t0 < t1) {
-    if constexpr (NKG == 0) {
+    if constexpr (ENG == 0) {
       stream_start(st, yq, Xs, ld_bytes, t0);
+    } else if constexpr (ENG == 1) {
+      ql_start(ql, yq, Xs, t0, lds);
     } else {
       yreg_load<NK>(yf, yq, ld_bytes, wq, lane);
       xs_load(xs, Xs + t0 * BN * ld_bytes, ld_bytes);
       xs.buf = 0;
     }
   }
+  // The data norms of a tile are fetched one tile ahead, one per thread, and
+  // staged in LDS (double-buffered) when the tile starts; the barrier inside
+  // the tile sweep publishes them before the epilogue.  xnorm covers the
+  // padded rows.
+  __shared__ double xns[2][BN];
+  double xn_reg = (threadIdx.x < BN && t0 < t1) ? xnorm[t0 * BN + threadIdx.x] : 0.0;
   for (int64_t t = t0; t < t1; ++t) {
+    const int nb = (int)((t - t0) & 1);
+    if (threadIdx.x < BN) {
+      xns[nb][threadIdx.x] = xn_reg;
+      if (t + 1 < t1) xn_reg = xnorm[(t + 1) * BN + threadIdx.x];
+    }
     f32x4 acc[4][4];
-    if constexpr (NKG == 0)
+    if constexpr (ENG == 0)
       stream_tile<T>(acc, st, yq, Xs, ld_bytes, nchunks, t, t1, lds, wq, wn, lane);
+    else if constexpr (ENG == 1)
+      ql_tile<T>(acc, ql, Xs, t, t1, lds, wq, wn, lane);
     else
       yreg_tile<T, NK>(acc, xs, yf, Xs, ld_bytes, t, t1, lds, wn, lane);
     // per-column data terms; padding columns get a term that zeroes the kernel
@@ -76,7 +92,7 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-      const double xn = xnorm[col];
+      const double xn = xns[nb][wn * 64 + j * 16 + (lane & 15)];
       if (KERN == KERNEL_GAUSSIAN)
         xt[j] = col < n ? (float)(-(double)Lf * xn) : -__builtin_inff();
       else
@@ -145,9 +161,9 @@ __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t sp
   out[i] = s * inv_n;
 }
 
-template <typename T, int KERN, int NKG>
+template <typename T, int KERN, int ENG>
 static void launch_kde_k(const TileProblem& p, float L, double* partial, hipStream_t s) {
-  kde_tile_kernel<T, KERN, NKG><<<dim3((unsigned)p.map.grid), dim3(WG), 0, s>>>(
+  kde_tile_kernel<T, KERN, ENG><<<dim3((unsigned)p.map.grid), dim3(WG), 0, s>>>(
       p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
       partial, p.qp, p.map);
 }
@@ -155,8 +171,9 @@ static void launch_kde_k(const TileProblem& p, float L, double* partial, hipStre
 template <typename T, int KERN>
 static void launch_kde_n(const TileProblem& p, float L, double* partial, hipStream_t s) {
   if constexpr (elem_of<T>::bytes == 2) {
-    const int nkg = query_stationary_kgroups<T>(p.ld_bytes);
-    if (nkg == 2) return launch_kde_k<T, KERN, 2>(p, L, partial, s);
+    const int eng = tile_engine<T>(p.ld_bytes);
+    if (eng == 2) return launch_kde_k<T, KERN, 2>(p, L, partial, s);
+    if (eng == 1) return launch_kde_k<T, KERN, 1>(p, L, partial, s);
   }
   launch_kde_k<T, KERN, 0>(p, L, partial, s);
 }

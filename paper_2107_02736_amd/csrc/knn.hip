@@ -302,14 +302,21 @@ knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
   __syncthreads();   // thr / cnt initialised
   StreamState st;
   if (t0 < t1) stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+  __shared__ float xks[2][BN];   // data key norms, one tile ahead (see kde_tile_kernel)
+  float xk_reg = (threadIdx.x < BN && t0 < t1) ? p.xknorm[t0 * BN + threadIdx.x] : 0.f;
   for (int64_t t = t0; t < t1; ++t) {
+    const int nb = (int)((t - t0) & 1);
+    if (threadIdx.x < BN) {
+      xks[nb][threadIdx.x] = xk_reg;
+      if (t + 1 < t1) xk_reg = p.xknorm[(t + 1) * BN + threadIdx.x];
+    }
     f32x4 acc[4][4];
     stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
     float xk[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-      xk[j] = col < p.n ? p.xknorm[col] : __builtin_inff();
+      xk[j] = col < p.n ? xks[nb][wn * 64 + j * 16 + (lane & 15)] : __builtin_inff();
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -344,7 +351,7 @@ knn_scan_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
 // ---------------------------------------------------------------------------
 constexpr int CELLS = 32;   // cells per (split, query): 16 lane columns x 2 waves
 
-template <typename T, int NKG>
+template <typename T, int ENG>   // ENG: see tile_engine
 __global__ void __launch_bounds__(WG, 2)
 knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
@@ -369,30 +376,42 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
       btile[i][r] = -1;
     }
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
-  constexpr int NK = NKG > 0 ? NKG : 1;
+  constexpr int NK = 2;   // k-groups of the register-resident engine
   StreamState st;
   XStream<NK> xs;
   u32x4 yf[4][NK];
+  QlState ql;
   if (t0 < t1) {
-    if constexpr (NKG == 0) {
+    if constexpr (ENG == 0) {
       stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+    } else if constexpr (ENG == 1) {
+      ql_start(ql, yq, p.Xs, t0, lds);
     } else {
       yreg_load<NK>(yf, yq, p.ld_bytes, wq, lane);
       xs_load(xs, p.Xs + t0 * BN * p.ld_bytes, p.ld_bytes);
       xs.buf = 0;
     }
   }
+  __shared__ float xks[2][BN];   // data key norms, one tile ahead (see kde_tile_kernel)
+  float xk_reg = (threadIdx.x < BN && t0 < t1) ? p.xknorm[t0 * BN + threadIdx.x] : 0.f;
   for (int64_t t = t0; t < t1; ++t) {
+    const int nb = (int)((t - t0) & 1);
+    if (threadIdx.x < BN) {
+      xks[nb][threadIdx.x] = xk_reg;
+      if (t + 1 < t1) xk_reg = p.xknorm[(t + 1) * BN + threadIdx.x];
+    }
     f32x4 acc[4][4];
-    if constexpr (NKG == 0)
+    if constexpr (ENG == 0)
       stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
+    else if constexpr (ENG == 1)
+      ql_tile<T>(acc, ql, p.Xs, t, t1, lds, wq, wn, lane);
     else
       yreg_tile<T, NK>(acc, xs, yf, p.Xs, p.ld_bytes, t, t1, lds, wn, lane);
     float xk[4];   // padding columns: a huge finite key (never NaN after packing)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-      xk[j] = col < p.n ? p.xknorm[col] : 3.0e38f;
+      xk[j] = col < p.n ? xks[nb][wn * 64 + j * 16 + (lane & 15)] : 3.0e38f;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -533,7 +552,7 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
 // ---------------------------------------------------------------------------
 // 3. second pass: collect every point whose key admits distance <= d_k
 // ---------------------------------------------------------------------------
-template <typename T, int NKG>
+template <typename T, int ENG>   // ENG: see tile_engine
 __global__ void __launch_bounds__(WG, 2)
 knn_collect_kernel(TileProblem p, KnnBuffers b) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
@@ -553,23 +572,35 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
       th[i][r] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
     }
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
-  constexpr int NK = NKG > 0 ? NKG : 1;
+  constexpr int NK = 2;   // k-groups of the register-resident engine
   StreamState st;
   XStream<NK> xs;
   u32x4 yf[4][NK];
+  QlState ql;
   if (t0 < t1) {
-    if constexpr (NKG == 0) {
+    if constexpr (ENG == 0) {
       stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+    } else if constexpr (ENG == 1) {
+      ql_start(ql, yq, p.Xs, t0, lds);
     } else {
       yreg_load<NK>(yf, yq, p.ld_bytes, wq, lane);
       xs_load(xs, p.Xs + t0 * BN * p.ld_bytes, p.ld_bytes);
       xs.buf = 0;
     }
   }
+  __shared__ float xks[2][BN];   // data key norms, one tile ahead (see kde_tile_kernel)
+  float xk_reg = (threadIdx.x < BN && t0 < t1) ? p.xknorm[t0 * BN + threadIdx.x] : 0.f;
   for (int64_t t = t0; t < t1; ++t) {
+    const int nb = (int)((t - t0) & 1);
+    if (threadIdx.x < BN) {
+      xks[nb][threadIdx.x] = xk_reg;
+      if (t + 1 < t1) xk_reg = p.xknorm[(t + 1) * BN + threadIdx.x];
+    }
     f32x4 acc[4][4];
-    if constexpr (NKG == 0)
+    if constexpr (ENG == 0)
       stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
+    else if constexpr (ENG == 1)
+      ql_tile<T>(acc, ql, p.Xs, t, t1, lds, wq, wn, lane);
     else
       yreg_tile<T, NK>(acc, xs, yf, p.Xs, p.ld_bytes, t, t1, lds, wn, lane);
     // fl(key - th) <= 0 exactly when key <= th; padding columns (infinite
@@ -578,7 +609,7 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-      xk[j] = col < p.n ? p.xknorm[col] : __builtin_inff();
+      xk[j] = col < p.n ? xks[nb][wn * 64 + j * 16 + (lane & 15)] : __builtin_inff();
     }
     float m = __builtin_inff();
 #pragma unroll
@@ -735,20 +766,23 @@ static hipError_t launch_tiles(const TileProblem& p, const KnnBuffers& b, bool c
                                hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), blk(WG);
   if (collect) {
-    const int nkg = query_stationary_kgroups<T>(p.ld_bytes);
+    const int eng = tile_engine<T>(p.ld_bytes);
     if constexpr (elem_of<T>::bytes == 2) {
-      if (nkg == 2) knn_collect_kernel<T, 2><<<g, blk, 0, s>>>(p, b);
+      if (eng == 2) knn_collect_kernel<T, 2><<<g, blk, 0, s>>>(p, b);
+      else if (eng == 1) knn_collect_kernel<T, 1><<<g, blk, 0, s>>>(p, b);
       else knn_collect_kernel<T, 0><<<g, blk, 0, s>>>(p, b);
     } else {
       knn_collect_kernel<T, 0><<<g, blk, 0, s>>>(p, b);
     }
-  } else {
+  } else if constexpr (elem_of<T>::bytes == 4) {   // 16-bit scans use the candidate pass
     switch (b.cap1) {
       case 256: knn_scan_kernel<T, 4><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1); break;
       case 512: knn_scan_kernel<T, 8><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1); break;
       case 1024: knn_scan_kernel<T, 16><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1); break;
       default: knn_scan_kernel<T, 32><<<g, blk, 0, s>>>(p, b.cand, b.cand_cnt, (int)b.K1); break;
     }
+  } else {
+    return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -775,12 +809,14 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
   if (approx) {
     // 16-bit scans: cheap cell candidates, then the certified second pass
     const dim3 g((unsigned)pc.map.grid), blk(WG);
-    const int nkg = query_stationary_kgroups<__bf16>(pc.ld_bytes);
+    const int eng = tile_engine<__bf16>(pc.ld_bytes);
     if (prec == PREC_BF16) {
-      if (nkg == 2) knn_cand_kernel<__bf16, 2><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
+      if (eng == 2) knn_cand_kernel<__bf16, 2><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
+      else if (eng == 1) knn_cand_kernel<__bf16, 1><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
       else knn_cand_kernel<__bf16, 0><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
     } else {
-      if (nkg == 2) knn_cand_kernel<_Float16, 2><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
+      if (eng == 2) knn_cand_kernel<_Float16, 2><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
+      else if (eng == 1) knn_cand_kernel<_Float16, 1><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
       else knn_cand_kernel<_Float16, 0><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;

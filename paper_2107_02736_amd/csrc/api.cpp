@@ -156,7 +156,11 @@ TileProblem make_problem(const Prep& p, int64_t n, int64_t q, int prec, int64_t 
   t.qtiles = p.qp / BQ;
   t.ntiles = p.np / BN;
   t.splits = choose_splits(t.qtiles, t.ntiles, splits_target);
-  t.map = make_tile_map(t.qtiles, t.splits);
+  // engines that re-read the query tile per data tile group 4 splits per
+  // query-tile sweep (L2 reuse of both operands); the 16-bit engines for rows
+  // of at most 256 bytes hold the query tile in LDS or registers
+  const bool resident_query = prec != DEANN_FP32 && t.ld_bytes <= 2 * CHUNK_BYTES;
+  t.map = make_tile_map(t.qtiles, t.splits, resident_query ? 1 : 4);
   return t;
 }
 
@@ -453,6 +457,9 @@ int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int
   hipError_t e = run_prep(P.prep, X, n, Y, q, d, DEANN_FP32, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, kKdeSplitTarget);
+  // one 8-wave workgroup per CU: the query tiles of the split-major order
+  // already fit the L2 next to the shared data tiles
+  tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
   e = launch_kde_backward(tp, Y, d, h, kernel, grad_out, P.gy_part, P.gh_part, grad_Y, grad_h, s,
                           timer_hook(1));
   if (e != hipSuccess) return hip_fail(e, "kde backward");

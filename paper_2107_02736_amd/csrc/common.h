@@ -401,19 +401,32 @@ inline int tile_engine(int64_t ld_bytes) {
 // Returns false for the padding items beyond qtiles * splits.
 struct TileMap {
   int64_t grid;     // launched workgroups: qtiles * splits rounded up to 8
+  int64_t group;    // data splits per group (see map_tile)
 };
 
+// Workgroup placement.  Hardware workgroup ids are dealt round-robin to the 8
+// XCDs, so v below enumerates, for each XCD in turn, the workgroups it runs in
+// dispatch order.  Consecutive v cover `group` data splits for every query
+// tile in turn (query tile major within the group): the workgroups resident
+// on one XCD at a time then share the data tiles of a few splits in its L2
+// while their query tiles (re-read every data tile by the generic stream)
+// stay few enough to remain cached too.  With group = 1 it is split-major.
 __device__ __forceinline__ bool map_tile(int64_t hw, const TileMap& m, int64_t qtiles,
                                          int64_t splits, int64_t& qt, int64_t& split) {
   const int64_t v = (hw % 8) * (m.grid / 8) + hw / 8;
-  split = v / qtiles;
-  qt = v % qtiles;
-  return split < splits;
+  const int64_t span = qtiles * m.group;
+  const int64_t sg = v / span, rem = v % span;
+  const int64_t g = splits - sg * m.group < m.group ? splits - sg * m.group : m.group;
+  if (g <= 0) return false;
+  qt = rem / g;
+  split = sg * m.group + rem % g;
+  return qt < qtiles;
 }
 
-inline TileMap make_tile_map(int64_t qtiles, int64_t splits) {
+inline TileMap make_tile_map(int64_t qtiles, int64_t splits, int64_t group) {
   TileMap m;
   m.grid = (qtiles * splits + 7) / 8 * 8;
+  m.group = group < 1 ? 1 : (group > splits ? splits : group);
   return m;
 }
 

@@ -108,11 +108,12 @@ deann_backward_kernel(const float* __restrict__ X, const float* __restrict__ Y, 
   if (threadIdx.x == 0 && gh_part) gh_part[qi] = scale * hsum;
 }
 
-// Register-resident variant for d % 4 == 0 and d <= 64 * U: a group of 16
-// lanes gathers a row once (float4 loads, 256 contiguous bytes per group and
-// step), reduces ||x - y||^2 with shuffles, and accumulates w (x - y) into its
-// own FP64 coordinates; the 16 group partials are summed in a fixed order.
-template <int U>
+// Register-resident variant for d % 4 == 0 and d <= 4 * GW * U: a group of GW
+// lanes (16, or a whole wave for long rows) gathers a row once (float4 loads,
+// 16 * GW contiguous bytes per group and step), reduces ||x - y||^2 with
+// shuffles, and accumulates w (x - y) into its own FP64 coordinates; the group
+// partials are summed in a fixed order.
+template <int U, int GW>
 __global__ void __launch_bounds__(WG)
 deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
                           int64_t d, double h, int kern, int64_t k, int64_t m,
@@ -120,35 +121,36 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
                           const double* __restrict__ grad_out, float* __restrict__ grad_Y,
                           double* __restrict__ gh_part) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  double* part = reinterpret_cast<double*>(smem);   // [16][d]
-  double* hpart = part + 16 * d;                    // [16]
+  constexpr int NG = WG / GW;   // groups (rows in flight) per workgroup
+  double* part = reinterpret_cast<double*>(smem);   // [NG][d]
+  double* hpart = part + NG * d;                    // [NG]
   const int64_t qi = blockIdx.x;
-  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  const int g = threadIdx.x / GW, lg = threadIdx.x % GW;
   const int64_t size2 = n - k;
   const int64_t ms = (size2 > 0) ? m : 0;
   const int64_t R = k + ms;
   const double csamp = ms > 0 ? (double)size2 / (double)m : 0.0;
   const double inv_h2 = 1.0 / (h * h);
-  // this lane's coordinates: 4 * l16 + 64 * u + {0..3}
+  // this lane's coordinates: 4 * lg + 4 * GW * u + {0..3}
   float yv[U][4];
   double acc[U][4];
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int64_t t = 4 * l16 + 64 * u + c;
+      const int64_t t = 4 * lg + 4 * GW * u + c;
       yv[u][c] = t < d ? Y[qi * d + t] : 0.f;
       acc[u][c] = 0.0;
     }
   double hs = 0.0;
-  for (int64_t j = g; j < R; j += WG / 16) {
+  for (int64_t j = g; j < R; j += NG) {
     const int32_t row = j < k ? nn[qi * k + j] : samp[qi * m + (j - k)];
     const float* xr = X + (int64_t)row * d;
     float xv[U][4];
     double s = 0.0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t t = 4 * l16 + 64 * u;
+      const int64_t t = 4 * lg + 4 * GW * u;
       if (t < d) {
         const f32x4 v = *reinterpret_cast<const f32x4*>(xr + t);
         xv[u][0] = v[0]; xv[u][1] = v[1]; xv[u][2] = v[2]; xv[u][3] = v[3];
@@ -161,10 +163,8 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
         s = __builtin_fma(df, df, s);
       }
     }
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 4, 64);
-    s += __shfl_xor(s, 8, 64);
+#pragma unroll
+    for (int off = 1; off < GW; off <<= 1) s += __shfl_xor(s, off, 64);
     const double c = j < k ? 1.0 : csamp;
     double w, dh;
     if (kern == KERNEL_GAUSSIAN) {
@@ -189,21 +189,21 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
   for (int u = 0; u < U; ++u)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int64_t t = 4 * l16 + 64 * u + c;
+      const int64_t t = 4 * lg + 4 * GW * u + c;
       if (t < d) part[g * d + t] = acc[u][c];
     }
-  if (l16 == 0) hpart[g] = hs;
+  if (lg == 0) hpart[g] = hs;
   __syncthreads();
   const double scale = grad_out[qi] / (double)n;
   if (grad_Y)
     for (int64_t t = threadIdx.x; t < d; t += WG) {
       double v = 0.0;
-      for (int gg = 0; gg < WG / 16; ++gg) v += part[gg * d + t];
+      for (int gg = 0; gg < NG; ++gg) v += part[gg * d + t];
       grad_Y[qi * d + t] = (float)(scale * v);
     }
   if (threadIdx.x == 0 && gh_part) {
     double v = 0.0;
-    for (int gg = 0; gg < WG / 16; ++gg) v += hpart[gg];
+    for (int gg = 0; gg < NG; ++gg) v += hpart[gg];
     gh_part[qi] = scale * v;
   }
 }
@@ -228,22 +228,32 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
                                  const int32_t* samp, const double* grad_out, float* grad_Y,
                                  double* gh_part, double* grad_h, hipStream_t s) {
   if (q == 0) return hipSuccess;
-  const bool vec = (d % 4 == 0) && d <= 256 &&
-                   (reinterpret_cast<uintptr_t>(X) % 16 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
-  if (vec) {
+  const bool aligned = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+                       (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
+  const dim3 g((unsigned)q), b(WG);
+  if (aligned && d <= 256) {   // 16 lanes per row
     const size_t sm = (16 * d + 16) * 8;
-    const int U = (int)((d + 63) / 64);
-    const dim3 g((unsigned)q), b(WG);
-    switch (U) {
-      case 1: deann_backward_vec_kernel<1><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-      case 2: deann_backward_vec_kernel<2><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-      case 3: deann_backward_vec_kernel<3><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-      default: deann_backward_vec_kernel<4><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+    switch ((d + 63) / 64) {
+      case 1: deann_backward_vec_kernel<1, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+      case 2: deann_backward_vec_kernel<2, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+      case 3: deann_backward_vec_kernel<3, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+      default: deann_backward_vec_kernel<4, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+    }
+  } else if (aligned && d <= 2048) {   // a wave per row
+    const size_t sm = (4 * d + 4) * 8;
+    switch ((d + 255) / 256) {
+      case 1:
+      case 2: deann_backward_vec_kernel<2, 64><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+      case 3:
+      case 4: deann_backward_vec_kernel<4, 64><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+      case 5:
+      case 6: deann_backward_vec_kernel<6, 64><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
+      default: deann_backward_vec_kernel<8, 64><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
     }
   } else {
     const size_t sm = BWD_CHUNK * (8 + 8 + 4) + d * 4 + 16;
-    deann_backward_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(X, Y, n, d, h, kern, k, m, nn,
-                                                                  samp, grad_out, grad_Y, gh_part);
+    deann_backward_kernel<<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y,
+                                           gh_part);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !grad_h) return e;

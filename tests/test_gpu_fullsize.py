@@ -117,3 +117,41 @@ def test_fullsize_d960_bf16_refine():
         assert abs(mu[j] - ref) <= 1e-5 * ref
         _, gy_ref, _ = oracle.deann_grad(X, Y[j], h, GAUSSIAN, nn_ref, s_ref, m)
         assert np.linalg.norm(gy[j] - g[j] * gy_ref) <= 1e-6 * np.linalg.norm(g[j] * gy_ref)
+
+
+def test_fullsize_mean_shift_d64():
+    """Differentiation workload (50-cluster mixture, n = 500,000, d = 64,
+    q = 4,096): 20 Gaussian mean-shift steps of every query through the
+    autograd functions, exact (FP32 tiles) and DEANN (BF16 scan, k = 64,
+    m = 512).  Exact trajectories of sampled queries against the oracle's;
+    DEANN steps from the final points against the oracle's step."""
+    import time
+    import torch
+    import paper_2107_02736_amd as dk
+    dev = device()
+    wl = "mix50_n5e5_d64"
+    spec, X, Y = synth.workload(wl)
+    h = bandwidth(wl, "gaussian")
+    k, m, steps = 64, 512, 20
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    t0 = time.perf_counter()
+    ye = dk.mean_shift(Xd, Yd, h, steps, "exact")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    yd = dk.mean_shift(Xd, Yd, h, steps, "deann", k=k, m=m, seed=2, precision="bf16")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"20 mean-shift steps of 4096 queries: exact {t1 - t0:.3f} s, DEANN {t2 - t1:.3f} s")
+    ye, yd = ye.cpu().numpy(), yd.cpu().numpy()
+    assert np.all(np.isfinite(ye)) and np.all(np.isfinite(yd))
+    sub = synth.query_subset(Y.shape[0], 2, seed=17)
+    for j in sub:
+        ref = oracle.mean_shift_exact(X, Y[j], h, steps)
+        assert np.max(np.abs(ye[j] - ref)) <= 1e-3, j
+    # one more DEANN step from the GPU's end points (streams 0 and 1 of the subset)
+    y_end = np.ascontiguousarray(yd[sub])
+    y1 = dk.mean_shift(Xd, to_dev(y_end, dev), h, 1, "deann", k=k, m=m, seed=2,
+                       precision="bf16").cpu().numpy()
+    for i in range(len(sub)):
+        ref = oracle.mean_shift_deann(X, y_end[i], h, k, m, 2, i, 1)
+        assert np.max(np.abs(y1[i] - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))

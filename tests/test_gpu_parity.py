@@ -250,12 +250,13 @@ def test_extreme_bandwidths(dev):
 # adjoints
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("d", [12, 300, 301])   # 16 lanes per row, a wave per row, generic
 @pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
-def test_deann_backward_vs_oracle(dev, kern):
+def test_deann_backward_vs_oracle(dev, kern, d):
     import paper_2107_02736_amd as dk
-    X, Y = _small(3000, 40, 12, seed=7)
+    X, Y = _small(3000, 40, d, seed=7)
     Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
-    h, k, m = 1.3, 16, 100
+    h, k, m = 1.3 * np.sqrt(d / 12), 16, 100   # comparable kernel values at every d
     out, nn, sm = dk.deann_query(Xd, Yd, h, k, m, KNAME[kern], seed=4)
     g = np.linspace(0.5, 1.5, 40)
     gy, gh = dk.deann_query_backward(Xd, Yd, h, k, m, nn, sm, to_dev(g, dev), KNAME[kern])

@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-all-cores", action="store_true",
+                    help="skip the all-cores oracle run (single-core baseline only)")
     ap.add_argument("--cpu-sample", type=int, default=6, help="queries in the oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (counter calibration)")
@@ -183,12 +185,25 @@ def main():
     torch.cuda.synchronize()
     ms_deann32 = a.elapsed_time(b) / reps
 
+    # exact KDE with BF16 operands (not part of the step): speed and its error
+    # against the FP32 exact path (itself within about 1e-6 of the FP64 oracle)
+    mu16 = dk.kde_exact(Xd, Yd, h, KERNEL, "bf16")
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        mu16 = dk.kde_exact(Xd, Yd, h, KERNEL, "bf16")
+    b.record()
+    torch.cuda.synchronize()
+    ms_exact16 = a.elapsed_time(b) / reps
+
     mu_h = mu.cpu().numpy()
+    mu16_h = mu16.cpu().numpy()
     est_h, est32_h = est.cpu().numpy(), est32.cpu().numpy()
     same_idx = bool(torch.equal(nn, nn32) and torch.equal(sm, sm32))
     keep = mu_h >= 1e-16
     rel_bf16_vs_fp32 = float(np.max(np.abs(est_h - est32_h)[keep] / est32_h[keep])) if keep.any() else 0.0
     rel_deann_vs_exact = np.abs(est_h[keep] - mu_h[keep]) / mu_h[keep]
+    rel_exact16 = np.abs(mu16_h[keep] - mu_h[keep]) / mu_h[keep]
 
     flops_exact = 2.0 * n * d * q
     tile_avg_ms = float(np.mean(tile_ms))
@@ -229,6 +244,7 @@ def main():
             "deann_bf16_refine": q / (comp_ms["deann_bf16"] * 1e-3),
             "deann_fp32": q / (ms_deann32 * 1e-3),
             "kde_exact_fp32": q / (comp_ms["kde_exact_fp32"] * 1e-3),
+            "kde_exact_bf16": q / (ms_exact16 * 1e-3),
             "deann_backward": q / (comp_ms["deann_backward"] * 1e-3),
             "kde_exact_backward": (q / (comp_ms["kde_exact_backward"] * 1e-3)
                                    if exact_bwd else None),
@@ -236,6 +252,8 @@ def main():
         "accuracy": {
             "deann_bf16_vs_fp32_same_indices": same_idx,
             "deann_bf16_vs_fp32_max_rel": rel_bf16_vs_fp32,
+            "exact_bf16_vs_fp32_mean_rel": float(rel_exact16.mean()) if keep.any() else None,
+            "exact_bf16_vs_fp32_max_rel": float(rel_exact16.max()) if keep.any() else None,
             "deann_vs_exact_mean_rel": float(rel_deann_vs_exact.mean()) if keep.any() else None,
             "deann_vs_exact_median_rel": float(np.median(rel_deann_vs_exact)) if keep.any() else None,
             "queries_below_1e-16": int((~keep).sum()),
@@ -246,6 +264,9 @@ def main():
         out["cpu_baseline"], out["parity_sample"] = cpu_baseline(
             X, Y, h, args.cpu_sample, mu_h, est_h, nn.cpu().numpy(), sm.cpu().numpy(),
             gy.cpu().numpy(), K_NN, M_SAMPLES, exact_bwd)
+        if not args.no_all_cores:
+            out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(args.workload, h, K_NN,
+                                                                   M_SAMPLES, exact_bwd)
     print(json.dumps(out), flush=True)
 
 
@@ -287,6 +308,47 @@ def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu, K_NN, M
            "deann_max_rel": max(rel_deann) if rel_deann else None,
            "deann_grad_y_max_rel": max(rel_gy) if rel_gy else None}
     return base, par
+
+
+def _oracle_shard(workload, h, k_nn, m_samples, exact_bwd, queries):
+    """Worker of the all-cores oracle run: regenerates the workload (seeded) and
+    times the same per-query oracle work as cpu_baseline on its queries."""
+    import oracle
+    import synth
+    spec, X, Y = synth.workload(workload)
+    t0 = time.perf_counter()
+    for j in queries:
+        oracle.kde_exact(X, Y[j:j + 1], h, oracle.GAUSSIAN)
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, oracle.GAUSSIAN, k_nn, m_samples,
+                                                   0, int(j))
+        oracle.deann_grad(X, Y[j], h, oracle.GAUSSIAN, nn_ref, s_ref, m_samples)
+        if exact_bwd:
+            oracle.kde_grad(X, Y[j], h, oracle.GAUSSIAN)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(workload, h, k_nn, m_samples, exact_bwd, per_worker=2):
+    """The same oracle work on every host core: one spawned process per core
+    (at most 16), each on its own queries; queries/s = all queries over the
+    slowest worker's time (data generation excluded)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import synth
+    spec = synth.WORKLOADS[workload]
+    # each worker holds the data and FP64 temporaries of about 5x its size
+    workers = max(1, min(16, os.cpu_count() or 1, int(150e9 // (5 * spec.n * spec.d * 4))))
+    sub = synth.query_subset(spec.q, workers * per_worker, seed=13)
+    shards = [[int(j) for j in sub[w::workers]] for w in range(workers)]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        times = list(ex.map(_oracle_shard, [workload] * workers, [h] * workers,
+                            [k_nn] * workers, [m_samples] * workers, [exact_bwd] * workers,
+                            shards))
+    return {"value": len(sub) / max(times), "unit": "queries/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"{len(sub)} queries of the same workload in {workers} processes "
+                      f"({per_worker} each), same per-query work as cpu_baseline",
+            "seconds": max(times)}
 
 
 if __name__ == "__main__":

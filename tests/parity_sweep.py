@@ -1,0 +1,105 @@
+"""Large parity sweep (not collected by pytest; run on a GPU host):
+
+    python tests/parity_sweep.py --workload mix100_n1e6_d128 --queries 500
+
+Runs the GPU path once on the whole workload (exact KDE in FP32, DEANN with
+the given scan precision, DEANN adjoint) and checks a fixed random subset of
+queries against the FP64 oracle, computed in spawned processes (one per host
+core, at most 16, fewer when the data is large).  Prints one JSON summary:
+neighbour sets and draws must be bit-identical, DEANN estimates within 1e-12,
+FP32 exact KDE within 1e-5 and the DEANN adjoint within 1e-6 (normwise)."""
+import argparse
+import concurrent.futures as cf
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def _oracle_queries(workload, kern, h, k, m, queries):
+    import numpy as np
+
+    import oracle
+    import synth
+    spec, X, Y = synth.workload(workload)
+    out = []
+    for j in queries:
+        mu = oracle.kde_exact(X, Y[j:j + 1], h, kern)[0]
+        est, nn, s = oracle.deann_estimate(X, Y[j], h, kern, k, m, 0, int(j))
+        _, gy, _ = oracle.deann_grad(X, Y[j], h, kern, nn, s, m)
+        out.append((int(j), float(mu), float(est), np.asarray(nn), np.asarray(s), np.asarray(gy)))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="mix100_n1e6_d128")
+    ap.add_argument("--queries", type=int, default=500)
+    ap.add_argument("--kernel", default="gaussian", choices=["gaussian", "exponential"])
+    ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--m", type=int, default=1000)
+    ap.add_argument("--precision", default="bf16")
+    args = ap.parse_args()
+
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2107_02736_amd as dk
+    import synth
+
+    with open(os.path.join(ROOT, "tests", "golden", "bandwidths.json")) as f:
+        h = float(json.load(f)[args.workload][args.kernel]["h"])
+    kern = oracle.GAUSSIAN if args.kernel == "gaussian" else oracle.EXPONENTIAL
+    spec, X, Y = synth.workload(args.workload)
+    dev = torch.device("cuda:0")
+    Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+    mu = dk.kde_exact(Xd, Yd, h, args.kernel, "fp32").cpu().numpy()
+    est, nn, sm = dk.deann_query(Xd, Yd, h, args.k, args.m, args.kernel, seed=0,
+                                 precision=args.precision)
+    g = torch.ones(Y.shape[0], dtype=torch.float64, device=dev)
+    gy, _ = dk.deann_query_backward(Xd, Yd, h, args.k, args.m, nn, sm, g, args.kernel)
+    est, nn, sm, gy = (t.cpu().numpy() for t in (est, nn, sm, gy))
+
+    sub = [int(j) for j in synth.query_subset(Y.shape[0], args.queries, seed=23)]
+    workers = max(1, min(16, os.cpu_count() or 1, int(150e9 // (5 * X.nbytes))))
+    shards = [sub[w::workers] for w in range(workers)]
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        parts = list(ex.map(_oracle_queries, [args.workload] * workers, [kern] * workers,
+                            [h] * workers, [args.k] * workers, [args.m] * workers, shards))
+    t_oracle = time.perf_counter() - t0
+    nn_bad, s_bad, e_exact, e_est, e_gy, excluded = 0, 0, [], [], [], 0
+    for part in parts:
+        for j, mu_r, est_r, nn_r, s_r, gy_r in part:
+            nn_bad += not np.array_equal(nn[j], nn_r)
+            s_bad += not np.array_equal(sm[j], s_r)
+            if mu_r >= 1e-16:
+                e_exact.append(abs(mu[j] - mu_r) / mu_r)
+            else:
+                excluded += 1
+            if est_r > 0:
+                e_est.append(abs(est[j] - est_r) / est_r)
+            nrm = np.linalg.norm(gy_r)
+            if nrm > 0:
+                e_gy.append(float(np.linalg.norm(gy[j] - gy_r) / nrm))
+    res = {"workload": args.workload, "kernel": args.kernel, "k": args.k, "m": args.m,
+           "scan_precision": args.precision, "queries": len(sub),
+           "nn_mismatches": nn_bad, "sample_mismatches": s_bad,
+           "exact_fp32_max_rel": max(e_exact) if e_exact else None,
+           "exact_excluded_below_1e-16": excluded,
+           "deann_max_rel": max(e_est) if e_est else None,
+           "deann_grad_y_max_rel": max(e_gy) if e_gy else None,
+           "oracle_processes": workers, "oracle_seconds": t_oracle}
+    res["pass"] = bool(nn_bad == 0 and s_bad == 0 and (not e_exact or max(e_exact) <= 1e-5)
+                       and (not e_est or max(e_est) <= 1e-12) and (not e_gy or max(e_gy) <= 1e-6))
+    print(json.dumps(res), flush=True)
+    sys.exit(0 if res["pass"] else 1)
+
+
+if __name__ == "__main__":
+    main()

@@ -73,7 +73,7 @@ def main():
         parts = list(ex.map(_oracle_queries, [args.workload] * workers, [kern] * workers,
                             [h] * workers, [args.k] * workers, [args.m] * workers, shards))
     t_oracle = time.perf_counter() - t0
-    nn_bad, s_bad, e_exact, e_est, e_gy, excluded = 0, 0, [], [], [], 0
+    nn_bad, s_bad, e_exact, e_est, e_gy, excluded, gy_tiny, e_abs = 0, 0, [], [], [], 0, 0, 0.0
     for part in parts:
         for j, mu_r, est_r, nn_r, s_r, gy_r in part:
             nn_bad += not np.array_equal(nn[j], nn_r)
@@ -85,8 +85,11 @@ def main():
             if est_r > 0:
                 e_est.append(abs(est[j] - est_r) / est_r)
             nrm = np.linalg.norm(gy_r)
-            if nrm > 0:
+            if nrm >= 1e-30:   # grad_Y is float32: smaller gradients underflow
                 e_gy.append(float(np.linalg.norm(gy[j] - gy_r) / nrm))
+            else:
+                gy_tiny += 1
+                e_abs = max(e_abs, float(np.linalg.norm(gy[j] - gy_r)))
     res = {"workload": args.workload, "kernel": args.kernel, "k": args.k, "m": args.m,
            "scan_precision": args.precision, "queries": len(sub),
            "nn_mismatches": nn_bad, "sample_mismatches": s_bad,
@@ -94,9 +97,11 @@ def main():
            "exact_excluded_below_1e-16": excluded,
            "deann_max_rel": max(e_est) if e_est else None,
            "deann_grad_y_max_rel": max(e_gy) if e_gy else None,
+           "deann_grad_y_below_1e-30": gy_tiny, "deann_grad_y_max_abs_there": e_abs,
            "oracle_processes": workers, "oracle_seconds": t_oracle}
     res["pass"] = bool(nn_bad == 0 and s_bad == 0 and (not e_exact or max(e_exact) <= 1e-5)
-                       and (not e_est or max(e_est) <= 1e-12) and (not e_gy or max(e_gy) <= 1e-6))
+                       and (not e_est or max(e_est) <= 1e-12) and (not e_gy or max(e_gy) <= 1e-6)
+                       and e_abs <= 1e-30)
     print(json.dumps(res), flush=True)
     sys.exit(0 if res["pass"] else 1)
 

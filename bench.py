@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-all-cores", action="store_true",
                     help="skip the all-cores oracle run (single-core baseline only)")
     ap.add_argument("--cpu-sample", type=int, default=6, help="queries in the oracle sample")
+    ap.add_argument("--sweep-km", action="store_true",
+                    help="only run DEANN (BF16 scan + refinement) over a (k, m) grid and print its "
+                         "error against the exact KDE and its queries/s")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (counter calibration)")
     return ap.parse_args()
@@ -119,6 +122,9 @@ def main():
     spec, X, Y = synth.workload(args.workload)
     h = bandwidth(args.workload, KERNEL)
     K_NN, M_SAMPLES = KM[args.workload]
+    if args.sweep_km:
+        sweep_km(args, X, Y, h)
+        return
     n, d = X.shape
     exact_bwd = d <= 128     # kde_exact_backward supports d <= 128
     q = Y.shape[0]
@@ -308,6 +314,43 @@ def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu, K_NN, M
            "deann_max_rel": max(rel_deann) if rel_deann else None,
            "deann_grad_y_max_rel": max(rel_gy) if rel_gy else None}
     return base, par
+
+
+def sweep_km(args, X, Y, h):
+    """Error against the exact KDE and queries/s of DEANN (BF16 scan +
+    refinement) over a grid of k and m (powers of 2 times 10), one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_2107_02736_amd as dk
+    dev = torch.device("cuda:0")
+    Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+    q = Y.shape[0]
+    mu = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32").cpu().numpy()
+    keep = mu >= 1e-16
+    rows = []
+    for k in (0, 10, 20, 40, 80, 160, 320):
+        for m in (0, 10, 40, 160, 640, 2560):
+            if k == 0 and m == 0:
+                continue
+            dk.deann_query(Xd, Yd, h, k, m, KERNEL, seed=0, precision="bf16")
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            for _ in range(3):
+                est = dk.deann_query(Xd, Yd, h, k, m, KERNEL, seed=0, precision="bf16")[0]
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / 3
+            e = np.abs(est.cpu().numpy()[keep] - mu[keep]) / mu[keep]
+            rows.append({"k": k, "m": m, "queries_per_s": q / (ms * 1e-3), "ms": ms,
+                         "mean_rel_err": float(e.mean()), "median_rel_err": float(np.median(e)),
+                         "p90_rel_err": float(np.percentile(e, 90))})
+            print(f"# k={k} m={m}: {ms:.2f} ms, mean rel err {e.mean():.3e}", file=sys.stderr,
+                  flush=True)
+    print(json.dumps({"sweep": "deann_km", "workload": args.workload, "kernel": KERNEL, "h": h,
+                      "scan": "bf16", "queries_excluded_below_1e-16": int((~keep).sum()),
+                      "rows": rows}), flush=True)
 
 
 def _oracle_shard(workload, h, k_nn, m_samples, exact_bwd, queries):

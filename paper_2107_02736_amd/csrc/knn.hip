@@ -562,15 +562,14 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
-  float yk[4][4], th[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
-      yk[i][r] = p.yknorm[row];
-      th[i][r] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
-    }
+  // per query row: key norm and threshold (-inf: no second pass for that
+  // query), published by the first barrier of the sweep
+  __shared__ float yks[BQ], ths[BQ];
+  if (threadIdx.x < BQ) {
+    const int64_t row = qt * BQ + threadIdx.x;
+    yks[threadIdx.x] = p.yknorm[row];
+    ths[threadIdx.x] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
+  }
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
   constexpr int NK = 2;   // k-groups of the register-resident engine
   StreamState st;
@@ -611,31 +610,39 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
       xk[j] = col < p.n ? xks[nb][wn * 64 + j * 16 + (lane & 15)] : __builtin_inff();
     }
-    float m = __builtin_inff();
+    // one bit per query row (i, r) of this lane that has a hit in this tile
+    uint32_t hit = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r) {
+        const int rl = wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const float yk = yks[rl], th = ths[rl];
+        float m = __builtin_fmaf(-2.f, acc[i][0][r], yk + xk[0]) - th;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          m = fminf(m, __builtin_fmaf(-2.f, acc[i][j][r], yk[i][r] + xk[j]) - th[i][r]);
-    if (m <= 0.f) {   // rare: append the hits of this lane
+        for (int j = 1; j < 4; ++j)
+          m = fminf(m, __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]) - th);
+        hit |= m <= 0.f ? 1u << (i * 4 + r) : 0u;
+      }
+    if (hit) {   // rare: append the hits, visiting only the rows that have one
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-        if (col >= p.n) continue;
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int r = 0; r < 4; ++r) {
+          if (!(hit & (1u << (i * 4 + r)))) continue;
+          const int rl = wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+          const int64_t row = qt * BQ + rl;
+          const float yk = yks[rl], th = ths[rl];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk[i][r] + xk[j]);
-            if (key <= th[i][r]) {
-              const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+          for (int j = 0; j < 4; ++j) {
+            const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
+            const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]);
+            if (col < p.n && key <= th) {
               const int slot = atomicAdd(&b.cand2_cnt[row], 1);
               if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = (uint64_t)col;
             }
           }
-      }
+        }
     }
   }
 }

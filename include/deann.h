@@ -100,6 +100,27 @@ int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
                 void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * DEANN with permuted random sampling (DEANNP; App. G, Algorithm 2): as
+ * deann_query, but the sample of query i is the block of the data's permuted
+ * order that starts at the running index l_i = (start + i m) mod n, with the
+ * query's neighbours skipped: m distinct rows of X2, without replacement.
+ * The permutation is keyed by `seed`: a balanced 4-round Feistel network on
+ * b-bit words (b the smallest even number >= 2 with 2^b >= n) whose round
+ * function is word 0 of Philox4x64-10 with key (seed, 1) and counter
+ * (half, round, 0, 0), restricted to [n] by cycle walking.  Passing start +
+ * i0 m for a batch that begins at query i0 reproduces the same samples.
+ *   sample_idx  [q, m] int32 rows in block order (or NULL); deann_query_backward
+ *               accepts them unchanged.
+ * Requirements: as deann_query, plus m <= n - k when k < n.
+ * ------------------------------------------------------------------------- */
+size_t deann_query_permuted_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
+                                      int precision);
+int deann_query_permuted(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                         double h, int kernel, int64_t k, int64_t m, uint64_t seed,
+                         uint64_t start, int precision, double* out, int32_t* nn_idx,
+                         int32_t* sample_idx, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Adjoint of deann_query with the index sets held fixed (the selection is
  * piecewise constant in y and h, so this is the derivative almost everywhere):
  *   grad_Y[j] = grad_out[j] * d out[j] / d y_j          [q, d] float32, or NULL

@@ -25,6 +25,12 @@ Parity status of each function (what pins it in tests/test_oracle_*.py):
   deann_estimate pinned: k=n gives kde_exact, unbiasedness over many seeds,
       variance formula of random sampling with repetition, Bernoulli worst
       case of App. D.
+  permutation, permutation_inverse pinned: bijection of [n] and mutual
+      inverses (exhaustive on small n), uniformity of pi over seeds.
+  permuted_sample_indices / deann_estimate_permuted pinned: m distinct rows
+      outside NN; consecutive running indices partition the permuted order;
+      m = n - k gives exactly X2, so the estimate equals kde_exact;
+      unbiasedness over seeds.
   kde_grad / deann_grad pinned: central finite differences, n=1 closed form.
   mean_shift pinned: n=1 lands on the point in one step; density never
       decreases along exact Gaussian mean-shift steps.
@@ -225,6 +231,103 @@ def deann_estimate(X: np.ndarray, y: np.ndarray, h: float, kernel: int, k: int, 
     s_idx = sample_indices(n, nn, m, seed, stream, word2)
     z1 = math.fsum(kernel_values(sq_dists(X[nn], y), h, kernel)) if k else 0.0
     if m > 0 and n - k > 0:
+        z2 = math.fsum(kernel_values(sq_dists(X[s_idx], y), h, kernel))
+        est = (z1 + (n - k) / m * z2) / n
+    else:
+        est = z1 / n
+    return est, nn, s_idx
+
+
+# --------------------------------------------------------------------------
+# Permuted random sampling (App. G, Algorithm 2) for DEANN
+# --------------------------------------------------------------------------
+# The permutation pi of Algorithm 2 is a keyed pseudo-random permutation of
+# [n]: a balanced 4-round Feistel network on b-bit words (b even, 2^b >= n)
+# whose round function is word 0 of Philox4x64-10 with key (seed, 1) and
+# counter (half, round, 0, 0), restricted to [n] by cycle walking (Black and
+# Rogaway, CT-RSA 2002).  Query i reads the permuted rows starting at the
+# running index l_i = (start + i m) mod n, as Algorithm 2 advances l by m per
+# query; the neighbours of the query are skipped, so the sample is m distinct
+# rows of X2 (m <= n - k).
+
+PERM_ROUNDS = 4
+
+
+def perm_bits(n: int) -> int:
+    """Smallest even b >= 2 with 2^b >= n."""
+    b = max(2, (n - 1).bit_length())
+    return b + (b & 1)
+
+
+def feistel(x: int, b: int, seed: int, inverse: bool = False) -> int:
+    """One pass of the balanced Feistel network on [0, 2^b) (or its inverse)."""
+    half = b // 2
+    mask = (1 << half) - 1
+    left, right = x >> half, x & mask
+    if not inverse:
+        for rnd in range(PERM_ROUNDS):
+            f = philox4x64_10((seed, 1), (right, rnd, 0, 0))[0] & mask
+            left, right = right, left ^ f
+    else:
+        for rnd in reversed(range(PERM_ROUNDS)):
+            f = philox4x64_10((seed, 1), (left, rnd, 0, 0))[0] & mask
+            left, right = right ^ f, left
+    return (left << half) | right
+
+
+def permutation(n: int, seed: int, x: int) -> int:
+    """pi(x) for x in [n]: apply the network until the value falls in [n]."""
+    b = perm_bits(n)
+    y = feistel(x, b, seed)
+    while y >= n:
+        y = feistel(y, b, seed)
+    return y
+
+
+def permutation_inverse(n: int, seed: int, y: int) -> int:
+    """pi^-1(y): the inverse network, walked the same way."""
+    b = perm_bits(n)
+    x = feistel(y, b, seed, inverse=True)
+    while x >= n:
+        x = feistel(x, b, seed, inverse=True)
+    return x
+
+
+def permuted_sample_indices(n: int, nn_sorted: np.ndarray, m: int, seed: int,
+                            start: int) -> np.ndarray:
+    """The m rows at permuted positions start, start + 1, ... (cyclic) that
+    are not neighbours, in that order (Algorithm 2 with X1 skipped).
+
+    With the neighbours' positions relative to start sorted, r_0 < ... <
+    r_{k-1}, draw j takes relative position j + #{t : r_t - t <= j}, the j-th
+    position not held by a neighbour.
+    """
+    k = len(nn_sorted)
+    if m <= 0:
+        return np.empty(0, dtype=np.int64)
+    if m > n - k:
+        raise ValueError("permuted sampling needs m <= n - k")
+    rel = sorted((permutation_inverse(n, seed, int(e)) - start) % n for e in nn_sorted)
+    out = np.empty(m, dtype=np.int64)
+    for j in range(m):
+        u = rank_to_index(rel, j)
+        out[j] = permutation(n, seed, (start + u) % n)
+    return out
+
+
+def deann_estimate_permuted(X: np.ndarray, y: np.ndarray, h: float, kernel: int, k: int,
+                            m: int, seed: int, start: int, nn: np.ndarray | None = None):
+    """DEANN with permuted random sampling for one query whose running index is
+    ``start``.  Returns (estimate, nn_sorted, sample_idx); the estimate has the
+    same form as deann_estimate, (Z1 + ((n-k)/m) Z2) / n."""
+    n = X.shape[0]
+    if nn is None:
+        nn = knn(X, y, k)
+    nn = np.sort(np.asarray(nn, dtype=np.int64))
+    k = len(nn)
+    s_idx = permuted_sample_indices(n, nn, m, seed, start % n)
+    z1 = math.fsum(kernel_values(sq_dists(X[nn], y), h, kernel)) if k else 0.0
+    if m > 0:
         z2 = math.fsum(kernel_values(sq_dists(X[s_idx], y), h, kernel))
         est = (z1 + (n - k) / m * z2) / n
     else:

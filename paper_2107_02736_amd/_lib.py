@@ -18,6 +18,7 @@ FP32, BF16, FP16 = 0, 1, 2
 EXPORTS = (
     "kde_exact_workspace", "kde_exact",
     "deann_query_workspace", "deann_query",
+    "deann_query_permuted_workspace", "deann_query_permuted",
     "deann_query_backward_workspace", "deann_query_backward",
     "kde_exact_backward_workspace", "kde_exact_backward",
     "deann_last_error",
@@ -58,6 +59,11 @@ def load(path: str = LIB_PATH):
     lib.deann_query.restype = _int
     lib.deann_query.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64, _u64, _u64,
                                 _u64, _int, _vp, _vp, _vp, _vp, _sz, _vp]
+    lib.deann_query_permuted_workspace.restype = _sz
+    lib.deann_query_permuted_workspace.argtypes = [_i64, _i64, _i64, _i64, _i64, _int]
+    lib.deann_query_permuted.restype = _int
+    lib.deann_query_permuted.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64, _u64,
+                                         _u64, _int, _vp, _vp, _vp, _vp, _sz, _vp]
     lib.deann_query_backward_workspace.restype = _sz
     lib.deann_query_backward_workspace.argtypes = [_i64, _i64, _i64, _i64, _i64]
     lib.deann_query_backward.restype = _int

@@ -88,6 +88,28 @@ def deann_query(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int, kern
     return out, nn, sm
 
 
+def deann_query_permuted(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int,
+                         kernel="gaussian", seed: int = 0, start: int = 0, precision="fp32",
+                         return_indices: bool = True):
+    """DEANN with permuted random sampling (query i reads the permuted rows from
+    running index start + i m): (out float64 [q], nn_idx [q,k], sample_idx [q,m])."""
+    _check_xy(X, Y)
+    lib = _lib.load()
+    n, d = X.shape
+    q = Y.shape[0]
+    p = precision_id(precision)
+    dev = X.device
+    out = torch.empty(q, dtype=torch.float64, device=dev)
+    nn = torch.empty((q, k), dtype=torch.int32, device=dev) if return_indices else None
+    sm = torch.empty((q, m), dtype=torch.int32, device=dev) if return_indices else None
+    ws = _workspace(lib.deann_query_permuted_workspace(n, q, d, k, m, p), dev)
+    _lib.check(lib.deann_query_permuted(X.data_ptr(), n, Y.data_ptr(), q, d, float(h),
+                                        kernel_id(kernel), int(k), int(m), int(seed), int(start),
+                                        p, out.data_ptr(), _ptr(nn), _ptr(sm), ws.data_ptr(),
+                                        ws.numel(), _stream(dev)))
+    return out, nn, sm
+
+
 def deann_query_backward(X, Y, h, k, m, nn_idx, sample_idx, grad_out, kernel="gaussian",
                          need_grad_y: bool = True, need_grad_h: bool = True):
     """(grad_Y float32 [q,d] or None, grad_h float64 [1] or None) of deann_query."""

@@ -364,10 +364,13 @@ size_t deann_query_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t
   return (size_t)plan_deann(nullptr, n, q, d, k, precision).bytes;
 }
 
-int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                int kernel, int64_t k, int64_t m, uint64_t seed, uint64_t query_offset,
-                uint64_t word2, int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
-                void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+static int deann_query_impl(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                            double h, int kernel, int64_t k, int64_t m, uint64_t seed,
+                            uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
+                            int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
+                            void* ws, size_t ws_bytes, void* stream) {
   int st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_prec(precision)) return fail(DEANN_EINVAL, "unknown precision %d", precision);
@@ -377,6 +380,8 @@ int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
     return fail(DEANN_EUNSUPPORTED, "k = %lld: supported are k <= %lld and k = n", (long long)k,
                 (long long)kMaxK);
   if (d > 4096) return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported by deann_query");
+  if (permuted && k < n && m > n - k)
+    return fail(DEANN_EINVAL, "permuted sampling needs m <= n - k (got m = %lld)", (long long)m);
   if (q == 0) return DEANN_OK;
   if (!out) return fail(DEANN_EINVAL, "out is NULL");
   const int64_t need = plan_deann(nullptr, n, q, d, k, precision).bytes;
@@ -397,10 +402,33 @@ int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
     e = launch_knn(precision, tp, tc, P.kb, X, Y, d, k, h, kernel, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "knn");
   }
-  e = launch_sample(X, Y, n, q, d, h, kernel, k, m, seed, query_offset, word2, P.kb.nn_work,
-                    P.kb.z1, out, sample_idx, s);
+  e = launch_sample(X, Y, n, q, d, h, kernel, k, m, seed, query_offset, word2, permuted, start,
+                    P.kb.nn_work, P.kb.z1, out, sample_idx, s);
   if (e != hipSuccess) return hip_fail(e, "sample");
   return DEANN_OK;
+}
+
+extern "C" {
+
+int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                int kernel, int64_t k, int64_t m, uint64_t seed, uint64_t query_offset,
+                uint64_t word2, int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
+                void* ws, size_t ws_bytes, void* stream) {
+  return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, query_offset, word2, 0, 0,
+                          precision, out, nn_idx, sample_idx, ws, ws_bytes, stream);
+}
+
+size_t deann_query_permuted_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
+                                      int precision) {
+  return deann_query_workspace(n, q, d, k, m, precision);
+}
+
+int deann_query_permuted(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                         double h, int kernel, int64_t k, int64_t m, uint64_t seed,
+                         uint64_t start, int precision, double* out, int32_t* nn_idx,
+                         int32_t* sample_idx, void* ws, size_t ws_bytes, void* stream) {
+  return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, 0, 0, 1, start, precision, out,
+                          nn_idx, sample_idx, ws, ws_bytes, stream);
 }
 
 size_t deann_query_backward_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m) {

@@ -69,8 +69,9 @@ hipError_t launch_knn_all(const float* X, const float* Y, int64_t n, int64_t q, 
 // ---- sampler, gather and combine --------------------------------------------
 hipError_t launch_sample(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                          double h, int kern, int64_t k, int64_t m, uint64_t seed,
-                         uint64_t query_offset, uint64_t word2, const int32_t* nn_sorted,
-                         const double* z1, double* out, int32_t* sample_idx, hipStream_t s);
+                         uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
+                         const int32_t* nn_sorted, const double* z1, double* out,
+                         int32_t* sample_idx, hipStream_t s);
 
 // ---- adjoints ----------------------------------------------------------------
 hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,

@@ -36,6 +36,72 @@ __device__ __forceinline__ Philox4x64 philox4x64_10(uint64_t k0, uint64_t k1, ui
   return o;
 }
 
+__host__ __device__ inline int next_pow2_i(int64_t v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Keyed pseudo-random permutation of [n] for permuted random sampling
+// (App. G, Algorithm 2): a balanced 4-round Feistel network on b-bit words
+// (b even, 2^b >= n) with round function word 0 of Philox4x64-10, key
+// (seed, 1), counter (half, round, 0, 0); values outside [n] are walked
+// through the network again until they fall inside (cycle walking, Black and
+// Rogaway, CT-RSA 2002).
+constexpr int PERM_ROUNDS = 4;
+
+__host__ __device__ inline int perm_bits(int64_t n) {
+  int b = 2;
+  while (b < 62 && (int64_t(1) << b) < n) ++b;
+  return b + (b & 1);
+}
+
+__device__ __forceinline__ uint64_t feistel(uint64_t x, int b, uint64_t seed, bool inverse) {
+  const int half = b >> 1;
+  const uint64_t mask = (uint64_t(1) << half) - 1;
+  uint64_t left = x >> half, right = x & mask;
+  if (!inverse) {
+#pragma unroll
+    for (int r = 0; r < PERM_ROUNDS; ++r) {
+      const uint64_t f = philox4x64_10(seed, 1, right, (uint64_t)r, 0, 0).v[0] & mask;
+      const uint64_t nl = right;
+      right = left ^ f;
+      left = nl;
+    }
+  } else {
+#pragma unroll
+    for (int r = PERM_ROUNDS - 1; r >= 0; --r) {
+      const uint64_t f = philox4x64_10(seed, 1, left, (uint64_t)r, 0, 0).v[0] & mask;
+      const uint64_t nr = left;
+      left = right ^ f;
+      right = nr;
+    }
+  }
+  return (left << half) | right;
+}
+
+__device__ __forceinline__ int64_t permute(int64_t x, int64_t n, int b, uint64_t seed, bool inverse) {
+  uint64_t y = feistel((uint64_t)x, b, seed, inverse);
+  while (y >= (uint64_t)n) y = feistel(y, b, seed, inverse);   // ends: x lies on y's cycle
+  return (int64_t)y;
+}
+
+// Workgroup bitonic sort of N int32 values in LDS (N a power of two).
+__device__ void block_sort_i32(int32_t* a, int N) {
+  for (int kk = 2; kk <= N; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int32_t x = a[i], y = a[ixj];
+          if ((x > y) == ((i & kk) == 0)) { a[i] = y; a[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 constexpr int DRAW_CHUNK = 1024;   // draws handled per pass through LDS
 
 __device__ __forceinline__ double kval(double d2, double h, int kern) {
@@ -46,14 +112,15 @@ __device__ __forceinline__ double kval(double d2, double h, int kern) {
 __global__ void __launch_bounds__(WG)
 deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
                     int64_t d, double h, int kern, int64_t k, int64_t m, uint64_t seed,
-                    uint64_t query_offset, uint64_t word2, const int32_t* __restrict__ nn_sorted,
-                    const double* __restrict__ z1, double* __restrict__ out,
-                    int32_t* __restrict__ sample_idx) {
+                    uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
+                    const int32_t* __restrict__ nn_sorted, const double* __restrict__ z1,
+                    double* __restrict__ out, int32_t* __restrict__ sample_idx) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int kp = permuted ? next_pow2_i(k) : (int)k;   // sorted in place when permuted
   double* kv = reinterpret_cast<double*>(smem);                    // DRAW_CHUNK
   int32_t* sidx = reinterpret_cast<int32_t*>(kv + DRAW_CHUNK);     // DRAW_CHUNK
-  int32_t* gaps = sidx + DRAW_CHUNK;                               // k
-  float* ys = reinterpret_cast<float*>(gaps + k);                  // d
+  int32_t* gaps = sidx + DRAW_CHUNK;                               // kp
+  float* ys = reinterpret_cast<float*>(gaps + kp);                 // d
   const int64_t qi = blockIdx.x;
   const uint64_t size2 = (uint64_t)(n - k);
   const double zz1 = k > 0 ? z1[qi] : 0.0;
@@ -63,7 +130,22 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
     if (threadIdx.x == 0) out[qi] = zz1 / (double)n;
     return;
   }
-  for (int64_t t = threadIdx.x; t < k; t += WG) gaps[t] = nn_sorted[qi * k + t] - (int32_t)t;
+  // gaps[t] = e_t - t over the sorted excluded positions e_t: the neighbours'
+  // indices (draws with repetition over X2), or, for permuted sampling, the
+  // neighbours' positions in the permuted order relative to this query's
+  // running index l = (start + i m) mod n
+  const int bits = perm_bits(n);
+  const int64_t run = permuted ? (int64_t)((start % (uint64_t)n + ((uint64_t)qi * (uint64_t)m) % (uint64_t)n) % (uint64_t)n) : 0;
+  if (permuted) {
+    for (int t = threadIdx.x; t < kp; t += WG)
+      gaps[t] = t < k ? (int32_t)((permute(nn_sorted[qi * k + t], n, bits, seed, true) - run + n) % n)
+                      : INT32_MAX;
+    __syncthreads();
+    block_sort_i32(gaps, kp);
+    for (int t = threadIdx.x; t < k; t += WG) gaps[t] -= t;
+  } else {
+    for (int64_t t = threadIdx.x; t < k; t += WG) gaps[t] = nn_sorted[qi * k + t] - (int32_t)t;
+  }
   for (int64_t t = threadIdx.x; t < d; t += WG) ys[t] = Y[qi * d + t];
   __syncthreads();
   const uint64_t stream = query_offset + (uint64_t)qi;
@@ -72,22 +154,26 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
   for (int64_t j0 = 0; j0 < m; j0 += DRAW_CHUNK) {
     const int cnt = (int)(m - j0 < DRAW_CHUNK ? m - j0 : DRAW_CHUNK);
-    // draws: each thread makes one Philox block = 4 consecutive draws
+    // draws: each thread makes one Philox block = 4 consecutive draws (with
+    // repetition), or 4 consecutive positions of the permuted block
     for (int b = threadIdx.x; b * 4 < cnt; b += WG) {
       const int64_t jb = (j0 >> 2) + b;     // j0 is a multiple of 4
-      const Philox4x64 blk = philox4x64_10(seed, 0, (uint64_t)jb, stream, word2, 0);
+      Philox4x64 blk;
+      if (!permuted) blk = philox4x64_10(seed, 0, (uint64_t)jb, stream, word2, 0);
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         const int jj = b * 4 + w;
         if (jj < cnt) {
-          const uint64_t r = __umul64hi(blk.v[w], size2);
+          const uint64_t r = permuted ? (uint64_t)(j0 + jj) : __umul64hi(blk.v[w], size2);
           // #{t : gaps[t] <= r}: gaps is non-decreasing
           int lo = 0, hi = (int)k;
           while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if ((uint64_t)(int64_t)gaps[mid] <= r) lo = mid + 1; else hi = mid;
           }
-          const int32_t idx = (int32_t)(r + (uint64_t)lo);
+          const int64_t u = (int64_t)(r + (uint64_t)lo);
+          const int32_t idx = permuted ? (int32_t)permute((run + u) % n, n, bits, seed, false)
+                                       : (int32_t)u;
           sidx[jj] = idx;
           if (sample_idx) sample_idx[qi * m + j0 + jj] = idx;
         }
@@ -136,13 +222,15 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
 
 hipError_t launch_sample(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                          double h, int kern, int64_t k, int64_t m, uint64_t seed,
-                         uint64_t query_offset, uint64_t word2, const int32_t* nn_sorted,
-                         const double* z1, double* out, int32_t* sample_idx, hipStream_t s) {
+                         uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
+                         const int32_t* nn_sorted, const double* z1, double* out,
+                         int32_t* sample_idx, hipStream_t s) {
   if (q == 0) return hipSuccess;
-  const size_t sm = DRAW_CHUNK * (8 + 4) + k * 4 + d * 4 + 16;
-  deann_sample_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(X, Y, n, d, h, kern, k, m, seed,
-                                                              query_offset, word2, nn_sorted, z1,
-                                                              out, sample_idx);
+  const int64_t kp = permuted ? next_pow2_i(k) : k;
+  const size_t sm = DRAW_CHUNK * (8 + 4) + kp * 4 + d * 4 + 16;
+  deann_sample_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(
+      X, Y, n, d, h, kern, k, m, seed, query_offset, word2, permuted, start, nn_sorted, z1, out,
+      sample_idx);
   return hipGetLastError();
 }
 

@@ -191,6 +191,18 @@ def main():
     torch.cuda.synchronize()
     ms_deann32 = a.elapsed_time(b) / reps
 
+    # DEANN with permuted random sampling (App. G), BF16 scan (not part of the step)
+    estp = dk.deann_query_permuted(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, start=0,
+                                   precision="bf16")[0]
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        estp = dk.deann_query_permuted(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, start=0,
+                                       precision="bf16")[0]
+    b.record()
+    torch.cuda.synchronize()
+    ms_deannp = a.elapsed_time(b) / reps
+
     # exact KDE with BF16 operands (not part of the step): speed and its error
     # against the FP32 exact path (itself within about 1e-6 of the FP64 oracle)
     mu16 = dk.kde_exact(Xd, Yd, h, KERNEL, "bf16")
@@ -210,6 +222,8 @@ def main():
     rel_bf16_vs_fp32 = float(np.max(np.abs(est_h - est32_h)[keep] / est32_h[keep])) if keep.any() else 0.0
     rel_deann_vs_exact = np.abs(est_h[keep] - mu_h[keep]) / mu_h[keep]
     rel_exact16 = np.abs(mu16_h[keep] - mu_h[keep]) / mu_h[keep]
+    estp_h = estp.cpu().numpy()
+    rel_deannp = np.abs(estp_h[keep] - mu_h[keep]) / mu_h[keep]
 
     flops_exact = 2.0 * n * d * q
     tile_avg_ms = float(np.mean(tile_ms))
@@ -249,6 +263,7 @@ def main():
             "step": q / (ms_step * 1e-3),
             "deann_bf16_refine": q / (comp_ms["deann_bf16"] * 1e-3),
             "deann_fp32": q / (ms_deann32 * 1e-3),
+            "deann_permuted_bf16_refine": q / (ms_deannp * 1e-3),
             "kde_exact_fp32": q / (comp_ms["kde_exact_fp32"] * 1e-3),
             "kde_exact_bf16": q / (ms_exact16 * 1e-3),
             "deann_backward": q / (comp_ms["deann_backward"] * 1e-3),
@@ -262,6 +277,7 @@ def main():
             "exact_bf16_vs_fp32_max_rel": float(rel_exact16.max()) if keep.any() else None,
             "deann_vs_exact_mean_rel": float(rel_deann_vs_exact.mean()) if keep.any() else None,
             "deann_vs_exact_median_rel": float(np.median(rel_deann_vs_exact)) if keep.any() else None,
+            "deann_permuted_vs_exact_mean_rel": float(rel_deannp.mean()) if keep.any() else None,
             "queries_below_1e-16": int((~keep).sum()),
         },
     }

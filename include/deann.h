@@ -72,7 +72,7 @@ int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, d
  *   X1  = the k nearest rows of X to y (exact; ties to the lower index),
  *   Z1  = sum over X1 of K_h,  S = m draws with repetition from X2 = X \ X1,
  *   Z2  = sum over S of K_h,   out = (Z1 + ((n-k)/m) Z2) / n,
- * which is (k/n) Z1/k + ((n-k)/n) Z2/m of Algorithm 1 line 6, valid also for
+ * which is the (k/n) Z1/k + ((n-k)/n) Z2/m of Algorithm 1, valid also for
  * k = 0 (random sampling) and m = 0 (far points dropped, biased).  With k = n
  * the result is the exact KDE and no draw is made.
  *

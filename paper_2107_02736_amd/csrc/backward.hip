@@ -4,7 +4,7 @@
 //   Gaussian:    dK/dy = K (x - y) / h^2,        dK/dh = K r^2 / h^3
 //   exponential: dK/dy = K (x - y) / (h r),      dK/dh = K r / h^2   (dK/dy = 0 at r = 0)
 //
-// DEANN estimate (Algorithm 1, line 6): the index sets are held fixed (the
+// DEANN estimate (Algorithm 1): the index sets are held fixed (the
 // selection is piecewise constant in y and h), each neighbour weighs 1 and each
 // draw (n-k)/m, all over n.  The rows are gathered again and the distances
 // recomputed in FP64; nothing from the forward pass is stored but the indices.

@@ -144,42 +144,6 @@ __device__ __forceinline__ void mfma_chunk(f32x4 (&acc)[4][4], const char* qa, c
   }
 }
 
-// Full d-loop for one (query tile, data tile) pair with LDS double buffering.
-// lds must hold 4 * TILE_LDS bytes: [q0 | x0 | q1 | x1].
-template <typename T>
-__device__ __forceinline__ void tile_dot(f32x4 (&acc)[4][4], const char* __restrict__ yq,
-                                         const char* __restrict__ xt, int64_t ld_bytes,
-                                         int nchunks, char* lds, int wq, int wn, int lane) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  ChunkRegs rq, rx;
-  load_chunk(rq, yq, ld_bytes, 0);
-  load_chunk(rx, xt, ld_bytes, 0);
-  __syncthreads();   // previous users of the LDS buffers are done
-  store_chunk(rq, lds);
-  store_chunk(rx, lds + TILE_LDS);
-  __syncthreads();
-  for (int c = 0; c < nchunks; ++c) {
-    const int cur = c & 1;
-    char* qa = lds + cur * 2 * TILE_LDS;
-    char* xa = qa + TILE_LDS;
-    const bool more = c + 1 < nchunks;
-    if (more) {
-      load_chunk(rq, yq, ld_bytes, (int64_t)(c + 1) * CHUNK_BYTES);
-      load_chunk(rx, xt, ld_bytes, (int64_t)(c + 1) * CHUNK_BYTES);
-    }
-    mfma_chunk<T>(acc, qa, xa, wq, wn, lane);
-    if (more) {
-      char* qn = lds + (cur ^ 1) * 2 * TILE_LDS;
-      store_chunk(rq, qn);
-      store_chunk(rx, qn + TILE_LDS);
-    }
-    __syncthreads();
-  }
-}
-
 // Streamed sweep over data tiles [t0, t1) against one query tile.  The chunk
 // sequence is continuous across tiles: the registers always hold the next
 // chunk (of this tile or of the next one) while the current one is multiplied,
@@ -303,11 +267,10 @@ __device__ __forceinline__ void ql_tile(f32x4 (&acc)[4][4], QlState& st,
   }
 }
 
-// Query-stationary sweep for 16-bit operands with at most 256 bytes per row
-// (d <= 128): each wave keeps its 64 query rows' A fragments in registers for
-// the whole kernel, and only the data tiles stream through LDS, a whole tile
-// (all NKG 64-byte k-groups of 128 rows) per barrier.  Halves the LDS and L2
-// traffic of tile_stream and removes the query-tile reloads.
+// Query fragments resident in registers, for 16-bit rows of 128 bytes
+// (d <= 64): each wave keeps its 64 query rows' A fragments for the whole
+// kernel and only the data tiles stream through LDS, a whole tile (NKG 64-byte
+// k-groups of 128 rows) per barrier, prefetched a tile ahead in registers.
 template <int NKG>
 struct XStream {
   static constexpr int ROWB = NKG * KG_BYTES;          // bytes of a row

@@ -1,19 +1,22 @@
-// Exact k nearest neighbours: the ANN black box of Algorithm 1 (line 2)
-// replaced by an exact brute-force search whose result equals the sequence of
+// Exact k nearest neighbours: the ANN black box of Algorithm 1 replaced by
+// an exact brute-force search whose result equals the sequence of
 // points sorted by distance (Sec. 2) with ties broken towards the lower index.
 //
-// 1. scan     : the MFMA distance tile of the prepared (possibly BF16/FP16)
-//               operands gives a key per pair that provably never exceeds
-//               ||x~ - y~||^2.  Each (split, query) keeps the K1 smallest keys
-//               in a global list (threshold in LDS, append on accept,
-//               workgroup bitonic compaction when the list runs full).
+// 1. scan     : the MFMA distance tile of the prepared operands gives a key per
+//               pair that provably never exceeds ||x~ - y~||^2.
+//               FP32: each (split, query) keeps the K1 smallest keys in a
+//               global list (threshold in LDS, append on accept, wave-level
+//               register sorts compact the list when it runs full).
+//               BF16/FP16: each (split, query, lane column) keeps only its
+//               smallest key ("cell" candidates), with no list traffic.
 // 2. refine   : per query, the K1 smallest keys over all splits are re-evaluated
 //               exactly (FP64 direct differences, double-double for near ties),
-//               sorted by (d^2, index); the first k are the candidates.  A
+//               sorted by (d^2, index); the first k are the candidates.  FP32: a
 //               certificate checks that every excluded point is provably farther
 //               than the k-th candidate: sqrt(T) - E - e_y > d_k, with T the K1-th
-//               key and E, e_y bounds of the rounding of the rows.
-// 3. collect  : queries failing the certificate rescan and gather every point
+//               key and E, e_y bounds of the rounding of the rows.  16-bit: the
+//               candidates only bound d_k and the second pass always runs.
+// 3. collect  : queries without a certificate rescan and gather every point
 //               whose key admits a distance <= d_k; refine2 then sorts that set.
 // 4. exhaustive: a query whose second-pass set overflowed is scanned with exact
 //               FP64 distances by one workgroup (rare fallback).

@@ -1,6 +1,8 @@
-// Random-sampling part of DEANN (Algorithm 1, lines 3-6): m uniform draws
-// with repetition from X2 = X minus the k neighbours, the exact kernel sum over
-// the drawn rows, and the combined estimate (Z1 + ((n-k)/m) Z2) / n.
+// Random-sampling part of DEANN (Algorithm 1): m uniform draws with
+// repetition from X2 = X minus the k neighbours, the exact kernel sum over the
+// drawn rows, and the combined estimate (Z1 + ((n-k)/m) Z2) / n.  The same
+// kernel also takes the permuted blocks of App. G (Algorithm 2) instead of
+// the draws; see `permute` below.
 //
 // Draw j of query i uses word (j mod 4) of Philox4x64-10 (Salmon et al., SC'11)
 // with key (seed, 0) and counter (j div 4, query_offset + i, word2, 0).  The

@@ -345,3 +345,57 @@ def test_mean_shift_matches_oracle(dev):
         assert np.allclose(ye[j], ref_e, rtol=1e-4, atol=1e-4)
         ref_d = oracle.mean_shift_deann(X, Y[j], h, 20, 100, 1, j, 5)
         assert np.allclose(yd[j], ref_d, rtol=1e-4, atol=1e-4)
+
+
+# --------------------------------------------------------------------------
+# largest supported shapes and empty batches
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_maximum_k_and_d(dev, prec):
+    # k = 496 (largest list size), d = 4096 (largest row for the query path),
+    # the DEANN adjoint at its largest row (d = 2048), exact KDE at d = 4096
+    import paper_2107_02736_amd as dk
+    X, Y = _small(3000, 12, 4096, seed=41)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h, k, m = 40.0, 496, 64
+    out, nn, sm = (t.cpu().numpy() for t in dk.deann_query(Xd, Yd, h, k, m, "gaussian", seed=9,
+                                                            precision=prec))
+    for j in range(0, 12, 3):
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, GAUSSIAN, k, m, 9, j)
+        assert np.array_equal(nn[j], nn_ref), j
+        assert np.array_equal(sm[j], s_ref), j
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
+    mu = dk.kde_exact(Xd, Yd, h, "gaussian", "fp32").cpu().numpy()
+    ref = oracle.kde_exact(X, Y, h, GAUSSIAN)
+    err, _ = rel_err(mu, ref)
+    Xc, Yc = X - X.mean(axis=0), Y - X.mean(axis=0)   # the GEMM-form bound of the edge tests
+    bound = 4 * 2.0 ** -24 * np.sqrt(4096) * ((Xc ** 2).sum(1).max() + (Yc ** 2).sum(1)) / (2 * h * h)
+    assert np.all(err <= np.maximum(1e-5, bound[ref >= 1e-16]))
+    X2, Y2 = np.ascontiguousarray(X[:, :2048]), np.ascontiguousarray(Y[:, :2048])
+    X2d, Y2d = to_dev(X2, dev), to_dev(Y2, dev)
+    h2 = 28.0
+    _, nn2, sm2 = dk.deann_query(X2d, Y2d, h2, 32, 100, "gaussian", seed=1, precision=prec)
+    g = np.linspace(1.0, 2.0, 12)
+    gy, _ = dk.deann_query_backward(X2d, Y2d, h2, 32, 100, nn2, sm2, to_dev(g, dev), "gaussian")
+    gy, nn2, sm2 = gy.cpu().numpy(), nn2.cpu().numpy(), sm2.cpu().numpy()
+    for j in range(0, 12, 4):
+        _, gy_ref, _ = oracle.deann_grad(X2, Y2[j], h2, GAUSSIAN, nn2[j], sm2[j], 100)
+        assert np.linalg.norm(gy[j] - g[j] * gy_ref) <= 1e-6 * np.linalg.norm(g[j] * gy_ref)
+
+
+def test_empty_query_batches(dev):
+    import torch
+    import paper_2107_02736_amd as dk
+    X, _ = _small(500, 1, 8, seed=2)
+    Xd = to_dev(X, dev)
+    Y0 = torch.empty((0, 8), dtype=torch.float32, device=dev)
+    assert dk.kde_exact(Xd, Y0, 1.0, "gaussian").numel() == 0
+    out, nn, sm = dk.deann_query(Xd, Y0, 1.0, 5, 7, precision="bf16")
+    assert out.numel() == 0 and nn.shape == (0, 5) and sm.shape == (0, 7)
+    out, nn, sm = dk.deann_query_permuted(Xd, Y0, 1.0, 5, 7)
+    assert out.numel() == 0
+    gy, _ = dk.deann_query_backward(Xd, Y0, 1.0, 5, 7, nn, sm,
+                                    torch.empty(0, dtype=torch.float64, device=dev), "gaussian",
+                                    True, False)
+    assert gy.shape == (0, 8)

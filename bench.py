@@ -1,15 +1,18 @@
 """Benchmark of DEANN's query path on one MI355X.
 
 One step = the whole hot path over one batch of queries:
-  exact KDE (FP32 MFMA tiles, FP64 reduction)             kde_exact
+  exact KDE with its gradient in one pass over     kde_exact_with_grad
+  the FP32 MFMA distance tiles (d/dy, d/dh)
   DEANN estimate with the BF16 scan + FP64 refinement      deann_query
   DEANN adjoint (d/dy, d/dh)                               deann_query_backward
-  exact-KDE adjoint (d/dy, d/dh), tiles recomputed         kde_exact_backward
 on the synthetic 100-cluster mixture with n = 1,000,000, d = 128 and
-q = 10,000 queries, Gaussian kernel, k = 100, m = 1,000.  Inputs are resident
-in HBM before the timed region.  Prints one JSON line.
+q = 10,000 queries, Gaussian kernel, k = 100, m = 1,000 (for d > 128 the step
+has the exact KDE without its gradient).  Inputs are resident in HBM before the
+timed region.  Also measured, outside the step: the exact KDE alone (its own
+roofline), the FP32-scan and permuted-sampling DEANN, the BF16 exact KDE.
+Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -126,7 +129,6 @@ def main():
         sweep_km(args, X, Y, h)
         return
     n, d = X.shape
-    exact_bwd = d <= 128     # kde_exact_backward supports d <= 128
     q = Y.shape[0]
     Xd = torch.from_numpy(X).to(dev)
     Yd = torch.from_numpy(Y).to(dev)
@@ -137,19 +139,24 @@ def main():
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
-    comp = {"kde_exact_fp32": [], "deann_bf16": [], "deann_backward": [], "kde_exact_backward": []}
+    # exact KDE and its gradient from one pass over the distance tiles (the
+    # fused entry point supports d <= 128; above, the step has the KDE only)
+    fused = d <= 128
+    comp = {"exact_kde_and_grad_fp32" if fused else "exact_kde_fp32": [], "deann_bf16": [],
+            "deann_backward": []}
 
     def step(record):
-        e = [ev() for _ in range(5)]
+        e = [ev() for _ in range(4)]
         e[0].record()
-        mu = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32")
+        if fused:
+            mu, gye, ghe = dk.kde_exact_with_grad(Xd, Yd, h, KERNEL)
+        else:
+            mu, gye, ghe = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32"), None, None
         e[1].record()
         est, nn, sm = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16")
         e[2].record()
         gy, gh = dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn, sm, gout, KERNEL)
         e[3].record()
-        gye, ghe = dk.kde_exact_backward(Xd, Yd, h, gout, KERNEL) if exact_bwd else (None, None)
-        e[4].record()
         if record is not None:
             record.append(e)
         return mu, est, nn, sm, gy, gh, gye, ghe
@@ -165,8 +172,7 @@ def main():
         res = step(events)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    tile_ms = dk.kernel_times("kde_exact")
-    bwd_tile_ms = dk.kernel_times("kde_exact_backward")
+    step_tile_ms = dk.kernel_times("kde_exact_backward" if fused else "kde_exact")
     dk.kernel_timing(0)
     names = list(comp)
     for e in events:
@@ -174,6 +180,21 @@ def main():
             comp[name].append(e[i].elapsed_time(e[i + 1]))
     ms_step = wall * 1e3 / args.steps
     comp_ms = {k: float(np.mean(v)) for k, v in comp.items()}
+
+    # the exact KDE alone (forward tiles only), outside the step: its own roofline
+    reps = max(2, args.steps // 2)
+    dk.kde_exact(Xd, Yd, h, KERNEL, "fp32")
+    torch.cuda.synchronize()
+    dk.kernel_timing(reps)
+    a, b = ev(), ev()
+    a.record()
+    for _ in range(reps):
+        mu_fwd = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32")
+    b.record()
+    torch.cuda.synchronize()
+    ms_exact_fwd = a.elapsed_time(b) / reps
+    tile_ms = dk.kernel_times("kde_exact")
+    dk.kernel_timing(0)
     mu, est, nn, sm, gy, gh, gye, ghe = res
 
     # FP32-scan DEANN for the BF16+refine vs FP32 comparison (same seed)
@@ -181,8 +202,6 @@ def main():
         est32, nn32, sm32 = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
                                            precision="fp32")
     torch.cuda.synchronize()
-    a, b = ev(), ev()
-    reps = max(2, args.steps // 2)
     a.record()
     for _ in range(reps):
         est32, nn32, sm32 = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
@@ -227,7 +246,29 @@ def main():
 
     flops_exact = 2.0 * n * d * q
     tile_avg_ms = float(np.mean(tile_ms))
-    roof_achieved = flops_exact / (tile_avg_ms * 1e-3)
+    fwd_achieved = flops_exact / (tile_avg_ms * 1e-3)
+    roof_fwd = {"bound": "mfma", "kernel": "kde_tile_kernel<float,gaussian>",
+                "achieved": fwd_achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                "unit": "TFLOP/s", "frac": fwd_achieved / PEAK_FP32_MFMA,
+                "traffic": measured_traffic("kde_tile_kernel<float,gaussian>"),
+                "flops_per_launch": flops_exact, "kernel_avg_ms": tile_avg_ms,
+                "launches_timed": len(tile_ms),
+                "note": "exact KDE alone: 2*n*d*q flops per launch / the tile kernel's own "
+                        "duration (HIP events recorded by the library around it on its stream)"}
+    if fused:
+        step_avg_ms = float(np.mean(step_tile_ms))
+        achieved = 2.0 * flops_exact / (step_avg_ms * 1e-3)
+        roofline = {"bound": "mfma", "kernel": "kde_backward_kernel<gaussian>",
+                    "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                    "traffic": measured_traffic("kde_backward_kernel<gaussian>"),
+                    "flops_per_launch": 2.0 * flops_exact, "kernel_avg_ms": step_avg_ms,
+                    "launches_timed": len(step_tile_ms),
+                    "note": "exact KDE with its gradient (the step's dominant kernel): 4*n*d*q "
+                            "flops per launch (distance tile recomputed + W X) / the kernel's own "
+                            "duration (HIP events recorded by the library on its stream)"}
+    else:
+        roofline = roof_fwd
     out = {
         "metric": METRIC,
         "value": q / (ms_step * 1e-3),
@@ -243,32 +284,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "q": q, "kernel": KERNEL, "h": h,
                    "k": K_NN, "m": M_SAMPLES, "deann_scan": "bf16", "exact": "fp32",
-                   "exact_backward_in_step": exact_bwd},
-        "roofline": {"bound": "mfma", "kernel": "kde_tile_kernel<float,gaussian>",
-                     "achieved": roof_achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": roof_achieved / PEAK_FP32_MFMA,
-                     "traffic": measured_traffic("kde_tile_kernel<float,gaussian>"),
-                     "flops_per_launch": flops_exact, "kernel_avg_ms": tile_avg_ms,
-                     "launches_timed": len(tile_ms),
-                     "note": "2*n*d*q flops per launch / the tile kernel's own duration "
-                             "(HIP events recorded by the library around it on its stream)"},
-        "roofline_exact_backward": None if not bwd_tile_ms else {
-            "bound": "mfma", "kernel": "kde_backward_kernel<gaussian>",
-            "achieved": 4.0 * n * d * q / (float(np.mean(bwd_tile_ms)) * 1e-3) / 1e12,
-            "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-            "frac": 4.0 * n * d * q / (float(np.mean(bwd_tile_ms)) * 1e-3) / PEAK_FP32_MFMA,
-            "flops_per_launch": 4.0 * n * d * q, "kernel_avg_ms": float(np.mean(bwd_tile_ms))},
+                   "exact_gradient_in_step": fused},
+        "roofline": roofline,
+        "roofline_exact_kde": roof_fwd,
         "components_ms": comp_ms,
         "queries_per_s": {
             "step": q / (ms_step * 1e-3),
             "deann_bf16_refine": q / (comp_ms["deann_bf16"] * 1e-3),
             "deann_fp32": q / (ms_deann32 * 1e-3),
             "deann_permuted_bf16_refine": q / (ms_deannp * 1e-3),
-            "kde_exact_fp32": q / (comp_ms["kde_exact_fp32"] * 1e-3),
+            "exact_kde_and_grad_fp32": (q / (comp_ms["exact_kde_and_grad_fp32"] * 1e-3)
+                                        if fused else None),
+            "kde_exact_fp32": q / (ms_exact_fwd * 1e-3),
             "kde_exact_bf16": q / (ms_exact16 * 1e-3),
             "deann_backward": q / (comp_ms["deann_backward"] * 1e-3),
-            "kde_exact_backward": (q / (comp_ms["kde_exact_backward"] * 1e-3)
-                                   if exact_bwd else None),
         },
         "accuracy": {
             "deann_bf16_vs_fp32_same_indices": same_idx,
@@ -285,15 +314,16 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity_sample"] = cpu_baseline(
             X, Y, h, args.cpu_sample, mu_h, est_h, nn.cpu().numpy(), sm.cpu().numpy(),
-            gy.cpu().numpy(), K_NN, M_SAMPLES, exact_bwd)
+            gy.cpu().numpy(), K_NN, M_SAMPLES, fused,
+            gye.cpu().numpy() if gye is not None else None)
         if not args.no_all_cores:
             out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(args.workload, h, K_NN,
-                                                                   M_SAMPLES, exact_bwd)
+                                                                   M_SAMPLES, fused)
     print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu, K_NN, M_SAMPLES,
-                 exact_bwd):
+                 exact_bwd, gye_gpu=None):
     """The FP64 oracle timed on the host for a few queries of the same workload,
     doing the same per-query work as one step; also checks those queries."""
     import numpy as np
@@ -303,14 +333,15 @@ def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu, K_NN, M
 
     sub = synth.query_subset(Y.shape[0], size, seed=11)
     t0 = time.perf_counter()
-    rel_exact, rel_deann, nn_ok, sm_ok, rel_gy = [], [], True, True, []
+    rel_exact, rel_deann, nn_ok, sm_ok, rel_gy, gye_ref = [], [], True, True, [], {}
     for j in sub:
-        mu = oracle.kde_exact(X, Y[j:j + 1], h, oracle.GAUSSIAN)[0]
+        if exact_bwd:   # the KDE and its gradient
+            mu, gye_ref[j], _ = oracle.kde_grad(X, Y[j], h, oracle.GAUSSIAN)
+        else:
+            mu = oracle.kde_exact(X, Y[j:j + 1], h, oracle.GAUSSIAN)[0]
         est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, oracle.GAUSSIAN, K_NN, M_SAMPLES,
                                                    0, int(j))
         _, gy_ref, _ = oracle.deann_grad(X, Y[j], h, oracle.GAUSSIAN, nn_ref, s_ref, M_SAMPLES)
-        if exact_bwd:
-            oracle.kde_grad(X, Y[j], h, oracle.GAUSSIAN)
         if mu >= 1e-16:
             rel_exact.append(abs(mu_gpu[j] - mu) / mu)
             rel_deann.append(abs(est_gpu[j] - est) / est)
@@ -320,15 +351,25 @@ def cpu_baseline(X, Y, h, size, mu_gpu, est_gpu, nn_gpu, sm_gpu, gy_gpu, K_NN, M
         if nrm >= 1e-30:   # grad_Y is float32: smaller gradients underflow
             rel_gy.append(float(np.linalg.norm(gy_gpu[j] - gy_ref) / nrm))
     dt = time.perf_counter() - t0
+    # exact gradient, normwise against sum_i K_i ||x_i - y|| / (n h^2) (not timed)
+    rel_gye = []
+    if gye_gpu is not None:
+        for j, g_ref in gye_ref.items():
+            d2 = oracle.sq_dists(X, Y[j])
+            scale = (oracle.kernel_values(d2, h, oracle.GAUSSIAN) * np.sqrt(d2)).sum() / (
+                X.shape[0] * h * h)
+            if scale > 0:
+                rel_gye.append(float(np.linalg.norm(gye_gpu[j] - g_ref) / scale))
     base = {"value": len(sub) / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(sub)} queries of the same workload, full step per query "
-                      "(exact KDE, DEANN, DEANN adjoint" + (", exact adjoint" if exact_bwd else "")
+                      "(exact KDE" + (" with its gradient" if exact_bwd else "") + ", DEANN, DEANN adjoint"
                       + "), FP64 NumPy, single thread",
             "seconds": dt}
     par = {"queries": [int(j) for j in sub], "nn_equal": nn_ok, "samples_equal": sm_ok,
            "exact_fp32_max_rel": max(rel_exact) if rel_exact else None,
            "deann_max_rel": max(rel_deann) if rel_deann else None,
-           "deann_grad_y_max_rel": max(rel_gy) if rel_gy else None}
+           "deann_grad_y_max_rel": max(rel_gy) if rel_gy else None,
+           "exact_grad_y_max_err_normwise": max(rel_gye) if rel_gye else None}
     return base, par
 
 
@@ -377,12 +418,13 @@ def _oracle_shard(workload, h, k_nn, m_samples, exact_bwd, queries):
     spec, X, Y = synth.workload(workload)
     t0 = time.perf_counter()
     for j in queries:
-        oracle.kde_exact(X, Y[j:j + 1], h, oracle.GAUSSIAN)
+        if exact_bwd:
+            oracle.kde_grad(X, Y[j], h, oracle.GAUSSIAN)
+        else:
+            oracle.kde_exact(X, Y[j:j + 1], h, oracle.GAUSSIAN)
         est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, oracle.GAUSSIAN, k_nn, m_samples,
                                                    0, int(j))
         oracle.deann_grad(X, Y[j], h, oracle.GAUSSIAN, nn_ref, s_ref, m_samples)
-        if exact_bwd:
-            oracle.kde_grad(X, Y[j], h, oracle.GAUSSIAN)
     return time.perf_counter() - t0
 
 

@@ -147,6 +147,31 @@ int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int
                        int kernel, const double* grad_out, float* grad_Y, double* grad_h,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Exact KDE with its derivatives in one pass over the distance tiles (FP32
+ * operands; d <= 128), for callers that need both (mean shift, fitting h):
+ *   out[j]      = (1/n) sum_i K_h(x_i, y_j)                [q] float64
+ *   grad_Y[j]   = d out[j] / d y_j                          [q, d] float32, or NULL
+ *   grad_h[j]   = d out[j] / d h                            [q] float64, or NULL
+ * i.e. kde_exact, and kde_exact_backward with grad_out = 1 except that the h
+ * derivative is returned per query.  Costs one kde_exact_backward.
+ * ------------------------------------------------------------------------- */
+size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d);
+int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                        int kernel, double* out, float* grad_Y, double* grad_h, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Gaussian mean-shift step (the application the paper cites for density
+ * gradients): Y_out[j] = Y[j] + h^2 grad_Y[j] / density[j], i.e. the
+ * kernel-weighted mean of the rows when grad_Y and density come from
+ * kde_exact_with_grad (or the DEANN estimate and its adjoint with
+ * grad_out = 1).  Y, grad_Y, Y_out [q, d] float32 (Y_out may alias Y),
+ * density [q] float64; a query with density 0 keeps its point.
+ * ------------------------------------------------------------------------- */
+int mean_shift_update(const float* Y, const float* grad_Y, const double* density, int64_t q,
+                      int64_t d, double h, float* Y_out, void* stream);
+
 /* Message for the last non-OK status returned on the calling thread. */
 const char* deann_last_error(void);
 
@@ -155,7 +180,7 @@ const char* deann_last_error(void);
  * deann_kernel_timing(capacity): capacity in [1, 4096] makes the calling thread
  * record a pair of HIP events on the call's stream around the dense tile
  * kernel of each following call, for up to `capacity` calls per site:
- *   site 0 = kde_exact, site 1 = kde_exact_backward.
+ *   site 0 = kde_exact, site 1 = kde_exact_backward and kde_exact_with_grad.
  * Recording happens only while a site has unread slots left.  capacity = 0
  * stops and releases the events (also done before a new capacity is set).
  * deann_kernel_times(site, ms, max_count): waits for the recorded events,

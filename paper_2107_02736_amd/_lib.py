@@ -21,6 +21,7 @@ EXPORTS = (
     "deann_query_permuted_workspace", "deann_query_permuted",
     "deann_query_backward_workspace", "deann_query_backward",
     "kde_exact_backward_workspace", "kde_exact_backward",
+    "kde_exact_with_grad_workspace", "kde_exact_with_grad", "mean_shift_update",
     "deann_last_error",
     "deann_kernel_timing", "deann_kernel_times",
 )
@@ -74,6 +75,13 @@ def load(path: str = LIB_PATH):
     lib.kde_exact_backward.restype = _int
     lib.kde_exact_backward.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _vp, _vp, _vp, _vp,
                                        _sz, _vp]
+    lib.kde_exact_with_grad_workspace.restype = _sz
+    lib.kde_exact_with_grad_workspace.argtypes = [_i64, _i64, _i64]
+    lib.kde_exact_with_grad.restype = _int
+    lib.kde_exact_with_grad.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _vp, _vp, _vp, _vp,
+                                        _sz, _vp]
+    lib.mean_shift_update.restype = _int
+    lib.mean_shift_update.argtypes = [_vp, _vp, _vp, _i64, _i64, _dbl, _vp, _vp]
     lib.deann_kernel_timing.restype = _int
     lib.deann_kernel_timing.argtypes = [_int]
     lib.deann_kernel_times.restype = _int

@@ -147,6 +147,40 @@ def kde_exact_backward(X, Y, h, grad_out, kernel="gaussian", need_grad_y: bool =
     return gy, gh
 
 
+def kde_exact_with_grad(X, Y, h, kernel="gaussian", need_grad_y: bool = True,
+                        need_grad_h: bool = True):
+    """Exact KDE and its derivatives in one pass (FP32 tiles, d <= 128):
+    (mu float64 [q], d mu/d y float32 [q,d] or None, d mu/d h float64 [q] or None)."""
+    _check_xy(X, Y)
+    lib = _lib.load()
+    n, d = X.shape
+    q = Y.shape[0]
+    dev = X.device
+    mu = torch.empty(q, dtype=torch.float64, device=dev)
+    gy = torch.empty((q, d), dtype=torch.float32, device=dev) if need_grad_y else None
+    gh = torch.empty(q, dtype=torch.float64, device=dev) if need_grad_h else None
+    ws = _workspace(lib.kde_exact_with_grad_workspace(n, q, d), dev)
+    _lib.check(lib.kde_exact_with_grad(X.data_ptr(), n, Y.data_ptr(), q, d, float(h),
+                                       kernel_id(kernel), mu.data_ptr(), _ptr(gy), _ptr(gh),
+                                       ws.data_ptr(), ws.numel(), _stream(dev)))
+    return mu, gy, gh
+
+
+def mean_shift_update(Y, grad_Y, density, h, out=None):
+    """Gaussian mean-shift step y + h^2 grad / density (out may be Y)."""
+    lib = _lib.load()
+    q, d = Y.shape
+    if out is None:
+        out = torch.empty_like(Y)
+    for t, dt in ((Y, torch.float32), (grad_Y, torch.float32), (density, torch.float64),
+                  (out, torch.float32)):
+        if t.dtype != dt or not t.is_contiguous() or t.device != Y.device:
+            raise ValueError("mean_shift_update: contiguous tensors of the expected dtypes on one device")
+    _lib.check(lib.mean_shift_update(Y.data_ptr(), grad_Y.data_ptr(), density.data_ptr(), q, d,
+                                     float(h), out.data_ptr(), _stream(Y.device)))
+    return out
+
+
 TIMING_SITES = {"kde_exact": 0, "kde_exact_backward": 1}
 
 

@@ -265,7 +265,7 @@ DeannPlan plan_deann(void* ws, int64_t n, int64_t q, int64_t d, int64_t k, int p
 struct KdeBwdPlan {
   Prep prep;
   double* gy_part;
-  double* gh_part;   // gh [splits][qp], rw [splits][qp], per-query [q]
+  double* gh_part;   // gh, rw, ks [splits][qp] each, then per-query [q]
   int64_t bytes;
 };
 
@@ -276,7 +276,7 @@ KdeBwdPlan plan_kde_bwd(void* ws, int64_t n, int64_t q, int64_t d) {
   const int64_t qtiles = P.prep.qp / BQ, ntiles = P.prep.np / BN;
   const int64_t splits = choose_splits(qtiles, ntiles, kKdeSplitTarget);
   P.gy_part = cv.take<double>(splits * P.prep.qp * P.prep.dp);
-  P.gh_part = cv.take<double>(2 * splits * P.prep.qp + (q > 0 ? q : 1));
+  P.gh_part = cv.take<double>(3 * splits * P.prep.qp + (q > 0 ? q : 1));
   P.bytes = cv.off + kAlign;
   return P;
 }
@@ -491,6 +491,45 @@ int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int
   e = launch_kde_backward(tp, Y, d, h, kernel, grad_out, P.gy_part, P.gh_part, grad_Y, grad_h, s,
                           timer_hook(1));
   if (e != hipSuccess) return hip_fail(e, "kde backward");
+  return DEANN_OK;
+}
+
+int mean_shift_update(const float* Y, const float* grad_Y, const double* density, int64_t q,
+                      int64_t d, double h, float* Y_out, void* stream) {
+  if (q < 0 || d < 1) return fail(DEANN_EINVAL, "need q >= 0 and d >= 1");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(DEANN_EINVAL, "h must be finite and > 0");
+  if (q == 0) return DEANN_OK;
+  if (!Y || !grad_Y || !density || !Y_out) return fail(DEANN_EINVAL, "NULL array");
+  const hipError_t e = launch_mean_shift_update(Y, grad_Y, density, q, d, h, Y_out,
+                                                static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "mean shift update");
+  return DEANN_OK;
+}
+
+size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d) {
+  return kde_exact_backward_workspace(n, q, d);
+}
+
+int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                        int kernel, double* out, float* grad_Y, double* grad_h, void* ws,
+                        size_t ws_bytes, void* stream) {
+  int st = check_common(X, n, Y, q, d, h, kernel);
+  if (st != DEANN_OK) return st;
+  if (d > 128) return fail(DEANN_EUNSUPPORTED, "kde_exact_with_grad supports d <= 128");
+  if (q == 0) return DEANN_OK;
+  if (!out) return fail(DEANN_EINVAL, "out is NULL");
+  const int64_t need = plan_kde_bwd(nullptr, n, q, d).bytes;
+  if (!ws || (int64_t)ws_bytes < need)
+    return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  KdeBwdPlan P = plan_kde_bwd(align_ws(ws), n, q, d);
+  hipError_t e = run_prep(P.prep, X, n, Y, q, d, DEANN_FP32, s);
+  if (e != hipSuccess) return hip_fail(e, "prep");
+  TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, kKdeSplitTarget);
+  tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
+  e = launch_kde_backward(tp, Y, d, h, kernel, nullptr, P.gy_part, P.gh_part, grad_Y, nullptr, s,
+                          timer_hook(1), out, grad_h);
+  if (e != hipSuccess) return hip_fail(e, "kde value and gradient");
   return DEANN_OK;
 }
 

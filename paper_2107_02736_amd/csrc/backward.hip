@@ -297,11 +297,14 @@ __device__ __forceinline__ void bstore(const u32x4 (&r)[BCV], char* lds) {
 // wave (8 coordinates x 8 rows) spread over all banks.
 __device__ __forceinline__ int xt_col(int t, int i) { return i ^ (((t >> 3) & 3) << 2); }
 
-template <int KERN, int TB>   // TB = padded d / 16: 2, 4, 6 or 8
+// VAL: also sum the kernel values themselves (the KDE); needed separately for
+// the exponential kernel only, whose weights are K / r (Gaussian: K).
+template <int KERN, int TB, bool VAL>   // TB = padded d / 16: 2, 4, 6 or 8
 __global__ void __launch_bounds__(BWG, 1)
 kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
-                    double* __restrict__ rw_part,
-                    double* __restrict__ gh_part) {
+                    double* __restrict__ rw_part, double* __restrict__ gh_part,
+                    double* __restrict__ ks_part) {
+  constexpr bool KS = VAL && KERN != KERNEL_GAUSSIAN;
   constexpr int DP = TB * 16;
   constexpr int XTS = BN + 4;          // row stride (floats) of the transposed data tile
   constexpr int WS = BN + 4;           // row stride (floats) of W[q][i]
@@ -309,7 +312,7 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
   static_assert(BQ * WS * 4 <= 4 * TILE_LDS, "W must fit in the staging area");
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];   // staging, then W
   __shared__ __attribute__((aligned(16))) float xt[DP * XTS];       // x~ tile as [t][i]
-  __shared__ double rsum[2][4][BQ];   // [rowsum of W | dK/dh sum][wi][query]
+  __shared__ double rsum[KS ? 3 : 2][4][BQ];   // [rowsum of W | dK/dh | K][wi][query]
   int64_t qt, split;
   if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
@@ -330,9 +333,11 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
   for (int bq = 0; bq < 4; ++bq)
 #pragma unroll
     for (int tb = 0; tb < TBW; ++tb) gacc[bq][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  double rws[4], dhs[4];
+  double rws[4], dhs[4], kss[KS ? 4 : 1];
 #pragma unroll
   for (int bq = 0; bq < 4; ++bq) { rws[bq] = 0.0; dhs[bq] = 0.0; }
+#pragma unroll
+  for (int bq = 0; bq < (KS ? 4 : 1); ++bq) kss[bq] = 0.0;
 
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
   u32x4 ry[BCV], rx[BCV];
@@ -399,6 +404,9 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
     // constant factors 1/h^2, 1/h, -1/L and the Gaussian query factor are
     // applied per query by the reduction); per-tile FP32 row sums folded into FP64
     float rw32[4] = {0.f, 0.f, 0.f, 0.f}, dh32[4] = {0.f, 0.f, 0.f, 0.f};
+    float ks32[KS ? 4 : 1];
+#pragma unroll
+    for (int bq = 0; bq < (KS ? 4 : 1); ++bq) ks32[bq] = 0.f;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
@@ -423,6 +431,7 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
             const float K = __builtin_amdgcn_exp2f(-L * rr);
             w = rr > 0.f ? K * __builtin_amdgcn_rcpf(rr) : 0.f;
             dh = K * rr;
+            if constexpr (KS) ks32[bq] += K;
           }
           acc[bi][bq][r] = w;
           rw32[bq] += w;
@@ -432,6 +441,10 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
     }
 #pragma unroll
     for (int bq = 0; bq < 4; ++bq) { rws[bq] += (double)rw32[bq]; dhs[bq] += (double)dh32[bq]; }
+    if constexpr (KS) {
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) kss[bq] += (double)ks32[bq];
+    }
     __syncthreads();   // the staging area (now W) is free
     // W[q][i]: lane holds 4 consecutive i of one q per block
 #pragma unroll
@@ -478,6 +491,12 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
       rsum[0][wi][wq * 64 + bq * 16 + lane] = a;
       rsum[1][wi][wq * 64 + bq * 16 + lane] = bb;
     }
+    if constexpr (KS) {
+      double c = kss[bq];
+      c += __shfl_xor(c, 16, 64);
+      c += __shfl_xor(c, 32, 64);
+      if (lane < 16) rsum[KS ? 2 : 0][wi][wq * 64 + bq * 16 + lane] = c;
+    }
   }
   __syncthreads();
   const int64_t qbase = split * p.qp + qt * BQ;
@@ -497,39 +516,50 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
     const int ql = threadIdx.x;
     rw_part[qbase + ql] = (rsum[0][0][ql] + rsum[0][1][ql]) + (rsum[0][2][ql] + rsum[0][3][ql]);
     gh_part[qbase + ql] = (rsum[1][0][ql] + rsum[1][1][ql]) + (rsum[1][2][ql] + rsum[1][3][ql]);
+    if constexpr (KS)
+      ks_part[qbase + ql] =
+          (rsum[KS ? 2 : 0][0][ql] + rsum[KS ? 2 : 0][1][ql]) + (rsum[KS ? 2 : 0][2][ql] + rsum[KS ? 2 : 0][3][ql]);
   }
 }
 
 // grad_Y[q] = g_q / n * c_y * f_q * (sum_s G_s[q] - y~_q sum_s rowsum_s[q]) and the
 // per-query h term g_q / n * c_h * f_q * sum_s dh_s[q], where c_y, c_h are the
 // constant factors left out of the tile weights and f_q is the Gaussian query
-// factor 2^(rounding remainder of -L ||y||^2) (1 for the exponential kernel).
+// factor 2^(rounding remainder of -L ||y||^2) (1 for the exponential kernel);
+// g_q = grad_out[q], or 1 when grad_out is null.  With mu non-null also the
+// KDE itself, f_q / n * sum_s K_s[q] (ks_part, or the Gaussian weight sums).
 __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
                                            const double* __restrict__ rw_part,
                                            const double* __restrict__ gh_part,
+                                           const double* __restrict__ ks_part,
                                            const float* __restrict__ Ys, int64_t splits,
                                            int64_t qp, int64_t q, int64_t d, int64_t dp,
                                            double inv_n, const double* __restrict__ ynorm,
                                            float L, int kern, double c_y, double c_h,
                                            const double* __restrict__ grad_out,
-                                           float* __restrict__ grad_Y, double* __restrict__ ghq) {
+                                           float* __restrict__ grad_Y, double* __restrict__ ghq,
+                                           double* __restrict__ mu) {
   const int64_t qi = blockIdx.x;
   __shared__ double rw_s, f_s;
   if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0;
     for (int64_t s = 0; s < splits; ++s) { a += rw_part[s * qp + qi]; b += gh_part[s * qp + qi]; }
+    if (mu && ks_part)
+      for (int64_t s = 0; s < splits; ++s) c += ks_part[s * qp + qi];
     double f = 1.0;
     if (kern == KERNEL_GAUSSIAN) {
       const double e = -(double)L * ynorm[qi];
       f = exp2(e - (double)(float)e);
     }
+    const double g = grad_out ? grad_out[qi] : 1.0;
     rw_s = a;
     f_s = f;
-    if (ghq) ghq[qi] = grad_out[qi] * inv_n * c_h * f * b;
+    if (ghq) ghq[qi] = g * inv_n * c_h * f * b;
+    if (mu) mu[qi] = f * (ks_part ? c : a) * inv_n;
   }
   __syncthreads();
   if (!grad_Y) return;
-  const double sc = grad_out[qi] * inv_n * c_y * f_s;
+  const double sc = (grad_out ? grad_out[qi] : 1.0) * inv_n * c_y * f_s;
   for (int64_t t = threadIdx.x; t < d; t += blockDim.x) {
     double g = 0.0;
     for (int64_t s = 0; s < splits; ++s) g += gy_part[(s * qp + qi) * dp + t];
@@ -537,42 +567,70 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
   }
 }
 
-template <int KERN>
+template <int KERN, bool VAL>
 static hipError_t launch_kde_bwd_k(const TileProblem& p, int TB, float L, double* gy, double* rw,
-                                   double* gh, hipStream_t s) {
+                                   double* gh, double* ks, hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), b(BWG);
   switch (TB) {
-    case 2: kde_backward_kernel<KERN, 2><<<g, b, 0, s>>>(p, L, gy, rw, gh); break;
-    case 4: kde_backward_kernel<KERN, 4><<<g, b, 0, s>>>(p, L, gy, rw, gh); break;
-    case 6: kde_backward_kernel<KERN, 6><<<g, b, 0, s>>>(p, L, gy, rw, gh); break;
-    default: kde_backward_kernel<KERN, 8><<<g, b, 0, s>>>(p, L, gy, rw, gh); break;
+    case 2: kde_backward_kernel<KERN, 2, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 4: kde_backward_kernel<KERN, 4, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 6: kde_backward_kernel<KERN, 6, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    default: kde_backward_kernel<KERN, 8, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
   }
+  return hipGetLastError();
+}
+
+// Gaussian mean-shift step from the density and its gradient:
+// y <- y + h^2 grad / mu, which is the kernel-weighted mean of the rows.
+__global__ void mean_shift_update_kernel(const float* Y, const float* __restrict__ g,
+                                         const double* __restrict__ mu, int64_t q, int64_t d,
+                                         double h2, float* Y_out) {   // Y_out may alias Y
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= q * d) return;
+  const double m = mu[i / d];
+  Y_out[i] = m > 0.0 ? (float)((double)Y[i] + h2 * (double)g[i] / m) : Y[i];
+}
+
+hipError_t launch_mean_shift_update(const float* Y, const float* g, const double* mu, int64_t q,
+                                    int64_t d, double h, float* Y_out, hipStream_t s) {
+  if (q == 0) return hipSuccess;
+  const int64_t total = q * d;
+  mean_shift_update_kernel<<<dim3((unsigned)ceil_div(total, WG)), dim3(WG), 0, s>>>(
+      Y, g, mu, q, d, h * h, Y_out);
   return hipGetLastError();
 }
 
 hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, double h, int kern,
                                const double* grad_out, double* gy_part, double* gh_part,
-                               float* grad_Y, double* grad_h, hipStream_t s, TimingHook th) {
+                               float* grad_Y, double* grad_h, hipStream_t s, TimingHook th,
+                               double* mu, double* gh_per_query) {
   (void)Y;
   const int64_t dp = p.ld_bytes / 4;
   const int TB = (int)(dp / 16);
   const double log2e = 1.4426950408889634;
   const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
-  double* rw_part = gh_part + p.splits * p.qp;   // layout: gh [splits][qp], rw [splits][qp], ghq [q]
-  double* ghq = rw_part + p.splits * p.qp;
+  // layout: gh [splits][qp], rw [splits][qp], ks [splits][qp], ghq [q]
+  double* rw_part = gh_part + p.splits * p.qp;
+  double* ks_part = rw_part + p.splits * p.qp;
+  double* ghq = gh_per_query ? gh_per_query : ks_part + p.splits * p.qp;
+  const bool val = mu != nullptr;
   hipError_t e;
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
-  e = (kern == KERNEL_GAUSSIAN)
-          ? launch_kde_bwd_k<KERNEL_GAUSSIAN>(p, TB, L, gy_part, rw_part, gh_part, s)
-          : launch_kde_bwd_k<KERNEL_EXPONENTIAL>(p, TB, L, gy_part, rw_part, gh_part, s);
+  if (kern == KERNEL_GAUSSIAN)   // the KDE is the sum of the weights themselves
+    e = launch_kde_bwd_k<KERNEL_GAUSSIAN, false>(p, TB, L, gy_part, rw_part, gh_part, ks_part, s);
+  else
+    e = val ? launch_kde_bwd_k<KERNEL_EXPONENTIAL, true>(p, TB, L, gy_part, rw_part, gh_part, ks_part, s)
+            : launch_kde_bwd_k<KERNEL_EXPONENTIAL, false>(p, TB, L, gy_part, rw_part, gh_part, ks_part, s);
   if (e != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
   // Gaussian: weights K, dh terms K * (-L d^2); exponential: weights K / r, dh terms K r
   const double c_y = kern == KERNEL_GAUSSIAN ? 1.0 / (h * h) : 1.0 / h;
   const double c_h = kern == KERNEL_GAUSSIAN ? -1.0 / (h * h * h * (double)L) : 1.0 / (h * h);
+  const bool need_ghq = grad_h || gh_per_query;
   kde_backward_reduce_kernel<<<dim3((unsigned)p.q), dim3(128), 0, s>>>(
-      gy_part, rw_part, gh_part, reinterpret_cast<const float*>(p.Ys), p.splits, p.qp, p.q, d, dp,
-      1.0 / (double)p.n, p.ynorm, L, kern, c_y, c_h, grad_out, grad_Y, ghq);
+      gy_part, rw_part, gh_part, (val && kern != KERNEL_GAUSSIAN) ? ks_part : nullptr,
+      reinterpret_cast<const float*>(p.Ys), p.splits, p.qp, p.q, d, dp, 1.0 / (double)p.n,
+      p.ynorm, L, kern, c_y, c_h, grad_out, grad_Y, need_ghq ? ghq : nullptr, mu);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!grad_h) return hipSuccess;
   sum_scalar_kernel<<<dim3(1), dim3(WG), 0, s>>>(ghq, p.q, grad_h);

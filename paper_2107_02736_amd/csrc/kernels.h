@@ -81,6 +81,10 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
 
 hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, double h, int kern,
                                const double* grad_out, double* gy_part, double* gh_part,
-                               float* grad_Y, double* grad_h, hipStream_t s, TimingHook th = {});
+                               float* grad_Y, double* grad_h, hipStream_t s, TimingHook th = {},
+                               double* mu = nullptr, double* gh_per_query = nullptr);
+
+hipError_t launch_mean_shift_update(const float* Y, const float* g, const double* mu, int64_t q,
+                                    int64_t d, double h, float* Y_out, hipStream_t s);
 
 }  // namespace deann

@@ -296,6 +296,30 @@ def test_exact_backward_vs_oracle(dev, kern):
     assert abs(gh - gh_ref) <= 1e-4 * gh_scale
 
 
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_exact_value_and_gradient_in_one_pass(dev, kern):
+    # kde_exact_with_grad: the KDE, its y-gradient and its per-query h-derivative
+    import paper_2107_02736_amd as dk
+    X, Y = _small(6000, 70, 64, seed=9)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h = 6.0
+    mu, gy, gh = (t.cpu().numpy() for t in dk.kde_exact_with_grad(Xd, Yd, h, KNAME[kern]))
+    mu_fwd = dk.kde_exact(Xd, Yd, h, KNAME[kern], "fp32").cpu().numpy()
+    gy_bwd, _ = dk.kde_exact_backward(Xd, Yd, h, to_dev(np.ones(70), dev), KNAME[kern])
+    assert np.allclose(gy, gy_bwd.cpu().numpy(), rtol=0, atol=0)   # same kernel, same order
+    for j in range(70):
+        mu_ref, gy_ref, gh_ref = oracle.kde_grad(X, Y[j].astype(np.float64), h, kern)
+        assert abs(mu[j] - mu_ref) <= 1e-5 * mu_ref
+        assert abs(mu[j] - mu_fwd[j]) <= 2e-6 * mu_ref
+        d2 = oracle.sq_dists(X, Y[j])
+        K = oracle.kernel_values(d2, h, kern)
+        r = np.sqrt(d2)
+        scale = (K * r).sum() / (X.shape[0] * h * h) if kern == GAUSSIAN else K.sum() / (X.shape[0] * h)
+        assert np.linalg.norm(gy[j] - gy_ref) <= 1e-4 * scale
+        hs = (K * d2).sum() / (X.shape[0] * h ** 3) if kern == GAUSSIAN else (K * r).sum() / (X.shape[0] * h * h)
+        assert abs(gh[j] - gh_ref) <= 1e-4 * hs
+
+
 def test_autograd_matches_finite_differences(dev):
     # DEANN with the index sets fixed: central differences of the GPU forward.
     import torch

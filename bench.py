@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-all-cores", action="store_true",
                     help="skip the all-cores oracle run (single-core baseline only)")
-    ap.add_argument("--cpu-sample", type=int, default=6, help="queries in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=16, help="queries in the oracle sample")
     ap.add_argument("--sweep-km", action="store_true",
                     help="only run DEANN (BF16 scan + refinement) over a (k, m) grid and print its "
                          "error against the exact KDE and its queries/s")

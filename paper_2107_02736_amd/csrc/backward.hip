@@ -262,263 +262,216 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
 }
 
 // ---------------------------------------------------------------------------
-// Exact-KDE backward on MFMA (FP32 operands, padded d <= 128)
+// Exact-KDE backward on MFMA (FP32 operands, padded d = DP <= 128)
 // ---------------------------------------------------------------------------
-// 512 threads (8 waves, two per SIMD so that one wave's epilogue overlaps the
-// other's MFMAs).  First product: wave (wi, wq) computes S^T for data rows
-// wi*32..+32 and queries wq*64..+64 and turns it into the weights W, which go
-// to LDS as W[q][i].  Second product: wave (wq, wt) accumulates
-// G[q][t] = sum_i W[q][i] x~[i][t] for queries wq*64..+64 and coordinates
-// wt*DP/4..+DP/4 over all 128 rows of the tile, so no cross-wave sum of G is
-// needed.
+// 512 threads (8 waves, two per SIMD).  Wave w owns queries w*16..+16 of the
+// query tile; their FP32 rows stay in registers for the whole sweep (the
+// B-operand fragments of every k-group).  Each 128-row data tile is staged
+// whole in LDS (double-buffered, one barrier per tile) and serves both
+// products of the wave:
+//   S^T = X~ Y~^T   A = data-row fragments from LDS, B = the resident queries;
+//                   lane (g, c) = (lane/16, lane%16) receives rows
+//                   16*bi + 4*g + r (r = 0..3) of query column c;
+//   weights         W = f(S^T) in place (FP32, same exponent arithmetic as the
+//                   forward tiles);
+//   G += W X~       16x16x4 MFMAs whose k index g stands for data row
+//                   16*bi + 4*g + r: the A operand is the weight register
+//                   itself, the B operand one 16-byte LDS read of that row
+//                   (4 consecutive coordinates, used by 4 MFMAs whose output
+//                   column c stands for coordinate 4*c + j of the block).
+// Nothing goes through LDS but the data tile; G, the weight sums and the dK/dh
+// sums stay in registers until the end of the split.
 constexpr int BWG = 512;
-constexpr int BCV = BQ * CHUNK_BYTES / 16 / BWG;   // 16-byte chunk loads per thread (= 2)
 
-__device__ __forceinline__ void bload(u32x4 (&r)[BCV], const char* __restrict__ base,
-                                      int64_t ld_bytes, int64_t kbyte) {
-#pragma unroll
-  for (int i = 0; i < BCV; ++i) {
-    const int v = threadIdx.x + i * BWG;
-    r[i] = *reinterpret_cast<const u32x4*>(base + (v / 8) * ld_bytes + kbyte + (v % 8) * 16);
-  }
-}
-
-__device__ __forceinline__ void bstore(const u32x4 (&r)[BCV], char* lds) {
-#pragma unroll
-  for (int i = 0; i < BCV; ++i) {
-    const int v = threadIdx.x + i * BWG;
-    *reinterpret_cast<u32x4*>(lds + (v / 8) * LDS_ROW + (v % 8) * 16) = r[i];
-  }
-}
-
-// Column of element (t, i) within row t of the transposed tile: groups of four
-// consecutive i stay contiguous (16-byte reads in the second product) and are
-// XOR-permuted by bits 3..4 of t, so that the transposed 4-byte writes of one
-// wave (8 coordinates x 8 rows) spread over all banks.
-__device__ __forceinline__ int xt_col(int t, int i) { return i ^ (((t >> 3) & 3) << 2); }
+template <int DP>
+struct GradTile {
+  static constexpr int KGS = DP / 16;            // 64-byte k-groups per row
+  static constexpr int PITCH = DP * 4 + 16;      // LDS row pitch (bytes)
+  static constexpr int NB = DP / 64;             // 64-coordinate blocks of G
+  static constexpr int HB = (DP % 64) / 32;      // trailing 32-coordinate block
+  static constexpr int GB = 4 * NB + 2 * HB;     // 16x16 G blocks per wave
+  static constexpr int NPT = BN * DP / 4 / BWG;  // 16-byte tile pieces per thread
+  static constexpr int PPR = DP / 4;             // 16-byte pieces per row
+};
 
 // VAL: also sum the kernel values themselves (the KDE); needed separately for
 // the exponential kernel only, whose weights are K / r (Gaussian: K).
-template <int KERN, int TB, bool VAL>   // TB = padded d / 16: 2, 4, 6 or 8
+template <int KERN, int DP, bool VAL>
 __global__ void __launch_bounds__(BWG, 1)
 kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
                     double* __restrict__ rw_part, double* __restrict__ gh_part,
                     double* __restrict__ ks_part) {
+  using G = GradTile<DP>;
   constexpr bool KS = VAL && KERN != KERNEL_GAUSSIAN;
-  constexpr int DP = TB * 16;
-  constexpr int XTS = BN + 4;          // row stride (floats) of the transposed data tile
-  constexpr int WS = BN + 4;           // row stride (floats) of W[q][i]
-  constexpr int TBW = (TB + 3) / 4;    // coordinate blocks per wave in the second product
-  static_assert(BQ * WS * 4 <= 4 * TILE_LDS, "W must fit in the staging area");
-  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];   // staging, then W
-  __shared__ __attribute__((aligned(16))) float xt[DP * XTS];       // x~ tile as [t][i]
-  __shared__ double rsum[KS ? 3 : 2][4][BQ];   // [rowsum of W | dK/dh | K][wi][query]
+  __shared__ __attribute__((aligned(16))) char xs[2][BN * G::PITCH];
+  __shared__ __attribute__((aligned(16))) float xvs[2][BN];   // per-row exponent terms
   int64_t qt, split;
   if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wi = wave >> 1, wq = wave & 1;   // first product
-  const int wt = wave >> 1;                  // second product: coordinate quarter
-  // per-query terms of the exponent (as in the forward tiles)
-  float yv[4];
-#pragma unroll
-  for (int bq = 0; bq < 4; ++bq) {
-    const double yn = p.ynorm[qt * BQ + wq * 64 + bq * 16 + (lane & 15)];
-    yv[bq] = KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * yn) : (float)yn;
-  }
-  float* W = reinterpret_cast<float*>(lds);
+  const int g = lane >> 4, c = lane & 15;
 
-  f32x4 gacc[4][TBW];
+  // resident query fragments and the query's exponent term
+  const int64_t qrow = qt * BQ + wave * 16 + c;
+  u32x4 yf[G::KGS];
 #pragma unroll
-  for (int bq = 0; bq < 4; ++bq)
-#pragma unroll
-    for (int tb = 0; tb < TBW; ++tb) gacc[bq][tb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  double rws[4], dhs[4], kss[KS ? 4 : 1];
-#pragma unroll
-  for (int bq = 0; bq < 4; ++bq) { rws[bq] = 0.0; dhs[bq] = 0.0; }
-#pragma unroll
-  for (int bq = 0; bq < (KS ? 4 : 1); ++bq) kss[bq] = 0.0;
+  for (int kg = 0; kg < G::KGS; ++kg)
+    yf[kg] = *reinterpret_cast<const u32x4*>(p.Ys + qrow * p.ld_bytes + kg * KG_BYTES + g * 16);
+  const double ynq = p.ynorm[qrow];
+  const float yv = KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * ynq) : (float)ynq;
 
-  const char* yq = p.Ys + qt * BQ * p.ld_bytes;
-  u32x4 ry[BCV], rx[BCV];
-  int buf = 0;
+  // data tile: global -> registers -> LDS; row terms by the first 128 threads
+  u32x4 xr[G::NPT];
+  float xvr = 0.f;
+  auto gload = [&](int64_t t) {
+    const char* base = p.Xs + t * BN * p.ld_bytes;
+#pragma unroll
+    for (int i = 0; i < G::NPT; ++i) {
+      const int v = threadIdx.x + i * BWG;
+      xr[i] = *reinterpret_cast<const u32x4*>(base + (v / G::PPR) * p.ld_bytes + (v % G::PPR) * 16);
+    }
+    if (threadIdx.x < BN) {
+      const int64_t row = t * BN + threadIdx.x;
+      // padding rows: a huge finite term, so that K = 0 and K * d^2 = 0
+      xvr = row < p.n ? (KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * p.xnorm[row])
+                                                 : (float)p.xnorm[row])
+                      : (KERN == KERNEL_GAUSSIAN ? -1e30f : 1e30f);
+    }
+  };
+  auto lstore = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < G::NPT; ++i) {
+      const int v = threadIdx.x + i * BWG;
+      *reinterpret_cast<u32x4*>(&xs[b][(v / G::PPR) * G::PITCH + (v % G::PPR) * 16]) = xr[i];
+    }
+    if (threadIdx.x < BN) xvs[b][threadIdx.x] = xvr;
+  };
+
+  f32x4 gacc[G::GB];
+#pragma unroll
+  for (int i = 0; i < G::GB; ++i) gacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double rws = 0.0, dhs = 0.0, kss = 0.0;
+
   if (t0 < t1) {
-    bload(ry, yq, p.ld_bytes, 0);
-    bload(rx, p.Xs + t0 * BN * p.ld_bytes, p.ld_bytes, 0);
+    gload(t0);
+    lstore(0);
   }
   __syncthreads();
-  // data norms one tile ahead, one per thread, staged in LDS when the tile
-  // starts (published by the chunk barriers; xnorm covers the padded rows)
-  __shared__ double xns[2][BN];
-  double xn_reg = (threadIdx.x < BN && t0 < t1) ? p.xnorm[t0 * BN + threadIdx.x] : 0.0;
   for (int64_t t = t0; t < t1; ++t) {
-    const int nb = (int)((t - t0) & 1);
-    if (threadIdx.x < BN) {
-      xns[nb][threadIdx.x] = xn_reg;
-      if (t + 1 < t1) xn_reg = p.xnorm[(t + 1) * BN + threadIdx.x];
+    const int b = (int)((t - t0) & 1);
+    const bool more = t + 1 < t1;
+    if (more) gload(t + 1);   // in flight behind the first product
+    const char* xb = xs[b];
+
+    // S^T for the 128 rows of the tile against the wave's 16 queries
+    f32x4 acc[8];
+#pragma unroll
+    for (int bi = 0; bi < 8; ++bi) acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int kg = 0; kg < G::KGS; ++kg) {
+#pragma unroll
+      for (int bi = 0; bi < 8; ++bi) {
+        const u32x4 a = *reinterpret_cast<const u32x4*>(xb + (bi * 16 + c) * G::PITCH +
+                                                         kg * KG_BYTES + g * 16);
+        acc[bi] = mfma_kgroup<float>(a, yf[kg], acc[bi]);
+      }
     }
-    f32x4 acc[2][4];   // [bi][bq]: rows = data, columns = queries
+    __builtin_amdgcn_s_setprio(0);
+    if (more) lstore(b ^ 1);   // the other buffer was last read before the previous barrier
+
+    // weights (constant factors 1/h^2, 1/h, -1/L and the Gaussian query
+    // correction are applied per query by the reduction); FP32 partial sums of
+    // eight rows folded into FP64
+    const f32x4* xv4 = reinterpret_cast<const f32x4*>(xvs[b]);
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bp = 0; bp < 4; ++bp) {
+      float rw32 = 0.f, dh32 = 0.f, ks32 = 0.f;
 #pragma unroll
-      for (int bq = 0; bq < 4; ++bq) acc[bi][bq] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int c = 0; c < p.nchunks; ++c) {
-      char* qa = lds + buf * 2 * TILE_LDS;
-      char* xa = qa + TILE_LDS;
-      bstore(ry, qa);
-      bstore(rx, xa);
-      // the same data chunk, transposed into xt[t][i] for the second product
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const int bi = 2 * bp + h2;
+        const f32x4 xv = xv4[bi * 4 + g];
 #pragma unroll
-      for (int i = 0; i < BCV; ++i) {
-        const int v = threadIdx.x + i * BWG;
-        const int t4 = c * (CHUNK_BYTES / 4) + (v % 8) * 4;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          xt[(t4 + j) * XTS + xt_col(t4 + j, v / 8)] = __uint_as_float(rx[i][j]);
-      }
-      __syncthreads();
-      int nc = c + 1;
-      int64_t nt = t;
-      if (nc == p.nchunks) { nc = 0; nt = t + 1; }
-      if (nt < t1) {
-        bload(ry, yq, p.ld_bytes, (int64_t)nc * CHUNK_BYTES);
-        bload(rx, p.Xs + nt * BN * p.ld_bytes, p.ld_bytes, (int64_t)nc * CHUNK_BYTES);
-      }
-      __builtin_amdgcn_s_setprio(1);   // favour the wave issuing MFMAs
-#pragma unroll
-      for (int kg = 0; kg < CHUNK_BYTES / KG_BYTES; ++kg) {
-        u32x4 a[2], b[4];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi) a[bi] = lds_frag(xa, wi * 32 + bi * 16, kg, lane);
-#pragma unroll
-        for (int bq = 0; bq < 4; ++bq) b[bq] = lds_frag(qa, wq * 64 + bq * 16, kg, lane);
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bq = 0; bq < 4; ++bq) acc[bi][bq] = mfma_kgroup<float>(a[bi], b[bq], acc[bi][bq]);
-      }
-      __builtin_amdgcn_s_setprio(0);
-      buf ^= 1;
-    }
-    // weights in FP32 (the same exponent arithmetic as the forward tiles; the
-    // constant factors 1/h^2, 1/h, -1/L and the Gaussian query factor are
-    // applied per query by the reduction); per-tile FP32 row sums folded into FP64
-    float rw32[4] = {0.f, 0.f, 0.f, 0.f}, dh32[4] = {0.f, 0.f, 0.f, 0.f};
-    float ks32[KS ? 4 : 1];
-#pragma unroll
-    for (int bq = 0; bq < (KS ? 4 : 1); ++bq) ks32[bq] = 0.f;
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = t * BN + wi * 32 + bi * 16 + 4 * (lane >> 4) + r;
-        const double xn = xns[nb][wi * 32 + bi * 16 + 4 * (lane >> 4) + r];
-        // padding rows: a huge finite term, so that K = 0 and K * d^2 = 0
-        const float xv = row < p.n ? (KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * xn) : (float)xn)
-                                   : (KERN == KERNEL_GAUSSIAN ? -1e30f : 1e30f);
-#pragma unroll
-        for (int bq = 0; bq < 4; ++bq) {
-          const float s = acc[bi][bq][r];
+        for (int r = 0; r < 4; ++r) {
+          const float s = acc[bi][r];
           float w, dh;
           if (KERN == KERNEL_GAUSSIAN) {
-            const float a = fminf(__builtin_fmaf(2.f * L, s, yv[bq] + xv), 0.f);   // -L d^2
+            const float a = fminf(__builtin_fmaf(2.f * L, s, yv + xv[r]), 0.f);   // -L d^2
             const float K = __builtin_amdgcn_exp2f(a);
             w = K;
             dh = K * a;
           } else {
-            const float d2 = fmaxf(__builtin_fmaf(-2.f, s, yv[bq] + xv), 0.f);
+            const float d2 = fmaxf(__builtin_fmaf(-2.f, s, yv + xv[r]), 0.f);
             const float rr = __builtin_sqrtf(d2);
             const float K = __builtin_amdgcn_exp2f(-L * rr);
             w = rr > 0.f ? K * __builtin_amdgcn_rcpf(rr) : 0.f;
             dh = K * rr;
-            if constexpr (KS) ks32[bq] += K;
+            if constexpr (KS) ks32 += K;
           }
-          acc[bi][bq][r] = w;
-          rw32[bq] += w;
-          dh32[bq] += dh;
+          acc[bi][r] = w;
+          rw32 += w;
+          dh32 += dh;
+        }
+      }
+      rws += (double)rw32;
+      dhs += (double)dh32;
+      if constexpr (KS) kss += (double)ks32;
+    }
+
+    // G[q][t] += sum over the tile's rows of W[q][i] x~[i][t]
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int bi = 0; bi < 8; ++bi) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const char* row = xb + (bi * 16 + 4 * g + r) * G::PITCH;
+        const float w = acc[bi][r];
+#pragma unroll
+        for (int nb = 0; nb < G::NB; ++nb) {
+          const u32x4 xv = *reinterpret_cast<const u32x4*>(row + (nb * 64 + 4 * c) * 4);
+          gacc[4 * nb + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.x), gacc[4 * nb + 0], 0, 0, 0);
+          gacc[4 * nb + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.y), gacc[4 * nb + 1], 0, 0, 0);
+          gacc[4 * nb + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.z), gacc[4 * nb + 2], 0, 0, 0);
+          gacc[4 * nb + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.w), gacc[4 * nb + 3], 0, 0, 0);
+        }
+        if constexpr (G::HB) {
+          const uint2 xv = *reinterpret_cast<const uint2*>(row + (G::NB * 64 + 2 * c) * 4);
+          gacc[4 * G::NB + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.x), gacc[4 * G::NB + 0], 0, 0, 0);
+          gacc[4 * G::NB + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.y), gacc[4 * G::NB + 1], 0, 0, 0);
         }
       }
     }
-#pragma unroll
-    for (int bq = 0; bq < 4; ++bq) { rws[bq] += (double)rw32[bq]; dhs[bq] += (double)dh32[bq]; }
-    if constexpr (KS) {
-#pragma unroll
-      for (int bq = 0; bq < 4; ++bq) kss[bq] += (double)ks32[bq];
-    }
-    __syncthreads();   // the staging area (now W) is free
-    // W[q][i]: lane holds 4 consecutive i of one q per block
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bq = 0; bq < 4; ++bq)
-        *reinterpret_cast<f32x4*>(&W[(wq * 64 + bq * 16 + (lane & 15)) * WS + wi * 32 + bi * 16 +
-                                     4 * (lane >> 4)]) = acc[bi][bq];
-    __syncthreads();
-    // G[q][t] += sum_i W[q][i] x~[i][t] over the tile's 128 rows
-#pragma unroll 2
-    for (int kb = 0; kb < BN / 16; ++kb) {
-      f32x4 a[4];
-#pragma unroll
-      for (int bq = 0; bq < 4; ++bq)
-        a[bq] = *reinterpret_cast<const f32x4*>(
-            &W[(wq * 64 + bq * 16 + (lane & 15)) * WS + kb * 16 + 4 * (lane >> 4)]);
-#pragma unroll
-      for (int tb = 0; tb < TBW; ++tb) {
-        const int tcol = (wt * TBW + tb) * 16;
-        if (tcol < DP) {
-          const f32x4 b = *reinterpret_cast<const f32x4*>(
-              &xt[(tcol + (lane & 15)) * XTS + xt_col(tcol + (lane & 15), kb * 16 + 4 * (lane >> 4))]);
-#pragma unroll
-          for (int bq = 0; bq < 4; ++bq)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-              gacc[bq][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bq][j], b[j], gacc[bq][tb],
-                                                                   0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();   // W (staging) and xt are reused by the next tile
+    __builtin_amdgcn_s_setprio(0);
+    __syncthreads();   // tile t+1 staged; buffer b free for tile t+2
   }
-  // row sums: lanes sharing a query column, then the four wi waves (fixed order)
-#pragma unroll
-  for (int bq = 0; bq < 4; ++bq) {
-    double a = rws[bq], bb = dhs[bq];
-    a += __shfl_xor(a, 16, 64);
-    a += __shfl_xor(a, 32, 64);
-    bb += __shfl_xor(bb, 16, 64);
-    bb += __shfl_xor(bb, 32, 64);
-    if (lane < 16) {
-      rsum[0][wi][wq * 64 + bq * 16 + lane] = a;
-      rsum[1][wi][wq * 64 + bq * 16 + lane] = bb;
-    }
-    if constexpr (KS) {
-      double c = kss[bq];
-      c += __shfl_xor(c, 16, 64);
-      c += __shfl_xor(c, 32, 64);
-      if (lane < 16) rsum[KS ? 2 : 0][wi][wq * 64 + bq * 16 + lane] = c;
-    }
+
+  // per-query sums: the four lane groups of a query column (fixed order)
+  rws += __shfl_xor(rws, 16, 64);
+  rws += __shfl_xor(rws, 32, 64);
+  dhs += __shfl_xor(dhs, 16, 64);
+  dhs += __shfl_xor(dhs, 32, 64);
+  if constexpr (KS) {
+    kss += __shfl_xor(kss, 16, 64);
+    kss += __shfl_xor(kss, 32, 64);
   }
-  __syncthreads();
-  const int64_t qbase = split * p.qp + qt * BQ;
+  const int64_t qbase = split * p.qp + qt * BQ + wave * 16;
+  if (g == 0) {
+    rw_part[qbase + c] = rws;
+    gh_part[qbase + c] = dhs;
+    if constexpr (KS) ks_part[qbase + c] = kss;
+  }
+  // G block (nb, j): lane (g, c), register rr holds query 4g + rr, coordinate
+  // nb*64 + 4c + j (trailing block: NB*64 + 2c + j)
 #pragma unroll
-  for (int bq = 0; bq < 4; ++bq)
+  for (int rr = 0; rr < 4; ++rr) {
+    double* dst = gy_part + (qbase + 4 * g + rr) * DP;
 #pragma unroll
-    for (int tb = 0; tb < TBW; ++tb) {
-      const int tcol = (wt * TBW + tb) * 16;
-      if (tcol < DP)
+    for (int nb = 0; nb < G::NB; ++nb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int ql = wq * 64 + bq * 16 + 4 * (lane >> 4) + r;
-          gy_part[(qbase + ql) * DP + tcol + (lane & 15)] = (double)gacc[bq][tb][r];
-        }
-    }
-  if (threadIdx.x < BQ) {
-    const int ql = threadIdx.x;
-    rw_part[qbase + ql] = (rsum[0][0][ql] + rsum[0][1][ql]) + (rsum[0][2][ql] + rsum[0][3][ql]);
-    gh_part[qbase + ql] = (rsum[1][0][ql] + rsum[1][1][ql]) + (rsum[1][2][ql] + rsum[1][3][ql]);
-    if constexpr (KS)
-      ks_part[qbase + ql] =
-          (rsum[KS ? 2 : 0][0][ql] + rsum[KS ? 2 : 0][1][ql]) + (rsum[KS ? 2 : 0][2][ql] + rsum[KS ? 2 : 0][3][ql]);
+      for (int j = 0; j < 4; ++j) dst[nb * 64 + 4 * c + j] = (double)gacc[4 * nb + j][rr];
+    if constexpr (G::HB)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) dst[G::NB * 64 + 2 * c + j] = (double)gacc[4 * G::NB + j][rr];
   }
 }
 
@@ -568,14 +521,15 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
 }
 
 template <int KERN, bool VAL>
-static hipError_t launch_kde_bwd_k(const TileProblem& p, int TB, float L, double* gy, double* rw,
+static hipError_t launch_kde_bwd_k(const TileProblem& p, int64_t dp, float L, double* gy, double* rw,
                                    double* gh, double* ks, hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), b(BWG);
-  switch (TB) {
-    case 2: kde_backward_kernel<KERN, 2, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
-    case 4: kde_backward_kernel<KERN, 4, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
-    case 6: kde_backward_kernel<KERN, 6, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
-    default: kde_backward_kernel<KERN, 8, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+  switch (dp) {
+    case 32: kde_backward_kernel<KERN, 32, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 64: kde_backward_kernel<KERN, 64, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 96: kde_backward_kernel<KERN, 96, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 128: kde_backward_kernel<KERN, 128, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -606,7 +560,6 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, 
                                double* mu, double* gh_per_query) {
   (void)Y;
   const int64_t dp = p.ld_bytes / 4;
-  const int TB = (int)(dp / 16);
   const double log2e = 1.4426950408889634;
   const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
   // layout: gh [splits][qp], rw [splits][qp], ks [splits][qp], ghq [q]
@@ -617,10 +570,10 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, 
   hipError_t e;
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
   if (kern == KERNEL_GAUSSIAN)   // the KDE is the sum of the weights themselves
-    e = launch_kde_bwd_k<KERNEL_GAUSSIAN, false>(p, TB, L, gy_part, rw_part, gh_part, ks_part, s);
+    e = launch_kde_bwd_k<KERNEL_GAUSSIAN, false>(p, dp, L, gy_part, rw_part, gh_part, ks_part, s);
   else
-    e = val ? launch_kde_bwd_k<KERNEL_EXPONENTIAL, true>(p, TB, L, gy_part, rw_part, gh_part, ks_part, s)
-            : launch_kde_bwd_k<KERNEL_EXPONENTIAL, false>(p, TB, L, gy_part, rw_part, gh_part, ks_part, s);
+    e = val ? launch_kde_bwd_k<KERNEL_EXPONENTIAL, true>(p, dp, L, gy_part, rw_part, gh_part, ks_part, s)
+            : launch_kde_bwd_k<KERNEL_EXPONENTIAL, false>(p, dp, L, gy_part, rw_part, gh_part, ks_part, s);
   if (e != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
   // Gaussian: weights K, dh terms K * (-L d^2); exponential: weights K / r, dh terms K r

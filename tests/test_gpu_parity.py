@@ -296,11 +296,13 @@ def test_exact_backward_vs_oracle(dev, kern):
     assert abs(gh - gh_ref) <= 1e-4 * gh_scale
 
 
+@pytest.mark.parametrize("d", [16, 64, 90, 128])
 @pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
-def test_exact_value_and_gradient_in_one_pass(dev, kern):
-    # kde_exact_with_grad: the KDE, its y-gradient and its per-query h-derivative
+def test_exact_value_and_gradient_in_one_pass(dev, kern, d):
+    # kde_exact_with_grad: the KDE, its y-gradient and its per-query h-derivative;
+    # padded widths 32, 64, 96 and 128 (a trailing 32-coordinate block at 32 and 96)
     import paper_2107_02736_amd as dk
-    X, Y = _small(6000, 70, 64, seed=9)
+    X, Y = _small(6000, 70, d, seed=9)
     Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
     h = 6.0
     mu, gy, gh = (t.cpu().numpy() for t in dk.kde_exact_with_grad(Xd, Yd, h, KNAME[kern]))

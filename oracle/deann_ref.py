@@ -35,6 +35,15 @@ Parity status of each function (what pins it in tests/test_oracle_*.py):
   mean_shift pinned: n=1 lands on the point in one step; density never
       decreases along exact Gaussian mean-shift steps.
   bisect_h   pinned: monotonicity of KDE in h and the target tolerance.
+  kmeans_init / kmeans_assign / kmeans_update / ivf_train pinned: Lloyd
+      steps computed by hand on one-dimensional data (an empty cluster,
+      centroid ties), the update equals the mean of the rows, the k-means
+      objective never grows, exact-rational brute force of the assignment.
+  ivf_probe / ivf_knn / deann_estimate_ivf pinned: every cluster inspected or
+      a single cluster gives the exact k-NN (and then DEANN itself),
+      exact-rational brute force on tiny inputs with ties, the fallback when
+      the inspected clusters hold fewer than k rows.
+  recall     pinned: identical sets give 1, disjoint sets 0.
 """
 from __future__ import annotations
 
@@ -476,3 +485,94 @@ def bisect_h(D2: np.ndarray, target: float, kernel: int, stat: str = "mean",
         else:
             hi = mid
     raise RuntimeError("bisection did not converge")
+
+
+# --------------------------------------------------------------------------
+# Inverted-file index: the approximate nearest neighbours of the experiments
+# (Sec. 5).  k-means over the data gives n_l centroids, each row belongs to
+# its closest centroid, and a query inspects every row of the n_q closest
+# centroids.  The estimate of Algorithm 1 stays unbiased for any neighbour
+# set (only the split of X into X1 and X2 changes), so the returned set is
+# used as X1 unchanged.
+#
+# Readings where the paper leaves the index unspecified:
+#   * initial centroids are the rows floor(l n / n_l), l = 0..n_l-1;
+#   * "closest" is the exact order (||c - x||^2, l) with ties towards the
+#     lower centroid, like the k-NN order above;
+#   * a Lloyd step replaces each centroid by the mean of its rows (an FP64
+#     sum rounded once to float32); a centroid without rows stays;
+#   * training runs `iters` Lloyd steps and then assigns every row to the
+#     closest final centroid;
+#   * a query whose n_q inspected clusters hold fewer than k rows falls back
+#     to the exact k nearest rows of all of X.
+# --------------------------------------------------------------------------
+
+def kmeans_init(X: np.ndarray, n_clusters: int) -> np.ndarray:
+    """Initial centroids: the rows floor(l n / n_l) of X, as float32."""
+    n = X.shape[0]
+    rows = [(l * n) // n_clusters for l in range(n_clusters)]
+    return np.asarray(X[rows], dtype=np.float32)
+
+
+def kmeans_assign(X: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """Index of the closest centroid of every row (exact order, ties to the
+    lower centroid)."""
+    return np.asarray([knn(C, x, 1)[0] for x in X], dtype=np.int64)
+
+
+def kmeans_update(X: np.ndarray, assign: np.ndarray, C_prev: np.ndarray) -> np.ndarray:
+    """Lloyd step: each centroid becomes the mean of its rows, summed exactly
+    (math.fsum per coordinate) and divided in FP64, then rounded to float32;
+    a centroid without rows keeps its previous value."""
+    C = np.array(C_prev, dtype=np.float32, copy=True)
+    Xd = np.asarray(X, dtype=np.float64)
+    for l in range(C.shape[0]):
+        rows = np.nonzero(assign == l)[0]
+        if rows.size == 0:
+            continue
+        sums = [math.fsum(Xd[rows, t].tolist()) for t in range(X.shape[1])]
+        C[l] = np.asarray([s / rows.size for s in sums], dtype=np.float64).astype(np.float32)
+    return C
+
+
+def ivf_train(X: np.ndarray, n_clusters: int, iters: int):
+    """(centroids float32 [n_l, d], assignment int64 [n]) after `iters`
+    Lloyd steps from kmeans_init and a final assignment."""
+    C = kmeans_init(X, n_clusters)
+    for _ in range(iters):
+        C = kmeans_update(X, kmeans_assign(X, C), C)
+    return C, kmeans_assign(X, C)
+
+
+def ivf_probe(C: np.ndarray, y: np.ndarray, n_probe: int) -> np.ndarray:
+    """The n_q clusters whose centroids are closest to y, ascending by id."""
+    return knn(C, y, n_probe)
+
+
+def ivf_knn(X: np.ndarray, y: np.ndarray, C: np.ndarray, assign: np.ndarray, n_probe: int,
+            k: int) -> np.ndarray:
+    """The k nearest rows among those of the n_q closest clusters (sorted by
+    index); the exact k-NN of all of X when those clusters hold < k rows."""
+    if k <= 0:
+        return np.empty(0, dtype=np.int64)
+    probes = ivf_probe(C, y, n_probe)
+    rows = np.nonzero(np.isin(assign, probes))[0]
+    if rows.size < k:
+        return knn(X, y, k)
+    # the rows keep ascending order, so the lower position is the lower index
+    return np.sort(rows[knn(X[rows], y, k)])
+
+
+def deann_estimate_ivf(X: np.ndarray, y: np.ndarray, h: float, kernel: int, C: np.ndarray,
+                       assign: np.ndarray, n_probe: int, k: int, m: int, seed: int,
+                       stream: int):
+    """DEANN (Algorithm 1) with the inverted-file neighbours as X1."""
+    nn = ivf_knn(X, y, C, assign, n_probe, k)
+    return deann_estimate(X, y, h, kernel, k, m, seed, stream, nn=nn)
+
+
+def recall(nn_true: np.ndarray, nn_found: np.ndarray) -> float:
+    """|NN_k(q) & NN~_k(q)| / |NN_k(q)| (the recall of Sec. 5)."""
+    if len(nn_true) == 0:
+        return 1.0
+    return len(np.intersect1d(nn_true, nn_found)) / len(nn_true)

@@ -162,6 +162,57 @@ int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, in
                         size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Inverted-file index: the approximate nearest neighbours of the experiments
+ * (Sec. 5).  k-means over the data gives n_clusters centroids (the paper's
+ * n_l); each row belongs to its closest centroid; a query inspects every row
+ * of its n_probe closest centroids (the paper's n_q).  The DEANN estimate of
+ * Algorithm 1 stays unbiased for any neighbour set, so these neighbours
+ * replace the exact ones unchanged.
+ *
+ * ivf_build: Lloyd's k-means.  centroids[n_clusters, d] (float32, output) start
+ *   as the rows floor(l n / n_clusters); each of `iters` steps assigns every row
+ *   to its closest centroid (exact order (||c - x||^2, l), ties to the lower l)
+ *   and replaces each centroid by the mean of its rows (FP64 sum in row order,
+ *   rounded once to float32; a centroid without rows stays).  assign[n] (int32,
+ *   output) is the closest final centroid of every row.
+ *   Requirements: 1 <= n_clusters <= min(n, 8192), 0 <= iters <= 1000, d <= 4096.
+ *
+ * ivf_index_create: lays the rows out by cluster in the caller's index buffer
+ *   (ivf_index_bytes bytes, opaque, device memory): members in row order, each
+ *   cluster padded to whole 128-row tiles, the rows centred and prepared for
+ *   the FP32 tile scan.  assign[n] may come from ivf_build or from anywhere
+ *   else; rows whose id is outside [0, n_clusters) are left out of the index.
+ *   The index stays valid as long as X is unchanged; deann_ivf_query only
+ *   reads it.
+ *
+ * deann_ivf_query: DEANN with the index's neighbours.  For query j: the
+ *   n_probe closest centroids (exact k-NN among the centroids), then the k
+ *   nearest rows among their members (exact order (||x - y||^2, i), found by an
+ *   FP32 MFMA scan of those clusters with certified lower-bound keys and an FP64
+ *   refinement).  When the inspected clusters hold fewer than k rows, the
+ *   exact k nearest rows of all of X are used.  Sampling, the estimate and the
+ *   outputs (out, nn_idx sorted by index, sample_idx) are those of deann_query
+ *   with the same seed and query_offset; deann_query_backward accepts the
+ *   indices unchanged.  centroids and n_clusters must be those the index was
+ *   made with; 1 <= n_probe <= min(n_clusters, 496); k <= 496 or k = n.
+ * ------------------------------------------------------------------------- */
+size_t ivf_build_workspace(int64_t n, int64_t d, int64_t n_clusters);
+int ivf_build(const float* X, int64_t n, int64_t d, int64_t n_clusters, int iters,
+              float* centroids, int32_t* assign, void* ws, size_t ws_bytes, void* stream);
+size_t ivf_index_bytes(int64_t n, int64_t d, int64_t n_clusters);
+size_t ivf_index_create_workspace(int64_t n, int64_t d, int64_t n_clusters);
+int ivf_index_create(const float* X, int64_t n, int64_t d, const int32_t* assign,
+                     int64_t n_clusters, void* index, size_t index_bytes, void* ws,
+                     size_t ws_bytes, void* stream);
+size_t deann_ivf_query_workspace(int64_t n, int64_t q, int64_t d, int64_t n_clusters,
+                                 int64_t n_probe, int64_t k, int64_t m);
+int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                    const void* index, const float* centroids, int64_t n_clusters,
+                    int64_t n_probe, double h, int kernel, int64_t k, int64_t m, uint64_t seed,
+                    uint64_t query_offset, double* out, int32_t* nn_idx, int32_t* sample_idx,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Gaussian mean-shift step (the application the paper cites for density
  * gradients): Y_out[j] = Y[j] + h^2 grad_Y[j] / density[j], i.e. the
  * kernel-weighted mean of the rows when grad_Y and density come from

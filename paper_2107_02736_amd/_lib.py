@@ -22,6 +22,8 @@ EXPORTS = (
     "deann_query_backward_workspace", "deann_query_backward",
     "kde_exact_backward_workspace", "kde_exact_backward",
     "kde_exact_with_grad_workspace", "kde_exact_with_grad", "mean_shift_update",
+    "ivf_build_workspace", "ivf_build", "ivf_index_bytes", "ivf_index_create_workspace",
+    "ivf_index_create", "deann_ivf_query_workspace", "deann_ivf_query",
     "deann_last_error",
     "deann_kernel_timing", "deann_kernel_times",
 )
@@ -82,6 +84,21 @@ def load(path: str = LIB_PATH):
                                         _sz, _vp]
     lib.mean_shift_update.restype = _int
     lib.mean_shift_update.argtypes = [_vp, _vp, _vp, _i64, _i64, _dbl, _vp, _vp]
+    lib.ivf_build_workspace.restype = _sz
+    lib.ivf_build_workspace.argtypes = [_i64, _i64, _i64]
+    lib.ivf_build.restype = _int
+    lib.ivf_build.argtypes = [_vp, _i64, _i64, _i64, _int, _vp, _vp, _vp, _sz, _vp]
+    lib.ivf_index_bytes.restype = _sz
+    lib.ivf_index_bytes.argtypes = [_i64, _i64, _i64]
+    lib.ivf_index_create_workspace.restype = _sz
+    lib.ivf_index_create_workspace.argtypes = [_i64, _i64, _i64]
+    lib.ivf_index_create.restype = _int
+    lib.ivf_index_create.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _sz, _vp, _sz, _vp]
+    lib.deann_ivf_query_workspace.restype = _sz
+    lib.deann_ivf_query_workspace.argtypes = [_i64, _i64, _i64, _i64, _i64, _i64, _i64]
+    lib.deann_ivf_query.restype = _int
+    lib.deann_ivf_query.argtypes = [_vp, _i64, _vp, _i64, _i64, _vp, _vp, _i64, _i64, _dbl, _int,
+                                    _i64, _i64, _u64, _u64, _vp, _vp, _vp, _vp, _sz, _vp]
     lib.deann_kernel_timing.restype = _int
     lib.deann_kernel_timing.argtypes = [_int]
     lib.deann_kernel_times.restype = _int

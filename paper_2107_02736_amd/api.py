@@ -199,3 +199,69 @@ def kernel_times(site: str, max_count: int = 4096) -> list:
     if n < 0:
         _lib.check(_lib.EHIP)
     return [float(buf[i]) for i in range(n)]
+
+
+# ---- inverted-file neighbours (the ANN of the experiments, Sec. 5) ----------------
+def ivf_build(X: torch.Tensor, n_clusters: int, iters: int = 10):
+    """k-means over the rows of X: (centroids float32 [n_clusters, d],
+    assign int32 [n], the closest final centroid of every row)."""
+    if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous float32 [n, d] device tensor")
+    lib = _lib.load()
+    n, d = X.shape
+    dev = X.device
+    C = torch.empty((n_clusters, d), dtype=torch.float32, device=dev)
+    a = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = _workspace(lib.ivf_build_workspace(n, d, n_clusters), dev)
+    _lib.check(lib.ivf_build(X.data_ptr(), n, d, int(n_clusters), int(iters), C.data_ptr(),
+                             a.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)))
+    return C, a
+
+
+class IvfIndex:
+    """Rows of X laid out by cluster (an opaque device buffer) with the
+    centroids they were assigned to."""
+
+    def __init__(self, X: torch.Tensor, centroids: torch.Tensor, assign: torch.Tensor):
+        if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous():
+            raise ValueError("X must be a contiguous float32 [n, d] device tensor")
+        lib = _lib.load()
+        n, d = X.shape
+        dev = X.device
+        self.centroids = centroids.to(device=dev, dtype=torch.float32).contiguous()
+        if self.centroids.dim() != 2 or self.centroids.shape[1] != d:
+            raise ValueError("centroids must be [n_clusters, d]")
+        self.n_clusters = self.centroids.shape[0]
+        self.n, self.d = n, d
+        assign = assign.to(device=dev, dtype=torch.int32).contiguous()
+        if assign.shape != (n,):
+            raise ValueError("assign must be [n]")
+        self.buffer = _workspace(lib.ivf_index_bytes(n, d, self.n_clusters), dev)
+        ws = _workspace(lib.ivf_index_create_workspace(n, d, self.n_clusters), dev)
+        _lib.check(lib.ivf_index_create(X.data_ptr(), n, d, assign.data_ptr(), self.n_clusters,
+                                        self.buffer.data_ptr(), self.buffer.numel(),
+                                        ws.data_ptr(), ws.numel(), _stream(dev)))
+
+
+def deann_ivf_query(X: torch.Tensor, Y: torch.Tensor, index: IvfIndex, n_probe: int, h: float,
+                    k: int, m: int, kernel="gaussian", seed: int = 0, query_offset: int = 0,
+                    return_indices: bool = True):
+    """DEANN with the inverted-file neighbours (the k nearest rows among the
+    n_probe closest clusters): (out float64 [q], nn_idx [q,k], sample_idx [q,m])."""
+    _check_xy(X, Y)
+    if (index.n, index.d) != tuple(X.shape):
+        raise ValueError("the index was made for another X")
+    lib = _lib.load()
+    n, d = X.shape
+    q = Y.shape[0]
+    dev = X.device
+    out = torch.empty(q, dtype=torch.float64, device=dev)
+    nn = torch.empty((q, k), dtype=torch.int32, device=dev) if return_indices else None
+    sm = torch.empty((q, m), dtype=torch.int32, device=dev) if return_indices else None
+    ws = _workspace(lib.deann_ivf_query_workspace(n, q, d, index.n_clusters, n_probe, k, m), dev)
+    _lib.check(lib.deann_ivf_query(
+        X.data_ptr(), n, Y.data_ptr(), q, d, index.buffer.data_ptr(), index.centroids.data_ptr(),
+        index.n_clusters, int(n_probe), float(h), kernel_id(kernel), int(k), int(m), int(seed),
+        int(query_offset), out.data_ptr(), _ptr(nn), _ptr(sm), ws.data_ptr(), ws.numel(),
+        _stream(dev)))
+    return out, nn, sm

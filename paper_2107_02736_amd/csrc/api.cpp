@@ -534,3 +534,333 @@ int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, in
 }
 
 }  // extern "C"
+
+// ---- inverted-file index (Sec. 5) -------------------------------------------------
+namespace {
+
+constexpr int64_t kMaxClusters = 8192;       // cluster counters of one workgroup in LDS
+constexpr int64_t kAssignBatch = 65536;      // rows per nearest-centroid k-NN call
+
+int64_t ivf_cap(int64_t n, int64_t L) { return round_up(n + (BN - 1) * L, BN); }
+
+// Layout of the caller's index buffer.
+struct IvfIndex {
+  int32_t *off, *poff, *ids, *pids, *skipped;
+  float* c;
+  char* Xs;
+  double* xnorm;
+  float *xknorm, *xerr;
+  uint32_t* err_max;
+  int64_t cap, dp, bytes;
+};
+
+IvfIndex carve_index(void* base, int64_t n, int64_t d, int64_t L) {
+  Carve cv(base);
+  IvfIndex x{};
+  x.cap = ivf_cap(n, L);
+  x.dp = padded_d(d, DEANN_FP32);
+  x.off = cv.take<int32_t>(L + 1);
+  x.poff = cv.take<int32_t>(L + 1);
+  x.ids = cv.take<int32_t>(n);
+  x.pids = cv.take<int32_t>(x.cap);
+  x.skipped = cv.take<int32_t>(1);
+  x.c = cv.take<float>(d);
+  x.Xs = cv.take<char>(x.cap * x.dp * 4);
+  x.xnorm = cv.take<double>(x.cap);
+  x.xknorm = cv.take<float>(x.cap);
+  x.xerr = cv.take<float>(x.cap);
+  x.err_max = cv.take<uint32_t>(2);
+  x.bytes = cv.off + kAlign;
+  return x;
+}
+
+struct IvfLayoutWs {
+  int32_t *hist, *count;
+  int64_t bytes;
+};
+
+IvfLayoutWs carve_layout_ws(Carve& cv, int64_t n, int64_t L) {
+  IvfLayoutWs w{};
+  w.hist = cv.take<int32_t>(ivf_hist_blocks(n) * L);
+  w.count = cv.take<int32_t>(L);
+  return w;
+}
+
+struct IvfBuildPlan {
+  void* knn_ws;
+  int64_t knn_bytes;
+  float* C_tmp;
+  IvfLayoutWs lw;
+  int32_t *off, *ids, *skipped;
+  int64_t bytes;
+};
+
+IvfBuildPlan plan_ivf_build(void* ws, int64_t n, int64_t d, int64_t L) {
+  Carve cv(ws);
+  IvfBuildPlan P{};
+  const int64_t qb = n < kAssignBatch ? n : kAssignBatch;
+  P.knn_bytes = plan_deann(nullptr, L, qb, d, 1, DEANN_FP32).bytes;
+  P.knn_ws = cv.take<char>(P.knn_bytes);
+  P.C_tmp = cv.take<float>(L * d);
+  P.lw = carve_layout_ws(cv, n, L);
+  P.off = cv.take<int32_t>(L + 1);
+  P.ids = cv.take<int32_t>(n);
+  P.skipped = cv.take<int32_t>(1);
+  P.bytes = cv.off + kAlign;
+  return P;
+}
+
+// assign[i] = the closest centroid of row i (exact k-NN with k = 1, in batches).
+hipError_t assign_rows(void* knn_ws, const float* X, int64_t n, int64_t d, const float* C,
+                       int64_t L, int32_t* assign, hipStream_t s) {
+  for (int64_t r0 = 0; r0 < n; r0 += kAssignBatch) {
+    const int64_t qb = n - r0 < kAssignBatch ? n - r0 : kAssignBatch;
+    hipError_t e;
+    if (L == 1) {   // the only centroid
+      if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(assign + r0), qb, 0u, s)) != hipSuccess)
+        return e;
+      continue;
+    }
+    DeannPlan P = plan_deann(knn_ws, L, qb, d, 1, DEANN_FP32);
+    P.kb.nn_work = assign + r0;
+    const float* Xb = X + r0 * d;
+    e = run_prep(P.prep, C, L, Xb, qb, d, DEANN_FP32, s);
+    if (e != hipSuccess) return e;
+    TileProblem tp = make_problem(P.prep, L, qb, DEANN_FP32, kKnnSplitTarget);
+    TileProblem tc = make_problem(P.prep, L, qb, DEANN_FP32, kCollectSplitTarget);
+    e = launch_knn(DEANN_FP32, tp, tc, P.kb, C, Xb, d, 1, 1.0, DEANN_GAUSSIAN, nullptr, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+struct IvfCreatePlan {
+  IvfLayoutWs lw;
+  float* Xperm;
+  double* cpart;
+  int64_t bytes;
+};
+
+IvfCreatePlan plan_ivf_create(void* ws, int64_t n, int64_t d, int64_t L) {
+  Carve cv(ws);
+  IvfCreatePlan P{};
+  P.lw = carve_layout_ws(cv, n, L);
+  P.Xperm = cv.take<float>(ivf_cap(n, L) * d);
+  P.cpart = cv.take<double>(kCenterRows * d);
+  P.bytes = cv.off + kAlign;
+  return P;
+}
+
+struct IvfQueryPlan {
+  DeannPlan probe;        // k-NN of the queries among the centroids
+  char* Ys;
+  double* ynorm;
+  float *yknorm, *yerr;
+  uint32_t* err_max;
+  int32_t *pcount, *pfill, *pp, *pair_q, *pair_of;
+  float *Yg, *ygk;
+  KnnBuffers kb;
+  int32_t* nn_internal;
+  int64_t pcap, bytes;
+};
+
+IvfQueryPlan plan_ivf_query(void* ws, int64_t n, int64_t q, int64_t d, int64_t L, int64_t np,
+                            int64_t k) {
+  IvfQueryPlan P{};
+  P.probe = plan_deann(ws, L, q, d, np, DEANN_FP32);
+  Carve cv(ws);
+  cv.off = P.probe.bytes;
+  const int64_t dp = padded_d(d, DEANN_FP32), qp = round_up(q, BQ);
+  P.Ys = cv.take<char>(qp * dp * 4);
+  P.ynorm = cv.take<double>(qp);
+  P.yknorm = cv.take<float>(qp);
+  P.yerr = cv.take<float>(qp);
+  P.err_max = cv.take<uint32_t>(2);
+  P.pcap = round_up(q * np + (BN - 1) * L, BN);
+  P.pcount = cv.take<int32_t>(L);
+  P.pfill = cv.take<int32_t>(L + 1);
+  P.pp = cv.take<int32_t>(L + 1);
+  P.pair_q = cv.take<int32_t>(P.pcap);
+  P.pair_of = cv.take<int32_t>(q * np);
+  P.Yg = cv.take<float>(P.pcap * dp);
+  P.ygk = cv.take<float>(P.pcap);
+  KnnBuffers& b = P.kb;
+  b.K1 = knn_K1(k);
+  b.cap1 = 256;
+  while (b.cap1 < 2 * b.K1 + BN) b.cap1 <<= 1;
+  b.cand = cv.take<uint64_t>(P.pcap * b.cap1);
+  b.cand_cnt = cv.take<int32_t>(P.pcap);
+  P.nn_internal = cv.take<int32_t>(q * (k > 0 ? k : 1));
+  b.z1 = cv.take<double>(q > 0 ? q : 1);
+  b.status = cv.take<int32_t>(q > 0 ? q : 1);
+  b.yerr = P.yerr;
+  P.bytes = cv.off + kAlign;
+  (void)n;
+  return P;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ivf_build_workspace(int64_t n, int64_t d, int64_t n_clusters) {
+  if (n < 1 || d < 1 || n_clusters < 1 || n_clusters > n || n_clusters > kMaxClusters) return 0;
+  return (size_t)plan_ivf_build(nullptr, n, d, n_clusters).bytes;
+}
+
+int ivf_build(const float* X, int64_t n, int64_t d, int64_t n_clusters, int iters,
+              float* centroids, int32_t* assign, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 1 || d < 1) return fail(DEANN_EINVAL, "need n >= 1 and d >= 1");
+  if (n >= (int64_t)1 << 31) return fail(DEANN_EINVAL, "n must be < 2^31");
+  if (n_clusters < 1 || n_clusters > n)
+    return fail(DEANN_EINVAL, "n_clusters must be in [1, n] (got %lld)", (long long)n_clusters);
+  if (n_clusters > kMaxClusters)
+    return fail(DEANN_EUNSUPPORTED, "n_clusters > %lld is not supported", (long long)kMaxClusters);
+  if (iters < 0 || iters > 1000) return fail(DEANN_EINVAL, "iters must be in [0, 1000]");
+  if (d > 4096) return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported");
+  if (!X || !centroids || !assign) return fail(DEANN_EINVAL, "NULL array");
+  const int64_t need = plan_ivf_build(nullptr, n, d, n_clusters).bytes;
+  if (!ws || (int64_t)ws_bytes < need)
+    return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  IvfBuildPlan P = plan_ivf_build(align_ws(ws), n, d, n_clusters);
+  hipError_t e = launch_kmeans_init(X, n, d, n_clusters, centroids, s);
+  for (int it = 0; e == hipSuccess; ++it) {
+    e = assign_rows(P.knn_ws, X, n, d, centroids, n_clusters, assign, s);
+    if (e != hipSuccess || it == iters) break;
+    e = launch_list_layout(assign, n, n_clusters, P.lw.hist, P.lw.count, P.off, nullptr, P.ids,
+                           P.skipped, s);
+    if (e != hipSuccess) break;
+    e = launch_kmeans_mean(X, d, P.ids, P.off, n_clusters, centroids, P.C_tmp, s);
+    if (e != hipSuccess) break;
+    e = hipMemcpyAsync(centroids, P.C_tmp, (size_t)(n_clusters * d) * 4, hipMemcpyDeviceToDevice, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "ivf build");
+  return DEANN_OK;
+}
+
+size_t ivf_index_bytes(int64_t n, int64_t d, int64_t n_clusters) {
+  if (n < 1 || d < 1 || n_clusters < 1 || n_clusters > kMaxClusters) return 0;
+  return (size_t)carve_index(nullptr, n, d, n_clusters).bytes;
+}
+
+size_t ivf_index_create_workspace(int64_t n, int64_t d, int64_t n_clusters) {
+  if (n < 1 || d < 1 || n_clusters < 1 || n_clusters > kMaxClusters) return 0;
+  return (size_t)plan_ivf_create(nullptr, n, d, n_clusters).bytes;
+}
+
+int ivf_index_create(const float* X, int64_t n, int64_t d, const int32_t* assign,
+                     int64_t n_clusters, void* index, size_t index_bytes, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (n < 1 || d < 1) return fail(DEANN_EINVAL, "need n >= 1 and d >= 1");
+  if (n >= (int64_t)1 << 31) return fail(DEANN_EINVAL, "n must be < 2^31");
+  if (n_clusters < 1) return fail(DEANN_EINVAL, "n_clusters must be >= 1");
+  if (n_clusters > kMaxClusters)
+    return fail(DEANN_EUNSUPPORTED, "n_clusters > %lld is not supported", (long long)kMaxClusters);
+  if (d > 4096) return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported");
+  if (!X || !assign || !index) return fail(DEANN_EINVAL, "NULL array");
+  const int64_t need_i = carve_index(nullptr, n, d, n_clusters).bytes;
+  if ((int64_t)index_bytes < need_i)
+    return fail(DEANN_EWORKSPACE, "index buffer of %lld bytes needed", (long long)need_i);
+  const int64_t need = plan_ivf_create(nullptr, n, d, n_clusters).bytes;
+  if (!ws || (int64_t)ws_bytes < need)
+    return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  IvfIndex x = carve_index(align_ws(index), n, d, n_clusters);
+  IvfCreatePlan P = plan_ivf_create(align_ws(ws), n, d, n_clusters);
+  hipError_t e = launch_list_layout(assign, n, n_clusters, P.lw.hist, P.lw.count, x.off, x.poff,
+                                    x.ids, x.skipped, s);
+  if (e == hipSuccess)
+    e = launch_list_tiles(X, d, x.ids, x.off, x.poff, n_clusters, x.cap, x.pids, P.Xperm, s);
+  // the centring of the scan is the mean of the data rows
+  const int64_t R = n < kCenterRows ? n : kCenterRows;
+  if (e == hipSuccess) e = launch_center(X, n, d, P.cpart, R, x.c, s);
+  if (e == hipSuccess) e = launch_fill_u32(x.err_max, 2, 0u, s);
+  if (e == hipSuccess)
+    e = launch_prep_rows_prec(DEANN_FP32, P.Xperm, x.cap, x.cap, d, x.dp, x.c, key_scale(x.dp),
+                              x.Xs, x.xnorm, x.xknorm, x.xerr, x.err_max, s);
+  if (e == hipSuccess) e = launch_empty_row_keys(x.pids, x.poff + n_clusters, x.cap, x.xknorm, s);
+  if (e != hipSuccess) return hip_fail(e, "ivf index");
+  return DEANN_OK;
+}
+
+size_t deann_ivf_query_workspace(int64_t n, int64_t q, int64_t d, int64_t n_clusters,
+                                 int64_t n_probe, int64_t k, int64_t m) {
+  (void)m;
+  if (n < 1 || d < 1 || q < 0 || k < 0 || k > n || n_clusters < 1 || n_probe < 1 ||
+      n_probe > n_clusters)
+    return 0;
+  return (size_t)plan_ivf_query(nullptr, n, q, d, n_clusters, n_probe, k).bytes;
+}
+
+int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                    const void* index, const float* centroids, int64_t n_clusters,
+                    int64_t n_probe, double h, int kernel, int64_t k, int64_t m, uint64_t seed,
+                    uint64_t query_offset, double* out, int32_t* nn_idx, int32_t* sample_idx,
+                    void* ws, size_t ws_bytes, void* stream) {
+  int st = check_common(X, n, Y, q, d, h, kernel);
+  if (st != DEANN_OK) return st;
+  if (k < 0 || k > n) return fail(DEANN_EINVAL, "k must be in [0, n] (got %lld)", (long long)k);
+  if (m < 0) return fail(DEANN_EINVAL, "m must be >= 0 (got %lld)", (long long)m);
+  if (k > kMaxK && k != n)
+    return fail(DEANN_EUNSUPPORTED, "k = %lld: supported are k <= %lld and k = n", (long long)k,
+                (long long)kMaxK);
+  if (d > 4096) return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported");
+  if (n_clusters < 1 || n_clusters > kMaxClusters)
+    return fail(DEANN_EINVAL, "n_clusters must be in [1, %lld]", (long long)kMaxClusters);
+  if (n_probe < 1 || n_probe > n_clusters || n_probe > kMaxK)
+    return fail(DEANN_EINVAL, "n_probe must be in [1, min(n_clusters, %lld)]", (long long)kMaxK);
+  if (!index || !centroids) return fail(DEANN_EINVAL, "NULL index or centroids");
+  if (q == 0) return DEANN_OK;
+  if (!out) return fail(DEANN_EINVAL, "out is NULL");
+  const int64_t need = plan_ivf_query(nullptr, n, q, d, n_clusters, n_probe, k).bytes;
+  if (!ws || (int64_t)ws_bytes < need)
+    return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  IvfQueryPlan P = plan_ivf_query(align_ws(ws), n, q, d, n_clusters, n_probe, k);
+  // the index buffer is read only
+  IvfIndex x = carve_index(align_ws(const_cast<void*>(index)), n, d, n_clusters);
+  P.kb.nn_work = nn_idx ? nn_idx : P.nn_internal;
+  P.kb.xerr_max = x.err_max;
+  hipError_t e = hipSuccess;
+  if (k == n) {
+    e = launch_knn_all(X, Y, n, q, d, h, kernel, P.kb.nn_work, P.kb.z1, s);
+  } else if (k > 0) {
+    // clusters to inspect: the n_probe closest centroids (exact k-NN)
+    int32_t* probe = P.probe.nn_internal;
+    P.probe.kb.nn_work = probe;
+    e = run_prep(P.probe.prep, centroids, n_clusters, Y, q, d, DEANN_FP32, s);
+    if (e == hipSuccess) {
+      TileProblem tp = make_problem(P.probe.prep, n_clusters, q, DEANN_FP32, kKnnSplitTarget);
+      TileProblem tc = make_problem(P.probe.prep, n_clusters, q, DEANN_FP32, kCollectSplitTarget);
+      if (n_probe == n_clusters)
+        e = launch_knn_all(centroids, Y, n_clusters, q, d, h, kernel, probe, P.kb.z1, s);
+      else
+        e = launch_knn(DEANN_FP32, tp, tc, P.probe.kb, centroids, Y, d, n_probe, h, kernel,
+                       nullptr, s);
+    }
+    // the queries in the index's centring, then in (cluster, query) pair order
+    const int64_t dp = x.dp, qp = round_up(q, BQ);
+    if (e == hipSuccess) e = launch_fill_u32(P.err_max, 2, 0u, s);
+    if (e == hipSuccess)
+      e = launch_prep_rows_prec(DEANN_FP32, Y, q, qp, d, dp, x.c, key_scale(dp), P.Ys, P.ynorm,
+                                P.yknorm, P.yerr, P.err_max + 1, s);
+    if (e == hipSuccess)
+      e = launch_pairs(probe, q, n_probe, n_clusters, P.pcount, P.pfill, P.pp, P.pair_q,
+                       P.pair_of, P.pcap, reinterpret_cast<const float*>(P.Ys), P.yknorm, dp,
+                       P.Yg, P.ygk, s);
+    if (e == hipSuccess) {
+      IvfTiles t{reinterpret_cast<const char*>(P.Yg), x.Xs, dp * 4, (int)(dp * 4 / CHUNK_BYTES),
+                 P.ygk, x.xknorm, P.pp, x.poff, n_clusters};
+      IvfRefine v{probe, n_probe, P.pair_of, x.off, x.ids, x.pids};
+      e = launch_ivf_knn(t, P.pcap, P.kb, v, X, Y, n, q, d, k, h, kernel, nullptr, s);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "ivf neighbours");
+  e = launch_sample(X, Y, n, q, d, h, kernel, k, m, seed, query_offset, 0, 0, 0, P.kb.nn_work,
+                    P.kb.z1, out, sample_idx, s);
+  if (e != hipSuccess) return hip_fail(e, "sample");
+  return DEANN_OK;
+}
+
+}  // extern "C"

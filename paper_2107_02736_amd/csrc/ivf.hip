@@ -1,0 +1,281 @@
+// Inverted-file index (the approximate nearest neighbours of the experiments,
+// Sec. 5): k-means training, the list layout of the data rows, and the
+// (cluster, query) pairs of a query batch.  The tile sweep over the inspected
+// clusters and the refinement live with the other k-NN kernels.
+//
+// Clusters are stored as contiguous row ranges.  The stable order inside a
+// cluster is the row index, obtained by a block histogram, a per-cluster scan
+// over blocks and a block-local stable rank, so every layout is deterministic.
+// In the tile layout each cluster is padded with empty rows to a multiple of
+// the 128-row tile; an empty row has index -1.
+#include "common.h"
+#include "kernels.h"
+
+namespace deann {
+
+constexpr int IVF_HIST_ROWS = 1024;   // rows per histogram block
+constexpr int IVF_SCAN_THREADS = 1024;
+
+// Centroid l <- row floor(l n / n_l).
+__global__ void kmeans_init_kernel(const float* __restrict__ X, int64_t n, int64_t d,
+                                   int64_t L, float* __restrict__ C) {
+  const int64_t l = blockIdx.x;
+  const int64_t row = l * n / L;
+  for (int64_t t = threadIdx.x; t < d; t += blockDim.x) C[l * d + t] = X[row * d + t];
+}
+
+// hist[b][l] = rows of block b in cluster l; out-of-range ids are counted in
+// *skipped and left out.
+__global__ void __launch_bounds__(WG)
+list_hist_kernel(const int32_t* __restrict__ a, int64_t n, int64_t L, int32_t* __restrict__ hist,
+                 int32_t* __restrict__ skipped) {
+  extern __shared__ int32_t cnt[];   // [L]
+  for (int64_t l = threadIdx.x; l < L; l += WG) cnt[l] = 0;
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * IVF_HIST_ROWS;
+  int bad = 0;
+  for (int64_t i = r0 + threadIdx.x; i < n && i < r0 + IVF_HIST_ROWS; i += WG) {
+    const int32_t l = a[i];
+    if (l >= 0 && l < L) atomicAdd(&cnt[l], 1);
+    else ++bad;
+  }
+  if (bad) atomicAdd(skipped, bad);
+  __syncthreads();
+  for (int64_t l = threadIdx.x; l < L; l += WG) hist[(int64_t)blockIdx.x * L + l] = cnt[l];
+}
+
+// Exclusive prefix of hist over blocks, per cluster; count[l] = cluster size.
+__global__ void list_colscan_kernel(int32_t* __restrict__ hist, int64_t B, int64_t L,
+                                    int32_t* __restrict__ count) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= L) return;
+  int32_t run = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    const int32_t v = hist[b * L + l];
+    hist[b * L + l] = run;
+    run += v;
+  }
+  count[l] = run;
+}
+
+// off = exclusive prefix of count (off[L] = total); poff the same over the
+// sizes rounded up to `pad` (one workgroup).
+__global__ void __launch_bounds__(IVF_SCAN_THREADS)
+list_offsets_kernel(const int32_t* __restrict__ count, int64_t L, int pad,
+                    int32_t* __restrict__ off, int32_t* __restrict__ poff) {
+  __shared__ int64_t s_a[IVF_SCAN_THREADS], s_b[IVF_SCAN_THREADS];
+  const int64_t per = (L + IVF_SCAN_THREADS - 1) / IVF_SCAN_THREADS;
+  const int64_t l0 = threadIdx.x * per, l1 = l0 + per < L ? l0 + per : L;
+  int64_t a = 0, b = 0;
+  for (int64_t l = l0; l < l1; ++l) {
+    a += count[l];
+    b += (count[l] + pad - 1) / pad * pad;
+  }
+  s_a[threadIdx.x] = a;
+  s_b[threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {   // serial scan of the 1024 partial sums
+    int64_t ra = 0, rb = 0;
+    for (int i = 0; i < IVF_SCAN_THREADS; ++i) {
+      const int64_t va = s_a[i], vb = s_b[i];
+      s_a[i] = ra;
+      s_b[i] = rb;
+      ra += va;
+      rb += vb;
+    }
+    off[L] = (int32_t)ra;
+    if (poff) poff[L] = (int32_t)rb;
+  }
+  __syncthreads();
+  a = s_a[threadIdx.x];
+  b = s_b[threadIdx.x];
+  for (int64_t l = l0; l < l1; ++l) {
+    off[l] = (int32_t)a;
+    if (poff) poff[l] = (int32_t)b;
+    a += count[l];
+    b += (count[l] + pad - 1) / pad * pad;
+  }
+}
+
+// ids[off[l] + rank] = i, where rank orders the rows of cluster l by index:
+// rows of earlier blocks come first (hist prefix), inside a block the rows are
+// taken in rounds of WG in index order.
+__global__ void __launch_bounds__(WG)
+list_scatter_kernel(const int32_t* __restrict__ a, int64_t n, int64_t L,
+                    const int32_t* __restrict__ hist, const int32_t* __restrict__ off,
+                    int32_t* __restrict__ ids) {
+  extern __shared__ int32_t base[];   // [L] next slot of each cluster in this block
+  __shared__ int32_t lab[WG];
+  for (int64_t l = threadIdx.x; l < L; l += WG)
+    base[l] = off[l] + hist[(int64_t)blockIdx.x * L + l];
+  const int64_t r0 = (int64_t)blockIdx.x * IVF_HIST_ROWS;
+  for (int64_t s = r0; s < n && s < r0 + IVF_HIST_ROWS; s += WG) {
+    const int64_t i = s + threadIdx.x;
+    const bool in = i < n && i < r0 + IVF_HIST_ROWS;
+    int32_t l = in ? a[i] : -1;
+    if (l >= L) l = -1;
+    lab[threadIdx.x] = l;
+    __syncthreads();   // also publishes base[] on the first round
+    int rank = 0;
+    if (l >= 0)
+      for (int j = 0; j < (int)threadIdx.x; ++j) rank += lab[j] == l;
+    const int32_t slot = l >= 0 ? base[l] + rank : 0;
+    __syncthreads();
+    if (l >= 0) {
+      ids[slot] = (int32_t)i;
+      atomicAdd(&base[l], 1);
+    }
+    __syncthreads();
+  }
+}
+
+// Lloyd update: centroid l <- mean of its rows (FP64 sum in row order, one
+// rounding to float32); a cluster without rows keeps its centroid.
+__global__ void __launch_bounds__(WG)
+kmeans_mean_kernel(const float* __restrict__ X, int64_t d, const int32_t* __restrict__ ids,
+                   const int32_t* __restrict__ off, const float* __restrict__ C_prev,
+                   float* __restrict__ C_new) {
+  const int64_t l = blockIdx.x;
+  const int32_t j0 = off[l], j1 = off[l + 1];
+  for (int64_t t = threadIdx.x; t < d; t += WG) {
+    double s = 0.0;
+    for (int32_t j = j0; j < j1; ++j) s += (double)X[(int64_t)ids[j] * d + t];
+    C_new[l * d + t] = j1 > j0 ? (float)(s / (double)(j1 - j0)) : C_prev[l * d + t];
+  }
+}
+
+// Padded row ids of the tile layout: cluster l occupies rows
+// [poff[l], poff[l+1]), the first off[l+1]-off[l] of them real.
+__global__ void list_pad_ids_kernel(const int32_t* __restrict__ ids, const int32_t* __restrict__ off,
+                                    const int32_t* __restrict__ poff, int32_t* __restrict__ pids) {
+  const int64_t l = blockIdx.x;
+  const int32_t c = off[l + 1] - off[l];
+  for (int32_t j = threadIdx.x; j < poff[l + 1] - poff[l]; j += blockDim.x)
+    pids[poff[l] + j] = j < c ? ids[off[l] + j] : -1;
+}
+
+// out[r] = X[pids[r]] (zeros for empty rows); rows in [0, rows).
+__global__ void gather_rows_kernel(const float* __restrict__ X, int64_t d,
+                                   const int32_t* __restrict__ pids, const int32_t* __restrict__ nrows,
+                                   int64_t cap, float* __restrict__ out) {
+  const int64_t r = blockIdx.x;
+  if (r >= cap) return;
+  const int32_t src = r < *nrows ? pids[r] : -1;
+  for (int64_t t = threadIdx.x; t < d; t += blockDim.x)
+    out[r * d + t] = src >= 0 ? X[(int64_t)src * d + t] : 0.f;
+}
+
+// Empty rows get an infinite key norm so that no tile key selects them.
+__global__ void empty_row_keys_kernel(const int32_t* __restrict__ pids,
+                                      const int32_t* __restrict__ nrows, int64_t cap,
+                                      float* __restrict__ xknorm) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= cap) return;
+  if (r >= *nrows || pids[r] < 0) xknorm[r] = __builtin_inff();
+}
+
+// ---- query batch: (cluster, query) pairs ------------------------------------
+__global__ void pair_count_kernel(const int32_t* __restrict__ probe, int64_t total,
+                                  int32_t* __restrict__ pcount) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) atomicAdd(&pcount[probe[i]], 1);
+}
+
+// Pair rows of cluster l: [pp[l], pp[l] + pcount[l]), padded to the tile.
+__global__ void pair_scatter_kernel(const int32_t* __restrict__ probe, int64_t total, int64_t np,
+                                    const int32_t* __restrict__ pp, int32_t* __restrict__ pfill,
+                                    int32_t* __restrict__ pair_q, int32_t* __restrict__ pair_of) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int32_t l = probe[i];
+  const int32_t row = pp[l] + atomicAdd(&pfill[l], 1);
+  pair_q[row] = (int32_t)(i / np);
+  pair_of[i] = row;
+}
+
+// Prepared query rows and key norms in pair order (zeros for padding rows).
+__global__ void pair_gather_kernel(const float* __restrict__ Ys, const float* __restrict__ yknorm,
+                                   int64_t dp, const int32_t* __restrict__ pair_q, int64_t cap,
+                                   float* __restrict__ Yg, float* __restrict__ ygk) {
+  const int64_t r = blockIdx.x;
+  if (r >= cap) return;
+  const int32_t qi = pair_q[r];
+  for (int64_t t = threadIdx.x; t < dp; t += blockDim.x)
+    Yg[r * dp + t] = qi >= 0 ? Ys[(int64_t)qi * dp + t] : 0.f;
+  if (threadIdx.x == 0) ygk[r] = qi >= 0 ? yknorm[qi] : 0.f;
+}
+
+// ---- host launches -------------------------------------------------------------
+int64_t ivf_hist_blocks(int64_t n) { return ceil_div(n, IVF_HIST_ROWS); }
+
+hipError_t launch_kmeans_init(const float* X, int64_t n, int64_t d, int64_t L, float* C,
+                              hipStream_t s) {
+  kmeans_init_kernel<<<dim3((unsigned)L), dim3(128), 0, s>>>(X, n, d, L, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_layout(const int32_t* a, int64_t n, int64_t L, int32_t* hist,
+                              int32_t* count, int32_t* off, int32_t* poff, int32_t* ids,
+                              int32_t* skipped, hipStream_t s) {
+  const int64_t B = ivf_hist_blocks(n);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(skipped), 1, 0u, s);
+  if (e != hipSuccess) return e;
+  const size_t sm = (size_t)L * 4;
+  list_hist_kernel<<<dim3((unsigned)B), dim3(WG), sm, s>>>(a, n, L, hist, skipped);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  list_colscan_kernel<<<dim3((unsigned)ceil_div(L, WG)), dim3(WG), 0, s>>>(hist, B, L, count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  list_offsets_kernel<<<dim3(1), dim3(IVF_SCAN_THREADS), 0, s>>>(count, L, BN, off, poff);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  list_scatter_kernel<<<dim3((unsigned)B), dim3(WG), sm, s>>>(a, n, L, hist, off, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_kmeans_mean(const float* X, int64_t d, const int32_t* ids, const int32_t* off,
+                              int64_t L, const float* C_prev, float* C_new, hipStream_t s) {
+  kmeans_mean_kernel<<<dim3((unsigned)L), dim3(WG), 0, s>>>(X, d, ids, off, C_prev, C_new);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_tiles(const float* X, int64_t d, const int32_t* ids, const int32_t* off,
+                             const int32_t* poff, int64_t L, int64_t cap, int32_t* pids,
+                             float* Xperm, hipStream_t s) {
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(pids), cap, 0xffffffffu, s);
+  if (e != hipSuccess) return e;
+  list_pad_ids_kernel<<<dim3((unsigned)L), dim3(WG), 0, s>>>(ids, off, poff, pids);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  gather_rows_kernel<<<dim3((unsigned)cap), dim3(128), 0, s>>>(X, d, pids, poff + L, cap, Xperm);
+  return hipGetLastError();
+}
+
+hipError_t launch_empty_row_keys(const int32_t* pids, const int32_t* nrows, int64_t cap,
+                                 float* xknorm, hipStream_t s) {
+  empty_row_keys_kernel<<<dim3((unsigned)ceil_div(cap, WG)), dim3(WG), 0, s>>>(pids, nrows, cap,
+                                                                            xknorm);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t np, int64_t L, int32_t* pcount,
+                        int32_t* pfill, int32_t* pp, int32_t* pair_q, int32_t* pair_of,
+                        int64_t cap, const float* Ys, const float* yknorm, int64_t dp,
+                        float* Yg, float* ygk, hipStream_t s) {
+  const int64_t total = q * np;
+  hipError_t e;
+  if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pcount), L, 0u, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pfill), L, 0u, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pair_q), cap, 0xffffffffu, s)) != hipSuccess)
+    return e;
+  const unsigned g = (unsigned)ceil_div(total, WG);
+  pair_count_kernel<<<dim3(g), dim3(WG), 0, s>>>(probe, total, pcount);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  list_offsets_kernel<<<dim3(1), dim3(IVF_SCAN_THREADS), 0, s>>>(pcount, L, BN, pfill, pp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // pfill held the unpadded prefix; reset it to count the slots
+  if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pfill), L, 0u, s)) != hipSuccess) return e;
+  pair_scatter_kernel<<<dim3(g), dim3(WG), 0, s>>>(probe, total, np, pp, pfill, pair_q, pair_of);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  pair_gather_kernel<<<dim3((unsigned)cap), dim3(128), 0, s>>>(Ys, yknorm, dp, pair_q, cap, Yg, ygk);
+  return hipGetLastError();
+}
+
+}  // namespace deann

@@ -66,6 +66,55 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
 hipError_t launch_knn_all(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                           double h, int kern, int32_t* nn, double* z1, hipStream_t s);
 
+// ---- inverted-file neighbours --------------------------------------------------
+int64_t ivf_hist_blocks(int64_t n);
+hipError_t launch_kmeans_init(const float* X, int64_t n, int64_t d, int64_t L, float* C,
+                              hipStream_t s);
+// Cluster ranges off[L+1] (and poff[L+1] padded to the tile), member rows in
+// index order ids[off[L]]; hist [ivf_hist_blocks(n)][L] is scratch.
+hipError_t launch_list_layout(const int32_t* a, int64_t n, int64_t L, int32_t* hist,
+                              int32_t* count, int32_t* off, int32_t* poff, int32_t* ids,
+                              int32_t* skipped, hipStream_t s);
+hipError_t launch_kmeans_mean(const float* X, int64_t d, const int32_t* ids, const int32_t* off,
+                              int64_t L, const float* C_prev, float* C_new, hipStream_t s);
+// Tile layout: pids[cap] (-1 for empty rows) and the float32 rows Xperm[cap][d].
+hipError_t launch_list_tiles(const float* X, int64_t d, const int32_t* ids, const int32_t* off,
+                             const int32_t* poff, int64_t L, int64_t cap, int32_t* pids,
+                             float* Xperm, hipStream_t s);
+hipError_t launch_empty_row_keys(const int32_t* pids, const int32_t* nrows, int64_t cap,
+                                 float* xknorm, hipStream_t s);
+// (cluster, query) pair rows of a batch: pp[L+1] (pfill needs L+1 entries).
+hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t np, int64_t L, int32_t* pcount,
+                        int32_t* pfill, int32_t* pp, int32_t* pair_q, int32_t* pair_of,
+                        int64_t cap, const float* Ys, const float* yknorm, int64_t dp,
+                        float* Yg, float* ygk, hipStream_t s);
+
+struct IvfTiles {
+  const char* Ys;          // prepared query rows in pair order [prow_cap][dp]
+  const char* Xs;          // prepared index rows in tile layout [xrows][dp]
+  int64_t ld_bytes;
+  int nchunks;
+  const float* yknorm;     // [prow_cap]
+  const float* xknorm;     // [xrows], infinite for empty rows
+  const int32_t* pp;       // [L+1] pair rows of each cluster (multiples of 128)
+  const int32_t* poff;     // [L+1] index rows of each cluster (multiples of 128)
+  int64_t L;
+};
+
+struct IvfRefine {
+  const int32_t* probe;    // [q][np] inspected clusters
+  int64_t np;
+  const int32_t* pair_of;  // [q][np] pair row of each inspected cluster
+  const int32_t* off;      // [L+1] cluster ranges of ids
+  const int32_t* ids;      // member rows in cluster order
+  const int32_t* pids;     // [xrows] row of each tile-layout row (-1: empty)
+};
+
+hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers& b,
+                          const IvfRefine& v, const float* X, const float* Y, int64_t n,
+                          int64_t q, int64_t d, int64_t k, double h, int kern, int32_t* nn_out,
+                          hipStream_t s);
+
 // ---- sampler, gather and combine --------------------------------------------
 hipError_t launch_sample(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                          double h, int kern, int64_t k, int64_t m, uint64_t seed,

@@ -850,3 +850,265 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
 }
 
 }  // namespace deann
+
+namespace deann {
+
+// ---------------------------------------------------------------------------
+// Inverted-file neighbours (Sec. 5): the k nearest rows among the clusters a
+// query inspects.  Pair row r of a batch is one (cluster, query) pair; the pair
+// rows of cluster l form the range [pp[l], pp[l+1]) (a multiple of the tile),
+// so one workgroup sweeps one query tile of one cluster over that cluster's
+// rows [poff[l], poff[l+1]) of the index, keeping per pair the K1 smallest
+// lower-bound keys exactly as the FP32 scan keeps them per (split, query).
+// The refinement then merges the lists of the query's pairs; keys are exact
+// lower bounds, so the certificate of the FP32 scan carries over unchanged.
+// ---------------------------------------------------------------------------
+template <int EPL>   // list capacity = 64 * EPL
+__global__ void __launch_bounds__(WG, 2)
+ivf_scan_kernel(IvfTiles v, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt, int K1) {
+  constexpr int cap1 = 64 * EPL;
+  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
+  __shared__ float thr[BQ];
+  __shared__ float yks[BQ];
+  __shared__ int cnt[BQ];
+  const int64_t row0 = (int64_t)blockIdx.x * BQ;
+  if (row0 >= v.pp[v.L]) return;
+  // the cluster whose pair rows hold row0: pp[l] <= row0 < pp[l + 1]
+  int64_t lo = 0, hi = v.L;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (v.pp[mid] <= row0) lo = mid; else hi = mid;
+  }
+  const int64_t t0 = v.poff[lo] / BN, t1 = v.poff[lo + 1] / BN;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wq = wave >> 1, wn = wave & 1;
+  if (threadIdx.x < BQ) {
+    thr[threadIdx.x] = __builtin_inff();
+    cnt[threadIdx.x] = 0;
+    yks[threadIdx.x] = v.yknorm[row0 + threadIdx.x];
+  }
+  uint64_t* lists = cand + row0 * (int64_t)cap1;
+  const char* yq = v.Ys + row0 * v.ld_bytes;
+  const int limit = cap1 - BN;
+  __syncthreads();
+  StreamState st;
+  if (t0 < t1) stream_start(st, yq, v.Xs, v.ld_bytes, t0);
+  __shared__ float xks[2][BN];
+  float xk_reg = (threadIdx.x < BN && t0 < t1) ? v.xknorm[t0 * BN + threadIdx.x] : 0.f;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int nb = (int)((t - t0) & 1);
+    if (threadIdx.x < BN) {
+      xks[nb][threadIdx.x] = xk_reg;
+      if (t + 1 < t1) xk_reg = v.xknorm[(t + 1) * BN + threadIdx.x];
+    }
+    f32x4 acc[4][4];
+    stream_tile<float>(acc, st, yq, v.Xs, v.ld_bytes, v.nchunks, t, t1, lds, wq, wn, lane);
+    float xk[4];   // empty rows carry an infinite key norm
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xk[j] = xks[nb][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ql = wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const float yk = yks[ql], th = thr[ql];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]);
+          if (key < th) {
+            const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
+            const int slot = atomicAdd(&cnt[ql], 1);
+            lists[(int64_t)ql * cap1 + slot] =
+                ((uint64_t)float_key(key) << 32) | (uint64_t)(uint32_t)col;
+          }
+        }
+      }
+    __syncthreads();
+    compact_lists<EPL>(lists, cnt, thr, limit, K1, wave, lane);
+  }
+  compact_lists<EPL>(lists, cnt, thr, K1, K1, wave, lane);
+  if (threadIdx.x < BQ) cand_cnt[row0 + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// Rows the query's clusters hold (clusters probed by one query are distinct).
+__device__ __forceinline__ int64_t ivf_rows(const IvfRefine& v, int64_t qi) {
+  int64_t tot = 0;
+  for (int64_t p = 0; p < v.np; ++p) {
+    const int32_t l = v.probe[qi * v.np + p];
+    tot += v.off[l + 1] - v.off[l];
+  }
+  return tot;
+}
+
+// status: 0 certified, 2 exact scan of the inspected clusters, 3 exact scan
+// of all rows (the inspected clusters hold fewer than k rows).
+__global__ void __launch_bounds__(WG)
+ivf_refine_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restrict__ nn_out) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  uint64_t* buf = reinterpret_cast<uint64_t*>(smem);                  // SORT_CAP
+  uint64_t* dkey = buf + SORT_CAP;                                     // K_MAX
+  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + K_MAX);         // K_MAX
+  uint32_t* tmp = didx + K_MAX;                                        // K_MAX
+  double* red = reinterpret_cast<double*>(tmp + K_MAX);               // WG
+  float* ys = reinterpret_cast<float*>(red + WG);                      // d
+  __shared__ int fill_s;
+  const int64_t qi = blockIdx.x;
+  const int K1 = (int)b.K1;
+  const int k = (int)a.k;
+  const int64_t rows = ivf_rows(v, qi);
+  if (rows < k) {
+    if (threadIdx.x == 0) b.status[qi] = 3;
+    return;
+  }
+  for (int64_t t = threadIdx.x; t < a.d; t += WG) ys[t] = a.Y[qi * a.d + t];
+  if (threadIdx.x == 0) fill_s = 0;
+  __syncthreads();
+  int64_t seen = 0;
+  for (int64_t p = 0; p < v.np; ++p) {
+    const int32_t row = v.pair_of[qi * v.np + p];
+    const int c = b.cand_cnt[row];
+    const uint64_t* lst = b.cand + (int64_t)row * b.cap1;
+    seen += c;
+    __syncthreads();
+    for (int i = threadIdx.x; i < c; i += WG) buf[atomicAdd(&fill_s, 1)] = lst[i];
+    __syncthreads();
+    const bool flush = (fill_s + K1 > SORT_CAP) || (p + 1 == v.np);
+    if (flush && fill_s >= K1) {
+      const int F = fill_s;
+      const int N = next_pow2(F);
+      for (int i = F + threadIdx.x; i < N; i += WG) buf[i] = ~0ull;
+      __syncthreads();
+      block_sort_u64(buf, N);
+      if (threadIdx.x == 0) fill_s = K1;
+      __syncthreads();
+    }
+  }
+  const int C = fill_s;
+  const bool complete = (seen == rows) && (C == rows);
+  const float Tkey = (C == K1) ? key_float((uint32_t)(buf[K1 - 1] >> 32)) : __builtin_inff();
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  for (int c = g; c < C; c += WG / 16) {
+    // a real row (empty rows have infinite keys and are never listed)
+    const int32_t pid = v.pids[(uint32_t)(buf[c] & 0xffffffffu)];
+    const int32_t id = pid >= 0 ? pid : 0;
+    const double d2 = group16_d2(a.X, id, a.d, ys, l16);
+    if (l16 == 0) { dkey[c] = __builtin_bit_cast(uint64_t, d2); didx[c] = (uint32_t)id; }
+  }
+  const int N = next_pow2(C > 1 ? C : 2);
+  for (int i = C + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
+  __syncthreads();
+  block_sort_pairs(dkey, didx, N);
+  fix_boundary(dkey, didx, C, k, a.X, a.d, ys);
+  bool ok = complete;
+  if (!ok && C >= k) {
+    const double Dk = __builtin_bit_cast(double, dkey[k - 1]) * (1.0 + fp64_rel(a.d));
+    const double E = (double)__builtin_bit_cast(float, *b.xerr_max);
+    const double ey = (double)b.yerr[qi];
+    const double lhs = sqrt((double)fmaxf(Tkey, 0.f)) - E - ey;
+    ok = lhs > 0.0 && lhs * lhs > Dk * (1.0 + 1e-14);
+  }
+  if (!ok) {
+    if (threadIdx.x == 0) b.status[qi] = 2;
+    return;
+  }
+  if (threadIdx.x == 0) b.status[qi] = 0;
+  emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
+                  nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
+}
+
+// Exact FP64 scan for status 2 (rows of the inspected clusters) and status 3
+// (all rows), one workgroup per query, as knn_exhaustive_kernel.
+__global__ void __launch_bounds__(WG)
+ivf_exhaustive_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restrict__ nn_out) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  uint64_t* dkey = reinterpret_cast<uint64_t*>(smem);
+  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + SORT_CAP);
+  uint32_t* tmp = didx + SORT_CAP;
+  double* red = reinterpret_cast<double*>(tmp + K_MAX);
+  float* ys = reinterpret_cast<float*>(red + WG);
+  int64_t* cum = reinterpret_cast<int64_t*>(ys + ((a.d + 3) & ~3ll));   // [np + 1]
+  __shared__ int fill_s;
+  const int64_t qi = blockIdx.x;
+  const int st = b.status[qi];
+  if (st != 2 && st != 3) return;
+  const int k = (int)a.k;
+  for (int64_t t = threadIdx.x; t < a.d; t += WG) ys[t] = a.Y[qi * a.d + t];
+  if (threadIdx.x == 0) {
+    fill_s = 0;
+    int64_t c = 0;
+    for (int64_t p = 0; p < v.np; ++p) {
+      cum[p] = c;
+      const int32_t l = v.probe[qi * v.np + p];
+      c += v.off[l + 1] - v.off[l];
+    }
+    cum[v.np] = c;
+  }
+  __syncthreads();
+  const int64_t R = st == 3 ? a.n : cum[v.np];
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  const int kkeep = k + 32 < SORT_CAP / 2 ? k + 32 : SORT_CAP / 2;
+  const int chunk = SORT_CAP - kkeep;
+  uint64_t kth_key = ~0ull;
+  uint32_t kth_idx = 0xffffffffu;
+  for (int64_t r0 = 0; r0 < R; r0 += chunk) {
+    const int64_t r1 = r0 + chunk < R ? r0 + chunk : R;
+    for (int64_t r = r0 + g; r < r1; r += WG / 16) {
+      int64_t id = r;
+      if (st == 2) {   // r-th row of the inspected clusters
+        int64_t lo = 0, hi = v.np;   // cum[lo] <= r < cum[hi]
+        while (hi - lo > 1) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (cum[mid] <= r) lo = mid; else hi = mid;
+        }
+        const int32_t l = v.probe[qi * v.np + lo];
+        id = v.ids[v.off[l] + (r - cum[lo])];
+      }
+      const double d2 = group16_d2(a.X, id, a.d, ys, l16);
+      const uint64_t kb = __builtin_bit_cast(uint64_t, d2);
+      if (l16 == 0 && (kb < kth_key || (kb == kth_key && (uint32_t)id < kth_idx))) {
+        const int slot = atomicAdd(&fill_s, 1);
+        dkey[slot] = kb;
+        didx[slot] = (uint32_t)id;
+      }
+    }
+    __syncthreads();
+    const int F = fill_s;
+    for (int i = F + threadIdx.x; i < SORT_CAP; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
+    __syncthreads();
+    block_sort_pairs(dkey, didx, SORT_CAP);
+    if (F >= kkeep) { kth_key = dkey[kkeep - 1]; kth_idx = didx[kkeep - 1]; }
+    __syncthreads();
+    if (threadIdx.x == 0) fill_s = F < kkeep ? F : kkeep;
+    __syncthreads();
+  }
+  fix_boundary(dkey, didx, fill_s, k, a.X, a.d, ys);
+  if (threadIdx.x == 0) b.status[qi] = 0;
+  emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
+                  nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
+}
+
+hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers& b,
+                          const IvfRefine& v, const float* X, const float* Y, int64_t n,
+                          int64_t q, int64_t d, int64_t k, double h, int kern, int32_t* nn_out,
+                          hipStream_t s) {
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(b.status), q, 0u, s);
+  if (e != hipSuccess) return e;
+  const dim3 g((unsigned)(prow_cap / BQ)), blk(WG);
+  switch (b.cap1) {
+    case 256: ivf_scan_kernel<4><<<g, blk, 0, s>>>(t, b.cand, b.cand_cnt, (int)b.K1); break;
+    case 512: ivf_scan_kernel<8><<<g, blk, 0, s>>>(t, b.cand, b.cand_cnt, (int)b.K1); break;
+    case 1024: ivf_scan_kernel<16><<<g, blk, 0, s>>>(t, b.cand, b.cand_cnt, (int)b.K1); break;
+    default: ivf_scan_kernel<32><<<g, blk, 0, s>>>(t, b.cand, b.cand_cnt, (int)b.K1); break;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  RefineArgs a{X, Y, n, q, d, k, 0, 0, h, kern, 0};
+  const size_t sm1 = SORT_CAP * 8 + K_MAX * (8 + 4 + 4) + WG * 8 + d * 4;
+  ivf_refine_kernel<<<dim3((unsigned)q), dim3(WG), sm1, s>>>(a, b, v, nn_out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + ((d + 3) & ~3ll) * 4 +
+                     (v.np + 1) * 8;
+  ivf_exhaustive_kernel<<<dim3((unsigned)q), dim3(WG), sm2, s>>>(a, b, v, nn_out);
+  return hipGetLastError();
+}
+
+}  // namespace deann

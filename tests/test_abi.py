@@ -86,3 +86,46 @@ def test_workspace_sizes_grow(lib):
     assert 0 < a < b
     assert lib.deann_query_workspace(10_000, 1_000, 16, 50, 500, 1) > 0
     assert lib.kde_exact_workspace(0, 1, 1, 0) == 0
+
+
+def _ivfq(lib, n=1000, q=4, d=3, L=10, np_=2, h=1.0, k=5, m=10, index=FAKE, C=FAKE, ws=FAKE,
+          wsb=1 << 34):
+    return lib.deann_ivf_query(FAKE, n, FAKE, q, d, index, C, L, np_, h, 0, k, m, 0, 0, FAKE,
+                               FAKE, FAKE, ws, wsb, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(L=0), _lib.EINVAL), (dict(L=9000), _lib.EINVAL), (dict(np_=0), _lib.EINVAL),
+    (dict(np_=11), _lib.EINVAL), (dict(L=600, np_=500), _lib.EINVAL), (dict(k=-1), _lib.EINVAL),
+    (dict(k=1001), _lib.EINVAL), (dict(k=600), _lib.EUNSUPPORTED), (dict(m=-1), _lib.EINVAL),
+    (dict(index=None), _lib.EINVAL), (dict(C=None), _lib.EINVAL), (dict(h=-1.0), _lib.EINVAL),
+    (dict(ws=None), _lib.EWORKSPACE), (dict(wsb=64), _lib.EWORKSPACE),
+])
+def test_ivf_query_validation(lib, kw, status):
+    assert _ivfq(lib, **kw) == status
+    assert lib.deann_last_error().decode()
+
+
+def test_ivf_build_and_index_validation(lib):
+    def build(n=1000, d=3, L=10, iters=5, ws=FAKE, wsb=1 << 34):
+        return lib.ivf_build(FAKE, n, d, L, iters, FAKE, FAKE, ws, wsb, None)
+    assert build(L=0) == _lib.EINVAL
+    assert build(L=1001) == _lib.EINVAL
+    assert build(n=100000, L=9000) == _lib.EUNSUPPORTED
+    assert build(iters=-1) == _lib.EINVAL
+    assert build(d=5000) == _lib.EUNSUPPORTED
+    assert build(ws=None) == _lib.EWORKSPACE
+
+    def create(n=1000, d=3, L=10, index=FAKE, ib=1 << 34, ws=FAKE, wsb=1 << 34):
+        return lib.ivf_index_create(FAKE, n, d, FAKE, L, index, ib, ws, wsb, None)
+    assert create(L=0) == _lib.EINVAL
+    assert create(L=9000) == _lib.EUNSUPPORTED
+    assert create(index=None) == _lib.EINVAL
+    assert create(ib=64) == _lib.EWORKSPACE
+    assert create(wsb=64) == _lib.EWORKSPACE
+    # sizes: positive, growing with n and with the cluster count
+    assert lib.ivf_index_bytes(1000, 3, 10) > 0
+    assert lib.ivf_index_bytes(2000, 3, 10) > lib.ivf_index_bytes(1000, 3, 10)
+    assert lib.ivf_index_bytes(1000, 3, 20) > lib.ivf_index_bytes(1000, 3, 10)
+    assert lib.ivf_build_workspace(1000, 3, 0) == 0
+    assert lib.deann_ivf_query_workspace(1000, 4, 3, 10, 11, 5, 10) == 0

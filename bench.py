@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--sweep-km", action="store_true",
                     help="only run DEANN (BF16 scan + refinement) over a (k, m) grid and print its "
                          "error against the exact KDE and its queries/s")
+    ap.add_argument("--sweep-ivf", action="store_true",
+                    help="print recall, error and queries/s of the inverted-file DEANN over "
+                         "cluster counts and inspected clusters, then exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (counter calibration)")
     return ap.parse_args()
@@ -104,6 +107,12 @@ def bandwidth(workload, kernel):
         return float(json.load(f)[workload][kernel]["h"])
 
 
+def ivf_config(n):
+    """Inverted-file parameters: about sqrt(n) clusters, 16 inspected, 4 Lloyd steps."""
+    n_clusters = max(1, min(8192, int(round(math.sqrt(n)))))
+    return n_clusters, min(16, n_clusters), 4
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -127,6 +136,9 @@ def main():
     K_NN, M_SAMPLES = KM[args.workload]
     if args.sweep_km:
         sweep_km(args, X, Y, h)
+        return
+    if args.sweep_ivf:
+        sweep_ivf(args, X, Y, h, K_NN, M_SAMPLES)
         return
     n, d = X.shape
     q = Y.shape[0]
@@ -222,6 +234,30 @@ def main():
     torch.cuda.synchronize()
     ms_deannp = a.elapsed_time(b) / reps
 
+    # DEANN with the inverted-file neighbours of the experiments (Sec. 5), not
+    # part of the step: index build, query time, recall against the exact k-NN
+    n_clusters, n_probe, ivf_iters = ivf_config(n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C_ivf, a_ivf = dk.ivf_build(Xd, n_clusters, iters=ivf_iters)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    index = dk.IvfIndex(Xd, C_ivf, a_ivf)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    esti, nni, _ = dk.deann_ivf_query(Xd, Yd, index, n_probe, h, K_NN, M_SAMPLES, KERNEL, seed=0)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        esti, nni, _ = dk.deann_ivf_query(Xd, Yd, index, n_probe, h, K_NN, M_SAMPLES, KERNEL,
+                                          seed=0)
+    b.record()
+    torch.cuda.synchronize()
+    ms_ivf = a.elapsed_time(b) / reps
+    nn_h, nni_h = nn.cpu().numpy(), nni.cpu().numpy()
+    recall = np.array([np.intersect1d(nn_h[j], nni_h[j]).size / max(K_NN, 1) for j in range(q)])
+    del index, C_ivf, a_ivf
+
     # exact KDE with BF16 operands (not part of the step): speed and its error
     # against the FP32 exact path (itself within about 1e-6 of the FP64 oracle)
     mu16 = dk.kde_exact(Xd, Yd, h, KERNEL, "bf16")
@@ -243,6 +279,8 @@ def main():
     rel_exact16 = np.abs(mu16_h[keep] - mu_h[keep]) / mu_h[keep]
     estp_h = estp.cpu().numpy()
     rel_deannp = np.abs(estp_h[keep] - mu_h[keep]) / mu_h[keep]
+    esti_h = esti.cpu().numpy()
+    rel_ivf = np.abs(esti_h[keep] - mu_h[keep]) / mu_h[keep]
 
     flops_exact = 2.0 * n * d * q
     tile_avg_ms = float(np.mean(tile_ms))
@@ -293,6 +331,7 @@ def main():
             "deann_bf16_refine": q / (comp_ms["deann_bf16"] * 1e-3),
             "deann_fp32": q / (ms_deann32 * 1e-3),
             "deann_permuted_bf16_refine": q / (ms_deannp * 1e-3),
+            "deann_ivf_fp32": q / (ms_ivf * 1e-3),
             "exact_kde_and_grad_fp32": (q / (comp_ms["exact_kde_and_grad_fp32"] * 1e-3)
                                         if fused else None),
             "kde_exact_fp32": q / (ms_exact_fwd * 1e-3),
@@ -309,6 +348,14 @@ def main():
             "deann_permuted_vs_exact_mean_rel": float(rel_deannp.mean()) if keep.any() else None,
             "queries_below_1e-16": int((~keep).sum()),
         },
+        "ivf": {"n_clusters": n_clusters, "n_probe": n_probe, "iters": ivf_iters,
+                "build_s": t1 - t0, "index_s": t2 - t1, "ms": ms_ivf,
+                "queries_per_s": q / (ms_ivf * 1e-3),
+                "recall_mean": float(recall.mean()), "recall_min": float(recall.min()),
+                "vs_exact_mean_rel": float(rel_ivf.mean()) if keep.any() else None,
+                "note": "DEANN with the k nearest rows among the n_probe closest of n_clusters "
+                        "k-means clusters (FP32 scan of those clusters); recall against the "
+                        "exact k-NN of the step"},
     }
 
     if not args.no_cpu_baseline:
@@ -408,6 +455,67 @@ def sweep_km(args, X, Y, h):
     print(json.dumps({"sweep": "deann_km", "workload": args.workload, "kernel": KERNEL, "h": h,
                       "scan": "bf16", "queries_excluded_below_1e-16": int((~keep).sum()),
                       "rows": rows}), flush=True)
+
+
+def sweep_ivf(args, X, Y, h, k_nn, m_samples):
+    """Inverted-file DEANN over cluster counts n_l and inspected clusters n_q:
+    build time, queries/s, recall against the exact k-NN and error against the
+    exact KDE, one JSON line; the exact-k-NN DEANN (BF16 scan) for reference."""
+    import numpy as np
+    import torch
+
+    import paper_2107_02736_amd as dk
+    dev = torch.device("cuda:0")
+    Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+    n, q = X.shape[0], Y.shape[0]
+    mu = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32").cpu().numpy()
+    keep = mu >= 1e-16
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(3):
+            r = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 3, r
+
+    ms, (est, nn, _) = timed(lambda: dk.deann_query(Xd, Yd, h, k_nn, m_samples, KERNEL, seed=0,
+                                                    precision="bf16"))
+    nn = nn.cpu().numpy()
+    e = np.abs(est.cpu().numpy()[keep] - mu[keep]) / mu[keep]
+    ref = {"queries_per_s": q / (ms * 1e-3), "ms": ms, "mean_rel_err": float(e.mean())}
+    rows = []
+    for n_clusters in (256, 1024, 4096):
+        if n_clusters > n:
+            continue
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C, a = dk.ivf_build(Xd, n_clusters, iters=4)
+        index = dk.IvfIndex(Xd, C, a)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        for n_probe in (1, 2, 4, 8, 16, 32, 64):
+            if n_probe > n_clusters:
+                continue
+            ms, (est, nni, _) = timed(lambda: dk.deann_ivf_query(
+                Xd, Yd, index, n_probe, h, k_nn, m_samples, KERNEL, seed=0))
+            nni = nni.cpu().numpy()
+            rec = np.array([np.intersect1d(nn[j], nni[j]).size / max(k_nn, 1) for j in range(q)])
+            e = np.abs(est.cpu().numpy()[keep] - mu[keep]) / mu[keep]
+            rows.append({"n_clusters": n_clusters, "n_probe": n_probe, "build_s": build_s,
+                         "queries_per_s": q / (ms * 1e-3), "ms": ms,
+                         "recall_mean": float(rec.mean()), "recall_min": float(rec.min()),
+                         "mean_rel_err": float(e.mean())})
+            print(f"# n_l={n_clusters} n_q={n_probe}: {ms:.2f} ms, recall {rec.mean():.3f}, "
+                  f"mean rel err {e.mean():.3e}", file=sys.stderr, flush=True)
+        del index, C, a
+    print(json.dumps({"sweep": "deann_ivf", "workload": args.workload, "kernel": KERNEL, "h": h,
+                      "k": k_nn, "m": m_samples, "exact_knn_bf16": ref,
+                      "queries_excluded_below_1e-16": int((~keep).sum()), "rows": rows}),
+          flush=True)
 
 
 def _oracle_shard(workload, h, k_nn, m_samples, exact_bwd, queries):

@@ -185,12 +185,15 @@ int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, in
  *   The index stays valid as long as X is unchanged; deann_ivf_query only
  *   reads it.
  *
- * deann_ivf_query: DEANN with the index's neighbours.  For query j: the
- *   n_probe closest centroids (exact k-NN among the centroids), then the k
- *   nearest rows among their members (exact order (||x - y||^2, i), found by an
- *   FP32 MFMA scan of those clusters with certified lower-bound keys and an FP64
- *   refinement).  When the inspected clusters hold fewer than k rows, the
- *   exact k nearest rows of all of X are used.  Sampling, the estimate and the
+ * deann_ivf_query: DEANN with the index's neighbours.  For query j: its
+ *   clusters in the exact order (||c - y||^2, l); it inspects the n_probe
+ *   closest, and while these hold fewer than k rows the next closest as well,
+ *   up to min(n_clusters, max(2 n_probe, n_probe + 64), 496) clusters in all;
+ *   the neighbours are the k nearest rows among their members (exact order
+ *   (||x - y||^2, i), found by an FP32 MFMA scan of those clusters with
+ *   certified lower-bound keys and an FP64 refinement).  If even the most
+ *   clusters allowed hold fewer than k rows, the exact k nearest rows of all
+ *   of X are used.  Sampling, the estimate and the
  *   outputs (out, nn_idx sorted by index, sample_idx) are those of deann_query
  *   with the same seed and query_offset; deann_query_backward accepts the
  *   indices unchanged.  centroids and n_clusters must be those the index was

@@ -39,10 +39,12 @@ Parity status of each function (what pins it in tests/test_oracle_*.py):
       steps computed by hand on one-dimensional data (an empty cluster,
       centroid ties), the update equals the mean of the rows, the k-means
       objective never grows, exact-rational brute force of the assignment.
-  ivf_probe / ivf_knn / deann_estimate_ivf pinned: every cluster inspected or
-      a single cluster gives the exact k-NN (and then DEANN itself),
-      exact-rational brute force on tiny inputs with ties, the fallback when
-      the inspected clusters hold fewer than k rows.
+  cluster_order / ivf_probe / ivf_knn / deann_estimate_ivf pinned: every
+      cluster inspected or a single cluster gives the exact k-NN (and then
+      DEANN itself), exact-rational brute force on tiny inputs with ties
+      (including the extension to further clusters and the cap), the
+      extension and the fallback on hand-made clusters, the order against an
+      exact-rational sort.
   recall     pinned: identical sets give 1, disjoint sets 0.
 """
 from __future__ import annotations
@@ -503,8 +505,11 @@ def bisect_h(D2: np.ndarray, target: float, kernel: int, stat: str = "mean",
 #     sum rounded once to float32); a centroid without rows stays;
 #   * training runs `iters` Lloyd steps and then assigns every row to the
 #     closest final centroid;
-#   * a query whose n_q inspected clusters hold fewer than k rows falls back
-#     to the exact k nearest rows of all of X.
+#   * a query whose n_q closest clusters hold fewer than k rows inspects the
+#     next closest clusters too, one at a time, until they hold at least k
+#     rows, but never more than probe_cap(n_l, n_q) = min(n_l, max(2 n_q,
+#     n_q + 64), 496) clusters in all; if even those hold fewer than k rows,
+#     the exact k nearest rows of all of X are used.
 # --------------------------------------------------------------------------
 
 def kmeans_init(X: np.ndarray, n_clusters: int) -> np.ndarray:
@@ -544,18 +549,54 @@ def ivf_train(X: np.ndarray, n_clusters: int, iters: int):
     return C, kmeans_assign(X, C)
 
 
-def ivf_probe(C: np.ndarray, y: np.ndarray, n_probe: int) -> np.ndarray:
-    """The n_q clusters whose centroids are closest to y, ascending by id."""
-    return knn(C, y, n_probe)
+def probe_cap(n_clusters: int, n_probe: int) -> int:
+    """Most clusters one query may inspect."""
+    return min(n_clusters, max(2 * n_probe, n_probe + 64), 496)
+
+
+def cluster_order(C: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Every cluster id in the exact order (||c_l - y||^2, l): an FP64 sort,
+    with runs of values too close for FP64 to decide re-sorted exactly."""
+    L, d = C.shape
+    d2 = sq_dists(C, y)
+    order = list(np.lexsort((np.arange(L), d2)))
+    rel = 4.0 * (d + 2) * 2.0 ** -53
+    i = 0
+    while i < L:
+        j = i
+        while j + 1 < L and d2[order[j + 1]] <= d2[order[j]] * (1.0 + 2.0 * rel) + 1e-300:
+            j += 1
+        if j > i:
+            order[i:j + 1] = sorted(order[i:j + 1], key=lambda l: (_exact_sq_dist(C[l], y), l))
+        i = j + 1
+    return np.asarray(order, dtype=np.int64)
+
+
+def ivf_probe(C: np.ndarray, y: np.ndarray, n_probe: int, sizes: np.ndarray | None = None,
+              k: int = 0) -> np.ndarray:
+    """The clusters a query inspects, ascending by id: the n_q closest, and
+    with cluster sizes given, the next closest too while they hold fewer than
+    k rows (at most probe_cap clusters).  Empty when even those hold fewer
+    than k rows (the caller then uses the exact k-NN)."""
+    order = cluster_order(C, y)
+    p = n_probe
+    if sizes is not None:
+        cap = probe_cap(C.shape[0], n_probe)
+        while p < cap and int(sizes[order[:p]].sum()) < k:
+            p += 1
+        if int(sizes[order[:p]].sum()) < k:
+            return np.empty(0, dtype=np.int64)
+    return np.sort(order[:p])
 
 
 def ivf_knn(X: np.ndarray, y: np.ndarray, C: np.ndarray, assign: np.ndarray, n_probe: int,
             k: int) -> np.ndarray:
-    """The k nearest rows among those of the n_q closest clusters (sorted by
-    index); the exact k-NN of all of X when those clusters hold < k rows."""
+    """The k nearest rows among those of the inspected clusters (sorted by
+    index); the exact k-NN of all of X when those hold fewer than k rows."""
     if k <= 0:
         return np.empty(0, dtype=np.int64)
-    probes = ivf_probe(C, y, n_probe)
+    sizes = np.bincount(assign[(assign >= 0) & (assign < C.shape[0])], minlength=C.shape[0])
+    probes = ivf_probe(C, y, n_probe, sizes, k)
     rows = np.nonzero(np.isin(assign, probes))[0]
     if rows.size < k:
         return knn(X, y, k)

@@ -543,6 +543,14 @@ constexpr int64_t kAssignBatch = 65536;      // rows per nearest-centroid k-NN c
 
 int64_t ivf_cap(int64_t n, int64_t L) { return round_up(n + (BN - 1) * L, BN); }
 
+// Most clusters one query inspects (n_probe, extended while they hold < k rows).
+int64_t ivf_probe_cap(int64_t L, int64_t n_probe) {
+  int64_t c = 2 * n_probe > n_probe + 64 ? 2 * n_probe : n_probe + 64;
+  if (c > L) c = L;
+  if (c > kMaxK) c = kMaxK;
+  return c;
+}
+
 // Layout of the caller's index buffer.
 struct IvfIndex {
   int32_t *off, *poff, *ids, *pids, *skipped;
@@ -653,6 +661,8 @@ IvfCreatePlan plan_ivf_create(void* ws, int64_t n, int64_t d, int64_t L) {
 
 struct IvfQueryPlan {
   DeannPlan probe;        // k-NN of the queries among the centroids
+  int32_t *order, *np_q;  // inspected clusters [q][kp] and their count [q]
+  int64_t kp;
   char* Ys;
   double* ynorm;
   float *yknorm, *yerr;
@@ -667,21 +677,24 @@ struct IvfQueryPlan {
 IvfQueryPlan plan_ivf_query(void* ws, int64_t n, int64_t q, int64_t d, int64_t L, int64_t np,
                             int64_t k) {
   IvfQueryPlan P{};
-  P.probe = plan_deann(ws, L, q, d, np, DEANN_FP32);
+  P.kp = ivf_probe_cap(L, np);
+  P.probe = plan_deann(ws, L, q, d, P.kp, DEANN_FP32);
   Carve cv(ws);
   cv.off = P.probe.bytes;
   const int64_t dp = padded_d(d, DEANN_FP32), qp = round_up(q, BQ);
+  P.order = cv.take<int32_t>(q * P.kp);
+  P.np_q = cv.take<int32_t>(q > 0 ? q : 1);
   P.Ys = cv.take<char>(qp * dp * 4);
   P.ynorm = cv.take<double>(qp);
   P.yknorm = cv.take<float>(qp);
   P.yerr = cv.take<float>(qp);
   P.err_max = cv.take<uint32_t>(2);
-  P.pcap = round_up(q * np + (BN - 1) * L, BN);
+  P.pcap = round_up(q * P.kp + (BN - 1) * L, BN);
   P.pcount = cv.take<int32_t>(L);
   P.pfill = cv.take<int32_t>(L + 1);
   P.pp = cv.take<int32_t>(L + 1);
   P.pair_q = cv.take<int32_t>(P.pcap);
-  P.pair_of = cv.take<int32_t>(q * np);
+  P.pair_of = cv.take<int32_t>(q * P.kp);
   P.Yg = cv.take<float>(P.pcap * dp);
   P.ygk = cv.take<float>(P.pcap);
   KnnBuffers& b = P.kb;
@@ -826,19 +839,25 @@ int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_
   if (k == n) {
     e = launch_knn_all(X, Y, n, q, d, h, kernel, P.kb.nn_work, P.kb.z1, s);
   } else if (k > 0) {
-    // clusters to inspect: the n_probe closest centroids (exact k-NN)
-    int32_t* probe = P.probe.nn_internal;
-    P.probe.kb.nn_work = probe;
+    // clusters to inspect: the kp closest centroids (exact k-NN), ordered by
+    // distance; the query takes the shortest prefix of at least n_probe of
+    // them that holds k rows
+    int32_t* cand = P.probe.nn_internal;
+    P.probe.kb.nn_work = cand;
     e = run_prep(P.probe.prep, centroids, n_clusters, Y, q, d, DEANN_FP32, s);
     if (e == hipSuccess) {
       TileProblem tp = make_problem(P.probe.prep, n_clusters, q, DEANN_FP32, kKnnSplitTarget);
       TileProblem tc = make_problem(P.probe.prep, n_clusters, q, DEANN_FP32, kCollectSplitTarget);
-      if (n_probe == n_clusters)
-        e = launch_knn_all(centroids, Y, n_clusters, q, d, h, kernel, probe, P.kb.z1, s);
+      if (P.kp == n_clusters)
+        e = launch_knn_all(centroids, Y, n_clusters, q, d, h, kernel, cand, P.kb.z1, s);
       else
-        e = launch_knn(DEANN_FP32, tp, tc, P.probe.kb, centroids, Y, d, n_probe, h, kernel,
+        e = launch_knn(DEANN_FP32, tp, tc, P.probe.kb, centroids, Y, d, P.kp, h, kernel,
                        nullptr, s);
     }
+    if (e == hipSuccess)
+      e = launch_probe_order(centroids, Y, q, d, cand, P.kp, x.off, n_probe, k, P.order, P.np_q,
+                             s);
+    const int32_t* probe = P.order;
     // the queries in the index's centring, then in (cluster, query) pair order
     const int64_t dp = x.dp, qp = round_up(q, BQ);
     if (e == hipSuccess) e = launch_fill_u32(P.err_max, 2, 0u, s);
@@ -846,13 +865,13 @@ int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_
       e = launch_prep_rows_prec(DEANN_FP32, Y, q, qp, d, dp, x.c, key_scale(dp), P.Ys, P.ynorm,
                                 P.yknorm, P.yerr, P.err_max + 1, s);
     if (e == hipSuccess)
-      e = launch_pairs(probe, q, n_probe, n_clusters, P.pcount, P.pfill, P.pp, P.pair_q,
+      e = launch_pairs(probe, q, P.kp, P.np_q, n_clusters, P.pcount, P.pfill, P.pp, P.pair_q,
                        P.pair_of, P.pcap, reinterpret_cast<const float*>(P.Ys), P.yknorm, dp,
                        P.Yg, P.ygk, s);
     if (e == hipSuccess) {
       IvfTiles t{reinterpret_cast<const char*>(P.Yg), x.Xs, dp * 4, (int)(dp * 4 / CHUNK_BYTES),
                  P.ygk, x.xknorm, P.pp, x.poff, n_clusters};
-      IvfRefine v{probe, n_probe, P.pair_of, x.off, x.ids, x.pids};
+      IvfRefine v{probe, P.kp, P.np_q, P.pair_of, x.off, x.ids, x.pids};
       e = launch_ivf_knn(t, P.pcap, P.kb, v, X, Y, n, q, d, k, h, kernel, nullptr, s);
     }
   }

@@ -175,21 +175,23 @@ __global__ void empty_row_keys_kernel(const int32_t* __restrict__ pids,
 }
 
 // ---- query batch: (cluster, query) pairs ------------------------------------
-__global__ void pair_count_kernel(const int32_t* __restrict__ probe, int64_t total,
-                                  int32_t* __restrict__ pcount) {
+// probe[q][kp]: inspected clusters of each query, the first np_q[q] valid.
+__global__ void pair_count_kernel(const int32_t* __restrict__ probe, int64_t total, int64_t kp,
+                                  const int32_t* __restrict__ np_q, int32_t* __restrict__ pcount) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < total) atomicAdd(&pcount[probe[i]], 1);
+  if (i < total && i % kp < np_q[i / kp]) atomicAdd(&pcount[probe[i]], 1);
 }
 
 // Pair rows of cluster l: [pp[l], pp[l] + pcount[l]), padded to the tile.
-__global__ void pair_scatter_kernel(const int32_t* __restrict__ probe, int64_t total, int64_t np,
-                                    const int32_t* __restrict__ pp, int32_t* __restrict__ pfill,
-                                    int32_t* __restrict__ pair_q, int32_t* __restrict__ pair_of) {
+__global__ void pair_scatter_kernel(const int32_t* __restrict__ probe, int64_t total, int64_t kp,
+                                    const int32_t* __restrict__ np_q, const int32_t* __restrict__ pp,
+                                    int32_t* __restrict__ pfill, int32_t* __restrict__ pair_q,
+                                    int32_t* __restrict__ pair_of) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
+  if (i >= total || i % kp >= np_q[i / kp]) return;
   const int32_t l = probe[i];
   const int32_t row = pp[l] + atomicAdd(&pfill[l], 1);
-  pair_q[row] = (int32_t)(i / np);
+  pair_q[row] = (int32_t)(i / kp);
   pair_of[i] = row;
 }
 
@@ -255,24 +257,25 @@ hipError_t launch_empty_row_keys(const int32_t* pids, const int32_t* nrows, int6
   return hipGetLastError();
 }
 
-hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t np, int64_t L, int32_t* pcount,
-                        int32_t* pfill, int32_t* pp, int32_t* pair_q, int32_t* pair_of,
-                        int64_t cap, const float* Ys, const float* yknorm, int64_t dp,
-                        float* Yg, float* ygk, hipStream_t s) {
-  const int64_t total = q * np;
+hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t kp, const int32_t* np_q,
+                        int64_t L, int32_t* pcount, int32_t* pfill, int32_t* pp, int32_t* pair_q,
+                        int32_t* pair_of, int64_t cap, const float* Ys, const float* yknorm,
+                        int64_t dp, float* Yg, float* ygk, hipStream_t s) {
+  const int64_t total = q * kp;
   hipError_t e;
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pcount), L, 0u, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pfill), L, 0u, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pair_q), cap, 0xffffffffu, s)) != hipSuccess)
     return e;
   const unsigned g = (unsigned)ceil_div(total, WG);
-  pair_count_kernel<<<dim3(g), dim3(WG), 0, s>>>(probe, total, pcount);
+  pair_count_kernel<<<dim3(g), dim3(WG), 0, s>>>(probe, total, kp, np_q, pcount);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   list_offsets_kernel<<<dim3(1), dim3(IVF_SCAN_THREADS), 0, s>>>(pcount, L, BN, pfill, pp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // pfill held the unpadded prefix; reset it to count the slots
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pfill), L, 0u, s)) != hipSuccess) return e;
-  pair_scatter_kernel<<<dim3(g), dim3(WG), 0, s>>>(probe, total, np, pp, pfill, pair_q, pair_of);
+  pair_scatter_kernel<<<dim3(g), dim3(WG), 0, s>>>(probe, total, kp, np_q, pp, pfill, pair_q,
+                                                   pair_of);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   pair_gather_kernel<<<dim3((unsigned)cap), dim3(128), 0, s>>>(Ys, yknorm, dp, pair_q, cap, Yg, ygk);
   return hipGetLastError();

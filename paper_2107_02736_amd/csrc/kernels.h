@@ -83,11 +83,12 @@ hipError_t launch_list_tiles(const float* X, int64_t d, const int32_t* ids, cons
                              float* Xperm, hipStream_t s);
 hipError_t launch_empty_row_keys(const int32_t* pids, const int32_t* nrows, int64_t cap,
                                  float* xknorm, hipStream_t s);
-// (cluster, query) pair rows of a batch: pp[L+1] (pfill needs L+1 entries).
-hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t np, int64_t L, int32_t* pcount,
-                        int32_t* pfill, int32_t* pp, int32_t* pair_q, int32_t* pair_of,
-                        int64_t cap, const float* Ys, const float* yknorm, int64_t dp,
-                        float* Yg, float* ygk, hipStream_t s);
+// (cluster, query) pair rows of a batch: pp[L+1] (pfill needs L+1 entries);
+// probe[q][kp] holds the inspected clusters, the first np_q[q] of them valid.
+hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t kp, const int32_t* np_q,
+                        int64_t L, int32_t* pcount, int32_t* pfill, int32_t* pp, int32_t* pair_q,
+                        int32_t* pair_of, int64_t cap, const float* Ys, const float* yknorm,
+                        int64_t dp, float* Yg, float* ygk, hipStream_t s);
 
 struct IvfTiles {
   const char* Ys;          // prepared query rows in pair order [prow_cap][dp]
@@ -102,13 +103,19 @@ struct IvfTiles {
 };
 
 struct IvfRefine {
-  const int32_t* probe;    // [q][np] inspected clusters
-  int64_t np;
-  const int32_t* pair_of;  // [q][np] pair row of each inspected cluster
+  const int32_t* probe;    // [q][kp] inspected clusters
+  int64_t kp;
+  const int32_t* np_q;     // [q] inspected clusters of each query (0: exact scan of all rows)
+  const int32_t* pair_of;  // [q][kp] pair row of each inspected cluster
   const int32_t* off;      // [L+1] cluster ranges of ids
   const int32_t* ids;      // member rows in cluster order
   const int32_t* pids;     // [xrows] row of each tile-layout row (-1: empty)
 };
+
+// Inspected clusters of each query (see probe_order_kernel); order[q][kp].
+hipError_t launch_probe_order(const float* C, const float* Y, int64_t q, int64_t d,
+                              const int32_t* cand, int64_t kp, const int32_t* off, int64_t n_probe,
+                              int64_t k, int32_t* order, int32_t* np_q, hipStream_t s);
 
 hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers& b,
                           const IvfRefine& v, const float* X, const float* Y, int64_t n,

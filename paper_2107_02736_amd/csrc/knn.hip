@@ -687,6 +687,39 @@ knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
 // ---------------------------------------------------------------------------
 // 4. exhaustive exact scan for the rare overflow (one workgroup per query)
 // ---------------------------------------------------------------------------
+constexpr int EXH_CHUNK = 512;   // rows examined between checks of the candidate buffer
+
+// The k + 32 smallest (FP64 d^2 bits, index) pairs seen so far, in LDS.  Rows
+// below the current (k+32)-th pair are appended; the buffer is sorted and cut
+// back only when another chunk could overflow it (and after the last chunk),
+// so once the cut-off is tight almost every row is a compare and nothing else.
+struct ExhaustiveTop {
+  int kkeep;
+  uint64_t kth_key = ~0ull;
+  uint32_t kth_idx = 0xffffffffu;
+  __device__ explicit ExhaustiveTop(int k) : kkeep(k + 32 < SORT_CAP / 2 ? k + 32 : SORT_CAP / 2) {}
+  __device__ void offer(uint64_t kb, uint32_t id, uint64_t* dkey, uint32_t* didx, int* fill) {
+    if (kb < kth_key || (kb == kth_key && id < kth_idx)) {
+      const int slot = atomicAdd(fill, 1);
+      dkey[slot] = kb;
+      didx[slot] = id;
+    }
+  }
+  // whole block; `last`: after the final chunk (leaves the buffer sorted)
+  __device__ void settle(uint64_t* dkey, uint32_t* didx, int* fill, bool last) {
+    __syncthreads();
+    const int F = *fill;
+    if (F <= SORT_CAP - EXH_CHUNK && !last) return;   // uniform: F read after the barrier
+    const int N = next_pow2(F > 1 ? F : 2);
+    for (int i = F + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
+    __syncthreads();
+    block_sort_pairs(dkey, didx, N);
+    if (F >= kkeep) { kth_key = dkey[kkeep - 1]; kth_idx = didx[kkeep - 1]; }
+    __syncthreads();
+    if (threadIdx.x == 0) *fill = F < kkeep ? F : kkeep;
+    __syncthreads();
+  }
+};
 __global__ void __launch_bounds__(WG)
 knn_exhaustive_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -703,31 +736,14 @@ knn_exhaustive_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) 
   if (threadIdx.x == 0) fill_s = 0;
   __syncthreads();
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
-  // keep a margin beyond k so that near ties at the k-th place can be re-ordered
-  const int kkeep = k + 32 < SORT_CAP / 2 ? k + 32 : SORT_CAP / 2;
-  const int chunk = SORT_CAP - kkeep;        // rows examined between sorts
-  uint64_t kth_key = ~0ull;
-  uint32_t kth_idx = 0xffffffffu;
-  for (int64_t r0 = 0; r0 < a.n; r0 += chunk) {
-    const int64_t r1 = r0 + chunk < a.n ? r0 + chunk : a.n;
+  ExhaustiveTop top(k);
+  for (int64_t r0 = 0; r0 < a.n; r0 += EXH_CHUNK) {
+    const int64_t r1 = r0 + EXH_CHUNK < a.n ? r0 + EXH_CHUNK : a.n;
     for (int64_t r = r0 + g; r < r1; r += WG / 16) {
       const double d2 = group16_d2(a.X, r, a.d, ys, l16);
-      const uint64_t kb = __builtin_bit_cast(uint64_t, d2);
-      if (l16 == 0 && (kb < kth_key || (kb == kth_key && (uint32_t)r < kth_idx))) {
-        const int slot = atomicAdd(&fill_s, 1);
-        dkey[slot] = kb;
-        didx[slot] = (uint32_t)r;
-      }
+      if (l16 == 0) top.offer(__builtin_bit_cast(uint64_t, d2), (uint32_t)r, dkey, didx, &fill_s);
     }
-    __syncthreads();
-    const int F = fill_s;
-    for (int i = F + threadIdx.x; i < SORT_CAP; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
-    __syncthreads();
-    block_sort_pairs(dkey, didx, SORT_CAP);
-    if (F >= kkeep) { kth_key = dkey[kkeep - 1]; kth_idx = didx[kkeep - 1]; }
-    __syncthreads();
-    if (threadIdx.x == 0) fill_s = F < kkeep ? F : kkeep;
-    __syncthreads();
+    top.settle(dkey, didx, &fill_s, r1 == a.n);
   }
   fix_boundary(dkey, didx, fill_s, k, a.X, a.d, ys);
   if (threadIdx.x == 0) b.status[qi] = 0;
@@ -933,8 +949,8 @@ ivf_scan_kernel(IvfTiles v, uint64_t* __restrict__ cand, int32_t* __restrict__ c
 // Rows the query's clusters hold (clusters probed by one query are distinct).
 __device__ __forceinline__ int64_t ivf_rows(const IvfRefine& v, int64_t qi) {
   int64_t tot = 0;
-  for (int64_t p = 0; p < v.np; ++p) {
-    const int32_t l = v.probe[qi * v.np + p];
+  for (int64_t p = 0; p < v.np_q[qi]; ++p) {
+    const int32_t l = v.probe[qi * v.kp + p];
     tot += v.off[l + 1] - v.off[l];
   }
   return tot;
@@ -964,15 +980,16 @@ ivf_refine_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restrict__
   if (threadIdx.x == 0) fill_s = 0;
   __syncthreads();
   int64_t seen = 0;
-  for (int64_t p = 0; p < v.np; ++p) {
-    const int32_t row = v.pair_of[qi * v.np + p];
+  const int64_t np = v.np_q[qi];
+  for (int64_t p = 0; p < np; ++p) {
+    const int32_t row = v.pair_of[qi * v.kp + p];
     const int c = b.cand_cnt[row];
     const uint64_t* lst = b.cand + (int64_t)row * b.cap1;
     seen += c;
     __syncthreads();
     for (int i = threadIdx.x; i < c; i += WG) buf[atomicAdd(&fill_s, 1)] = lst[i];
     __syncthreads();
-    const bool flush = (fill_s + K1 > SORT_CAP) || (p + 1 == v.np);
+    const bool flush = (fill_s + K1 > SORT_CAP) || (p + 1 == np);
     if (flush && fill_s >= K1) {
       const int F = fill_s;
       const int N = next_pow2(F);
@@ -1026,65 +1043,111 @@ ivf_exhaustive_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restri
   uint32_t* tmp = didx + SORT_CAP;
   double* red = reinterpret_cast<double*>(tmp + K_MAX);
   float* ys = reinterpret_cast<float*>(red + WG);
-  int64_t* cum = reinterpret_cast<int64_t*>(ys + ((a.d + 3) & ~3ll));   // [np + 1]
+  int64_t* cum = reinterpret_cast<int64_t*>(ys + ((a.d + 3) & ~3ll));   // [kp + 1]
   __shared__ int fill_s;
   const int64_t qi = blockIdx.x;
   const int st = b.status[qi];
   if (st != 2 && st != 3) return;
   const int k = (int)a.k;
   for (int64_t t = threadIdx.x; t < a.d; t += WG) ys[t] = a.Y[qi * a.d + t];
+  const int64_t np = v.np_q[qi];
   if (threadIdx.x == 0) {
     fill_s = 0;
     int64_t c = 0;
-    for (int64_t p = 0; p < v.np; ++p) {
+    for (int64_t p = 0; p < np; ++p) {
       cum[p] = c;
-      const int32_t l = v.probe[qi * v.np + p];
+      const int32_t l = v.probe[qi * v.kp + p];
       c += v.off[l + 1] - v.off[l];
     }
-    cum[v.np] = c;
+    cum[np] = c;
   }
   __syncthreads();
-  const int64_t R = st == 3 ? a.n : cum[v.np];
+  const int64_t R = st == 3 ? a.n : cum[np];
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
-  const int kkeep = k + 32 < SORT_CAP / 2 ? k + 32 : SORT_CAP / 2;
-  const int chunk = SORT_CAP - kkeep;
-  uint64_t kth_key = ~0ull;
-  uint32_t kth_idx = 0xffffffffu;
-  for (int64_t r0 = 0; r0 < R; r0 += chunk) {
-    const int64_t r1 = r0 + chunk < R ? r0 + chunk : R;
+  ExhaustiveTop top(k);
+  for (int64_t r0 = 0; r0 < R; r0 += EXH_CHUNK) {
+    const int64_t r1 = r0 + EXH_CHUNK < R ? r0 + EXH_CHUNK : R;
     for (int64_t r = r0 + g; r < r1; r += WG / 16) {
       int64_t id = r;
       if (st == 2) {   // r-th row of the inspected clusters
-        int64_t lo = 0, hi = v.np;   // cum[lo] <= r < cum[hi]
+        int64_t lo = 0, hi = np;   // cum[lo] <= r < cum[hi]
         while (hi - lo > 1) {
           const int64_t mid = (lo + hi) >> 1;
           if (cum[mid] <= r) lo = mid; else hi = mid;
         }
-        const int32_t l = v.probe[qi * v.np + lo];
+        const int32_t l = v.probe[qi * v.kp + lo];
         id = v.ids[v.off[l] + (r - cum[lo])];
       }
       const double d2 = group16_d2(a.X, id, a.d, ys, l16);
-      const uint64_t kb = __builtin_bit_cast(uint64_t, d2);
-      if (l16 == 0 && (kb < kth_key || (kb == kth_key && (uint32_t)id < kth_idx))) {
-        const int slot = atomicAdd(&fill_s, 1);
-        dkey[slot] = kb;
-        didx[slot] = (uint32_t)id;
-      }
+      if (l16 == 0) top.offer(__builtin_bit_cast(uint64_t, d2), (uint32_t)id, dkey, didx, &fill_s);
     }
-    __syncthreads();
-    const int F = fill_s;
-    for (int i = F + threadIdx.x; i < SORT_CAP; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
-    __syncthreads();
-    block_sort_pairs(dkey, didx, SORT_CAP);
-    if (F >= kkeep) { kth_key = dkey[kkeep - 1]; kth_idx = didx[kkeep - 1]; }
-    __syncthreads();
-    if (threadIdx.x == 0) fill_s = F < kkeep ? F : kkeep;
-    __syncthreads();
+    top.settle(dkey, didx, &fill_s, r1 == R);
   }
   fix_boundary(dkey, didx, fill_s, k, a.X, a.d, ys);
   if (threadIdx.x == 0) b.status[qi] = 0;
   emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
                   nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
+}
+
+// Inspected clusters of each query: its kp closest clusters (an exact k-NN
+// among the centroids, cand[q][kp] ascending by id) put in the exact order
+// (||c - y||^2, l): FP64 distances, then every run of values too close for
+// FP64 to decide re-ordered in double-double (runs of at most 32; longer runs
+// keep the FP64 order, which is exact for identical centroids).  The query
+// inspects the shortest prefix of at least n_probe clusters holding k rows,
+// or none (np_q = 0: exact scan of all rows) if all kp hold fewer.
+constexpr int PROBE_MAX = 512;
+__global__ void __launch_bounds__(WG)
+probe_order_kernel(const float* __restrict__ C, const float* __restrict__ Y, int64_t d,
+                   const int32_t* __restrict__ cand, int kp, const int32_t* __restrict__ off,
+                   int n_probe, int64_t k, int32_t* __restrict__ order, int32_t* __restrict__ np_q) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  uint64_t* dkey = reinterpret_cast<uint64_t*>(smem);                 // PROBE_MAX
+  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + PROBE_MAX);     // PROBE_MAX
+  float* ys = reinterpret_cast<float*>(didx + PROBE_MAX);             // d
+  const int64_t qi = blockIdx.x;
+  for (int64_t t = threadIdx.x; t < d; t += WG) ys[t] = Y[qi * d + t];
+  __syncthreads();
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  for (int i = g; i < kp; i += WG / 16) {
+    const int32_t l = cand[qi * kp + i];
+    const double d2 = group16_d2(C, l, d, ys, l16);
+    if (l16 == 0) { dkey[i] = __builtin_bit_cast(uint64_t, d2); didx[i] = (uint32_t)l; }
+  }
+  const int N = next_pow2(kp > 1 ? kp : 2);
+  for (int i = kp + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
+  __syncthreads();
+  block_sort_pairs(dkey, didx, N);
+  if (threadIdx.x == 0) {
+    const double rel = fp64_rel(d);
+    for (int i = 0; i < kp;) {
+      int j = i;
+      while (j + 1 < kp && __builtin_bit_cast(double, dkey[j + 1]) <=
+                               __builtin_bit_cast(double, dkey[j]) * (1.0 + 2.0 * rel) + 1e-300)
+        ++j;
+      if (j > i && j - i < 32) resolve_band(dkey, didx, i, j, C, d, ys);
+      i = j + 1;
+    }
+    int64_t rows = 0;
+    int p = 0;
+    while (p < kp && (p < n_probe || rows < k)) {
+      rows += off[didx[p] + 1] - off[didx[p]];
+      ++p;
+    }
+    np_q[qi] = rows >= k ? p : 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kp; i += WG) order[qi * kp + i] = (int32_t)didx[i];
+}
+
+hipError_t launch_probe_order(const float* C, const float* Y, int64_t q, int64_t d,
+                              const int32_t* cand, int64_t kp, const int32_t* off, int64_t n_probe,
+                              int64_t k, int32_t* order, int32_t* np_q, hipStream_t s) {
+  if (kp > PROBE_MAX) return hipErrorInvalidValue;
+  const size_t sm = PROBE_MAX * (8 + 4) + d * 4;
+  probe_order_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(C, Y, d, cand, (int)kp, off,
+                                                             (int)n_probe, k, order, np_q);
+  return hipGetLastError();
 }
 
 hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers& b,
@@ -1106,7 +1169,7 @@ hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers&
   ivf_refine_kernel<<<dim3((unsigned)q), dim3(WG), sm1, s>>>(a, b, v, nn_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + ((d + 3) & ~3ll) * 4 +
-                     (v.np + 1) * 8;
+                     (v.kp + 1) * 8;
   ivf_exhaustive_kernel<<<dim3((unsigned)q), dim3(WG), sm2, s>>>(a, b, v, nn_out);
   return hipGetLastError();
 }

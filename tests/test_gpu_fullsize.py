@@ -155,3 +155,28 @@ def test_fullsize_mean_shift_d64():
     for i in range(len(sub)):
         ref = oracle.mean_shift_deann(X, y_end[i], h, k, m, 2, i, 1)
         assert np.max(np.abs(y1[i] - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_fullsize_inverted_file(big):
+    # the benchmark's inverted-file configuration: 1000 clusters, 4 Lloyd steps,
+    # 16 inspected clusters; sampled rows' clusters are their closest
+    # centroids, sampled queries equal the oracle given that index
+    import paper_2107_02736_amd as dk
+    X, Y, Xd, Yd = big
+    h = bandwidth(WL, "gaussian")
+    k, m = 100, 1000
+    Cd, ad = dk.ivf_build(Xd, 1000, iters=4)
+    C, a = Cd.cpu().numpy(), ad.cpu().numpy().astype(np.int64)
+    rows = synth.query_subset(X.shape[0], 1000, seed=5)
+    assert np.array_equal(a[rows], oracle.kmeans_assign(X[rows], C))
+    index = dk.IvfIndex(Xd, Cd, ad)
+    out, nn, sm = (t.cpu().numpy() for t in dk.deann_ivf_query(Xd, Yd, index, 16, h, k, m,
+                                                               seed=0))
+    _check_indices(nn, sm, X.shape[0], k)
+    for j in synth.query_subset(Y.shape[0], 4, seed=6):
+        est, nn_ref, s_ref = oracle.deann_estimate_ivf(X, Y[j], h, GAUSSIAN, C, a, 16, k, m,
+                                                       0, int(j))
+        assert np.array_equal(nn[j], nn_ref), j
+        assert np.array_equal(sm[j], s_ref), j
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
+        print(f"query {j}: recall {oracle.recall(oracle.knn(X, Y[j], k), nn[j]):.2f}")

@@ -3,7 +3,8 @@ against the oracle: k-means initial assignment bit-exact and one Lloyd step
 within float32 rounding; with an index trained by the oracle, the inspected
 clusters' k nearest rows, the draws and the DEANN estimates equal the
 oracle's for several n_probe, k, widths and both kernels, including the
-fallback to the exact k-NN when the inspected clusters are too small; every
+extension to further clusters and the fallback to the exact k-NN when the
+inspected clusters are too small; every
 cluster inspected reproduces deann_query; the adjoint takes the indices
 unchanged."""
 import numpy as np
@@ -95,23 +96,32 @@ def test_ivf_query_matches_oracle(kern, d):
         _check_queries(X, Y, C, a, n_probe, k, m, kern, h, 7, out, nn, sm, range(40))
 
 
-def test_fallback_when_the_inspected_clusters_are_too_small():
+def test_extension_to_further_clusters_and_the_fallback():
     import paper_2107_02736_amd as dk
     dev = device()
+    # about 50 rows per cluster: k above the median size extends many queries
     X, Y = _mix(3000, 30, 6, seed=4, centres=30)
     C, a = oracle.ivf_train(X, 60, 1)
     sizes = np.bincount(a, minlength=60)
-    k = int(np.sort(sizes)[len(sizes) // 2]) + 1   # larger than half of the clusters
+    k = int(np.sort(sizes)[len(sizes) // 2]) + 1
     Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
     index = dk.IvfIndex(Xd, to_dev(C, dev), to_dev(a.astype(np.int32), dev))
-    fallbacks = 0
+    extended = 0
     for n_probe in (1, 2):
         out, nn, sm = (t.cpu().numpy() for t in dk.deann_ivf_query(
             Xd, Yd, index, n_probe, 2.0, k, 50, "gaussian", seed=1))
         _check_queries(X, Y, C, a, n_probe, k, 50, GAUSSIAN, 2.0, 1, out, nn, sm, range(30))
-        for y in Y:
-            fallbacks += np.isin(a, oracle.ivf_probe(C, y, n_probe)).sum() < k
-    assert fallbacks > 0
+        extended += sum(len(oracle.ivf_probe(C, y, n_probe, sizes, k)) > n_probe for y in Y)
+    assert extended > 0
+    # about 5 rows per cluster: at most 65 clusters hold fewer than k = 400 rows,
+    # so every query uses the exact k nearest rows of all of X
+    C, a = oracle.ivf_train(X, 600, 1)
+    index = dk.IvfIndex(Xd, to_dev(C, dev), to_dev(a.astype(np.int32), dev))
+    out, nn, sm = (t.cpu().numpy() for t in dk.deann_ivf_query(Xd, Yd, index, 1, 2.0, 400, 50,
+                                                               "gaussian", seed=1))
+    sizes = np.bincount(a, minlength=600)
+    assert all(oracle.ivf_probe(C, y, 1, sizes, 400).size == 0 for y in Y[:5])
+    _check_queries(X, Y, C, a, 1, 400, 50, GAUSSIAN, 2.0, 1, out, nn, sm, range(0, 30, 3))
 
 
 def test_every_cluster_inspected_is_deann_query_and_the_adjoint():

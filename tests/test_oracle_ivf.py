@@ -93,6 +93,17 @@ def _exact(x, y):
     return sum((Fraction(float(p)) - Fraction(float(q))) ** 2 for p, q in zip(x, y))
 
 
+def _probe_by_hand(C, y, n_probe, sizes, k):
+    order = sorted(range(len(C)), key=lambda l: (_exact(C[l], y), l))
+    cap = min(len(C), max(2 * n_probe, n_probe + 64), 496)
+    p = n_probe
+    while p < cap and sum(sizes[l] for l in order[:p]) < k:
+        p += 1
+    if sum(sizes[l] for l in order[:p]) < k:
+        return None
+    return order[:p]
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_brute_force_on_tiny_inputs(seed):
     rng = np.random.default_rng(100 + seed)
@@ -100,25 +111,47 @@ def test_brute_force_on_tiny_inputs(seed):
     C = rng.integers(-3, 4, size=(4, 2)).astype(np.float32)
     a = np.asarray([min(range(4), key=lambda l: (_exact(C[l], x), l)) for x in X])
     assert np.array_equal(a, oracle.kmeans_assign(X, C))
+    sizes = np.bincount(a, minlength=4)
     for y in rng.integers(-3, 4, size=(5, 2)).astype(np.float32):
-        for n_probe, k in itertools.product((1, 2, 3), (1, 3)):
-            probes = sorted(range(4), key=lambda l: (_exact(C[l], y), l))[:n_probe]
-            rows = [i for i in range(14) if a[i] in probes]
-            if len(rows) < k:
-                rows = list(range(14))
+        want_order = sorted(range(4), key=lambda l: (_exact(C[l], y), l))
+        assert oracle.cluster_order(C, y).tolist() == want_order
+        for n_probe, k in itertools.product((1, 2, 3), (1, 3, 9)):
+            probes = _probe_by_hand(C, y, n_probe, sizes, k)
+            rows = list(range(14)) if probes is None else [i for i in range(14) if a[i] in probes]
             want = sorted(sorted(rows, key=lambda i: (_exact(X[i], y), i))[:k])
             got = oracle.ivf_knn(X, y, C, a, n_probe, k)
             assert got.tolist() == want
 
 
-def test_fallback_when_the_inspected_clusters_are_too_small():
+def test_cluster_order_is_the_exact_order():
+    rng = np.random.default_rng(7)
+    C = rng.normal(size=(40, 5)).astype(np.float32)
+    C[7] = C[3]                       # an exact tie: the lower id first
+    C[9] = np.nextafter(C[2], np.float32(np.inf))   # a near tie
+    for y in rng.normal(size=(6, 5)).astype(np.float32):
+        want = sorted(range(40), key=lambda l: (_exact(C[l], y), l))
+        assert oracle.cluster_order(C, y).tolist() == want
+
+
+def test_extension_to_further_clusters_and_the_fallback():
     X = np.array([[0], [1], [2], [50], [51], [52], [53]], dtype=np.float32)
     C = np.array([[1], [52]], dtype=np.float32)
     a = oracle.kmeans_assign(X, C)
+    sizes = np.bincount(a, minlength=2)
     y = np.array([0.4], dtype=np.float32)
-    # cluster 0 holds 3 rows: k = 3 stays inside it, k = 4 falls back
+    # cluster 0 holds 3 rows: k = 3 stays inside it, k = 4 also inspects cluster 1
+    assert oracle.ivf_probe(C, y, 1, sizes, 3).tolist() == [0]
+    assert oracle.ivf_probe(C, y, 1, sizes, 4).tolist() == [0, 1]
     assert oracle.ivf_knn(X, y, C, a, 1, 3).tolist() == [0, 1, 2]
-    assert oracle.ivf_knn(X, y, C, a, 1, 4).tolist() == oracle.knn(X, y, 4).tolist() == [0, 1, 2, 3]
+    assert oracle.ivf_knn(X, y, C, a, 1, 4).tolist() == [0, 1, 2, 3]
+    # 70 single-row clusters: at most min(70, max(2, 1 + 64)) = 65 are inspected
+    X = np.arange(70, dtype=np.float32).reshape(-1, 1)
+    C, a = X.copy(), np.arange(70)
+    sizes = np.ones(70, dtype=np.int64)
+    y = np.array([0.0], dtype=np.float32)
+    assert oracle.ivf_probe(C, y, 1, sizes, 65).tolist() == list(range(65))
+    assert oracle.ivf_probe(C, y, 1, sizes, 66).size == 0          # exact fallback
+    assert oracle.ivf_knn(X, y, C, a, 1, 66).tolist() == list(range(66))
 
 
 def test_estimate_with_every_cluster_equals_deann_and_recall():

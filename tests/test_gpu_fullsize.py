@@ -158,9 +158,9 @@ def test_fullsize_mean_shift_d64():
 
 
 def test_fullsize_inverted_file(big):
-    # the benchmark's inverted-file configuration: 1000 clusters, 4 Lloyd steps,
-    # 16 inspected clusters; sampled rows' clusters are their closest
-    # centroids, sampled queries equal the oracle given that index
+    # an inverted-file configuration of the cluster-count sweep: 1000 clusters,
+    # 4 Lloyd steps, 16 inspected clusters; sampled rows' clusters are their
+    # closest centroids, sampled queries equal the oracle given that index
     import paper_2107_02736_amd as dk
     X, Y, Xd, Yd = big
     h = bandwidth(WL, "gaussian")

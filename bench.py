@@ -286,10 +286,12 @@ def main():
     flops_exact = 2.0 * n * d * q
     tile_avg_ms = float(np.mean(tile_ms))
     fwd_achieved = flops_exact / (tile_avg_ms * 1e-3)
-    roof_fwd = {"bound": "mfma", "kernel": "kde_tile_kernel<float,gaussian>",
+    # FP32 rows of at most 128 floats: the register-resident query kernel
+    fwd_kernel = "kde_yres_kernel<gaussian>" if d <= 128 else "kde_tile_kernel<float,gaussian>"
+    roof_fwd = {"bound": "mfma", "kernel": fwd_kernel,
                 "achieved": fwd_achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                 "unit": "TFLOP/s", "frac": fwd_achieved / PEAK_FP32_MFMA,
-                "traffic": measured_traffic("kde_tile_kernel<float,gaussian>"),
+                "traffic": measured_traffic(fwd_kernel),
                 "flops_per_launch": flops_exact, "kernel_avg_ms": tile_avg_ms,
                 "launches_timed": len(tile_ms),
                 "note": "exact KDE alone: 2*n*d*q flops per launch / the tile kernel's own "

@@ -172,8 +172,8 @@ int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, in
  * ivf_build: Lloyd's k-means.  centroids[n_clusters, d] (float32, output) start
  *   as the rows floor(l n / n_clusters); each of `iters` steps assigns every row
  *   to its closest centroid (exact order (||c - x||^2, l), ties to the lower l)
- *   and replaces each centroid by the mean of its rows (FP64 sum in row order,
- *   rounded once to float32; a centroid without rows stays).  assign[n] (int32,
+ *   and replaces each centroid by the mean of its rows (FP64 sums in a fixed
+ *   order, rounded once to float32; a centroid without rows stays).  assign[n] (int32,
  *   output) is the closest final centroid of every row.
  *   Requirements: 1 <= n_clusters <= min(n, 8192), 0 <= iters <= 1000, d <= 4096.
  *

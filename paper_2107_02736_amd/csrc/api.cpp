@@ -706,6 +706,10 @@ IvfQueryPlan plan_ivf_query(void* ws, int64_t n, int64_t q, int64_t d, int64_t L
   P.nn_internal = cv.take<int32_t>(q * (k > 0 ? k : 1));
   b.z1 = cv.take<double>(q > 0 ? q : 1);
   b.status = cv.take<int32_t>(q > 0 ? q : 1);
+  b.thr2 = cv.take<float>(q > 0 ? q : 1);
+  b.cap2 = kSortCap;
+  b.cand2 = cv.take<uint64_t>(q * b.cap2);
+  b.cand2_cnt = cv.take<int32_t>(q > 0 ? q : 1);
   b.yerr = P.yerr;
   P.bytes = cv.off + kAlign;
   (void)n;
@@ -870,7 +874,7 @@ int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_
                        P.Yg, P.ygk, s);
     if (e == hipSuccess) {
       IvfTiles t{reinterpret_cast<const char*>(P.Yg), x.Xs, dp * 4, (int)(dp * 4 / CHUNK_BYTES),
-                 P.ygk, x.xknorm, P.pp, x.poff, n_clusters};
+                 P.ygk, x.xknorm, P.pp, x.poff, n_clusters, P.pair_q, x.pids};
       IvfRefine v{probe, P.kp, P.np_q, P.pair_of, x.off, x.ids, x.pids};
       e = launch_ivf_knn(t, P.pcap, P.kb, v, X, Y, n, q, d, k, h, kernel, nullptr, s);
     }

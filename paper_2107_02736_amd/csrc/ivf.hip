@@ -129,18 +129,30 @@ list_scatter_kernel(const int32_t* __restrict__ a, int64_t n, int64_t L,
   }
 }
 
-// Lloyd update: centroid l <- mean of its rows (FP64 sum in row order, one
-// rounding to float32); a cluster without rows keeps its centroid.
+// Lloyd update: centroid l <- mean of its rows (FP64 sums, one rounding to
+// float32); a cluster without rows keeps its centroid.  Workgroup (l, 64
+// coordinates); its four waves sum the members j = j0 + w, j0 + w + 4, ... in
+// order and the four partial sums are added in a fixed order, so the result
+// does not depend on scheduling.
+constexpr int MEAN_COLS = 64;
 __global__ void __launch_bounds__(WG)
 kmeans_mean_kernel(const float* __restrict__ X, int64_t d, const int32_t* __restrict__ ids,
                    const int32_t* __restrict__ off, const float* __restrict__ C_prev,
                    float* __restrict__ C_new) {
+  __shared__ double part[WG / MEAN_COLS][MEAN_COLS];
   const int64_t l = blockIdx.x;
+  const int64_t t = (int64_t)blockIdx.y * MEAN_COLS + (threadIdx.x % MEAN_COLS);
+  const int ph = threadIdx.x / MEAN_COLS;
   const int32_t j0 = off[l], j1 = off[l + 1];
-  for (int64_t t = threadIdx.x; t < d; t += WG) {
-    double s = 0.0;
-    for (int32_t j = j0; j < j1; ++j) s += (double)X[(int64_t)ids[j] * d + t];
-    C_new[l * d + t] = j1 > j0 ? (float)(s / (double)(j1 - j0)) : C_prev[l * d + t];
+  double s = 0.0;
+  if (t < d)
+    for (int32_t j = j0 + ph; j < j1; j += WG / MEAN_COLS) s += (double)X[(int64_t)ids[j] * d + t];
+  part[ph][threadIdx.x % MEAN_COLS] = s;
+  __syncthreads();
+  if (ph == 0 && t < d) {
+    const int c = threadIdx.x;
+    const double tot = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
+    C_new[l * d + t] = j1 > j0 ? (float)(tot / (double)(j1 - j0)) : C_prev[l * d + t];
   }
 }
 
@@ -235,7 +247,9 @@ hipError_t launch_list_layout(const int32_t* a, int64_t n, int64_t L, int32_t* h
 
 hipError_t launch_kmeans_mean(const float* X, int64_t d, const int32_t* ids, const int32_t* off,
                               int64_t L, const float* C_prev, float* C_new, hipStream_t s) {
-  kmeans_mean_kernel<<<dim3((unsigned)L), dim3(WG), 0, s>>>(X, d, ids, off, C_prev, C_new);
+  static_assert(WG / MEAN_COLS == 4, "four partial sums per coordinate");
+  kmeans_mean_kernel<<<dim3((unsigned)L, (unsigned)ceil_div(d, MEAN_COLS)), dim3(WG), 0, s>>>(
+      X, d, ids, off, C_prev, C_new);
   return hipGetLastError();
 }
 

@@ -100,6 +100,8 @@ struct IvfTiles {
   const int32_t* pp;       // [L+1] pair rows of each cluster (multiples of 128)
   const int32_t* poff;     // [L+1] index rows of each cluster (multiples of 128)
   int64_t L;
+  const int32_t* pair_q;   // [prow_cap] query of each pair row (-1: padding)
+  const int32_t* pids;     // [xrows] row of each tile-layout row (-1: empty)
 };
 
 struct IvfRefine {

@@ -367,8 +367,12 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
   // packed into its two low mantissa bits so that one min tracks both, and
   // the tile it came from.  The packing perturbs keys by at most 3 ulp; the
   // candidates only seed the second pass, which alone decides the result.
-  __shared__ float yks[BQ];
-  if (threadIdx.x < BQ) yks[threadIdx.x] = p.yknorm[qt * BQ + threadIdx.x];
+  // key norms of the lane's 16 query rows, loop invariant
+  float ykr[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ykr[i][r] = p.yknorm[qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r];
   float best[4][4];
   int32_t btile[4][4];
 #pragma unroll
@@ -420,7 +424,7 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float yk = yks[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
+        const float yk = ykr[i][r];
         float m = __builtin_inff();
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -565,12 +569,17 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
-  // per query row: key norm and threshold (-inf: no second pass for that
-  // query), published by the first barrier of the sweep
-  __shared__ float yks[BQ], ths[BQ];
+  // key norms of the lane's 16 query rows (loop invariant, in registers) and
+  // the thresholds per query row (-inf: no second pass for that query),
+  // published by the first barrier of the sweep
+  float ykr[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ykr[i][r] = p.yknorm[qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r];
+  __shared__ float ths[BQ];
   if (threadIdx.x < BQ) {
     const int64_t row = qt * BQ + threadIdx.x;
-    yks[threadIdx.x] = p.yknorm[row];
     ths[threadIdx.x] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
   }
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
@@ -605,27 +614,27 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
       ql_tile<T>(acc, ql, p.Xs, t, t1, lds, wq, wn, lane);
     else
       yreg_tile<T, NK>(acc, xs, yf, p.Xs, p.ld_bytes, t, t1, lds, wn, lane);
-    // fl(key - th) <= 0 exactly when key <= th; padding columns (infinite
-    // key) and queries without a second pass (th = -inf) never hit
+    // queries without a second pass (th = -inf) never hit; padding columns
+    // (infinite key) can only hit a query with th = +inf and are dropped by
+    // the column check of the append
     float xk[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
       xk[j] = col < p.n ? xks[nb][wn * 64 + j * 16 + (lane & 15)] : __builtin_inff();
     }
-    // one bit per query row (i, r) of this lane that has a hit in this tile
+    // one bit per query row (i, r) of this lane that has a hit in this tile:
+    // some key of the row is <= its threshold
     uint32_t hit = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int rl = wq * 64 + i * 16 + 4 * (lane >> 4) + r;
-        const float yk = yks[rl], th = ths[rl];
-        float m = __builtin_fmaf(-2.f, acc[i][0][r], yk + xk[0]) - th;
+        const float yk = ykr[i][r];
+        float m = __builtin_fmaf(-2.f, acc[i][0][r], yk + xk[0]);
 #pragma unroll
-        for (int j = 1; j < 4; ++j)
-          m = fminf(m, __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]) - th);
-        hit |= m <= 0.f ? 1u << (i * 4 + r) : 0u;
+        for (int j = 1; j < 4; ++j) m = fminf(m, __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]));
+        hit |= m <= ths[wq * 64 + i * 16 + 4 * (lane >> 4) + r] ? 1u << (i * 4 + r) : 0u;
       }
     if (hit) {   // rare: append the hits, visiting only the rows that have one
 #pragma unroll
@@ -633,9 +642,8 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           if (!(hit & (1u << (i * 4 + r)))) continue;
-          const int rl = wq * 64 + i * 16 + 4 * (lane >> 4) + r;
-          const int64_t row = qt * BQ + rl;
-          const float yk = yks[rl], th = ths[rl];
+          const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+          const float yk = ykr[i][r], th = ths[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
@@ -956,8 +964,10 @@ __device__ __forceinline__ int64_t ivf_rows(const IvfRefine& v, int64_t qi) {
   return tot;
 }
 
-// status: 0 certified, 2 exact scan of the inspected clusters, 3 exact scan
-// of all rows (the inspected clusters hold fewer than k rows).
+// status: 0 certified, 1 second pass over the inspected clusters (collect
+// every row whose key admits a distance <= d_k), 2 exact scan of the
+// inspected clusters (second-pass overflow), 3 exact scan of all rows (the
+// inspected clusters hold fewer than k rows).
 __global__ void __launch_bounds__(WG)
 ivf_refine_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restrict__ nn_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -1024,13 +1034,87 @@ ivf_refine_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restrict__
     const double lhs = sqrt((double)fmaxf(Tkey, 0.f)) - E - ey;
     ok = lhs > 0.0 && lhs * lhs > Dk * (1.0 + 1e-14);
   }
-  if (!ok) {
-    if (threadIdx.x == 0) b.status[qi] = 2;
+  if (!ok) {   // C = K1 >= k here: d_k is bounded, the second pass collects
+    if (threadIdx.x == 0) {
+      const double Dk = __builtin_bit_cast(double, dkey[k - 1]) * (1.0 + fp64_rel(a.d));
+      const double E = (double)__builtin_bit_cast(float, *b.xerr_max);
+      const double ey = (double)b.yerr[qi];
+      const double r = (sqrt(Dk) + E + ey) * (1.0 + 1e-6);
+      b.thr2[qi] = (float)(r * r * (1.0 + 1e-6));
+      b.cand2_cnt[qi] = 0;
+      b.status[qi] = 1;
+    }
     return;
   }
   if (threadIdx.x == 0) b.status[qi] = 0;
   emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
                   nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
+}
+
+// Second pass over the pair tiles: every row of an inspected cluster whose key
+// is <= the threshold of the pair's query (status 1) is appended to that
+// query's candidates, as its row index.
+__global__ void __launch_bounds__(WG, 2)
+ivf_collect_kernel(IvfTiles v, KnnBuffers b) {
+  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
+  __shared__ float yks[BQ], ths[BQ];
+  __shared__ int qry[BQ];
+  const int64_t row0 = (int64_t)blockIdx.x * BQ;
+  if (row0 >= v.pp[v.L]) return;
+  int need = 0;
+  if (threadIdx.x < BQ) {
+    const int32_t qi = v.pair_q[row0 + threadIdx.x];
+    const bool on = qi >= 0 && b.status[qi] == 1;
+    qry[threadIdx.x] = qi;
+    yks[threadIdx.x] = v.yknorm[row0 + threadIdx.x];
+    ths[threadIdx.x] = on ? b.thr2[qi] : -__builtin_inff();
+    need = on;
+  }
+  if (!__syncthreads_or(need)) return;   // no query of this tile needs the pass
+  int64_t lo = 0, hi = v.L;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (v.pp[mid] <= row0) lo = mid; else hi = mid;
+  }
+  const int64_t t0 = v.poff[lo] / BN, t1 = v.poff[lo + 1] / BN;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wq = wave >> 1, wn = wave & 1;
+  const char* yq = v.Ys + row0 * v.ld_bytes;
+  StreamState st;
+  if (t0 < t1) stream_start(st, yq, v.Xs, v.ld_bytes, t0);
+  __shared__ float xks[2][BN];
+  float xk_reg = (threadIdx.x < BN && t0 < t1) ? v.xknorm[t0 * BN + threadIdx.x] : 0.f;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int nb = (int)((t - t0) & 1);
+    if (threadIdx.x < BN) {
+      xks[nb][threadIdx.x] = xk_reg;
+      if (t + 1 < t1) xk_reg = v.xknorm[(t + 1) * BN + threadIdx.x];
+    }
+    f32x4 acc[4][4];
+    stream_tile<float>(acc, st, yq, v.Xs, v.ld_bytes, v.nchunks, t, t1, lds, wq, wn, lane);
+    float xk[4];   // empty rows carry an infinite key norm
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xk[j] = xks[nb][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ql = wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const float yk = yks[ql], th = ths[ql];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]);
+          if (key <= th) {   // th = -inf for rows without a second pass
+            const int32_t id = v.pids[t * BN + wn * 64 + j * 16 + (lane & 15)];
+            if (id >= 0) {
+              const int32_t qi = qry[ql];
+              const int slot = atomicAdd(&b.cand2_cnt[qi], 1);
+              if (slot < b.cap2) b.cand2[(int64_t)qi * b.cap2 + slot] = (uint64_t)id;
+            }
+          }
+        }
+      }
+  }
 }
 
 // Exact FP64 scan for status 2 (rows of the inspected clusters) and status 3
@@ -1167,6 +1251,11 @@ hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers&
   RefineArgs a{X, Y, n, q, d, k, 0, 0, h, kern, 0};
   const size_t sm1 = SORT_CAP * 8 + K_MAX * (8 + 4 + 4) + WG * 8 + d * 4;
   ivf_refine_kernel<<<dim3((unsigned)q), dim3(WG), sm1, s>>>(a, b, v, nn_out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  ivf_collect_kernel<<<g, blk, 0, s>>>(t, b);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t smr = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + d * 4;
+  knn_refine2_kernel<<<dim3((unsigned)q), dim3(WG), smr, s>>>(a, b, nn_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + ((d + 3) & ~3ll) * 4 +
                      (v.kp + 1) * 8;

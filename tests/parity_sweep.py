@@ -2,12 +2,15 @@
 
     python tests/parity_sweep.py --workload mix100_n1e6_d128 --queries 500
 
-Runs the GPU path once on the whole workload (exact KDE in FP32, DEANN with
-the given scan precision, DEANN adjoint) and checks a fixed random subset of
+Runs the GPU path once on the whole workload (exact KDE in FP32, for d <= 128
+also the exact KDE with its gradient in one pass, DEANN with the given scan
+precision, DEANN adjoint) and checks a fixed random subset of
 queries against the FP64 oracle, computed in spawned processes (one per host
 core, at most 16, fewer when the data is large).  Prints one JSON summary:
 neighbour sets and draws must be bit-identical, DEANN estimates within 1e-12,
-FP32 exact KDE within 1e-5 and the DEANN adjoint within 1e-6 (normwise)."""
+FP32 exact KDE within 1e-5, the DEANN adjoint within 1e-6 (normwise) and the
+exact gradient within 1e-4 of the normwise scale sum K |x - y| / (n h^2)
+(Gaussian) or sum K / (n h) (exponential)."""
 import argparse
 import concurrent.futures as cf
 import json
@@ -20,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 
-def _oracle_queries(workload, kern, h, k, m, queries):
+def _oracle_queries(workload, kern, h, k, m, queries, with_grad):
     import numpy as np
 
     import oracle
@@ -28,10 +31,18 @@ def _oracle_queries(workload, kern, h, k, m, queries):
     spec, X, Y = synth.workload(workload)
     out = []
     for j in queries:
-        mu = oracle.kde_exact(X, Y[j:j + 1], h, kern)[0]
+        if with_grad:   # the exact KDE with its y-gradient and the normwise scale
+            mu, gye, _ = oracle.kde_grad(X, Y[j].astype(np.float64), h, kern)
+            d2 = oracle.sq_dists(X, Y[j])
+            K = oracle.kernel_values(d2, h, kern)
+            scale = ((K * np.sqrt(d2)).sum() / (X.shape[0] * h * h) if kern == oracle.GAUSSIAN
+                     else K.sum() / (X.shape[0] * h))
+        else:
+            mu, gye, scale = oracle.kde_exact(X, Y[j:j + 1], h, kern)[0], None, None
         est, nn, s = oracle.deann_estimate(X, Y[j], h, kern, k, m, 0, int(j))
         _, gy, _ = oracle.deann_grad(X, Y[j], h, kern, nn, s, m)
-        out.append((int(j), float(mu), float(est), np.asarray(nn), np.asarray(s), np.asarray(gy)))
+        out.append((int(j), float(mu), float(est), np.asarray(nn), np.asarray(s), np.asarray(gy),
+                    gye, scale))
     return out
 
 
@@ -59,6 +70,9 @@ def main():
     dev = torch.device("cuda:0")
     Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
     mu = dk.kde_exact(Xd, Yd, h, args.kernel, "fp32").cpu().numpy()
+    with_grad = X.shape[1] <= 128   # the fused exact value + gradient kernel
+    if with_grad:
+        mu_g, gy_e, _ = (t.cpu().numpy() for t in dk.kde_exact_with_grad(Xd, Yd, h, args.kernel))
     est, nn, sm = dk.deann_query(Xd, Yd, h, args.k, args.m, args.kernel, seed=0,
                                  precision=args.precision)
     g = torch.ones(Y.shape[0], dtype=torch.float64, device=dev)
@@ -71,11 +85,18 @@ def main():
     t0 = time.perf_counter()
     with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
         parts = list(ex.map(_oracle_queries, [args.workload] * workers, [kern] * workers,
-                            [h] * workers, [args.k] * workers, [args.m] * workers, shards))
+                            [h] * workers, [args.k] * workers, [args.m] * workers, shards,
+                            [with_grad] * workers))
     t_oracle = time.perf_counter() - t0
     nn_bad, s_bad, e_exact, e_est, e_gy, excluded, gy_tiny, e_abs = 0, 0, [], [], [], 0, 0, 0.0
+    e_fused, e_egrad = [], []
     for part in parts:
-        for j, mu_r, est_r, nn_r, s_r, gy_r in part:
+        for j, mu_r, est_r, nn_r, s_r, gy_r, gye_r, scale in part:
+            # below a KDE of 1e-16 the FP32 kernel values underflow: such queries
+            # are excluded from relative errors (as for the exact KDE)
+            if with_grad and mu_r >= 1e-16:
+                e_fused.append(abs(mu_g[j] - mu_r) / mu_r)
+                e_egrad.append(float(np.linalg.norm(gy_e[j] - gye_r) / scale))
             nn_bad += not np.array_equal(nn[j], nn_r)
             s_bad += not np.array_equal(sm[j], s_r)
             if mu_r >= 1e-16:
@@ -98,10 +119,13 @@ def main():
            "deann_max_rel": max(e_est) if e_est else None,
            "deann_grad_y_max_rel": max(e_gy) if e_gy else None,
            "deann_grad_y_below_1e-30": gy_tiny, "deann_grad_y_max_abs_there": e_abs,
+           "exact_with_grad_value_max_rel": max(e_fused) if e_fused else None,
+           "exact_grad_y_max_err_normwise": max(e_egrad) if e_egrad else None,
            "oracle_processes": workers, "oracle_seconds": t_oracle}
     res["pass"] = bool(nn_bad == 0 and s_bad == 0 and (not e_exact or max(e_exact) <= 1e-5)
                        and (not e_est or max(e_est) <= 1e-12) and (not e_gy or max(e_gy) <= 1e-6)
-                       and e_abs <= 1e-30)
+                       and e_abs <= 1e-30 and (not e_fused or max(e_fused) <= 1e-5)
+                       and (not e_egrad or max(e_egrad) <= 1e-4))
     print(json.dumps(res), flush=True)
     sys.exit(0 if res["pass"] else 1)
 

@@ -42,7 +42,7 @@ typedef enum { DEANN_GAUSSIAN = 0, DEANN_EXPONENTIAL = 1 } deann_kernel;
 /* Precision of the distance tiles on MFMA (FP32 accumulation in every case).
  * Values that reach an estimate in deann_query are always recomputed exactly
  * in FP64 from the float32 inputs, whatever the precision here. */
-typedef enum { DEANN_FP32 = 0, DEANN_BF16 = 1, DEANN_FP16 = 2 } deann_precision;
+typedef enum { DEANN_FP32 = 0, DEANN_BF16 = 1, DEANN_FP16 = 2, DEANN_FP32_SPLIT = 3 } deann_precision;
 
 typedef enum {
   DEANN_OK = 0,

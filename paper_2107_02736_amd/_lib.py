@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libdeann.so")
 
 OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
 GAUSSIAN, EXPONENTIAL = 0, 1
-FP32, BF16, FP16 = 0, 1, 2
+FP32, BF16, FP16, FP32_SPLIT = 0, 1, 2, 3
 
 EXPORTS = (
     "kde_exact_workspace", "kde_exact",

@@ -11,7 +11,7 @@ import torch
 from . import _lib
 
 _KERNELS = {"gaussian": _lib.GAUSSIAN, "exponential": _lib.EXPONENTIAL}
-_PRECS = {"fp32": _lib.FP32, "bf16": _lib.BF16, "fp16": _lib.FP16}
+_PRECS = {"fp32": _lib.FP32, "bf16": _lib.BF16, "fp16": _lib.FP16, "fp32_split": _lib.FP32_SPLIT}
 
 
 def kernel_id(kernel) -> int:

@@ -203,13 +203,21 @@ constexpr int64_t kCollectSplitTarget = 4096;  // candidate and collect passes
 struct KdePlan {
   Prep prep;
   double* partial;
+  char *Xsp, *Ysp;   // three-part bfloat16 rows (DEANN_FP32_SPLIT)
+  int64_t dps;
   int64_t bytes;
 };
 
 KdePlan plan_kde(void* ws, int64_t n, int64_t q, int64_t d, int prec) {
   Carve cv(ws);
   KdePlan k{};
-  k.prep = carve_prep(cv, n, q, d, prec);
+  const bool split = prec == DEANN_FP32_SPLIT;
+  k.prep = carve_prep(cv, n, q, d, split ? DEANN_FP32 : prec);
+  if (split) {
+    k.dps = round_up(d, 64);
+    k.Xsp = cv.take<char>(k.prep.np * 3 * k.dps * 2);
+    k.Ysp = cv.take<char>(k.prep.qp * 3 * k.dps * 2);
+  }
   const int64_t qtiles = k.prep.qp / BQ, ntiles = k.prep.np / BN;
   const int64_t splits = choose_splits(qtiles, ntiles, kKdeSplitTarget);
   k.partial = cv.take<double>(splits * k.prep.qp);
@@ -333,7 +341,7 @@ int deann_kernel_times(int site, float* ms, int max_count) {
 }
 
 size_t kde_exact_workspace(int64_t n, int64_t q, int64_t d, int precision) {
-  if (n < 1 || d < 1 || q < 0 || bad_prec(precision)) return 0;
+  if (n < 1 || d < 1 || q < 0 || (bad_prec(precision) && precision != DEANN_FP32_SPLIT)) return 0;
   return (size_t)plan_kde(nullptr, n, q, d, precision).bytes;
 }
 
@@ -341,7 +349,9 @@ int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, d
               int kernel, int precision, double* out, void* ws, size_t ws_bytes, void* stream) {
   int st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
-  if (bad_prec(precision)) return fail(DEANN_EINVAL, "unknown precision %d", precision);
+  const bool split = precision == DEANN_FP32_SPLIT;
+  if (bad_prec(precision) && !split) return fail(DEANN_EINVAL, "unknown precision %d", precision);
+  if (split && d > 128) return fail(DEANN_EUNSUPPORTED, "DEANN_FP32_SPLIT supports d <= 128");
   if (q == 0) return DEANN_OK;
   if (!out) return fail(DEANN_EINVAL, "out is NULL");
   const int64_t need = plan_kde(nullptr, n, q, d, precision).bytes;
@@ -349,10 +359,22 @@ int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, d
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   KdePlan P = plan_kde(align_ws(ws), n, q, d, precision);
-  hipError_t e = run_prep(P.prep, X, n, Y, q, d, precision, s);
+  const int prep_prec = split ? DEANN_FP32 : precision;
+  hipError_t e = run_prep(P.prep, X, n, Y, q, d, prep_prec, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
-  TileProblem tp = make_problem(P.prep, n, q, precision, kKdeSplitTarget);
-  e = launch_kde_exact(precision, tp, kernel, h, P.partial, out, s, timer_hook(0));
+  TileProblem tp = make_problem(P.prep, n, q, prep_prec, kKdeSplitTarget);
+  if (split) {
+    e = launch_split_rows(reinterpret_cast<const float*>(P.prep.Xs), P.prep.np, P.prep.dp, P.dps,
+                          P.Xsp, s);
+    if (e == hipSuccess)
+      e = launch_split_rows(reinterpret_cast<const float*>(P.prep.Ys), P.prep.qp, P.prep.dp,
+                            P.dps, P.Ysp, s);
+    if (e == hipSuccess)
+      e = launch_kde_exact_split(tp, P.Xsp, P.Ysp, P.dps, kernel, h, P.partial, out, s,
+                                 timer_hook(0));
+  } else {
+    e = launch_kde_exact(precision, tp, kernel, h, P.partial, out, s, timer_hook(0));
+  }
   if (e != hipSuccess) return hip_fail(e, "kde_exact");
   return DEANN_OK;
 }

@@ -271,6 +271,176 @@ kde_yres_kernel(TileProblem p, float Lf, double* __restrict__ partial) {
   if (g == 0) partial[split * p.qp + qt * BQ + wave * 16 + c] = sum;
 }
 
+// The same sweep with float32-accurate dot products from bfloat16 MFMAs: every
+// prepared value is split into three bfloat16 parts (v = h + m + l exactly) and
+// <x, y> is accumulated from the six products h h, h m, m h, h l, m m, l h of
+// each 32-element k-chunk (v_mfma_f32_16x16x32_bf16, products exact in FP32);
+// the three dropped products are below 2^-23 |x||y| together.  Rows hold the
+// planes h, m, l of DPS elements each; the queries' planes stay in registers.
+template <int KERN, int DPS, int NBI>
+__global__ void __launch_bounds__(YWG, NBI <= 2 ? 2 : 1)
+kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __restrict__ Ysp,
+                 float Lf, double* __restrict__ partial) {
+  constexpr int TR = 16 * NBI;
+  constexpr int KC = DPS / 32;                // 32-element k-chunks per plane
+  constexpr int RB = 3 * DPS * 2;             // bytes per split row
+  constexpr int PITCH = RB + 16;
+  constexpr int PPR = RB / 16;
+  constexpr int NPT = TR * PPR / YWG;
+  constexpr int UPT = BN / TR;
+  static_assert(NPT >= 1 && TR * PPR == NPT * YWG, "tile pieces must split evenly");
+  __shared__ __attribute__((aligned(16))) char xs[2][TR * PITCH];
+  __shared__ __attribute__((aligned(16))) float xvs[2][TR];
+  int64_t qt, split;
+  if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
+  const int64_t u0 = split * p.ntiles / p.splits * UPT, u1 = (split + 1) * p.ntiles / p.splits * UPT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const float L2 = 2.f * Lf;
+  const int64_t qrow = qt * BQ + wave * 16 + c;
+  u32x4 yh[KC], ym[KC], yl[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    const char* yr = Ysp + qrow * RB + kc * 64 + g * 16;
+    yh[kc] = *reinterpret_cast<const u32x4*>(yr);
+    ym[kc] = *reinterpret_cast<const u32x4*>(yr + DPS * 2);
+    yl[kc] = *reinterpret_cast<const u32x4*>(yr + DPS * 4);
+  }
+  const double ynq = p.ynorm[qrow];
+  const float yt = KERN == KERNEL_GAUSSIAN ? (float)(-(double)Lf * ynq) : (float)ynq;
+
+  u32x4 xr[NPT];
+  float xvr = 0.f;
+  auto gload = [&](int64_t u) {
+    const char* base = Xsp + u * TR * RB;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int v = threadIdx.x + i * YWG;
+      xr[i] = *reinterpret_cast<const u32x4*>(base + (v / PPR) * RB + (v % PPR) * 16);
+    }
+    if (threadIdx.x < TR) {
+      const int64_t row = u * TR + threadIdx.x;
+      if (KERN == KERNEL_GAUSSIAN)
+        xvr = row < p.n ? (float)(-(double)Lf * p.xnorm[row]) : -__builtin_inff();
+      else
+        xvr = row < p.n ? (float)p.xnorm[row] : __builtin_inff();
+    }
+  };
+  auto lstore = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int v = threadIdx.x + i * YWG;
+      *reinterpret_cast<u32x4*>(&xs[b][(v / PPR) * PITCH + (v % PPR) * 16]) = xr[i];
+    }
+    if (threadIdx.x < TR) xvs[b][threadIdx.x] = xvr;
+  };
+
+  double sum = 0.0;
+  if (u0 < u1) {
+    gload(u0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int64_t u = u0; u < u1; ++u) {
+    const int b = (int)((u - u0) & 1);
+    const bool more = u + 1 < u1;
+    if (more) gload(u + 1);
+    const char* xb = xs[b];
+    f32x4 acc[NBI];
+#pragma unroll
+    for (int bi = 0; bi < NBI; ++bi) acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+#pragma unroll
+      for (int bi = 0; bi < NBI; ++bi) {
+        const char* ar = xb + (bi * 16 + c) * PITCH + kc * 64 + g * 16;
+        const u32x4 ah = *reinterpret_cast<const u32x4*>(ar);
+        const u32x4 am = *reinterpret_cast<const u32x4*>(ar + DPS * 2);
+        const u32x4 al = *reinterpret_cast<const u32x4*>(ar + DPS * 4);
+        f32x4 t = acc[bi];
+        t = mfma_kgroup<__bf16>(al, yh[kc], t);
+        t = mfma_kgroup<__bf16>(am, ym[kc], t);
+        t = mfma_kgroup<__bf16>(ah, yl[kc], t);
+        t = mfma_kgroup<__bf16>(am, yh[kc], t);
+        t = mfma_kgroup<__bf16>(ah, ym[kc], t);
+        acc[bi] = mfma_kgroup<__bf16>(ah, yh[kc], t);
+      }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    if (more) lstore(b ^ 1);
+    const f32x4* xv4 = reinterpret_cast<const f32x4*>(xvs[b]);
+#pragma unroll
+    for (int bp = 0; bp < (NBI + 1) / 2; ++bp) {
+      float part = 0.f;
+#pragma unroll
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const int bi = 2 * bp + h2;
+        if (bi >= NBI) break;
+        const f32x4 xt = xv4[bi * 4 + g];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float kv;
+          if (KERN == KERNEL_GAUSSIAN) {
+            const float a = fminf(__builtin_fmaf(L2, acc[bi][r], yt + xt[r]), 0.f);
+            kv = __builtin_amdgcn_exp2f(a);
+          } else {
+            const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[bi][r], yt + xt[r]), 0.f);
+            kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
+          }
+          part += kv;
+        }
+      }
+      sum += (double)part;
+    }
+    __syncthreads();
+  }
+  sum += __shfl_xor(sum, 16, 64);
+  sum += __shfl_xor(sum, 32, 64);
+  if (g == 0) partial[split * p.qp + qt * BQ + wave * 16 + c] = sum;
+}
+
+#ifndef SPLIT_NBI
+#define SPLIT_NBI 2
+#endif
+
+__global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t splits, int64_t qp,
+                                  int64_t q, double inv_n, const double* __restrict__ ynorm,
+                                  float Lf, int kern, double* __restrict__ out);
+
+template <int KERN, int DPS>
+static void launch_split(const TileProblem& p, const void* Xsp, const void* Ysp, float L,
+                         double* partial, hipStream_t s) {
+  TileProblem q = p;
+  q.map = make_tile_map(p.qtiles, p.splits, 1);
+  constexpr int NBI = DPS == 64 ? 4 : SPLIT_NBI;   // whole 16-byte pieces per thread
+  kde_split_kernel<KERN, DPS, NBI><<<dim3((unsigned)q.map.grid), dim3(YWG), 0, s>>>(
+      q, reinterpret_cast<const char*>(Xsp), reinterpret_cast<const char*>(Ysp), L, partial);
+}
+
+hipError_t launch_kde_exact_split(const TileProblem& p, const void* Xsp, const void* Ysp,
+                                  int64_t dps, int kern, double h, double* partial, double* out,
+                                  hipStream_t s, TimingHook th) {
+  const double log2e = 1.4426950408889634;
+  const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
+  hipError_t e;
+  if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
+  if (dps == 64) {
+    if (kern == KERNEL_GAUSSIAN) launch_split<KERNEL_GAUSSIAN, 64>(p, Xsp, Ysp, L, partial, s);
+    else launch_split<KERNEL_EXPONENTIAL, 64>(p, Xsp, Ysp, L, partial, s);
+  } else if (dps == 128) {
+    if (kern == KERNEL_GAUSSIAN) launch_split<KERNEL_GAUSSIAN, 128>(p, Xsp, Ysp, L, partial, s);
+    else launch_split<KERNEL_EXPONENTIAL, 128>(p, Xsp, Ysp, L, partial, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
+  kde_reduce_kernel<<<dim3((unsigned)ceil_div(p.q, 256)), dim3(256), 0, s>>>(
+      partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, p.ynorm, L, kern, out);
+  return hipGetLastError();
+}
+
 // Sum of the per-split partials in split order, times the Gaussian query
 // factor 2^(rounding remainder of -L ||y||^2), times 1/n.
 __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t splits, int64_t qp,

@@ -32,6 +32,10 @@ hipError_t launch_prep_rows_prec(int prec, const float* src, int64_t rows, int64
                                  double* norm, float* knorm, float* err, uint32_t* err_max,
                                  hipStream_t s);
 
+// Three bfloat16 planes per prepared float32 row (see prep.hip), dps >= dp32.
+hipError_t launch_split_rows(const float* src, int64_t rows, int64_t dp32, int64_t dps,
+                             void* dst, hipStream_t s);
+
 // Optional pair of events recorded around a dense tile kernel (both null: none).
 struct TimingHook {
   hipEvent_t start = nullptr, stop = nullptr;
@@ -39,6 +43,11 @@ struct TimingHook {
 
 hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, double* partial,
                             double* out, hipStream_t s, TimingHook th = {});
+// Exact KDE from the three-part bfloat16 rows (Xsp, Ysp: [rows][3][dps]); p holds
+// the float32 problem (norms, sizes, placement).
+hipError_t launch_kde_exact_split(const TileProblem& p, const void* Xsp, const void* Ysp,
+                                  int64_t dps, int kern, double h, double* partial, double* out,
+                                  hipStream_t s, TimingHook th = {});
 
 // ---- exact k nearest neighbours -------------------------------------------
 struct KnnBuffers {

@@ -152,6 +152,36 @@ hipError_t launch_prep_rows(const float* src, int64_t rows, int64_t rows_padded,
   return hipGetLastError();
 }
 
+// Three bfloat16 parts of every prepared float32 value, v = h + m + l exactly
+// (h the nearest bfloat16 to v, m the nearest to v - h, l = v - h - m, which
+// has at most 8 significant bits): row r holds the planes h, m, l of dps
+// elements each (zeros beyond dp32).
+__global__ void __launch_bounds__(WG) split_rows_kernel(const float* __restrict__ src,
+                                                        int64_t rows, int64_t dp32, int64_t dps,
+                                                        __bf16* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i >= rows * dps) return;
+  const int64_t r = i / dps, t = i % dps;
+  const float v = t < dp32 ? src[r * dp32 + t] : 0.f;
+  const __bf16 h = (__bf16)v;
+  const float rem = v - (float)h;          // exact
+  const __bf16 m = (__bf16)rem;
+  const __bf16 l = (__bf16)(rem - (float)m);   // exact
+  __bf16* out = dst + r * 3 * dps;
+  out[t] = h;
+  out[dps + t] = m;
+  out[2 * dps + t] = l;
+}
+
+hipError_t launch_split_rows(const float* src, int64_t rows, int64_t dp32, int64_t dps,
+                             void* dst, hipStream_t s) {
+  const int64_t total = rows * dps;
+  if (total == 0) return hipSuccess;
+  split_rows_kernel<<<dim3((unsigned)ceil_div(total, WG)), dim3(WG), 0, s>>>(
+      src, rows, dp32, dps, reinterpret_cast<__bf16*>(dst));
+  return hipGetLastError();
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, int64_t count, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = v;

@@ -10,6 +10,11 @@ roundoffs, worst case over summation orders):
   * the kernel constant rounded to FP32 (and the square root of the
     exponential kernel): u_32 d^2 resp. 2 u_32 d in the exponent's units;
   * exp2 and the FP32 tile partial sums: 1e-6 relative.
+The float32-split form (fp32_split) splits every prepared float32 value into
+three bfloat16 parts exactly (v = h + m + l) and accumulates six products per
+element (h h, h m, m h, h l, m m, l h; exact in FP32) with FP32 additions:
+no operand rounding beyond FP32, 6 d_p + 2 accumulated terms in gamma, and the
+three dropped products below 2^-26 |x~||y~| (2^-25 of d^2 after the factor 2).
 With D the sum of the d^2 terms, a Gaussian term is off by at most a factor
 exp((D + u_32 d^2) / (2 h^2)), an exponential one by
 exp((min(sqrt(D), D / d) + 2 u_32 d) / h).  The bound of a query is the
@@ -21,8 +26,12 @@ import oracle
 from oracle import GAUSSIAN
 
 U32 = 2.0 ** -24
-UNIT = {"fp32": 0.0, "bf16": 2.0 ** -8, "fp16": 2.0 ** -11}   # operand rounding beyond FP32
-ELEMS_PER_CHUNK = {"fp32": 32, "bf16": 64, "fp16": 64}        # rows are padded to these
+UNIT = {"fp32": 0.0, "bf16": 2.0 ** -8, "fp16": 2.0 ** -11,   # operand rounding beyond FP32
+        "fp32_split": 0.0}
+ELEMS_PER_CHUNK = {"fp32": 32, "bf16": 64, "fp16": 64,        # rows are padded to these
+                   "fp32_split": 64}
+TERMS_PER_ELEM = {"fp32": 1, "bf16": 1, "fp16": 1, "fp32_split": 6}
+DROPPED = {"fp32": 0.0, "bf16": 0.0, "fp16": 0.0, "fp32_split": 2.0 ** -26}
 
 
 def geometry(X, Y):
@@ -40,11 +49,12 @@ def exact_kde_bound(geo, dim, h, kern, prec):
     up = UNIT[prec] + U32
     per = ELEMS_PER_CHUNK[prec]
     dp = (dim + per - 1) // per * per
-    gam = (dp + 2) * U32 / (1 - (dp + 2) * U32)
+    terms = TERMS_PER_ELEM[prec] * dp + 2
+    gam = terms * U32 / (1 - terms * U32)
     xt, yt = xn * (1 + up), yn * (1 + up)              # bounds on ||x~||, ||y~||
     E = up * (xn[None, :] + yn[:, None])
     d = np.sqrt(d2)
-    D = (2 * d * E + E * E + 2 * gam * xt[None, :] * yt[:, None]
+    D = (2 * d * E + E * E + 2 * (gam + DROPPED[prec]) * xt[None, :] * yt[:, None]
          + 1.5 * U32 * (xt[None, :] ** 2 + yt[:, None] ** 2))
     if kern == GAUSSIAN:
         K = np.exp(-d2 / (2 * h * h))

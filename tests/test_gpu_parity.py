@@ -34,14 +34,17 @@ def c1_exact():
             for kern in (GAUSSIAN, EXPONENTIAL)}
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp32_split"])
 @pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
-def test_exact_kde_fp32_within_1e5(c1, c1_exact, kern):
+def test_exact_kde_fp32_within_1e5(c1, c1_exact, kern, prec):
+    # fp32_split: float32-accurate dot products from three bfloat16 parts
     import paper_2107_02736_amd as dk
     X, Y, Xd, Yd = c1
     h = bandwidth(WL, KNAME[kern])
-    got = dk.kde_exact(Xd, Yd, h, KNAME[kern], "fp32").cpu().numpy()
+    got = dk.kde_exact(Xd, Yd, h, KNAME[kern], prec).cpu().numpy()
     err, excluded = rel_err(got, c1_exact[kern])
-    print(f"exact fp32 {KNAME[kern]}: max rel {err.max():.3e} mean {err.mean():.3e} excluded {excluded}")
+    print(f"exact {prec} {KNAME[kern]}: max rel {err.max():.3e} mean {err.mean():.3e} "
+          f"excluded {excluded}")
     assert err.max() <= 1e-5
 
 
@@ -120,6 +123,30 @@ def _small(n, q, d, seed=0):
     X = (cen[rng.integers(0, 5, n)] + rng.normal(size=(n, d))).astype(np.float32)
     Y = (cen[rng.integers(0, 5, q)] + rng.normal(size=(q, d))).astype(np.float32)
     return X, Y
+
+
+@pytest.mark.parametrize("n,q,d", [(1000, 37, 9), (129, 1, 3), (1, 5, 2), (300, 130, 33),
+                                   (700, 50, 100), (500, 20, 128)])
+def test_edge_shapes_split_exact(dev, n, q, d):
+    # the three-part bfloat16 form: every query within the derived bound and
+    # within the 1e-5 of the float32 path where that bound allows it
+    import paper_2107_02736_amd as dk
+    X, Y = _small(n, q, d, seed=n + d)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h = 2.0 + 0.1 * d
+    ref = oracle.kde_exact(X, Y, h, GAUSSIAN)
+    got = dk.kde_exact(Xd, Yd, h, "gaussian", "fp32_split").cpu().numpy()
+    keep = ref >= 1e-16
+    err = np.abs(got[keep] - ref[keep]) / ref[keep]
+    bound = exact_kde_bound(bound_geometry(X, Y), d, h, GAUSSIAN, "fp32_split")[keep]
+    assert np.all(err <= bound), (err.max(), bound.min())
+
+
+def test_split_precision_width_limit(dev):
+    import paper_2107_02736_amd as dk
+    X, Y = _small(200, 4, 129, seed=1)
+    with pytest.raises(dk.DeannError):
+        dk.kde_exact(to_dev(X, dev), to_dev(Y, dev), 3.0, "gaussian", "fp32_split")
 
 
 @pytest.mark.parametrize("n,q,d", [(1000, 37, 9), (129, 1, 3), (1, 5, 2), (300, 130, 33),

@@ -1,6 +1,6 @@
 """Precision form of the small workload (10-cluster mixture, n = 10,000, d = 16,
 q = 1,000): exact KDE with FP32, BF16 and FP16 operands of the distance GEMM
-(FP32 accumulation), for both kernels at the workload bandwidth scaled by
+(FP32 accumulation) and with float32 operands split into three bfloat16 parts, for both kernels at the workload bandwidth scaled by
 0.25, 1 and 4, against the FP64 oracle; and DEANN with the 16-bit scans, whose
 refined neighbour sets, draws and estimates must equal the FP32 scan's.
 
@@ -45,7 +45,7 @@ def test_precision_exact_and_deann(data, geometry, kern, scale):
     X, Y, Xd, Yd = data
     h = scale * bandwidth(WL, KNAME[kern])
     ref = oracle.kde_exact(X, Y, h, kern)
-    for prec in ("fp32", "bf16", "fp16"):
+    for prec in ("fp32", "fp32_split", "bf16", "fp16"):
         got = dk.kde_exact(Xd, Yd, h, KNAME[kern], prec).cpu().numpy()
         err, excluded = rel_err(got, ref)
         keep = ref >= 1e-16

@@ -259,6 +259,30 @@ def main():
     recall = np.array([np.intersect1d(nn_h[j], nni_h[j]).size / max(K_NN, 1) for j in range(q)])
     del index, C_ivf, a_ivf
 
+    # float32-accurate dot products from three-part bfloat16 MFMAs (not part of
+    # the step): the exact KDE alone and with its gradient, speed and their
+    # difference from the float32 MFMA path
+    ms_split = ms_split_grad = None
+    mus_h = musg_h = None
+    if d <= 128:
+        mus = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32_split")
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            mus = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32_split")
+        b.record()
+        torch.cuda.synchronize()
+        ms_split = a.elapsed_time(b) / reps
+        musg = dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")[0]
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            musg = dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")[0]
+        b.record()
+        torch.cuda.synchronize()
+        ms_split_grad = a.elapsed_time(b) / reps
+        mus_h, musg_h = mus.cpu().numpy(), musg.cpu().numpy()
+
     # exact KDE with BF16 operands (not part of the step): speed and its error
     # against the FP32 exact path (itself within about 1e-6 of the FP64 oracle)
     mu16 = dk.kde_exact(Xd, Yd, h, KERNEL, "bf16")
@@ -271,6 +295,7 @@ def main():
     ms_exact16 = a.elapsed_time(b) / reps
 
     mu_h = mu.cpu().numpy()
+    mu_fwd_h = mu_fwd.cpu().numpy()
     mu16_h = mu16.cpu().numpy()
     est_h, est32_h = est.cpu().numpy(), est32.cpu().numpy()
     same_idx = bool(torch.equal(nn, nn32) and torch.equal(sm, sm32))
@@ -339,6 +364,9 @@ def main():
                                         if fused else None),
             "kde_exact_fp32": q / (ms_exact_fwd * 1e-3),
             "kde_exact_bf16": q / (ms_exact16 * 1e-3),
+            "kde_exact_fp32_split": q / (ms_split * 1e-3) if ms_split else None,
+            "exact_kde_and_grad_fp32_split": (q / (ms_split_grad * 1e-3)
+                                              if ms_split_grad else None),
             "deann_backward": q / (comp_ms["deann_backward"] * 1e-3),
         },
         "accuracy": {
@@ -349,6 +377,12 @@ def main():
             "deann_vs_exact_mean_rel": float(rel_deann_vs_exact.mean()) if keep.any() else None,
             "deann_vs_exact_median_rel": float(np.median(rel_deann_vs_exact)) if keep.any() else None,
             "deann_permuted_vs_exact_mean_rel": float(rel_deannp.mean()) if keep.any() else None,
+            "exact_split_vs_fp32_max_rel": (float(np.max(np.abs(mus_h - mu_fwd_h)[keep]
+                                                         / mu_fwd_h[keep]))
+                                            if mus_h is not None and keep.any() else None),
+            "exact_and_grad_split_vs_fp32_max_rel": (float(np.max(np.abs(musg_h - mu_h)[keep]
+                                                                  / mu_h[keep]))
+                                                     if musg_h is not None and keep.any() else None),
             "queries_below_1e-16": int((~keep).sum()),
         },
         "ivf": {"n_clusters": n_clusters, "n_probe": n_probe, "iters": ivf_iters,

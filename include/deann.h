@@ -137,29 +137,33 @@ int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, i
                          double* grad_h, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Adjoint of kde_exact (FP32 operands only; d <= 128):
+ * Adjoint of kde_exact (d <= 128):
  *   grad_Y[j] = grad_out[j] * (1/n) sum_i dK/dy (x_i, y_j),   [q, d] or NULL
  *   grad_h    = sum_j grad_out[j] * (1/n) sum_i dK/dh,        [1] or NULL.
- * The distance tiles are recomputed on MFMA, never stored.
+ * The distance tiles are recomputed on MFMA, never stored.  precision:
+ * DEANN_FP32 (float32 MFMAs) or DEANN_FP32_SPLIT (the distance product from
+ * three-part bfloat16 operands as in kde_exact; the weighted sum W X on float32
+ * MFMAs either way).
  * ------------------------------------------------------------------------- */
-size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d);
+size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d, int precision);
 int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                       int kernel, const double* grad_out, float* grad_Y, double* grad_h,
-                       void* ws, size_t ws_bytes, void* stream);
+                       int kernel, int precision, const double* grad_out, float* grad_Y,
+                       double* grad_h, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Exact KDE with its derivatives in one pass over the distance tiles (FP32
- * operands; d <= 128), for callers that need both (mean shift, fitting h):
+ * Exact KDE with its derivatives in one pass over the distance tiles (d <= 128;
+ * precision DEANN_FP32 or DEANN_FP32_SPLIT as for kde_exact_backward), for
+ * callers that need both (mean shift, fitting h):
  *   out[j]      = (1/n) sum_i K_h(x_i, y_j)                [q] float64
  *   grad_Y[j]   = d out[j] / d y_j                          [q, d] float32, or NULL
  *   grad_h[j]   = d out[j] / d h                            [q] float64, or NULL
  * i.e. kde_exact, and kde_exact_backward with grad_out = 1 except that the h
  * derivative is returned per query.  Costs one kde_exact_backward.
  * ------------------------------------------------------------------------- */
-size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d);
+size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d, int precision);
 int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                        int kernel, double* out, float* grad_Y, double* grad_h, void* ws,
-                        size_t ws_bytes, void* stream);
+                        int kernel, int precision, double* out, float* grad_Y, double* grad_h,
+                        void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Inverted-file index: the approximate nearest neighbours of the experiments

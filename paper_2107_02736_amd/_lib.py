@@ -73,14 +73,16 @@ def load(path: str = LIB_PATH):
     lib.deann_query_backward.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64, _vp,
                                          _vp, _vp, _vp, _vp, _vp, _sz, _vp]
     lib.kde_exact_backward_workspace.restype = _sz
-    lib.kde_exact_backward_workspace.argtypes = [_i64, _i64, _i64]
+    lib.kde_exact_backward_workspace.argtypes = [_i64, _i64, _i64, _int]
     lib.kde_exact_backward.restype = _int
-    lib.kde_exact_backward.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _vp, _vp, _vp, _vp,
+    lib.kde_exact_backward.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _int, _vp, _vp, _vp,
+                                       _vp,
                                        _sz, _vp]
     lib.kde_exact_with_grad_workspace.restype = _sz
-    lib.kde_exact_with_grad_workspace.argtypes = [_i64, _i64, _i64]
+    lib.kde_exact_with_grad_workspace.argtypes = [_i64, _i64, _i64, _int]
     lib.kde_exact_with_grad.restype = _int
-    lib.kde_exact_with_grad.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _vp, _vp, _vp, _vp,
+    lib.kde_exact_with_grad.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _int, _vp, _vp,
+                                        _vp, _vp,
                                         _sz, _vp]
     lib.mean_shift_update.restype = _int
     lib.mean_shift_update.argtypes = [_vp, _vp, _vp, _i64, _i64, _dbl, _vp, _vp]

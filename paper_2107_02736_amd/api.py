@@ -130,8 +130,9 @@ def deann_query_backward(X, Y, h, k, m, nn_idx, sample_idx, grad_out, kernel="ga
 
 
 def kde_exact_backward(X, Y, h, grad_out, kernel="gaussian", need_grad_y: bool = True,
-                       need_grad_h: bool = True):
-    """(grad_Y float32 [q,d] or None, grad_h float64 [1] or None) of kde_exact (FP32)."""
+                       need_grad_h: bool = True, precision="fp32"):
+    """(grad_Y float32 [q,d] or None, grad_h float64 [1] or None) of kde_exact;
+    precision "fp32" or "fp32_split" (distance product from bfloat16 parts)."""
     _check_xy(X, Y)
     lib = _lib.load()
     n, d = X.shape
@@ -140,17 +141,19 @@ def kde_exact_backward(X, Y, h, grad_out, kernel="gaussian", need_grad_y: bool =
     grad_out = grad_out.to(device=dev, dtype=torch.float64).contiguous()
     gy = torch.empty((q, d), dtype=torch.float32, device=dev) if need_grad_y else None
     gh = torch.empty(1, dtype=torch.float64, device=dev) if need_grad_h else None
-    ws = _workspace(lib.kde_exact_backward_workspace(n, q, d), dev)
+    p = precision_id(precision)
+    ws = _workspace(lib.kde_exact_backward_workspace(n, q, d, p), dev)
     _lib.check(lib.kde_exact_backward(
-        X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), grad_out.data_ptr(),
+        X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), p, grad_out.data_ptr(),
         _ptr(gy), _ptr(gh), ws.data_ptr(), ws.numel(), _stream(dev)))
     return gy, gh
 
 
 def kde_exact_with_grad(X, Y, h, kernel="gaussian", need_grad_y: bool = True,
-                        need_grad_h: bool = True):
-    """Exact KDE and its derivatives in one pass (FP32 tiles, d <= 128):
-    (mu float64 [q], d mu/d y float32 [q,d] or None, d mu/d h float64 [q] or None)."""
+                        need_grad_h: bool = True, precision="fp32"):
+    """Exact KDE and its derivatives in one pass (d <= 128; precision "fp32" or
+    "fp32_split"): (mu float64 [q], d mu/d y float32 [q,d] or None, d mu/d h
+    float64 [q] or None)."""
     _check_xy(X, Y)
     lib = _lib.load()
     n, d = X.shape
@@ -159,9 +162,10 @@ def kde_exact_with_grad(X, Y, h, kernel="gaussian", need_grad_y: bool = True,
     mu = torch.empty(q, dtype=torch.float64, device=dev)
     gy = torch.empty((q, d), dtype=torch.float32, device=dev) if need_grad_y else None
     gh = torch.empty(q, dtype=torch.float64, device=dev) if need_grad_h else None
-    ws = _workspace(lib.kde_exact_with_grad_workspace(n, q, d), dev)
+    p = precision_id(precision)
+    ws = _workspace(lib.kde_exact_with_grad_workspace(n, q, d, p), dev)
     _lib.check(lib.kde_exact_with_grad(X.data_ptr(), n, Y.data_ptr(), q, d, float(h),
-                                       kernel_id(kernel), mu.data_ptr(), _ptr(gy), _ptr(gh),
+                                       kernel_id(kernel), p, mu.data_ptr(), _ptr(gy), _ptr(gh),
                                        ws.data_ptr(), ws.numel(), _stream(dev)))
     return mu, gy, gh
 

@@ -274,10 +274,12 @@ struct KdeBwdPlan {
   Prep prep;
   double* gy_part;
   double* gh_part;   // gh, rw, ks [splits][qp] each, then per-query [q]
+  char *Xsp, *Ysp;   // three-part bfloat16 rows (DEANN_FP32_SPLIT)
+  int64_t dps;
   int64_t bytes;
 };
 
-KdeBwdPlan plan_kde_bwd(void* ws, int64_t n, int64_t q, int64_t d) {
+KdeBwdPlan plan_kde_bwd(void* ws, int64_t n, int64_t q, int64_t d, int precision) {
   Carve cv(ws);
   KdeBwdPlan P{};
   P.prep = carve_prep(cv, n, q, d, DEANN_FP32);
@@ -285,8 +287,32 @@ KdeBwdPlan plan_kde_bwd(void* ws, int64_t n, int64_t q, int64_t d) {
   const int64_t splits = choose_splits(qtiles, ntiles, kKdeSplitTarget);
   P.gy_part = cv.take<double>(splits * P.prep.qp * P.prep.dp);
   P.gh_part = cv.take<double>(3 * splits * P.prep.qp + (q > 0 ? q : 1));
+  if (precision == DEANN_FP32_SPLIT) {
+    P.dps = round_up(d, 64);
+    P.Xsp = cv.take<char>(P.prep.np * 3 * P.dps * 2);
+    P.Ysp = cv.take<char>(P.prep.qp * 3 * P.dps * 2);
+  }
   P.bytes = cv.off + kAlign;
   return P;
+}
+
+bool bad_exact_grad_prec(int p) { return p != DEANN_FP32 && p != DEANN_FP32_SPLIT; }
+
+// Float32 prep (and for DEANN_FP32_SPLIT the bfloat16 parts) of the exact
+// gradient paths; returns the split rows to use (X null: float32).
+hipError_t prep_exact_grad(const KdeBwdPlan& P, const float* X, int64_t n, const float* Y,
+                           int64_t q, int64_t d, int precision, SplitRows& sp, hipStream_t s) {
+  hipError_t e = run_prep(P.prep, X, n, Y, q, d, DEANN_FP32, s);
+  if (e != hipSuccess || precision != DEANN_FP32_SPLIT) return e;
+  e = launch_split_rows(reinterpret_cast<const float*>(P.prep.Xs), P.prep.np, P.prep.dp, P.dps,
+                        P.Xsp, s);
+  if (e == hipSuccess)
+    e = launch_split_rows(reinterpret_cast<const float*>(P.prep.Ys), P.prep.qp, P.prep.dp, P.dps,
+                          P.Ysp, s);
+  sp.X = P.Xsp;
+  sp.Y = P.Ysp;
+  sp.dps = P.dps;
+  return e;
 }
 
 // Align the caller's workspace pointer.
@@ -486,32 +512,35 @@ int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, i
   return DEANN_OK;
 }
 
-size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d) {
-  if (n < 1 || d < 1 || q < 0) return 0;
-  return (size_t)plan_kde_bwd(nullptr, n, q, d).bytes;
+size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d, int precision) {
+  if (n < 1 || d < 1 || q < 0 || bad_exact_grad_prec(precision)) return 0;
+  return (size_t)plan_kde_bwd(nullptr, n, q, d, precision).bytes;
 }
 
 int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                       int kernel, const double* grad_out, float* grad_Y, double* grad_h,
-                       void* ws, size_t ws_bytes, void* stream) {
+                       int kernel, int precision, const double* grad_out, float* grad_Y,
+                       double* grad_h, void* ws, size_t ws_bytes, void* stream) {
   int st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
+  if (bad_exact_grad_prec(precision))
+    return fail(DEANN_EINVAL, "precision must be DEANN_FP32 or DEANN_FP32_SPLIT");
   if (d > 128) return fail(DEANN_EUNSUPPORTED, "kde_exact_backward supports d <= 128");
   if (q == 0) return DEANN_OK;
   if (!grad_out) return fail(DEANN_EINVAL, "grad_out is NULL");
-  const int64_t need = plan_kde_bwd(nullptr, n, q, d).bytes;
+  const int64_t need = plan_kde_bwd(nullptr, n, q, d, precision).bytes;
   if (!ws || (int64_t)ws_bytes < need)
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  KdeBwdPlan P = plan_kde_bwd(align_ws(ws), n, q, d);
-  hipError_t e = run_prep(P.prep, X, n, Y, q, d, DEANN_FP32, s);
+  KdeBwdPlan P = plan_kde_bwd(align_ws(ws), n, q, d, precision);
+  SplitRows sp;
+  hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, kKdeSplitTarget);
   // one 8-wave workgroup per CU: the query tiles of the split-major order
   // already fit the L2 next to the shared data tiles
   tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
   e = launch_kde_backward(tp, Y, d, h, kernel, grad_out, P.gy_part, P.gh_part, grad_Y, grad_h, s,
-                          timer_hook(1));
+                          timer_hook(1), nullptr, nullptr, sp);
   if (e != hipSuccess) return hip_fail(e, "kde backward");
   return DEANN_OK;
 }
@@ -528,29 +557,32 @@ int mean_shift_update(const float* Y, const float* grad_Y, const double* density
   return DEANN_OK;
 }
 
-size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d) {
-  return kde_exact_backward_workspace(n, q, d);
+size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d, int precision) {
+  return kde_exact_backward_workspace(n, q, d, precision);
 }
 
 int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                        int kernel, double* out, float* grad_Y, double* grad_h, void* ws,
-                        size_t ws_bytes, void* stream) {
+                        int kernel, int precision, double* out, float* grad_Y, double* grad_h,
+                        void* ws, size_t ws_bytes, void* stream) {
   int st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
+  if (bad_exact_grad_prec(precision))
+    return fail(DEANN_EINVAL, "precision must be DEANN_FP32 or DEANN_FP32_SPLIT");
   if (d > 128) return fail(DEANN_EUNSUPPORTED, "kde_exact_with_grad supports d <= 128");
   if (q == 0) return DEANN_OK;
   if (!out) return fail(DEANN_EINVAL, "out is NULL");
-  const int64_t need = plan_kde_bwd(nullptr, n, q, d).bytes;
+  const int64_t need = plan_kde_bwd(nullptr, n, q, d, precision).bytes;
   if (!ws || (int64_t)ws_bytes < need)
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  KdeBwdPlan P = plan_kde_bwd(align_ws(ws), n, q, d);
-  hipError_t e = run_prep(P.prep, X, n, Y, q, d, DEANN_FP32, s);
+  KdeBwdPlan P = plan_kde_bwd(align_ws(ws), n, q, d, precision);
+  SplitRows sp;
+  hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, kKdeSplitTarget);
   tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
   e = launch_kde_backward(tp, Y, d, h, kernel, nullptr, P.gy_part, P.gh_part, grad_Y, nullptr, s,
-                          timer_hook(1), out, grad_h);
+                          timer_hook(1), out, grad_h, sp);
   if (e != hipSuccess) return hip_fail(e, "kde value and gradient");
   return DEANN_OK;
 }

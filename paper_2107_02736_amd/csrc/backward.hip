@@ -475,6 +475,216 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
   }
 }
 
+// The same pass with the distance product from three-part bfloat16 rows (see
+// kde_split_kernel): S^T on v_mfma_f32_16x16x32_bf16 (six products per element,
+// float32-accurate), the second product G += W X~ on FP32 MFMAs as above.
+// Data rows are staged 64 at a time: the split rows double-buffered for the
+// first product, the float32 rows of the current 64 for the second (two
+// barriers per staged tile).
+template <int KERN, int DPS, int DP, bool VAL>
+__global__ void __launch_bounds__(BWG, 1)
+kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
+                          const char* __restrict__ Ysp, float L, double* __restrict__ gy_part,
+                          double* __restrict__ rw_part, double* __restrict__ gh_part,
+                          double* __restrict__ ks_part) {
+  using G = GradTile<DP>;
+  constexpr bool KS = VAL && KERN != KERNEL_GAUSSIAN;
+  constexpr int TR = 64, NBI = TR / 16, UPT = BN / TR;
+  constexpr int KC = DPS / 32;                 // 32-element k-chunks per plane
+  constexpr int RB = 3 * DPS * 2;              // bytes per split row
+  constexpr int SPITCH = RB + 16, SPPR = RB / 16, SNPT = TR * SPPR / BWG;
+  constexpr int FNPT = TR * G::PPR / BWG;      // float32 pieces per thread
+  static_assert(SNPT >= 1 && TR * SPPR == SNPT * BWG, "split pieces must split evenly");
+  static_assert(FNPT >= 1 && TR * G::PPR == FNPT * BWG, "row pieces must split evenly");
+  __shared__ __attribute__((aligned(16))) char xs[2][TR * SPITCH];   // split rows
+  __shared__ __attribute__((aligned(16))) char xf[TR * G::PITCH];    // float32 rows
+  __shared__ __attribute__((aligned(16))) float xvs[2][TR];
+  int64_t qt, split;
+  if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
+  const int64_t u0 = split * p.ntiles / p.splits * UPT, u1 = (split + 1) * p.ntiles / p.splits * UPT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+
+  const int64_t qrow = qt * BQ + wave * 16 + c;
+  u32x4 yh[KC], ym[KC], yl[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    const char* yr = Ysp + qrow * RB + kc * 64 + g * 16;
+    yh[kc] = *reinterpret_cast<const u32x4*>(yr);
+    ym[kc] = *reinterpret_cast<const u32x4*>(yr + DPS * 2);
+    yl[kc] = *reinterpret_cast<const u32x4*>(yr + DPS * 4);
+  }
+  const double ynq = p.ynorm[qrow];
+  const float yv = KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * ynq) : (float)ynq;
+
+  u32x4 xr[SNPT], xq[FNPT];
+  float xvr = 0.f;
+  auto gload = [&](int64_t u) {
+    const char* sb = Xsp + u * TR * RB;
+#pragma unroll
+    for (int i = 0; i < SNPT; ++i) {
+      const int v = threadIdx.x + i * BWG;
+      xr[i] = *reinterpret_cast<const u32x4*>(sb + (v / SPPR) * RB + (v % SPPR) * 16);
+    }
+    const char* fb = p.Xs + u * TR * p.ld_bytes;
+#pragma unroll
+    for (int i = 0; i < FNPT; ++i) {
+      const int v = threadIdx.x + i * BWG;
+      xq[i] = *reinterpret_cast<const u32x4*>(fb + (v / G::PPR) * p.ld_bytes + (v % G::PPR) * 16);
+    }
+    if (threadIdx.x < TR) {
+      const int64_t row = u * TR + threadIdx.x;
+      xvr = row < p.n ? (KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * p.xnorm[row])
+                                                 : (float)p.xnorm[row])
+                      : (KERN == KERNEL_GAUSSIAN ? -1e30f : 1e30f);
+    }
+  };
+  auto store_split = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < SNPT; ++i) {
+      const int v = threadIdx.x + i * BWG;
+      *reinterpret_cast<u32x4*>(&xs[b][(v / SPPR) * SPITCH + (v % SPPR) * 16]) = xr[i];
+    }
+    if (threadIdx.x < TR) xvs[b][threadIdx.x] = xvr;
+  };
+  auto store_rows = [&]() {
+#pragma unroll
+    for (int i = 0; i < FNPT; ++i) {
+      const int v = threadIdx.x + i * BWG;
+      *reinterpret_cast<u32x4*>(&xf[(v / G::PPR) * G::PITCH + (v % G::PPR) * 16]) = xq[i];
+    }
+  };
+
+  f32x4 gacc[G::GB];
+#pragma unroll
+  for (int i = 0; i < G::GB; ++i) gacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double rws = 0.0, dhs = 0.0, kss = 0.0;
+
+  if (u0 < u1) {
+    gload(u0);
+    store_split(0);
+    store_rows();
+  }
+  __syncthreads();
+  for (int64_t u = u0; u < u1; ++u) {
+    const int b = (int)((u - u0) & 1);
+    const bool more = u + 1 < u1;
+    if (more) gload(u + 1);
+    const char* xb = xs[b];
+    f32x4 acc[NBI];
+#pragma unroll
+    for (int bi = 0; bi < NBI; ++bi) acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+#pragma unroll
+      for (int bi = 0; bi < NBI; ++bi) {
+        const char* ar = xb + (bi * 16 + c) * SPITCH + kc * 64 + g * 16;
+        const u32x4 ah = *reinterpret_cast<const u32x4*>(ar);
+        const u32x4 am = *reinterpret_cast<const u32x4*>(ar + DPS * 2);
+        const u32x4 al = *reinterpret_cast<const u32x4*>(ar + DPS * 4);
+        f32x4 t = acc[bi];
+        t = mfma_kgroup<__bf16>(al, yh[kc], t);
+        t = mfma_kgroup<__bf16>(am, ym[kc], t);
+        t = mfma_kgroup<__bf16>(ah, yl[kc], t);
+        t = mfma_kgroup<__bf16>(am, yh[kc], t);
+        t = mfma_kgroup<__bf16>(ah, ym[kc], t);
+        acc[bi] = mfma_kgroup<__bf16>(ah, yh[kc], t);
+      }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    if (more) store_split(b ^ 1);   // that buffer was last read before the previous barriers
+
+    const f32x4* xv4 = reinterpret_cast<const f32x4*>(xvs[b]);
+#pragma unroll
+    for (int bp = 0; bp < NBI / 2; ++bp) {
+      float rw32 = 0.f, dh32 = 0.f, ks32 = 0.f;
+#pragma unroll
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const int bi = 2 * bp + h2;
+        const f32x4 xv = xv4[bi * 4 + g];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float sv = acc[bi][r];
+          float w, dh;
+          if (KERN == KERNEL_GAUSSIAN) {
+            const float a = fminf(__builtin_fmaf(2.f * L, sv, yv + xv[r]), 0.f);   // -L d^2
+            const float K = __builtin_amdgcn_exp2f(a);
+            w = K;
+            dh = K * a;
+          } else {
+            const float d2 = fmaxf(__builtin_fmaf(-2.f, sv, yv + xv[r]), 0.f);
+            const float rr = __builtin_sqrtf(d2);
+            const float K = __builtin_amdgcn_exp2f(-L * rr);
+            w = rr > 0.f ? K * __builtin_amdgcn_rcpf(rr) : 0.f;
+            dh = K * rr;
+            if constexpr (KS) ks32 += K;
+          }
+          acc[bi][r] = w;
+          rw32 += w;
+          dh32 += dh;
+        }
+      }
+      rws += (double)rw32;
+      dhs += (double)dh32;
+      if constexpr (KS) kss += (double)ks32;
+    }
+
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int bi = 0; bi < NBI; ++bi) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const char* row = xf + (bi * 16 + 4 * g + r) * G::PITCH;
+        const float w = acc[bi][r];
+#pragma unroll
+        for (int nb = 0; nb < G::NB; ++nb) {
+          const u32x4 xv = *reinterpret_cast<const u32x4*>(row + (nb * 64 + 4 * c) * 4);
+          gacc[4 * nb + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.x), gacc[4 * nb + 0], 0, 0, 0);
+          gacc[4 * nb + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.y), gacc[4 * nb + 1], 0, 0, 0);
+          gacc[4 * nb + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.z), gacc[4 * nb + 2], 0, 0, 0);
+          gacc[4 * nb + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.w), gacc[4 * nb + 3], 0, 0, 0);
+        }
+        if constexpr (G::HB) {
+          const uint2 xv = *reinterpret_cast<const uint2*>(row + (G::NB * 64 + 2 * c) * 4);
+          gacc[4 * G::NB + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.x), gacc[4 * G::NB + 0], 0, 0, 0);
+          gacc[4 * G::NB + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, __uint_as_float(xv.y), gacc[4 * G::NB + 1], 0, 0, 0);
+        }
+      }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    __syncthreads();   // the float32 rows and split buffer b are no longer read
+    if (more) store_rows();
+    __syncthreads();   // staged tile u+1 published
+  }
+
+  rws += __shfl_xor(rws, 16, 64);
+  rws += __shfl_xor(rws, 32, 64);
+  dhs += __shfl_xor(dhs, 16, 64);
+  dhs += __shfl_xor(dhs, 32, 64);
+  if constexpr (KS) {
+    kss += __shfl_xor(kss, 16, 64);
+    kss += __shfl_xor(kss, 32, 64);
+  }
+  const int64_t qbase = split * p.qp + qt * BQ + wave * 16;
+  if (g == 0) {
+    rw_part[qbase + c] = rws;
+    gh_part[qbase + c] = dhs;
+    if constexpr (KS) ks_part[qbase + c] = kss;
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    double* dst = gy_part + (qbase + 4 * g + rr) * DP;
+#pragma unroll
+    for (int nb = 0; nb < G::NB; ++nb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dst[nb * 64 + 4 * c + j] = (double)gacc[4 * nb + j][rr];
+    if constexpr (G::HB)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) dst[G::NB * 64 + 2 * c + j] = (double)gacc[4 * G::NB + j][rr];
+  }
+}
+
 // grad_Y[q] = g_q / n * c_y * f_q * (sum_s G_s[q] - y~_q sum_s rowsum_s[q]) and the
 // per-query h term g_q / n * c_h * f_q * sum_s dh_s[q], where c_y, c_h are the
 // constant factors left out of the tile weights and f_q is the Gaussian query
@@ -521,6 +731,26 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
 }
 
 template <int KERN, bool VAL>
+static hipError_t launch_kde_bwd_split(const TileProblem& p, const SplitRows& sp, int64_t dp,
+                                       float L, double* gy, double* rw, double* gh, double* ks,
+                                       hipStream_t s) {
+  const dim3 g((unsigned)p.map.grid), b(BWG);
+  const char* Xs = reinterpret_cast<const char*>(sp.X);
+  const char* Ys = reinterpret_cast<const char*>(sp.Y);
+  if (sp.dps == 64 && dp == 32)
+    kde_backward_split_kernel<KERN, 64, 32, VAL><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks);
+  else if (sp.dps == 64 && dp == 64)
+    kde_backward_split_kernel<KERN, 64, 64, VAL><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks);
+  else if (sp.dps == 128 && dp == 96)
+    kde_backward_split_kernel<KERN, 128, 96, VAL><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks);
+  else if (sp.dps == 128 && dp == 128)
+    kde_backward_split_kernel<KERN, 128, 128, VAL><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int KERN, bool VAL>
 static hipError_t launch_kde_bwd_k(const TileProblem& p, int64_t dp, float L, double* gy, double* rw,
                                    double* gh, double* ks, hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), b(BWG);
@@ -557,7 +787,7 @@ hipError_t launch_mean_shift_update(const float* Y, const float* g, const double
 hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, double h, int kern,
                                const double* grad_out, double* gy_part, double* gh_part,
                                float* grad_Y, double* grad_h, hipStream_t s, TimingHook th,
-                               double* mu, double* gh_per_query) {
+                               double* mu, double* gh_per_query, SplitRows split) {
   (void)Y;
   const int64_t dp = p.ld_bytes / 4;
   const double log2e = 1.4426950408889634;
@@ -569,11 +799,21 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, 
   const bool val = mu != nullptr;
   hipError_t e;
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
-  if (kern == KERNEL_GAUSSIAN)   // the KDE is the sum of the weights themselves
+  if (split.X) {   // distance product from three-part bfloat16 rows
+    if (kern == KERNEL_GAUSSIAN)
+      e = launch_kde_bwd_split<KERNEL_GAUSSIAN, false>(p, split, dp, L, gy_part, rw_part, gh_part,
+                                                       ks_part, s);
+    else
+      e = val ? launch_kde_bwd_split<KERNEL_EXPONENTIAL, true>(p, split, dp, L, gy_part, rw_part,
+                                                               gh_part, ks_part, s)
+              : launch_kde_bwd_split<KERNEL_EXPONENTIAL, false>(p, split, dp, L, gy_part, rw_part,
+                                                                gh_part, ks_part, s);
+  } else if (kern == KERNEL_GAUSSIAN) {   // the KDE is the sum of the weights themselves
     e = launch_kde_bwd_k<KERNEL_GAUSSIAN, false>(p, dp, L, gy_part, rw_part, gh_part, ks_part, s);
-  else
+  } else {
     e = val ? launch_kde_bwd_k<KERNEL_EXPONENTIAL, true>(p, dp, L, gy_part, rw_part, gh_part, ks_part, s)
             : launch_kde_bwd_k<KERNEL_EXPONENTIAL, false>(p, dp, L, gy_part, rw_part, gh_part, ks_part, s);
+  }
   if (e != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
   // Gaussian: weights K, dh terms K * (-L d^2); exponential: weights K / r, dh terms K r

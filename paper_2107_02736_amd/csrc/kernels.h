@@ -146,10 +146,19 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
                                  const int32_t* samp, const double* grad_out, float* grad_Y,
                                  double* gh_part, double* grad_h, hipStream_t s);
 
+// Three-part bfloat16 rows of the prepared operands ([rows][3][dps], see
+// launch_split_rows); X null: the float32 distance product.
+struct SplitRows {
+  const void* X = nullptr;
+  const void* Y = nullptr;
+  int64_t dps = 0;
+};
+
 hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, double h, int kern,
                                const double* grad_out, double* gy_part, double* gh_part,
                                float* grad_Y, double* grad_h, hipStream_t s, TimingHook th = {},
-                               double* mu = nullptr, double* gh_per_query = nullptr);
+                               double* mu = nullptr, double* gh_per_query = nullptr,
+                               SplitRows split = {});
 
 hipError_t launch_mean_shift_update(const float* Y, const float* g, const double* mu, int64_t q,
                                     int64_t d, double h, float* Y_out, hipStream_t s);

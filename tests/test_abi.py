@@ -75,9 +75,19 @@ def test_backward_validation(lib):
                                   FAKE, FAKE, 1 << 20, None)
     assert st == _lib.EINVAL
     # exact backward beyond d = 128
-    st = lib.kde_exact_backward(FAKE, 100, FAKE, 4, 200, 1.0, 0, FAKE, FAKE, FAKE, FAKE, 1 << 30,
-                                None)
+    st = lib.kde_exact_backward(FAKE, 100, FAKE, 4, 200, 1.0, 0, 0, FAKE, FAKE, FAKE, FAKE,
+                                1 << 30, None)
     assert st == _lib.EUNSUPPORTED
+    # precisions other than FP32 and the float32 split
+    for prec in (1, 2, 7):
+        st = lib.kde_exact_backward(FAKE, 100, FAKE, 4, 8, 1.0, 0, prec, FAKE, FAKE, FAKE, FAKE,
+                                    1 << 30, None)
+        assert st == _lib.EINVAL
+        st = lib.kde_exact_with_grad(FAKE, 100, FAKE, 4, 8, 1.0, 0, prec, FAKE, FAKE, FAKE, FAKE,
+                                     1 << 30, None)
+        assert st == _lib.EINVAL
+    assert lib.kde_exact_with_grad_workspace(1000, 10, 64, 3) > lib.kde_exact_with_grad_workspace(
+        1000, 10, 64, 0)
 
 
 def test_workspace_sizes_grow(lib):

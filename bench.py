@@ -262,7 +262,7 @@ def main():
     # float32-accurate dot products from three-part bfloat16 MFMAs (not part of
     # the step): the exact KDE alone and with its gradient, speed and their
     # difference from the float32 MFMA path
-    ms_split = ms_split_grad = None
+    ms_split = ms_split_grad = ms_step_split = None
     mus_h = musg_h = None
     if d <= 128:
         mus = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32_split")
@@ -282,6 +282,21 @@ def main():
         torch.cuda.synchronize()
         ms_split_grad = a.elapsed_time(b) / reps
         mus_h, musg_h = mus.cpu().numpy(), musg.cpu().numpy()
+        # the whole step with the split exact part (same work, same outputs)
+        for _ in range(max(1, args.warmup)):
+            dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")
+            _, nn_s, sm_s = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
+                                           precision="bf16")
+            dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn_s, sm_s, gout, KERNEL)
+        torch.cuda.synchronize()
+        t0s = time.perf_counter()
+        for _ in range(args.steps):
+            dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")
+            _, nn_s, sm_s = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
+                                           precision="bf16")
+            dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn_s, sm_s, gout, KERNEL)
+        torch.cuda.synchronize()
+        ms_step_split = (time.perf_counter() - t0s) * 1e3 / args.steps
 
     # exact KDE with BF16 operands (not part of the step): speed and its error
     # against the FP32 exact path (itself within about 1e-6 of the FP64 oracle)
@@ -385,6 +400,12 @@ def main():
                                                      if musg_h is not None and keep.any() else None),
             "queries_below_1e-16": int((~keep).sum()),
         },
+        "step_fp32_split": ({"ms_per_step": ms_step_split,
+                             "queries_per_s": q / (ms_step_split * 1e-3),
+                             "note": "the same step with the exact KDE and its gradient from "
+                                     "three-part bfloat16 MFMAs (DEANN_FP32_SPLIT), outside the "
+                                     "timed step above"}
+                            if ms_step_split else None),
         "ivf": {"n_clusters": n_clusters, "n_probe": n_probe, "iters": ivf_iters,
                 "build_s": t1 - t0, "index_s": t2 - t1, "ms": ms_ivf,
                 "queries_per_s": q / (ms_ivf * 1e-3),

@@ -346,9 +346,12 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
     const bool more = u + 1 < u1;
     if (more) gload(u + 1);
     const char* xb = xs[b];
-    f32x4 acc[NBI];
+    f32x4 acc[NBI], accx[NBI];
 #pragma unroll
-    for (int bi = 0; bi < NBI; ++bi) acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int bi = 0; bi < NBI; ++bi) {
+      acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+      accx[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
     __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
@@ -358,15 +361,20 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
         const u32x4 ah = *reinterpret_cast<const u32x4*>(ar);
         const u32x4 am = *reinterpret_cast<const u32x4*>(ar + DPS * 2);
         const u32x4 al = *reinterpret_cast<const u32x4*>(ar + DPS * 4);
-        f32x4 t = acc[bi];
+        f32x4 t = accx[bi];
         t = mfma_kgroup<__bf16>(al, yh[kc], t);
         t = mfma_kgroup<__bf16>(am, ym[kc], t);
         t = mfma_kgroup<__bf16>(ah, yl[kc], t);
         t = mfma_kgroup<__bf16>(am, yh[kc], t);
-        t = mfma_kgroup<__bf16>(ah, ym[kc], t);
-        acc[bi] = mfma_kgroup<__bf16>(ah, yh[kc], t);
+        accx[bi] = mfma_kgroup<__bf16>(ah, ym[kc], t);
+        acc[bi] = mfma_kgroup<__bf16>(ah, yh[kc], acc[bi]);
       }
     }
+    // the leading products and the five small ones accumulate apart: each MFMA
+    // rounds into its accumulator, so the small terms do not round into the
+    // large running sum
+#pragma unroll
+    for (int bi = 0; bi < NBI; ++bi) acc[bi] += accx[bi];
     __builtin_amdgcn_s_setprio(0);
     if (more) lstore(b ^ 1);
     const f32x4* xv4 = reinterpret_cast<const f32x4*>(xvs[b]);

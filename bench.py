@@ -309,15 +309,37 @@ def main():
     torch.cuda.synchronize()
     ms_exact16 = a.elapsed_time(b) / reps
 
+    # near/far form (not part of the step): the k nearest rows exact, the rest
+    # from the BF16 sweep; alone (its own k-NN) and with the step's neighbours
+    muh = dk.kde_hybrid(Xd, Yd, h, K_NN, KERNEL, "bf16")
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        muh = dk.kde_hybrid(Xd, Yd, h, K_NN, KERNEL, "bf16")
+    b.record()
+    torch.cuda.synchronize()
+    ms_hyb = a.elapsed_time(b) / reps
+    muhn = dk.kde_hybrid(Xd, Yd, h, K_NN, KERNEL, "bf16", nn_idx=nn)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        muhn = dk.kde_hybrid(Xd, Yd, h, K_NN, KERNEL, "bf16", nn_idx=nn)
+    b.record()
+    torch.cuda.synchronize()
+    ms_hyb_nn = a.elapsed_time(b) / reps
+
     mu_h = mu.cpu().numpy()
     mu_fwd_h = mu_fwd.cpu().numpy()
     mu16_h = mu16.cpu().numpy()
+    muh_h, muhn_h = muh.cpu().numpy(), muhn.cpu().numpy()
     est_h, est32_h = est.cpu().numpy(), est32.cpu().numpy()
     same_idx = bool(torch.equal(nn, nn32) and torch.equal(sm, sm32))
     keep = mu_h >= 1e-16
     rel_bf16_vs_fp32 = float(np.max(np.abs(est_h - est32_h)[keep] / est32_h[keep])) if keep.any() else 0.0
     rel_deann_vs_exact = np.abs(est_h[keep] - mu_h[keep]) / mu_h[keep]
     rel_exact16 = np.abs(mu16_h[keep] - mu_h[keep]) / mu_h[keep]
+    rel_hyb = np.abs(muh_h[keep] - mu_h[keep]) / mu_h[keep]
+    rel_hyb_nn = np.abs(muhn_h[keep] - mu_h[keep]) / mu_h[keep]
     estp_h = estp.cpu().numpy()
     rel_deannp = np.abs(estp_h[keep] - mu_h[keep]) / mu_h[keep]
     esti_h = esti.cpu().numpy()
@@ -379,6 +401,8 @@ def main():
                                         if fused else None),
             "kde_exact_fp32": q / (ms_exact_fwd * 1e-3),
             "kde_exact_bf16": q / (ms_exact16 * 1e-3),
+            "kde_hybrid_bf16": q / (ms_hyb * 1e-3),
+            "kde_hybrid_bf16_given_neighbours": q / (ms_hyb_nn * 1e-3),
             "kde_exact_fp32_split": q / (ms_split * 1e-3) if ms_split else None,
             "exact_kde_and_grad_fp32_split": (q / (ms_split_grad * 1e-3)
                                               if ms_split_grad else None),
@@ -389,6 +413,10 @@ def main():
             "deann_bf16_vs_fp32_max_rel": rel_bf16_vs_fp32,
             "exact_bf16_vs_fp32_mean_rel": float(rel_exact16.mean()) if keep.any() else None,
             "exact_bf16_vs_fp32_max_rel": float(rel_exact16.max()) if keep.any() else None,
+            "hybrid_bf16_vs_fp32_mean_rel": float(rel_hyb.mean()) if keep.any() else None,
+            "hybrid_bf16_vs_fp32_max_rel": float(rel_hyb.max()) if keep.any() else None,
+            "hybrid_bf16_given_nn_vs_fp32_max_rel": (float(rel_hyb_nn.max()) if keep.any()
+                                                     else None),
             "deann_vs_exact_mean_rel": float(rel_deann_vs_exact.mean()) if keep.any() else None,
             "deann_vs_exact_median_rel": float(np.median(rel_deann_vs_exact)) if keep.any() else None,
             "deann_permuted_vs_exact_mean_rel": float(rel_deannp.mean()) if keep.any() else None,

@@ -166,6 +166,30 @@ int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, in
                         void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Near/far form of the exact KDE (derived from Algorithm 1: the near part is
+ * Z1 over the k nearest rows X1, the far part is summed over all of X2 = X \ X1
+ * instead of being sampled):
+ *   out[j] = (1/n) (Z1_j + sum over X2 of K16_h(x_i, y_j)),
+ * where Z1_j is computed in FP64 from the float32 rows and K16 is the kernel
+ * value of kde_exact with 16-bit operands (precision DEANN_BF16 or DEANN_FP16),
+ * so only the far rows carry the 16-bit operand error.  k = 0 gives
+ * kde_exact with that precision, k = n the exact FP64 sum.
+ *   nn_in   [q, k] int32 neighbour lists to use as X1 (distinct rows of [0, n)
+ *           per query, any order; entries outside [0, n) are left out of both
+ *           parts, repeated rows make Z1 count them again), e.g. the nn_idx
+ *           of deann_query; NULL to compute the exact k nearest rows as
+ *           deann_query does (k <= 496 or k = n, d <= 4096).
+ *   out     [q] float64.
+ *   nn_idx  [q, k] int32, the neighbour lists used (sorted ascending when
+ *           computed here, a copy of nn_in otherwise), or NULL.
+ * Requirements: as kde_exact, plus 0 <= k <= n and q k < 2^31 when 0 < k < n.
+ * ------------------------------------------------------------------------- */
+size_t kde_hybrid_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int precision);
+int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+               int kernel, int64_t k, int precision, const int32_t* nn_in, double* out,
+               int32_t* nn_idx, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Inverted-file index: the approximate nearest neighbours of the experiments
  * (Sec. 5).  k-means over the data gives n_clusters centroids (the paper's
  * n_l); each row belongs to its closest centroid; a query inspects every row
@@ -238,7 +262,8 @@ const char* deann_last_error(void);
  * deann_kernel_timing(capacity): capacity in [1, 4096] makes the calling thread
  * record a pair of HIP events on the call's stream around the dense tile
  * kernel of each following call, for up to `capacity` calls per site:
- *   site 0 = kde_exact, site 1 = kde_exact_backward and kde_exact_with_grad.
+ *   site 0 = kde_exact, site 1 = kde_exact_backward and kde_exact_with_grad,
+ *   site 2 = the 16-bit tile sweep of kde_hybrid.
  * Recording happens only while a site has unread slots left.  capacity = 0
  * stops and releases the events (also done before a new capacity is set).
  * deann_kernel_times(site, ms, max_count): waits for the recorded events,

@@ -25,6 +25,10 @@ Parity status of each function (what pins it in tests/test_oracle_*.py):
   deann_estimate pinned: k=n gives kde_exact, unbiasedness over many seeds,
       variance formula of random sampling with repetition, Bernoulli worst
       case of App. D.
+  kde_near_far pinned: the near part is the sum of the k largest kernel
+      values (a sort of the values, independent of the k-NN), k = 0 and k = n
+      give all-far and all-near, near + far equals the exact KDE computed by a
+      fresh loop, every far value is at most the k-th nearest value.
   permutation, permutation_inverse pinned: bijection of [n] and mutual
       inverses (exhaustive on small n), uniformity of pi over seeds.
   permuted_sample_indices / deann_estimate_permuted pinned: m distinct rows
@@ -247,6 +251,26 @@ def deann_estimate(X: np.ndarray, y: np.ndarray, h: float, kernel: int, k: int, 
     else:
         est = z1 / n
     return est, nn, s_idx
+
+
+def kde_near_far(X: np.ndarray, y: np.ndarray, h: float, kernel: int, k: int,
+                 nn: np.ndarray | None = None):
+    """Near/far split of the exact KDE of one query: (nn_sorted, near, far).
+
+    The split of Algorithm 1 into X1 = the k nearest rows (exact k-NN unless
+    ``nn`` is given) and X2 = the rest, with both parts summed exactly:
+    near = Z1 / n over X1, far = (1/n) sum over all of X2 (no sampling), so
+    near + far is the exact KDE of Eq. (1) for any X1.  The 16-bit form of
+    the library approximates only the far part.
+    """
+    n = X.shape[0]
+    if nn is None:
+        nn = knn(X, y, k)
+    nn = np.sort(np.asarray(nn, dtype=np.int64))
+    kv = kernel_values(sq_dists(X, y), h, kernel)
+    inside = np.zeros(n, dtype=bool)
+    inside[nn] = True
+    return nn, math.fsum(kv[inside]) / n, math.fsum(kv[~inside]) / n
 
 
 # --------------------------------------------------------------------------

@@ -22,6 +22,7 @@ EXPORTS = (
     "deann_query_backward_workspace", "deann_query_backward",
     "kde_exact_backward_workspace", "kde_exact_backward",
     "kde_exact_with_grad_workspace", "kde_exact_with_grad", "mean_shift_update",
+    "kde_hybrid_workspace", "kde_hybrid",
     "ivf_build_workspace", "ivf_build", "ivf_index_bytes", "ivf_index_create_workspace",
     "ivf_index_create", "deann_ivf_query_workspace", "deann_ivf_query",
     "deann_last_error",
@@ -78,6 +79,11 @@ def load(path: str = LIB_PATH):
     lib.kde_exact_backward.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _int, _vp, _vp, _vp,
                                        _vp,
                                        _sz, _vp]
+    lib.kde_hybrid_workspace.restype = _sz
+    lib.kde_hybrid_workspace.argtypes = [_i64, _i64, _i64, _i64, _int]
+    lib.kde_hybrid.restype = _int
+    lib.kde_hybrid.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _int, _vp, _vp, _vp,
+                               _vp, _sz, _vp]
     lib.kde_exact_with_grad_workspace.restype = _sz
     lib.kde_exact_with_grad_workspace.argtypes = [_i64, _i64, _i64, _int]
     lib.kde_exact_with_grad.restype = _int

@@ -88,6 +88,32 @@ def deann_query(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int, kern
     return out, nn, sm
 
 
+def kde_hybrid(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, kernel="gaussian",
+               precision="bf16", nn_idx: torch.Tensor | None = None,
+               return_indices: bool = False):
+    """Near/far exact KDE (float64 [q]): the k nearest rows of each query summed
+    exactly in FP64, the other rows by the 16-bit tile sweep.  nn_idx (int32
+    [q, k]) supplies the neighbour lists instead of computing them; with
+    return_indices the lists used are returned as well."""
+    _check_xy(X, Y)
+    lib = _lib.load()
+    n, d = X.shape
+    q = Y.shape[0]
+    p = precision_id(precision)
+    dev = X.device
+    if nn_idx is not None:
+        if (nn_idx.dtype != torch.int32 or nn_idx.device != dev or not nn_idx.is_contiguous()
+                or tuple(nn_idx.shape) != (q, k)):
+            raise ValueError("nn_idx must be a contiguous int32 [q, k] tensor on X's device")
+    out = torch.empty(q, dtype=torch.float64, device=dev)
+    nn_out = torch.empty((q, k), dtype=torch.int32, device=dev) if return_indices else None
+    ws = _workspace(lib.kde_hybrid_workspace(n, q, d, int(k), p), dev)
+    _lib.check(lib.kde_hybrid(X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel),
+                              int(k), p, _ptr(nn_idx), out.data_ptr(), _ptr(nn_out),
+                              ws.data_ptr(), ws.numel(), _stream(dev)))
+    return (out, nn_out) if return_indices else out
+
+
 def deann_query_permuted(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int,
                          kernel="gaussian", seed: int = 0, start: int = 0, precision="fp32",
                          return_indices: bool = True):
@@ -185,7 +211,7 @@ def mean_shift_update(Y, grad_Y, density, h, out=None):
     return out
 
 
-TIMING_SITES = {"kde_exact": 0, "kde_exact_backward": 1}
+TIMING_SITES = {"kde_exact": 0, "kde_exact_backward": 1, "kde_hybrid": 2}
 
 
 def kernel_timing(capacity: int) -> None:

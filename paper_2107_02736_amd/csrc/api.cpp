@@ -34,11 +34,12 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 // Per-thread event pairs around the dense tile kernels (measurement only).
-constexpr int kTimingSites = 2;   // 0: kde_exact tiles, 1: kde_exact_backward tiles
+// 0: kde_exact tiles, 1: kde_exact_backward / kde_exact_with_grad tiles, 2: kde_hybrid tiles
+constexpr int kTimingSites = 3;
 struct KernelTimer {
   int cap = 0;
-  int used[kTimingSites] = {0, 0};
-  hipEvent_t* ev[kTimingSites] = {nullptr, nullptr};   // [cap][2] per site
+  int used[kTimingSites] = {0, 0, 0};
+  hipEvent_t* ev[kTimingSites] = {nullptr, nullptr, nullptr};   // [cap][2] per site
 };
 thread_local KernelTimer g_timer;
 
@@ -269,6 +270,35 @@ DeannPlan plan_deann(void* ws, int64_t n, int64_t q, int64_t d, int64_t k, int p
   P.bytes = cv.off + kAlign;
   return P;
 }
+
+// Near/far form: the k-NN plan (its prepared 16-bit operands also feed the
+// tile sweep), then the sweep's partials and the neighbour-pair CSR.
+struct HybPlan {
+  DeannPlan dn;
+  double* partial;
+  int32_t *cnt, *off, *tot;
+  uint16_t* hits;
+  int64_t bytes;
+};
+
+HybPlan plan_hybrid(void* ws, int64_t n, int64_t q, int64_t d, int64_t k, int prec) {
+  HybPlan H{};
+  H.dn = plan_deann(ws, n, q, d, k, prec);
+  const int64_t head = round_up(H.dn.bytes, kAlign);
+  Carve cv(ws ? static_cast<char*>(ws) + head : nullptr);
+  const int64_t qtiles = H.dn.prep.qp / BQ, ntiles = H.dn.prep.np / BN;
+  const int64_t splits = choose_splits(qtiles, ntiles, kKdeSplitTarget);
+  H.partial = cv.take<double>(splits * H.dn.prep.qp);
+  const int64_t keys = qtiles * ntiles;
+  H.cnt = cv.take<int32_t>(keys);
+  H.off = cv.take<int32_t>(keys + 1);
+  H.tot = cv.take<int32_t>(scan_blocks(keys));
+  H.hits = cv.take<uint16_t>(k > 0 && k < n ? q * k : 1);
+  H.bytes = head + cv.off + kAlign;
+  return H;
+}
+
+bool bad_hyb_prec(int p) { return p != DEANN_BF16 && p != DEANN_FP16; }
 
 struct KdeBwdPlan {
   Prep prep;
@@ -554,6 +584,81 @@ int mean_shift_update(const float* Y, const float* grad_Y, const double* density
   const hipError_t e = launch_mean_shift_update(Y, grad_Y, density, q, d, h, Y_out,
                                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "mean shift update");
+  return DEANN_OK;
+}
+
+size_t kde_hybrid_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int precision) {
+  if (n < 1 || d < 1 || q < 0 || k < 0 || k > n || bad_hyb_prec(precision)) return 0;
+  return (size_t)plan_hybrid(nullptr, n, q, d, k, precision).bytes;
+}
+
+int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+               int kernel, int64_t k, int precision, const int32_t* nn_in, double* out,
+               int32_t* nn_idx, void* ws, size_t ws_bytes, void* stream) {
+  int st = check_common(X, n, Y, q, d, h, kernel);
+  if (st != DEANN_OK) return st;
+  if (bad_hyb_prec(precision))
+    return fail(DEANN_EINVAL, "kde_hybrid takes DEANN_BF16 or DEANN_FP16 (got %d)", precision);
+  if (k < 0 || k > n) return fail(DEANN_EINVAL, "k must be in [0, n] (got %lld)", (long long)k);
+  if (!nn_in && k > kMaxK && k != n)
+    return fail(DEANN_EUNSUPPORTED, "k = %lld: supported are k <= %lld and k = n", (long long)k,
+                (long long)kMaxK);
+  if (!nn_in && k > 0 && d > 4096)
+    return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported by the k-NN of kde_hybrid");
+  if (k > 0 && k < n && q * k >= ((int64_t)1 << 31))
+    return fail(DEANN_EUNSUPPORTED, "q * k must be < 2^31");
+  if (q == 0) return DEANN_OK;
+  if (!out) return fail(DEANN_EINVAL, "out is NULL");
+  const int64_t need = plan_hybrid(nullptr, n, q, d, k, precision).bytes;
+  if (!ws || (int64_t)ws_bytes < need)
+    return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HybPlan H = plan_hybrid(align_ws(ws), n, q, d, k, precision);
+  hipError_t e;
+  if (k == n) {   // every row is near: the exact FP64 sum
+    if (nn_in) {
+      e = launch_knn_list_sum(X, Y, n, q, d, h, kernel, nn_in, k, H.dn.kb.z1, s);
+      if (e == hipSuccess && nn_idx)
+        e = hipMemcpyAsync(nn_idx, nn_in, (size_t)(q * k) * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, s);
+    } else {
+      e = launch_knn_all(X, Y, n, q, d, h, kernel, nn_idx ? nn_idx : H.dn.nn_internal,
+                         H.dn.kb.z1, s);
+    }
+    if (e == hipSuccess)
+      e = launch_sample(X, Y, n, q, d, h, kernel, k, 0, 0, 0, 0, 0, 0, nullptr, H.dn.kb.z1, out,
+                        nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "kde_hybrid (k = n)");
+    return DEANN_OK;
+  }
+  e = run_prep(H.dn.prep, X, n, Y, q, d, precision, s);
+  if (e != hipSuccess) return hip_fail(e, "prep");
+  TileProblem tk = make_problem(H.dn.prep, n, q, precision, kKdeSplitTarget);
+  if (k == 0) {   // nothing is near: the 16-bit sweep of kde_exact
+    e = launch_kde_exact(precision, tk, kernel, h, H.partial, out, s, timer_hook(2));
+    if (e != hipSuccess) return hip_fail(e, "kde_hybrid (k = 0)");
+    return DEANN_OK;
+  }
+  const int32_t* nn_use = nn_in;
+  if (nn_in) {
+    e = launch_knn_list_sum(X, Y, n, q, d, h, kernel, nn_in, k, H.dn.kb.z1, s);
+    if (e == hipSuccess && nn_idx)
+      e = hipMemcpyAsync(nn_idx, nn_in, (size_t)(q * k) * sizeof(int32_t),
+                         hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "neighbour sum");
+  } else {
+    H.dn.kb.nn_work = nn_idx ? nn_idx : H.dn.nn_internal;
+    TileProblem tp = make_problem(H.dn.prep, n, q, precision, kKnnSplitTarget);
+    TileProblem tc = make_problem(H.dn.prep, n, q, precision, kCollectSplitTarget);
+    e = launch_knn(precision, tp, tc, H.dn.kb, X, Y, d, k, h, kernel, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "knn");
+    nn_use = H.dn.kb.nn_work;
+  }
+  e = launch_hybrid_hits(nn_use, q, k, n, tk.qtiles, tk.ntiles, H.cnt, H.off, H.tot, H.hits, s);
+  if (e != hipSuccess) return hip_fail(e, "neighbour pairs");
+  e = launch_kde_hybrid(precision, tk, kernel, h, H.off, H.hits, H.dn.kb.z1, H.partial, out, s,
+                        timer_hook(2));
+  if (e != hipSuccess) return hip_fail(e, "kde_hybrid");
   return DEANN_OK;
 }
 

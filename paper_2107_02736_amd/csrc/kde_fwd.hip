@@ -22,19 +22,47 @@
 
 namespace deann {
 
-template <typename T, int KERN, int ENG>   // ENG: see tile_engine
+template <bool B>
+struct BoolTag {
+  static constexpr bool value = B;
+};
+
+// Neighbour pairs staged in LDS per workgroup (near/far form); a workgroup
+// whose tiles hold more reads them from global memory.
+constexpr int HYB_LDS = 1024;
+
+// HYB: near/far form.  hoff[(qt * ntiles + t) .. + 1] delimit the entries
+// (query mod 128) << 7 | (row mod 128) in hits of the neighbour pairs of query
+// tile qt in data tile t; those elements are left out of the sums.
+template <typename T, int KERN, int ENG, bool HYB>   // ENG: see tile_engine
 __global__ void __launch_bounds__(WG, 2)
 kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_t ld_bytes,
                 int nchunks, const double* __restrict__ ynorm, const double* __restrict__ xnorm,
                 int64_t n, int64_t qtiles, int64_t splits, int64_t ntiles, float Lf,
-                double* __restrict__ partial, int64_t qp, TileMap map) {
+                double* __restrict__ partial, int64_t qp, TileMap map,
+                const int32_t* __restrict__ hoff, const uint16_t* __restrict__ hits) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
+  __shared__ uint16_t hl[HYB ? HYB_LDS : 1];
   int64_t qt, split;
   if (!map_tile(blockIdx.x, map, qtiles, splits, qt, split)) return;
   const int64_t t0 = split * ntiles / splits, t1 = (split + 1) * ntiles / splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
   const float L2 = 2.f * Lf;
+
+  // the neighbour pairs of this workgroup's tiles are contiguous in hits; the
+  // barrier inside the first tile sweep publishes the LDS copy
+  int32_t hbase = 0;
+  bool hlds = true;
+  if constexpr (HYB) {
+    if (t0 < t1) {
+      hbase = hoff[qt * ntiles + t0];
+      const int32_t hcnt = hoff[qt * ntiles + t1] - hbase;
+      hlds = hcnt <= HYB_LDS;
+      if (hlds)
+        for (int i = threadIdx.x; i < hcnt; i += WG) hl[i] = hits[hbase + i];
+    }
+  }
 
   // per-row query terms (see the file comment)
   float yt[4][4];
@@ -87,6 +115,20 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       ql_tile<T>(acc, ql, Xs, t, t1, lds, wq, wn, lane);
     else
       yreg_tile<T, NK>(acc, xs, yf, Xs, ld_bytes, t, t1, lds, wn, lane);
+    // bit (4 i + j) * 4 + r of hm: element acc[i][j][r] of this lane is a
+    // neighbour pair
+    uint64_t hm = 0;
+    if constexpr (HYB) {
+      const int32_t ha = hoff[qt * ntiles + t] - hbase, hb = hoff[qt * ntiles + t + 1] - hbase;
+      for (int32_t e = ha; e < hb; ++e) {
+        const unsigned v = hlds ? hl[e] : hits[hbase + e];
+        const int ql_ = (int)(v >> 7), cl = (int)(v & 127);
+        const bool own = (ql_ >> 6) == wq && (cl >> 6) == wn &&
+                         lane == ((((ql_ & 15) >> 2) << 4) | (cl & 15));
+        if (own)
+          hm |= 1ull << (((((ql_ & 63) >> 4) << 2) + ((cl & 63) >> 4)) * 4 + (ql_ & 3));
+      }
+    }
     // per-column data terms; padding columns get a term that zeroes the kernel
     float xt[4];
 #pragma unroll
@@ -98,26 +140,35 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       else
         xt[j] = col < n ? (float)xn : __builtin_inff();
     }
+    auto epilogue = [&](auto tag) {
+      constexpr bool MASK = decltype(tag)::value;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < 4; ++i) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float part = 0.f;
+        for (int r = 0; r < 4; ++r) {
+          float part = 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          float kv;
-          if (KERN == KERNEL_GAUSSIAN) {   // exp(-d^2 / (2 h^2))
-            const float a = fminf(__builtin_fmaf(L2, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
-            kv = __builtin_amdgcn_exp2f(a);
-          } else {                          // exp(-d / h)
-            const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
-            kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
+          for (int j = 0; j < 4; ++j) {
+            float kv;
+            if (KERN == KERNEL_GAUSSIAN) {   // exp(-d^2 / (2 h^2))
+              const float a = fminf(__builtin_fmaf(L2, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
+              kv = __builtin_amdgcn_exp2f(a);
+            } else {                          // exp(-d / h)
+              const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
+              kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
+            }
+            if constexpr (MASK)
+              if ((hm >> ((i * 4 + j) * 4 + r)) & 1ull) kv = 0.f;
+            part += kv;
           }
-          part += kv;
+          sum[i][r] += (double)part;
         }
-        sum[i][r] += (double)part;
       }
-    }
+    };
+    if (HYB && __any(hm != 0ull))
+      epilogue(BoolTag<true>{});
+    else
+      epilogue(BoolTag<false>{});
   }
   __syncthreads();
 
@@ -414,7 +465,8 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
 
 __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t splits, int64_t qp,
                                   int64_t q, double inv_n, const double* __restrict__ ynorm,
-                                  float Lf, int kern, double* __restrict__ out);
+                                  float Lf, int kern, const double* __restrict__ add,
+                                  double* __restrict__ out);
 
 template <int KERN, int DPS>
 static void launch_split(const TileProblem& p, const void* Xsp, const void* Ysp, float L,
@@ -445,15 +497,17 @@ hipError_t launch_kde_exact_split(const TileProblem& p, const void* Xsp, const v
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
   kde_reduce_kernel<<<dim3((unsigned)ceil_div(p.q, 256)), dim3(256), 0, s>>>(
-      partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, p.ynorm, L, kern, out);
+      partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, p.ynorm, L, kern, nullptr, out);
   return hipGetLastError();
 }
 
 // Sum of the per-split partials in split order, times the Gaussian query
-// factor 2^(rounding remainder of -L ||y||^2), times 1/n.
+// factor 2^(rounding remainder of -L ||y||^2), plus add[i] (the exact sum over
+// the neighbours in the near/far form; NULL otherwise), times 1/n.
 __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t splits, int64_t qp,
                                   int64_t q, double inv_n, const double* __restrict__ ynorm,
-                                  float Lf, int kern, double* __restrict__ out) {
+                                  float Lf, int kern, const double* __restrict__ add,
+                                  double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= q) return;
   double s = 0.0;
@@ -462,14 +516,16 @@ __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t sp
     const double e = -(double)Lf * ynorm[i];
     s *= exp2(e - (double)(float)e);
   }
+  if (add) s += add[i];
   out[i] = s * inv_n;
 }
 
-template <typename T, int KERN, int ENG>
-static void launch_kde_k(const TileProblem& p, float L, double* partial, hipStream_t s) {
-  kde_tile_kernel<T, KERN, ENG><<<dim3((unsigned)p.map.grid), dim3(WG), 0, s>>>(
+template <typename T, int KERN, int ENG, bool HYB = false>
+static void launch_kde_k(const TileProblem& p, float L, double* partial, hipStream_t s,
+                         const int32_t* hoff = nullptr, const uint16_t* hits = nullptr) {
+  kde_tile_kernel<T, KERN, ENG, HYB><<<dim3((unsigned)p.map.grid), dim3(WG), 0, s>>>(
       p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
-      partial, p.qp, p.map);
+      partial, p.qp, p.map, hoff, hits);
 }
 
 template <typename T, int KERN>
@@ -480,6 +536,24 @@ static void launch_kde_n(const TileProblem& p, float L, double* partial, hipStre
     if (eng == 1) return launch_kde_k<T, KERN, 1>(p, L, partial, s);
   }
   launch_kde_k<T, KERN, 0>(p, L, partial, s);
+}
+
+template <typename T, int KERN>
+static void launch_hyb_n(const TileProblem& p, float L, double* partial, const int32_t* hoff,
+                         const uint16_t* hits, hipStream_t s) {
+  const int eng = tile_engine<T>(p.ld_bytes);
+  if (eng == 2) return launch_kde_k<T, KERN, 2, true>(p, L, partial, s, hoff, hits);
+  if (eng == 1) return launch_kde_k<T, KERN, 1, true>(p, L, partial, s, hoff, hits);
+  launch_kde_k<T, KERN, 0, true>(p, L, partial, s, hoff, hits);
+}
+
+template <typename T>
+static void launch_hyb_t(const TileProblem& p, int kern, float L, double* partial,
+                         const int32_t* hoff, const uint16_t* hits, hipStream_t s) {
+  if (kern == KERNEL_GAUSSIAN)
+    launch_hyb_n<T, KERNEL_GAUSSIAN>(p, L, partial, hoff, hits, s);
+  else
+    launch_hyb_n<T, KERNEL_EXPONENTIAL>(p, L, partial, hoff, hits, s);
 }
 
 template <int KERN, int DP>
@@ -530,7 +604,27 @@ hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, 
   if (e != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
   kde_reduce_kernel<<<dim3((unsigned)ceil_div(p.q, 256)), dim3(256), 0, s>>>(
-      partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, p.ynorm, L, kern, out);
+      partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, p.ynorm, L, kern, nullptr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_kde_hybrid(int prec, const TileProblem& p, int kern, double h,
+                             const int32_t* hoff, const uint16_t* hits, const double* z1,
+                             double* partial, double* out, hipStream_t s, TimingHook th) {
+  const double log2e = 1.4426950408889634;
+  const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
+  hipError_t e;
+  if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
+  if (prec == PREC_BF16)
+    launch_hyb_t<__bf16>(p, kern, L, partial, hoff, hits, s);
+  else if (prec == PREC_FP16)
+    launch_hyb_t<_Float16>(p, kern, L, partial, hoff, hits, s);
+  else
+    return hipErrorInvalidValue;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
+  kde_reduce_kernel<<<dim3((unsigned)ceil_div(p.q, 256)), dim3(256), 0, s>>>(
+      partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, p.ynorm, L, kern, z1, out);
   return hipGetLastError();
 }
 

@@ -74,6 +74,23 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
 
 hipError_t launch_knn_all(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                           double h, int kern, int32_t* nn, double* z1, hipStream_t s);
+// Z1 over given neighbour lists nn[q][k] (entries outside [0, n) skipped).
+hipError_t launch_knn_list_sum(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
+                               double h, int kern, const int32_t* nn, int64_t k, double* z1,
+                               hipStream_t s);
+
+// ---- near/far form of the exact KDE ----------------------------------------
+// CSR of the neighbour pairs per (query tile, data tile): cnt [qtiles * ntiles]
+// scratch, off [qtiles * ntiles + 1], tot [scan_blocks(qtiles * ntiles)],
+// hits [q * k] entries (query mod 128) << 7 | (row mod 128).
+int64_t scan_blocks(int64_t count);
+hipError_t launch_hybrid_hits(const int32_t* nn, int64_t q, int64_t k, int64_t n, int64_t qtiles,
+                              int64_t ntiles, int32_t* cnt, int32_t* off, int32_t* tot,
+                              uint16_t* hits, hipStream_t s);
+// 16-bit tile sweep without the listed pairs, then out = (sum + z1) / n.
+hipError_t launch_kde_hybrid(int prec, const TileProblem& p, int kern, double h,
+                             const int32_t* hoff, const uint16_t* hits, const double* z1,
+                             double* partial, double* out, hipStream_t s, TimingHook th = {});
 
 // ---- inverted-file neighbours --------------------------------------------------
 int64_t ivf_hist_blocks(int64_t n);

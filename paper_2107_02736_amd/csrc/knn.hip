@@ -792,6 +792,43 @@ hipError_t launch_knn_all(const float* X, const float* Y, int64_t n, int64_t q, 
   return hipGetLastError();
 }
 
+// Z1 over given neighbour lists nn[q][k]: FP64 kernel sum in a fixed order
+// (16-lane groups take every 16th entry, then the groups in order); entries
+// outside [0, n) are skipped.
+__global__ void __launch_bounds__(WG)
+knn_list_sum_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
+                    int64_t d, double h, int kern, const int32_t* __restrict__ nn, int64_t k,
+                    double* __restrict__ z1) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  double* red = reinterpret_cast<double*>(smem);   // WG / 16
+  float* ys = reinterpret_cast<float*>(red + WG / 16);
+  const int64_t qi = blockIdx.x;
+  for (int64_t t = threadIdx.x; t < d; t += WG) ys[t] = Y[qi * d + t];
+  __syncthreads();
+  const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  double s = 0.0;
+  for (int64_t j = g; j < k; j += WG / 16) {
+    const int32_t r = nn[qi * k + j];
+    if (r >= 0 && r < n) s += kernel_value(group16_d2(X, r, d, ys, l16), h, kern);
+  }
+  if (l16 == 0) red[g] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < WG / 16; ++i) t += red[i];
+    z1[qi] = t;
+  }
+}
+
+hipError_t launch_knn_list_sum(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
+                               double h, int kern, const int32_t* nn, int64_t k, double* z1,
+                               hipStream_t s) {
+  if (q == 0) return hipSuccess;
+  const size_t sm = (WG / 16) * 8 + d * 4 + 16;
+  knn_list_sum_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(X, Y, n, d, h, kern, nn, k, z1);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // host launch
 // ---------------------------------------------------------------------------

@@ -228,7 +228,10 @@ hipError_t launch_sample(const float* X, const float* Y, int64_t n, int64_t q, i
                          const int32_t* nn_sorted, const double* z1, double* out,
                          int32_t* sample_idx, hipStream_t s) {
   if (q == 0) return hipSuccess;
-  const int64_t kp = permuted ? next_pow2_i(k) : k;
+  // without draws (m = 0 or k = n) the kernel only writes Z1 / n and needs no
+  // gap table, whose size would otherwise grow with k
+  const bool draws = m > 0 && k < n;
+  const int64_t kp = !draws ? 0 : permuted ? next_pow2_i(k) : k;
   const size_t sm = DRAW_CHUNK * (8 + 4) + kp * 4 + d * 4 + 16;
   deann_sample_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(
       X, Y, n, d, h, kern, k, m, seed, query_offset, word2, permuted, start, nn_sorted, z1, out,

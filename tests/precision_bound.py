@@ -18,7 +18,8 @@ three dropped products below 2^-26 |x~||y~| (2^-25 of d^2 after the factor 2).
 With D the sum of the d^2 terms, a Gaussian term is off by at most a factor
 exp((D + u_32 d^2) / (2 h^2)), an exponential one by
 exp((min(sqrt(D), D / d) + 2 u_32 d) / h).  The bound of a query is the
-kernel-weighted mean of those factors minus one, plus the 1e-6.
+kernel-weighted mean of those factors minus one, plus the 1e-6.  In the
+near/far form the terms of the neighbours are exact (FP64) and leave the mean.
 """
 import numpy as np
 
@@ -43,8 +44,13 @@ def geometry(X, Y):
     return xn, yn, d2
 
 
-def exact_kde_bound(geo, dim, h, kern, prec):
-    """Per-query relative error bound (see the module docstring); geo from geometry()."""
+def exact_kde_bound(geo, dim, h, kern, prec, near=None):
+    """Per-query relative error bound (see the module docstring); geo from geometry().
+
+    near: [q, k] rows of each query whose kernel values are exact (the near
+    part of the near/far form, FP64 from the float32 rows); their terms drop
+    out of the bound, and the 1e-6 applies to the far share of the sum only.
+    """
     xn, yn, d2 = geo
     up = UNIT[prec] + U32
     per = ELEMS_PER_CHUNK[prec]
@@ -63,6 +69,11 @@ def exact_kde_bound(geo, dim, h, kern, prec):
         K = np.exp(-d / h)
         f = np.expm1((np.minimum(np.sqrt(D), D / np.maximum(d, 1e-300)) + 2 * U32 * d) / h)
     w = K.sum(1)
+    far = np.ones_like(K, dtype=bool)
+    if near is not None:
+        for j, rows in enumerate(near):
+            far[j, np.asarray(rows, dtype=np.int64)] = False
     with np.errstate(invalid="ignore", divide="ignore"):
-        b = (K * f).sum(1) / w
-    return b + 1e-6
+        b = (K * f * far).sum(1) / w
+        share = (K * far).sum(1) / w
+    return b + 1e-6 * share + 1e-12

@@ -139,3 +139,30 @@ def test_ivf_build_and_index_validation(lib):
     assert lib.ivf_index_bytes(1000, 3, 20) > lib.ivf_index_bytes(1000, 3, 10)
     assert lib.ivf_build_workspace(1000, 3, 0) == 0
     assert lib.deann_ivf_query_workspace(1000, 4, 3, 10, 11, 5, 10) == 0
+
+
+def _hyb(lib, n=1000, q=4, d=3, h=1.0, kernel=0, k=5, prec=1, nn_in=None, out=FAKE, ws=FAKE,
+         wsb=1 << 34):
+    return lib.kde_hybrid(FAKE, n, FAKE, q, d, h, kernel, k, prec, nn_in, out, None, ws, wsb, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(prec=0), _lib.EINVAL), (dict(prec=3), _lib.EINVAL), (dict(k=-1), _lib.EINVAL),
+    (dict(k=1001), _lib.EINVAL), (dict(kernel=5), _lib.EINVAL), (dict(out=None), _lib.EINVAL),
+    (dict(k=600), _lib.EUNSUPPORTED), (dict(d=5000), _lib.EUNSUPPORTED),
+    (dict(n=1 << 30, q=1 << 24, k=200), _lib.EUNSUPPORTED), (dict(wsb=64), _lib.EWORKSPACE),
+    (dict(ws=None), _lib.EWORKSPACE),
+])
+def test_kde_hybrid_validation(lib, kw, status):
+    assert _hyb(lib, **kw) == status
+    assert lib.deann_last_error().decode()
+
+
+def test_kde_hybrid_given_neighbours_lift_the_knn_limits(lib):
+    # with the lists supplied no k-NN runs, so k > 496 and d > 4096 pass validation
+    # (and fail only at the deliberately short workspace)
+    assert _hyb(lib, k=600, nn_in=FAKE, wsb=64) == _lib.EWORKSPACE
+    assert _hyb(lib, d=5000, nn_in=FAKE, wsb=64) == _lib.EWORKSPACE
+    assert _hyb(lib, q=0, out=None, ws=None, wsb=0) == _lib.OK
+    assert lib.kde_hybrid_workspace(1000, 4, 3, 5, 0) == 0
+    assert lib.kde_hybrid_workspace(1000, 4, 3, 5, 1) > lib.kde_exact_workspace(1000, 4, 3, 1)

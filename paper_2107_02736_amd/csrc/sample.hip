@@ -111,12 +111,16 @@ __device__ __forceinline__ double kval(double d2, double h, int kern) {
   return exp(-sqrt(d2) / h);
 }
 
+// PERM: permuted blocks (App. G) instead of draws with repetition; a template
+// argument so that the draw loop of the plain sampler carries none of it.
+template <bool PERM>
 __global__ void __launch_bounds__(WG)
 deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
                     int64_t d, double h, int kern, int64_t k, int64_t m, uint64_t seed,
-                    uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
+                    uint64_t query_offset, uint64_t word2, uint64_t start,
                     const int32_t* __restrict__ nn_sorted, const double* __restrict__ z1,
                     double* __restrict__ out, int32_t* __restrict__ sample_idx) {
+  constexpr bool permuted = PERM;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int kp = permuted ? next_pow2_i(k) : (int)k;   // sorted in place when permuted
   double* kv = reinterpret_cast<double*>(smem);                    // DRAW_CHUNK
@@ -138,7 +142,7 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
   // running index l = (start + i m) mod n
   const int bits = perm_bits(n);
   const int64_t run = permuted ? (int64_t)((start % (uint64_t)n + ((uint64_t)qi * (uint64_t)m) % (uint64_t)n) % (uint64_t)n) : 0;
-  if (permuted) {
+  if constexpr (permuted) {
     for (int t = threadIdx.x; t < kp; t += WG)
       gaps[t] = t < k ? (int32_t)((permute(nn_sorted[qi * k + t], n, bits, seed, true) - run + n) % n)
                       : INT32_MAX;
@@ -161,7 +165,7 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
     for (int b = threadIdx.x; b * 4 < cnt; b += WG) {
       const int64_t jb = (j0 >> 2) + b;     // j0 is a multiple of 4
       Philox4x64 blk;
-      if (!permuted) blk = philox4x64_10(seed, 0, (uint64_t)jb, stream, word2, 0);
+      if constexpr (!permuted) blk = philox4x64_10(seed, 0, (uint64_t)jb, stream, word2, 0);
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         const int jj = b * 4 + w;
@@ -233,9 +237,14 @@ hipError_t launch_sample(const float* X, const float* Y, int64_t n, int64_t q, i
   const bool draws = m > 0 && k < n;
   const int64_t kp = !draws ? 0 : permuted ? next_pow2_i(k) : k;
   const size_t sm = DRAW_CHUNK * (8 + 4) + kp * 4 + d * 4 + 16;
-  deann_sample_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(
-      X, Y, n, d, h, kern, k, m, seed, query_offset, word2, permuted, start, nn_sorted, z1, out,
-      sample_idx);
+  if (permuted)
+    deann_sample_kernel<true><<<dim3((unsigned)q), dim3(WG), sm, s>>>(
+        X, Y, n, d, h, kern, k, m, seed, query_offset, word2, start, nn_sorted, z1, out,
+        sample_idx);
+  else
+    deann_sample_kernel<false><<<dim3((unsigned)q), dim3(WG), sm, s>>>(
+        X, Y, n, d, h, kern, k, m, seed, query_offset, word2, start, nn_sorted, z1, out,
+        sample_idx);
   return hipGetLastError();
 }
 

@@ -62,6 +62,35 @@ def test_fullsize_deann_and_exact(big, kern):
             assert abs(mu[j] - ref) <= 1e-5 * ref
 
 
+def test_fullsize_near_far(big):
+    # the near/far exact KDE in the benchmark's configuration (BF16, k = 100):
+    # its neighbour lists are DEANN's on every query; sampled queries against
+    # the oracle's k-NN and the exact KDE within the bound without the exact
+    # neighbour terms
+    import paper_2107_02736_amd as dk
+    from .precision_bound import exact_kde_bound, geometry as bound_geometry
+    X, Y, Xd, Yd = big
+    h = bandwidth(WL, "gaussian")
+    got, nn = dk.kde_hybrid(Xd, Yd, h, 100, "gaussian", "bf16", return_indices=True)
+    got, nn = got.cpu().numpy(), nn.cpu().numpy()
+    nn_deann = dk.deann_query(Xd, Yd, h, 100, 0, "gaussian", precision="bf16")[1].cpu().numpy()
+    assert np.array_equal(nn, nn_deann)
+    assert np.all((got >= 0) & (got <= 1))
+    given = dk.kde_hybrid(Xd, Yd, h, 100, "gaussian", "bf16", nn_idx=to_dev(nn, Xd.device))
+    assert np.allclose(given.cpu().numpy(), got, rtol=1e-13, atol=0)
+    for j in synth.query_subset(Y.shape[0], 3, seed=11):
+        near = oracle.knn(X, Y[j], 100)
+        assert np.array_equal(nn[j], near), j
+        ref = oracle.kde_exact(X, Y[j:j + 1], h, GAUSSIAN)[0]
+        if ref < 1e-16:
+            continue
+        bound = exact_kde_bound(bound_geometry(X, Y[j:j + 1]), X.shape[1], h, GAUSSIAN, "bf16",
+                                near=near[None, :])[0]
+        err = abs(got[j] - ref) / ref
+        print(f"query {j}: near/far bf16 rel err {err:.2e} (bound {bound:.2e})")
+        assert err <= bound
+
+
 def test_fullsize_exact_backward():
     import paper_2107_02736_amd as dk
     dev = device()

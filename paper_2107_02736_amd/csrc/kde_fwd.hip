@@ -140,8 +140,40 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       else
         xt[j] = col < n ? (float)xn : __builtin_inff();
     }
-    auto epilogue = [&](auto tag) {
-      constexpr bool MASK = decltype(tag)::value;
+    if constexpr (HYB) {
+      // one 16-row block i of the lane's rows (bits i*16 .. i*16+15 of hm);
+      // the masked copy runs only for the blocks in which some lane of the
+      // wave holds a neighbour pair
+      auto block = [&](auto tag, const int i) {
+        constexpr bool MASK = decltype(tag)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float part = 0.f;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            float kv;
+            if (KERN == KERNEL_GAUSSIAN) {
+              const float a = fminf(__builtin_fmaf(L2, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
+              kv = __builtin_amdgcn_exp2f(a);
+            } else {
+              const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
+              kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
+            }
+            if constexpr (MASK)
+              if ((hm >> ((i * 4 + j) * 4 + r)) & 1ull) kv = 0.f;
+            part += kv;
+          }
+          sum[i][r] += (double)part;
+        }
+      };
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (__any(((hm >> (16 * i)) & 0xffffull) != 0ull))
+          block(BoolTag<true>{}, i);
+        else
+          block(BoolTag<false>{}, i);
+      }
+    } else {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -157,18 +189,12 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
               const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
               kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
             }
-            if constexpr (MASK)
-              if ((hm >> ((i * 4 + j) * 4 + r)) & 1ull) kv = 0.f;
             part += kv;
           }
           sum[i][r] += (double)part;
         }
       }
-    };
-    if (HYB && __any(hm != 0ull))
-      epilogue(BoolTag<true>{});
-    else
-      epilogue(BoolTag<false>{});
+    }
   }
   __syncthreads();
 

@@ -282,6 +282,13 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
 // Nothing goes through LDS but the data tile; G, the weight sums and the dK/dh
 // sums stay in registers until the end of the split.
 constexpr int BWG = 512;
+// Rows staged per step of the exact adjoint: 64 for rows of 64 floats, where
+// 64-row steps let two workgroups share a CU (measured 6% faster at d = 64);
+// 128 otherwise (rows of 32 floats fit two workgroups per CU with 128-row
+// steps already, rows of 96 and 128 floats do not fit two in the registers).
+#ifndef BWD_TR_64
+#define BWD_TR_64 64
+#endif
 
 template <int DP>
 struct GradTile {
@@ -296,18 +303,24 @@ struct GradTile {
 
 // VAL: also sum the kernel values themselves (the KDE); needed separately for
 // the exponential kernel only, whose weights are K / r (Gaussian: K).
-template <int KERN, int DP, bool VAL>
-__global__ void __launch_bounds__(BWG, 1)
+// TR: data rows staged per step, 128 (one workgroup per CU) or 64 (two
+// workgroups per CU, whose steps need not line up, so one workgroup's MFMAs
+// run while the other computes weights).
+template <int KERN, int DP, bool VAL, int TR>
+__global__ void __launch_bounds__(BWG, TR == 64 ? 4 : 1)
 kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
                     double* __restrict__ rw_part, double* __restrict__ gh_part,
                     double* __restrict__ ks_part) {
   using G = GradTile<DP>;
   constexpr bool KS = VAL && KERN != KERNEL_GAUSSIAN;
-  __shared__ __attribute__((aligned(16))) char xs[2][BN * G::PITCH];
-  __shared__ __attribute__((aligned(16))) float xvs[2][BN];   // per-row exponent terms
+  constexpr int NBI = TR / 16, UPT = BN / TR;
+  constexpr int NPT = TR * DP / 4 / BWG;   // 16-byte pieces per thread and step
+  static_assert(NPT >= 1 && TR * DP / 4 == NPT * BWG, "row pieces must split evenly");
+  __shared__ __attribute__((aligned(16))) char xs[2][TR * G::PITCH];
+  __shared__ __attribute__((aligned(16))) float xvs[2][TR];   // per-row exponent terms
   int64_t qt, split;
   if (!map_tile(blockIdx.x, p.map, p.qtiles, p.splits, qt, split)) return;
-  const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
+  const int64_t t0 = split * p.ntiles / p.splits * UPT, t1 = (split + 1) * p.ntiles / p.splits * UPT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
 
@@ -320,18 +333,18 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
   const double ynq = p.ynorm[qrow];
   const float yv = KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * ynq) : (float)ynq;
 
-  // data tile: global -> registers -> LDS; row terms by the first 128 threads
-  u32x4 xr[G::NPT];
+  // data rows: global -> registers -> LDS; row terms by the first TR threads
+  u32x4 xr[NPT];
   float xvr = 0.f;
   auto gload = [&](int64_t t) {
-    const char* base = p.Xs + t * BN * p.ld_bytes;
+    const char* base = p.Xs + t * TR * p.ld_bytes;
 #pragma unroll
-    for (int i = 0; i < G::NPT; ++i) {
+    for (int i = 0; i < NPT; ++i) {
       const int v = threadIdx.x + i * BWG;
       xr[i] = *reinterpret_cast<const u32x4*>(base + (v / G::PPR) * p.ld_bytes + (v % G::PPR) * 16);
     }
-    if (threadIdx.x < BN) {
-      const int64_t row = t * BN + threadIdx.x;
+    if (threadIdx.x < TR) {
+      const int64_t row = t * TR + threadIdx.x;
       // padding rows: a huge finite term, so that K = 0 and K * d^2 = 0
       xvr = row < p.n ? (KERN == KERNEL_GAUSSIAN ? (float)(-(double)L * p.xnorm[row])
                                                  : (float)p.xnorm[row])
@@ -340,11 +353,11 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
   };
   auto lstore = [&](int b) {
 #pragma unroll
-    for (int i = 0; i < G::NPT; ++i) {
+    for (int i = 0; i < NPT; ++i) {
       const int v = threadIdx.x + i * BWG;
       *reinterpret_cast<u32x4*>(&xs[b][(v / G::PPR) * G::PITCH + (v % G::PPR) * 16]) = xr[i];
     }
-    if (threadIdx.x < BN) xvs[b][threadIdx.x] = xvr;
+    if (threadIdx.x < TR) xvs[b][threadIdx.x] = xvr;
   };
 
   f32x4 gacc[G::GB];
@@ -363,15 +376,15 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
     if (more) gload(t + 1);   // in flight behind the first product
     const char* xb = xs[b];
 
-    // S^T for the 128 rows of the tile against the wave's 16 queries
-    f32x4 acc[8];
+    // S^T for the TR staged rows against the wave's 16 queries
+    f32x4 acc[NBI];
 #pragma unroll
-    for (int bi = 0; bi < 8; ++bi) acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int bi = 0; bi < NBI; ++bi) acc[bi] = f32x4{0.f, 0.f, 0.f, 0.f};
     __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int kg = 0; kg < G::KGS; ++kg) {
 #pragma unroll
-      for (int bi = 0; bi < 8; ++bi) {
+      for (int bi = 0; bi < NBI; ++bi) {
         const u32x4 a = *reinterpret_cast<const u32x4*>(xb + (bi * 16 + c) * G::PITCH +
                                                          kg * KG_BYTES + g * 16);
         acc[bi] = mfma_kgroup<float>(a, yf[kg], acc[bi]);
@@ -385,7 +398,7 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
     // eight rows folded into FP64
     const f32x4* xv4 = reinterpret_cast<const f32x4*>(xvs[b]);
 #pragma unroll
-    for (int bp = 0; bp < 4; ++bp) {
+    for (int bp = 0; bp < NBI / 2; ++bp) {
       float rw32 = 0.f, dh32 = 0.f, ks32 = 0.f;
 #pragma unroll
       for (int h2 = 0; h2 < 2; ++h2) {
@@ -418,10 +431,10 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
       if constexpr (KS) kss += (double)ks32;
     }
 
-    // G[q][t] += sum over the tile's rows of W[q][i] x~[i][t]
+    // G[q][t] += sum over the staged rows of W[q][i] x~[i][t]
     __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-    for (int bi = 0; bi < 8; ++bi) {
+    for (int bi = 0; bi < NBI; ++bi) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const char* row = xb + (bi * 16 + 4 * g + r) * G::PITCH;
@@ -763,10 +776,10 @@ static hipError_t launch_kde_bwd_k(const TileProblem& p, int64_t dp, float L, do
                                    double* gh, double* ks, hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), b(BWG);
   switch (dp) {
-    case 32: kde_backward_kernel<KERN, 32, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
-    case 64: kde_backward_kernel<KERN, 64, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
-    case 96: kde_backward_kernel<KERN, 96, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
-    case 128: kde_backward_kernel<KERN, 128, VAL><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 32: kde_backward_kernel<KERN, 32, VAL, 128><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 64: kde_backward_kernel<KERN, 64, VAL, BWD_TR_64><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 96: kde_backward_kernel<KERN, 96, VAL, 128><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 128: kde_backward_kernel<KERN, 128, VAL, 128><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

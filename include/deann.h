@@ -178,11 +178,12 @@ int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, in
  *           per query, any order; entries outside [0, n) are left out of both
  *           parts, repeated rows make Z1 count them again), e.g. the nn_idx
  *           of deann_query; NULL to compute the exact k nearest rows as
- *           deann_query does (k <= 496 or k = n, d <= 4096).
+ *           deann_query does (then k <= 496 or k = n).
  *   out     [q] float64.
  *   nn_idx  [q, k] int32, the neighbour lists used (sorted ascending when
  *           computed here, a copy of nn_in otherwise), or NULL.
- * Requirements: as kde_exact, plus 0 <= k <= n and q k < 2^31 when 0 < k < n.
+ * Requirements: as kde_exact, plus 0 <= k <= n, d <= 4096 when k > 0 and
+ * q k < 2^31 when 0 < k < n.
  * ------------------------------------------------------------------------- */
 size_t kde_hybrid_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int precision);
 int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,

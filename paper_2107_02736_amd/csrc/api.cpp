@@ -603,8 +603,8 @@ int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, 
   if (!nn_in && k > kMaxK && k != n)
     return fail(DEANN_EUNSUPPORTED, "k = %lld: supported are k <= %lld and k = n", (long long)k,
                 (long long)kMaxK);
-  if (!nn_in && k > 0 && d > 4096)
-    return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported by the k-NN of kde_hybrid");
+  if (k > 0 && d > 4096)
+    return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported by kde_hybrid with k > 0");
   if (k > 0 && k < n && q * k >= ((int64_t)1 << 31))
     return fail(DEANN_EUNSUPPORTED, "q * k must be < 2^31");
   if (q == 0) return DEANN_OK;

@@ -159,10 +159,11 @@ def test_kde_hybrid_validation(lib, kw, status):
 
 
 def test_kde_hybrid_given_neighbours_lift_the_knn_limits(lib):
-    # with the lists supplied no k-NN runs, so k > 496 and d > 4096 pass validation
-    # (and fail only at the deliberately short workspace)
+    # with the lists supplied no k-NN runs, so k > 496 passes validation (and
+    # fails only at the deliberately short workspace); d stays <= 4096
     assert _hyb(lib, k=600, nn_in=FAKE, wsb=64) == _lib.EWORKSPACE
-    assert _hyb(lib, d=5000, nn_in=FAKE, wsb=64) == _lib.EWORKSPACE
+    assert _hyb(lib, d=5000, nn_in=FAKE, wsb=64) == _lib.EUNSUPPORTED
+    assert _hyb(lib, d=5000, k=0, wsb=64) == _lib.EWORKSPACE
     assert _hyb(lib, q=0, out=None, ws=None, wsb=0) == _lib.OK
     assert lib.kde_hybrid_workspace(1000, 4, 3, 5, 0) == 0
     assert lib.kde_hybrid_workspace(1000, 4, 3, 5, 1) > lib.kde_exact_workspace(1000, 4, 3, 1)

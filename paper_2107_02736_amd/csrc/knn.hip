@@ -113,14 +113,27 @@ __device__ __forceinline__ void wave_sort_u64(uint64_t (&v)[EPL], int lane) {
 }
 
 // Exact FP64 squared distance of row `row` of X to the query held in LDS,
-// computed by a group of 16 consecutive lanes (all 16 get the result).
+// computed by a group of 16 consecutive lanes (all 16 get the result).  Rows
+// whose start is 16-byte aligned are read as float4 (256 contiguous bytes per
+// group and step).
 __device__ __forceinline__ double group16_d2(const float* __restrict__ X, int64_t row, int64_t d,
                                              const float* ys, int l16) {
   const float* xr = X + row * d;
   double s = 0.0;
-  for (int64_t t = l16; t < d; t += 16) {
-    const double df = (double)xr[t] - (double)ys[t];
-    s = __builtin_fma(df, df, s);
+  if (((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0)) {
+    for (int64_t t = 4 * l16; t < d; t += 64) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(xr + t);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double df = (double)v[c] - (double)ys[t + c];
+        s = __builtin_fma(df, df, s);
+      }
+    }
+  } else {
+    for (int64_t t = l16; t < d; t += 16) {
+      const double df = (double)xr[t] - (double)ys[t];
+      s = __builtin_fma(df, df, s);
+    }
   }
   s += __shfl_xor(s, 1, 64);
   s += __shfl_xor(s, 2, 64);
@@ -480,7 +493,33 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   __syncthreads();
   // gather the split lists, keeping the K1 smallest keys
   int64_t seen = 0;
-  for (int64_t s = 0; s < a.splits; ++s) {
+  if (a.approx) {
+    // cell candidates: CELLS per (split, query), contiguous; read in chunks of
+    // at most SORT_CAP - K1 entries whose loads are all in flight together
+    const int64_t total = a.splits * (int64_t)CELLS, chunk = SORT_CAP - K1;
+    for (int64_t c0 = 0; c0 < total; c0 += chunk) {
+      const int64_t c1 = c0 + chunk < total ? c0 + chunk : total;
+      __syncthreads();   // every thread has read fill_s for the previous decision
+      for (int64_t i = c0 + threadIdx.x; i < c1; i += WG) {
+        const uint64_t v = b.cand[((i / CELLS) * a.qp + qi) * CELLS + i % CELLS];
+        if (v != ~0ull) buf[atomicAdd(&fill_s, 1)] = v;
+      }
+      __syncthreads();
+      const bool last = c1 == total;
+      // before another chunk the buffer is cut back to K1; after the last one
+      // it is sorted whenever the K1-th key is used
+      if ((last && fill_s >= K1) || (!last && fill_s > K1)) {
+        const int F = fill_s;
+        const int N = next_pow2(F);   // <= SORT_CAP
+        for (int i = F + threadIdx.x; i < N; i += WG) buf[i] = ~0ull;
+        __syncthreads();
+        block_sort_u64(buf, N);
+        if (threadIdx.x == 0) fill_s = K1;
+        __syncthreads();
+      }
+    }
+  }
+  for (int64_t s = 0; s < (a.approx ? 0 : a.splits); ++s) {
     const int c = b.cand_cnt[s * a.qp + qi];
     const uint64_t* lst = b.cand + (s * a.qp + qi) * b.cap1;
     seen += c;

@@ -142,6 +142,50 @@ __device__ __forceinline__ double group16_d2(const float* __restrict__ X, int64_
   return s;
 }
 
+// group16_d2 of four rows at once, their loads in flight together; the sum of
+// each row is formed in the same order as by group16_d2, so the results are
+// bitwise the same.  Rows r[i] < 0 give 0.
+__device__ __forceinline__ void group16_d2_4(const float* __restrict__ X, const int64_t (&r)[4],
+                                             int64_t d, const float* ys, int l16, double (&out)[4]) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0)) {
+    for (int64_t t = 4 * l16; t < d; t += 64) {
+      f32x4 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        v[i] = r[i] >= 0 ? *reinterpret_cast<const f32x4*>(X + r[i] * d + t)
+                         : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double df = (double)v[i][c] - (double)ys[t + c];
+          s[i] = __builtin_fma(df, df, s[i]);
+        }
+    }
+  } else {
+    for (int64_t t = l16; t < d; t += 16) {
+      float v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = r[i] >= 0 ? X[r[i] * d + t] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double df = (double)v[i] - (double)ys[t];
+        s[i] = __builtin_fma(df, df, s[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double v = s[i];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    out[i] = r[i] >= 0 ? v : 0.0;
+  }
+}
+
 // ||x - y||^2 as an unevaluated double-double sum (error-free squares and
 // two-sum accumulation); used only to order near ties.
 __device__ void dd_d2(const float* __restrict__ xr, const float* ys, int64_t d, double& hi,
@@ -545,12 +589,23 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   // all points were candidates iff no list ever dropped anything
   const bool complete = !a.approx && (seen == a.n) && (C == a.n);
   const float Tkey = (C == K1) ? key_float((uint32_t)(buf[K1 - 1] >> 32)) : __builtin_inff();
-  // exact FP64 distances
+  // exact FP64 distances, four rows per 16-lane group at a time
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
-  for (int c = g; c < C; c += WG / 16) {
-    const uint32_t id = (uint32_t)(buf[c] & 0xffffffffu);
-    const double d2 = group16_d2(a.X, id, a.d, ys, l16);
-    if (l16 == 0) { dkey[c] = __builtin_bit_cast(uint64_t, d2); didx[c] = id; }
+  for (int c0 = g; c0 < C; c0 += 4 * (WG / 16)) {
+    int64_t rr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = c0 + i * (WG / 16);
+      rr[i] = c < C ? (int64_t)(buf[c] & 0xffffffffu) : -1;
+    }
+    double d2[4];
+    group16_d2_4(a.X, rr, a.d, ys, l16, d2);
+    if (l16 == 0)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = c0 + i * (WG / 16);
+        if (c < C) { dkey[c] = __builtin_bit_cast(uint64_t, d2[i]); didx[c] = (uint32_t)rr[i]; }
+      }
   }
   const int N = next_pow2(C > 1 ? C : 2);
   for (int i = C + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
@@ -715,10 +770,21 @@ knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   for (int64_t t = threadIdx.x; t < a.d; t += WG) ys[t] = a.Y[qi * a.d + t];
   __syncthreads();
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
-  for (int c = g; c < C; c += WG / 16) {
-    const uint32_t id = (uint32_t)b.cand2[qi * b.cap2 + c];
-    const double d2 = group16_d2(a.X, id, a.d, ys, l16);
-    if (l16 == 0) { dkey[c] = __builtin_bit_cast(uint64_t, d2); didx[c] = id; }
+  for (int c0 = g; c0 < C; c0 += 4 * (WG / 16)) {
+    int64_t rr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = c0 + i * (WG / 16);
+      rr[i] = c < C ? (int64_t)(uint32_t)b.cand2[qi * b.cap2 + c] : -1;
+    }
+    double d2[4];
+    group16_d2_4(a.X, rr, a.d, ys, l16, d2);
+    if (l16 == 0)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = c0 + i * (WG / 16);
+        if (c < C) { dkey[c] = __builtin_bit_cast(uint64_t, d2[i]); didx[c] = (uint32_t)rr[i]; }
+      }
   }
   const int N = next_pow2(C > 1 ? C : 2);
   for (int i = C + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }

@@ -879,7 +879,17 @@ knn_all_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t
   __syncthreads();
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
   double s = 0.0;
-  for (int64_t r = g; r < n; r += WG / 16) s += kernel_value(group16_d2(X, r, d, ys, l16), h, kern);
+  // rows g, g + 16, ... in order, four at a time
+  for (int64_t r0 = g; r0 < n; r0 += 4 * (WG / 16)) {
+    int64_t rr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rr[i] = r0 + i * (WG / 16) < n ? r0 + i * (WG / 16) : -1;
+    double d2[4];
+    group16_d2_4(X, rr, d, ys, l16, d2);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (rr[i] >= 0) s += kernel_value(d2[i], h, kern);
+  }
   if (l16 == 0) red[g] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -912,9 +922,19 @@ knn_list_sum_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
   __syncthreads();
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
   double s = 0.0;
-  for (int64_t j = g; j < k; j += WG / 16) {
-    const int32_t r = nn[qi * k + j];
-    if (r >= 0 && r < n) s += kernel_value(group16_d2(X, r, d, ys, l16), h, kern);
+  for (int64_t j0 = g; j0 < k; j0 += 4 * (WG / 16)) {   // entries j0, j0 + 16, ... in order
+    int64_t rr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t j = j0 + i * (WG / 16);
+      const int32_t r = j < k ? nn[qi * k + j] : -1;
+      rr[i] = (r >= 0 && r < n) ? (int64_t)r : -1;
+    }
+    double d2[4];
+    group16_d2_4(X, rr, d, ys, l16, d2);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (rr[i] >= 0) s += kernel_value(d2[i], h, kern);
   }
   if (l16 == 0) red[g] = s;
   __syncthreads();
@@ -1156,12 +1176,23 @@ ivf_refine_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restrict__
   const bool complete = (seen == rows) && (C == rows);
   const float Tkey = (C == K1) ? key_float((uint32_t)(buf[K1 - 1] >> 32)) : __builtin_inff();
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
-  for (int c = g; c < C; c += WG / 16) {
-    // a real row (empty rows have infinite keys and are never listed)
-    const int32_t pid = v.pids[(uint32_t)(buf[c] & 0xffffffffu)];
-    const int32_t id = pid >= 0 ? pid : 0;
-    const double d2 = group16_d2(a.X, id, a.d, ys, l16);
-    if (l16 == 0) { dkey[c] = __builtin_bit_cast(uint64_t, d2); didx[c] = (uint32_t)id; }
+  for (int c0 = g; c0 < C; c0 += 4 * (WG / 16)) {   // four rows per group at a time
+    int64_t rr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = c0 + i * (WG / 16);
+      // a real row (empty rows have infinite keys and are never listed)
+      const int32_t pid = c < C ? v.pids[(uint32_t)(buf[c] & 0xffffffffu)] : -1;
+      rr[i] = c < C ? (int64_t)(pid >= 0 ? pid : 0) : -1;
+    }
+    double d2[4];
+    group16_d2_4(a.X, rr, a.d, ys, l16, d2);
+    if (l16 == 0)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = c0 + i * (WG / 16);
+        if (c < C) { dkey[c] = __builtin_bit_cast(uint64_t, d2[i]); didx[c] = (uint32_t)rr[i]; }
+      }
   }
   const int N = next_pow2(C > 1 ? C : 2);
   for (int i = C + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }

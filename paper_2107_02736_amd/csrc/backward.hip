@@ -143,26 +143,35 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
       acc[u][c] = 0.0;
     }
   double hs = 0.0;
-  for (int64_t j = g; j < R; j += NG) {
+  // the group's rows j = g, g + NG, ...: the next row is loaded while the
+  // current one is evaluated
+  auto load_row = [&](int64_t j, float (&dst)[U][4]) {
     const int32_t row = j < k ? nn[qi * k + j] : samp[qi * m + (j - k)];
     const float* xr = X + (int64_t)row * d;
-    float xv[U][4];
-    double s = 0.0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t t = 4 * lg + 4 * GW * u;
       if (t < d) {
         const f32x4 v = *reinterpret_cast<const f32x4*>(xr + t);
-        xv[u][0] = v[0]; xv[u][1] = v[1]; xv[u][2] = v[2]; xv[u][3] = v[3];
+        dst[u][0] = v[0]; dst[u][1] = v[1]; dst[u][2] = v[2]; dst[u][3] = v[3];
       } else {
-        xv[u][0] = xv[u][1] = xv[u][2] = xv[u][3] = 0.f;
+        dst[u][0] = dst[u][1] = dst[u][2] = dst[u][3] = 0.f;
       }
+    }
+  };
+  float xv[U][4], xn[U][4];
+  if (g < R) load_row(g, xv);
+  for (int64_t j = g; j < R; j += NG) {
+    const bool more = j + NG < R;
+    if (more) load_row(j + NG, xn);
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const double df = (double)xv[u][c] - (double)yv[u][c];
         s = __builtin_fma(df, df, s);
       }
-    }
 #pragma unroll
     for (int off = 1; off < GW; off <<= 1) s += __shfl_xor(s, off, 64);
     const double c = j < k ? 1.0 : csamp;
@@ -184,6 +193,11 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
 #pragma unroll
       for (int cc = 0; cc < 4; ++cc)
         acc[u][cc] = __builtin_fma(w, (double)xv[u][cc] - (double)yv[u][cc], acc[u][cc]);
+    if (more)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) xv[u][cc] = xn[u][cc];
   }
 #pragma unroll
   for (int u = 0; u < U; ++u)

@@ -403,4 +403,51 @@ __device__ __forceinline__ float key_float(uint32_t k) {
   return __builtin_bit_cast(float, b);
 }
 
+// Exact FP64 squared distances of four rows of X to the query ys (LDS), by a
+// group of 16 consecutive lanes (all 16 get the results); the four rows'
+// loads are in flight together.  Rows whose start is 16-byte aligned are read
+// as float4.  Each sum is formed in a fixed order (coordinates of a lane in
+// ascending order, then a butterfly over the 16 lanes), the same for one row
+// at a time.  Rows r[i] < 0 give 0.
+__device__ __forceinline__ void group16_d2_4(const float* __restrict__ X, const int64_t (&r)[4],
+                                             int64_t d, const float* ys, int l16, double (&out)[4]) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0)) {
+    for (int64_t t = 4 * l16; t < d; t += 64) {
+      f32x4 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        v[i] = r[i] >= 0 ? *reinterpret_cast<const f32x4*>(X + r[i] * d + t)
+                         : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double df = (double)v[i][c] - (double)ys[t + c];
+          s[i] = __builtin_fma(df, df, s[i]);
+        }
+    }
+  } else {
+    for (int64_t t = l16; t < d; t += 16) {
+      float v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = r[i] >= 0 ? X[r[i] * d + t] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double df = (double)v[i] - (double)ys[t];
+        s[i] = __builtin_fma(df, df, s[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double v = s[i];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    out[i] = r[i] >= 0 ? v : 0.0;
+  }
+}
+
 }  // namespace deann

@@ -142,50 +142,6 @@ __device__ __forceinline__ double group16_d2(const float* __restrict__ X, int64_
   return s;
 }
 
-// group16_d2 of four rows at once, their loads in flight together; the sum of
-// each row is formed in the same order as by group16_d2, so the results are
-// bitwise the same.  Rows r[i] < 0 give 0.
-__device__ __forceinline__ void group16_d2_4(const float* __restrict__ X, const int64_t (&r)[4],
-                                             int64_t d, const float* ys, int l16, double (&out)[4]) {
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  if (((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0)) {
-    for (int64_t t = 4 * l16; t < d; t += 64) {
-      f32x4 v[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        v[i] = r[i] >= 0 ? *reinterpret_cast<const f32x4*>(X + r[i] * d + t)
-                         : f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double df = (double)v[i][c] - (double)ys[t + c];
-          s[i] = __builtin_fma(df, df, s[i]);
-        }
-    }
-  } else {
-    for (int64_t t = l16; t < d; t += 16) {
-      float v[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = r[i] >= 0 ? X[r[i] * d + t] : 0.f;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double df = (double)v[i] - (double)ys[t];
-        s[i] = __builtin_fma(df, df, s[i]);
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double v = s[i];
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
-    v += __shfl_xor(v, 8, 64);
-    out[i] = r[i] >= 0 ? v : 0.0;
-  }
-}
-
 // ||x - y||^2 as an unevaluated double-double sum (error-free squares and
 // two-sum accumulation); used only to order near ties.
 __device__ void dd_d2(const float* __restrict__ xr, const float* ys, int64_t d, double& hi,

@@ -155,7 +155,6 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
   for (int64_t t = threadIdx.x; t < d; t += WG) ys[t] = Y[qi * d + t];
   __syncthreads();
   const uint64_t stream = query_offset + (uint64_t)qi;
-  const bool vec = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
   double total = 0.0;   // meaningful in thread 0
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
   for (int64_t j0 = 0; j0 < m; j0 += DRAW_CHUNK) {
@@ -186,30 +185,22 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
       }
     }
     __syncthreads();
-    // gather and evaluate: 16 lanes per drawn row
-    for (int jj = g; jj < cnt; jj += WG / 16) {
-      const float* xr = X + (int64_t)sidx[jj] * d;
-      double s = 0.0;
-      if (vec) {   // 16-byte loads: 256 contiguous bytes per group and step
-        for (int64_t t = 4 * l16; t < d; t += 64) {
-          const f32x4 v = *reinterpret_cast<const f32x4*>(xr + t);
+    // gather and evaluate: 16 lanes per drawn row, four rows in flight
+    for (int j0 = g; j0 < cnt; j0 += 4 * (WG / 16)) {
+      int64_t rr[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const double df = (double)v[c] - (double)ys[t + c];
-            s = __builtin_fma(df, df, s);
-          }
-        }
-      } else {
-        for (int64_t t = l16; t < d; t += 16) {
-          const double df = (double)xr[t] - (double)ys[t];
-          s = __builtin_fma(df, df, s);
-        }
+      for (int i = 0; i < 4; ++i) {
+        const int jj = j0 + i * (WG / 16);
+        rr[i] = jj < cnt ? (int64_t)sidx[jj] : -1;
       }
-      s += __shfl_xor(s, 1, 64);
-      s += __shfl_xor(s, 2, 64);
-      s += __shfl_xor(s, 4, 64);
-      s += __shfl_xor(s, 8, 64);
-      if (l16 == 0) kv[jj] = kval(s, h, kern);
+      double s4[4];
+      group16_d2_4(X, rr, d, ys, l16, s4);
+      if (l16 == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int jj = j0 + i * (WG / 16);
+          if (jj < cnt) kv[jj] = kval(s4[i], h, kern);
+        }
     }
     __syncthreads();
     // fixed-order reduction of the chunk

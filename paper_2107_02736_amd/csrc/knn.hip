@@ -476,6 +476,42 @@ struct RefineArgs {
   int approx;   // candidates come from the cell pass: no certificate, always collect
 };
 
+// The K1 smallest of a query's `cells` cell candidates (packed key, index;
+// empty cells are ~0), sorted ascending, in buf[0 .. min(K1, valid)), and
+// *fill = min(K1, number of non-empty cells).  Wave w takes cells
+// [w * 64 * EPL, (w + 1) * 64 * EPL) and sorts them in registers; K1 <= 64 * EPL
+// of each wave go to buf, which one workgroup sort then orders.  Whole block.
+template <int EPL>
+__device__ void cells_wave_select(const uint64_t* __restrict__ cand, int64_t qp, int64_t qi,
+                                  int64_t cells, int K1, uint64_t* buf, int* fill) {
+  __shared__ int valid_w[WG / 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint64_t v[EPL];
+  int valid = 0;
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) {
+    const int64_t e = (int64_t)wave * 64 * EPL + lane * EPL + r;
+    v[r] = e < cells ? cand[((e / CELLS) * qp + qi) * CELLS + e % CELLS] : ~0ull;
+    valid += v[r] != ~0ull;
+  }
+  for (int off = 32; off > 0; off >>= 1) valid += __shfl_xor(valid, off, 64);
+  wave_sort_u64<EPL>(v, lane);
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) {
+    const int el = lane * EPL + r;
+    if (el < K1) buf[wave * K1 + el] = v[r];
+  }
+  if (lane == 0) valid_w[wave] = valid;
+  __syncthreads();
+  block_sort_u64(buf, (WG / 64) * K1);
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < WG / 64; ++w) tot += valid_w[w];
+    *fill = tot < K1 ? tot : K1;
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(WG)
 knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -493,7 +529,16 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   __syncthreads();
   // gather the split lists, keeping the K1 smallest keys
   int64_t seen = 0;
-  if (a.approx) {
+  const int64_t cells = a.approx ? a.splits * (int64_t)CELLS : 0;
+  if (a.approx && cells <= (WG / 64) * 64 * 16 && K1 <= 512) {
+    // at most 1024 cells per wave: each wave sorts its share in registers, the
+    // K1 smallest of every wave meet in LDS, and one sort of those gives the
+    // K1 smallest of all (empty cells sort last)
+    if (cells <= (WG / 64) * 64 * 8)
+      cells_wave_select<8>(b.cand, a.qp, qi, cells, K1, buf, &fill_s);
+    else
+      cells_wave_select<16>(b.cand, a.qp, qi, cells, K1, buf, &fill_s);
+  } else if (a.approx) {
     // cell candidates: CELLS per (split, query), contiguous; read in chunks of
     // at most SORT_CAP - K1 entries whose loads are all in flight together
     const int64_t total = a.splits * (int64_t)CELLS, chunk = SORT_CAP - K1;

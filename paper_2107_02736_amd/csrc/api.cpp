@@ -200,6 +200,7 @@ int check_common(const float* X, int64_t n, const float* Y, int64_t q, int64_t d
 constexpr int64_t kKdeSplitTarget = 4096;
 constexpr int64_t kKnnSplitTarget = 512;     // selection scan: about one wave of workgroups
 constexpr int64_t kCollectSplitTarget = 4096;  // candidate and collect passes
+constexpr int64_t kIvfPartTarget = 512;        // inverted-file sweep parts: 2 per CU
 
 struct KdePlan {
   Prep prep;
@@ -826,7 +827,8 @@ struct IvfQueryPlan {
   double* ynorm;
   float *yknorm, *yerr;
   uint32_t* err_max;
-  int32_t *pcount, *pfill, *pp, *pair_q, *pair_of;
+  int32_t *pcount, *pfill, *pp, *pair_q, *pair_of, *lbase, *nparts;
+  uint32_t* qthr;
   float *Yg, *ygk;
   KnnBuffers kb;
   int32_t* nn_internal;
@@ -854,6 +856,9 @@ IvfQueryPlan plan_ivf_query(void* ws, int64_t n, int64_t q, int64_t d, int64_t L
   P.pp = cv.take<int32_t>(L + 1);
   P.pair_q = cv.take<int32_t>(P.pcap);
   P.pair_of = cv.take<int32_t>(q * P.kp);
+  P.lbase = cv.take<int32_t>(P.pcap / BN + 1);
+  P.nparts = cv.take<int32_t>(2);
+  P.qthr = cv.take<uint32_t>(q > 0 ? q : 1);
   P.Yg = cv.take<float>(P.pcap * dp);
   P.ygk = cv.take<float>(P.pcap);
   KnnBuffers& b = P.kb;
@@ -1031,10 +1036,15 @@ int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_
       e = launch_pairs(probe, q, P.kp, P.np_q, n_clusters, P.pcount, P.pfill, P.pp, P.pair_q,
                        P.pair_of, P.pcap, reinterpret_cast<const float*>(P.Ys), P.yknorm, dp,
                        P.Yg, P.ygk, s);
+    // long sweeps in parts: each list slot of the workspace holds one part
+    if (e == hipSuccess)
+      e = launch_pair_parts(P.pp, x.poff, n_clusters, P.pcap / BN, kIvfPartTarget, P.lbase,
+                            P.nparts, s);
     if (e == hipSuccess) {
       IvfTiles t{reinterpret_cast<const char*>(P.Yg), x.Xs, dp * 4, (int)(dp * 4 / CHUNK_BYTES),
-                 P.ygk, x.xknorm, P.pp, x.poff, n_clusters, P.pair_q, x.pids};
-      IvfRefine v{probe, P.kp, P.np_q, P.pair_of, x.off, x.ids, x.pids};
+                 P.ygk, x.xknorm, P.pp, x.poff, n_clusters, P.pair_q, x.pids, P.lbase,
+                 P.nparts, P.qthr};
+      IvfRefine v{probe, P.kp, P.np_q, P.pair_of, x.off, x.ids, x.pids, P.lbase, P.qthr};
       e = launch_ivf_knn(t, P.pcap, P.kb, v, X, Y, n, q, d, k, h, kernel, nullptr, s);
     }
   }

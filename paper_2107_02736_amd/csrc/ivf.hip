@@ -219,6 +219,69 @@ __global__ void pair_gather_kernel(const float* __restrict__ Ys, const float* __
   if (threadIdx.x == 0) ygk[r] = qi >= 0 ? yknorm[qi] : 0.f;
 }
 
+// Parts of the pair tiles' sweeps.  Pair tile b (pair rows [128b, 128b+128))
+// sweeps the tiles_b data tiles of its cluster; it is split into
+// P_b = ceil(tiles_b / T) parts of near-equal length, each with lists of its
+// own, so that the longest workgroup of the scan is at most T tiles rather than
+// the largest cluster.  T = max(PART_MIN, ceil(S / target), ceil(S / (budget -
+// nb))) over the S tiles of all nb pair tiles keeps the parts at most budget:
+// sum P_b <= nb + S / T.  lbase[b] is the first part of pair tile b,
+// lbase[nb] = nparts[0] the number of parts; nparts[1] = T.
+constexpr int64_t PART_MIN = 8;
+__global__ void __launch_bounds__(IVF_SCAN_THREADS)
+pair_parts_kernel(const int32_t* __restrict__ pp, const int32_t* __restrict__ poff, int64_t L,
+                  int64_t budget, int64_t target, int32_t* __restrict__ lbase,
+                  int32_t* __restrict__ nparts) {
+  __shared__ int64_t red[IVF_SCAN_THREADS];
+  __shared__ int32_t s[IVF_SCAN_THREADS];
+  const int64_t nb = pp[L] / BN;
+  auto tiles_of = [&](int64_t b) -> int64_t {   // the cluster l with pp[l] <= 128b < pp[l+1]
+    int64_t lo = 0, hi = L;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)pp[mid] <= b * BN) lo = mid; else hi = mid;
+    }
+    return (int64_t)(poff[lo + 1] - poff[lo]) / BN;
+  };
+  int64_t acc = 0;
+  for (int64_t b = threadIdx.x; b < nb; b += IVF_SCAN_THREADS) acc += tiles_of(b);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = IVF_SCAN_THREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const int64_t S = red[0];
+  int64_t T = PART_MIN;
+  if (target > 0 && (S + target - 1) / target > T) T = (S + target - 1) / target;
+  const int64_t room = budget - nb;
+  if (room <= 0) T = S + 1;   // no room for a second part anywhere
+  else if ((S + room - 1) / room > T) T = (S + room - 1) / room;
+  int32_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += IVF_SCAN_THREADS) {
+    const int64_t b = c0 + threadIdx.x;
+    const int64_t tb = b < nb ? tiles_of(b) : 0;
+    const int32_t v = b < nb ? (int32_t)(tb > T ? (tb + T - 1) / T : 1) : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < IVF_SCAN_THREADS; off <<= 1) {
+      const int32_t a = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += a;
+      __syncthreads();
+    }
+    const int32_t incl = s[threadIdx.x], total = s[IVF_SCAN_THREADS - 1];
+    __syncthreads();
+    if (b < nb) lbase[b] = carry + incl - v;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    lbase[nb] = carry;
+    nparts[0] = carry;
+    nparts[1] = (int32_t)(T < 0x7fffffff ? T : 0x7fffffff);
+  }
+}
+
 // ---- host launches -------------------------------------------------------------
 int64_t ivf_hist_blocks(int64_t n) { return ceil_div(n, IVF_HIST_ROWS); }
 
@@ -292,6 +355,13 @@ hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t kp, const int32
                                                    pair_of);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   pair_gather_kernel<<<dim3((unsigned)cap), dim3(128), 0, s>>>(Ys, yknorm, dp, pair_q, cap, Yg, ygk);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_parts(const int32_t* pp, const int32_t* poff, int64_t L, int64_t budget,
+                             int64_t target, int32_t* lbase, int32_t* nparts, hipStream_t s) {
+  pair_parts_kernel<<<dim3(1), dim3(IVF_SCAN_THREADS), 0, s>>>(pp, poff, L, budget, target, lbase,
+                                                                nparts);
   return hipGetLastError();
 }
 

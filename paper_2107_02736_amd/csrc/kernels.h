@@ -116,6 +116,11 @@ hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t kp, const int32
                         int32_t* pair_of, int64_t cap, const float* Ys, const float* yknorm,
                         int64_t dp, float* Yg, float* ygk, hipStream_t s);
 
+// Parts of the pair tiles' sweeps (see pair_parts_kernel): lbase[nb+1] with
+// nb = pp[L] / 128 <= budget; at most budget parts; nparts[2].
+hipError_t launch_pair_parts(const int32_t* pp, const int32_t* poff, int64_t L, int64_t budget,
+                             int64_t target, int32_t* lbase, int32_t* nparts, hipStream_t s);
+
 struct IvfTiles {
   const char* Ys;          // prepared query rows in pair order [prow_cap][dp]
   const char* Xs;          // prepared index rows in tile layout [xrows][dp]
@@ -128,6 +133,9 @@ struct IvfTiles {
   int64_t L;
   const int32_t* pair_q;   // [prow_cap] query of each pair row (-1: padding)
   const int32_t* pids;     // [xrows] row of each tile-layout row (-1: empty)
+  const int32_t* lbase;    // [nb+1] first part of each pair tile; part j lists at rows 128j..
+  const int32_t* nparts;   // [0]: parts in all
+  uint32_t* qthr;          // [q] smallest K1-th key published for each query (float_key order)
 };
 
 struct IvfRefine {
@@ -138,6 +146,8 @@ struct IvfRefine {
   const int32_t* off;      // [L+1] cluster ranges of ids
   const int32_t* ids;      // member rows in cluster order
   const int32_t* pids;     // [xrows] row of each tile-layout row (-1: empty)
+  const int32_t* lbase;    // [nb+1] first part of each pair tile
+  const uint32_t* qthr;    // [q] final shared bound of each query's scan
 };
 
 // Inspected clusters of each query (see probe_order_kernel); order[q][kp].

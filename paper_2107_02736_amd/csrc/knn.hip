@@ -1044,12 +1044,40 @@ namespace deann {
 // Inverted-file neighbours (Sec. 5): the k nearest rows among the clusters a
 // query inspects.  Pair row r of a batch is one (cluster, query) pair; the pair
 // rows of cluster l form the range [pp[l], pp[l+1]) (a multiple of the tile),
-// so one workgroup sweeps one query tile of one cluster over that cluster's
-// rows [poff[l], poff[l+1]) of the index, keeping per pair the K1 smallest
-// lower-bound keys exactly as the FP32 scan keeps them per (split, query).
-// The refinement then merges the lists of the query's pairs; keys are exact
-// lower bounds, so the certificate of the FP32 scan carries over unchanged.
+// so one query tile of one cluster sweeps that cluster's rows [poff[l],
+// poff[l+1]) of the index, in one or more parts (one workgroup each), keeping
+// per pair and part the K1 smallest lower-bound keys exactly as the FP32 scan
+// keeps them per (split, query).  The refinement then merges the lists of the
+// query's pairs and parts; keys are exact lower bounds and the merged K1
+// smallest are those of the whole sweep, so the certificate of the FP32 scan
+// carries over unchanged.
 // ---------------------------------------------------------------------------
+// Pair tile and data-tile range of part w of the sweeps (see
+// pair_parts_kernel: part p of P sweeps tiles [t0 + p*tiles/P, t0 +
+// (p+1)*tiles/P) of the cluster); false past the last part.
+struct IvfPart {
+  int64_t row0, t0, t1;
+};
+__device__ __forceinline__ bool ivf_part(const IvfTiles& v, int64_t w, IvfPart& o) {
+  if (w >= v.nparts[0]) return false;
+  int64_t lo = 0, hi = v.pp[v.L] / BQ;   // lbase[lo] <= w < lbase[lo + 1]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (v.lbase[mid] <= w) lo = mid; else hi = mid;
+  }
+  o.row0 = lo * BQ;
+  int64_t a = 0, z = v.L;   // the cluster: pp[a] <= row0 < pp[a + 1]
+  while (z - a > 1) {
+    const int64_t mid = (a + z) >> 1;
+    if (v.pp[mid] <= o.row0) a = mid; else z = mid;
+  }
+  const int64_t c0 = v.poff[a] / BN, tiles = v.poff[a + 1] / BN - c0;
+  const int64_t P = v.lbase[lo + 1] - v.lbase[lo], p = w - v.lbase[lo];
+  o.t0 = c0 + tiles * p / P;
+  o.t1 = c0 + tiles * (p + 1) / P;
+  return true;
+}
+
 template <int EPL>   // list capacity = 64 * EPL
 __global__ void __launch_bounds__(WG, 2)
 ivf_scan_kernel(IvfTiles v, uint64_t* __restrict__ cand, int32_t* __restrict__ cand_cnt, int K1) {
@@ -1058,23 +1086,30 @@ ivf_scan_kernel(IvfTiles v, uint64_t* __restrict__ cand, int32_t* __restrict__ c
   __shared__ float thr[BQ];
   __shared__ float yks[BQ];
   __shared__ int cnt[BQ];
-  const int64_t row0 = (int64_t)blockIdx.x * BQ;
-  if (row0 >= v.pp[v.L]) return;
-  // the cluster whose pair rows hold row0: pp[l] <= row0 < pp[l + 1]
-  int64_t lo = 0, hi = v.L;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (v.pp[mid] <= row0) lo = mid; else hi = mid;
-  }
-  const int64_t t0 = v.poff[lo] / BN, t1 = v.poff[lo + 1] / BN;
+  IvfPart pt;
+  if (!ivf_part(v, blockIdx.x, pt)) return;
+  const int64_t row0 = pt.row0, t0 = pt.t0, t1 = pt.t1;
+  const int64_t lrow0 = (int64_t)blockIdx.x * BQ;   // list rows of this part
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
+  // The query's own bound: thr is the K1-th key of this list or a value of
+  // qthr[query], the smallest K1-th key any list of the query has published.
+  // Either has K1 keys at or below it among the query's lists, so a key at or
+  // above it is not among the K1 smallest of the query's inspected rows.
+  const int32_t qi = threadIdx.x < BQ ? v.pair_q[row0 + threadIdx.x] : -1;
+  auto share_bound = [&]() {
+    if (qi >= 0) {
+      const float th = thr[threadIdx.x];
+      const uint32_t was = atomicMin(&v.qthr[qi], float_key(th));
+      thr[threadIdx.x] = fminf(th, key_float(was));
+    }
+  };
   if (threadIdx.x < BQ) {
-    thr[threadIdx.x] = __builtin_inff();
+    thr[threadIdx.x] = qi >= 0 ? key_float(v.qthr[qi]) : __builtin_inff();
     cnt[threadIdx.x] = 0;
     yks[threadIdx.x] = v.yknorm[row0 + threadIdx.x];
   }
-  uint64_t* lists = cand + row0 * (int64_t)cap1;
+  uint64_t* lists = cand + lrow0 * (int64_t)cap1;
   const char* yq = v.Ys + row0 * v.ld_bytes;
   const int limit = cap1 - BN;
   __syncthreads();
@@ -1112,9 +1147,12 @@ ivf_scan_kernel(IvfTiles v, uint64_t* __restrict__ cand, int32_t* __restrict__ c
       }
     __syncthreads();
     compact_lists<EPL>(lists, cnt, thr, limit, K1, wave, lane);
+    share_bound();
+    __syncthreads();
   }
   compact_lists<EPL>(lists, cnt, thr, K1, K1, wave, lane);
-  if (threadIdx.x < BQ) cand_cnt[row0 + threadIdx.x] = cnt[threadIdx.x];
+  share_bound();
+  if (threadIdx.x < BQ) cand_cnt[lrow0 + threadIdx.x] = cnt[threadIdx.x];
 }
 
 // Rows the query's clusters hold (clusters probed by one query are distinct).
@@ -1154,23 +1192,35 @@ ivf_refine_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restrict__
   __syncthreads();
   int64_t seen = 0;
   const int64_t np = v.np_q[qi];
+  // the query's lists hold at least K1 keys at or below its final shared
+  // bound, so the K1 smallest are among the entries at or below it
+  const uint64_t cut = ((uint64_t)v.qthr[qi] << 32) | 0xffffffffull;
   for (int64_t p = 0; p < np; ++p) {
     const int32_t row = v.pair_of[qi * v.kp + p];
-    const int c = b.cand_cnt[row];
-    const uint64_t* lst = b.cand + (int64_t)row * b.cap1;
-    seen += c;
-    __syncthreads();
-    for (int i = threadIdx.x; i < c; i += WG) buf[atomicAdd(&fill_s, 1)] = lst[i];
-    __syncthreads();
-    const bool flush = (fill_s + K1 > SORT_CAP) || (p + 1 == np);
-    if (flush && fill_s >= K1) {
-      const int F = fill_s;
-      const int N = next_pow2(F);
-      for (int i = F + threadIdx.x; i < N; i += WG) buf[i] = ~0ull;
+    const int64_t tile = row / BQ, ql = row % BQ;
+    const int32_t j1 = v.lbase[tile + 1];
+    for (int32_t j = v.lbase[tile]; j < j1; ++j) {   // the parts of the pair's sweep
+      const int64_t lrow = (int64_t)j * BQ + ql;
+      const uint64_t* lst = b.cand + lrow * b.cap1;
+      const uint64_t e0 = lst[threadIdx.x];   // issued with the count (WG <= cap1 slots)
+      const int c = b.cand_cnt[lrow];
+      seen += c;
       __syncthreads();
-      block_sort_u64(buf, N);
-      if (threadIdx.x == 0) fill_s = K1;
+      for (int i = threadIdx.x; i < c; i += WG) {
+        const uint64_t e = i < WG ? e0 : lst[i];
+        if (e <= cut) buf[atomicAdd(&fill_s, 1)] = e;
+      }
       __syncthreads();
+      const bool flush = (fill_s + K1 > SORT_CAP) || (p + 1 == np && j + 1 == j1);
+      if (flush && fill_s >= K1) {
+        const int F = fill_s;
+        const int N = next_pow2(F);
+        for (int i = F + threadIdx.x; i < N; i += WG) buf[i] = ~0ull;
+        __syncthreads();
+        block_sort_u64(buf, N);
+        if (threadIdx.x == 0) fill_s = K1;
+        __syncthreads();
+      }
     }
   }
   const int C = fill_s;
@@ -1233,8 +1283,9 @@ ivf_collect_kernel(IvfTiles v, KnnBuffers b) {
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
   __shared__ float yks[BQ], ths[BQ];
   __shared__ int qry[BQ];
-  const int64_t row0 = (int64_t)blockIdx.x * BQ;
-  if (row0 >= v.pp[v.L]) return;
+  IvfPart pt;
+  if (!ivf_part(v, blockIdx.x, pt)) return;
+  const int64_t row0 = pt.row0, t0 = pt.t0, t1 = pt.t1;
   int need = 0;
   if (threadIdx.x < BQ) {
     const int32_t qi = v.pair_q[row0 + threadIdx.x];
@@ -1245,12 +1296,6 @@ ivf_collect_kernel(IvfTiles v, KnnBuffers b) {
     need = on;
   }
   if (!__syncthreads_or(need)) return;   // no query of this tile needs the pass
-  int64_t lo = 0, hi = v.L;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (v.pp[mid] <= row0) lo = mid; else hi = mid;
-  }
-  const int64_t t0 = v.poff[lo] / BN, t1 = v.poff[lo + 1] / BN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
   const char* yq = v.Ys + row0 * v.ld_bytes;
@@ -1414,6 +1459,7 @@ hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers&
                           hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(b.status), q, 0u, s);
   if (e != hipSuccess) return e;
+  if ((e = launch_fill_u32(t.qthr, q, 0xff800000u, s)) != hipSuccess) return e;   // +inf key
   const dim3 g((unsigned)(prow_cap / BQ)), blk(WG);
   switch (b.cap1) {
     case 256: ivf_scan_kernel<4><<<g, blk, 0, s>>>(t, b.cand, b.cand_cnt, (int)b.K1); break;

@@ -163,3 +163,27 @@ def test_gpu_trained_index_and_recall():
     rec = [oracle.recall(oracle.knn(X, y, 40), nn[j]) for j, y in enumerate(Y)]
     print(f"recall at n_probe = 4 of 24 clusters: mean {np.mean(rec):.3f} min {np.min(rec):.3f}")
     assert np.mean(rec) > 0.5
+
+
+def test_long_sweeps_in_parts():
+    # uneven clusters (k-means gives about 4000, 4200, 2200 and 1100 rows, up
+    # to 34 data tiles): the query tiles of the large clusters sweep them in
+    # up to 4 parts, each with lists of its own, which the refinement merges
+    import paper_2107_02736_amd as dk
+    dev = device()
+    rng = np.random.default_rng(8)
+    d = 16
+    cen = rng.uniform(-20, 20, size=(4, d))
+    sizes = (8000, 2000, 1000, 500)
+    X = np.concatenate([cen[i] + rng.normal(size=(c, d)) for i, c in enumerate(sizes)])
+    X = X[rng.permutation(X.shape[0])].astype(np.float32)
+    Y = (cen[rng.choice(4, size=300, p=[0.55, 0.25, 0.1, 0.1])] +
+         rng.normal(size=(300, d))).astype(np.float32)
+    C, a = oracle.ivf_train(X, 4, 2)
+    assert np.bincount(a, minlength=4).max() >= 4000
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    index = dk.IvfIndex(Xd, to_dev(C, dev), to_dev(a.astype(np.int32), dev))
+    for n_probe, k, m in ((1, 50, 100), (2, 200, 60)):
+        out, nn, sm = (t.cpu().numpy() for t in dk.deann_ivf_query(
+            Xd, Yd, index, n_probe, 2.0, k, m, "gaussian", seed=3))
+        _check_queries(X, Y, C, a, n_probe, k, m, GAUSSIAN, 2.0, 3, out, nn, sm, range(0, 300, 4))

@@ -654,6 +654,8 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
 // ---------------------------------------------------------------------------
 // 3. second pass: collect every point whose key admits distance <= d_k
 // ---------------------------------------------------------------------------
+constexpr int COLLECT_STAGE = 128;   // staged second-pass hits per wave
+
 template <typename T, int ENG>   // ENG: see tile_engine
 __global__ void __launch_bounds__(WG, 2)
 knn_collect_kernel(TileProblem p, KnnBuffers b) {
@@ -677,6 +679,29 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
     const int64_t row = qt * BQ + threadIdx.x;
     ths[threadIdx.x] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
   }
+  // Hits are staged per wave in LDS, (query row in the tile) << 32 | column,
+  // and appended to the global lists in bulk, so a wave waits for one round of
+  // global atomics per drain rather than one per tile with a hit.  The stage is
+  // private to its wave: no barrier is needed to fill, test or drain it.  A hit
+  // that finds the stage full marks its query's list as overflowed (count above
+  // cap2), which sends that query to the exact scan, as a full list does.
+  __shared__ uint64_t stage[WG / 64][COLLECT_STAGE];
+  __shared__ int nst[WG / 64];
+  if (lane == 0) nst[wave] = 0;
+  auto drain = [&]() {
+    __builtin_amdgcn_wave_barrier();
+    const int c = nst[wave];
+    const int m = c < COLLECT_STAGE ? c : COLLECT_STAGE;
+    for (int e = lane; e < m; e += 64) {
+      const uint64_t v = stage[wave][e];
+      const int64_t row = qt * BQ + (int64_t)(v >> 32);
+      const int slot = atomicAdd(&b.cand2_cnt[row], 1);
+      if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = v & 0xffffffffull;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) nst[wave] = 0;
+    __builtin_amdgcn_wave_barrier();
+  };
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
   constexpr int NK = 2;   // k-groups of the register-resident engine
   StreamState st;
@@ -744,13 +769,19 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
             const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
             const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]);
             if (col < p.n && key <= th) {
-              const int slot = atomicAdd(&b.cand2_cnt[row], 1);
-              if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = (uint64_t)col;
+              const int e = atomicAdd(&nst[wave], 1);
+              if (e < COLLECT_STAGE)
+                stage[wave][e] = ((uint64_t)(row - qt * BQ) << 32) | (uint64_t)(uint32_t)col;
+              else
+                atomicMax(&b.cand2_cnt[row], b.cap2 + 1);
             }
           }
         }
     }
+    __builtin_amdgcn_wave_barrier();
+    if (nst[wave] >= COLLECT_STAGE / 2) drain();
   }
+  drain();
 }
 
 __global__ void __launch_bounds__(WG)

@@ -241,6 +241,33 @@ def test_knn_more_neighbours_than_cells(dev, n, k, prec):
         assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_second_pass_heavy_and_light_queries(dev, prec):
+    # half the queries sit in a blob of 1500 nearly equal rows that 16-bit keys
+    # cannot tell apart (every blob row passes the second-pass threshold, far
+    # more hits per tile than a wave stages: those queries go to the exact
+    # scan), the other half in sparse data with few hits; all must equal the
+    # oracle's k-NN and estimate
+    import paper_2107_02736_amd as dk
+    rng = np.random.default_rng(31)
+    d = 24
+    P = rng.uniform(-1, 1, size=d)
+    blob = P + 1e-3 * rng.normal(size=(1500, d))
+    rest = 3.0 * rng.normal(size=(1500, d))
+    X = np.concatenate([blob, rest])[rng.permutation(3000)].astype(np.float32)
+    Y = np.concatenate([P + 1e-3 * rng.normal(size=(64, d)),
+                        3.0 * rng.normal(size=(64, d))]).astype(np.float32)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    k, m, h = 50, 40, 2.0
+    out, nn, sm = (t.cpu().numpy() for t in dk.deann_query(Xd, Yd, h, k, m, "gaussian", seed=6,
+                                                            precision=prec))
+    for j in list(range(0, 64, 3)) + list(range(64, 128, 3)):
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, GAUSSIAN, k, m, 6, j)
+        assert np.array_equal(nn[j], nn_ref), j
+        assert np.array_equal(sm[j], s_ref), j
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_knn_exact_ties_and_duplicates(dev, prec):
     # integer lattice data: many exactly equal distances, duplicate rows

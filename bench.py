@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("queries/s at ≤1% rel KDE err, BF16+refine vs FP32; exact KDE % MFMA peak")
 WORKLOAD = "mix100_n1e6_d128"
 KERNEL = "gaussian"
+MEAN_SHIFT_STEPS = 20
 # (k, m) per workload; the default line is the 100-cluster mixture, the others
 # are for separate runs with --workload
 KM = {"mix100_n1e6_d128": (100, 1000), "mix10_n1e4_d16": (50, 500),
@@ -328,6 +329,21 @@ def main():
     torch.cuda.synchronize()
     ms_hyb_nn = a.elapsed_time(b) / reps
 
+    # Gaussian mean shift of all queries (not part of the step): MEAN_SHIFT_STEPS
+    # steps y <- y + h^2 grad(mu)/mu, with the exact density and gradient
+    # (one fused pass per step, d <= 128) and with DEANN (BF16 scan) and its adjoint
+    def time_mean_shift(method, **kw):
+        dk.mean_shift(Xd, Yd, h, 1, method, **kw)   # workspaces allocated once
+        torch.cuda.synchronize()
+        a.record()
+        y_end = dk.mean_shift(Xd, Yd, h, MEAN_SHIFT_STEPS, method, **kw)
+        b.record()
+        torch.cuda.synchronize()
+        del y_end
+        return a.elapsed_time(b)
+    ms_shift_exact = time_mean_shift("exact") if fused else None
+    ms_shift_deann = time_mean_shift("deann", k=K_NN, m=M_SAMPLES, seed=0, precision="bf16")
+
     mu_h = mu.cpu().numpy()
     mu_fwd_h = mu_fwd.cpu().numpy()
     mu16_h = mu16.cpu().numpy()
@@ -434,6 +450,15 @@ def main():
                                      "three-part bfloat16 MFMAs (DEANN_FP32_SPLIT), outside the "
                                      "timed step above"}
                             if ms_step_split else None),
+        "mean_shift": {"steps": MEAN_SHIFT_STEPS,
+                       "exact_ms": ms_shift_exact,
+                       "exact_query_steps_per_s": (q * MEAN_SHIFT_STEPS / (ms_shift_exact * 1e-3)
+                                                   if ms_shift_exact else None),
+                       "deann_bf16_ms": ms_shift_deann,
+                       "deann_bf16_query_steps_per_s": q * MEAN_SHIFT_STEPS
+                                                       / (ms_shift_deann * 1e-3),
+                       "note": "Gaussian mean shift of all queries; exact: kde_exact_with_grad "
+                               "per step (d <= 128 only); DEANN: deann_query + adjoint per step"},
         "ivf": {"n_clusters": n_clusters, "n_probe": n_probe, "iters": ivf_iters,
                 "build_s": t1 - t0, "index_s": t2 - t1, "ms": ms_ivf,
                 "queries_per_s": q / (ms_ivf * 1e-3),

@@ -221,12 +221,13 @@ __global__ void pair_gather_kernel(const float* __restrict__ Ys, const float* __
 
 // Parts of the pair tiles' sweeps.  Pair tile b (pair rows [128b, 128b+128))
 // sweeps the tiles_b data tiles of its cluster; it is split into
-// P_b = ceil(tiles_b / T) parts of near-equal length, each with lists of its
-// own, so that the longest workgroup of the scan is at most T tiles rather than
-// the largest cluster.  T = max(PART_MIN, ceil(S / target), ceil(S / (budget -
-// nb))) over the S tiles of all nb pair tiles keeps the parts at most budget:
-// sum P_b <= nb + S / T.  lbase[b] is the first part of pair tile b,
-// lbase[nb] = nparts[0] the number of parts; nparts[1] = T.
+// P_b = max(1, ceil(tiles_b / T)) parts of near-equal length, each with lists
+// of its own, so that the longest workgroup of the scan is at most T tiles
+// rather than the largest cluster.  T = max(PART_MIN, ceil(S / target),
+// ceil(S / (budget - nb))) over the S tiles of all nb pair tiles keeps the parts
+// at most budget: sum P_b <= nb + S / T (no tile is split when budget <= nb).
+// lbase[b] is the first part of pair tile b, lbase[nb] = nparts[0] the number
+// of parts; nparts[1] = T.
 constexpr int64_t PART_MIN = 8;
 __global__ void __launch_bounds__(IVF_SCAN_THREADS)
 pair_parts_kernel(const int32_t* __restrict__ pp, const int32_t* __restrict__ poff, int64_t L,

@@ -683,8 +683,7 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
   // and appended to the global lists in bulk, so a wave waits for one round of
   // global atomics per drain rather than one per tile with a hit.  The stage is
   // private to its wave: no barrier is needed to fill, test or drain it.  A hit
-  // that finds the stage full marks its query's list as overflowed (count above
-  // cap2), which sends that query to the exact scan, as a full list does.
+  // that finds the stage full goes straight to its query's list.
   __shared__ uint64_t stage[WG / 64][COLLECT_STAGE];
   __shared__ int nst[WG / 64];
   if (lane == 0) nst[wave] = 0;
@@ -772,8 +771,10 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
               const int e = atomicAdd(&nst[wave], 1);
               if (e < COLLECT_STAGE)
                 stage[wave][e] = ((uint64_t)(row - qt * BQ) << 32) | (uint64_t)(uint32_t)col;
-              else
-                atomicMax(&b.cand2_cnt[row], b.cap2 + 1);
+              else {   // stage full: straight to the list
+                const int slot = atomicAdd(&b.cand2_cnt[row], 1);
+                if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = (uint64_t)col;
+              }
             }
           }
         }

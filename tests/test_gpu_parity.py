@@ -245,8 +245,8 @@ def test_knn_more_neighbours_than_cells(dev, n, k, prec):
 def test_second_pass_heavy_and_light_queries(dev, prec):
     # half the queries sit in a blob of 1500 nearly equal rows that 16-bit keys
     # cannot tell apart (every blob row passes the second-pass threshold, far
-    # more hits per tile than a wave stages: those queries go to the exact
-    # scan), the other half in sparse data with few hits; all must equal the
+    # more hits per tile than a wave stages: the rest go straight to the
+    # lists), the other half in sparse data with few hits; all must equal the
     # oracle's k-NN and estimate
     import paper_2107_02736_amd as dk
     rng = np.random.default_rng(31)

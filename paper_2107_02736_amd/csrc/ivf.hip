@@ -207,16 +207,21 @@ __global__ void pair_scatter_kernel(const int32_t* __restrict__ probe, int64_t t
   pair_of[i] = row;
 }
 
-// Prepared query rows and key norms in pair order (zeros for padding rows).
+// Prepared query rows and key norms in pair order (zeros for padding rows),
+// one row per workgroup in turn; rows from pp[L] on belong to no pair tile
+// and are left unwritten.
+constexpr int64_t PAIR_GATHER_WGS = 8192;
 __global__ void pair_gather_kernel(const float* __restrict__ Ys, const float* __restrict__ yknorm,
-                                   int64_t dp, const int32_t* __restrict__ pair_q, int64_t cap,
+                                   int64_t dp, const int32_t* __restrict__ pair_q,
+                                   const int32_t* __restrict__ pp, int64_t L, int64_t cap,
                                    float* __restrict__ Yg, float* __restrict__ ygk) {
-  const int64_t r = blockIdx.x;
-  if (r >= cap) return;
-  const int32_t qi = pair_q[r];
-  for (int64_t t = threadIdx.x; t < dp; t += blockDim.x)
-    Yg[r * dp + t] = qi >= 0 ? Ys[(int64_t)qi * dp + t] : 0.f;
-  if (threadIdx.x == 0) ygk[r] = qi >= 0 ? yknorm[qi] : 0.f;
+  const int64_t rows = (int64_t)pp[L] < cap ? (int64_t)pp[L] : cap;
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int32_t qi = pair_q[r];
+    for (int64_t t = threadIdx.x; t < dp; t += blockDim.x)
+      Yg[r * dp + t] = qi >= 0 ? Ys[(int64_t)qi * dp + t] : 0.f;
+    if (threadIdx.x == 0) ygk[r] = qi >= 0 ? yknorm[qi] : 0.f;
+  }
 }
 
 // Parts of the pair tiles' sweeps.  Pair tile b (pair rows [128b, 128b+128))
@@ -355,7 +360,10 @@ hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t kp, const int32
   pair_scatter_kernel<<<dim3(g), dim3(WG), 0, s>>>(probe, total, kp, np_q, pp, pfill, pair_q,
                                                    pair_of);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  pair_gather_kernel<<<dim3((unsigned)cap), dim3(128), 0, s>>>(Ys, yknorm, dp, pair_q, cap, Yg, ygk);
+  const int64_t gw = cap < PAIR_GATHER_WGS ? cap : PAIR_GATHER_WGS;
+  if (gw == 0) return hipSuccess;
+  pair_gather_kernel<<<dim3((unsigned)gw), dim3(128), 0, s>>>(Ys, yknorm, dp, pair_q, pp, L, cap,
+                                                              Yg, ygk);
   return hipGetLastError();
 }
 

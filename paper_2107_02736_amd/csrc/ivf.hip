@@ -188,23 +188,55 @@ __global__ void empty_row_keys_kernel(const int32_t* __restrict__ pids,
 
 // ---- query batch: (cluster, query) pairs ------------------------------------
 // probe[q][kp]: inspected clusters of each query, the first np_q[q] valid.
-__global__ void pair_count_kernel(const int32_t* __restrict__ probe, int64_t total, int64_t kp,
-                                  const int32_t* __restrict__ np_q, int32_t* __restrict__ pcount) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < total && i % kp < np_q[i / kp]) atomicAdd(&pcount[probe[i]], 1);
+// A workgroup takes PAIR_CHUNK consecutive (query, slot) entries and counts
+// its pairs per cluster in LDS, so the global counters of the few clusters
+// see one atomic per workgroup instead of one per pair.
+constexpr int64_t PAIR_CHUNK = 16384;
+__global__ void __launch_bounds__(WG)
+pair_count_kernel(const int32_t* __restrict__ probe, int64_t total, int64_t kp,
+                  const int32_t* __restrict__ np_q, int64_t L, int32_t* __restrict__ pcount) {
+  extern __shared__ int32_t hist[];   // [L]
+  for (int64_t l = threadIdx.x; l < L; l += WG) hist[l] = 0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * PAIR_CHUNK;
+  const int64_t i1 = i0 + PAIR_CHUNK < total ? i0 + PAIR_CHUNK : total;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += WG)
+    if (i % kp < np_q[i / kp]) atomicAdd(&hist[probe[i]], 1);
+  __syncthreads();
+  for (int64_t l = threadIdx.x; l < L; l += WG)
+    if (hist[l] != 0) atomicAdd(&pcount[l], hist[l]);
 }
 
-// Pair rows of cluster l: [pp[l], pp[l] + pcount[l]), padded to the tile.
-__global__ void pair_scatter_kernel(const int32_t* __restrict__ probe, int64_t total, int64_t kp,
-                                    const int32_t* __restrict__ np_q, const int32_t* __restrict__ pp,
-                                    int32_t* __restrict__ pfill, int32_t* __restrict__ pair_q,
-                                    int32_t* __restrict__ pair_of) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total || i % kp >= np_q[i / kp]) return;
-  const int32_t l = probe[i];
-  const int32_t row = pp[l] + atomicAdd(&pfill[l], 1);
-  pair_q[row] = (int32_t)(i / kp);
-  pair_of[i] = row;
+// Pair rows of cluster l: [pp[l], pp[l] + pcount[l]), padded to the tile.  A
+// workgroup reserves one range of slots per cluster (one global atomic) and
+// hands them out to its pairs from LDS; the order of pairs inside a cluster
+// is unspecified.
+__global__ void __launch_bounds__(WG)
+pair_scatter_kernel(const int32_t* __restrict__ probe, int64_t total, int64_t kp,
+                    const int32_t* __restrict__ np_q, int64_t L, const int32_t* __restrict__ pp,
+                    int32_t* __restrict__ pfill, int32_t* __restrict__ pair_q,
+                    int32_t* __restrict__ pair_of) {
+  extern __shared__ int32_t hist[];   // [2L]: counts, then slot bases
+  int32_t* base = hist + L;
+  for (int64_t l = threadIdx.x; l < L; l += WG) hist[l] = 0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * PAIR_CHUNK;
+  const int64_t i1 = i0 + PAIR_CHUNK < total ? i0 + PAIR_CHUNK : total;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += WG)
+    if (i % kp < np_q[i / kp]) atomicAdd(&hist[probe[i]], 1);
+  __syncthreads();
+  for (int64_t l = threadIdx.x; l < L; l += WG) {
+    base[l] = hist[l] != 0 ? pp[l] + atomicAdd(&pfill[l], hist[l]) : 0;
+    hist[l] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += WG) {
+    if (i % kp >= np_q[i / kp]) continue;
+    const int32_t l = probe[i];
+    const int32_t row = base[l] + atomicAdd(&hist[l], 1);
+    pair_q[row] = (int32_t)(i / kp);
+    pair_of[i] = row;
+  }
 }
 
 // Prepared query rows and key norms in pair order (zeros for padding rows),
@@ -350,15 +382,17 @@ hipError_t launch_pairs(const int32_t* probe, int64_t q, int64_t kp, const int32
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pfill), L, 0u, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pair_q), cap, 0xffffffffu, s)) != hipSuccess)
     return e;
-  const unsigned g = (unsigned)ceil_div(total, WG);
-  pair_count_kernel<<<dim3(g), dim3(WG), 0, s>>>(probe, total, kp, np_q, pcount);
+  const unsigned g = (unsigned)ceil_div(total, PAIR_CHUNK);
+  const size_t sm = (size_t)L * 4;
+  if (g > 0) pair_count_kernel<<<dim3(g), dim3(WG), sm, s>>>(probe, total, kp, np_q, L, pcount);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   list_offsets_kernel<<<dim3(1), dim3(IVF_SCAN_THREADS), 0, s>>>(pcount, L, BN, pfill, pp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // pfill held the unpadded prefix; reset it to count the slots
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(pfill), L, 0u, s)) != hipSuccess) return e;
-  pair_scatter_kernel<<<dim3(g), dim3(WG), 0, s>>>(probe, total, kp, np_q, pp, pfill, pair_q,
-                                                   pair_of);
+  if (g > 0)
+    pair_scatter_kernel<<<dim3(g), dim3(WG), 2 * sm, s>>>(probe, total, kp, np_q, L, pp, pfill,
+                                                          pair_q, pair_of);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t gw = cap < PAIR_GATHER_WGS ? cap : PAIR_GATHER_WGS;
   if (gw == 0) return hipSuccess;

@@ -37,7 +37,10 @@ Parity status of each function (what pins it in tests/test_oracle_*.py):
       unbiasedness over seeds.
   kde_grad / deann_grad pinned: central finite differences, n=1 closed form.
   mean_shift pinned: n=1 lands on the point in one step; density never
-      decreases along exact Gaussian mean-shift steps.
+      decreases along exact Gaussian mean-shift steps; a DEANN step with
+      k < n equals y + h^2 grad/est of deann_grad over the same neighbours and
+      draws (counter word 2 = step), and a wrong sample weight or a repeated
+      word 2 moves the end point detectably.
   bisect_h   pinned: monotonicity of KDE in h and the target tolerance.
   kmeans_init / kmeans_assign / kmeans_update / ivf_train pinned: Lloyd
       steps computed by hand on one-dimensional data (an empty cluster,

@@ -146,6 +146,41 @@ def test_mean_shift_pins():
     assert np.allclose(a, b, rtol=1e-6, atol=1e-6)
 
 
+def test_mean_shift_deann_sampled_step_pins():
+    # k < n: a DEANN mean-shift step is y + h^2 grad(est) / est with the
+    # estimate and gradient of the same neighbour set and draws (Gaussian:
+    # grad = (1/n) sum W (x - y) / h^2 with W = K times the Algorithm 1
+    # weight), and step t draws with counter word 2 = t.
+    Xd, Yd = _data(n=300, d=3, seed=8)
+    n, h, k, m, seed, stream = 300, 0.8, 20, 40, 3, 2
+    y0 = Yd[2]
+    got = oracle.mean_shift_deann(Xd, y0, h, k, m, seed, stream, steps=2)
+
+    def step(y, t):
+        y32 = np.asarray(y, dtype=np.float32)
+        nn = oracle.knn(Xd, y32, k)
+        s = oracle.sample_indices(n, nn, m, seed, stream, word2=t)
+        est, gy, _ = oracle.deann_grad(Xd, y32.astype(np.float64), h, GAUSSIAN, nn, s, m)
+        return (y32.astype(np.float64) + h * h * gy / est).astype(np.float32), nn, s
+
+    y1, nn0, s0 = step(y0, 0)
+    y2, _, s1 = step(y1, 1)
+    assert np.allclose(got, y2.astype(np.float64), rtol=0, atol=1e-6)
+    assert not np.array_equal(s0, s1)            # the two steps draw different rows
+    # the pin tells the sample weight apart: with weight 1 instead of (n-k)/m
+    # (or with step 1 drawing word 2 = 0) the end point moves far beyond atol
+    y1w = y1.astype(np.float64)
+    rows = np.concatenate([nn0, s0])
+    wts = np.concatenate([np.ones(k), np.ones(m)])
+    R = Xd[rows].astype(np.float64)
+    y0d = np.asarray(y0, dtype=np.float32).astype(np.float64)
+    K = np.exp(-((R - y0d) ** 2).sum(1) / (2 * h * h)) * wts
+    y1_wrong = (K[:, None] * R).sum(0) / K.sum()
+    assert np.abs(y1_wrong - y1w).max() > 1e-3
+    y2_same_draws = step(y1, 0)[0]
+    assert np.abs(y2_same_draws.astype(np.float64) - y2.astype(np.float64)).max() > 1e-4
+
+
 def test_bisect_bandwidth_hits_target():
     X, Y = _data(n=500, d=6)
     D2 = oracle.pairwise_sq_dists(X, Y)

@@ -137,6 +137,28 @@ int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, i
                          double* grad_h, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the same adjoint
+ * as deann_query_backward, with the same arguments, kernels and results bit
+ * for bit, but with no workspace.  Its per-query scratch (the dK/dh terms,
+ * DEANN_NOALLOC_MAX_Q doubles = 8 MiB) is a device array of the library; each
+ * GPU the library runs on holds its own copy from the first call on that
+ * device until the process ends.  The entry point allocates nothing and frees
+ * nothing.  `stream` must belong to the current device.
+ *   q > DEANN_NOALLOC_MAX_Q  -> DEANN_EUNSUPPORTED (nothing launched).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (different streams or host threads) race and must be ordered by the
+ * caller.  Each call writes every entry it reads, so a call never sees the
+ * contents a previous call left.
+ * ------------------------------------------------------------------------- */
+#define DEANN_NOALLOC_MAX_Q (1 << 20)
+int deann_query_backward_noalloc(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                                 double h, int kernel, int64_t k, int64_t m,
+                                 const int32_t* nn_idx, const int32_t* sample_idx,
+                                 const double* grad_out, float* grad_Y, double* grad_h,
+                                 void* stream);
+
+/* ---------------------------------------------------------------------------
  * Adjoint of kde_exact (d <= 128):
  *   grad_Y[j] = grad_out[j] * (1/n) sum_i dK/dy (x_i, y_j),   [q, d] or NULL
  *   grad_h    = sum_j grad_out[j] * (1/n) sum_i dK/dh,        [1] or NULL.

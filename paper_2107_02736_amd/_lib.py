@@ -12,6 +12,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdeann.so")
 
 OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
+NOALLOC_MAX_Q = 1 << 20   # DEANN_NOALLOC_MAX_Q
 GAUSSIAN, EXPONENTIAL = 0, 1
 FP32, BF16, FP16, FP32_SPLIT = 0, 1, 2, 3
 
@@ -19,7 +20,7 @@ EXPORTS = (
     "kde_exact_workspace", "kde_exact",
     "deann_query_workspace", "deann_query",
     "deann_query_permuted_workspace", "deann_query_permuted",
-    "deann_query_backward_workspace", "deann_query_backward",
+    "deann_query_backward_workspace", "deann_query_backward", "deann_query_backward_noalloc",
     "kde_exact_backward_workspace", "kde_exact_backward",
     "kde_exact_with_grad_workspace", "kde_exact_with_grad", "mean_shift_update",
     "kde_hybrid_workspace", "kde_hybrid",
@@ -73,6 +74,9 @@ def load(path: str = LIB_PATH):
     lib.deann_query_backward.restype = _int
     lib.deann_query_backward.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64, _vp,
                                          _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    lib.deann_query_backward_noalloc.restype = _int
+    lib.deann_query_backward_noalloc.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64,
+                                                 _i64, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kde_exact_backward_workspace.restype = _sz
     lib.kde_exact_backward_workspace.argtypes = [_i64, _i64, _i64, _int]
     lib.kde_exact_backward.restype = _int

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/deann.h"
@@ -516,10 +517,15 @@ size_t deann_query_backward_workspace(int64_t n, int64_t q, int64_t d, int64_t k
   return (size_t)(round_up((q > 0 ? q : 1) * 8, kAlign) + kAlign);
 }
 
-int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
-                         double h, int kernel, int64_t k, int64_t m, const int32_t* nn_idx,
-                         const int32_t* sample_idx, const double* grad_out, float* grad_Y,
-                         double* grad_h, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+// Argument checks shared by both adjoint entry points of deann_query; returns
+// DEANN_OK with *noop set when q = 0 leaves nothing to do.
+static int check_deann_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                                double h, int kernel, int64_t k, int64_t m, const int32_t* nn_idx,
+                                const int32_t* sample_idx, const double* grad_out, double* grad_h,
+                                bool* noop) {
+  *noop = false;
   int st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (k < 0 || k > n) return fail(DEANN_EINVAL, "k must be in [0, n]");
@@ -527,16 +533,91 @@ int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, i
   if (d > 2048) return fail(DEANN_EUNSUPPORTED, "d > 2048 is not supported by the backward");
   if (q == 0) {
     if (grad_h) return fail(DEANN_EUNSUPPORTED, "grad_h with q = 0: nothing to write into");
+    *noop = true;
     return DEANN_OK;
   }
   if (k > 0 && !nn_idx) return fail(DEANN_EINVAL, "nn_idx is NULL");
   if (m > 0 && k < n && !sample_idx) return fail(DEANN_EINVAL, "sample_idx is NULL");
   if (!grad_out) return fail(DEANN_EINVAL, "grad_out is NULL");
+  return DEANN_OK;
+}
+
+// Scratch of deann_query_backward_noalloc: the per-query dK/dh terms that the
+// workspace holds otherwise.  Each device holds its own copy of the array; in
+// host code its name is only a stand-in, so its device address is looked up
+// once per device (hipGetSymbolAddress with that device current) and only that
+// address is ever handed to a kernel.
+static __device__ __align__(256) double scratch[DEANN_NOALLOC_MAX_Q];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device that `stream` runs on, which must
+// be the current device.
+int scratch_address(hipStream_t stream, double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (stream) {
+    int sdev = 0;
+    e = hipStreamGetDevice(stream, &sdev);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+    if (sdev != dev)
+      return fail(DEANN_EINVAL, "stream is on device %d but device %d is current", sdev, dev);
+  }
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(DEANN_EUNSUPPORTED, "device ordinal %d is beyond %d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return DEANN_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                         double h, int kernel, int64_t k, int64_t m, const int32_t* nn_idx,
+                         const int32_t* sample_idx, const double* grad_out, float* grad_Y,
+                         double* grad_h, void* ws, size_t ws_bytes, void* stream) {
+  bool noop = false;
+  int st = check_deann_backward(X, n, Y, q, d, h, kernel, k, m, nn_idx, sample_idx, grad_out,
+                                grad_h, &noop);
+  if (st != DEANN_OK || noop) return st;
   const int64_t need = (int64_t)deann_query_backward_workspace(n, q, d, k, m);
   if (!ws || (int64_t)ws_bytes < need)
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* gh_part = static_cast<double*>(align_ws(ws));
+  hipError_t e = launch_deann_backward(X, Y, n, q, d, h, kernel, k, m, nn_idx, sample_idx,
+                                       grad_out, grad_Y, gh_part, grad_h, s);
+  if (e != hipSuccess) return hip_fail(e, "deann backward");
+  return DEANN_OK;
+}
+
+int deann_query_backward_noalloc(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                                 double h, int kernel, int64_t k, int64_t m,
+                                 const int32_t* nn_idx, const int32_t* sample_idx,
+                                 const double* grad_out, float* grad_Y, double* grad_h,
+                                 void* stream) {
+  bool noop = false;
+  int st = check_deann_backward(X, n, Y, q, d, h, kernel, k, m, nn_idx, sample_idx, grad_out,
+                                grad_h, &noop);
+  if (st != DEANN_OK || noop) return st;
+  if (q > DEANN_NOALLOC_MAX_Q)
+    return fail(DEANN_EUNSUPPORTED, "q = %lld exceeds the %d queries of the library's scratch",
+                (long long)q, DEANN_NOALLOC_MAX_Q);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* gh_part = nullptr;
+  if ((st = scratch_address(s, &gh_part)) != DEANN_OK) return st;
+  // every query's entry is written before the h sum reads it: nothing to clear
   hipError_t e = launch_deann_backward(X, Y, n, q, d, h, kernel, k, m, nn_idx, sample_idx,
                                        grad_out, grad_Y, gh_part, grad_h, s);
   if (e != hipSuccess) return hip_fail(e, "deann backward");

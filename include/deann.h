@@ -53,6 +53,53 @@ typedef enum {
 } deann_status;
 
 /* ---------------------------------------------------------------------------
+ * Options of the calls a host thread makes (thread-local; the defaults hold
+ * until deann_set_options is called on that thread).  Workspace sizes depend
+ * on knn_slack: query them after setting the options.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  /* float32-operand exact KDE (kde_exact with DEANN_FP32 or DEANN_FP32_SPLIT,
+   * kde_exact_backward, kde_exact_with_grad): every query carries a bound of
+   * the relative error of its kernel sum, from the sums of K and K^2 of the
+   * tile sweep (probabilistic: roundings taken as independent, failure
+   * probability below 3e-8 per query); a query whose bound exceeds rel_tol is
+   * re-evaluated exactly (FP64 differences of the float32 rows), unless its
+   * value is certainly below value_floor.  rel_tol in [1e-7, 1], default
+   * 1e-5; value_floor >= 0, default 1e-16 (the paper reports no relative
+   * error below 1e-16); value_floor = 0 re-evaluates every such query. */
+  double rel_tol;
+  double value_floor;
+  /* exact k-NN: each candidate list keeps K1 = the power of two >= max(k +
+   * knn_slack, 64) smallest keys (k + knn_slack <= 512; default 16); a query
+   * whose second pass collects more than knn_cap2 rows (in [1, 4096], default
+   * 4096) is scanned exhaustively in FP64.  Neither changes any result. */
+  int64_t knn_slack;
+  int64_t knn_cap2;
+  /* 1 (default): rows are centred on the column mean of X before the
+   * distance tiles (the KDE is translation invariant; centring shrinks the
+   * norms the GEMM identity cancels); 0: raw coordinates. */
+  int32_t center;
+  int32_t reserved; /* 0 */
+} deann_options;
+
+void deann_default_options(deann_options* opt);
+deann_status deann_get_options(deann_options* opt);
+/* DEANN_EINVAL (options unchanged) if a field is out of range. */
+deann_status deann_set_options(const deann_options* opt);
+
+/* Counts of the last call made on this thread (measurement and tests): the
+ * queries the exact KDE re-evaluated in FP64, the queries of the k-NN that
+ * needed its second pass and those scanned exhaustively; -1 where the call
+ * had no such step.  Synchronises `stream` and copies counters from that
+ * call's workspace, which must still be allocated. */
+typedef struct {
+  int64_t exact_refined;
+  int64_t knn_second_pass;
+  int64_t knn_exhaustive;
+} deann_stats;
+deann_status deann_last_stats(deann_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Exact KDE, Eq. (1):  out[j] = (1/n) sum_i K_h(x_i, y_j).
  *
  * Distances use the identity ||x-y||^2 = ||x||^2 + ||y||^2 - 2<x,y> of App. F
@@ -63,9 +110,9 @@ typedef enum {
  * Requirements: n >= 1, d >= 1, q >= 0 (q = 0 is a no-op), h finite and > 0,
  * n and q < 2^31.
  * ------------------------------------------------------------------------- */
-size_t kde_exact_workspace(int64_t n, int64_t q, int64_t d, int precision);
-int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-              int kernel, int precision, double* out, void* ws, size_t ws_bytes, void* stream);
+size_t kde_exact_workspace(int64_t n, int64_t q, int64_t d, deann_precision precision);
+deann_status kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+              deann_kernel kernel, deann_precision precision, double* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * DEANN estimate, Algorithm 1, with an exact k-NN in place of the ANN:
@@ -93,10 +140,10 @@ int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, d
  * m >= 0, n < 2^31.
  * ------------------------------------------------------------------------- */
 size_t deann_query_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
-                             int precision);
-int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                int kernel, int64_t k, int64_t m, uint64_t seed, uint64_t query_offset,
-                uint64_t word2, int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
+                             deann_precision precision);
+deann_status deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                deann_kernel kernel, int64_t k, int64_t m, uint64_t seed, uint64_t query_offset,
+                uint64_t word2, deann_precision precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
                 void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
@@ -114,10 +161,10 @@ int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
  * Requirements: as deann_query, plus m <= n - k when k < n.
  * ------------------------------------------------------------------------- */
 size_t deann_query_permuted_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
-                                      int precision);
-int deann_query_permuted(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
-                         double h, int kernel, int64_t k, int64_t m, uint64_t seed,
-                         uint64_t start, int precision, double* out, int32_t* nn_idx,
+                                      deann_precision precision);
+deann_status deann_query_permuted(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                         double h, deann_kernel kernel, int64_t k, int64_t m, uint64_t seed,
+                         uint64_t start, deann_precision precision, double* out, int32_t* nn_idx,
                          int32_t* sample_idx, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
@@ -131,8 +178,8 @@ int deann_query_permuted(const float* X, int64_t n, const float* Y, int64_t q, i
  * (n, k, m).  Rows are gathered again and distances recomputed in FP64.
  * ------------------------------------------------------------------------- */
 size_t deann_query_backward_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m);
-int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
-                         double h, int kernel, int64_t k, int64_t m, const int32_t* nn_idx,
+deann_status deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                         double h, deann_kernel kernel, int64_t k, int64_t m, const int32_t* nn_idx,
                          const int32_t* sample_idx, const double* grad_out, float* grad_Y,
                          double* grad_h, void* ws, size_t ws_bytes, void* stream);
 
@@ -152,8 +199,8 @@ int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, i
  * contents a previous call left.
  * ------------------------------------------------------------------------- */
 #define DEANN_NOALLOC_MAX_Q (1 << 20)
-int deann_query_backward_noalloc(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
-                                 double h, int kernel, int64_t k, int64_t m,
+deann_status deann_query_backward_noalloc(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                                 double h, deann_kernel kernel, int64_t k, int64_t m,
                                  const int32_t* nn_idx, const int32_t* sample_idx,
                                  const double* grad_out, float* grad_Y, double* grad_h,
                                  void* stream);
@@ -167,9 +214,9 @@ int deann_query_backward_noalloc(const float* X, int64_t n, const float* Y, int6
  * three-part bfloat16 operands as in kde_exact; the weighted sum W X on float32
  * MFMAs either way).
  * ------------------------------------------------------------------------- */
-size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d, int precision);
-int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                       int kernel, int precision, const double* grad_out, float* grad_Y,
+size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d, deann_precision precision);
+deann_status kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                       deann_kernel kernel, deann_precision precision, const double* grad_out, float* grad_Y,
                        double* grad_h, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
@@ -182,9 +229,9 @@ int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int
  * i.e. kde_exact, and kde_exact_backward with grad_out = 1 except that the h
  * derivative is returned per query.  Costs one kde_exact_backward.
  * ------------------------------------------------------------------------- */
-size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d, int precision);
-int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                        int kernel, int precision, double* out, float* grad_Y, double* grad_h,
+size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d, deann_precision precision);
+deann_status kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                        deann_kernel kernel, deann_precision precision, double* out, float* grad_Y, double* grad_h,
                         void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
@@ -207,9 +254,9 @@ int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, in
  * Requirements: as kde_exact, plus 0 <= k <= n, d <= 4096 when k > 0 and
  * q k < 2^31 when 0 < k < n.
  * ------------------------------------------------------------------------- */
-size_t kde_hybrid_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int precision);
-int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-               int kernel, int64_t k, int precision, const int32_t* nn_in, double* out,
+size_t kde_hybrid_workspace(int64_t n, int64_t q, int64_t d, int64_t k, deann_precision precision);
+deann_status kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+               deann_kernel kernel, int64_t k, deann_precision precision, const int32_t* nn_in, double* out,
                int32_t* nn_idx, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
@@ -251,18 +298,18 @@ int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, 
  *   made with; 1 <= n_probe <= min(n_clusters, 496); k <= 496 or k = n.
  * ------------------------------------------------------------------------- */
 size_t ivf_build_workspace(int64_t n, int64_t d, int64_t n_clusters);
-int ivf_build(const float* X, int64_t n, int64_t d, int64_t n_clusters, int iters,
+deann_status ivf_build(const float* X, int64_t n, int64_t d, int64_t n_clusters, int iters,
               float* centroids, int32_t* assign, void* ws, size_t ws_bytes, void* stream);
 size_t ivf_index_bytes(int64_t n, int64_t d, int64_t n_clusters);
 size_t ivf_index_create_workspace(int64_t n, int64_t d, int64_t n_clusters);
-int ivf_index_create(const float* X, int64_t n, int64_t d, const int32_t* assign,
+deann_status ivf_index_create(const float* X, int64_t n, int64_t d, const int32_t* assign,
                      int64_t n_clusters, void* index, size_t index_bytes, void* ws,
                      size_t ws_bytes, void* stream);
 size_t deann_ivf_query_workspace(int64_t n, int64_t q, int64_t d, int64_t n_clusters,
                                  int64_t n_probe, int64_t k, int64_t m);
-int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+deann_status deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
                     const void* index, const float* centroids, int64_t n_clusters,
-                    int64_t n_probe, double h, int kernel, int64_t k, int64_t m, uint64_t seed,
+                    int64_t n_probe, double h, deann_kernel kernel, int64_t k, int64_t m, uint64_t seed,
                     uint64_t query_offset, double* out, int32_t* nn_idx, int32_t* sample_idx,
                     void* ws, size_t ws_bytes, void* stream);
 
@@ -274,7 +321,7 @@ int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_
  * grad_out = 1).  Y, grad_Y, Y_out [q, d] float32 (Y_out may alias Y),
  * density [q] float64; a query with density 0 keeps its point.
  * ------------------------------------------------------------------------- */
-int mean_shift_update(const float* Y, const float* grad_Y, const double* density, int64_t q,
+deann_status mean_shift_update(const float* Y, const float* grad_Y, const double* density, int64_t q,
                       int64_t d, double h, float* Y_out, void* stream);
 
 /* Message for the last non-OK status returned on the calling thread. */
@@ -293,7 +340,7 @@ const char* deann_last_error(void);
  * writes up to max_count durations in milliseconds to the host array ms (in
  * call order), frees the site's slots and returns the count, or -1 on error.
  * ------------------------------------------------------------------------- */
-int deann_kernel_timing(int capacity);
+deann_status deann_kernel_timing(int capacity);
 int deann_kernel_times(int site, float* ms, int max_count);
 
 #ifdef __cplusplus

@@ -26,9 +26,23 @@ EXPORTS = (
     "kde_hybrid_workspace", "kde_hybrid",
     "ivf_build_workspace", "ivf_build", "ivf_index_bytes", "ivf_index_create_workspace",
     "ivf_index_create", "deann_ivf_query_workspace", "deann_ivf_query",
-    "deann_last_error",
+    "deann_last_error", "deann_default_options", "deann_get_options", "deann_set_options",
+    "deann_last_stats",
     "deann_kernel_timing", "deann_kernel_times",
 )
+
+
+class Options(ctypes.Structure):
+    """deann_options (include/deann.h)."""
+    _fields_ = [("rel_tol", ctypes.c_double), ("value_floor", ctypes.c_double),
+                ("knn_slack", ctypes.c_int64), ("knn_cap2", ctypes.c_int64),
+                ("center", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    """deann_stats (include/deann.h)."""
+    _fields_ = [("exact_refined", ctypes.c_int64), ("knn_second_pass", ctypes.c_int64),
+                ("knn_exhaustive", ctypes.c_int64)]
 
 
 class DeannError(RuntimeError):
@@ -111,6 +125,14 @@ def load(path: str = LIB_PATH):
     lib.deann_ivf_query.restype = _int
     lib.deann_ivf_query.argtypes = [_vp, _i64, _vp, _i64, _i64, _vp, _vp, _i64, _i64, _dbl, _int,
                                     _i64, _i64, _u64, _u64, _vp, _vp, _vp, _vp, _sz, _vp]
+    lib.deann_default_options.restype = None
+    lib.deann_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.deann_get_options.restype = _int
+    lib.deann_get_options.argtypes = [ctypes.POINTER(Options)]
+    lib.deann_set_options.restype = _int
+    lib.deann_set_options.argtypes = [ctypes.POINTER(Options)]
+    lib.deann_last_stats.restype = _int
+    lib.deann_last_stats.argtypes = [ctypes.POINTER(Stats), _vp]
     lib.deann_kernel_timing.restype = _int
     lib.deann_kernel_timing.argtypes = [_int]
     lib.deann_kernel_times.restype = _int

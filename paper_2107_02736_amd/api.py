@@ -144,6 +144,16 @@ def deann_query_backward(X, Y, h, k, m, nn_idx, sample_idx, grad_out, kernel="ga
     n, d = X.shape
     q = Y.shape[0]
     dev = X.device
+    # the kernels use the entries as row indices of X: shapes, dtype and device
+    # are checked here (values are those a forward call returned)
+    for name, t, cols in (("nn_idx", nn_idx, k), ("sample_idx", sample_idx, m)):
+        if t is None:
+            continue
+        if (t.dtype != torch.int32 or t.device != dev or not t.is_contiguous()
+                or tuple(t.shape) != (q, cols)):
+            raise ValueError(f"{name} must be a contiguous int32 [q, {cols}] tensor on X's device")
+    if grad_out.numel() != q:
+        raise ValueError("grad_out must hold one value per query")
     grad_out = grad_out.to(device=dev, dtype=torch.float64).contiguous()
     gy = torch.empty((q, d), dtype=torch.float32, device=dev) if need_grad_y else None
     gh = torch.empty(1, dtype=torch.float64, device=dev) if need_grad_h else None
@@ -209,6 +219,43 @@ def mean_shift_update(Y, grad_Y, density, h, out=None):
     _lib.check(lib.mean_shift_update(Y.data_ptr(), grad_Y.data_ptr(), density.data_ptr(), q, d,
                                      float(h), out.data_ptr(), _stream(Y.device)))
     return out
+
+
+def get_options() -> dict:
+    """The options of this thread's calls (deann_options) as a dict."""
+    o = _lib.Options()
+    _lib.check(_lib.load().deann_get_options(o))
+    return {name: getattr(o, name) for name, _ in _lib.Options._fields_ if name != "reserved"}
+
+
+def set_options(**kw) -> dict:
+    """Change some options of this thread's calls (rel_tol, value_floor, knn_slack,
+    knn_cap2, center); returns the previous options."""
+    prev = get_options()
+    o = _lib.Options()
+    _lib.check(_lib.load().deann_get_options(o))
+    for name, v in kw.items():
+        if name not in prev:
+            raise KeyError(name)
+        setattr(o, name, v)
+    _lib.check(_lib.load().deann_set_options(o))
+    return prev
+
+
+def default_options() -> dict:
+    o = _lib.Options()
+    _lib.load().deann_default_options(o)
+    return {name: getattr(o, name) for name, _ in _lib.Options._fields_ if name != "reserved"}
+
+
+def last_stats(device=None) -> dict:
+    """Counts of the last call on this thread (synchronises the stream): queries
+    re-evaluated exactly by the exact KDE, and the k-NN queries that needed the
+    second pass or the exhaustive scan (-1: no such step)."""
+    st = _lib.Stats()
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    _lib.check(_lib.load().deann_last_stats(st, _stream(dev)))
+    return {name: int(getattr(st, name)) for name, _ in _lib.Stats._fields_}
 
 
 TIMING_SITES = {"kde_exact": 0, "kde_exact_backward": 1, "kde_hybrid": 2}

@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdeann.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["prep.hip", "kde_fwd.hip", "knn.hip", "sample.hip", "backward.hip", "ivf.hip", "hybrid.hip",
-           "api.cpp"]
+SOURCES = ["prep.hip", "kde_fwd.hip", "cert.hip", "knn.hip", "sample.hip", "backward.hip", "ivf.hip",
+           "hybrid.hip", "api.cpp"]
 ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

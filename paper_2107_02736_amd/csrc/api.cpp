@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/deann.h"
 #include "common.h"
@@ -19,8 +20,8 @@ namespace {
 
 thread_local std::string g_last_error;
 
-int fail(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int status, const char* fmt, ...) {
+deann_status fail(deann_status status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+deann_status fail(deann_status status, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -30,7 +31,7 @@ int fail(int status, const char* fmt, ...) {
   return status;
 }
 
-int hip_fail(hipError_t e, const char* what) {
+deann_status hip_fail(hipError_t e, const char* what) {
   return fail(DEANN_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -67,9 +68,38 @@ TimingHook timer_hook(int site) {
 }
 
 constexpr int64_t kAlign = 256;
+constexpr int64_t kSortCapMax = 4096;      // second-pass candidate capacity per query (workspace)
+
+deann_options default_options() {
+  deann_options o{};
+  o.rel_tol = 1e-5;
+  o.value_floor = 1e-16;
+  o.knn_slack = 16;
+  o.knn_cap2 = kSortCapMax;
+  o.center = 1;
+  o.reserved = 0;
+  return o;
+}
+
+// Options of the calls made on this thread (deann_set_options).
+thread_local deann_options g_opt = default_options();
+
+// Device counters of the last call on this thread, for deann_last_stats: the
+// exact KDE's list length of re-evaluated queries, the k-NN status per query.
+struct LastCall {
+  const int32_t* refined = nullptr;
+  const int32_t* knn_status = nullptr;
+  int64_t knn_q = 0;
+};
+thread_local LastCall g_last;
+
+void record_last(const int32_t* refined, const int32_t* knn_status, int64_t q) {
+  g_last.refined = refined;
+  g_last.knn_status = knn_status;
+  g_last.knn_q = knn_status ? q : 0;
+}
 constexpr int64_t kMaxK = 496;             // k limit of the candidate-list kernels (K1 <= 512)
 constexpr int64_t kCenterRows = 2048;      // row slices of the column-mean reduction
-constexpr int64_t kSortCap = 4096;         // second-pass candidate capacity per query
 
 int64_t elem_bytes(int prec) { return prec == DEANN_FP32 ? 4 : 2; }
 
@@ -122,7 +152,7 @@ Prep carve_prep(Carve& cv, int64_t n, int64_t q, int64_t d, int prec) {
   p.ynorm = cv.take<double>(p.qp);
   p.yknorm = cv.take<float>(p.qp);
   p.yerr = cv.take<float>(p.qp);
-  p.err_max = cv.take<uint32_t>(2);
+  p.err_max = cv.take<uint32_t>(3);   // rounding bounds of X and Y, largest data norm
   return p;
 }
 
@@ -169,13 +199,15 @@ TileProblem make_problem(const Prep& p, int64_t n, int64_t q, int prec, int64_t 
 hipError_t run_prep(const Prep& p, const float* X, int64_t n, const float* Y, int64_t q,
                     int64_t d, int prec, hipStream_t s) {
   const int64_t R = n < kCenterRows ? n : kCenterRows;
-  hipError_t e = launch_center(X, n, d, p.cpart, R, p.c, s);
+  hipError_t e = g_opt.center ? launch_center(X, n, d, p.cpart, R, p.c, s)
+                              : launch_fill_u32(reinterpret_cast<uint32_t*>(p.c), d, 0u, s);
   if (e != hipSuccess) return e;
-  if ((e = launch_fill_u32(p.err_max, 2, 0u, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(p.err_max, 3, 0u, s)) != hipSuccess) return e;
   const double a = key_scale(p.dp);
   e = launch_prep_rows_prec(prec, X, n, p.np, d, p.dp, p.c, a, p.Xs, p.xnorm, p.xknorm, p.xerr,
                             p.err_max, s);
   if (e != hipSuccess) return e;
+  if ((e = launch_max_u32(p.xknorm, n, p.err_max + 2, s)) != hipSuccess) return e;
   return launch_prep_rows_prec(prec, Y, q, p.qp, d, p.dp, p.c, a, p.Ys, p.ynorm, p.yknorm, p.yerr,
                                p.err_max + 1, s);
 }
@@ -183,7 +215,7 @@ hipError_t run_prep(const Prep& p, const float* X, int64_t n, const float* Y, in
 bool bad_prec(int prec) { return prec != DEANN_FP32 && prec != DEANN_BF16 && prec != DEANN_FP16; }
 bool bad_kernel(int k) { return k != DEANN_GAUSSIAN && k != DEANN_EXPONENTIAL; }
 
-int check_common(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+deann_status check_common(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
                  int kernel) {
   if (n < 1) return fail(DEANN_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
   if (d < 1) return fail(DEANN_EINVAL, "d must be >= 1 (got %lld)", (long long)d);
@@ -203,11 +235,46 @@ constexpr int64_t kKnnSplitTarget = 512;     // selection scan: about one wave o
 constexpr int64_t kCollectSplitTarget = 4096;  // candidate and collect passes
 constexpr int64_t kIvfPartTarget = 512;        // inverted-file sweep parts: 2 per CU
 
+// Certificate of the float32-operand sweeps (see cert.hip): queries whose
+// bounded relative error exceeds the rel_tol option are re-evaluated exactly,
+// unless their value is certainly below the value_floor option (by default
+// 1e-16: the paper reports no relative error for KDE values under 1e-16).
+
+struct CertBuf {
+  float2* part;      // [splits][qp]
+  int32_t* ids;      // [q]
+  int32_t* count;    // [1]
+};
+
+CertBuf carve_cert(Carve& cv, int64_t splits, int64_t qp, int64_t q) {
+  CertBuf c{};
+  c.part = cv.take<float2>(splits * qp);
+  c.ids = cv.take<int32_t>(q > 0 ? q : 1);
+  c.count = cv.take<int32_t>(1);
+  return c;
+}
+
+// cd: roundings of one dot product (its accumulation length)
+CertArgs cert_args(const CertBuf& c, const Prep& p, int64_t cd) {
+  CertArgs a{};
+  a.part = c.part;
+  a.xnmax = p.err_max + 2;
+  a.a_scale = key_scale(p.dp);
+  a.cd = (int)cd;
+  a.tau = g_opt.rel_tol;
+  a.floor = g_opt.value_floor;
+  a.fb_ids = c.ids;
+  a.fb_count = c.count;
+  return a;
+}
+
 struct KdePlan {
   Prep prep;
   double* partial;
   char *Xsp, *Ysp;   // three-part bfloat16 rows (DEANN_FP32_SPLIT)
   int64_t dps;
+  CertBuf cert;      // float32 operands only
+  double* fb_part;   // [direct_splits(n)][q]
   int64_t bytes;
 };
 
@@ -224,12 +291,16 @@ KdePlan plan_kde(void* ws, int64_t n, int64_t q, int64_t d, int prec) {
   const int64_t qtiles = k.prep.qp / BQ, ntiles = k.prep.np / BN;
   const int64_t splits = choose_splits(qtiles, ntiles, kKdeSplitTarget);
   k.partial = cv.take<double>(splits * k.prep.qp);
+  if (prec == DEANN_FP32 || split) {
+    k.cert = carve_cert(cv, splits, k.prep.qp, q);
+    k.fb_part = cv.take<double>(direct_splits(n) * (q > 0 ? q : 1));
+  }
   k.bytes = cv.off + kAlign;
   return k;
 }
 
 int64_t knn_K1(int64_t k) {
-  int64_t v = k + 16;
+  int64_t v = k + g_opt.knn_slack;
   if (v < 64) v = 64;
   int64_t p = 1;
   while (p < v) p <<= 1;
@@ -263,8 +334,8 @@ DeannPlan plan_deann(void* ws, int64_t n, int64_t q, int64_t d, int64_t k, int p
   b.z1 = cv.take<double>(q > 0 ? q : 1);
   b.thr2 = cv.take<float>(q > 0 ? q : 1);
   b.flags = cv.take<int32_t>(qtiles > 0 ? qtiles : 1);
-  b.cap2 = kSortCap;
-  b.cand2 = cv.take<uint64_t>(q * b.cap2);
+  b.cand2 = cv.take<uint64_t>(q * kSortCapMax);
+  b.cap2 = g_opt.knn_cap2;   // row stride of cand2 as well: within the carved rows
   b.cand2_cnt = cv.take<int32_t>(q > 0 ? q : 1);
   b.status = cv.take<int32_t>(q > 0 ? q : 1);
   b.yerr = P.prep.yerr;
@@ -308,6 +379,7 @@ struct KdeBwdPlan {
   double* gh_part;   // gh, rw, ks [splits][qp] each, then per-query [q]
   char *Xsp, *Ysp;   // three-part bfloat16 rows (DEANN_FP32_SPLIT)
   int64_t dps;
+  CertBuf cert;
   int64_t bytes;
 };
 
@@ -324,6 +396,7 @@ KdeBwdPlan plan_kde_bwd(void* ws, int64_t n, int64_t q, int64_t d, int precision
     P.Xsp = cv.take<char>(P.prep.np * 3 * P.dps * 2);
     P.Ysp = cv.take<char>(P.prep.qp * 3 * P.dps * 2);
   }
+  P.cert = carve_cert(cv, splits, P.prep.qp, q);
   P.bytes = cv.off + kAlign;
   return P;
 }
@@ -359,7 +432,62 @@ extern "C" {
 
 const char* deann_last_error(void) { return g_last_error.c_str(); }
 
-int deann_kernel_timing(int capacity) {
+void deann_default_options(deann_options* o) {
+  if (o) *o = default_options();
+}
+
+deann_status deann_get_options(deann_options* o) {
+  if (!o) return fail(DEANN_EINVAL, "options pointer is NULL");
+  *o = g_opt;
+  return DEANN_OK;
+}
+
+deann_status deann_set_options(const deann_options* o) {
+  if (!o) return fail(DEANN_EINVAL, "options pointer is NULL");
+  if (!(o->rel_tol >= 1e-7 && o->rel_tol <= 1.0))
+    return fail(DEANN_EINVAL, "rel_tol must be in [1e-7, 1]");
+  if (!(o->value_floor >= 0.0 && std::isfinite(o->value_floor)))
+    return fail(DEANN_EINVAL, "value_floor must be finite and >= 0");
+  if (o->knn_slack < 0 || o->knn_slack > 512)
+    return fail(DEANN_EINVAL, "knn_slack must be in [0, 512]");
+  if (o->knn_cap2 < 1 || o->knn_cap2 > kSortCapMax)
+    return fail(DEANN_EINVAL, "knn_cap2 must be in [1, %lld]", (long long)kSortCapMax);
+  if (o->center != 0 && o->center != 1) return fail(DEANN_EINVAL, "center must be 0 or 1");
+  if (o->reserved != 0) return fail(DEANN_EINVAL, "reserved must be 0");
+  g_opt = *o;
+  return DEANN_OK;
+}
+
+deann_status deann_last_stats(deann_stats* st, void* stream) {
+  if (!st) return fail(DEANN_EINVAL, "stats pointer is NULL");
+  st->exact_refined = -1;
+  st->knn_second_pass = -1;
+  st->knn_exhaustive = -1;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (g_last.refined) {
+    int32_t c = 0;
+    e = hipMemcpy(&c, g_last.refined, sizeof(c), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "stats copy");
+    st->exact_refined = c;
+  }
+  if (g_last.knn_status && g_last.knn_q > 0) {
+    std::vector<int32_t> v((size_t)g_last.knn_q);
+    e = hipMemcpy(v.data(), g_last.knn_status, v.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "stats copy");
+    int64_t a = 0, b = 0;
+    for (int32_t x : v) {   // final states: 0 first pass, 4 second pass, 5 exhaustive scan
+      a += x == 4 || x == 5;
+      b += x == 5;
+    }
+    st->knn_second_pass = a;
+    st->knn_exhaustive = b;
+  }
+  return DEANN_OK;
+}
+
+deann_status deann_kernel_timing(int capacity) {
   if (capacity < 0 || capacity > 4096)
     return fail(DEANN_EINVAL, "timing capacity must be in [0, 4096] (got %d)", capacity);
   timer_release();
@@ -398,14 +526,14 @@ int deann_kernel_times(int site, float* ms, int max_count) {
   return n;
 }
 
-size_t kde_exact_workspace(int64_t n, int64_t q, int64_t d, int precision) {
+size_t kde_exact_workspace(int64_t n, int64_t q, int64_t d, deann_precision precision) {
   if (n < 1 || d < 1 || q < 0 || (bad_prec(precision) && precision != DEANN_FP32_SPLIT)) return 0;
   return (size_t)plan_kde(nullptr, n, q, d, precision).bytes;
 }
 
-int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-              int kernel, int precision, double* out, void* ws, size_t ws_bytes, void* stream) {
-  int st = check_common(X, n, Y, q, d, h, kernel);
+deann_status kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+              deann_kernel kernel, deann_precision precision, double* out, void* ws, size_t ws_bytes, void* stream) {
+  deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   const bool split = precision == DEANN_FP32_SPLIT;
   if (bad_prec(precision) && !split) return fail(DEANN_EINVAL, "unknown precision %d", precision);
@@ -417,6 +545,7 @@ int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, d
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   KdePlan P = plan_kde(align_ws(ws), n, q, d, precision);
+  record_last(P.cert.count, nullptr, q);   // null for 16-bit operands
   const int prep_prec = split ? DEANN_FP32 : precision;
   hipError_t e = run_prep(P.prep, X, n, Y, q, d, prep_prec, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
@@ -429,16 +558,19 @@ int kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, d
                             P.dps, P.Ysp, s);
     if (e == hipSuccess)
       e = launch_kde_exact_split(tp, P.Xsp, P.Ysp, P.dps, kernel, h, P.partial, out, s,
-                                 timer_hook(0));
+                                 timer_hook(0), cert_args(P.cert, P.prep, P.dps + 4), X, Y, d,
+                                 P.fb_part);
   } else {
-    e = launch_kde_exact(precision, tp, kernel, h, P.partial, out, s, timer_hook(0));
+    const CertArgs ca = precision == DEANN_FP32 ? cert_args(P.cert, P.prep, P.prep.dp) : CertArgs{};
+    e = launch_kde_exact(precision, tp, kernel, h, P.partial, out, s, timer_hook(0), ca, X, Y, d,
+                         P.fb_part);
   }
   if (e != hipSuccess) return hip_fail(e, "kde_exact");
   return DEANN_OK;
 }
 
 size_t deann_query_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
-                             int precision) {
+                             deann_precision precision) {
   (void)m;
   if (n < 1 || d < 1 || q < 0 || k < 0 || k > n || bad_prec(precision)) return 0;
   return (size_t)plan_deann(nullptr, n, q, d, k, precision).bytes;
@@ -446,12 +578,12 @@ size_t deann_query_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t
 
 }  // extern "C"
 
-static int deann_query_impl(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+static deann_status deann_query_impl(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
                             double h, int kernel, int64_t k, int64_t m, uint64_t seed,
                             uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
                             int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
                             void* ws, size_t ws_bytes, void* stream) {
-  int st = check_common(X, n, Y, q, d, h, kernel);
+  deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_prec(precision)) return fail(DEANN_EINVAL, "unknown precision %d", precision);
   if (k < 0 || k > n) return fail(DEANN_EINVAL, "k must be in [0, n] (got %lld)", (long long)k);
@@ -459,6 +591,9 @@ static int deann_query_impl(const float* X, int64_t n, const float* Y, int64_t q
   if (k > kMaxK && k != n)
     return fail(DEANN_EUNSUPPORTED, "k = %lld: supported are k <= %lld and k = n", (long long)k,
                 (long long)kMaxK);
+  if (k > 0 && k < n && knn_K1(k) > 512)
+    return fail(DEANN_EUNSUPPORTED, "k + knn_slack = %lld exceeds the 512 candidates of a list",
+                (long long)(k + g_opt.knn_slack));
   if (d > 4096) return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported by deann_query");
   if (permuted && k < n && m > n - k)
     return fail(DEANN_EINVAL, "permuted sampling needs m <= n - k (got m = %lld)", (long long)m);
@@ -470,6 +605,7 @@ static int deann_query_impl(const float* X, int64_t n, const float* Y, int64_t q
   hipStream_t s = static_cast<hipStream_t>(stream);
   DeannPlan P = plan_deann(align_ws(ws), n, q, d, k, precision);
   P.kb.nn_work = nn_idx ? nn_idx : P.nn_internal;
+  record_last(nullptr, (k > 0 && k < n) ? P.kb.status : nullptr, q);
   hipError_t e;
   if (k == n) {
     e = launch_knn_all(X, Y, n, q, d, h, kernel, P.kb.nn_work, P.kb.z1, s);
@@ -490,22 +626,22 @@ static int deann_query_impl(const float* X, int64_t n, const float* Y, int64_t q
 
 extern "C" {
 
-int deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                int kernel, int64_t k, int64_t m, uint64_t seed, uint64_t query_offset,
-                uint64_t word2, int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
+deann_status deann_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                deann_kernel kernel, int64_t k, int64_t m, uint64_t seed, uint64_t query_offset,
+                uint64_t word2, deann_precision precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
                 void* ws, size_t ws_bytes, void* stream) {
   return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, query_offset, word2, 0, 0,
                           precision, out, nn_idx, sample_idx, ws, ws_bytes, stream);
 }
 
 size_t deann_query_permuted_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
-                                      int precision) {
+                                      deann_precision precision) {
   return deann_query_workspace(n, q, d, k, m, precision);
 }
 
-int deann_query_permuted(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
-                         double h, int kernel, int64_t k, int64_t m, uint64_t seed,
-                         uint64_t start, int precision, double* out, int32_t* nn_idx,
+deann_status deann_query_permuted(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                         double h, deann_kernel kernel, int64_t k, int64_t m, uint64_t seed,
+                         uint64_t start, deann_precision precision, double* out, int32_t* nn_idx,
                          int32_t* sample_idx, void* ws, size_t ws_bytes, void* stream) {
   return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, 0, 0, 1, start, precision, out,
                           nn_idx, sample_idx, ws, ws_bytes, stream);
@@ -521,12 +657,12 @@ size_t deann_query_backward_workspace(int64_t n, int64_t q, int64_t d, int64_t k
 
 // Argument checks shared by both adjoint entry points of deann_query; returns
 // DEANN_OK with *noop set when q = 0 leaves nothing to do.
-static int check_deann_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+static deann_status check_deann_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
                                 double h, int kernel, int64_t k, int64_t m, const int32_t* nn_idx,
                                 const int32_t* sample_idx, const double* grad_out, double* grad_h,
                                 bool* noop) {
   *noop = false;
-  int st = check_common(X, n, Y, q, d, h, kernel);
+  deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (k < 0 || k > n) return fail(DEANN_EINVAL, "k must be in [0, n]");
   if (m < 0) return fail(DEANN_EINVAL, "m must be >= 0");
@@ -556,7 +692,7 @@ double* g_scratch_ptr[kMaxDevices] = {};
 
 // Device address of `scratch` on the device that `stream` runs on, which must
 // be the current device.
-int scratch_address(hipStream_t stream, double** out) {
+deann_status scratch_address(hipStream_t stream, double** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -583,12 +719,12 @@ int scratch_address(hipStream_t stream, double** out) {
 
 extern "C" {
 
-int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
-                         double h, int kernel, int64_t k, int64_t m, const int32_t* nn_idx,
+deann_status deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                         double h, deann_kernel kernel, int64_t k, int64_t m, const int32_t* nn_idx,
                          const int32_t* sample_idx, const double* grad_out, float* grad_Y,
                          double* grad_h, void* ws, size_t ws_bytes, void* stream) {
   bool noop = false;
-  int st = check_deann_backward(X, n, Y, q, d, h, kernel, k, m, nn_idx, sample_idx, grad_out,
+  deann_status st = check_deann_backward(X, n, Y, q, d, h, kernel, k, m, nn_idx, sample_idx, grad_out,
                                 grad_h, &noop);
   if (st != DEANN_OK || noop) return st;
   const int64_t need = (int64_t)deann_query_backward_workspace(n, q, d, k, m);
@@ -602,13 +738,13 @@ int deann_query_backward(const float* X, int64_t n, const float* Y, int64_t q, i
   return DEANN_OK;
 }
 
-int deann_query_backward_noalloc(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
-                                 double h, int kernel, int64_t k, int64_t m,
+deann_status deann_query_backward_noalloc(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                                 double h, deann_kernel kernel, int64_t k, int64_t m,
                                  const int32_t* nn_idx, const int32_t* sample_idx,
                                  const double* grad_out, float* grad_Y, double* grad_h,
                                  void* stream) {
   bool noop = false;
-  int st = check_deann_backward(X, n, Y, q, d, h, kernel, k, m, nn_idx, sample_idx, grad_out,
+  deann_status st = check_deann_backward(X, n, Y, q, d, h, kernel, k, m, nn_idx, sample_idx, grad_out,
                                 grad_h, &noop);
   if (st != DEANN_OK || noop) return st;
   if (q > DEANN_NOALLOC_MAX_Q)
@@ -624,15 +760,15 @@ int deann_query_backward_noalloc(const float* X, int64_t n, const float* Y, int6
   return DEANN_OK;
 }
 
-size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d, int precision) {
+size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d, deann_precision precision) {
   if (n < 1 || d < 1 || q < 0 || bad_exact_grad_prec(precision)) return 0;
   return (size_t)plan_kde_bwd(nullptr, n, q, d, precision).bytes;
 }
 
-int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                       int kernel, int precision, const double* grad_out, float* grad_Y,
+deann_status kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                       deann_kernel kernel, deann_precision precision, const double* grad_out, float* grad_Y,
                        double* grad_h, void* ws, size_t ws_bytes, void* stream) {
-  int st = check_common(X, n, Y, q, d, h, kernel);
+  deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_exact_grad_prec(precision))
     return fail(DEANN_EINVAL, "precision must be DEANN_FP32 or DEANN_FP32_SPLIT");
@@ -644,6 +780,7 @@ int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   KdeBwdPlan P = plan_kde_bwd(align_ws(ws), n, q, d, precision);
+  record_last(P.cert.count, nullptr, q);
   SplitRows sp;
   hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
@@ -651,13 +788,14 @@ int kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int
   // one 8-wave workgroup per CU: the query tiles of the split-major order
   // already fit the L2 next to the shared data tiles
   tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
-  e = launch_kde_backward(tp, Y, d, h, kernel, grad_out, P.gy_part, P.gh_part, grad_Y, grad_h, s,
-                          timer_hook(1), nullptr, nullptr, sp);
+  e = launch_kde_backward(tp, X, Y, d, h, kernel, grad_out, P.gy_part, P.gh_part, grad_Y, grad_h,
+                          s, timer_hook(1), nullptr, nullptr, sp,
+                          cert_args(P.cert, P.prep, sp.X ? P.dps + 4 : P.prep.dp));
   if (e != hipSuccess) return hip_fail(e, "kde backward");
   return DEANN_OK;
 }
 
-int mean_shift_update(const float* Y, const float* grad_Y, const double* density, int64_t q,
+deann_status mean_shift_update(const float* Y, const float* grad_Y, const double* density, int64_t q,
                       int64_t d, double h, float* Y_out, void* stream) {
   if (q < 0 || d < 1) return fail(DEANN_EINVAL, "need q >= 0 and d >= 1");
   if (!(h > 0.0) || !std::isfinite(h)) return fail(DEANN_EINVAL, "h must be finite and > 0");
@@ -669,15 +807,15 @@ int mean_shift_update(const float* Y, const float* grad_Y, const double* density
   return DEANN_OK;
 }
 
-size_t kde_hybrid_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int precision) {
+size_t kde_hybrid_workspace(int64_t n, int64_t q, int64_t d, int64_t k, deann_precision precision) {
   if (n < 1 || d < 1 || q < 0 || k < 0 || k > n || bad_hyb_prec(precision)) return 0;
   return (size_t)plan_hybrid(nullptr, n, q, d, k, precision).bytes;
 }
 
-int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-               int kernel, int64_t k, int precision, const int32_t* nn_in, double* out,
+deann_status kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+               deann_kernel kernel, int64_t k, deann_precision precision, const int32_t* nn_in, double* out,
                int32_t* nn_idx, void* ws, size_t ws_bytes, void* stream) {
-  int st = check_common(X, n, Y, q, d, h, kernel);
+  deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_hyb_prec(precision))
     return fail(DEANN_EINVAL, "kde_hybrid takes DEANN_BF16 or DEANN_FP16 (got %d)", precision);
@@ -685,6 +823,9 @@ int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, 
   if (!nn_in && k > kMaxK && k != n)
     return fail(DEANN_EUNSUPPORTED, "k = %lld: supported are k <= %lld and k = n", (long long)k,
                 (long long)kMaxK);
+  if (!nn_in && k > 0 && k < n && knn_K1(k) > 512)
+    return fail(DEANN_EUNSUPPORTED, "k + knn_slack = %lld exceeds the 512 candidates of a list",
+                (long long)(k + g_opt.knn_slack));
   if (k > 0 && d > 4096)
     return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported by kde_hybrid with k > 0");
   if (k > 0 && k < n && q * k >= ((int64_t)1 << 31))
@@ -696,6 +837,7 @@ int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, 
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   HybPlan H = plan_hybrid(align_ws(ws), n, q, d, k, precision);
+  record_last(nullptr, (!nn_in && k > 0 && k < n) ? H.dn.kb.status : nullptr, q);
   hipError_t e;
   if (k == n) {   // every row is near: the exact FP64 sum
     if (nn_in) {
@@ -717,7 +859,8 @@ int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, 
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tk = make_problem(H.dn.prep, n, q, precision, kKdeSplitTarget);
   if (k == 0) {   // nothing is near: the 16-bit sweep of kde_exact
-    e = launch_kde_exact(precision, tk, kernel, h, H.partial, out, s, timer_hook(2));
+    e = launch_kde_exact(precision, tk, kernel, h, H.partial, out, s, timer_hook(2), CertArgs{},
+                         X, Y, d, nullptr);
     if (e != hipSuccess) return hip_fail(e, "kde_hybrid (k = 0)");
     return DEANN_OK;
   }
@@ -744,14 +887,14 @@ int kde_hybrid(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, 
   return DEANN_OK;
 }
 
-size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d, int precision) {
+size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d, deann_precision precision) {
   return kde_exact_backward_workspace(n, q, d, precision);
 }
 
-int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                        int kernel, int precision, double* out, float* grad_Y, double* grad_h,
+deann_status kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                        deann_kernel kernel, deann_precision precision, double* out, float* grad_Y, double* grad_h,
                         void* ws, size_t ws_bytes, void* stream) {
-  int st = check_common(X, n, Y, q, d, h, kernel);
+  deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_exact_grad_prec(precision))
     return fail(DEANN_EINVAL, "precision must be DEANN_FP32 or DEANN_FP32_SPLIT");
@@ -763,13 +906,15 @@ int kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, in
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   KdeBwdPlan P = plan_kde_bwd(align_ws(ws), n, q, d, precision);
+  record_last(P.cert.count, nullptr, q);
   SplitRows sp;
   hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, kKdeSplitTarget);
   tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
-  e = launch_kde_backward(tp, Y, d, h, kernel, nullptr, P.gy_part, P.gh_part, grad_Y, nullptr, s,
-                          timer_hook(1), out, grad_h, sp);
+  e = launch_kde_backward(tp, X, Y, d, h, kernel, nullptr, P.gy_part, P.gh_part, grad_Y, nullptr,
+                          s, timer_hook(1), out, grad_h, sp,
+                          cert_args(P.cert, P.prep, sp.X ? P.dps + 4 : P.prep.dp));
   if (e != hipSuccess) return hip_fail(e, "kde value and gradient");
   return DEANN_OK;
 }
@@ -952,8 +1097,8 @@ IvfQueryPlan plan_ivf_query(void* ws, int64_t n, int64_t q, int64_t d, int64_t L
   b.z1 = cv.take<double>(q > 0 ? q : 1);
   b.status = cv.take<int32_t>(q > 0 ? q : 1);
   b.thr2 = cv.take<float>(q > 0 ? q : 1);
-  b.cap2 = kSortCap;
-  b.cand2 = cv.take<uint64_t>(q * b.cap2);
+  b.cand2 = cv.take<uint64_t>(q * kSortCapMax);
+  b.cap2 = g_opt.knn_cap2;   // row stride of cand2 as well: within the carved rows
   b.cand2_cnt = cv.take<int32_t>(q > 0 ? q : 1);
   b.yerr = P.yerr;
   P.bytes = cv.off + kAlign;
@@ -970,7 +1115,7 @@ size_t ivf_build_workspace(int64_t n, int64_t d, int64_t n_clusters) {
   return (size_t)plan_ivf_build(nullptr, n, d, n_clusters).bytes;
 }
 
-int ivf_build(const float* X, int64_t n, int64_t d, int64_t n_clusters, int iters,
+deann_status ivf_build(const float* X, int64_t n, int64_t d, int64_t n_clusters, int iters,
               float* centroids, int32_t* assign, void* ws, size_t ws_bytes, void* stream) {
   if (n < 1 || d < 1) return fail(DEANN_EINVAL, "need n >= 1 and d >= 1");
   if (n >= (int64_t)1 << 31) return fail(DEANN_EINVAL, "n must be < 2^31");
@@ -1011,7 +1156,7 @@ size_t ivf_index_create_workspace(int64_t n, int64_t d, int64_t n_clusters) {
   return (size_t)plan_ivf_create(nullptr, n, d, n_clusters).bytes;
 }
 
-int ivf_index_create(const float* X, int64_t n, int64_t d, const int32_t* assign,
+deann_status ivf_index_create(const float* X, int64_t n, int64_t d, const int32_t* assign,
                      int64_t n_clusters, void* index, size_t index_bytes, void* ws,
                      size_t ws_bytes, void* stream) {
   if (n < 1 || d < 1) return fail(DEANN_EINVAL, "need n >= 1 and d >= 1");
@@ -1055,18 +1200,21 @@ size_t deann_ivf_query_workspace(int64_t n, int64_t q, int64_t d, int64_t n_clus
   return (size_t)plan_ivf_query(nullptr, n, q, d, n_clusters, n_probe, k).bytes;
 }
 
-int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+deann_status deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
                     const void* index, const float* centroids, int64_t n_clusters,
-                    int64_t n_probe, double h, int kernel, int64_t k, int64_t m, uint64_t seed,
+                    int64_t n_probe, double h, deann_kernel kernel, int64_t k, int64_t m, uint64_t seed,
                     uint64_t query_offset, double* out, int32_t* nn_idx, int32_t* sample_idx,
                     void* ws, size_t ws_bytes, void* stream) {
-  int st = check_common(X, n, Y, q, d, h, kernel);
+  deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (k < 0 || k > n) return fail(DEANN_EINVAL, "k must be in [0, n] (got %lld)", (long long)k);
   if (m < 0) return fail(DEANN_EINVAL, "m must be >= 0 (got %lld)", (long long)m);
   if (k > kMaxK && k != n)
     return fail(DEANN_EUNSUPPORTED, "k = %lld: supported are k <= %lld and k = n", (long long)k,
                 (long long)kMaxK);
+  if (k > 0 && k < n && knn_K1(k) > 512)
+    return fail(DEANN_EUNSUPPORTED, "k + knn_slack = %lld exceeds the 512 candidates of a list",
+                (long long)(k + g_opt.knn_slack));
   if (d > 4096) return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported");
   if (n_clusters < 1 || n_clusters > kMaxClusters)
     return fail(DEANN_EINVAL, "n_clusters must be in [1, %lld]", (long long)kMaxClusters);
@@ -1080,6 +1228,7 @@ int deann_ivf_query(const float* X, int64_t n, const float* Y, int64_t q, int64_
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   IvfQueryPlan P = plan_ivf_query(align_ws(ws), n, q, d, n_clusters, n_probe, k);
+  record_last(nullptr, nullptr, q);
   // the index buffer is read only
   IvfIndex x = carve_index(align_ws(const_cast<void*>(index)), n, d, n_clusters);
   P.kb.nn_work = nn_idx ? nn_idx : P.nn_internal;

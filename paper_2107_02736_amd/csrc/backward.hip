@@ -13,8 +13,7 @@
 // the weights W = dK/dy-scale land in registers exactly in the A-operand layout
 // of a second MFMA product G = W X~ (k dimension = data rows).  Then
 // dKDE/dy = (G - y~ rowsum(W)) / n in the centred coordinates.
-#include "common.h"
-#include "kernels.h"
+#include "cert.h"
 
 namespace deann {
 
@@ -324,9 +323,11 @@ template <int KERN, int DP, bool VAL, int TR>
 __global__ void __launch_bounds__(BWG, TR == 64 ? 4 : 1)
 kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
                     double* __restrict__ rw_part, double* __restrict__ gh_part,
-                    double* __restrict__ ks_part) {
+                    double* __restrict__ ks_part, float2* __restrict__ cert) {
   using G = GradTile<DP>;
-  constexpr bool KS = VAL && KERN != KERNEL_GAUSSIAN;
+  // the certificate needs sum K for the exponential kernel (Gaussian: the weights)
+  constexpr bool KS = KERN != KERNEL_GAUSSIAN;
+  (void)VAL;
   constexpr int NBI = TR / 16, UPT = BN / TR;
   constexpr int NPT = TR * DP / 4 / BWG;   // 16-byte pieces per thread and step
   static_assert(NPT >= 1 && TR * DP / 4 == NPT * BWG, "row pieces must split evenly");
@@ -378,6 +379,8 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
 #pragma unroll
   for (int i = 0; i < G::GB; ++i) gacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
   double rws = 0.0, dhs = 0.0, kss = 0.0;
+  // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential: largest K
+  float csq = 0.f, cmx = 0.f;
 
   if (t0 < t1) {
     gload(t0);
@@ -427,6 +430,8 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
             const float K = __builtin_amdgcn_exp2f(a);
             w = K;
             dh = K * a;
+            csq = __builtin_fmaf(K, K, csq);
+            cmx = __builtin_fmaf(-K, a, cmx);   // Gaussian: sum of K times its exponent
           } else {
             const float d2 = fmaxf(__builtin_fmaf(-2.f, s, yv + xv[r]), 0.f);
             const float rr = __builtin_sqrtf(d2);
@@ -434,6 +439,8 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
             w = rr > 0.f ? K * __builtin_amdgcn_rcpf(rr) : 0.f;
             dh = K * rr;
             if constexpr (KS) ks32 += K;
+            csq = __builtin_fmaf(K, K, csq);
+            cmx = fmaxf(cmx, K);
           }
           acc[bi][r] = w;
           rw32 += w;
@@ -481,11 +488,21 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
     kss += __shfl_xor(kss, 16, 64);
     kss += __shfl_xor(kss, 32, 64);
   }
+  csq += __shfl_xor(csq, 16, 64);
+  csq += __shfl_xor(csq, 32, 64);
+  if (KERN == KERNEL_GAUSSIAN) {
+    cmx += __shfl_xor(cmx, 16, 64);
+    cmx += __shfl_xor(cmx, 32, 64);
+  } else {
+    cmx = fmaxf(cmx, __shfl_xor(cmx, 16, 64));
+    cmx = fmaxf(cmx, __shfl_xor(cmx, 32, 64));
+  }
   const int64_t qbase = split * p.qp + qt * BQ + wave * 16;
   if (g == 0) {
     rw_part[qbase + c] = rws;
     gh_part[qbase + c] = dhs;
     if constexpr (KS) ks_part[qbase + c] = kss;
+    cert[qbase + c] = make_float2(csq, cmx);
   }
   // G block (nb, j): lane (g, c), register rr holds query 4g + rr, coordinate
   // nb*64 + 4c + j (trailing block: NB*64 + 2c + j)
@@ -513,9 +530,11 @@ __global__ void __launch_bounds__(BWG, 1)
 kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
                           const char* __restrict__ Ysp, float L, double* __restrict__ gy_part,
                           double* __restrict__ rw_part, double* __restrict__ gh_part,
-                          double* __restrict__ ks_part) {
+                          double* __restrict__ ks_part, float2* __restrict__ cert) {
   using G = GradTile<DP>;
-  constexpr bool KS = VAL && KERN != KERNEL_GAUSSIAN;
+  // the certificate needs sum K for the exponential kernel (Gaussian: the weights)
+  constexpr bool KS = KERN != KERNEL_GAUSSIAN;
+  (void)VAL;
   constexpr int TR = 64, NBI = TR / 16, UPT = BN / TR;
   constexpr int KC = DPS / 32;                 // 32-element k-chunks per plane
   constexpr int RB = 3 * DPS * 2;              // bytes per split row
@@ -586,6 +605,8 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
 #pragma unroll
   for (int i = 0; i < G::GB; ++i) gacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
   double rws = 0.0, dhs = 0.0, kss = 0.0;
+  // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential: largest K
+  float csq = 0.f, cmx = 0.f;
 
   if (u0 < u1) {
     gload(u0);
@@ -647,6 +668,8 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
             const float K = __builtin_amdgcn_exp2f(a);
             w = K;
             dh = K * a;
+            csq = __builtin_fmaf(K, K, csq);
+            cmx = __builtin_fmaf(-K, a, cmx);   // Gaussian: sum of K times its exponent
           } else {
             const float d2 = fmaxf(__builtin_fmaf(-2.f, sv, yv + xv[r]), 0.f);
             const float rr = __builtin_sqrtf(d2);
@@ -654,6 +677,8 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
             w = rr > 0.f ? K * __builtin_amdgcn_rcpf(rr) : 0.f;
             dh = K * rr;
             if constexpr (KS) ks32 += K;
+            csq = __builtin_fmaf(K, K, csq);
+            cmx = fmaxf(cmx, K);
           }
           acc[bi][r] = w;
           rw32 += w;
@@ -701,11 +726,21 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
     kss += __shfl_xor(kss, 16, 64);
     kss += __shfl_xor(kss, 32, 64);
   }
+  csq += __shfl_xor(csq, 16, 64);
+  csq += __shfl_xor(csq, 32, 64);
+  if (KERN == KERNEL_GAUSSIAN) {
+    cmx += __shfl_xor(cmx, 16, 64);
+    cmx += __shfl_xor(cmx, 32, 64);
+  } else {
+    cmx = fmaxf(cmx, __shfl_xor(cmx, 16, 64));
+    cmx = fmaxf(cmx, __shfl_xor(cmx, 32, 64));
+  }
   const int64_t qbase = split * p.qp + qt * BQ + wave * 16;
   if (g == 0) {
     rw_part[qbase + c] = rws;
     gh_part[qbase + c] = dhs;
     if constexpr (KS) ks_part[qbase + c] = kss;
+    cert[qbase + c] = make_float2(csq, cmx);
   }
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
@@ -732,17 +767,24 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
                                            const double* __restrict__ ks_part,
                                            const float* __restrict__ Ys, int64_t splits,
                                            int64_t qp, int64_t q, int64_t d, int64_t dp,
-                                           double inv_n, const double* __restrict__ ynorm,
+                                           int64_t n, double inv_n,
+                                           const double* __restrict__ ynorm,
                                            float L, int kern, double c_y, double c_h,
                                            const double* __restrict__ grad_out,
                                            float* __restrict__ grad_Y, double* __restrict__ ghq,
-                                           double* __restrict__ mu) {
+                                           double* __restrict__ mu, CertArgs ca) {
   const int64_t qi = blockIdx.x;
   __shared__ double rw_s, f_s;
   if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int64_t s = 0; s < splits; ++s) { a += rw_part[s * qp + qi]; b += gh_part[s * qp + qi]; }
-    if (mu && ks_part)
+    double a = 0.0, b = 0.0, c = 0.0, A = 0.0, y2 = 0.0;
+    for (int64_t s = 0; s < splits; ++s) {
+      a += rw_part[s * qp + qi];
+      b += gh_part[s * qp + qi];
+      const float2 cc = ca.part[s * qp + qi];
+      A += (double)cc.x;
+      y2 = kern == KERNEL_GAUSSIAN ? y2 + (double)cc.y : fmax(y2, (double)cc.y);
+    }
+    if (ks_part)
       for (int64_t s = 0; s < splits; ++s) c += ks_part[s * qp + qi];
     double f = 1.0;
     if (kern == KERNEL_GAUSSIAN) {
@@ -753,7 +795,10 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
     rw_s = a;
     f_s = f;
     if (ghq) ghq[qi] = g * inv_n * c_h * f * b;
-    if (mu) mu[qi] = f * (ks_part ? c : a) * inv_n;
+    const double T = ks_part ? c : a;   // sum of K (Gaussian: the weights themselves)
+    if (mu) mu[qi] = f * T * inv_n;
+    cert_check(qi, T, A * 1.01, kern == KERNEL_GAUSSIAN ? y2 * 1.01 : y2, f, ynorm[qi], n, L,
+               kern, ca);
   }
   __syncthreads();
   if (!grad_Y) return;
@@ -765,35 +810,38 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
   }
 }
 
-template <int KERN, bool VAL>
+// The weight loops no longer depend on VAL (the exponential kernel always sums
+// K for the certificate), so one instantiation serves the adjoint and the fused
+// value + gradient pass.
+template <int KERN>
 static hipError_t launch_kde_bwd_split(const TileProblem& p, const SplitRows& sp, int64_t dp,
                                        float L, double* gy, double* rw, double* gh, double* ks,
-                                       hipStream_t s) {
+                                       float2* cert, hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), b(BWG);
   const char* Xs = reinterpret_cast<const char*>(sp.X);
   const char* Ys = reinterpret_cast<const char*>(sp.Y);
   if (sp.dps == 64 && dp == 32)
-    kde_backward_split_kernel<KERN, 64, 32, VAL><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks);
+    kde_backward_split_kernel<KERN, 64, 32, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert);
   else if (sp.dps == 64 && dp == 64)
-    kde_backward_split_kernel<KERN, 64, 64, VAL><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks);
+    kde_backward_split_kernel<KERN, 64, 64, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert);
   else if (sp.dps == 128 && dp == 96)
-    kde_backward_split_kernel<KERN, 128, 96, VAL><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks);
+    kde_backward_split_kernel<KERN, 128, 96, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert);
   else if (sp.dps == 128 && dp == 128)
-    kde_backward_split_kernel<KERN, 128, 128, VAL><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks);
+    kde_backward_split_kernel<KERN, 128, 128, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-template <int KERN, bool VAL>
+template <int KERN>
 static hipError_t launch_kde_bwd_k(const TileProblem& p, int64_t dp, float L, double* gy, double* rw,
-                                   double* gh, double* ks, hipStream_t s) {
+                                   double* gh, double* ks, float2* cert, hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), b(BWG);
   switch (dp) {
-    case 32: kde_backward_kernel<KERN, 32, VAL, 128><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
-    case 64: kde_backward_kernel<KERN, 64, VAL, BWD_TR_64><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
-    case 96: kde_backward_kernel<KERN, 96, VAL, 128><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
-    case 128: kde_backward_kernel<KERN, 128, VAL, 128><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks); break;
+    case 32: kde_backward_kernel<KERN, 32, false, 128><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks, cert); break;
+    case 64: kde_backward_kernel<KERN, 64, false, BWD_TR_64><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks, cert); break;
+    case 96: kde_backward_kernel<KERN, 96, false, 128><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks, cert); break;
+    case 128: kde_backward_kernel<KERN, 128, false, 128><<<g, b, 0, s>>>(p, L, gy, rw, gh, ks, cert); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -819,11 +867,11 @@ hipError_t launch_mean_shift_update(const float* Y, const float* g, const double
   return hipGetLastError();
 }
 
-hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, double h, int kern,
-                               const double* grad_out, double* gy_part, double* gh_part,
-                               float* grad_Y, double* grad_h, hipStream_t s, TimingHook th,
-                               double* mu, double* gh_per_query, SplitRows split) {
-  (void)Y;
+hipError_t launch_kde_backward(const TileProblem& p, const float* X, const float* Y, int64_t d,
+                               double h, int kern, const double* grad_out, double* gy_part,
+                               double* gh_part, float* grad_Y, double* grad_h, hipStream_t s,
+                               TimingHook th, double* mu, double* gh_per_query, SplitRows split,
+                               const CertArgs& ca) {
   const int64_t dp = p.ld_bytes / 4;
   const double log2e = 1.4426950408889634;
   const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
@@ -831,35 +879,41 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, 
   double* rw_part = gh_part + p.splits * p.qp;
   double* ks_part = rw_part + p.splits * p.qp;
   double* ghq = gh_per_query ? gh_per_query : ks_part + p.splits * p.qp;
-  const bool val = mu != nullptr;
   hipError_t e;
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
-  if (split.X) {   // distance product from three-part bfloat16 rows
-    if (kern == KERNEL_GAUSSIAN)
-      e = launch_kde_bwd_split<KERNEL_GAUSSIAN, false>(p, split, dp, L, gy_part, rw_part, gh_part,
-                                                       ks_part, s);
-    else
-      e = val ? launch_kde_bwd_split<KERNEL_EXPONENTIAL, true>(p, split, dp, L, gy_part, rw_part,
-                                                               gh_part, ks_part, s)
-              : launch_kde_bwd_split<KERNEL_EXPONENTIAL, false>(p, split, dp, L, gy_part, rw_part,
-                                                                gh_part, ks_part, s);
-  } else if (kern == KERNEL_GAUSSIAN) {   // the KDE is the sum of the weights themselves
-    e = launch_kde_bwd_k<KERNEL_GAUSSIAN, false>(p, dp, L, gy_part, rw_part, gh_part, ks_part, s);
-  } else {
-    e = val ? launch_kde_bwd_k<KERNEL_EXPONENTIAL, true>(p, dp, L, gy_part, rw_part, gh_part, ks_part, s)
-            : launch_kde_bwd_k<KERNEL_EXPONENTIAL, false>(p, dp, L, gy_part, rw_part, gh_part, ks_part, s);
-  }
+  if (split.X)   // distance product from three-part bfloat16 rows
+    e = kern == KERNEL_GAUSSIAN
+            ? launch_kde_bwd_split<KERNEL_GAUSSIAN>(p, split, dp, L, gy_part, rw_part, gh_part,
+                                                    ks_part, ca.part, s)
+            : launch_kde_bwd_split<KERNEL_EXPONENTIAL>(p, split, dp, L, gy_part, rw_part, gh_part,
+                                                       ks_part, ca.part, s);
+  else
+    e = kern == KERNEL_GAUSSIAN
+            ? launch_kde_bwd_k<KERNEL_GAUSSIAN>(p, dp, L, gy_part, rw_part, gh_part, ks_part,
+                                                ca.part, s)
+            : launch_kde_bwd_k<KERNEL_EXPONENTIAL>(p, dp, L, gy_part, rw_part, gh_part, ks_part,
+                                                   ca.part, s);
   if (e != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
   // Gaussian: weights K, dh terms K * (-L d^2); exponential: weights K / r, dh terms K r
   const double c_y = kern == KERNEL_GAUSSIAN ? 1.0 / (h * h) : 1.0 / h;
   const double c_h = kern == KERNEL_GAUSSIAN ? -1.0 / (h * h * h * (double)L) : 1.0 / (h * h);
   const bool need_ghq = grad_h || gh_per_query;
+  if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(ca.fb_count), 1, 0u, s)) != hipSuccess)
+    return e;
   kde_backward_reduce_kernel<<<dim3((unsigned)p.q), dim3(128), 0, s>>>(
-      gy_part, rw_part, gh_part, (val && kern != KERNEL_GAUSSIAN) ? ks_part : nullptr,
-      reinterpret_cast<const float*>(p.Ys), p.splits, p.qp, p.q, d, dp, 1.0 / (double)p.n,
-      p.ynorm, L, kern, c_y, c_h, grad_out, grad_Y, need_ghq ? ghq : nullptr, mu);
+      gy_part, rw_part, gh_part, kern != KERNEL_GAUSSIAN ? ks_part : nullptr,
+      reinterpret_cast<const float*>(p.Ys), p.splits, p.qp, p.q, d, dp, p.n, 1.0 / (double)p.n,
+      p.ynorm, L, kern, c_y, c_h, grad_out, grad_Y, need_ghq ? ghq : nullptr, mu, ca);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // exact re-evaluation of the listed queries; its scratch reuses the sweep's
+  // partials, which the reduction has consumed: value and h sums in the gh and
+  // rw parts, the weighted row sums in gy_part ([splits][qp][dp] >= [fs][q][dp])
+  const int64_t fs = p.splits < 64 ? p.splits : 64;
+  e = launch_kde_direct_grad(X, Y, p.n, p.q, d, h, kern, ca.fb_ids, ca.fb_count, fs, gh_part,
+                             rw_part, gy_part, dp, grad_out, grad_Y, need_ghq ? ghq : nullptr, mu,
+                             s);
+  if (e != hipSuccess) return e;
   if (!grad_h) return hipSuccess;
   sum_scalar_kernel<<<dim3(1), dim3(WG), 0, s>>>(ghq, p.q, grad_h);
   return hipGetLastError();

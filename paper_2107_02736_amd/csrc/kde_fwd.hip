@@ -17,6 +17,10 @@
 // kde_reduce_kernel multiplies the query's FP64 total by 2^remainder.  The
 // remaining roundings (data term, the add, the FMA) differ from pair to pair.
 // Exponential: d^2 = ||y||^2 + ||x||^2 - 2 <x,y> in FP32, clamped at 0.
+//
+// The float32-operand sweeps also keep, per query and split, the sum of the
+// squared kernel values (and for the exponential kernel their maximum) for the
+// per-query error certificate of cert.hip.
 #include "common.h"
 #include "kernels.h"
 
@@ -40,7 +44,10 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
                 int nchunks, const double* __restrict__ ynorm, const double* __restrict__ xnorm,
                 int64_t n, int64_t qtiles, int64_t splits, int64_t ntiles, float Lf,
                 double* __restrict__ partial, int64_t qp, TileMap map,
-                const int32_t* __restrict__ hoff, const uint16_t* __restrict__ hits) {
+                const int32_t* __restrict__ hoff, const uint16_t* __restrict__ hits,
+                float2* __restrict__ cert) {
+  // float32 operands: certificate sums (see the file comment)
+  constexpr bool CERT = elem_of<T>::bytes == 4 && !HYB;
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
   __shared__ uint16_t hl[HYB ? HYB_LDS : 1];
   int64_t qt, split;
@@ -74,10 +81,17 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       yt[i][r] = KERN == KERNEL_GAUSSIAN ? (float)(-(double)Lf * yn) : (float)yn;
     }
   double sum[4][4];
+  // certificate (CERT only): sum of K^2; Gaussian: sum of K times its exponent,
+  // exponential: largest K
+  float csq[4][4], cmx[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sum[i][r] = 0.0;
+    for (int r = 0; r < 4; ++r) {
+      sum[i][r] = 0.0;
+      csq[i][r] = 0.f;
+      cmx[i][r] = 0.f;
+    }
 
   const char* yq = Ys + qt * BQ * ld_bytes;
   constexpr int NK = 2;   // k-groups of the register-resident engine
@@ -136,7 +150,7 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
       const double xn = xns[nb][wn * 64 + j * 16 + (lane & 15)];
       if (KERN == KERNEL_GAUSSIAN)
-        xt[j] = col < n ? (float)(-(double)Lf * xn) : -__builtin_inff();
+        xt[j] = col < n ? (float)(-(double)Lf * xn) : -1e30f;
       else
         xt[j] = col < n ? (float)xn : __builtin_inff();
     }
@@ -182,14 +196,20 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             float kv;
+            float a = 0.f;
             if (KERN == KERNEL_GAUSSIAN) {   // exp(-d^2 / (2 h^2))
-              const float a = fminf(__builtin_fmaf(L2, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
+              a = fminf(__builtin_fmaf(L2, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
               kv = __builtin_amdgcn_exp2f(a);
             } else {                          // exp(-d / h)
               const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
               kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
             }
             part += kv;
+            if constexpr (CERT) {
+              csq[i][r] = __builtin_fmaf(kv, kv, csq[i][r]);
+              if (KERN == KERNEL_GAUSSIAN) cmx[i][r] = __builtin_fmaf(-kv, a, cmx[i][r]);
+              else cmx[i][r] = fmaxf(cmx[i][r], kv);
+            }
           }
           sum[i][r] += (double)part;
         }
@@ -220,6 +240,37 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
   __syncthreads();
   if (threadIdx.x < BQ)
     partial[split * qp + qt * BQ + threadIdx.x] = red[threadIdx.x] + red[BQ + threadIdx.x];
+  if constexpr (CERT) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float a = csq[i][r], m = cmx[i][r];
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          a += __shfl_xor(a, o, 64);
+          const float mo = __shfl_xor(m, o, 64);
+          m = KERN == KERNEL_GAUSSIAN ? m + mo : fmaxf(m, mo);
+        }
+        csq[i][r] = a;
+        cmx[i][r] = m;
+      }
+    __syncthreads();   // red is reused
+    float2* cr = reinterpret_cast<float2*>(lds);   // [2][BQ]
+    if ((lane & 15) == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          cr[wn * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r] = make_float2(csq[i][r], cmx[i][r]);
+    }
+    __syncthreads();
+    if (threadIdx.x < BQ) {
+      const float2 a = cr[threadIdx.x], b = cr[BQ + threadIdx.x];
+      cert[split * qp + qt * BQ + threadIdx.x] =
+          make_float2(a.x + b.x, KERN == KERNEL_GAUSSIAN ? a.y + b.y : fmaxf(a.y, b.y));
+    }
+  }
 }
 
 // FP32 operands, padded width DP <= 128: the queries stay in registers.  512
@@ -240,7 +291,7 @@ constexpr int YWG = 512;
 
 template <int KERN, int DP, int NBI>
 __global__ void __launch_bounds__(YWG, NBI == 8 ? 1 : 2)
-kde_yres_kernel(TileProblem p, float Lf, double* __restrict__ partial) {
+kde_yres_kernel(TileProblem p, float Lf, double* __restrict__ partial, float2* __restrict__ cert) {
   constexpr int TR = 16 * NBI;                // data rows per staged tile
   constexpr int KGS = DP / 16;                // 64-byte k-groups per row
   constexpr int PITCH = DP * 4 + 16;          // LDS row pitch (bytes)
@@ -276,8 +327,8 @@ kde_yres_kernel(TileProblem p, float Lf, double* __restrict__ partial) {
     }
     if (threadIdx.x < TR) {   // padding rows: a term that zeroes the kernel
       const int64_t row = u * TR + threadIdx.x;
-      if (KERN == KERNEL_GAUSSIAN)
-        xvr = row < p.n ? (float)(-(double)Lf * p.xnorm[row]) : -__builtin_inff();
+      if (KERN == KERNEL_GAUSSIAN)   // finite: K = 0 and K times the exponent = 0
+        xvr = row < p.n ? (float)(-(double)Lf * p.xnorm[row]) : -1e30f;
       else
         xvr = row < p.n ? (float)p.xnorm[row] : __builtin_inff();
     }
@@ -292,6 +343,8 @@ kde_yres_kernel(TileProblem p, float Lf, double* __restrict__ partial) {
   };
 
   double sum = 0.0;
+  // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential: largest K
+  float csq = 0.f, cmx = 0.f;
   if (u0 < u1) {
     gload(u0);
     lstore(0);
@@ -331,11 +384,14 @@ kde_yres_kernel(TileProblem p, float Lf, double* __restrict__ partial) {
           if (KERN == KERNEL_GAUSSIAN) {   // exp(-d^2 / (2 h^2))
             const float a = fminf(__builtin_fmaf(L2, acc[bi][r], yt + xt[r]), 0.f);
             kv = __builtin_amdgcn_exp2f(a);
+            cmx = __builtin_fmaf(-kv, a, cmx);
           } else {                          // exp(-d / h)
             const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[bi][r], yt + xt[r]), 0.f);
             kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
+            cmx = fmaxf(cmx, kv);
           }
           part += kv;
+          csq = __builtin_fmaf(kv, kv, csq);
         }
       }
       sum += (double)part;
@@ -345,7 +401,19 @@ kde_yres_kernel(TileProblem p, float Lf, double* __restrict__ partial) {
   // the four lane groups of a query column, in a fixed order
   sum += __shfl_xor(sum, 16, 64);
   sum += __shfl_xor(sum, 32, 64);
-  if (g == 0) partial[split * p.qp + qt * BQ + wave * 16 + c] = sum;
+  csq += __shfl_xor(csq, 16, 64);
+  csq += __shfl_xor(csq, 32, 64);
+  if (KERN == KERNEL_GAUSSIAN) {
+    cmx += __shfl_xor(cmx, 16, 64);
+    cmx += __shfl_xor(cmx, 32, 64);
+  } else {
+    cmx = fmaxf(cmx, __shfl_xor(cmx, 16, 64));
+    cmx = fmaxf(cmx, __shfl_xor(cmx, 32, 64));
+  }
+  if (g == 0) {
+    partial[split * p.qp + qt * BQ + wave * 16 + c] = sum;
+    cert[split * p.qp + qt * BQ + wave * 16 + c] = make_float2(csq, cmx);
+  }
 }
 
 // The same sweep with float32-accurate dot products from bfloat16 MFMAs: every
@@ -357,7 +425,7 @@ kde_yres_kernel(TileProblem p, float Lf, double* __restrict__ partial) {
 template <int KERN, int DPS, int NBI>
 __global__ void __launch_bounds__(YWG, NBI <= 2 ? 2 : 1)
 kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __restrict__ Ysp,
-                 float Lf, double* __restrict__ partial) {
+                 float Lf, double* __restrict__ partial, float2* __restrict__ cert) {
   constexpr int TR = 16 * NBI;
   constexpr int KC = DPS / 32;                // 32-element k-chunks per plane
   constexpr int RB = 3 * DPS * 2;             // bytes per split row
@@ -397,8 +465,8 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
     }
     if (threadIdx.x < TR) {
       const int64_t row = u * TR + threadIdx.x;
-      if (KERN == KERNEL_GAUSSIAN)
-        xvr = row < p.n ? (float)(-(double)Lf * p.xnorm[row]) : -__builtin_inff();
+      if (KERN == KERNEL_GAUSSIAN)   // finite: K = 0 and K times the exponent = 0
+        xvr = row < p.n ? (float)(-(double)Lf * p.xnorm[row]) : -1e30f;
       else
         xvr = row < p.n ? (float)p.xnorm[row] : __builtin_inff();
     }
@@ -413,6 +481,8 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
   };
 
   double sum = 0.0;
+  // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential: largest K
+  float csq = 0.f, cmx = 0.f;
   if (u0 < u1) {
     gload(u0);
     lstore(0);
@@ -469,11 +539,14 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
           if (KERN == KERNEL_GAUSSIAN) {
             const float a = fminf(__builtin_fmaf(L2, acc[bi][r], yt + xt[r]), 0.f);
             kv = __builtin_amdgcn_exp2f(a);
+            cmx = __builtin_fmaf(-kv, a, cmx);
           } else {
             const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[bi][r], yt + xt[r]), 0.f);
             kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
+            cmx = fmaxf(cmx, kv);
           }
           part += kv;
+          csq = __builtin_fmaf(kv, kv, csq);
         }
       }
       sum += (double)part;
@@ -482,7 +555,19 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
   }
   sum += __shfl_xor(sum, 16, 64);
   sum += __shfl_xor(sum, 32, 64);
-  if (g == 0) partial[split * p.qp + qt * BQ + wave * 16 + c] = sum;
+  csq += __shfl_xor(csq, 16, 64);
+  csq += __shfl_xor(csq, 32, 64);
+  if (KERN == KERNEL_GAUSSIAN) {
+    cmx += __shfl_xor(cmx, 16, 64);
+    cmx += __shfl_xor(cmx, 32, 64);
+  } else {
+    cmx = fmaxf(cmx, __shfl_xor(cmx, 16, 64));
+    cmx = fmaxf(cmx, __shfl_xor(cmx, 32, 64));
+  }
+  if (g == 0) {
+    partial[split * p.qp + qt * BQ + wave * 16 + c] = sum;
+    cert[split * p.qp + qt * BQ + wave * 16 + c] = make_float2(csq, cmx);
+  }
 }
 
 #ifndef SPLIT_NBI
@@ -494,37 +579,45 @@ __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t sp
                                   float Lf, int kern, const double* __restrict__ add,
                                   double* __restrict__ out);
 
+static hipError_t finish_fp32(const TileProblem& p, int kern, double h, float L, double* partial,
+                              double* out, hipStream_t s, const CertArgs& ca, const float* X,
+                              const float* Y, int64_t d, double* fb_part);
+
 template <int KERN, int DPS>
 static void launch_split(const TileProblem& p, const void* Xsp, const void* Ysp, float L,
-                         double* partial, hipStream_t s) {
+                         double* partial, float2* cert, hipStream_t s) {
   TileProblem q = p;
   q.map = make_tile_map(p.qtiles, p.splits, 1);
   constexpr int NBI = DPS == 64 ? 4 : SPLIT_NBI;   // whole 16-byte pieces per thread
   kde_split_kernel<KERN, DPS, NBI><<<dim3((unsigned)q.map.grid), dim3(YWG), 0, s>>>(
-      q, reinterpret_cast<const char*>(Xsp), reinterpret_cast<const char*>(Ysp), L, partial);
+      q, reinterpret_cast<const char*>(Xsp), reinterpret_cast<const char*>(Ysp), L, partial,
+      cert);
 }
 
 hipError_t launch_kde_exact_split(const TileProblem& p, const void* Xsp, const void* Ysp,
                                   int64_t dps, int kern, double h, double* partial, double* out,
-                                  hipStream_t s, TimingHook th) {
+                                  hipStream_t s, TimingHook th, const CertArgs& ca,
+                                  const float* X, const float* Y, int64_t d, double* fb_part) {
   const double log2e = 1.4426950408889634;
   const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
   hipError_t e;
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
   if (dps == 64) {
-    if (kern == KERNEL_GAUSSIAN) launch_split<KERNEL_GAUSSIAN, 64>(p, Xsp, Ysp, L, partial, s);
-    else launch_split<KERNEL_EXPONENTIAL, 64>(p, Xsp, Ysp, L, partial, s);
+    if (kern == KERNEL_GAUSSIAN)
+      launch_split<KERNEL_GAUSSIAN, 64>(p, Xsp, Ysp, L, partial, ca.part, s);
+    else
+      launch_split<KERNEL_EXPONENTIAL, 64>(p, Xsp, Ysp, L, partial, ca.part, s);
   } else if (dps == 128) {
-    if (kern == KERNEL_GAUSSIAN) launch_split<KERNEL_GAUSSIAN, 128>(p, Xsp, Ysp, L, partial, s);
-    else launch_split<KERNEL_EXPONENTIAL, 128>(p, Xsp, Ysp, L, partial, s);
+    if (kern == KERNEL_GAUSSIAN)
+      launch_split<KERNEL_GAUSSIAN, 128>(p, Xsp, Ysp, L, partial, ca.part, s);
+    else
+      launch_split<KERNEL_EXPONENTIAL, 128>(p, Xsp, Ysp, L, partial, ca.part, s);
   } else {
     return hipErrorInvalidValue;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
-  kde_reduce_kernel<<<dim3((unsigned)ceil_div(p.q, 256)), dim3(256), 0, s>>>(
-      partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, p.ynorm, L, kern, nullptr, out);
-  return hipGetLastError();
+  return finish_fp32(p, kern, h, L, partial, out, s, ca, X, Y, d, fb_part);
 }
 
 // Sum of the per-split partials in split order, times the Gaussian query
@@ -548,20 +641,22 @@ __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t sp
 
 template <typename T, int KERN, int ENG, bool HYB = false>
 static void launch_kde_k(const TileProblem& p, float L, double* partial, hipStream_t s,
-                         const int32_t* hoff = nullptr, const uint16_t* hits = nullptr) {
+                         const int32_t* hoff = nullptr, const uint16_t* hits = nullptr,
+                         float2* cert = nullptr) {
   kde_tile_kernel<T, KERN, ENG, HYB><<<dim3((unsigned)p.map.grid), dim3(WG), 0, s>>>(
       p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
-      partial, p.qp, p.map, hoff, hits);
+      partial, p.qp, p.map, hoff, hits, cert);
 }
 
 template <typename T, int KERN>
-static void launch_kde_n(const TileProblem& p, float L, double* partial, hipStream_t s) {
+static void launch_kde_n(const TileProblem& p, float L, double* partial, float2* cert,
+                         hipStream_t s) {
   if constexpr (elem_of<T>::bytes == 2) {
     const int eng = tile_engine<T>(p.ld_bytes);
     if (eng == 2) return launch_kde_k<T, KERN, 2>(p, L, partial, s);
     if (eng == 1) return launch_kde_k<T, KERN, 1>(p, L, partial, s);
   }
-  launch_kde_k<T, KERN, 0>(p, L, partial, s);
+  launch_kde_k<T, KERN, 0>(p, L, partial, s, nullptr, nullptr, cert);
 }
 
 template <typename T, int KERN>
@@ -583,52 +678,70 @@ static void launch_hyb_t(const TileProblem& p, int kern, float L, double* partia
 }
 
 template <int KERN, int DP>
-static void launch_yres(const TileProblem& p, float L, double* partial, hipStream_t s) {
+static void launch_yres(const TileProblem& p, float L, double* partial, float2* cert,
+                        hipStream_t s) {
   // one workgroup sweeps a query tile over a data split; split-major placement
   TileProblem q = p;
   q.map = make_tile_map(p.qtiles, p.splits, 1);
-  kde_yres_kernel<KERN, DP, YRES_NBI><<<dim3((unsigned)q.map.grid), dim3(YWG), 0, s>>>(q, L, partial);
+  kde_yres_kernel<KERN, DP, YRES_NBI><<<dim3((unsigned)q.map.grid), dim3(YWG), 0, s>>>(
+      q, L, partial, cert);
 }
 
 template <int KERN>
-static bool launch_yres_d(const TileProblem& p, float L, double* partial, hipStream_t s) {
+static bool launch_yres_d(const TileProblem& p, float L, double* partial, float2* cert,
+                          hipStream_t s) {
   switch (p.ld_bytes / 4) {
-    case 32: launch_yres<KERN, 32>(p, L, partial, s); return true;
-    case 64: launch_yres<KERN, 64>(p, L, partial, s); return true;
-    case 96: launch_yres<KERN, 96>(p, L, partial, s); return true;
-    case 128: launch_yres<KERN, 128>(p, L, partial, s); return true;
+    case 32: launch_yres<KERN, 32>(p, L, partial, cert, s); return true;
+    case 64: launch_yres<KERN, 64>(p, L, partial, cert, s); return true;
+    case 96: launch_yres<KERN, 96>(p, L, partial, cert, s); return true;
+    case 128: launch_yres<KERN, 128>(p, L, partial, cert, s); return true;
     default: return false;
   }
 }
 
 template <typename T>
 static hipError_t launch_kde_t(const TileProblem& p, int kern, float L, double* partial,
-                               hipStream_t s) {
+                               float2* cert, hipStream_t s) {
   if constexpr (elem_of<T>::bytes == 4) {   // FP32 rows of at most 512 bytes
-    const bool done = kern == KERNEL_GAUSSIAN ? launch_yres_d<KERNEL_GAUSSIAN>(p, L, partial, s)
-                                              : launch_yres_d<KERNEL_EXPONENTIAL>(p, L, partial, s);
+    const bool done = kern == KERNEL_GAUSSIAN
+                          ? launch_yres_d<KERNEL_GAUSSIAN>(p, L, partial, cert, s)
+                          : launch_yres_d<KERNEL_EXPONENTIAL>(p, L, partial, cert, s);
     if (done) return hipGetLastError();
   }
   if (kern == KERNEL_GAUSSIAN)
-    launch_kde_n<T, KERNEL_GAUSSIAN>(p, L, partial, s);
+    launch_kde_n<T, KERNEL_GAUSSIAN>(p, L, partial, cert, s);
   else
-    launch_kde_n<T, KERNEL_EXPONENTIAL>(p, L, partial, s);
+    launch_kde_n<T, KERNEL_EXPONENTIAL>(p, L, partial, cert, s);
   return hipGetLastError();
 }
 
+// Reduction of a float32-operand sweep with the certificate, then the exact
+// re-evaluation of the queries it lists.
+static hipError_t finish_fp32(const TileProblem& p, int kern, double h, float L, double* partial,
+                              double* out, hipStream_t s, const CertArgs& ca, const float* X,
+                              const float* Y, int64_t d, double* fb_part) {
+  hipError_t e = launch_kde_reduce_cert(partial, p.splits, p.qp, p.q, p.n, p.ynorm, L, kern, ca,
+                                        out, s);
+  if (e != hipSuccess) return e;
+  return launch_kde_direct(X, Y, p.n, p.q, d, h, kern, ca.fb_ids, ca.fb_count,
+                           direct_splits(p.n), fb_part, out, s);
+}
+
 hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, double* partial,
-                            double* out, hipStream_t s, TimingHook th) {
+                            double* out, hipStream_t s, TimingHook th, const CertArgs& ca,
+                            const float* X, const float* Y, int64_t d, double* fb_part) {
   const double log2e = 1.4426950408889634;
   const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
   hipError_t e;
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
   switch (prec) {
-    case PREC_FP32: e = launch_kde_t<float>(p, kern, L, partial, s); break;
-    case PREC_BF16: e = launch_kde_t<__bf16>(p, kern, L, partial, s); break;
-    default: e = launch_kde_t<_Float16>(p, kern, L, partial, s); break;
+    case PREC_FP32: e = launch_kde_t<float>(p, kern, L, partial, ca.part, s); break;
+    case PREC_BF16: e = launch_kde_t<__bf16>(p, kern, L, partial, nullptr, s); break;
+    default: e = launch_kde_t<_Float16>(p, kern, L, partial, nullptr, s); break;
   }
   if (e != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
+  if (prec == PREC_FP32) return finish_fp32(p, kern, h, L, partial, out, s, ca, X, Y, d, fb_part);
   kde_reduce_kernel<<<dim3((unsigned)ceil_div(p.q, 256)), dim3(256), 0, s>>>(
       partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, p.ynorm, L, kern, nullptr, out);
   return hipGetLastError();

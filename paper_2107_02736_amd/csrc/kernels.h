@@ -25,6 +25,9 @@ struct TileProblem {
 };
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
+// Largest of count non-negative floats, as float bits, into *out (atomic max:
+// *out must hold a lower value first).
+hipError_t launch_max_u32(const float* v, int64_t count, uint32_t* out, hipStream_t s);
 hipError_t launch_center(const float* X, int64_t n, int64_t d, double* part, int64_t R, float* c,
                          hipStream_t s);
 hipError_t launch_prep_rows_prec(int prec, const float* src, int64_t rows, int64_t rows_padded,
@@ -41,13 +44,56 @@ struct TimingHook {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 
+// Per-query accuracy certificate of the float32-operand sweeps (cert.hip): the
+// sweeps write part; the reduction lists the queries whose error bound exceeds
+// tau (and whose value is not certainly below floor) for an exact FP64
+// re-evaluation.  fb_count must be zero before the reduction.
+struct CertArgs {
+  float2* part;            // [splits][qp] per split: sum of K^2, and (Gaussian) the sum of
+                           // K times its exponent -log2 K or (exponential) the largest K
+  const uint32_t* xnmax;   // float bits of the largest scaled data norm ||x~||^2 (1 - a)
+  double a_scale;          // that scaling a
+  int cd;                  // roundings of one dot product (its accumulation length)
+  double tau;              // relative error bound of a certified query
+  double floor;            // values certainly below it are not re-evaluated
+  int32_t* fb_ids;         // [q] queries to re-evaluate
+  int32_t* fb_count;       // [1]
+};
+
+// Fixed-order sum of the float32 sweep's partials into out (Gaussian query
+// factor and 1/n applied), the certificate of every query and the list of
+// those to re-evaluate (clears *ca.fb_count first).
+hipError_t launch_kde_reduce_cert(const double* partial, int64_t splits, int64_t qp, int64_t q,
+                                  int64_t n, const double* ynorm, float Lf, int kern,
+                                  const CertArgs& ca, double* out, hipStream_t s);
+// Row splits of the exact re-evaluation for n data rows.
+int64_t direct_splits(int64_t n);
+// Exact FP64 value of the listed queries (ids[0 .. *count)): part [splits][q]
+// scratch; overwrites out[ids[i]].
+hipError_t launch_kde_direct(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
+                             double h, int kern, const int32_t* ids, const int32_t* count,
+                             int64_t splits, double* part, double* out, hipStream_t s);
+// Exact FP64 value, gradient and per-query d/dh of the listed queries (d <= 128):
+// pval, pgh [splits][q] and pG [splits][q][ldg] scratch; overwrites the
+// entries of grad_Y, ghq and mu (each may be NULL) of the listed queries.
+hipError_t launch_kde_direct_grad(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
+                                  double h, int kern, const int32_t* ids, const int32_t* count,
+                                  int64_t splits, double* pval, double* pgh, double* pG,
+                                  int64_t ldg, const double* grad_out, float* grad_Y, double* ghq,
+                                  double* mu, hipStream_t s);
+
+// Float32 operands: the sweep, the reduction with the certificate (ca), and
+// the exact re-evaluation of the listed queries from X and Y (fb_part:
+// [direct_splits(n)][q] scratch).  16-bit operands: ca is not used.
 hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, double* partial,
-                            double* out, hipStream_t s, TimingHook th = {});
+                            double* out, hipStream_t s, TimingHook th, const CertArgs& ca,
+                            const float* X, const float* Y, int64_t d, double* fb_part);
 // Exact KDE from the three-part bfloat16 rows (Xsp, Ysp: [rows][3][dps]); p holds
 // the float32 problem (norms, sizes, placement).
 hipError_t launch_kde_exact_split(const TileProblem& p, const void* Xsp, const void* Ysp,
                                   int64_t dps, int kern, double h, double* partial, double* out,
-                                  hipStream_t s, TimingHook th = {});
+                                  hipStream_t s, TimingHook th, const CertArgs& ca,
+                                  const float* X, const float* Y, int64_t d, double* fb_part);
 
 // ---- exact k nearest neighbours -------------------------------------------
 struct KnnBuffers {
@@ -62,7 +108,9 @@ struct KnnBuffers {
   uint64_t* cand2;       // [q][cap2] second-pass candidates (index only)
   int32_t* cand2_cnt;    // [q]
   int64_t cap2;
-  int32_t* status;       // [q] 0 certified, 1 second pass, 2 exhaustive scan
+  int32_t* status;       // [q] 0 certified by the first pass, 1 second pass pending,
+                         // 2 (3: too few inspected rows) exhaustive scan pending,
+                         // 4 done by the second pass, 5 done by the exhaustive scan
   const float* yerr;     // [qp]
   const uint32_t* xerr_max;
 };
@@ -181,11 +229,15 @@ struct SplitRows {
   int64_t dps = 0;
 };
 
-hipError_t launch_kde_backward(const TileProblem& p, const float* Y, int64_t d, double h, int kern,
-                               const double* grad_out, double* gy_part, double* gh_part,
-                               float* grad_Y, double* grad_h, hipStream_t s, TimingHook th = {},
-                               double* mu = nullptr, double* gh_per_query = nullptr,
-                               SplitRows split = {});
+// The exact adjoint (and with mu the fused value + gradient): the sweep, the
+// reduction with the certificate (ca, cd as for kde_exact), and the exact
+// re-evaluation of the listed queries from the caller's X and Y (their
+// scratch reuses gy_part and gh_part, so splits must be at least 1).
+hipError_t launch_kde_backward(const TileProblem& p, const float* X, const float* Y, int64_t d,
+                               double h, int kern, const double* grad_out, double* gy_part,
+                               double* gh_part, float* grad_Y, double* grad_h, hipStream_t s,
+                               TimingHook th, double* mu, double* gh_per_query, SplitRows split,
+                               const CertArgs& ca);
 
 hipError_t launch_mean_shift_update(const float* Y, const float* g, const double* mu, int64_t q,
                                     int64_t d, double h, float* Y_out, hipStream_t s);

@@ -825,7 +825,7 @@ knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   block_sort_pairs(dkey, didx, N);
   const int k = (int)a.k;
   fix_boundary(dkey, didx, C, k, a.X, a.d, ys);
-  if (threadIdx.x == 0) b.status[qi] = 0;
+  if (threadIdx.x == 0) b.status[qi] = 4;   // done by the second pass
   emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
                   nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
 }
@@ -892,7 +892,7 @@ knn_exhaustive_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) 
     top.settle(dkey, didx, &fill_s, r1 == a.n);
   }
   fix_boundary(dkey, didx, fill_s, k, a.X, a.d, ys);
-  if (threadIdx.x == 0) b.status[qi] = 0;
+  if (threadIdx.x == 0) b.status[qi] = 5;   // done by the exhaustive scan
   emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
                   nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
 }
@@ -1419,7 +1419,7 @@ ivf_exhaustive_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restri
     top.settle(dkey, didx, &fill_s, r1 == R);
   }
   fix_boundary(dkey, didx, fill_s, k, a.X, a.d, ys);
-  if (threadIdx.x == 0) b.status[qi] = 0;
+  if (threadIdx.x == 0) b.status[qi] = 5;   // done by the exhaustive scan
   emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
                   nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
 }

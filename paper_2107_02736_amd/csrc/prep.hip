@@ -193,6 +193,13 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s
   return hipGetLastError();
 }
 
+hipError_t launch_max_u32(const float* v, int64_t count, uint32_t* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t mb = std::min<int64_t>(1024, ceil_div(count, WG));
+  max_u32_kernel<<<dim3((unsigned)mb), dim3(WG), 0, s>>>(v, count, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_center(const float* X, int64_t n, int64_t d, double* part, int64_t R, float* c,
                          hipStream_t s) {
   const int64_t rows_per = ceil_div(n, R);

@@ -167,3 +167,53 @@ def test_kde_hybrid_given_neighbours_lift_the_knn_limits(lib):
     assert _hyb(lib, q=0, out=None, ws=None, wsb=0) == _lib.OK
     assert lib.kde_hybrid_workspace(1000, 4, 3, 5, 0) == 0
     assert lib.kde_hybrid_workspace(1000, 4, 3, 5, 1) > lib.kde_exact_workspace(1000, 4, 3, 1)
+
+
+def test_options_roundtrip_and_validation(lib):
+    d = _lib.Options()
+    lib.deann_default_options(d)
+    assert (d.rel_tol, d.value_floor, d.knn_slack, d.knn_cap2, d.center) == (1e-5, 1e-16, 16,
+                                                                               4096, 1)
+    got = _lib.Options()
+    assert lib.deann_get_options(got) == _lib.OK
+    assert got.rel_tol == d.rel_tol and got.knn_cap2 == d.knn_cap2
+    try:
+        new = _lib.Options()
+        lib.deann_default_options(new)
+        new.knn_cap2, new.center, new.rel_tol = 8, 0, 1e-3
+        assert lib.deann_set_options(new) == _lib.OK
+        assert lib.deann_get_options(got) == _lib.OK
+        assert (got.knn_cap2, got.center, got.rel_tol) == (8, 0, 1e-3)
+        for field, bad in (("rel_tol", 0.0), ("rel_tol", 2.0), ("value_floor", -1.0),
+                           ("value_floor", float("inf")), ("knn_slack", -1), ("knn_slack", 513),
+                           ("knn_cap2", 0), ("knn_cap2", 4097), ("center", 2), ("reserved", 1)):
+            o = _lib.Options()
+            lib.deann_default_options(o)
+            setattr(o, field, bad)
+            assert lib.deann_set_options(o) == _lib.EINVAL, field
+            assert lib.deann_last_error().decode()
+        # a rejected call leaves the options as they were
+        assert lib.deann_get_options(got) == _lib.OK
+        assert (got.knn_cap2, got.center, got.rel_tol) == (8, 0, 1e-3)
+        assert lib.deann_set_options(None) == _lib.EINVAL
+    finally:
+        assert lib.deann_set_options(d) == _lib.OK
+
+
+def test_slack_enters_the_list_size_check(lib):
+    # k + knn_slack beyond the 512 candidates of a list is refused before any launch
+    d = _lib.Options()
+    lib.deann_default_options(d)
+    try:
+        o = _lib.Options()
+        lib.deann_default_options(o)
+        o.knn_slack = 100
+        assert lib.deann_set_options(o) == _lib.OK
+        assert _dq(lib, n=5000, k=450) == _lib.EUNSUPPORTED
+        assert "knn_slack" in lib.deann_last_error().decode()
+        o.knn_slack = 0
+        assert lib.deann_set_options(o) == _lib.OK
+        assert _dq(lib, n=5000, k=496, wsb=8) == _lib.EWORKSPACE
+    finally:
+        lib.deann_set_options(d)
+

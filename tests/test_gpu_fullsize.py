@@ -62,6 +62,38 @@ def test_fullsize_deann_and_exact(big, kern):
             assert abs(mu[j] - ref) <= 1e-5 * ref
 
 
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_fullsize_exact_with_grad(big, kern):
+    # the benchmark step's exact part (kde_exact_with_grad) at n = 1e6, d = 128
+    # on all 10,000 queries: values of sampled queries within 1e-5 and their
+    # gradients within 1e-4 of the normwise scale; every query's value agrees
+    # with kde_exact (both certified to 5e-6)
+    import paper_2107_02736_amd as dk
+    X, Y, Xd, Yd = big
+    h = bandwidth(WL, KNAME[kern])
+    mu, gy, gh = (t.cpu().numpy() for t in dk.kde_exact_with_grad(Xd, Yd, h, KNAME[kern]))
+    st = dk.last_stats(Xd.device)
+    mu_fwd = dk.kde_exact(Xd, Yd, h, KNAME[kern], "fp32").cpu().numpy()
+    keep = mu_fwd >= 1e-16
+    print(f"{KNAME[kern]}: queries re-evaluated {st['exact_refined']}, "
+          f"kept {keep.sum()} of {keep.size}")
+    assert np.all(np.abs(mu[keep] - mu_fwd[keep]) <= 1e-5 * mu_fwd[keep])
+    for j in synth.query_subset(Y.shape[0], 4, seed=11):
+        j = int(j)
+        mu_ref, gy_ref, gh_ref = oracle.kde_grad(X, Y[j].astype(np.float64), h, kern)
+        if mu_ref < 1e-16:
+            continue
+        assert abs(mu[j] - mu_ref) <= 1e-5 * mu_ref, j
+        d2 = oracle.sq_dists(X, Y[j])
+        K = oracle.kernel_values(d2, h, kern)
+        r = np.sqrt(d2)
+        scale = ((K * r).sum() / (X.shape[0] * h * h) if kern == GAUSSIAN
+                 else K.sum() / (X.shape[0] * h))
+        print(f"query {j}: value {abs(mu[j] - mu_ref) / mu_ref:.2e}, gradient "
+              f"{np.linalg.norm(gy[j] - gy_ref) / scale:.2e} of the normwise scale")
+        assert np.linalg.norm(gy[j] - gy_ref) <= 1e-4 * scale, j
+
+
 def test_fullsize_near_far(big):
     # the near/far exact KDE in the benchmark's configuration (BF16, k = 100):
     # its neighbour lists are DEANN's on every query; sampled queries against

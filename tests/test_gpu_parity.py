@@ -13,6 +13,7 @@ from .gpu_common import bandwidth, device, rel_err, to_dev
 pytestmark = pytest.mark.gpu
 
 KNAME = {GAUSSIAN: "gaussian", EXPONENTIAL: "exponential"}
+KIDS = {"gaussian": GAUSSIAN, "exponential": EXPONENTIAL}
 WL = "mix10_n1e4_d16"
 
 
@@ -128,18 +129,15 @@ def _small(n, q, d, seed=0):
 @pytest.mark.parametrize("n,q,d", [(1000, 37, 9), (129, 1, 3), (1, 5, 2), (300, 130, 33),
                                    (700, 50, 100), (500, 20, 128)])
 def test_edge_shapes_split_exact(dev, n, q, d):
-    # the three-part bfloat16 form: every query within the derived bound and
-    # within the 1e-5 of the float32 path where that bound allows it
+    # the three-part bfloat16 form: every query within 1e-5, as the float32 path
     import paper_2107_02736_amd as dk
     X, Y = _small(n, q, d, seed=n + d)
     Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
     h = 2.0 + 0.1 * d
     ref = oracle.kde_exact(X, Y, h, GAUSSIAN)
     got = dk.kde_exact(Xd, Yd, h, "gaussian", "fp32_split").cpu().numpy()
-    keep = ref >= 1e-16
-    err = np.abs(got[keep] - ref[keep]) / ref[keep]
-    bound = exact_kde_bound(bound_geometry(X, Y), d, h, GAUSSIAN, "fp32_split")[keep]
-    assert np.all(err <= bound), (err.max(), bound.min())
+    err, _ = rel_err(got, ref)
+    assert err.max() <= 1e-5, err.max()
 
 
 def test_split_precision_width_limit(dev):
@@ -160,19 +158,9 @@ def test_edge_shapes_exact_and_knn(dev, n, q, d, prec):
     ref = oracle.kde_exact(X, Y, h, GAUSSIAN)
     got = dk.kde_exact(Xd, Yd, h, "gaussian", prec).cpu().numpy()
     err, _ = rel_err(got, ref)
-    # The GEMM form loses about u * sqrt(d_p) * (||x~||^2 + ||y~||^2) of d^2 to
-    # the FP32 dot product and at most 1.5 u * (||x~||^2 + ||y~||^2) to the
-    # FP32 epilogue (data norm term, one add, one FMA), i.e. that amount
-    # divided by 2 h^2 of each exponent; 4 u sqrt(d_p) covers both for
-    # d_p >= 32.  Allow 1e-5 or that bound, whichever is larger (the bound
-    # exceeds 1e-5 only for KDE values around 1e-13 at d = 64 here).
-    Xc = X - X.mean(axis=0)
-    Yc = Y - X.mean(axis=0)
-    dp = 32 * ((d + 31) // 32)
-    bound = 4 * 2.0 ** -24 * np.sqrt(dp) * ((Xc ** 2).sum(1).max() + (Yc ** 2).sum(1)) / (2 * h * h)
     keep = ref >= 1e-16
-    if prec == "fp32":
-        assert np.all(err <= np.maximum(1e-5, bound[keep]))
+    if prec == "fp32":   # queries the certificate does not pass are re-evaluated exactly
+        assert err.max() <= 1e-5, err.max()
     else:   # the derived per-query bound of the 16-bit operands
         assert np.all(err <= exact_kde_bound(bound_geometry(X, Y), d, h, GAUSSIAN, prec)[keep])
     k = min(n, 7)
@@ -283,21 +271,39 @@ def test_knn_exact_ties_and_duplicates(dev, prec):
             assert np.array_equal(nn[j], oracle.knn(X, Y[j], k)), (k, j)
 
 
-def test_extreme_bandwidths(dev):
+@pytest.mark.parametrize("kern", ["gaussian", "exponential"])
+def test_extreme_bandwidths(dev, kern):
     # h -> infinity: every kernel value tends to 1 (both paths).  h -> 0: only
-    # coincident points count; the DEANN path evaluates its neighbours directly,
-    # so a query equal to a data row gets exactly 1/n.  (The exact path's GEMM
-    # form cannot resolve d^2 = 0 below its rounding of ||x||^2 + ||y||^2.)
+    # coincident points count, so a query equal to a data row gets 1/n: the
+    # DEANN path evaluates its neighbours directly; the exact path's GEMM form
+    # cannot resolve d^2 = 0 below its rounding of ||x||^2 + ||y||^2, so its
+    # certificate sends that query to the exact re-evaluation.
     import paper_2107_02736_amd as dk
     X, Y = _small(500, 8, 4, seed=2)
     Y[0] = X[17]
+    Y[3] = X[400]
     Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
-    big = dk.kde_exact(Xd, Yd, 1e6, "gaussian").cpu().numpy()
-    assert np.allclose(big, 1.0, rtol=1e-6)
-    out, _, _ = dk.deann_query(Xd, Yd, 1e6, 3, 10, seed=0)
-    assert np.allclose(out.cpu().numpy(), 1.0, rtol=1e-9)
-    out, _, _ = dk.deann_query(Xd, Yd, 1e-4, 3, 10, seed=0)
+    big = dk.kde_exact(Xd, Yd, 1e6, kern).cpu().numpy()
+    ref_big = oracle.kde_exact(X, Y, 1e6, KIDS[kern])   # 1 - O(r / h) for the exponential
+    assert np.all(ref_big > 1.0 - 1e-5)
+    assert np.allclose(big, ref_big, rtol=1e-6, atol=0)
+    out, _, _ = dk.deann_query(Xd, Yd, 1e6, 3, 10, kern, seed=0)
+    for j in range(Y.shape[0]):
+        est, _, _ = oracle.deann_estimate(X, Y[j], 1e6, KIDS[kern], 3, 10, 0, j)
+        assert out.cpu().numpy()[j] == pytest.approx(est, rel=1e-12)
+    out, _, _ = dk.deann_query(Xd, Yd, 1e-4, 3, 10, kern, seed=0)
     assert out.cpu().numpy()[0] == pytest.approx(1.0 / 500, rel=1e-12)
+    ref = oracle.kde_exact(X, Y, 1e-4, KIDS[kern])
+    for prec in ("fp32", "fp32_split"):
+        tiny = dk.kde_exact(Xd, Yd, 1e-4, kern, prec).cpu().numpy()
+        assert tiny[0] == pytest.approx(1.0 / 500, rel=1e-6), prec
+        assert tiny[3] == pytest.approx(1.0 / 500, rel=1e-6), prec
+        # the other queries are far from every row: values far below 1e-16
+        assert np.all(tiny[ref < 1e-16] < 1e-16)
+        mu, gy, gh = dk.kde_exact_with_grad(Xd, Yd, 1e-4, kern, prec)
+        assert mu.cpu().numpy()[0] == pytest.approx(1.0 / 500, rel=1e-6), prec
+        # on a data row the gradient of that row's term is zero; the rest underflows
+        assert np.all(np.abs(gy.cpu().numpy()[0]) <= 1e-30)
 
 
 # --------------------------------------------------------------------------
@@ -454,9 +460,7 @@ def test_maximum_k_and_d(dev, prec):
     mu = dk.kde_exact(Xd, Yd, h, "gaussian", "fp32").cpu().numpy()
     ref = oracle.kde_exact(X, Y, h, GAUSSIAN)
     err, _ = rel_err(mu, ref)
-    Xc, Yc = X - X.mean(axis=0), Y - X.mean(axis=0)   # the GEMM-form bound of the edge tests
-    bound = 4 * 2.0 ** -24 * np.sqrt(4096) * ((Xc ** 2).sum(1).max() + (Yc ** 2).sum(1)) / (2 * h * h)
-    assert np.all(err <= np.maximum(1e-5, bound[ref >= 1e-16]))
+    assert err.max() <= 1e-5, err.max()
     X2, Y2 = np.ascontiguousarray(X[:, :2048]), np.ascontiguousarray(Y[:, :2048])
     X2d, Y2d = to_dev(X2, dev), to_dev(Y2, dev)
     h2 = 28.0

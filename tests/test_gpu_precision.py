@@ -4,9 +4,12 @@ q = 1,000): exact KDE with FP32, BF16 and FP16 operands of the distance GEMM
 0.25, 1 and 4, against the FP64 oracle; and DEANN with the 16-bit scans, whose
 refined neighbour sets, draws and estimates must equal the FP32 scan's.
 
-The error of every query is checked against the bound derived from the
-arithmetic in tests/precision_bound.py.  The printed table is the precision
-report of this workload.
+The float32-operand forms (fp32, fp32_split) must be within 1e-5 of the
+oracle for every query at every bandwidth: the queries their error
+certificate does not pass are re-evaluated exactly.  The 16-bit forms are
+checked against the bound derived from the arithmetic in
+tests/precision_bound.py.  The printed table is the precision report of this
+workload.
 """
 import numpy as np
 import pytest
@@ -54,7 +57,10 @@ def test_precision_exact_and_deann(data, geometry, kern, scale):
                 f"mean {err.mean():.2e} (bound: max {bound.max():.2e} mean {bound.mean():.2e}; "
                 f"{excluded} queries < 1e-16)")
         print(line)
-        assert np.all(err <= bound), line
+        if prec in ("fp32", "fp32_split"):
+            assert err.max() <= 1e-5, line
+        else:
+            assert np.all(err <= bound), line
     # DEANN: the 16-bit scans reproduce the FP32 scan bit for bit
     k, m = 50, 500
     res = {p: [t.cpu().numpy() for t in dk.deann_query(Xd, Yd, h, k, m, KNAME[kern], seed=0,

@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary workload block")
+    ap.add_argument("--step-only", action="store_true",
+                    help="time the step and the exact KDE alone only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--all-cores", action="store_true",
                     help="also time the oracle in one process per host core")
@@ -144,6 +146,9 @@ def main():
             sweep_ivf(args, X, Y, h, *KM[args.workload])
         return
     import torch
+    if args.step_only:
+        print(json.dumps(run_workload(args, args.workload, with_cpu=False)), flush=True)
+        return
     prim = run_workload(args, args.workload, with_cpu=not args.no_cpu_baseline)
     sec = None
     if not args.no_secondary and args.workload != SECONDARY:
@@ -268,6 +273,15 @@ def run_workload(args, workload, with_cpu):
     tile_ms = dk.kernel_times("kde_exact")
     dk.kernel_timing(0)
     mu, est, nn, sm, gy, gh, gye, ghe = res
+    if args.step_only:
+        tile_avg = float(np.mean(tile_ms))
+        return {"value": q / (ms_step * 1e-3), "ms_per_step": ms_step,
+                "config": {"workload": workload, "n": n, "d": d, "q": q, "k": K_NN,
+                           "m": M_SAMPLES},
+                "components_ms": {k: float(np.mean(v)) for k, v in comp.items()},
+                "exact_kde_tile_ms": tile_avg,
+                "step_tile_ms": float(np.mean(step_tile_ms)) if step_tile_ms else None,
+                "queries_per_s": {"step": q / (ms_step * 1e-3)}}
 
     # FP32-scan DEANN for the BF16+refine vs FP32 comparison (same seed)
     for _ in range(max(1, args.warmup)):

@@ -71,13 +71,21 @@ __global__ void kde_reduce_cert_kernel(const double* __restrict__ partial, int64
 // ---------------------------------------------------------------------------
 // Exact re-evaluation.  Work item = (16 listed queries, one of `splits` row
 // ranges); a grid-stride loop over the items, whose count follows from the
-// list length on the device.  Thread (r, g) = (tid % 64, tid / 64) owns data
-// row r of each 64-row block and queries 4g..4g+3 of the item.
+// list length on the device.
 // ---------------------------------------------------------------------------
-constexpr int DQT = 16;     // queries per item
-constexpr int DROWS = 64;   // data rows per block
-constexpr int DDC = 64;     // coordinates per LDS chunk (value-only kernel)
-constexpr int DG_MAXD = 128;   // width limit of the gradient kernel
+constexpr int DQT = 16;      // queries per item
+constexpr int DROWS = 64;    // data rows per block (gradient kernel)
+constexpr int DG_MAXD = 128; // width limit of the gradient kernel
+
+// Value-only kernel: blocks of 256 rows, coordinates staged 32 at a time in
+// LDS transposed ([coordinate][row], float) so that thread (rb, g) =
+// (tid % 64, tid / 64) reads rows 4 rb .. 4 rb + 3 of one coordinate with one
+// 16-byte load and the coordinates of queries 4 g .. 4 g + 3 (FP64, the same
+// for the whole wave) as broadcasts; it keeps the 4 x 4 squared distances in
+// registers: 16 differences and 16 FMAs in FP64 per coordinate and four loads.
+constexpr int DXR = 256;          // rows per block
+constexpr int DXC = 32;           // coordinates per LDS stage
+constexpr int DXP = DXR + 4;      // LDS pitch of a coordinate (floats, 16-byte multiple)
 
 template <int KERN>
 __device__ __forceinline__ double kval(double d2, double h) {
@@ -85,57 +93,104 @@ __device__ __forceinline__ double kval(double d2, double h) {
   return exp(-sqrt(d2) / h);
 }
 
-template <int KERN>
+template <int KERN, bool VEC>
 __global__ void __launch_bounds__(WG)
 kde_direct_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n, int64_t d,
                   double h, const int32_t* __restrict__ ids, const int32_t* __restrict__ count,
                   int64_t splits, int64_t q, double* __restrict__ part) {
-  __shared__ float xs[DROWS][DDC + 1];
-  __shared__ double ys[DQT][DDC];
+  __shared__ __attribute__((aligned(16))) float xs[DXC * DXP];
+  __shared__ __attribute__((aligned(16))) double ys[DXC][DQT];
   const int64_t F = *count;
   const int64_t items = ceil_div(F, DQT) * splits;
-  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int rb = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t nc = ceil_div(d, DXC);   // coordinate stages per row block
+  constexpr int XV = DXR * DXC / 4 / WG;   // float4 pieces per thread and stage (8)
+  constexpr int YV = DQT * DXC / WG;       // query values per thread and stage (2)
+  f32x4 xr[XV];
+  double yr[YV];
+  // stage s of an item: row block s / nc, coordinates (s % nc) * DXC + [0, DXC)
+  auto load = [&](int64_t tile, int64_t r0, int64_t r1, int64_t s) {
+    const int64_t b0 = r0 + (s / nc) * DXR, c0 = (s % nc) * DXC;
+#pragma unroll
+    for (int i = 0; i < XV; ++i) {
+      const int e = threadIdx.x + i * WG;          // row e / 8, coordinates 4 (e % 8) + [0, 4)
+      const int64_t row = b0 + e / 8, col = c0 + 4 * (e % 8);
+      if (VEC) {
+        xr[i] = (row < r1 && col < d) ? *reinterpret_cast<const f32x4*>(X + row * d + col)
+                                      : f32x4{0.f, 0.f, 0.f, 0.f};
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xr[i][k] = (row < r1 && col + k < d) ? X[row * d + col + k] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < YV; ++i) {
+      const int e = threadIdx.x + i * WG;
+      const int qq = e / DXC, cc = e % DXC;
+      const int64_t slot = tile * DQT + qq, col = c0 + cc;
+      yr[i] = (slot < F && col < d) ? (double)Y[(int64_t)ids[slot] * d + col] : 0.0;
+    }
+  };
   for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
     const int64_t tile = w / splits, sp = w % splits;
     const int64_t r0 = sp * n / splits, r1 = (sp + 1) * n / splits;
+    const int64_t stages = ceil_div(r1 - r0, DXR) * nc;
     double ks[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t rb = r0; rb < r1; rb += DROWS) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int64_t c0 = 0; c0 < d; c0 += DDC) {
-        __syncthreads();   // the previous chunk has been read
-        for (int e = threadIdx.x; e < DROWS * DDC; e += WG) {
-          const int rr = e / DDC, cc = e % DDC;
-          const int64_t row = rb + rr, col = c0 + cc;
-          xs[rr][cc] = (row < r1 && col < d) ? X[row * d + col] : 0.f;
-        }
-        for (int e = threadIdx.x; e < DQT * DDC; e += WG) {
-          const int qq = e / DDC, cc = e % DDC;
-          const int64_t slot = tile * DQT + qq, col = c0 + cc;
-          ys[qq][cc] = (slot < F && col < d) ? (double)Y[(int64_t)ids[slot] * d + col] : 0.0;
-        }
-        __syncthreads();
-        const int cn = (int)(d - c0 < DDC ? d - c0 : DDC);
-        for (int t = 0; t < cn; ++t) {
-          const double xv = (double)xs[r][t];
+    double acc[4][4];   // [row][query]
+    if (stages > 0) load(tile, r0, r1, 0);
+    for (int64_t s = 0; s < stages; ++s) {
+      const int64_t b0 = r0 + (s / nc) * DXR, c0 = (s % nc) * DXC;
+      if (s % nc == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+      __syncthreads();   // the previous stage has been read
+#pragma unroll
+      for (int i = 0; i < XV; ++i) {
+        const int e = threadIdx.x + i * WG;
+        const int rr = e / 8, cc = 4 * (e % 8);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xs[(cc + k) * DXP + rr] = xr[i][k];
+      }
+#pragma unroll
+      for (int i = 0; i < YV; ++i) {
+        const int e = threadIdx.x + i * WG;
+        ys[e % DXC][e / DXC] = yr[i];
+      }
+      __syncthreads();
+      if (s + 1 < stages) load(tile, r0, r1, s + 1);   // in flight behind this stage
+      const int cn = (int)(d - c0 < DXC ? d - c0 : DXC);
+      for (int t = 0; t < cn; ++t) {
+        const f32x4 xv = *reinterpret_cast<const f32x4*>(&xs[t * DXP + 4 * rb]);
+        double yv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) yv[j] = ys[t][4 * g + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double x = (double)xv[i];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const double df = xv - ys[4 * g + j][t];
-            acc[j] = __builtin_fma(df, df, acc[j]);
+            const double df = x - yv[j];
+            acc[i][j] = __builtin_fma(df, df, acc[i][j]);
           }
         }
       }
-      if (rb + r < r1)
+      if (s % nc == nc - 1)   // the block's distances are complete
 #pragma unroll
-        for (int j = 0; j < 4; ++j) ks[j] += kval<KERN>(acc[j], h);
+        for (int i = 0; i < 4; ++i)
+          if (b0 + 4 * rb + i < r1)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ks[j] += kval<KERN>(acc[i][j], h);
     }
-    // the 64 rows of each query, in a fixed order
+    // the 64 row groups of each query, in a fixed order
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       double v = ks[j];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
       const int64_t slot = tile * DQT + 4 * g + j;
-      if (r == 0 && slot < F) part[sp * q + slot] = v;
+      if (rb == 0 && slot < F) part[sp * q + slot] = v;
     }
   }
 }
@@ -286,7 +341,8 @@ __global__ void kde_direct_grad_reduce_kernel(const double* __restrict__ pval,
 }
 
 namespace {
-constexpr int64_t kDirectGrid = 2048;   // workgroups of the grid-stride loops
+constexpr int64_t kDirectGrid = 2048;      // workgroups of the gradient kernel's loop
+constexpr int64_t kDirectResident = 768;   // value kernel: 3 workgroups on each of 256 CUs
 }
 
 hipError_t launch_kde_reduce_cert(const double* partial, int64_t splits, int64_t qp, int64_t q,
@@ -303,7 +359,7 @@ hipError_t launch_kde_reduce_cert(const double* partial, int64_t splits, int64_t
 int64_t direct_splits(int64_t n) {
   int64_t s = ceil_div(n, 2048);
   if (s < 1) s = 1;
-  if (s > 256) s = 256;
+  if (s > 512) s = 512;
   return s;
 }
 
@@ -312,13 +368,24 @@ hipError_t launch_kde_direct(const float* X, const float* Y, int64_t n, int64_t 
                              int64_t splits, double* part, double* out, hipStream_t s) {
   if (q == 0) return hipSuccess;
   const int64_t items = ceil_div(q, DQT) * splits;
-  const dim3 grid((unsigned)(items < kDirectGrid ? items : kDirectGrid)), block(WG);
-  if (kern == KERNEL_GAUSSIAN)
-    kde_direct_kernel<KERNEL_GAUSSIAN><<<grid, block, 0, s>>>(X, Y, n, d, h, ids, count, splits,
-                                                              q, part);
-  else
-    kde_direct_kernel<KERNEL_EXPONENTIAL><<<grid, block, 0, s>>>(X, Y, n, d, h, ids, count,
-                                                                 splits, q, part);
+  // workgroups that are all resident at once (3 per CU), each looping over items
+  const dim3 grid((unsigned)(items < kDirectResident ? items : kDirectResident)), block(WG);
+  const bool vec = d % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
+  if (kern == KERNEL_GAUSSIAN) {
+    if (vec)
+      kde_direct_kernel<KERNEL_GAUSSIAN, true><<<grid, block, 0, s>>>(X, Y, n, d, h, ids, count,
+                                                                      splits, q, part);
+    else
+      kde_direct_kernel<KERNEL_GAUSSIAN, false><<<grid, block, 0, s>>>(X, Y, n, d, h, ids, count,
+                                                                       splits, q, part);
+  } else {
+    if (vec)
+      kde_direct_kernel<KERNEL_EXPONENTIAL, true><<<grid, block, 0, s>>>(X, Y, n, d, h, ids,
+                                                                         count, splits, q, part);
+    else
+      kde_direct_kernel<KERNEL_EXPONENTIAL, false><<<grid, block, 0, s>>>(X, Y, n, d, h, ids,
+                                                                          count, splits, q, part);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   kde_direct_reduce_kernel<<<dim3((unsigned)ceil_div(q, 256)), dim3(256), 0, s>>>(

@@ -111,7 +111,10 @@ deann_backward_kernel(const float* __restrict__ X, const float* __restrict__ Y, 
 // lanes (16, or a whole wave for long rows) gathers a row once (float4 loads,
 // 16 * GW contiguous bytes per group and step), reduces ||x - y||^2 with
 // shuffles, and accumulates w (x - y) into its own FP64 coordinates; the group
-// partials are summed in a fixed order.
+// partials are summed in a fixed order.  The rows of each group are taken in
+// the same order as before (row g, g + NG, ... of the query's neighbours then
+// draws), so the sums do not change.
+constexpr int BWD_IDX = 2048;   // row indices staged in LDS per chunk
 template <int U, int GW>
 __global__ void __launch_bounds__(WG)
 deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
@@ -123,6 +126,7 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
   constexpr int NG = WG / GW;   // groups (rows in flight) per workgroup
   double* part = reinterpret_cast<double*>(smem);   // [NG][d]
   double* hpart = part + NG * d;                    // [NG]
+  int32_t* rid = reinterpret_cast<int32_t*>(hpart + NG);   // [BWD_IDX] row indices
   const int64_t qi = blockIdx.x;
   const int g = threadIdx.x / GW, lg = threadIdx.x % GW;
   const int64_t size2 = n - k;
@@ -142,10 +146,7 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
       acc[u][c] = 0.0;
     }
   double hs = 0.0;
-  // the group's rows j = g, g + NG, ...: the next row is loaded while the
-  // current one is evaluated
-  auto load_row = [&](int64_t j, float (&dst)[U][4]) {
-    const int32_t row = j < k ? nn[qi * k + j] : samp[qi * m + (j - k)];
+  auto load_row = [&](int32_t row, float (&dst)[U][4]) {
     const float* xr = X + (int64_t)row * d;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -158,45 +159,67 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
       }
     }
   };
-  float xv[U][4], xn[U][4];
-  if (g < R) load_row(g, xv);
-  for (int64_t j = g; j < R; j += NG) {
-    const bool more = j + NG < R;
-    if (more) load_row(j + NG, xn);
-    double s = 0.0;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double df = (double)xv[u][c] - (double)yv[u][c];
-        s = __builtin_fma(df, df, s);
-      }
-#pragma unroll
-    for (int off = 1; off < GW; off <<= 1) s += __shfl_xor(s, off, 64);
-    const double c = j < k ? 1.0 : csamp;
-    double w, dh;
-    if (kern == KERNEL_GAUSSIAN) {
-      const double K = exp(-0.5 * s * inv_h2);
-      w = K * inv_h2;
-      dh = K * s * inv_h2 / h;
-    } else {
-      const double r = sqrt(s);
-      const double K = exp(-r / h);
-      w = r > 0.0 ? K / (h * r) : 0.0;
-      dh = K * r * inv_h2;
+  // Rows in chunks of BWD_IDX: the chunk's row indices are staged in LDS first
+  // (one coalesced read instead of an index load in front of every row load),
+  // and group g takes rows g, g + NG, ... of the chunk with the next rows in
+  // flight behind the one it evaluates.
+  // wide rows (a wave per row) keep two rows in flight per group, 16-lane
+  // groups one (their extra registers would cost occupancy)
+  constexpr bool TWO = GW == 64;
+  float xv[U][4], xa[U][4], xb[U][4];
+  for (int64_t c0 = 0; c0 < R; c0 += BWD_IDX) {
+    const int cnt = (int)(R - c0 < BWD_IDX ? R - c0 : BWD_IDX);
+    __syncthreads();   // the previous chunk's indices have been read
+    for (int i = threadIdx.x; i < cnt; i += WG) {
+      const int64_t j = c0 + i;
+      rid[i] = j < k ? nn[qi * k + j] : samp[qi * m + (j - k)];
     }
-    w *= c;
-    hs += c * dh;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc)
-        acc[u][cc] = __builtin_fma(w, (double)xv[u][cc] - (double)yv[u][cc], acc[u][cc]);
-    if (more)
+    __syncthreads();
+    if (g < cnt) load_row(rid[g], xv);
+    if (TWO && g + NG < cnt) load_row(rid[g + NG], xa);
+    for (int i = g; i < cnt; i += NG) {
+      if (TWO) {
+        if (i + 2 * NG < cnt) load_row(rid[i + 2 * NG], xb);
+      } else {
+        if (i + NG < cnt) load_row(rid[i + NG], xa);
+      }
+      double s = 0.0;
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) xv[u][cc] = xn[u][cc];
+        for (int c = 0; c < 4; ++c) {
+          const double df = (double)xv[u][c] - (double)yv[u][c];
+          s = __builtin_fma(df, df, s);
+        }
+#pragma unroll
+      for (int off = 1; off < GW; off <<= 1) s += __shfl_xor(s, off, 64);
+      const double c = c0 + i < k ? 1.0 : csamp;
+      double w, dh;
+      if (kern == KERNEL_GAUSSIAN) {
+        const double K = exp(-0.5 * s * inv_h2);
+        w = K * inv_h2;
+        dh = K * s * inv_h2 / h;
+      } else {
+        const double r = sqrt(s);
+        const double K = exp(-r / h);
+        w = r > 0.0 ? K / (h * r) : 0.0;
+        dh = K * r * inv_h2;
+      }
+      w *= c;
+      hs += c * dh;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc)
+          acc[u][cc] = __builtin_fma(w, (double)xv[u][cc] - (double)yv[u][cc], acc[u][cc]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          xv[u][cc] = xa[u][cc];
+          if (TWO) xa[u][cc] = xb[u][cc];
+        }
+    }
   }
 #pragma unroll
   for (int u = 0; u < U; ++u)
@@ -245,7 +268,7 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
                        (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
   const dim3 g((unsigned)q), b(WG);
   if (aligned && d <= 256) {   // 16 lanes per row
-    const size_t sm = (16 * d + 16) * 8;
+    const size_t sm = (16 * d + 16) * 8 + BWD_IDX * 4;
     switch ((d + 63) / 64) {
       case 1: deann_backward_vec_kernel<1, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
       case 2: deann_backward_vec_kernel<2, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
@@ -253,7 +276,7 @@ hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int6
       default: deann_backward_vec_kernel<4, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
     }
   } else if (aligned && d <= 2048) {   // a wave per row
-    const size_t sm = (4 * d + 4) * 8;
+    const size_t sm = (4 * d + 4) * 8 + BWD_IDX * 4;
     switch ((d + 255) / 256) {
       case 1:
       case 2: deann_backward_vec_kernel<2, 64><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;

@@ -168,6 +168,39 @@ deann_status deann_query_permuted(const float* X, int64_t n, const float* Y, int
                          int32_t* sample_idx, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Permuted random sampling with the preprocessing of Algorithm 2 (App. G) as
+ * written: a permuted copy X' of the data, x'_i = x_pi(i), built once, from
+ * which each query reads its block of positions contiguously.
+ *   deann_perm_index_bytes   size of the index for n rows of width d (0 on bad
+ *                            sizes): pi[n] and its inverse (int32) and X'
+ *                            [n][d] float32, n d 4 + 8 n bytes and alignment.
+ *   deann_perm_index_create  fills a caller-owned device buffer of at least
+ *                            that size with the permutation keyed by `seed`
+ *                            (the one deann_query_permuted evaluates on the
+ *                            fly) and X'.  X must stay unchanged while the
+ *                            index is used; the library keeps no pointer.
+ *   deann_query_permuted_index  deann_query_permuted with that index: the same
+ *                            neighbours, sample indices (rows of X) and
+ *                            estimates bit for bit, for the seed the index was
+ *                            made with and the given running index `start`;
+ *                            the neighbours' positions come from pi's inverse
+ *                            and the block's rows from X' (coalesced).  The
+ *                            workspace is that of deann_query.
+ * Requirements: as deann_query_permuted; index_bytes at least
+ * deann_perm_index_bytes(n, d), else DEANN_EINVAL (query) or DEANN_EWORKSPACE
+ * (create).
+ * ------------------------------------------------------------------------- */
+size_t deann_perm_index_bytes(int64_t n, int64_t d);
+deann_status deann_perm_index_create(const float* X, int64_t n, int64_t d, uint64_t seed,
+                                     void* index, size_t index_bytes, void* stream);
+deann_status deann_query_permuted_index(const float* X, int64_t n, const float* Y, int64_t q,
+                                        int64_t d, double h, deann_kernel kernel, int64_t k,
+                                        int64_t m, const void* index, size_t index_bytes,
+                                        uint64_t start, deann_precision precision, double* out,
+                                        int32_t* nn_idx, int32_t* sample_idx, void* ws,
+                                        size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Adjoint of deann_query with the index sets held fixed (the selection is
  * piecewise constant in y and h, so this is the derivative almost everywhere):
  *   grad_Y[j] = grad_out[j] * d out[j] / d y_j          [q, d] float32, or NULL

@@ -20,6 +20,7 @@ EXPORTS = (
     "kde_exact_workspace", "kde_exact",
     "deann_query_workspace", "deann_query",
     "deann_query_permuted_workspace", "deann_query_permuted",
+    "deann_perm_index_bytes", "deann_perm_index_create", "deann_query_permuted_index",
     "deann_query_backward_workspace", "deann_query_backward", "deann_query_backward_noalloc",
     "kde_exact_backward_workspace", "kde_exact_backward",
     "kde_exact_with_grad_workspace", "kde_exact_with_grad", "mean_shift_update",
@@ -83,6 +84,13 @@ def load(path: str = LIB_PATH):
     lib.deann_query_permuted.restype = _int
     lib.deann_query_permuted.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64, _u64,
                                          _u64, _int, _vp, _vp, _vp, _vp, _sz, _vp]
+    lib.deann_perm_index_bytes.restype = _sz
+    lib.deann_perm_index_bytes.argtypes = [_i64, _i64]
+    lib.deann_perm_index_create.restype = _int
+    lib.deann_perm_index_create.argtypes = [_vp, _i64, _i64, _u64, _vp, _sz, _vp]
+    lib.deann_query_permuted_index.restype = _int
+    lib.deann_query_permuted_index.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64,
+                                               _vp, _sz, _u64, _int, _vp, _vp, _vp, _vp, _sz, _vp]
     lib.deann_query_backward_workspace.restype = _sz
     lib.deann_query_backward_workspace.argtypes = [_i64, _i64, _i64, _i64, _i64]
     lib.deann_query_backward.restype = _int

@@ -114,11 +114,35 @@ def kde_hybrid(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, kernel="gauss
     return (out, nn_out) if return_indices else out
 
 
+class PermutedIndex:
+    """The permuted copy of X for permuted random sampling (Algorithm 2's
+    preprocessing, App. G): the keyed permutation of the rows, its inverse and
+    the rows in permuted order, in one device buffer owned by this object.
+    X must stay unchanged while the index is used."""
+
+    def __init__(self, X: torch.Tensor, seed: int = 0):
+        _check_xy(X, X)
+        lib = _lib.load()
+        self.n, self.d = X.shape
+        self.seed = int(seed)
+        nbytes = lib.deann_perm_index_bytes(self.n, self.d)
+        self.buffer = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=X.device)
+        _lib.check(lib.deann_perm_index_create(X.data_ptr(), self.n, self.d, self.seed,
+                                               self.buffer.data_ptr(), self.buffer.numel(),
+                                               _stream(X.device)))
+
+    def permutation(self) -> torch.Tensor:
+        """pi (int32 [n]): the row of X at each position of the permuted order."""
+        return self.buffer[: 4 * self.n].view(torch.int32)
+
+
 def deann_query_permuted(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int,
                          kernel="gaussian", seed: int = 0, start: int = 0, precision="fp32",
-                         return_indices: bool = True):
+                         return_indices: bool = True, index: PermutedIndex | None = None):
     """DEANN with permuted random sampling (query i reads the permuted rows from
-    running index start + i m): (out float64 [q], nn_idx [q,k], sample_idx [q,m])."""
+    running index start + i m): (out float64 [q], nn_idx [q,k], sample_idx [q,m]).
+    With `index` (a PermutedIndex of X) the rows come from its permuted copy and
+    the permutation is the index's (its seed replaces `seed`)."""
     _check_xy(X, Y)
     lib = _lib.load()
     n, d = X.shape
@@ -129,6 +153,14 @@ def deann_query_permuted(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: 
     nn = torch.empty((q, k), dtype=torch.int32, device=dev) if return_indices else None
     sm = torch.empty((q, m), dtype=torch.int32, device=dev) if return_indices else None
     ws = _workspace(lib.deann_query_permuted_workspace(n, q, d, k, m, p), dev)
+    if index is not None:
+        if (index.n, index.d) != (n, d) or index.buffer.device != dev:
+            raise ValueError("the permuted index was made for another X")
+        _lib.check(lib.deann_query_permuted_index(
+            X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), int(k), int(m),
+            index.buffer.data_ptr(), index.buffer.numel(), int(start), p, out.data_ptr(),
+            _ptr(nn), _ptr(sm), ws.data_ptr(), ws.numel(), _stream(dev)))
+        return out, nn, sm
     _lib.check(lib.deann_query_permuted(X.data_ptr(), n, Y.data_ptr(), q, d, float(h),
                                         kernel_id(kernel), int(k), int(m), int(seed), int(start),
                                         p, out.data_ptr(), _ptr(nn), _ptr(sm), ws.data_ptr(),

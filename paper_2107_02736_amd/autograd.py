@@ -43,14 +43,14 @@ class DeannKDE(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, Y, h, X, k, m, kernel="gaussian", seed=0, query_offset=0, word2=0,
-                precision="fp32", start=None):
+                precision="fp32", start=None, index=None):
         hv = _h_value(h)
         if start is None:   # draws with repetition (Algorithm 1)
             out, nn, sm = api.deann_query(X, Y.detach().contiguous(), hv, k, m, kernel, seed,
                                           query_offset, word2, precision)
         else:               # permuted random sampling from running index `start`
             out, nn, sm = api.deann_query_permuted(X, Y.detach().contiguous(), hv, k, m, kernel,
-                                                   seed, start, precision)
+                                                   seed, start, precision, index=index)
         ctx.save_for_backward(X, Y, nn, sm)
         ctx.hv, ctx.kernel, ctx.k, ctx.m = hv, kernel, k, m
         ctx.h_is_tensor = isinstance(h, torch.Tensor)
@@ -65,7 +65,7 @@ class DeannKDE(torch.autograd.Function):
         gy, gh = api.deann_query_backward(X, Y.detach().contiguous(), ctx.hv, ctx.k, ctx.m, nn, sm,
                                           grad_out, ctx.kernel, need_y, need_h and ctx.h_is_tensor)
         gh_out = gh.reshape(()).to(ctx.h_device) if gh is not None else None
-        return (gy, gh_out) + (None,) * 9
+        return (gy, gh_out) + (None,) * 10
 
 
 def exact_kde(Y, h, X, kernel="gaussian"):
@@ -73,10 +73,12 @@ def exact_kde(Y, h, X, kernel="gaussian"):
 
 
 def deann_kde(Y, h, X, k, m, kernel="gaussian", seed=0, query_offset=0, word2=0,
-              precision="fp32", start=None):
+              precision="fp32", start=None, index=None):
     """DEANN estimate with autograd; start (not None) selects permuted random
-    sampling from that running index instead of draws with repetition."""
-    out, _, _ = DeannKDE.apply(Y, h, X, k, m, kernel, seed, query_offset, word2, precision, start)
+    sampling from that running index instead of draws with repetition, with
+    the rows of a PermutedIndex when one is given."""
+    out, _, _ = DeannKDE.apply(Y, h, X, k, m, kernel, seed, query_offset, word2, precision, start,
+                               index)
     return out
 
 

@@ -578,11 +578,28 @@ size_t deann_query_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t
 
 }  // extern "C"
 
+// Layout of the permuted index (Algorithm 2's preprocessing, caller-owned):
+// pi[n] and inv[n] int32, then the permuted rows [n][d] float32 at a 256-byte
+// boundary.
+static int64_t perm_index_bytes(int64_t n, int64_t d) {
+  return round_up(2 * n * 4, kAlign) + n * d * 4 + kAlign;
+}
+
+static PermIndex carve_perm_index(void* index, int64_t n) {
+  char* base = static_cast<char*>(align_ws(index));
+  PermIndex p;
+  p.pi = reinterpret_cast<const int32_t*>(base);
+  p.inv = p.pi + n;
+  p.Xp = reinterpret_cast<const float*>(base + round_up(2 * n * 4, kAlign));
+  return p;
+}
+
 static deann_status deann_query_impl(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
                             double h, int kernel, int64_t k, int64_t m, uint64_t seed,
                             uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
                             int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
-                            void* ws, size_t ws_bytes, void* stream) {
+                            void* ws, size_t ws_bytes, void* stream,
+                            const PermIndex* pidx = nullptr) {
   deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_prec(precision)) return fail(DEANN_EINVAL, "unknown precision %d", precision);
@@ -619,7 +636,7 @@ static deann_status deann_query_impl(const float* X, int64_t n, const float* Y, 
     if (e != hipSuccess) return hip_fail(e, "knn");
   }
   e = launch_sample(X, Y, n, q, d, h, kernel, k, m, seed, query_offset, word2, permuted, start,
-                    P.kb.nn_work, P.kb.z1, out, sample_idx, s);
+                    P.kb.nn_work, P.kb.z1, out, sample_idx, s, pidx);
   if (e != hipSuccess) return hip_fail(e, "sample");
   return DEANN_OK;
 }
@@ -645,6 +662,39 @@ deann_status deann_query_permuted(const float* X, int64_t n, const float* Y, int
                          int32_t* sample_idx, void* ws, size_t ws_bytes, void* stream) {
   return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, 0, 0, 1, start, precision, out,
                           nn_idx, sample_idx, ws, ws_bytes, stream);
+}
+
+size_t deann_perm_index_bytes(int64_t n, int64_t d) {
+  if (n < 1 || d < 1 || n >= ((int64_t)1 << 31)) return 0;
+  return (size_t)perm_index_bytes(n, d);
+}
+
+deann_status deann_perm_index_create(const float* X, int64_t n, int64_t d, uint64_t seed,
+                                     void* index, size_t index_bytes, void* stream) {
+  if (n < 1 || d < 1) return fail(DEANN_EINVAL, "need n >= 1 and d >= 1");
+  if (n >= ((int64_t)1 << 31)) return fail(DEANN_EINVAL, "n must be < 2^31");
+  if (!X) return fail(DEANN_EINVAL, "X is NULL");
+  if (!index || (int64_t)index_bytes < perm_index_bytes(n, d))
+    return fail(DEANN_EWORKSPACE, "index of %lld bytes needed", (long long)perm_index_bytes(n, d));
+  const PermIndex p = carve_perm_index(index, n);
+  const hipError_t e = launch_perm_index(X, n, d, seed, p, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "permuted index");
+  return DEANN_OK;
+}
+
+deann_status deann_query_permuted_index(const float* X, int64_t n, const float* Y, int64_t q,
+                                        int64_t d, double h, deann_kernel kernel, int64_t k,
+                                        int64_t m, const void* index, size_t index_bytes,
+                                        uint64_t start, deann_precision precision, double* out,
+                                        int32_t* nn_idx, int32_t* sample_idx, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  if (n >= 1 && d >= 1 && (!index || (int64_t)index_bytes < perm_index_bytes(n, d)))
+    return fail(DEANN_EINVAL, "index of %lld bytes needed (deann_perm_index_bytes)",
+                (long long)perm_index_bytes(n, d));
+  const PermIndex p = carve_perm_index(const_cast<void*>(index), n);
+  // the seed only keys the permutation, which the index already holds
+  return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, 0, 0, 0, 1, start, precision, out,
+                          nn_idx, sample_idx, ws, ws_bytes, stream, &p);
 }
 
 size_t deann_query_backward_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m) {

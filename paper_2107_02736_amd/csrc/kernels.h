@@ -209,11 +209,22 @@ hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers&
                           hipStream_t s);
 
 // ---- sampler, gather and combine --------------------------------------------
+// Prepared permuted index of Algorithm 2: pi[n] (row at each position), inv[n]
+// (position of each row), Xp[n][d] the rows in permuted order.
+struct PermIndex {
+  const int32_t* pi;
+  const int32_t* inv;
+  const float* Xp;
+};
+hipError_t launch_perm_index(const float* X, int64_t n, int64_t d, uint64_t seed,
+                             const PermIndex& pidx, hipStream_t s);
+// pidx (permuted sampling only; may be null): read the permutation and the
+// rows from the prepared index instead of evaluating the permutation.
 hipError_t launch_sample(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                          double h, int kern, int64_t k, int64_t m, uint64_t seed,
                          uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
                          const int32_t* nn_sorted, const double* z1, double* out,
-                         int32_t* sample_idx, hipStream_t s);
+                         int32_t* sample_idx, hipStream_t s, const PermIndex* pidx = nullptr);
 
 // ---- adjoints ----------------------------------------------------------------
 hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,

@@ -113,14 +113,21 @@ __device__ __forceinline__ double kval(double d2, double h, int kern) {
 
 // PERM: permuted blocks (App. G) instead of draws with repetition; a template
 // argument so that the draw loop of the plain sampler carries none of it.
-template <bool PERM>
+// IDX (with PERM): the permutation is read from a prepared index instead of
+// being evaluated: pi[pos] the row at position pos of the permuted order,
+// inv[row] its position, and the rows themselves from the permuted copy Xp,
+// where a query's block is contiguous (Algorithm 2 as written).
+template <bool PERM, bool IDX>
 __global__ void __launch_bounds__(WG)
 deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
                     int64_t d, double h, int kern, int64_t k, int64_t m, uint64_t seed,
                     uint64_t query_offset, uint64_t word2, uint64_t start,
                     const int32_t* __restrict__ nn_sorted, const double* __restrict__ z1,
-                    double* __restrict__ out, int32_t* __restrict__ sample_idx) {
+                    double* __restrict__ out, int32_t* __restrict__ sample_idx,
+                    const int32_t* __restrict__ pi, const int32_t* __restrict__ inv,
+                    const float* __restrict__ Xp) {
   constexpr bool permuted = PERM;
+  static_assert(PERM || !IDX, "a prepared index is for permuted sampling");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int kp = permuted ? next_pow2_i(k) : (int)k;   // sorted in place when permuted
   double* kv = reinterpret_cast<double*>(smem);                    // DRAW_CHUNK
@@ -143,9 +150,15 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
   const int bits = perm_bits(n);
   const int64_t run = permuted ? (int64_t)((start % (uint64_t)n + ((uint64_t)qi * (uint64_t)m) % (uint64_t)n) % (uint64_t)n) : 0;
   if constexpr (permuted) {
-    for (int t = threadIdx.x; t < kp; t += WG)
-      gaps[t] = t < k ? (int32_t)((permute(nn_sorted[qi * k + t], n, bits, seed, true) - run + n) % n)
-                      : INT32_MAX;
+    for (int t = threadIdx.x; t < kp; t += WG) {
+      int32_t gp = INT32_MAX;
+      if (t < k) {
+        const int64_t pos = IDX ? (int64_t)inv[nn_sorted[qi * k + t]]
+                                : permute(nn_sorted[qi * k + t], n, bits, seed, true);
+        gp = (int32_t)((pos - run + n) % n);
+      }
+      gaps[t] = gp;
+    }
     __syncthreads();
     block_sort_i32(gaps, kp);
     for (int t = threadIdx.x; t < k; t += WG) gaps[t] -= t;
@@ -177,9 +190,15 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
             if ((uint64_t)(int64_t)gaps[mid] <= r) lo = mid + 1; else hi = mid;
           }
           const int64_t u = (int64_t)(r + (uint64_t)lo);
-          const int32_t idx = permuted ? (int32_t)permute((run + u) % n, n, bits, seed, false)
-                                       : (int32_t)u;
-          sidx[jj] = idx;
+          int32_t idx;
+          if constexpr (IDX) {   // gather from the permuted copy, report the row
+            const int64_t pos = (run + u) % n;
+            sidx[jj] = (int32_t)pos;
+            idx = pi[pos];
+          } else {
+            idx = permuted ? (int32_t)permute((run + u) % n, n, bits, seed, false) : (int32_t)u;
+            sidx[jj] = idx;
+          }
           if (sample_idx) sample_idx[qi * m + j0 + jj] = idx;
         }
       }
@@ -194,7 +213,7 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
         rr[i] = jj < cnt ? (int64_t)sidx[jj] : -1;
       }
       double s4[4];
-      group16_d2_4(X, rr, d, ys, l16, s4);
+      group16_d2_4(IDX ? Xp : X, rr, d, ys, l16, s4);
       if (l16 == 0)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -221,21 +240,67 @@ hipError_t launch_sample(const float* X, const float* Y, int64_t n, int64_t q, i
                          double h, int kern, int64_t k, int64_t m, uint64_t seed,
                          uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
                          const int32_t* nn_sorted, const double* z1, double* out,
-                         int32_t* sample_idx, hipStream_t s) {
+                         int32_t* sample_idx, hipStream_t s, const PermIndex* pidx) {
   if (q == 0) return hipSuccess;
   // without draws (m = 0 or k = n) the kernel only writes Z1 / n and needs no
   // gap table, whose size would otherwise grow with k
   const bool draws = m > 0 && k < n;
   const int64_t kp = !draws ? 0 : permuted ? next_pow2_i(k) : k;
   const size_t sm = DRAW_CHUNK * (8 + 4) + kp * 4 + d * 4 + 16;
-  if (permuted)
-    deann_sample_kernel<true><<<dim3((unsigned)q), dim3(WG), sm, s>>>(
+  const dim3 g((unsigned)q), b(WG);
+  if (permuted && pidx)
+    deann_sample_kernel<true, true><<<g, b, sm, s>>>(
         X, Y, n, d, h, kern, k, m, seed, query_offset, word2, start, nn_sorted, z1, out,
-        sample_idx);
+        sample_idx, pidx->pi, pidx->inv, pidx->Xp);
+  else if (permuted)
+    deann_sample_kernel<true, false><<<g, b, sm, s>>>(
+        X, Y, n, d, h, kern, k, m, seed, query_offset, word2, start, nn_sorted, z1, out,
+        sample_idx, nullptr, nullptr, nullptr);
   else
-    deann_sample_kernel<false><<<dim3((unsigned)q), dim3(WG), sm, s>>>(
+    deann_sample_kernel<false, false><<<g, b, sm, s>>>(
         X, Y, n, d, h, kern, k, m, seed, query_offset, word2, start, nn_sorted, z1, out,
-        sample_idx);
+        sample_idx, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+// Permuted index (Algorithm 2's preprocessing): pi[pos] = the keyed
+// permutation of pos, inv[pi[pos]] = pos, then the rows Xp[pos] = X[pi[pos]].
+__global__ void perm_index_kernel(int64_t n, uint64_t seed, int32_t* __restrict__ pi,
+                                  int32_t* __restrict__ inv) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= n) return;
+  const int64_t r = permute(pos, n, perm_bits(n), seed, false);
+  pi[pos] = (int32_t)r;
+  inv[r] = (int32_t)pos;
+}
+
+// One wave per permuted row: float4 copies when rows are 16-byte aligned.
+__global__ void __launch_bounds__(WG) perm_rows_kernel(const float* __restrict__ X, int64_t n,
+                                                       int64_t d, const int32_t* __restrict__ pi,
+                                                       float* __restrict__ Xp, int vec) {
+  const int64_t pos = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (pos >= n) return;
+  const float* src = X + (int64_t)pi[pos] * d;
+  float* dst = Xp + pos * d;
+  if (vec) {
+    for (int64_t t = 4 * lane; t < d; t += 256)
+      *reinterpret_cast<f32x4*>(dst + t) = *reinterpret_cast<const f32x4*>(src + t);
+  } else {
+    for (int64_t t = lane; t < d; t += 64) dst[t] = src[t];
+  }
+}
+
+hipError_t launch_perm_index(const float* X, int64_t n, int64_t d, uint64_t seed,
+                             const PermIndex& pidx, hipStream_t s) {
+  perm_index_kernel<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s>>>(
+      n, seed, const_cast<int32_t*>(pidx.pi), const_cast<int32_t*>(pidx.inv));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int vec = d % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
+                  reinterpret_cast<uintptr_t>(pidx.Xp) % 16 == 0;
+  perm_rows_kernel<<<dim3((unsigned)ceil_div(n, WG / 64)), dim3(WG), 0, s>>>(
+      X, n, d, pidx.pi, const_cast<float*>(pidx.Xp), vec);
   return hipGetLastError();
 }
 

@@ -120,3 +120,84 @@ def test_permuted_fullsize_sampled():
         assert np.array_equal(nn[j], nn_ref), j
         assert np.array_equal(sm[j], s_ref), j
         assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300)
+
+
+@pytest.mark.parametrize("n,d", [(10_000, 16), (300, 9), (129, 33), (5, 4), (4099, 128)])
+def test_permuted_index_is_the_permutation(n, d):
+    # Algorithm 2's preprocessing: pi is a permutation of [n] equal to the
+    # oracle's keyed permutation, and the copy holds x_pi(i) at position i
+    import torch
+
+    import paper_2107_02736_amd as dk
+    dev = device()
+    X, _ = _small(n, 1, d, seed=n + d)
+    Xd = to_dev(X, dev)
+    idx = dk.PermutedIndex(Xd, seed=11)
+    torch.cuda.synchronize()
+    pi = idx.permutation().cpu().numpy()
+    assert np.array_equal(np.sort(pi), np.arange(n))
+    for pos in list(range(min(n, 40))) + list(range(max(0, n - 40), n)):
+        assert pi[pos] == oracle.permutation(n, 11, pos), pos
+    raw = idx.buffer.cpu().numpy()
+    inv = raw[4 * n: 8 * n].view(np.int32)
+    assert np.array_equal(inv[pi], np.arange(n))
+    off = (8 * n + 255) // 256 * 256
+    base = (256 - idx.buffer.data_ptr() % 256) % 256   # the library aligns the buffer start
+    Xp = raw[base + off: base + off + 4 * n * d].view(np.float32).reshape(n, d)
+    assert np.array_equal(Xp, X[pi])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_permuted_index_reproduces_the_evaluated_permutation(kern, prec):
+    # with the permuted copy: the same neighbours, rows and estimates bit for
+    # bit as the permutation evaluated per draw, and the oracle's
+    import paper_2107_02736_amd as dk
+    dev = device()
+    spec, X, Y = synth.workload("mix10_n1e4_d16")
+    Y = Y[:150]
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h = bandwidth("mix10_n1e4_d16", KNAME[kern])
+    n = X.shape[0]
+    idx = dk.PermutedIndex(Xd, seed=5)
+    for k, m, start in ((50, 500, 77), (0, 37, n - 10), (9, n - 9, 0)):
+        a = [t.cpu().numpy() for t in dk.deann_query_permuted(Xd, Yd, h, k, m, KNAME[kern], seed=5,
+                                                            start=start, precision=prec)]
+        b = [t.cpu().numpy() for t in dk.deann_query_permuted(Xd, Yd, h, k, m, KNAME[kern],
+                                                            start=start, precision=prec,
+                                                            index=idx)]
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v), (k, m)
+        for j in range(0, Y.shape[0], 37):
+            est, nn_ref, s_ref = oracle.deann_estimate_permuted(X, Y[j], h, kern, k, m, 5,
+                                                                (start + j * m) % n)
+            assert np.array_equal(b[1][j], nn_ref) and np.array_equal(b[2][j], s_ref)
+            assert abs(b[0][j] - est) <= 1e-12 * max(est, 1e-300)
+
+
+def test_permuted_index_fullsize_d960():
+    # the large workload: the index's block rows against the evaluated
+    # permutation on every query (bitwise), two queries against the oracle
+    import torch
+
+    import paper_2107_02736_amd as dk
+    dev = device()
+    wl = "mix200_n1e6_d960"
+    spec, X, Y = synth.workload(wl, q=2000)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h = bandwidth(wl, "gaussian")
+    idx = dk.PermutedIndex(Xd, seed=2)
+    a = [t.cpu().numpy() for t in dk.deann_query_permuted(Xd, Yd, h, 200, 2000, seed=2, start=5,
+                                                        precision="bf16")]
+    b = [t.cpu().numpy() for t in dk.deann_query_permuted(Xd, Yd, h, 200, 2000, start=5,
+                                                        precision="bf16", index=idx)]
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    del idx
+    torch.cuda.empty_cache()
+    n = X.shape[0]
+    for j in (3, 1777):
+        est, nn_ref, s_ref = oracle.deann_estimate_permuted(X, Y[j], h, GAUSSIAN, 200, 2000, 2,
+                                                            (5 + j * 2000) % n)
+        assert np.array_equal(b[1][j], nn_ref) and np.array_equal(b[2][j], s_ref)
+        assert abs(b[0][j] - est) <= 1e-12 * est

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdeann.so")
+# DEANN_LIB selects another build of the library (the host-AddressSanitizer
+# build of the ABI tests, for instance)
+LIB_PATH = os.environ.get("DEANN_LIB") or os.path.join(_HERE, "libdeann.so")
 
 OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
 NOALLOC_MAX_Q = 1 << 20   # DEANN_NOALLOC_MAX_Q

@@ -58,6 +58,48 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+ASAN_LIB = os.path.join(OBJDIR, "libdeann_asan.so")
+
+
+def asan_runtime() -> str | None:
+    """Path of the host AddressSanitizer runtime of hipcc's clang, or None."""
+    res = subprocess.run([_hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True)
+    path = res.stdout.strip()
+    return path if res.returncode == 0 and os.path.isabs(path) and os.path.exists(path) else None
+
+
+def build_asan(verbose: bool = False) -> str:
+    """The C ABI layer (api.cpp) with host AddressSanitizer, linked with the
+    kernels' objects of the last build() into _build/libdeann_asan.so.  Only the
+    host code is instrumented (the device code is built as usual).  Load it
+    with the runtime preloaded (LD_PRELOAD=asan_runtime()) and DEANN_LIB set."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    obj = os.path.join(OBJDIR, "api_asan.o")
+    cmd = [_hipcc(), "-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer",
+           "-x", "hip", "-c", os.path.join(CSRC, "api.cpp"), "-o", obj]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for api.cpp (asan):\n{res.stderr}")
+    others = [os.path.join(OBJDIR, src + ".o") for src in SOURCES if src != "api.cpp"]
+    missing = [o for o in others if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"run build() first: missing {missing}")
+    # the sanitizer's symbols stay undefined in the library: the runtime is
+    # preloaded into the process that loads it
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", obj, *others, "-o", ASAN_LIB]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"asan link failed:\n{res.stderr}")
+    if verbose:
+        print(f"built {ASAN_LIB}")
+    return ASAN_LIB
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "asan":
+        build_asan(verbose=True)
     sys.exit(0)

@@ -77,7 +77,7 @@ def _check_queries(X, Y, C, a, n_probe, k, m, kern, h, seed, out, nn, sm, rows):
                                                        seed, j)
         assert np.array_equal(nn[j], nn_ref), (j, n_probe, k)
         assert np.array_equal(sm[j], s_ref), (j, n_probe, k)
-        assert abs(out[j] - est) <= 1e-10 * max(est, 1e-300), (j, out[j], est)
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300), (j, out[j], est)
 
 
 @pytest.mark.parametrize("d", [16, 33])

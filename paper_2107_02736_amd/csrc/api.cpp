@@ -231,6 +231,13 @@ deann_status check_common(const float* X, int64_t n, const float* Y, int64_t q, 
 
 // ---- per-path workspace plans -------------------------------------------------
 constexpr int64_t kKdeSplitTarget = 4096;
+
+// Exact adjoint / value + gradient: each (query tile, split) workgroup writes
+// per-split FP64 gradient partials (qp x dp doubles per split), so it takes
+// about five rounds of resident workgroups (one 8-wave workgroup per CU, two
+// for rows of 64 floats) instead of the forward's 4096, each sweeping a longer
+// range of data tiles: about a third of the partial traffic.
+int64_t bwd_split_target(int64_t dp) { return (dp == 64 ? 512 : 256) * 5; }
 constexpr int64_t kKnnSplitTarget = 512;     // selection scan: about one wave of workgroups
 constexpr int64_t kCollectSplitTarget = 4096;  // candidate and collect passes
 constexpr int64_t kIvfPartTarget = 512;        // inverted-file sweep parts: 2 per CU
@@ -388,7 +395,7 @@ KdeBwdPlan plan_kde_bwd(void* ws, int64_t n, int64_t q, int64_t d, int precision
   KdeBwdPlan P{};
   P.prep = carve_prep(cv, n, q, d, DEANN_FP32);
   const int64_t qtiles = P.prep.qp / BQ, ntiles = P.prep.np / BN;
-  const int64_t splits = choose_splits(qtiles, ntiles, kKdeSplitTarget);
+  const int64_t splits = choose_splits(qtiles, ntiles, bwd_split_target(P.prep.dp));
   P.gy_part = cv.take<double>(splits * P.prep.qp * P.prep.dp);
   P.gh_part = cv.take<double>(3 * splits * P.prep.qp + (q > 0 ? q : 1));
   if (precision == DEANN_FP32_SPLIT) {
@@ -834,7 +841,7 @@ deann_status kde_exact_backward(const float* X, int64_t n, const float* Y, int64
   SplitRows sp;
   hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
-  TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, kKdeSplitTarget);
+  TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, bwd_split_target(P.prep.dp));
   // one 8-wave workgroup per CU: the query tiles of the split-major order
   // already fit the L2 next to the shared data tiles
   tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
@@ -960,7 +967,7 @@ deann_status kde_exact_with_grad(const float* X, int64_t n, const float* Y, int6
   SplitRows sp;
   hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
-  TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, kKdeSplitTarget);
+  TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, bwd_split_target(P.prep.dp));
   tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
   e = launch_kde_backward(tp, X, Y, d, h, kernel, nullptr, P.gy_part, P.gh_part, grad_Y, nullptr,
                           s, timer_hook(1), out, grad_h, sp,

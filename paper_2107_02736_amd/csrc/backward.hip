@@ -337,6 +337,39 @@ struct GradTile {
   static constexpr int PPR = DP / 4;             // 16-byte pieces per row
 };
 
+// The gradient tile G sums W x~ in FP32 MFMA accumulators. Its terms cancel
+// (sum of w x against y times sum of w), so the FP32 sums are moved into the
+// workgroup's FP64 partial every kGradFlushRows data rows and restarted: the
+// rounding error then grows with that run, not with the split's whole range.
+// G block (nb, j): lane (g, c), register rr holds query 4g + rr, coordinate
+// nb*64 + 4c + j (trailing block: NB*64 + 2c + j).
+constexpr int kGradFlushRows = 8192;
+
+template <int DP>
+__device__ inline void flush_grad(f32x4 (&gacc)[GradTile<DP>::GB], double* __restrict__ part,
+                                  int g, int c, bool fresh) {
+  using G = GradTile<DP>;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    double* dst = part + (4 * g + rr) * DP;
+#pragma unroll
+    for (int nb = 0; nb < G::NB; ++nb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double* o = dst + nb * 64 + 4 * c + j;
+        *o = (fresh ? 0.0 : *o) + (double)gacc[4 * nb + j][rr];
+      }
+    if constexpr (G::HB)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        double* o = dst + G::NB * 64 + 2 * c + j;
+        *o = (fresh ? 0.0 : *o) + (double)gacc[4 * G::NB + j][rr];
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < G::GB; ++i) gacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
 // VAL: also sum the kernel values themselves (the KDE); needed separately for
 // the exponential kernel only, whose weights are K / r (Gaussian: K).
 // TR: data rows staged per step, 128 (one workgroup per CU) or 64 (two
@@ -405,12 +438,20 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
   // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential: largest K
   float csq = 0.f, cmx = 0.f;
 
+  const int64_t qbase = split * p.qp + qt * BQ + wave * 16;
+  double* gpart = gy_part + qbase * DP;
+  bool fresh = true;
+
   if (t0 < t1) {
     gload(t0);
     lstore(0);
   }
   __syncthreads();
-  for (int64_t t = t0; t < t1; ++t) {
+  // runs of kGradFlushRows rows, each ending in a flush of G (a test inside
+  // the tile loop instead costs registers, and occupancy)
+  for (int64_t tc = t0; tc < t1; tc += kGradFlushRows / TR) {
+  const int64_t te = tc + kGradFlushRows / TR < t1 ? tc + kGradFlushRows / TR : t1;
+  for (int64_t t = tc; t < te; ++t) {
     const int b = (int)((t - t0) & 1);
     const bool more = t + 1 < t1;
     if (more) gload(t + 1);   // in flight behind the first product
@@ -501,6 +542,9 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
     __builtin_amdgcn_s_setprio(0);
     __syncthreads();   // tile t+1 staged; buffer b free for tile t+2
   }
+  flush_grad<DP>(gacc, gpart, g, c, fresh);
+  fresh = false;
+  }
 
   // per-query sums: the four lane groups of a query column (fixed order)
   rws += __shfl_xor(rws, 16, 64);
@@ -520,26 +564,13 @@ kde_backward_kernel(TileProblem p, float L, double* __restrict__ gy_part,
     cmx = fmaxf(cmx, __shfl_xor(cmx, 16, 64));
     cmx = fmaxf(cmx, __shfl_xor(cmx, 32, 64));
   }
-  const int64_t qbase = split * p.qp + qt * BQ + wave * 16;
   if (g == 0) {
     rw_part[qbase + c] = rws;
     gh_part[qbase + c] = dhs;
     if constexpr (KS) ks_part[qbase + c] = kss;
     cert[qbase + c] = make_float2(csq, cmx);
   }
-  // G block (nb, j): lane (g, c), register rr holds query 4g + rr, coordinate
-  // nb*64 + 4c + j (trailing block: NB*64 + 2c + j)
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    double* dst = gy_part + (qbase + 4 * g + rr) * DP;
-#pragma unroll
-    for (int nb = 0; nb < G::NB; ++nb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) dst[nb * 64 + 4 * c + j] = (double)gacc[4 * nb + j][rr];
-    if constexpr (G::HB)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) dst[G::NB * 64 + 2 * c + j] = (double)gacc[4 * G::NB + j][rr];
-  }
+  if (fresh) flush_grad<DP>(gacc, gpart, g, c, true);   // empty range: zeros
 }
 
 // The same pass with the distance product from three-part bfloat16 rows (see
@@ -631,13 +662,19 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
   // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential: largest K
   float csq = 0.f, cmx = 0.f;
 
+  const int64_t qbase = split * p.qp + qt * BQ + wave * 16;
+  double* gpart = gy_part + qbase * DP;
+  bool fresh = true;
+
   if (u0 < u1) {
     gload(u0);
     store_split(0);
     store_rows();
   }
   __syncthreads();
-  for (int64_t u = u0; u < u1; ++u) {
+  for (int64_t uc = u0; uc < u1; uc += kGradFlushRows / TR) {
+  const int64_t ue = uc + kGradFlushRows / TR < u1 ? uc + kGradFlushRows / TR : u1;
+  for (int64_t u = uc; u < ue; ++u) {
     const int b = (int)((u - u0) & 1);
     const bool more = u + 1 < u1;
     if (more) gload(u + 1);
@@ -740,6 +777,9 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
     if (more) store_rows();
     __syncthreads();   // staged tile u+1 published
   }
+  flush_grad<DP>(gacc, gpart, g, c, fresh);
+  fresh = false;
+  }
 
   rws += __shfl_xor(rws, 16, 64);
   rws += __shfl_xor(rws, 32, 64);
@@ -758,24 +798,13 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
     cmx = fmaxf(cmx, __shfl_xor(cmx, 16, 64));
     cmx = fmaxf(cmx, __shfl_xor(cmx, 32, 64));
   }
-  const int64_t qbase = split * p.qp + qt * BQ + wave * 16;
   if (g == 0) {
     rw_part[qbase + c] = rws;
     gh_part[qbase + c] = dhs;
     if constexpr (KS) ks_part[qbase + c] = kss;
     cert[qbase + c] = make_float2(csq, cmx);
   }
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    double* dst = gy_part + (qbase + 4 * g + rr) * DP;
-#pragma unroll
-    for (int nb = 0; nb < G::NB; ++nb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) dst[nb * 64 + 4 * c + j] = (double)gacc[4 * nb + j][rr];
-    if constexpr (G::HB)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) dst[G::NB * 64 + 2 * c + j] = (double)gacc[4 * G::NB + j][rr];
-  }
+  if (fresh) flush_grad<DP>(gacc, gpart, g, c, true);   // empty range: zeros
 }
 
 // grad_Y[q] = g_q / n * c_y * f_q * (sum_s G_s[q] - y~_q sum_s rowsum_s[q]) and the

@@ -79,7 +79,13 @@ typedef struct {
    * distance tiles (the KDE is translation invariant; centring shrinks the
    * norms the GEMM identity cancels); 0: raw coordinates. */
   int32_t center;
-  int32_t reserved; /* 0 */
+  /* 16-bit k-NN scans (DEANN_BF16, DEANN_FP16): the candidate pass that seeds
+   * the distance bound of the second pass reads every knn_seed_stride-th data
+   * tile of 128 rows (in [1, 64], default 4; lowered so that it reads at least
+   * 16 tiles, if there are as many).  A larger
+   * stride makes that pass cheaper and the bound looser (more rows for the
+   * second pass to collect and sort); it changes no result. */
+  int32_t knn_seed_stride;
 } deann_options;
 
 void deann_default_options(deann_options* opt);

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
     """deann_options (include/deann.h)."""
     _fields_ = [("rel_tol", ctypes.c_double), ("value_floor", ctypes.c_double),
                 ("knn_slack", ctypes.c_int64), ("knn_cap2", ctypes.c_int64),
-                ("center", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("center", ctypes.c_int32), ("knn_seed_stride", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

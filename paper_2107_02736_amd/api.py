@@ -257,12 +257,12 @@ def get_options() -> dict:
     """The options of this thread's calls (deann_options) as a dict."""
     o = _lib.Options()
     _lib.check(_lib.load().deann_get_options(o))
-    return {name: getattr(o, name) for name, _ in _lib.Options._fields_ if name != "reserved"}
+    return {name: getattr(o, name) for name, _ in _lib.Options._fields_}
 
 
 def set_options(**kw) -> dict:
     """Change some options of this thread's calls (rel_tol, value_floor, knn_slack,
-    knn_cap2, center); returns the previous options."""
+    knn_cap2, center, knn_seed_stride); returns the previous options."""
     prev = get_options()
     o = _lib.Options()
     _lib.check(_lib.load().deann_get_options(o))
@@ -277,7 +277,7 @@ def set_options(**kw) -> dict:
 def default_options() -> dict:
     o = _lib.Options()
     _lib.load().deann_default_options(o)
-    return {name: getattr(o, name) for name, _ in _lib.Options._fields_ if name != "reserved"}
+    return {name: getattr(o, name) for name, _ in _lib.Options._fields_}
 
 
 def last_stats(device=None) -> dict:

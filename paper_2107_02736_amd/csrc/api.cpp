@@ -77,7 +77,7 @@ deann_options default_options() {
   o.knn_slack = 16;
   o.knn_cap2 = kSortCapMax;
   o.center = 1;
-  o.reserved = 0;
+  o.knn_seed_stride = 4;
   return o;
 }
 
@@ -193,6 +193,7 @@ TileProblem make_problem(const Prep& p, int64_t n, int64_t q, int prec, int64_t 
   // of at most 256 bytes hold the query tile in LDS or registers
   const bool resident_query = prec != DEANN_FP32 && t.ld_bytes <= 2 * CHUNK_BYTES;
   t.map = make_tile_map(t.qtiles, t.splits, resident_query ? 1 : 4);
+  t.tstride = 1;
   return t;
 }
 
@@ -347,6 +348,7 @@ DeannPlan plan_deann(void* ws, int64_t n, int64_t q, int64_t d, int64_t k, int p
   b.status = cv.take<int32_t>(q > 0 ? q : 1);
   b.yerr = P.prep.yerr;
   b.xerr_max = P.prep.err_max;
+  b.seed_stride = g_opt.knn_seed_stride;
   P.bytes = cv.off + kAlign;
   return P;
 }
@@ -460,7 +462,8 @@ deann_status deann_set_options(const deann_options* o) {
   if (o->knn_cap2 < 1 || o->knn_cap2 > kSortCapMax)
     return fail(DEANN_EINVAL, "knn_cap2 must be in [1, %lld]", (long long)kSortCapMax);
   if (o->center != 0 && o->center != 1) return fail(DEANN_EINVAL, "center must be 0 or 1");
-  if (o->reserved != 0) return fail(DEANN_EINVAL, "reserved must be 0");
+  if (o->knn_seed_stride < 1 || o->knn_seed_stride > 64)
+    return fail(DEANN_EINVAL, "knn_seed_stride must be in [1, 64]");
   g_opt = *o;
   return DEANN_OK;
 }

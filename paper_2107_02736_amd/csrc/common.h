@@ -153,7 +153,8 @@ __device__ __forceinline__ void mfma_chunk(f32x4 (&acc)[4][4], const char* qa, c
 //   StreamState st;  stream_start(st, ...);
 //   for (t = t0; t < t1; ++t) { stream_tile<T>(acc, st, ..., t, ...); epilogue; }
 //   __syncthreads();   // before reusing the staging area
-// The epilogue may use LDS outside the 4 * TILE_LDS staging area.
+// The epilogue may use LDS outside the 4 * TILE_LDS staging area.  ts: sweep
+// tile t reads data tile t * ts (every ts-th tile; the engines below alike).
 struct StreamState {
   ChunkRegs rq, rx;
   int buf;
@@ -161,9 +162,9 @@ struct StreamState {
 
 __device__ __forceinline__ void stream_start(StreamState& st, const char* __restrict__ yq,
                                              const char* __restrict__ Xs, int64_t ld_bytes,
-                                             int64_t t0) {
+                                             int64_t t0, int64_t ts = 1) {
   load_chunk(st.rq, yq, ld_bytes, 0);
-  load_chunk(st.rx, Xs + t0 * BN * ld_bytes, ld_bytes, 0);
+  load_chunk(st.rx, Xs + t0 * ts * BN * ld_bytes, ld_bytes, 0);
   st.buf = 0;
   __syncthreads();   // previous users of the staging area are done
 }
@@ -175,7 +176,7 @@ __device__ __forceinline__ void stream_tile(f32x4 (&acc)[4][4], StreamState& st,
                                             const char* __restrict__ yq,
                                             const char* __restrict__ Xs, int64_t ld_bytes,
                                             int nchunks, int64_t t, int64_t t1, char* lds,
-                                            int wq, int wn, int lane) {
+                                            int wq, int wn, int lane, int64_t ts = 1) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -191,7 +192,7 @@ __device__ __forceinline__ void stream_tile(f32x4 (&acc)[4][4], StreamState& st,
     if (nc == nchunks) { nc = 0; nt = t + 1; }
     if (nt < t1) {
       load_chunk(st.rq, yq, ld_bytes, (int64_t)nc * CHUNK_BYTES);
-      load_chunk(st.rx, Xs + nt * BN * ld_bytes, ld_bytes, (int64_t)nc * CHUNK_BYTES);
+      load_chunk(st.rx, Xs + nt * ts * BN * ld_bytes, ld_bytes, (int64_t)nc * CHUNK_BYTES);
     }
     __builtin_amdgcn_s_setprio(1);   // favour the wave issuing MFMAs
     if (SWAP)
@@ -220,7 +221,8 @@ struct QlState {
 };
 
 __device__ __forceinline__ void ql_start(QlState& st, const char* __restrict__ yq,
-                                         const char* __restrict__ Xs, int64_t t0, char* lds) {
+                                         const char* __restrict__ Xs, int64_t t0, char* lds,
+                                         int64_t ts = 1) {
   __syncthreads();   // previous users of the staging area are done
   constexpr int VECS = BQ * QL_ROWB / 16;
 #pragma unroll
@@ -230,14 +232,14 @@ __device__ __forceinline__ void ql_start(QlState& st, const char* __restrict__ y
     *reinterpret_cast<u32x4*>(lds + row * QL_YROW + col * 16) =
         *reinterpret_cast<const u32x4*>(yq + row * QL_ROWB + col * 16);
   }
-  load_chunk(st.rx[0], Xs + t0 * BN * QL_ROWB, QL_ROWB, 0);
-  load_chunk(st.rx[1], Xs + t0 * BN * QL_ROWB, QL_ROWB, CHUNK_BYTES);
+  load_chunk(st.rx[0], Xs + t0 * ts * BN * QL_ROWB, QL_ROWB, 0);
+  load_chunk(st.rx[1], Xs + t0 * ts * BN * QL_ROWB, QL_ROWB, CHUNK_BYTES);
 }
 
 template <typename T>
 __device__ __forceinline__ void ql_tile(f32x4 (&acc)[4][4], QlState& st,
                                         const char* __restrict__ Xs, int64_t t, int64_t t1,
-                                        char* lds, int wq, int wn, int lane) {
+                                        char* lds, int wq, int wn, int lane, int64_t ts = 1) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -247,7 +249,7 @@ __device__ __forceinline__ void ql_tile(f32x4 (&acc)[4][4], QlState& st,
     char* xa = lds + QL_Y_BYTES + c * TILE_LDS;
     store_chunk(st.rx[c], xa);
     __syncthreads();
-    if (t + 1 < t1) load_chunk(st.rx[c], Xs + (t + 1) * BN * QL_ROWB, QL_ROWB, c * CHUNK_BYTES);
+    if (t + 1 < t1) load_chunk(st.rx[c], Xs + (t + 1) * ts * BN * QL_ROWB, QL_ROWB, c * CHUNK_BYTES);
     __builtin_amdgcn_s_setprio(1);   // favour the wave issuing MFMAs
 #pragma unroll
     for (int kg = 0; kg < CHUNK_BYTES / KG_BYTES; ++kg) {
@@ -320,11 +322,11 @@ template <typename T, int NKG>
 __device__ __forceinline__ void yreg_tile(f32x4 (&acc)[4][4], XStream<NKG>& st,
                                           const u32x4 (&yf)[4][NKG], const char* __restrict__ Xs,
                                           int64_t ld_bytes, int64_t t, int64_t t1, char* lds,
-                                          int wn, int lane) {
+                                          int wn, int lane, int64_t ts = 1) {
   char* xa = lds + st.buf * XStream<NKG>::BUF;
   xs_store(st, xa);
   __syncthreads();
-  if (t + 1 < t1) xs_load(st, Xs + (t + 1) * BN * ld_bytes, ld_bytes);
+  if (t + 1 < t1) xs_load(st, Xs + (t + 1) * ts * BN * ld_bytes, ld_bytes);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll

@@ -22,6 +22,7 @@ struct TileProblem {
   int64_t np, qp;        // padded to multiples of 128
   int64_t qtiles, ntiles, splits;
   TileMap map;           // workgroup -> (query tile, split), see common.h
+  int64_t tstride;       // sweep tile t is data tile t * tstride (1 but for the seed pass)
 };
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
@@ -105,7 +106,7 @@ struct KnnBuffers {
   double* z1;            // [q] sum of kernel values over the neighbours
   float* thr2;           // [q] second-pass key threshold (>= 0 flagged)
   int32_t* flags;        // [qtiles] query tile needs a second pass
-  uint64_t* cand2;       // [q][cap2] second-pass candidates (index only)
+  uint64_t* cand2;       // [q][cap2] second-pass candidates: lower-bound key code << 32 | index
   int32_t* cand2_cnt;    // [q]
   int64_t cap2;
   int32_t* status;       // [q] 0 certified by the first pass, 1 second pass pending,
@@ -113,6 +114,7 @@ struct KnnBuffers {
                          // 4 done by the second pass, 5 done by the exhaustive scan
   const float* yerr;     // [qp]
   const uint32_t* xerr_max;
+  int64_t seed_stride;   // 16-bit candidate pass: every seed_stride-th data tile
 };
 
 // p: geometry of the selection scan, pc: of the second-pass collect (more splits)

@@ -397,40 +397,43 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
     }
   const char* yq = p.Ys + qt * BQ * p.ld_bytes;
   constexpr int NK = 2;   // k-groups of the register-resident engine
+  // sweep tile t is data tile t * ts: the seeds come from every ts-th tile
+  const int64_t ts = p.tstride;
   StreamState st;
   XStream<NK> xs;
   u32x4 yf[4][NK];
   QlState ql;
   if (t0 < t1) {
     if constexpr (ENG == 0) {
-      stream_start(st, yq, p.Xs, p.ld_bytes, t0);
+      stream_start(st, yq, p.Xs, p.ld_bytes, t0, ts);
     } else if constexpr (ENG == 1) {
-      ql_start(ql, yq, p.Xs, t0, lds);
+      ql_start(ql, yq, p.Xs, t0, lds, ts);
     } else {
       yreg_load<NK>(yf, yq, p.ld_bytes, wq, lane);
-      xs_load(xs, p.Xs + t0 * BN * p.ld_bytes, p.ld_bytes);
+      xs_load(xs, p.Xs + t0 * ts * BN * p.ld_bytes, p.ld_bytes);
       xs.buf = 0;
     }
   }
   __shared__ float xks[2][BN];   // data key norms, one tile ahead (see kde_tile_kernel)
-  float xk_reg = (threadIdx.x < BN && t0 < t1) ? p.xknorm[t0 * BN + threadIdx.x] : 0.f;
+  float xk_reg = (threadIdx.x < BN && t0 < t1) ? p.xknorm[t0 * ts * BN + threadIdx.x] : 0.f;
   for (int64_t t = t0; t < t1; ++t) {
     const int nb = (int)((t - t0) & 1);
     if (threadIdx.x < BN) {
       xks[nb][threadIdx.x] = xk_reg;
-      if (t + 1 < t1) xk_reg = p.xknorm[(t + 1) * BN + threadIdx.x];
+      if (t + 1 < t1) xk_reg = p.xknorm[(t + 1) * ts * BN + threadIdx.x];
     }
     f32x4 acc[4][4];
     if constexpr (ENG == 0)
-      stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane);
+      stream_tile<T>(acc, st, yq, p.Xs, p.ld_bytes, p.nchunks, t, t1, lds, wq, wn, lane, ts);
     else if constexpr (ENG == 1)
-      ql_tile<T>(acc, ql, p.Xs, t, t1, lds, wq, wn, lane);
+      ql_tile<T>(acc, ql, p.Xs, t, t1, lds, wq, wn, lane, ts);
     else
-      yreg_tile<T, NK>(acc, xs, yf, p.Xs, p.ld_bytes, t, t1, lds, wn, lane);
+      yreg_tile<T, NK>(acc, xs, yf, p.Xs, p.ld_bytes, t, t1, lds, wn, lane, ts);
+    const int64_t dt = t * ts;   // the data tile
     float xk[4];   // padding columns: a huge finite key (never NaN after packing)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
+      const int64_t col = dt * BN + wn * 64 + j * 16 + (lane & 15);
       xk[j] = col < p.n ? xks[nb][wn * 64 + j * 16 + (lane & 15)] : 3.0e38f;
     }
 #pragma unroll
@@ -446,7 +449,7 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
         }
         const bool better = m < best[i][r];
         best[i][r] = better ? m : best[i][r];
-        btile[i][r] = better ? (int32_t)t : btile[i][r];
+        btile[i][r] = better ? (int32_t)dt : btile[i][r];
       }
   }
 #pragma unroll
@@ -679,11 +682,12 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
     const int64_t row = qt * BQ + threadIdx.x;
     ths[threadIdx.x] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
   }
-  // Hits are staged per wave in LDS, (query row in the tile) << 32 | column,
-  // and appended to the global lists in bulk, so a wave waits for one round of
-  // global atomics per drain rather than one per tile with a hit.  The stage is
-  // private to its wave: no barrier is needed to fill, test or drain it.  A hit
-  // that finds the stage full goes straight to its query's list.
+  // Hits are staged per wave in LDS, (query row in the tile) << 57 | (key code
+  // >> 7) << 32 | column, and appended to the global lists in bulk, so a wave
+  // waits for one round of global atomics per drain rather than one per tile
+  // with a hit.  The stage is private to its wave: no barrier is needed to
+  // fill, test or drain it.  A hit that finds the stage full goes straight to
+  // its query's list.
   __shared__ uint64_t stage[WG / 64][COLLECT_STAGE];
   __shared__ int nst[WG / 64];
   if (lane == 0) nst[wave] = 0;
@@ -693,9 +697,10 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
     const int m = c < COLLECT_STAGE ? c : COLLECT_STAGE;
     for (int e = lane; e < m; e += 64) {
       const uint64_t v = stage[wave][e];
-      const int64_t row = qt * BQ + (int64_t)(v >> 32);
+      const int64_t row = qt * BQ + (int64_t)(v >> 57);
       const int slot = atomicAdd(&b.cand2_cnt[row], 1);
-      if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = v & 0xffffffffull;
+      if (slot < b.cap2)
+        b.cand2[row * b.cap2 + slot] = (((v >> 32) & 0x1ffffffull) << 39) | (v & 0xffffffffull);
     }
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) nst[wave] = 0;
@@ -768,12 +773,14 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
             const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
             const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]);
             if (col < p.n && key <= th) {
+              const uint32_t code = float_key(key);
               const int e = atomicAdd(&nst[wave], 1);
               if (e < COLLECT_STAGE)
-                stage[wave][e] = ((uint64_t)(row - qt * BQ) << 32) | (uint64_t)(uint32_t)col;
+                stage[wave][e] = ((uint64_t)(row - qt * BQ) << 57) | ((uint64_t)(code >> 7) << 32) |
+                                 (uint64_t)(uint32_t)col;
               else {   // stage full: straight to the list
                 const int slot = atomicAdd(&b.cand2_cnt[row], 1);
-                if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = (uint64_t)col;
+                if (slot < b.cap2) b.cand2[row * b.cap2 + slot] = ((uint64_t)code << 32) | (uint64_t)col;
               }
             }
           }
@@ -785,14 +792,21 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
   drain();
 }
 
+// Second-pass entries are (key code << 32 | row): the row's lower-bound key,
+// as float_key, rounded down (a valid lower bound still), and its index.
+// The refinement sorts them by key, evaluates the K1 smallest exactly, and
+// then only the entries that the k-th of those distances cannot exclude:
+// an entry whose key gives sqrt(key) - E - e_y above it is farther than d_k.
 __global__ void __launch_bounds__(WG)
 knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   uint64_t* dkey = reinterpret_cast<uint64_t*>(smem);                // SORT_CAP
   uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + SORT_CAP);      // SORT_CAP
-  uint32_t* tmp = didx + SORT_CAP;                                     // K_MAX
+  uint64_t* kd = reinterpret_cast<uint64_t*>(didx + SORT_CAP);        // K_MAX
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(kd + K_MAX);            // K_MAX
   double* red = reinterpret_cast<double*>(tmp + K_MAX);               // WG
   float* ys = reinterpret_cast<float*>(red + WG);                      // d
+  __shared__ int kept_s;
   const int64_t qi = blockIdx.x;
   if (b.status[qi] != 1) return;
   const int C = b.cand2_cnt[qi];
@@ -801,14 +815,22 @@ knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
     return;
   }
   for (int64_t t = threadIdx.x; t < a.d; t += WG) ys[t] = a.Y[qi * a.d + t];
+  if (threadIdx.x == 0) kept_s = 0;
+  // 1. the entries in key order
+  const int N = next_pow2(C > 1 ? C : 2);
+  for (int i = threadIdx.x; i < N; i += WG) dkey[i] = i < C ? b.cand2[qi * b.cap2 + i] : ~0ull;
   __syncthreads();
+  block_sort_u64(dkey, N);
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
-  for (int c0 = g; c0 < C; c0 += 4 * (WG / 16)) {
+  const int k = (int)a.k;
+  // 2. exact distances of the P smallest keys (kd, tmp), sorted: their k-th bounds d_k
+  const int P = C < (int)b.K1 ? C : (int)b.K1;
+  for (int c0 = g; c0 < P; c0 += 4 * (WG / 16)) {
     int64_t rr[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int c = c0 + i * (WG / 16);
-      rr[i] = c < C ? (int64_t)(uint32_t)b.cand2[qi * b.cap2 + c] : -1;
+      rr[i] = c < P ? (int64_t)(uint32_t)dkey[c] : -1;
     }
     double d2[4];
     group16_d2_4(a.X, rr, a.d, ys, l16, d2);
@@ -816,15 +838,53 @@ knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int c = c0 + i * (WG / 16);
-        if (c < C) { dkey[c] = __builtin_bit_cast(uint64_t, d2[i]); didx[c] = (uint32_t)rr[i]; }
+        if (c < P) { kd[c] = __builtin_bit_cast(uint64_t, d2[i]); tmp[c] = (uint32_t)rr[i]; }
       }
   }
-  const int N = next_pow2(C > 1 ? C : 2);
-  for (int i = C + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
+  const int NP = next_pow2(P > 1 ? P : 2);
+  for (int i = P + threadIdx.x; i < NP; i += WG) { kd[i] = ~0ull; tmp[i] = 0xffffffffu; }
   __syncthreads();
-  block_sort_pairs(dkey, didx, N);
-  const int k = (int)a.k;
-  fix_boundary(dkey, didx, C, k, a.X, a.d, ys);
+  block_sort_pairs(kd, tmp, NP);
+  // 3. entries [P, C) kept while their bound does not exclude them (keys
+  // ascend, so the kept ones are a prefix)
+  int cstar = C;
+  if (C > P && P >= k && k > 0) {
+    const double Dk = __builtin_bit_cast(double, kd[k - 1]) * (1.0 + fp64_rel(a.d));
+    const double E = (double)__builtin_bit_cast(float, *b.xerr_max);
+    const double ey = (double)b.yerr[qi];
+    int kept = 0;
+    for (int c = P + threadIdx.x; c < C; c += WG) {
+      const float key = key_float((uint32_t)(dkey[c] >> 32));
+      const double lhs = sqrt((double)fmaxf(key, 0.f)) - E - ey;
+      kept += !(lhs > 0.0 && lhs * lhs > Dk * (1.0 + 1e-14));
+    }
+    if (kept) atomicAdd(&kept_s, kept);
+    __syncthreads();
+    cstar = P + kept_s;
+  }
+  // 4. the P evaluated entries in front, then the exact distances of [P, cstar)
+  for (int c0 = P + g; c0 < cstar; c0 += 4 * (WG / 16)) {
+    int64_t rr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = c0 + i * (WG / 16);
+      rr[i] = c < cstar ? (int64_t)(uint32_t)dkey[c] : -1;
+    }
+    double d2[4];
+    group16_d2_4(a.X, rr, a.d, ys, l16, d2);
+    if (l16 == 0)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = c0 + i * (WG / 16);
+        if (c < cstar) { dkey[c] = __builtin_bit_cast(uint64_t, d2[i]); didx[c] = (uint32_t)rr[i]; }
+      }
+  }
+  for (int i = threadIdx.x; i < P; i += WG) { dkey[i] = kd[i]; didx[i] = tmp[i]; }
+  const int N2 = next_pow2(cstar > 1 ? cstar : 2);
+  for (int i = cstar + threadIdx.x; i < N2; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
+  __syncthreads();
+  block_sort_pairs(dkey, didx, N2);
+  fix_boundary(dkey, didx, cstar, k, a.X, a.d, ys);
   if (threadIdx.x == 0) b.status[qi] = 4;   // done by the second pass
   emit_neighbours(dkey, didx, tmp, k, a.h, a.kern, b.nn_work + qi * k,
                   nn_out ? nn_out + qi * k : nullptr, b.z1 + qi, red);
@@ -1025,6 +1085,14 @@ static hipError_t launch_tiles_prec(int prec, const TileProblem& p, const KnnBuf
   }
 }
 
+// Tile stride of the 16-bit candidate pass: the requested one, unless that
+// leaves fewer than 16 seed tiles.
+static int64_t seed_stride(int64_t ntiles, int64_t want) {
+  if (want < 1) return 1;
+  const int64_t most = ntiles / 16;
+  return want < most ? want : (most > 1 ? most : 1);
+}
+
 hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, const KnnBuffers& b,
                       const float* X, const float* Y, int64_t d, int64_t k, double h, int kern,
                       int32_t* nn_out, hipStream_t s) {
@@ -1036,21 +1104,27 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
   KnnBuffers bb = b;
   RefineArgs a{X, Y, p.n, p.q, d, k, p.qp, p.splits, h, kern, 0};
   if (approx) {
-    // 16-bit scans: cheap cell candidates, then the certified second pass
-    const dim3 g((unsigned)pc.map.grid), blk(WG);
-    const int eng = tile_engine<__bf16>(pc.ld_bytes);
+    // 16-bit scans: cheap cell candidates from every ts-th data tile (at least
+    // 16 of them), then the certified second pass over all tiles
+    TileProblem ps = pc;
+    ps.tstride = seed_stride(pc.ntiles, b.seed_stride);
+    ps.ntiles = (pc.ntiles + ps.tstride - 1) / ps.tstride;
+    ps.splits = pc.splits < ps.ntiles ? pc.splits : ps.ntiles;
+    ps.map = make_tile_map(ps.qtiles, ps.splits, pc.map.group);
+    const dim3 g((unsigned)ps.map.grid), blk(WG);
+    const int eng = tile_engine<__bf16>(ps.ld_bytes);
     if (prec == PREC_BF16) {
-      if (eng == 2) knn_cand_kernel<__bf16, 2><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
-      else if (eng == 1) knn_cand_kernel<__bf16, 1><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
-      else knn_cand_kernel<__bf16, 0><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
+      if (eng == 2) knn_cand_kernel<__bf16, 2><<<g, blk, 0, s>>>(ps, b.cand, b.cand_cnt);
+      else if (eng == 1) knn_cand_kernel<__bf16, 1><<<g, blk, 0, s>>>(ps, b.cand, b.cand_cnt);
+      else knn_cand_kernel<__bf16, 0><<<g, blk, 0, s>>>(ps, b.cand, b.cand_cnt);
     } else {
-      if (eng == 2) knn_cand_kernel<_Float16, 2><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
-      else if (eng == 1) knn_cand_kernel<_Float16, 1><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
-      else knn_cand_kernel<_Float16, 0><<<g, blk, 0, s>>>(pc, b.cand, b.cand_cnt);
+      if (eng == 2) knn_cand_kernel<_Float16, 2><<<g, blk, 0, s>>>(ps, b.cand, b.cand_cnt);
+      else if (eng == 1) knn_cand_kernel<_Float16, 1><<<g, blk, 0, s>>>(ps, b.cand, b.cand_cnt);
+      else knn_cand_kernel<_Float16, 0><<<g, blk, 0, s>>>(ps, b.cand, b.cand_cnt);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     bb.cap1 = CELLS;
-    a.splits = pc.splits;
+    a.splits = ps.splits;
     a.approx = 1;
   } else {
     e = launch_tiles_prec(prec, p, b, false, s);
@@ -1061,7 +1135,7 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
   if ((e = hipGetLastError()) != hipSuccess) return e;
   e = launch_tiles_prec(prec, pc, b, true, s);
   if (e != hipSuccess) return e;
-  const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + d * 4;
+  const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * (8 + 4) + WG * 8 + d * 4;
   knn_refine2_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, bb, nn_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   knn_exhaustive_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, bb, nn_out);
@@ -1360,7 +1434,8 @@ ivf_collect_kernel(IvfTiles v, KnnBuffers b) {
             if (id >= 0) {
               const int32_t qi = qry[ql];
               const int slot = atomicAdd(&b.cand2_cnt[qi], 1);
-              if (slot < b.cap2) b.cand2[(int64_t)qi * b.cap2 + slot] = (uint64_t)id;
+              if (slot < b.cap2)
+                b.cand2[(int64_t)qi * b.cap2 + slot] = ((uint64_t)float_key(key) << 32) | (uint64_t)(uint32_t)id;
             }
           }
         }
@@ -1506,7 +1581,7 @@ hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers&
   if ((e = hipGetLastError()) != hipSuccess) return e;
   ivf_collect_kernel<<<g, blk, 0, s>>>(t, b);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t smr = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + d * 4;
+  const size_t smr = SORT_CAP * (8 + 4) + K_MAX * (8 + 4) + WG * 8 + d * 4;
   knn_refine2_kernel<<<dim3((unsigned)q), dim3(WG), smr, s>>>(a, b, nn_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + ((d + 3) & ~3ll) * 4 +

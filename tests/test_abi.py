@@ -172,8 +172,8 @@ def test_kde_hybrid_given_neighbours_lift_the_knn_limits(lib):
 def test_options_roundtrip_and_validation(lib):
     d = _lib.Options()
     lib.deann_default_options(d)
-    assert (d.rel_tol, d.value_floor, d.knn_slack, d.knn_cap2, d.center) == (1e-5, 1e-16, 16,
-                                                                               4096, 1)
+    assert (d.rel_tol, d.value_floor, d.knn_slack, d.knn_cap2, d.center,
+            d.knn_seed_stride) == (1e-5, 1e-16, 16, 4096, 1, 4)
     got = _lib.Options()
     assert lib.deann_get_options(got) == _lib.OK
     assert got.rel_tol == d.rel_tol and got.knn_cap2 == d.knn_cap2
@@ -186,7 +186,8 @@ def test_options_roundtrip_and_validation(lib):
         assert (got.knn_cap2, got.center, got.rel_tol) == (8, 0, 1e-3)
         for field, bad in (("rel_tol", 0.0), ("rel_tol", 2.0), ("value_floor", -1.0),
                            ("value_floor", float("inf")), ("knn_slack", -1), ("knn_slack", 513),
-                           ("knn_cap2", 0), ("knn_cap2", 4097), ("center", 2), ("reserved", 1)):
+                           ("knn_cap2", 0), ("knn_cap2", 4097), ("center", 2),
+                           ("knn_seed_stride", 0), ("knn_seed_stride", 65)):
             o = _lib.Options()
             lib.deann_default_options(o)
             setattr(o, field, bad)

@@ -164,7 +164,7 @@ def test_options_do_not_change_results(c1, options):
     h = bandwidth(WL, "gaussian")
     base = [t.cpu().numpy() for t in dk.deann_query(Xd, Yd, h, 20, 50, seed=1, precision="bf16")]
     mu0 = dk.kde_exact(Xd, Yd, h, "gaussian", "fp32").cpu().numpy()
-    for kw in (dict(knn_slack=100), dict(knn_cap2=16), dict(center=0)):
+    for kw in (dict(knn_slack=100), dict(knn_cap2=16), dict(center=0), dict(knn_seed_stride=1)):
         dk.set_options(**kw)
         got = [t.cpu().numpy() for t in dk.deann_query(Xd, Yd, h, 20, 50, seed=1,
                                                         precision="bf16")]
@@ -173,6 +173,35 @@ def test_options_do_not_change_results(c1, options):
         mu = dk.kde_exact(Xd, Yd, h, "gaussian", "fp32").cpu().numpy()
         assert np.all(np.abs(mu - mu0) <= 2e-5 * mu0), kw
         dk.set_options(**dk.default_options())
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_knn_seed_stride(options, prec):
+    # the 16-bit candidate pass reads every ts-th data tile (782 tiles here, so
+    # ts up to 48); the seeds only bound the second pass: the neighbours, draws
+    # and estimates are the same for every stride, and the oracle's
+    dk = options
+    spec, X, Y = synth.workload(WL, n=100_000, q=200)
+    dev = device()
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h, k, m = bandwidth(WL, "gaussian"), 40, 60
+    outs = {}
+    for ts in (1, 4, 48):
+        dk.set_options(knn_seed_stride=ts)
+        outs[ts] = [t.cpu().numpy() for t in dk.deann_query(Xd, Yd, h, k, m, seed=2,
+                                                             precision=prec)]
+        st = dk.last_stats(dev)
+        print(f"{prec} seed stride {ts}: exhaustive {st['knn_exhaustive']} of 200")
+    for ts in (4, 48):
+        for a, b in zip(outs[ts], outs[1]):
+            assert np.array_equal(a, b), ts
+    out, nn, sm = outs[48]
+    for j in synth.query_subset(Y.shape[0], 12, seed=4):
+        j = int(j)
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, GAUSSIAN, k, m, 2, j)
+        assert np.array_equal(nn[j], nn_ref), j
+        assert np.array_equal(sm[j], s_ref), j
+        assert abs(out[j] - est) <= 1e-12 * est
 
 
 def test_backward_rejects_bad_index_tensors(c1):

@@ -3,15 +3,16 @@
 One step = the whole hot path over one batch of queries:
   exact KDE (float32 MFMA tiles, certified per query)      kde_exact
     (d <= 128: with its gradient in one pass, d/dy, d/dh)   kde_exact_with_grad
-  DEANN estimate with the BF16 scan + FP64 refinement      deann_query
-  DEANN adjoint (d/dy, d/dh)                               deann_query_backward
+  DEANN estimate with the BF16 scan + FP64 refinement,     deann_query_with_grad
+    and its d/dy, d/dh from the same gather of the k + m rows
 The headline workload is the large high-dimensional one: the 200-cluster
 mixture with non-negative entries, n = 1,000,000, d = 960, q = 10,000,
 Gaussian kernel, k = 200, m = 2,000; the 100-cluster mixture with n =
 1,000,000, d = 128, q = 10,000 (k = 100, m = 1,000) follows as a secondary
 block.  Inputs are resident in HBM before the timed region.  Also measured,
-outside the step: the DEANN with the FP32 scan (the metric's comparison: same
-indices and estimates as BF16+refine), the exact KDE alone (its own roofline),
+outside the step: the DEANN estimate alone with the BF16 scan and with the FP32
+scan (the metric's comparison: same indices and estimates), the DEANN adjoint
+alone (deann_query_backward), the exact KDE alone (its own roofline),
 permuted-sampling and inverted-file DEANN, the BF16 exact KDE and the near/far
 form.  Prints one JSON line.
 
@@ -219,21 +220,20 @@ def run_workload(args, workload, with_cpu):
     # exact KDE and its gradient from one pass over the distance tiles (the
     # fused entry point supports d <= 128; above, the step has the KDE only)
     fused = d <= 128
-    comp = {"exact_kde_and_grad_fp32" if fused else "exact_kde_fp32": [], "deann_bf16": [],
-            "deann_backward": []}
+    comp = {"exact_kde_and_grad_fp32" if fused else "exact_kde_fp32": [],
+            "deann_bf16_with_grad": []}
 
     def step(record):
-        e = [ev() for _ in range(4)]
+        e = [ev() for _ in range(3)]
         e[0].record()
         if fused:
             mu, gye, ghe = dk.kde_exact_with_grad(Xd, Yd, h, KERNEL)
         else:
             mu, gye, ghe = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32"), None, None
         e[1].record()
-        est, nn, sm = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16")
+        est, gy, gh, nn, sm = dk.deann_query_with_grad(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
+                                                       precision="bf16")
         e[2].record()
-        gy, gh = dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn, sm, gout, KERNEL)
-        e[3].record()
         if record is not None:
             record.append(e)
         return mu, est, nn, sm, gy, gh, gye, ghe
@@ -282,6 +282,30 @@ def run_workload(args, workload, with_cpu):
                 "exact_kde_tile_ms": tile_avg,
                 "step_tile_ms": float(np.mean(step_tile_ms)) if step_tile_ms else None,
                 "queries_per_s": {"step": q / (ms_step * 1e-3)}}
+
+    # the DEANN estimate alone (BF16 scan + refinement) and its adjoint alone
+    for _ in range(max(1, args.warmup)):
+        est16, nn16, sm16 = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
+                                           precision="bf16")
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        est16, nn16, sm16 = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
+                                           precision="bf16")
+    b.record()
+    torch.cuda.synchronize()
+    ms_deann16 = a.elapsed_time(b) / reps
+    same_as_step = bool(torch.equal(nn16, nn) and torch.equal(sm16, sm))
+    step_vs_alone = float(((est - est16).abs() / est16).max())
+    dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn16, sm16, gout, KERNEL)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        gy16, _ = dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn16, sm16, gout, KERNEL)
+    b.record()
+    torch.cuda.synchronize()
+    ms_bwd = a.elapsed_time(b) / reps
+    same_grad_as_step = bool(torch.equal(gy16, gy))
 
     # FP32-scan DEANN for the BF16+refine vs FP32 comparison (same seed)
     for _ in range(max(1, args.warmup)):
@@ -379,16 +403,12 @@ def run_workload(args, workload, with_cpu):
         # the whole step with the split exact part (same work, same outputs)
         for _ in range(max(1, args.warmup)):
             dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")
-            _, nn_s, sm_s = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
-                                           precision="bf16")
-            dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn_s, sm_s, gout, KERNEL)
+            dk.deann_query_with_grad(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16")
         torch.cuda.synchronize()
         t0s = time.perf_counter()
         for _ in range(args.steps):
             dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")
-            _, nn_s, sm_s = dk.deann_query(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
-                                           precision="bf16")
-            dk.deann_query_backward(Xd, Yd, h, K_NN, M_SAMPLES, nn_s, sm_s, gout, KERNEL)
+            dk.deann_query_with_grad(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16")
         torch.cuda.synchronize()
         ms_step_split = (time.perf_counter() - t0s) * 1e3 / args.steps
 
@@ -441,10 +461,11 @@ def run_workload(args, workload, with_cpu):
     mu_fwd_h = mu_fwd.cpu().numpy()
     mu16_h = mu16.cpu().numpy()
     muh_h, muhn_h = muh.cpu().numpy(), muhn.cpu().numpy()
-    est_h, est32_h = est.cpu().numpy(), est32.cpu().numpy()
-    same_idx = bool(torch.equal(nn, nn32) and torch.equal(sm, sm32))
+    est_h, est16_h, est32_h = est.cpu().numpy(), est16.cpu().numpy(), est32.cpu().numpy()
+    same_idx = bool(torch.equal(nn16, nn32) and torch.equal(sm16, sm32))
     keep = mu_h >= 1e-16
-    rel_bf16_vs_fp32 = float(np.max(np.abs(est_h - est32_h)[keep] / est32_h[keep])) if keep.any() else 0.0
+    rel_bf16_vs_fp32 = (float(np.max(np.abs(est16_h - est32_h)[keep] / est32_h[keep]))
+                        if keep.any() else 0.0)
     rel_deann_vs_exact = np.abs(est_h[keep] - mu_h[keep]) / mu_h[keep]
     rel_exact16 = np.abs(mu16_h[keep] - mu_h[keep]) / mu_h[keep]
     rel_hyb = np.abs(muh_h[keep] - mu_h[keep]) / mu_h[keep]
@@ -492,7 +513,8 @@ def run_workload(args, workload, with_cpu):
         "components_ms": comp_ms,
         "queries_per_s": {
             "step": q / (ms_step * 1e-3),
-            "deann_bf16_refine": q / (comp_ms["deann_bf16"] * 1e-3),
+            "deann_bf16_refine": q / (ms_deann16 * 1e-3),
+            "deann_bf16_with_grad": q / (comp_ms["deann_bf16_with_grad"] * 1e-3),
             "deann_fp32": q / (ms_deann32 * 1e-3),
             "deann_permuted_bf16_refine": q / (ms_deannp * 1e-3),
             "deann_permuted_index_bf16_refine": q / (ms_deannp_idx * 1e-3),
@@ -506,11 +528,14 @@ def run_workload(args, workload, with_cpu):
             "kde_exact_fp32_split": q / (ms_split * 1e-3) if ms_split else None,
             "exact_kde_and_grad_fp32_split": (q / (ms_split_grad * 1e-3)
                                               if ms_split_grad else None),
-            "deann_backward": q / (comp_ms["deann_backward"] * 1e-3),
+            "deann_backward": q / (ms_bwd * 1e-3),
         },
         "accuracy": {
             "deann_bf16_vs_fp32_same_indices": same_idx,
             "deann_bf16_vs_fp32_max_rel": rel_bf16_vs_fp32,
+            "deann_with_grad_same_indices_as_deann_query": same_as_step,
+            "deann_with_grad_vs_deann_query_max_rel": step_vs_alone,
+            "deann_with_grad_same_gradient_as_backward": same_grad_as_step,
             "exact_bf16_vs_fp32_mean_rel": float(rel_exact16.mean()) if keep.any() else None,
             "exact_bf16_vs_fp32_max_rel": float(rel_exact16.max()) if keep.any() else None,
             "hybrid_bf16_vs_fp32_mean_rel": float(rel_hyb.mean()) if keep.any() else None,
@@ -561,7 +586,7 @@ def run_workload(args, workload, with_cpu):
     if with_cpu:
         # about 20 s of oracle work: one query costs about 3 n d FP64 element
         # operations per pass (exact KDE, k-NN) at roughly 4e8 per second
-        size = args.cpu_sample or max(2, min(16, int(20.0 / (6.0 * n * d / 4e8))))
+        size = args.cpu_sample or max(2, min(16, int(20.0 / (3e-9 * n * d))))   # ~20 s
         out["cpu_baseline"], out["parity_sample"] = cpu_baseline(
             X, Y, h, size, mu_h, est_h, nn.cpu().numpy(), sm.cpu().numpy(),
             gy.cpu().numpy(), K_NN, M_SAMPLES, fused,

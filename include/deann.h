@@ -153,6 +153,29 @@ deann_status deann_query(const float* X, int64_t n, const float* Y, int64_t q, i
                 void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * DEANN estimates with their derivatives (Algorithm 1 and its adjoint with the
+ * index sets held fixed, as deann_query_backward): the same neighbours, draws
+ * and sample_idx as deann_query with the same arguments, and
+ *   out[j]      the estimate, as deann_query up to the order of its FP64 sum
+ *               (about 1e-16 relative)                        [q] float64
+ *   grad_Y[j]   d out[j] / d y_j                               [q, d] float32, or NULL
+ *   grad_h[j]   d out[j] / d h                                 [q] float64, or NULL
+ * i.e. deann_query followed by deann_query_backward with grad_out = 1, except
+ * that the h derivative is returned per query; the k + m rows of a query are
+ * gathered once for all three (d % 4 == 0, 16-byte aligned X and Y, d <= 2048;
+ * other shapes gather twice, with the same results).  nn_idx, sample_idx may
+ * be NULL.  Requirements: as deann_query, plus d <= 2048.
+ * ------------------------------------------------------------------------- */
+size_t deann_query_with_grad_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
+                                       deann_precision precision);
+deann_status deann_query_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                                   double h, deann_kernel kernel, int64_t k, int64_t m,
+                                   uint64_t seed, uint64_t query_offset, uint64_t word2,
+                                   deann_precision precision, double* out, float* grad_Y,
+                                   double* grad_h, int32_t* nn_idx, int32_t* sample_idx, void* ws,
+                                   size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * DEANN with permuted random sampling (DEANNP; App. G, Algorithm 2): as
  * deann_query, but the sample of query i is the block of the data's permuted
  * order that starts at the running index l_i = (start + i m) mod n, with the

@@ -21,6 +21,7 @@ FP32, BF16, FP16, FP32_SPLIT = 0, 1, 2, 3
 EXPORTS = (
     "kde_exact_workspace", "kde_exact",
     "deann_query_workspace", "deann_query",
+    "deann_query_with_grad_workspace", "deann_query_with_grad",
     "deann_query_permuted_workspace", "deann_query_permuted",
     "deann_perm_index_bytes", "deann_perm_index_create", "deann_query_permuted_index",
     "deann_query_backward_workspace", "deann_query_backward", "deann_query_backward_noalloc",
@@ -81,6 +82,12 @@ def load(path: str = LIB_PATH):
     lib.deann_query.restype = _int
     lib.deann_query.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64, _u64, _u64,
                                 _u64, _int, _vp, _vp, _vp, _vp, _sz, _vp]
+    lib.deann_query_with_grad_workspace.restype = _sz
+    lib.deann_query_with_grad_workspace.argtypes = [_i64, _i64, _i64, _i64, _i64, _int]
+    lib.deann_query_with_grad.restype = _int
+    lib.deann_query_with_grad.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64,
+                                          _u64, _u64, _u64, _int, _vp, _vp, _vp, _vp, _vp, _vp,
+                                          _sz, _vp]
     lib.deann_query_permuted_workspace.restype = _sz
     lib.deann_query_permuted_workspace.argtypes = [_i64, _i64, _i64, _i64, _i64, _int]
     lib.deann_query_permuted.restype = _int

@@ -88,6 +88,33 @@ def deann_query(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int, kern
     return out, nn, sm
 
 
+def deann_query_with_grad(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int,
+                          kernel="gaussian", seed: int = 0, query_offset: int = 0, word2: int = 0,
+                          precision="fp32", need_grad_y: bool = True, need_grad_h: bool = True,
+                          return_indices: bool = True):
+    """DEANN estimates with their gradients from one gather of each query's rows:
+    (out float64 [q], grad_Y float32 [q,d] = d out_j / d y_j or None, grad_h
+    float64 [q] = d out_j / d h or None, nn_idx int32 [q,k], sample_idx int32
+    [q,m]); the same neighbours and draws as deann_query."""
+    _check_xy(X, Y)
+    lib = _lib.load()
+    n, d = X.shape
+    q = Y.shape[0]
+    p = precision_id(precision)
+    dev = X.device
+    out = torch.empty(q, dtype=torch.float64, device=dev)
+    gy = torch.empty((q, d), dtype=torch.float32, device=dev) if need_grad_y else None
+    gh = torch.empty(q, dtype=torch.float64, device=dev) if need_grad_h else None
+    nn = torch.empty((q, k), dtype=torch.int32, device=dev) if return_indices else None
+    sm = torch.empty((q, m), dtype=torch.int32, device=dev) if return_indices else None
+    ws = _workspace(lib.deann_query_with_grad_workspace(n, q, d, k, m, p), dev)
+    _lib.check(lib.deann_query_with_grad(
+        X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), int(k), int(m),
+        int(seed), int(query_offset), int(word2), p, out.data_ptr(), _ptr(gy), _ptr(gh), _ptr(nn),
+        _ptr(sm), ws.data_ptr(), ws.numel(), _stream(dev)))
+    return out, gy, gh, nn, sm
+
+
 def kde_hybrid(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, kernel="gaussian",
                precision="bf16", nn_idx: torch.Tensor | None = None,
                return_indices: bool = False):

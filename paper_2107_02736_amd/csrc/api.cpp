@@ -382,6 +382,28 @@ HybPlan plan_hybrid(void* ws, int64_t n, int64_t q, int64_t d, int64_t k, int pr
 
 bool bad_hyb_prec(int p) { return p != DEANN_BF16 && p != DEANN_FP16; }
 
+// DEANN with the gradient of every estimate: the k-NN plan, then the
+// per-query d/dh terms and room for the draws (used when the caller passes no
+// sample_idx and the shape takes the sampler followed by the adjoint).
+struct DeannGradPlan {
+  DeannPlan dn;
+  double* gh_part;
+  int32_t* samp;
+  int64_t bytes;
+};
+
+DeannGradPlan plan_deann_grad(void* ws, int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
+                              int prec) {
+  DeannGradPlan G{};
+  G.dn = plan_deann(ws, n, q, d, k, prec);
+  const int64_t head = round_up(G.dn.bytes, kAlign);
+  Carve cv(ws ? static_cast<char*>(ws) + head : nullptr);
+  G.gh_part = cv.take<double>(q > 0 ? q : 1);
+  G.samp = cv.take<int32_t>(q * m > 0 ? q * m : 1);
+  G.bytes = head + cv.off + kAlign;
+  return G;
+}
+
 struct KdeBwdPlan {
   Prep prep;
   double* gy_part;
@@ -604,12 +626,19 @@ static PermIndex carve_perm_index(void* index, int64_t n) {
   return p;
 }
 
+// grad (deann_query_with_grad only): also d out_j / d y_j into grad->Y and
+// d out_j / d h into grad->h[j] (each may be NULL), plain sampling.
+struct DeannGradOut {
+  float* Y;
+  double* h;
+};
+
 static deann_status deann_query_impl(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
                             double h, int kernel, int64_t k, int64_t m, uint64_t seed,
                             uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
                             int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
                             void* ws, size_t ws_bytes, void* stream,
-                            const PermIndex* pidx = nullptr) {
+                            const PermIndex* pidx = nullptr, const DeannGradOut* grad = nullptr) {
   deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_prec(precision)) return fail(DEANN_EINVAL, "unknown precision %d", precision);
@@ -622,15 +651,20 @@ static deann_status deann_query_impl(const float* X, int64_t n, const float* Y, 
     return fail(DEANN_EUNSUPPORTED, "k + knn_slack = %lld exceeds the 512 candidates of a list",
                 (long long)(k + g_opt.knn_slack));
   if (d > 4096) return fail(DEANN_EUNSUPPORTED, "d > 4096 is not supported by deann_query");
+  if (grad && d > 2048)
+    return fail(DEANN_EUNSUPPORTED, "d > 2048 is not supported by the gradient");
   if (permuted && k < n && m > n - k)
     return fail(DEANN_EINVAL, "permuted sampling needs m <= n - k (got m = %lld)", (long long)m);
   if (q == 0) return DEANN_OK;
   if (!out) return fail(DEANN_EINVAL, "out is NULL");
-  const int64_t need = plan_deann(nullptr, n, q, d, k, precision).bytes;
+  const int64_t need = grad ? plan_deann_grad(nullptr, n, q, d, k, m, precision).bytes
+                            : plan_deann(nullptr, n, q, d, k, precision).bytes;
   if (!ws || (int64_t)ws_bytes < need)
     return fail(DEANN_EWORKSPACE, "workspace of %lld bytes needed", (long long)need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  DeannPlan P = plan_deann(align_ws(ws), n, q, d, k, precision);
+  const DeannGradPlan G = grad ? plan_deann_grad(align_ws(ws), n, q, d, k, m, precision)
+                               : DeannGradPlan{};
+  DeannPlan P = grad ? G.dn : plan_deann(align_ws(ws), n, q, d, k, precision);
   P.kb.nn_work = nn_idx ? nn_idx : P.nn_internal;
   record_last(nullptr, (k > 0 && k < n) ? P.kb.status : nullptr, q);
   hipError_t e;
@@ -644,6 +678,13 @@ static deann_status deann_query_impl(const float* X, int64_t n, const float* Y, 
     TileProblem tc = make_problem(P.prep, n, q, precision, kCollectSplitTarget);
     e = launch_knn(precision, tp, tc, P.kb, X, Y, d, k, h, kernel, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "knn");
+  }
+  if (grad) {
+    e = launch_deann_value_grad(X, Y, n, q, d, h, kernel, k, m, seed, query_offset, word2,
+                                P.kb.nn_work, P.kb.z1, out, sample_idx ? sample_idx : G.samp,
+                                grad->Y, grad->h ? grad->h : G.gh_part, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "value and gradient");
+    return DEANN_OK;
   }
   e = launch_sample(X, Y, n, q, d, h, kernel, k, m, seed, query_offset, word2, permuted, start,
                     P.kb.nn_work, P.kb.z1, out, sample_idx, s, pidx);
@@ -659,6 +700,23 @@ deann_status deann_query(const float* X, int64_t n, const float* Y, int64_t q, i
                 void* ws, size_t ws_bytes, void* stream) {
   return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, query_offset, word2, 0, 0,
                           precision, out, nn_idx, sample_idx, ws, ws_bytes, stream);
+}
+
+size_t deann_query_with_grad_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
+                                       deann_precision precision) {
+  if (n < 1 || d < 1 || q < 0 || k < 0 || k > n || m < 0 || bad_prec(precision)) return 0;
+  return (size_t)plan_deann_grad(nullptr, n, q, d, k, m, precision).bytes;
+}
+
+deann_status deann_query_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d,
+                                   double h, deann_kernel kernel, int64_t k, int64_t m,
+                                   uint64_t seed, uint64_t query_offset, uint64_t word2,
+                                   deann_precision precision, double* out, float* grad_Y,
+                                   double* grad_h, int32_t* nn_idx, int32_t* sample_idx, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  const DeannGradOut g{grad_Y, grad_h};
+  return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, query_offset, word2, 0, 0,
+                          precision, out, nn_idx, sample_idx, ws, ws_bytes, stream, nullptr, &g);
 }
 
 size_t deann_query_permuted_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,

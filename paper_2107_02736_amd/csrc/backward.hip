@@ -14,6 +14,7 @@
 // of a second MFMA product G = W X~ (k dimension = data rows).  Then
 // dKDE/dy = (G - y~ rowsum(W)) / n in the centred coordinates.
 #include "cert.h"
+#include "philox.h"
 
 namespace deann {
 
@@ -95,7 +96,7 @@ deann_backward_kernel(const float* __restrict__ X, const float* __restrict__ Y, 
       for (int jj = 0; jj < cnt; ++jj) hsum += hh[jj];
     __syncthreads();
   }
-  const double go = grad_out[qi];
+  const double go = grad_out ? grad_out[qi] : 1.0;
   const double scale = go / (double)n;
   if (grad_Y) {
 #pragma unroll
@@ -114,19 +115,31 @@ deann_backward_kernel(const float* __restrict__ X, const float* __restrict__ Y, 
 // partials are summed in a fixed order.  The rows of each group are taken in
 // the same order as before (row g, g + NG, ... of the query's neighbours then
 // draws), so the sums do not change.
+//
+// DRAW: the fused value-and-gradient pass of DEANN.  The draws are made here
+// (the sampler's rows, bit for bit: see philox.h) instead of read from samp,
+// and the estimate itself, (1/n) sum of c K over the same rows, is written
+// to dr.out beside d out / d y (grad_out NULL: a unit upstream gradient).
 constexpr int BWD_IDX = 2048;   // row indices staged in LDS per chunk
-template <int U, int GW>
+struct DrawArgs {
+  uint64_t seed, query_offset, word2;
+  int32_t* sample_idx;   // [q][m] or NULL
+  double* out;           // [q]
+};
+template <int U, int GW, bool DRAW>
 __global__ void __launch_bounds__(WG)
 deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
                           int64_t d, double h, int kern, int64_t k, int64_t m,
                           const int32_t* __restrict__ nn, const int32_t* __restrict__ samp,
                           const double* __restrict__ grad_out, float* __restrict__ grad_Y,
-                          double* __restrict__ gh_part) {
+                          double* __restrict__ gh_part, DrawArgs dr) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int NG = WG / GW;   // groups (rows in flight) per workgroup
   double* part = reinterpret_cast<double*>(smem);   // [NG][d]
   double* hpart = part + NG * d;                    // [NG]
-  int32_t* rid = reinterpret_cast<int32_t*>(hpart + NG);   // [BWD_IDX] row indices
+  double* vpart = hpart + NG;                       // [NG] (DRAW)
+  int32_t* rid = reinterpret_cast<int32_t*>(vpart + NG);   // [BWD_IDX] row indices
+  int32_t* gaps = rid + BWD_IDX;                    // [k] (DRAW)
   const int64_t qi = blockIdx.x;
   const int g = threadIdx.x / GW, lg = threadIdx.x % GW;
   const int64_t size2 = n - k;
@@ -145,7 +158,13 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
       yv[u][c] = t < d ? Y[qi * d + t] : 0.f;
       acc[u][c] = 0.0;
     }
-  double hs = 0.0;
+  double hs = 0.0, vs = 0.0;
+  if constexpr (DRAW) {
+    if (ms > 0)
+      for (int64_t t = threadIdx.x; t < k; t += WG) gaps[t] = nn[qi * k + t] - (int32_t)t;
+    if (dr.sample_idx && ms == 0)
+      for (int64_t j = threadIdx.x; j < m; j += WG) dr.sample_idx[qi * m + j] = -1;
+  }
   auto load_row = [&](int32_t row, float (&dst)[U][4]) {
     const float* xr = X + (int64_t)row * d;
 #pragma unroll
@@ -169,10 +188,29 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
   float xv[U][4], xa[U][4], xb[U][4];
   for (int64_t c0 = 0; c0 < R; c0 += BWD_IDX) {
     const int cnt = (int)(R - c0 < BWD_IDX ? R - c0 : BWD_IDX);
-    __syncthreads();   // the previous chunk's indices have been read
-    for (int i = threadIdx.x; i < cnt; i += WG) {
-      const int64_t j = c0 + i;
-      rid[i] = j < k ? nn[qi * k + j] : samp[qi * m + (j - k)];
+    __syncthreads();   // the previous chunk's indices have been read (and gaps written)
+    if constexpr (DRAW) {
+      for (int i = threadIdx.x; i < cnt && c0 + i < k; i += WG) rid[i] = nn[qi * k + c0 + i];
+      // draws [j_lo, j_hi) of this chunk, one Philox block (4 draws) per thread
+      const int64_t j_lo = (c0 > k ? c0 : k) - k, j_hi = c0 + cnt - k;
+      const uint64_t stream = dr.query_offset + (uint64_t)qi;
+      for (int64_t jb = j_lo / 4 + threadIdx.x; jb * 4 < j_hi; jb += WG) {
+        const Philox4x64 blk = philox4x64_10(dr.seed, 0, (uint64_t)jb, stream, dr.word2, 0);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int64_t jd = jb * 4 + w;
+          if (jd >= j_lo && jd < j_hi) {
+            const int32_t row = (int32_t)draw_row(blk.v[w], (uint64_t)size2, gaps, k);
+            rid[jd + k - c0] = row;
+            if (dr.sample_idx) dr.sample_idx[qi * m + jd] = row;
+          }
+        }
+      }
+    } else {
+      for (int i = threadIdx.x; i < cnt; i += WG) {
+        const int64_t j = c0 + i;
+        rid[i] = j < k ? nn[qi * k + j] : samp[qi * m + (j - k)];
+      }
     }
     __syncthreads();
     if (g < cnt) load_row(rid[g], xv);
@@ -194,19 +232,20 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
 #pragma unroll
       for (int off = 1; off < GW; off <<= 1) s += __shfl_xor(s, off, 64);
       const double c = c0 + i < k ? 1.0 : csamp;
-      double w, dh;
+      double w, dh, K;
       if (kern == KERNEL_GAUSSIAN) {
-        const double K = exp(-0.5 * s * inv_h2);
+        K = exp(-0.5 * s * inv_h2);
         w = K * inv_h2;
         dh = K * s * inv_h2 / h;
       } else {
         const double r = sqrt(s);
-        const double K = exp(-r / h);
+        K = exp(-r / h);
         w = r > 0.0 ? K / (h * r) : 0.0;
         dh = K * r * inv_h2;
       }
       w *= c;
       hs += c * dh;
+      if constexpr (DRAW) vs += c * K;
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -228,9 +267,12 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
       const int64_t t = 4 * lg + 4 * GW * u + c;
       if (t < d) part[g * d + t] = acc[u][c];
     }
-  if (lg == 0) hpart[g] = hs;
+  if (lg == 0) {
+    hpart[g] = hs;
+    if constexpr (DRAW) vpart[g] = vs;
+  }
   __syncthreads();
-  const double scale = grad_out[qi] / (double)n;
+  const double scale = (grad_out ? grad_out[qi] : 1.0) / (double)n;
   if (grad_Y)
     for (int64_t t = threadIdx.x; t < d; t += WG) {
       double v = 0.0;
@@ -242,6 +284,12 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
     for (int gg = 0; gg < NG; ++gg) v += hpart[gg];
     gh_part[qi] = scale * v;
   }
+  if constexpr (DRAW)
+    if (threadIdx.x == 0) {
+      double v = 0.0;
+      for (int gg = 0; gg < NG; ++gg) v += vpart[gg];
+      dr.out[qi] = v / (double)n;
+    }
 }
 
 // Fixed-order sum of q per-query terms into one scalar (single workgroup).
@@ -259,37 +307,79 @@ __global__ void __launch_bounds__(WG) sum_scalar_kernel(const double* __restrict
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// The adjoint (DRAW = false: rows from samp) or the fused value-and-gradient
+// pass (DRAW = true); false if the shape needs the generic kernel.
+template <bool DRAW>
+static bool launch_vec(const float* X, const float* Y, int64_t n, int64_t q, int64_t d, double h,
+                       int kern, int64_t k, int64_t m, const int32_t* nn, const int32_t* samp,
+                       const double* grad_out, float* grad_Y, double* gh_part, const DrawArgs& dr,
+                       hipStream_t s) {
+  const bool aligned = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+                       (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
+  const dim3 g((unsigned)q), b(WG);
+  const size_t extra = BWD_IDX * 4 + (DRAW && k < n && m > 0 ? (size_t)k * 4 : 0);   // gaps
+#define DEANN_VEC(U_, GW_)                                                                    \
+  deann_backward_vec_kernel<U_, GW_, DRAW><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, \
+                                                             grad_out, grad_Y, gh_part, dr)
+  if (aligned && d <= 256) {   // 16 lanes per row
+    const size_t sm = (16 * d + 32) * 8 + extra;
+    switch ((d + 63) / 64) {
+      case 1: DEANN_VEC(1, 16); break;
+      case 2: DEANN_VEC(2, 16); break;
+      case 3: DEANN_VEC(3, 16); break;
+      default: DEANN_VEC(4, 16); break;
+    }
+    return true;
+  }
+  if (aligned && d <= 2048) {   // a wave per row
+    const size_t sm = (4 * d + 8) * 8 + extra;
+    switch ((d + 255) / 256) {
+      case 1:
+      case 2: DEANN_VEC(2, 64); break;
+      case 3:
+      case 4: DEANN_VEC(4, 64); break;
+      case 5:
+      case 6: DEANN_VEC(6, 64); break;
+      default: DEANN_VEC(8, 64); break;
+    }
+    return true;
+  }
+#undef DEANN_VEC
+  return false;
+}
+
 hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                                  double h, int kern, int64_t k, int64_t m, const int32_t* nn,
                                  const int32_t* samp, const double* grad_out, float* grad_Y,
                                  double* gh_part, double* grad_h, hipStream_t s) {
   if (q == 0) return hipSuccess;
-  const bool aligned = (d % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
-                       (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
-  const dim3 g((unsigned)q), b(WG);
-  if (aligned && d <= 256) {   // 16 lanes per row
-    const size_t sm = (16 * d + 16) * 8 + BWD_IDX * 4;
-    switch ((d + 63) / 64) {
-      case 1: deann_backward_vec_kernel<1, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-      case 2: deann_backward_vec_kernel<2, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-      case 3: deann_backward_vec_kernel<3, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-      default: deann_backward_vec_kernel<4, 16><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-    }
-  } else if (aligned && d <= 2048) {   // a wave per row
-    const size_t sm = (4 * d + 4) * 8 + BWD_IDX * 4;
-    switch ((d + 255) / 256) {
-      case 1:
-      case 2: deann_backward_vec_kernel<2, 64><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-      case 3:
-      case 4: deann_backward_vec_kernel<4, 64><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-      case 5:
-      case 6: deann_backward_vec_kernel<6, 64><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-      default: deann_backward_vec_kernel<8, 64><<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part); break;
-    }
-  } else {
+  if (!launch_vec<false>(X, Y, n, q, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part,
+                         DrawArgs{}, s)) {
     const size_t sm = BWD_CHUNK * (8 + 8 + 4) + d * 4 + 16;
-    deann_backward_kernel<<<g, b, sm, s>>>(X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y,
-                                           gh_part);
+    deann_backward_kernel<<<dim3((unsigned)q), dim3(WG), sm, s>>>(
+        X, Y, n, d, h, kern, k, m, nn, samp, grad_out, grad_Y, gh_part);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !grad_h) return e;
+  sum_scalar_kernel<<<dim3(1), dim3(WG), 0, s>>>(gh_part, q, grad_h);
+  return hipGetLastError();
+}
+
+hipError_t launch_deann_value_grad(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
+                                   double h, int kern, int64_t k, int64_t m, uint64_t seed,
+                                   uint64_t query_offset, uint64_t word2, const int32_t* nn_sorted,
+                                   const double* z1, double* out, int32_t* sample_idx,
+                                   float* grad_Y, double* gh_part, double* grad_h, hipStream_t s) {
+  if (q == 0) return hipSuccess;
+  const DrawArgs dr{seed, query_offset, word2, sample_idx, out};
+  if (!launch_vec<true>(X, Y, n, q, d, h, kern, k, m, nn_sorted, nullptr, nullptr, grad_Y,
+                        gh_part, dr, s)) {
+    // other shapes: the sampler, then the adjoint over its draws
+    hipError_t e = launch_sample(X, Y, n, q, d, h, kern, k, m, seed, query_offset, word2, 0, 0,
+                                 nn_sorted, z1, out, sample_idx, s);
+    if (e != hipSuccess) return e;
+    return launch_deann_backward(X, Y, n, q, d, h, kern, k, m, nn_sorted, sample_idx, nullptr,
+                                 grad_Y, gh_part, grad_h, s);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !grad_h) return e;

@@ -231,8 +231,17 @@ hipError_t launch_sample(const float* X, const float* Y, int64_t n, int64_t q, i
 // ---- adjoints ----------------------------------------------------------------
 hipError_t launch_deann_backward(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                                  double h, int kern, int64_t k, int64_t m, const int32_t* nn,
-                                 const int32_t* samp, const double* grad_out, float* grad_Y,
+                                 const int32_t* samp, const double* grad_out /* NULL: ones */, float* grad_Y,
                                  double* gh_part, double* grad_h, hipStream_t s);
+// DEANN's estimates (as launch_sample, plain sampling) and d out_j / d y_j,
+// sum_j d out_j / d h from one gather of the k + m rows of each query; the
+// draws go to sample_idx (required here: scratch for shapes that take the
+// sampler and then the adjoint).
+hipError_t launch_deann_value_grad(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
+                                   double h, int kern, int64_t k, int64_t m, uint64_t seed,
+                                   uint64_t query_offset, uint64_t word2, const int32_t* nn_sorted,
+                                   const double* z1, double* out, int32_t* sample_idx,
+                                   float* grad_Y, double* gh_part, double* grad_h, hipStream_t s);
 
 // Three-part bfloat16 rows of the prepared operands ([rows][3][dps], see
 // launch_split_rows); X null: the float32 distance product.

@@ -14,29 +14,9 @@
 // coalesced segments) and evaluates ||x - y||^2 directly in FP64.
 #include "common.h"
 #include "kernels.h"
+#include "philox.h"
 
 namespace deann {
-
-struct Philox4x64 {
-  uint64_t v[4];
-};
-
-__device__ __forceinline__ Philox4x64 philox4x64_10(uint64_t k0, uint64_t k1, uint64_t c0,
-                                                    uint64_t c1, uint64_t c2, uint64_t c3) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) { k0 += W0; k1 += W1; }
-    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
-    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-  }
-  Philox4x64 o;
-  o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
-  return o;
-}
 
 __host__ __device__ inline int next_pow2_i(int64_t v) {
   int p = 1;
@@ -182,14 +162,12 @@ deann_sample_kernel(const float* __restrict__ X, const float* __restrict__ Y, in
       for (int w = 0; w < 4; ++w) {
         const int jj = b * 4 + w;
         if (jj < cnt) {
-          const uint64_t r = permuted ? (uint64_t)(j0 + jj) : __umul64hi(blk.v[w], size2);
-          // #{t : gaps[t] <= r}: gaps is non-decreasing
-          int lo = 0, hi = (int)k;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if ((uint64_t)(int64_t)gaps[mid] <= r) lo = mid + 1; else hi = mid;
+          int64_t u;
+          if constexpr (permuted) {   // position j of the block, neighbours skipped
+            u = rank_to_row((uint64_t)(j0 + jj), gaps, k);
+          } else {
+            u = draw_row(blk.v[w], size2, gaps, k);
           }
-          const int64_t u = (int64_t)(r + (uint64_t)lo);
           int32_t idx;
           if constexpr (IDX) {   // gather from the permuted copy, report the row
             const int64_t pos = (run + u) % n;

@@ -330,6 +330,58 @@ def test_deann_backward_vs_oracle(dev, kern, d):
     assert gh == pytest.approx(gh_ref, rel=1e-10)
 
 
+@pytest.mark.parametrize("d", [12, 300, 301])   # fused (16 lanes, a wave per row), two gathers
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
+def test_deann_with_grad(dev, kern, d):
+    # one gather for the estimate and its derivatives: the neighbours and draws
+    # of deann_query, the gradient of deann_query_backward with unit upstream
+    # gradient bit for bit, and the oracle's estimate and derivatives
+    import paper_2107_02736_amd as dk
+    X, Y = _small(3000, 40, d, seed=7)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h, k, m = 1.3 * np.sqrt(d / 12), 16, 100
+    out, gy, gh, nn, sm = dk.deann_query_with_grad(Xd, Yd, h, k, m, KNAME[kern], seed=4,
+                                                   query_offset=3, word2=5)
+    out0, nn0, sm0 = dk.deann_query(Xd, Yd, h, k, m, KNAME[kern], seed=4, query_offset=3, word2=5)
+    ones = to_dev(np.ones(40), dev)
+    gy0, gh0 = dk.deann_query_backward(Xd, Yd, h, k, m, nn0, sm0, ones, KNAME[kern])
+    assert np.array_equal(nn.cpu().numpy(), nn0.cpu().numpy())
+    assert np.array_equal(sm.cpu().numpy(), sm0.cpu().numpy())
+    assert np.array_equal(gy.cpu().numpy(), gy0.cpu().numpy())
+    out, out0, gh = out.cpu().numpy(), out0.cpu().numpy(), gh.cpu().numpy()
+    assert np.all(np.abs(out - out0) <= 1e-14 * out0)
+    assert gh.sum() == pytest.approx(float(gh0.cpu().numpy()[0]), rel=1e-12)
+    gy, nn, sm = gy.cpu().numpy(), nn.cpu().numpy(), sm.cpu().numpy()
+    for j in range(40):
+        est, gy_ref, gh_ref = oracle.deann_grad(X, Y[j], h, kern, nn[j], sm[j], m)
+        assert abs(out[j] - est) <= 1e-12 * est, j
+        assert np.linalg.norm(gy[j] - gy_ref) <= 1e-6 * np.linalg.norm(gy_ref) + 1e-30, j
+        assert gh[j] == pytest.approx(gh_ref, rel=1e-10), j
+
+
+@pytest.mark.parametrize("k,m", [(0, 64), (300, 64), (7, 0), (299, 64)])
+def test_deann_with_grad_degenerate(dev, k, m):
+    # plain random sampling (k = 0), the exact sum (k = n: no draws, sample
+    # indices -1), neighbours only (m = 0), a single row left to draw from
+    import paper_2107_02736_amd as dk
+    X, Y = _small(300, 24, 32, seed=3)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h = 2.0
+    out, gy, gh, nn, sm = dk.deann_query_with_grad(Xd, Yd, h, k, m, "gaussian", seed=9)
+    out0, nn0, sm0 = dk.deann_query(Xd, Yd, h, k, m, "gaussian", seed=9)
+    assert np.array_equal(nn.cpu().numpy(), nn0.cpu().numpy())
+    assert np.array_equal(sm.cpu().numpy(), sm0.cpu().numpy())
+    out, out0 = out.cpu().numpy(), out0.cpu().numpy()
+    assert np.all(np.abs(out - out0) <= 1e-14 * out0)
+    gy, gh, nn, sm = gy.cpu().numpy(), gh.cpu().numpy(), nn.cpu().numpy(), sm.cpu().numpy()
+    for j in range(24):
+        est, gy_ref, gh_ref = oracle.deann_grad(X, Y[j], h, GAUSSIAN, nn[j],
+                                                sm[j] if k < 300 else sm[j][:0], m)
+        assert abs(out[j] - est) <= 1e-12 * est, j
+        assert np.linalg.norm(gy[j] - gy_ref) <= 1e-6 * np.linalg.norm(gy_ref) + 1e-30, j
+        assert gh[j] == pytest.approx(gh_ref, rel=1e-10, abs=1e-300), j
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp32_split"])
 @pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
 def test_exact_backward_vs_oracle(dev, kern, prec):

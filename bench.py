@@ -567,7 +567,7 @@ def run_workload(args, workload, with_cpu):
                        "deann_bf16_query_steps_per_s": q * MEAN_SHIFT_STEPS
                                                        / (ms_shift_deann * 1e-3),
                        "note": "Gaussian mean shift of all queries; exact: kde_exact_with_grad "
-                               "per step (d <= 128 only); DEANN: deann_query + adjoint per step"},
+                               "per step (d <= 128 only); DEANN: deann_query_with_grad per step"},
         "permuted_index": {"build_s": perm_build_s, "bytes": perm_bytes,
                            "ms": ms_deannp_idx, "ms_evaluated_permutation": ms_deannp,
                            "same_estimates_as_evaluated": perm_same,

@@ -86,18 +86,16 @@ def mean_shift(X, Y, h, steps, method="exact", k=0, m=0, seed=0, precision="fp32
     """Gaussian mean shift y <- y + h^2 grad(mu)/mu, i.e. the kernel-weighted mean
     of the rows (with DEANN weights for method="deann").  Exact: density and
     gradient from one pass (kde_exact_with_grad).  DEANN: the estimate and its
-    adjoint with grad_out = 1; step t draws with counter word 2 = t.  Returns the
-    float32 end point [q, d]."""
+    gradient from one gather (deann_query_with_grad); step t draws with counter
+    word 2 = t.  Returns the float32 end point [q, d]."""
     Y = Y.detach().clone().contiguous()
-    q = Y.shape[0]
-    ones = torch.ones(q, dtype=torch.float64, device=Y.device)
     for t in range(steps):
         if method == "exact":
             mu, g, _ = api.kde_exact_with_grad(X, Y, float(h), "gaussian", True, False)
         else:
-            mu, nn, sm = api.deann_query(X, Y, float(h), k, m, "gaussian", seed, 0, t, precision)
-            g, _ = api.deann_query_backward(X, Y, float(h), k, m, nn, sm, ones, "gaussian",
-                                            True, False)
+            mu, g, _, _, _ = api.deann_query_with_grad(X, Y, float(h), k, m, "gaussian", seed, 0, t,
+                                                       precision, need_grad_h=False,
+                                                       return_indices=False)
         api.mean_shift_update(Y, g, mu, float(h), out=Y)
     return Y
 

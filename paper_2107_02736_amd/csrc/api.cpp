@@ -250,6 +250,7 @@ constexpr int64_t kIvfPartTarget = 512;        // inverted-file sweep parts: 2 p
 
 struct CertBuf {
   float2* part;      // [splits][qp]
+  float* pn;         // [splits][qp] (the generic float32 tile kernel's per-pair norm sums)
   int32_t* ids;      // [q]
   int32_t* count;    // [1]
 };
@@ -257,6 +258,7 @@ struct CertBuf {
 CertBuf carve_cert(Carve& cv, int64_t splits, int64_t qp, int64_t q) {
   CertBuf c{};
   c.part = cv.take<float2>(splits * qp);
+  c.pn = cv.take<float>(splits * qp);
   c.ids = cv.take<int32_t>(q > 0 ? q : 1);
   c.count = cv.take<int32_t>(1);
   return c;
@@ -273,6 +275,7 @@ CertArgs cert_args(const CertBuf& c, const Prep& p, int64_t cd) {
   a.floor = g_opt.value_floor;
   a.fb_ids = c.ids;
   a.fb_count = c.count;
+  a.pn = c.pn;   // dropped by the launches whose sweep does not write it
   return a;
 }
 

@@ -23,9 +23,13 @@ __device__ inline double bernstein(double V, double b) {
 // True when query i must be re-evaluated.  T: the sweep's kernel sum (before
 // the Gaussian query factor f, which scales T and sqrt(A) alike), A: sum of
 // K^2, y2: for the Gaussian kernel the sum of K times its exponent (-log2 K,
-// before f), for the exponential kernel the largest K; yn = ||y~||^2.
+// before f), for the exponential kernel the largest K; yn = ||y~||^2.  AN >= 0:
+// the sum over pairs of (K N)^2 with the pair's own N = ||x~||^2 + ||y~||^2
+// (Gaussian: in units of L = Lf, the float32 log2-scaled 1/(2h^2)), which
+// replaces the largest row norm in the variance of the dot-product roundings;
+// AN < 0: not available.
 __device__ inline bool needs_refine(double T, double A, double y2, double f, double yn, double n,
-                                    float Lf, int kern, const CertArgs& ca) {
+                                    float Lf, int kern, const CertArgs& ca, double AN) {
   const double xn = (double)__uint_as_float(*ca.xnmax) / (1.0 - ca.a_scale) * (1.0 + 1e-6);
   const double N = xn + yn;
   const double cd = (double)ca.cd;
@@ -43,8 +47,11 @@ __device__ inline bool needs_refine(double T, double A, double y2, double f, dou
       // roundings per pair (dot product, data-norm term, add, FMA with |a| up
       // to 2 L N); the float32 partial sums add 56 u^2 A
       const double g = kU * Lnat * N;
-      const double V = A * (g * g * (cd + 6.0) + 56.0 * kU * kU) / 3.0;
-      const double t = bernstein(V, (g + 8.0 * kU) * sqrt(A));
+      // per pair: sum K^2 g_pair^2 = (u ln2)^2 AN; single terms at most
+      // sqrt of that plus 8 u sqrt(A)
+      const double GA = AN >= 0.0 ? kU * kLn2 * sqrt(AN) : g * sqrt(A);
+      const double V = (GA * GA * (cd + 6.0) + 56.0 * kU * kU * A) / 3.0;
+      const double t = bernstein(V, GA + 8.0 * kU * sqrt(A));
       // systematic: the float32 exponent scale (u per unit of the K-weighted
       // mean exponent) and exp2 (2 u)
       const double Ebar = kLn2 * y2 / T;
@@ -62,8 +69,9 @@ __device__ inline bool needs_refine(double T, double A, double y2, double f, dou
         const double rlo = sqrt(r2);
         // a rounding of d^2 by at most u N moves K by u N / (2 h r) relative
         const double g = kU * N * Lnat / (2.0 * rlo);
-        const double V = A * (g * g * (cd + 6.0) + 56.0 * kU * kU) / 3.0;
-        const double t = bernstein(V, (g + 8.0 * kU) * sqrt(A));
+        const double GA = AN >= 0.0 ? kU * Lnat / (2.0 * rlo) * sqrt(AN) : g * sqrt(A);
+        const double V = (GA * GA * (cd + 6.0) + 56.0 * kU * kU * A) / 3.0;
+        const double t = bernstein(V, GA + 8.0 * kU * sqrt(A));
         // systematic: the scale, the square root and the product L r (u each
         // per unit of the mean exponent, at most ln(n/T) + ln n), exp2, and the
         // rounding of ||y~||^2 shared by all pairs of the query
@@ -86,8 +94,9 @@ __device__ inline bool needs_refine(double T, double A, double y2, double f, dou
 }  // namespace cert_detail
 
 __device__ inline void cert_check(int64_t i, double T, double A, double y2, double f,
-                                  double yn, int64_t n, float Lf, int kern, const CertArgs& ca) {
-  if (cert_detail::needs_refine(T, A, y2, f, yn, (double)n, Lf, kern, ca)) {
+                                  double yn, int64_t n, float Lf, int kern, const CertArgs& ca,
+                                  double AN = -1.0) {
+  if (cert_detail::needs_refine(T, A, y2, f, yn, (double)n, Lf, kern, ca, AN)) {
     const int slot = atomicAdd(ca.fb_count, 1);
     ca.fb_ids[slot] = (int32_t)i;
   }

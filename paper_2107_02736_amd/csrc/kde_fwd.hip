@@ -45,8 +45,11 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
                 int64_t n, int64_t qtiles, int64_t splits, int64_t ntiles, float Lf,
                 double* __restrict__ partial, int64_t qp, TileMap map,
                 const int32_t* __restrict__ hoff, const uint16_t* __restrict__ hits,
-                float2* __restrict__ cert) {
-  // float32 operands: certificate sums (see the file comment)
+                float2* __restrict__ cert, float* __restrict__ certn) {
+  // float32 operands: certificate sums (see the file comment), and per pair
+  // the squared product of K and the pair's norm term N = ||x~||^2 + ||y~||^2
+  // (Gaussian: -L N, the exponent's norm part), so that the bound takes each
+  // pair's rounding scale instead of the largest row norm's
   constexpr bool CERT = elem_of<T>::bytes == 4 && !HYB;
   __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
   __shared__ uint16_t hl[HYB ? HYB_LDS : 1];
@@ -82,8 +85,8 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
     }
   double sum[4][4];
   // certificate (CERT only): sum of K^2; Gaussian: sum of K times its exponent,
-  // exponential: largest K
-  float csq[4][4], cmx[4][4];
+  // exponential: largest K; sum of (K N)^2
+  float csq[4][4], cmx[4][4], cqn[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -91,6 +94,7 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       sum[i][r] = 0.0;
       csq[i][r] = 0.f;
       cmx[i][r] = 0.f;
+      cqn[i][r] = 0.f;
     }
 
   const char* yq = Ys + qt * BQ * ld_bytes;
@@ -197,11 +201,12 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
           for (int j = 0; j < 4; ++j) {
             float kv;
             float a = 0.f;
+            const float nl = yt[i][r] + xt[j];
             if (KERN == KERNEL_GAUSSIAN) {   // exp(-d^2 / (2 h^2))
-              a = fminf(__builtin_fmaf(L2, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
+              a = fminf(__builtin_fmaf(L2, acc[i][j][r], nl), 0.f);
               kv = __builtin_amdgcn_exp2f(a);
             } else {                          // exp(-d / h)
-              const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[i][j][r], yt[i][r] + xt[j]), 0.f);
+              const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[i][j][r], nl), 0.f);
               kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
             }
             part += kv;
@@ -209,6 +214,9 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
               csq[i][r] = __builtin_fmaf(kv, kv, csq[i][r]);
               if (KERN == KERNEL_GAUSSIAN) cmx[i][r] = __builtin_fmaf(-kv, a, cmx[i][r]);
               else cmx[i][r] = fmaxf(cmx[i][r], kv);
+              // padding columns: K = 0 times a finite norm term
+              const float w = kv * (KERN == KERNEL_GAUSSIAN ? nl : fminf(nl, 3.0e38f));
+              cqn[i][r] = __builtin_fmaf(w, w, cqn[i][r]);
             }
           }
           sum[i][r] += (double)part;
@@ -245,30 +253,37 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float a = csq[i][r], m = cmx[i][r];
+        float a = csq[i][r], m = cmx[i][r], w = cqn[i][r];
 #pragma unroll
         for (int o = 1; o < 16; o <<= 1) {
           a += __shfl_xor(a, o, 64);
+          w += __shfl_xor(w, o, 64);
           const float mo = __shfl_xor(m, o, 64);
           m = KERN == KERNEL_GAUSSIAN ? m + mo : fmaxf(m, mo);
         }
         csq[i][r] = a;
         cmx[i][r] = m;
+        cqn[i][r] = w;
       }
     __syncthreads();   // red is reused
     float2* cr = reinterpret_cast<float2*>(lds);   // [2][BQ]
+    float* cw = reinterpret_cast<float*>(cr + 2 * BQ);   // [2][BQ]
     if ((lane & 15) == 0) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          cr[wn * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r] = make_float2(csq[i][r], cmx[i][r]);
+        for (int r = 0; r < 4; ++r) {
+          const int e = wn * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
+          cr[e] = make_float2(csq[i][r], cmx[i][r]);
+          cw[e] = cqn[i][r];
+        }
     }
     __syncthreads();
     if (threadIdx.x < BQ) {
       const float2 a = cr[threadIdx.x], b = cr[BQ + threadIdx.x];
       cert[split * qp + qt * BQ + threadIdx.x] =
           make_float2(a.x + b.x, KERN == KERNEL_GAUSSIAN ? a.y + b.y : fmaxf(a.y, b.y));
+      certn[split * qp + qt * BQ + threadIdx.x] = cw[threadIdx.x] + cw[BQ + threadIdx.x];
     }
   }
 }
@@ -617,7 +632,9 @@ hipError_t launch_kde_exact_split(const TileProblem& p, const void* Xsp, const v
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
-  return finish_fp32(p, kern, h, L, partial, out, s, ca, X, Y, d, fb_part);
+  CertArgs cb = ca;
+  cb.pn = nullptr;   // the split kernel keeps no per-pair norm sums
+  return finish_fp32(p, kern, h, L, partial, out, s, cb, X, Y, d, fb_part);
 }
 
 // Sum of the per-split partials in split order, times the Gaussian query
@@ -642,21 +659,21 @@ __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t sp
 template <typename T, int KERN, int ENG, bool HYB = false>
 static void launch_kde_k(const TileProblem& p, float L, double* partial, hipStream_t s,
                          const int32_t* hoff = nullptr, const uint16_t* hits = nullptr,
-                         float2* cert = nullptr) {
+                         float2* cert = nullptr, float* certn = nullptr) {
   kde_tile_kernel<T, KERN, ENG, HYB><<<dim3((unsigned)p.map.grid), dim3(WG), 0, s>>>(
       p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
-      partial, p.qp, p.map, hoff, hits, cert);
+      partial, p.qp, p.map, hoff, hits, cert, certn);
 }
 
 template <typename T, int KERN>
 static void launch_kde_n(const TileProblem& p, float L, double* partial, float2* cert,
-                         hipStream_t s) {
+                         float* certn, hipStream_t s) {
   if constexpr (elem_of<T>::bytes == 2) {
     const int eng = tile_engine<T>(p.ld_bytes);
     if (eng == 2) return launch_kde_k<T, KERN, 2>(p, L, partial, s);
     if (eng == 1) return launch_kde_k<T, KERN, 1>(p, L, partial, s);
   }
-  launch_kde_k<T, KERN, 0>(p, L, partial, s, nullptr, nullptr, cert);
+  launch_kde_k<T, KERN, 0>(p, L, partial, s, nullptr, nullptr, cert, certn);
 }
 
 template <typename T, int KERN>
@@ -699,19 +716,25 @@ static bool launch_yres_d(const TileProblem& p, float L, double* partial, float2
   }
 }
 
+// certn (float32 operands): set to null when the sweep does not write the
+// per-pair norm sums (rows of at most 512 bytes take kde_yres_kernel)
 template <typename T>
 static hipError_t launch_kde_t(const TileProblem& p, int kern, float L, double* partial,
-                               float2* cert, hipStream_t s) {
+                               float2* cert, float** certn, hipStream_t s) {
   if constexpr (elem_of<T>::bytes == 4) {   // FP32 rows of at most 512 bytes
     const bool done = kern == KERNEL_GAUSSIAN
                           ? launch_yres_d<KERNEL_GAUSSIAN>(p, L, partial, cert, s)
                           : launch_yres_d<KERNEL_EXPONENTIAL>(p, L, partial, cert, s);
-    if (done) return hipGetLastError();
+    if (done) {
+      *certn = nullptr;
+      return hipGetLastError();
+    }
   }
+  float* cn = certn ? *certn : nullptr;
   if (kern == KERNEL_GAUSSIAN)
-    launch_kde_n<T, KERNEL_GAUSSIAN>(p, L, partial, cert, s);
+    launch_kde_n<T, KERNEL_GAUSSIAN>(p, L, partial, cert, cn, s);
   else
-    launch_kde_n<T, KERNEL_EXPONENTIAL>(p, L, partial, cert, s);
+    launch_kde_n<T, KERNEL_EXPONENTIAL>(p, L, partial, cert, cn, s);
   return hipGetLastError();
 }
 
@@ -734,14 +757,15 @@ hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, 
   const float L = (float)(kern == KERNEL_GAUSSIAN ? log2e / (2.0 * h * h) : log2e / h);
   hipError_t e;
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
+  CertArgs cb = ca;
   switch (prec) {
-    case PREC_FP32: e = launch_kde_t<float>(p, kern, L, partial, ca.part, s); break;
-    case PREC_BF16: e = launch_kde_t<__bf16>(p, kern, L, partial, nullptr, s); break;
-    default: e = launch_kde_t<_Float16>(p, kern, L, partial, nullptr, s); break;
+    case PREC_FP32: e = launch_kde_t<float>(p, kern, L, partial, ca.part, &cb.pn, s); break;
+    case PREC_BF16: e = launch_kde_t<__bf16>(p, kern, L, partial, nullptr, nullptr, s); break;
+    default: e = launch_kde_t<_Float16>(p, kern, L, partial, nullptr, nullptr, s); break;
   }
   if (e != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
-  if (prec == PREC_FP32) return finish_fp32(p, kern, h, L, partial, out, s, ca, X, Y, d, fb_part);
+  if (prec == PREC_FP32) return finish_fp32(p, kern, h, L, partial, out, s, cb, X, Y, d, fb_part);
   kde_reduce_kernel<<<dim3((unsigned)ceil_div(p.q, 256)), dim3(256), 0, s>>>(
       partial, p.splits, p.qp, p.q, 1.0 / (double)p.n, p.ynorm, L, kern, nullptr, out);
   return hipGetLastError();

@@ -59,6 +59,9 @@ struct CertArgs {
   double floor;            // values certainly below it are not re-evaluated
   int32_t* fb_ids;         // [q] queries to re-evaluate
   int32_t* fb_count;       // [1]
+  float* pn;               // [splits][qp] per split: sum of (K N)^2 with N = ||x~||^2 +
+                           // ||y~||^2 of the pair (Gaussian: times (L log2 e)^2), written by
+                           // the generic float32 tile kernel only; null for the other sweeps
 };
 
 // Fixed-order sum of the float32 sweep's partials into out (Gaussian query

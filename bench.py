@@ -381,16 +381,30 @@ def run_workload(args, workload, with_cpu):
     # the step): the exact KDE alone and with its gradient, speed and their
     # difference from the float32 MFMA path
     ms_split = ms_split_grad = ms_step_split = None
-    mus_h = musg_h = None
-    if d <= 128:
+    musg_h = None
+    flops_exact = 2.0 * n * d * q
+    mus = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32_split")
+    torch.cuda.synchronize()
+    dk.kernel_timing(reps)
+    a.record()
+    for _ in range(reps):
         mus = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32_split")
-        torch.cuda.synchronize()
-        a.record()
-        for _ in range(reps):
-            mus = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32_split")
-        b.record()
-        torch.cuda.synchronize()
-        ms_split = a.elapsed_time(b) / reps
+    b.record()
+    torch.cuda.synchronize()
+    ms_split = a.elapsed_time(b) / reps
+    split_tile_ms = float(np.mean(dk.kernel_times("kde_exact")))
+    dk.kernel_timing(0)
+    mus_h = mus.cpu().numpy()
+    split_kernel = {
+        "kernel": "kde_tile_kernel<float,gaussian,split engine>" if d > 128
+                  else "kde_split_kernel<gaussian>",
+        "kernel_avg_ms": split_tile_ms,
+        "bf16_flops_per_launch": 6.0 * flops_exact,
+        "frac_of_bf16_peak": 6.0 * flops_exact / (split_tile_ms * 1e-3) / PEAK_BF16_MFMA,
+        "fp32_equivalent_tflops": flops_exact / (split_tile_ms * 1e-3) / 1e12,
+        "note": "six bfloat16 products per element (12*n*d*q flops) on BF16 MFMAs; the "
+                "FP32-equivalent rate counts the 2*n*d*q flops of the float32 product"}
+    if d <= 128:
         musg = dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")[0]
         torch.cuda.synchronize()
         a.record()
@@ -399,18 +413,23 @@ def run_workload(args, workload, with_cpu):
         b.record()
         torch.cuda.synchronize()
         ms_split_grad = a.elapsed_time(b) / reps
-        mus_h, musg_h = mus.cpu().numpy(), musg.cpu().numpy()
-        # the whole step with the split exact part (same work, same outputs)
-        for _ in range(max(1, args.warmup)):
-            dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")
-            dk.deann_query_with_grad(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16")
-        torch.cuda.synchronize()
-        t0s = time.perf_counter()
-        for _ in range(args.steps):
-            dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")
-            dk.deann_query_with_grad(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16")
-        torch.cuda.synchronize()
-        ms_step_split = (time.perf_counter() - t0s) * 1e3 / args.steps
+        musg_h = musg.cpu().numpy()
+
+    def exact_split():
+        if fused:
+            return dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, precision="fp32_split")
+        return dk.kde_exact(Xd, Yd, h, KERNEL, "fp32_split")
+    # the whole step with the split exact part (same work, same outputs)
+    for _ in range(max(1, args.warmup)):
+        exact_split()
+        dk.deann_query_with_grad(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16")
+    torch.cuda.synchronize()
+    t0s = time.perf_counter()
+    for _ in range(args.steps):
+        exact_split()
+        dk.deann_query_with_grad(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16")
+    torch.cuda.synchronize()
+    ms_step_split = (time.perf_counter() - t0s) * 1e3 / args.steps
 
     # exact KDE with BF16 operands (not part of the step): speed and its error
     # against the FP32 exact path (itself within about 1e-6 of the FP64 oracle)
@@ -475,7 +494,6 @@ def run_workload(args, workload, with_cpu):
     esti_h = esti.cpu().numpy()
     rel_ivf = np.abs(esti_h[keep] - mu_h[keep]) / mu_h[keep]
 
-    flops_exact = 2.0 * n * d * q
     tile_avg_ms = float(np.mean(tile_ms))
     fwd_achieved = flops_exact / (tile_avg_ms * 1e-3)
     # FP32 rows of at most 128 floats: the register-resident query kernel
@@ -555,9 +573,10 @@ def run_workload(args, workload, with_cpu):
         },
         "step_fp32_split": ({"ms_per_step": ms_step_split,
                              "queries_per_s": q / (ms_step_split * 1e-3),
-                             "note": "the same step with the exact KDE and its gradient from "
-                                     "three-part bfloat16 MFMAs (DEANN_FP32_SPLIT), outside the "
-                                     "timed step above"}
+                             "split_kernel": split_kernel,
+                             "note": "the same step with the exact KDE (and its gradient, d <= "
+                                     "128) from three-part bfloat16 MFMAs (DEANN_FP32_SPLIT, "
+                                     "certified to the same 1e-5), outside the timed step above"}
                             if ms_step_split else None),
         "mean_shift": {"steps": MEAN_SHIFT_STEPS,
                        "exact_ms": ms_shift_exact,

@@ -111,7 +111,11 @@ deann_status deann_last_stats(deann_stats* stats, void* stream);
  * Distances use the identity ||x-y||^2 = ||x||^2 + ||y||^2 - 2<x,y> of App. F
  * (with both sides centred on the column mean of X) and the kernel sum is
  * fused into the MFMA tile; per-split sums are combined in FP64.
- *   precision  DEANN_FP32, DEANN_BF16 or DEANN_FP16 operands of the GEMM.
+ *   precision  DEANN_FP32, DEANN_BF16 or DEANN_FP16 operands of the GEMM, or
+ *              DEANN_FP32_SPLIT: float32-accurate dot products from three
+ *              bfloat16 parts of every float32 value on BF16 MFMAs (six
+ *              products per element); the float32 forms are certified per
+ *              query (deann_options.rel_tol) like DEANN_FP32.
  *   out        [q] float64.
  * Requirements: n >= 1, d >= 1, q >= 0 (q = 0 is a no-op), h finite and > 0,
  * n and q < 2^31.

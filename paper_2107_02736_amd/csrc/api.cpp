@@ -251,6 +251,7 @@ constexpr int64_t kIvfPartTarget = 512;        // inverted-file sweep parts: 2 p
 struct CertBuf {
   float2* part;      // [splits][qp]
   float* pn;         // [splits][qp] (the generic float32 tile kernel's per-pair norm sums)
+  float* pk;         // [splits][qp] (its split engine's sums of K N)
   int32_t* ids;      // [q]
   int32_t* count;    // [1]
 };
@@ -259,14 +260,17 @@ CertBuf carve_cert(Carve& cv, int64_t splits, int64_t qp, int64_t q) {
   CertBuf c{};
   c.part = cv.take<float2>(splits * qp);
   c.pn = cv.take<float>(splits * qp);
+  c.pk = cv.take<float>(splits * qp);
   c.ids = cv.take<int32_t>(q > 0 ? q : 1);
   c.count = cv.take<int32_t>(1);
   return c;
 }
 
-// cd: roundings of one dot product (its accumulation length)
-CertArgs cert_args(const CertBuf& c, const Prep& p, int64_t cd) {
+// cd: roundings of one dot product (its accumulation length); split: the
+// distance product comes from three-part bfloat16 operands
+CertArgs cert_args(const CertBuf& c, const Prep& p, int64_t cd, bool split = false) {
   CertArgs a{};
+  a.sys = split ? 2.0 : 0.0;
   a.part = c.part;
   a.xnmax = p.err_max + 2;
   a.a_scale = key_scale(p.dp);
@@ -276,6 +280,7 @@ CertArgs cert_args(const CertBuf& c, const Prep& p, int64_t cd) {
   a.fb_ids = c.ids;
   a.fb_count = c.count;
   a.pn = c.pn;   // dropped by the launches whose sweep does not write it
+  a.pk = c.pk;
   return a;
 }
 
@@ -572,7 +577,6 @@ deann_status kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int
   if (st != DEANN_OK) return st;
   const bool split = precision == DEANN_FP32_SPLIT;
   if (bad_prec(precision) && !split) return fail(DEANN_EINVAL, "unknown precision %d", precision);
-  if (split && d > 128) return fail(DEANN_EUNSUPPORTED, "DEANN_FP32_SPLIT supports d <= 128");
   if (q == 0) return DEANN_OK;
   if (!out) return fail(DEANN_EINVAL, "out is NULL");
   const int64_t need = plan_kde(nullptr, n, q, d, precision).bytes;
@@ -593,7 +597,7 @@ deann_status kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int
                             P.dps, P.Ysp, s);
     if (e == hipSuccess)
       e = launch_kde_exact_split(tp, P.Xsp, P.Ysp, P.dps, kernel, h, P.partial, out, s,
-                                 timer_hook(0), cert_args(P.cert, P.prep, P.dps + 4), X, Y, d,
+                                 timer_hook(0), cert_args(P.cert, P.prep, P.dps + 4, true), X, Y, d,
                                  P.fb_part);
   } else {
     const CertArgs ca = precision == DEANN_FP32 ? cert_args(P.cert, P.prep, P.prep.dp) : CertArgs{};
@@ -911,7 +915,7 @@ deann_status kde_exact_backward(const float* X, int64_t n, const float* Y, int64
   tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
   e = launch_kde_backward(tp, X, Y, d, h, kernel, grad_out, P.gy_part, P.gh_part, grad_Y, grad_h,
                           s, timer_hook(1), nullptr, nullptr, sp,
-                          cert_args(P.cert, P.prep, sp.X ? P.dps + 4 : P.prep.dp));
+                          cert_args(P.cert, P.prep, sp.X ? P.dps + 4 : P.prep.dp, sp.X != nullptr));
   if (e != hipSuccess) return hip_fail(e, "kde backward");
   return DEANN_OK;
 }
@@ -1035,7 +1039,7 @@ deann_status kde_exact_with_grad(const float* X, int64_t n, const float* Y, int6
   tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
   e = launch_kde_backward(tp, X, Y, d, h, kernel, nullptr, P.gy_part, P.gh_part, grad_Y, nullptr,
                           s, timer_hook(1), out, grad_h, sp,
-                          cert_args(P.cert, P.prep, sp.X ? P.dps + 4 : P.prep.dp));
+                          cert_args(P.cert, P.prep, sp.X ? P.dps + 4 : P.prep.dp, sp.X != nullptr));
   if (e != hipSuccess) return hip_fail(e, "kde value and gradient");
   return DEANN_OK;
 }

@@ -674,7 +674,8 @@ __global__ void __launch_bounds__(BWG, 1)
 kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
                           const char* __restrict__ Ysp, float L, double* __restrict__ gy_part,
                           double* __restrict__ rw_part, double* __restrict__ gh_part,
-                          double* __restrict__ ks_part, float2* __restrict__ cert) {
+                          double* __restrict__ ks_part, float2* __restrict__ cert,
+                          float* __restrict__ certk) {
   using G = GradTile<DP>;
   // the certificate needs sum K for the exponential kernel (Gaussian: the weights)
   constexpr bool KS = KERN != KERNEL_GAUSSIAN;
@@ -749,8 +750,9 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
 #pragma unroll
   for (int i = 0; i < G::GB; ++i) gacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
   double rws = 0.0, dhs = 0.0, kss = 0.0;
-  // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential: largest K
-  float csq = 0.f, cmx = 0.f;
+  // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential:
+  // largest K; sum of K N (the bfloat16 MFMA's truncation bias, see cert.h)
+  float csq = 0.f, cmx = 0.f, ckn = 0.f;
 
   const int64_t qbase = split * p.qp + qt * BQ + wave * 16;
   double* gpart = gy_part + qbase * DP;
@@ -813,15 +815,17 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
         for (int r = 0; r < 4; ++r) {
           const float sv = acc[bi][r];
           float w, dh;
+          const float nl = yv + xv[r];   // -L N (Gaussian) or N; padding: huge
           if (KERN == KERNEL_GAUSSIAN) {
-            const float a = fminf(__builtin_fmaf(2.f * L, sv, yv + xv[r]), 0.f);   // -L d^2
+            const float a = fminf(__builtin_fmaf(2.f * L, sv, nl), 0.f);   // -L d^2
             const float K = __builtin_amdgcn_exp2f(a);
             w = K;
             dh = K * a;
             csq = __builtin_fmaf(K, K, csq);
             cmx = __builtin_fmaf(-K, a, cmx);   // Gaussian: sum of K times its exponent
+            ckn = __builtin_fmaf(K, -nl, ckn);
           } else {
-            const float d2 = fmaxf(__builtin_fmaf(-2.f, sv, yv + xv[r]), 0.f);
+            const float d2 = fmaxf(__builtin_fmaf(-2.f, sv, nl), 0.f);
             const float rr = __builtin_sqrtf(d2);
             const float K = __builtin_amdgcn_exp2f(-L * rr);
             w = rr > 0.f ? K * __builtin_amdgcn_rcpf(rr) : 0.f;
@@ -829,6 +833,7 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
             if constexpr (KS) ks32 += K;
             csq = __builtin_fmaf(K, K, csq);
             cmx = fmaxf(cmx, K);
+            ckn = __builtin_fmaf(K, fminf(nl, 3.0e38f), ckn);
           }
           acc[bi][r] = w;
           rw32 += w;
@@ -881,6 +886,8 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
   }
   csq += __shfl_xor(csq, 16, 64);
   csq += __shfl_xor(csq, 32, 64);
+  ckn += __shfl_xor(ckn, 16, 64);
+  ckn += __shfl_xor(ckn, 32, 64);
   if (KERN == KERNEL_GAUSSIAN) {
     cmx += __shfl_xor(cmx, 16, 64);
     cmx += __shfl_xor(cmx, 32, 64);
@@ -893,6 +900,7 @@ kde_backward_split_kernel(TileProblem p, const char* __restrict__ Xsp,
     gh_part[qbase + c] = dhs;
     if constexpr (KS) ks_part[qbase + c] = kss;
     cert[qbase + c] = make_float2(csq, cmx);
+    certk[qbase + c] = ckn;
   }
   if (fresh) flush_grad<DP>(gacc, gpart, g, c, true);   // empty range: zeros
 }
@@ -918,13 +926,14 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
   const int64_t qi = blockIdx.x;
   __shared__ double rw_s, f_s;
   if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0, c = 0.0, A = 0.0, y2 = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0, A = 0.0, y2 = 0.0, AK = 0.0;
     for (int64_t s = 0; s < splits; ++s) {
       a += rw_part[s * qp + qi];
       b += gh_part[s * qp + qi];
       const float2 cc = ca.part[s * qp + qi];
       A += (double)cc.x;
       y2 = kern == KERNEL_GAUSSIAN ? y2 + (double)cc.y : fmax(y2, (double)cc.y);
+      if (ca.pk) AK += (double)ca.pk[s * qp + qi];
     }
     if (ks_part)
       for (int64_t s = 0; s < splits; ++s) c += ks_part[s * qp + qi];
@@ -940,7 +949,7 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
     const double T = ks_part ? c : a;   // sum of K (Gaussian: the weights themselves)
     if (mu) mu[qi] = f * T * inv_n;
     cert_check(qi, T, A * 1.01, kern == KERNEL_GAUSSIAN ? y2 * 1.01 : y2, f, ynorm[qi], n, L,
-               kern, ca);
+               kern, ca, -1.0, ca.pk ? AK * 1.02 : -1.0);
   }
   __syncthreads();
   if (!grad_Y) return;
@@ -958,18 +967,18 @@ __global__ void kde_backward_reduce_kernel(const double* __restrict__ gy_part,
 template <int KERN>
 static hipError_t launch_kde_bwd_split(const TileProblem& p, const SplitRows& sp, int64_t dp,
                                        float L, double* gy, double* rw, double* gh, double* ks,
-                                       float2* cert, hipStream_t s) {
+                                       float2* cert, float* ck, hipStream_t s) {
   const dim3 g((unsigned)p.map.grid), b(BWG);
   const char* Xs = reinterpret_cast<const char*>(sp.X);
   const char* Ys = reinterpret_cast<const char*>(sp.Y);
   if (sp.dps == 64 && dp == 32)
-    kde_backward_split_kernel<KERN, 64, 32, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert);
+    kde_backward_split_kernel<KERN, 64, 32, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert, ck);
   else if (sp.dps == 64 && dp == 64)
-    kde_backward_split_kernel<KERN, 64, 64, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert);
+    kde_backward_split_kernel<KERN, 64, 64, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert, ck);
   else if (sp.dps == 128 && dp == 96)
-    kde_backward_split_kernel<KERN, 128, 96, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert);
+    kde_backward_split_kernel<KERN, 128, 96, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert, ck);
   else if (sp.dps == 128 && dp == 128)
-    kde_backward_split_kernel<KERN, 128, 128, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert);
+    kde_backward_split_kernel<KERN, 128, 128, false><<<g, b, 0, s>>>(p, Xs, Ys, L, gy, rw, gh, ks, cert, ck);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1026,9 +1035,9 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* X, const float
   if (split.X)   // distance product from three-part bfloat16 rows
     e = kern == KERNEL_GAUSSIAN
             ? launch_kde_bwd_split<KERNEL_GAUSSIAN>(p, split, dp, L, gy_part, rw_part, gh_part,
-                                                    ks_part, ca.part, s)
+                                                    ks_part, ca.part, ca.pk, s)
             : launch_kde_bwd_split<KERNEL_EXPONENTIAL>(p, split, dp, L, gy_part, rw_part, gh_part,
-                                                       ks_part, ca.part, s);
+                                                       ks_part, ca.part, ca.pk, s);
   else
     e = kern == KERNEL_GAUSSIAN
             ? launch_kde_bwd_k<KERNEL_GAUSSIAN>(p, dp, L, gy_part, rw_part, gh_part, ks_part,
@@ -1043,10 +1052,12 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* X, const float
   const bool need_ghq = grad_h || gh_per_query;
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(ca.fb_count), 1, 0u, s)) != hipSuccess)
     return e;
+  CertArgs cb = ca;
+  if (!split.X) cb.pk = nullptr;   // float32 MFMAs round to nearest: no bias term
   kde_backward_reduce_kernel<<<dim3((unsigned)p.q), dim3(128), 0, s>>>(
       gy_part, rw_part, gh_part, kern != KERNEL_GAUSSIAN ? ks_part : nullptr,
       reinterpret_cast<const float*>(p.Ys), p.splits, p.qp, p.q, d, dp, p.n, 1.0 / (double)p.n,
-      p.ynorm, L, kern, c_y, c_h, grad_out, grad_Y, need_ghq ? ghq : nullptr, mu, ca);
+      p.ynorm, L, kern, c_y, c_h, grad_out, grad_Y, need_ghq ? ghq : nullptr, mu, cb);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // exact re-evaluation of the listed queries; its scratch reuses the sweep's
   // partials, which the reduction has consumed: value and h sums in the gh and

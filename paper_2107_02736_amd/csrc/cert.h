@@ -27,9 +27,12 @@ __device__ inline double bernstein(double V, double b) {
 // the sum over pairs of (K N)^2 with the pair's own N = ||x~||^2 + ||y~||^2
 // (Gaussian: in units of L = Lf, the float32 log2-scaled 1/(2h^2)), which
 // replaces the largest row norm in the variance of the dot-product roundings;
-// AN < 0: not available.
+// AN < 0: not available.  AK >= 0 (three-part bfloat16 operands): the sum over
+// pairs of K N in the units of AN; the bias of the truncated group sums of
+// the bfloat16 MFMA, at most u N / 2 per dot product, is then u L per unit of
+// the K-weighted mean N (AK < 0: ca.sys u L times the largest N).
 __device__ inline bool needs_refine(double T, double A, double y2, double f, double yn, double n,
-                                    float Lf, int kern, const CertArgs& ca, double AN) {
+                                    float Lf, int kern, const CertArgs& ca, double AN, double AK) {
   const double xn = (double)__uint_as_float(*ca.xnmax) / (1.0 - ca.a_scale) * (1.0 + 1e-6);
   const double N = xn + yn;
   const double cd = (double)ca.cd;
@@ -55,7 +58,8 @@ __device__ inline bool needs_refine(double T, double A, double y2, double f, dou
       // systematic: the float32 exponent scale (u per unit of the K-weighted
       // mean exponent) and exp2 (2 u)
       const double Ebar = kLn2 * y2 / T;
-      const double R = t / T + kU * Ebar + 2.0 * kU + uflow;
+      const double bias = AK >= 0.0 ? kU * kLn2 * AK / T : ca.sys * g;
+      const double R = t / T + kU * Ebar + 2.0 * kU + uflow + bias;
       if (R <= ca.tau) return false;
     }
   } else {
@@ -76,8 +80,9 @@ __device__ inline bool needs_refine(double T, double A, double y2, double f, dou
         // per unit of the mean exponent, at most ln(n/T) + ln n), exp2, and the
         // rounding of ||y~||^2 shared by all pairs of the query
         const double Ebar = fmax(log(n / T), 0.0) + log(n);
+        const double bias = AK >= 0.0 ? kU * Lnat / (2.0 * rlo) * AK / T : ca.sys * g;
         const double R = t / T + kU * yn * Lnat / (2.0 * rlo) + 3.0 * kU * Ebar + 2.0 * kU +
-                         uflow;
+                         uflow + bias;
         if (R <= ca.tau) return false;
       }
     }
@@ -95,8 +100,8 @@ __device__ inline bool needs_refine(double T, double A, double y2, double f, dou
 
 __device__ inline void cert_check(int64_t i, double T, double A, double y2, double f,
                                   double yn, int64_t n, float Lf, int kern, const CertArgs& ca,
-                                  double AN = -1.0) {
-  if (cert_detail::needs_refine(T, A, y2, f, yn, (double)n, Lf, kern, ca, AN)) {
+                                  double AN = -1.0, double AK = -1.0) {
+  if (cert_detail::needs_refine(T, A, y2, f, yn, (double)n, Lf, kern, ca, AN, AK)) {
     const int slot = atomicAdd(ca.fb_count, 1);
     ca.fb_ids[slot] = (int32_t)i;
   }

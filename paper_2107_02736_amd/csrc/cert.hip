@@ -49,12 +49,13 @@ __global__ void kde_reduce_cert_kernel(const double* __restrict__ partial, int64
                                        CertArgs ca, double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= q) return;
-  double s = 0.0, A = 0.0, y2 = 0.0, AN = 0.0;
+  double s = 0.0, A = 0.0, y2 = 0.0, AN = 0.0, AK = 0.0;
   for (int64_t sp = 0; sp < splits; ++sp) {
     s += partial[sp * qp + i];
     const float2 c = ca.part[sp * qp + i];
     A += (double)c.x;
     if (ca.pn) AN += (double)ca.pn[sp * qp + i];
+    if (ca.pk) AK += (double)ca.pk[sp * qp + i];
     // Gaussian: sum of K times its exponent; exponential: the largest K
     y2 = kern == KERNEL_GAUSSIAN ? y2 + (double)c.y : fmax(y2, (double)c.y);
   }
@@ -67,7 +68,7 @@ __global__ void kde_reduce_cert_kernel(const double* __restrict__ partial, int64
   // FP32 sums of A and of the exponents lose at most a few 1e-4 relative: 1% margins
   // the norm terms of AN are float32 roundings of FP64 norms (a few u): inside the margin
   cert_check(i, s, A * 1.01, kern == KERNEL_GAUSSIAN ? y2 * 1.01 : y2, f, ynorm[i], n, Lf, kern,
-             ca, ca.pn ? AN * 1.02 : -1.0);
+             ca, ca.pn ? AN * 1.02 : -1.0, ca.pk ? AK * 1.02 : -1.0);
 }
 
 // ---------------------------------------------------------------------------

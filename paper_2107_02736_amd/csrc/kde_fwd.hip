@@ -38,20 +38,138 @@ constexpr int HYB_LDS = 1024;
 // HYB: near/far form.  hoff[(qt * ntiles + t) .. + 1] delimit the entries
 // (query mod 128) << 7 | (row mod 128) in hits of the neighbour pairs of query
 // tile qt in data tile t; those elements are left out of the sums.
-template <typename T, int KERN, int ENG, bool HYB>   // ENG: see tile_engine
-__global__ void __launch_bounds__(WG, 2)
+// Split-operand engine (ENG 3) for rows wider than 128 floats with float32-
+// accurate dot products from bfloat16 MFMAs (DEANN_FP32_SPLIT): every prepared
+// value is held as three bfloat16 parts v = h + m + l (row = planes h, m, l of
+// dps elements, see split_rows_kernel).  A 32-element k-chunk of a row is its
+// 64-byte slice of each plane; both tiles' chunks go global -> registers ->
+// LDS (double-buffered, one barrier per chunk, the next chunk in flight behind
+// the MFMAs).  Per chunk each wave forms, for its 64 x 64 quarter, the six
+// products h h, h m, m h, h l, m m, l h on v_mfma_f32_16x16x32_bf16 (products
+// exact in FP32); the three dropped products are below 2^-23 |x||y| together.
+// The leading products h h and the five small ones accumulate apart for the
+// whole tile and are added at its end: every MFMA rounds into its accumulator,
+// and rounding the small terms into the large running sum (one accumulator)
+// measured errors up to 1.5e-5 at d = 960 against a few 1e-7 for the float32
+// MFMAs.  One workgroup of 4 waves per CU (the staging of both
+// tiles' three planes takes two 53 KB buffers), so each wave may hold up to
+// 512 registers.
+constexpr int SPL_KB = 64;                                    // one plane's slice of a chunk
+constexpr int SPL_ROWB = 3 * SPL_KB;                          // a row's chunk, three planes
+constexpr int SPL_PITCH = SPL_ROWB + 16;                      // LDS row pitch (bytes)
+constexpr int SPL_BUF = (BQ + BN) * SPL_PITCH;                // one staged chunk, both tiles
+constexpr int SPL_NPT = (BQ + BN) * (SPL_ROWB / 16) / WG;     // 16-byte pieces per thread
+static_assert(SPL_NPT * WG == (BQ + BN) * (SPL_ROWB / 16), "chunk pieces must split evenly");
+
+struct SplitStream {
+  u32x4 r[SPL_NPT];
+  int buf;
+};
+
+// Chunk c of the query tile at yq and the data tile at xt: piece v is 16 bytes
+// (v % 4) of plane (v % 12) / 4 of row v / 12 (query rows first).  rowb: bytes
+// of a split row (3 planes), planeb: of one plane.
+__device__ __forceinline__ void split_load(SplitStream& st, const char* __restrict__ yq,
+                                           const char* __restrict__ xt, int64_t rowb,
+                                           int64_t planeb, int c) {
+#pragma unroll
+  for (int i = 0; i < SPL_NPT; ++i) {
+    const int v = threadIdx.x + i * WG;
+    const int row = v / 12, w = v % 12;
+    const char* base = row < BQ ? yq + (int64_t)row * rowb : xt + (int64_t)(row - BQ) * rowb;
+    st.r[i] = *reinterpret_cast<const u32x4*>(base + (w >> 2) * planeb + c * SPL_KB + (w & 3) * 16);
+  }
+}
+
+__device__ __forceinline__ void split_store(const SplitStream& st, char* buf) {
+#pragma unroll
+  for (int i = 0; i < SPL_NPT; ++i) {
+    const int v = threadIdx.x + i * WG;
+    *reinterpret_cast<u32x4*>(buf + (v / 12) * SPL_PITCH + (v % 12) * 16) = st.r[i];
+  }
+}
+
+__device__ __forceinline__ void split_start(SplitStream& st, const char* __restrict__ yq,
+                                            const char* __restrict__ Xs, int64_t rowb,
+                                            int64_t t0) {
+  split_load(st, yq, Xs + t0 * BN * rowb, rowb, rowb / 3, 0);
+  st.buf = 0;
+  __syncthreads();   // previous users of the staging area are done
+}
+
+__device__ __forceinline__ void split_tile(f32x4 (&acc)[4][4], SplitStream& st,
+                                           const char* __restrict__ yq,
+                                           const char* __restrict__ Xs, int64_t rowb,
+                                           int nchunks, int64_t t, int64_t t1, char* lds, int wq,
+                                           int wn, int lane) {
+  const int64_t planeb = rowb / 3;
+  f32x4 accx[4][4];   // the five small products
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      accx[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int c = 0; c < nchunks; ++c) {
+    char* b = lds + st.buf * SPL_BUF;
+    split_store(st, b);
+    __syncthreads();   // chunk c staged; the buffer written next was read two chunks ago
+    int nc = c + 1;
+    int64_t nt = t;
+    if (nc == nchunks) { nc = 0; nt = t + 1; }
+    if (nt < t1) split_load(st, yq, Xs + nt * BN * rowb, rowb, planeb, nc);
+    __builtin_amdgcn_s_setprio(1);   // favour the wave issuing MFMAs
+    u32x4 bh[4], bm[4], bl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const char* pr = b + (BQ + wn * 64 + j * 16 + (lane & 15)) * SPL_PITCH + (lane >> 4) * 16;
+      bh[j] = *reinterpret_cast<const u32x4*>(pr);
+      bm[j] = *reinterpret_cast<const u32x4*>(pr + SPL_KB);
+      bl[j] = *reinterpret_cast<const u32x4*>(pr + 2 * SPL_KB);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const char* pr = b + (wq * 64 + i * 16 + (lane & 15)) * SPL_PITCH + (lane >> 4) * 16;
+      const u32x4 ah = *reinterpret_cast<const u32x4*>(pr);
+      const u32x4 am = *reinterpret_cast<const u32x4*>(pr + SPL_KB);
+      const u32x4 al = *reinterpret_cast<const u32x4*>(pr + 2 * SPL_KB);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        f32x4 v = accx[i][j];
+        v = mfma_kgroup<__bf16>(al, bh[j], v);
+        v = mfma_kgroup<__bf16>(am, bm[j], v);
+        v = mfma_kgroup<__bf16>(ah, bl[j], v);
+        v = mfma_kgroup<__bf16>(am, bh[j], v);
+        accx[i][j] = mfma_kgroup<__bf16>(ah, bm[j], v);
+        acc[i][j] = mfma_kgroup<__bf16>(ah, bh[j], acc[i][j]);
+      }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    st.buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] += accx[i][j];
+}
+
+template <typename T, int KERN, int ENG, bool HYB>   // ENG: see tile_engine; 3: split (above)
+__global__ void __launch_bounds__(WG, ENG == 3 ? 1 : 2)
 kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_t ld_bytes,
                 int nchunks, const double* __restrict__ ynorm, const double* __restrict__ xnorm,
                 int64_t n, int64_t qtiles, int64_t splits, int64_t ntiles, float Lf,
                 double* __restrict__ partial, int64_t qp, TileMap map,
                 const int32_t* __restrict__ hoff, const uint16_t* __restrict__ hits,
-                float2* __restrict__ cert, float* __restrict__ certn) {
+                float2* __restrict__ cert, float* __restrict__ certn,
+                float* __restrict__ certk) {
   // float32 operands: certificate sums (see the file comment), and per pair
   // the squared product of K and the pair's norm term N = ||x~||^2 + ||y~||^2
   // (Gaussian: -L N, the exponent's norm part), so that the bound takes each
   // pair's rounding scale instead of the largest row norm's
   constexpr bool CERT = elem_of<T>::bytes == 4 && !HYB;
-  __shared__ __attribute__((aligned(16))) char lds[4 * TILE_LDS];
+  static_assert(ENG != 3 || (CERT && elem_of<T>::bytes == 4), "split rows carry float32 values");
+  __shared__ __attribute__((aligned(16))) char lds[ENG == 3 ? 2 * SPL_BUF : 4 * TILE_LDS];
   __shared__ uint16_t hl[HYB ? HYB_LDS : 1];
   int64_t qt, split;
   if (!map_tile(blockIdx.x, map, qtiles, splits, qt, split)) return;
@@ -85,8 +203,10 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
     }
   double sum[4][4];
   // certificate (CERT only): sum of K^2; Gaussian: sum of K times its exponent,
-  // exponential: largest K; sum of (K N)^2
-  float csq[4][4], cmx[4][4], cqn[4][4];
+  // exponential: largest K; sum of (K N)^2; split engine: sum of K N (the
+  // bfloat16 MFMA's truncated group sums bias each dot product by up to u N / 2)
+  constexpr bool KN = ENG == 3;
+  float csq[4][4], cmx[4][4], cqn[4][4], ckn[KN ? 4 : 1][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -95,6 +215,7 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       csq[i][r] = 0.f;
       cmx[i][r] = 0.f;
       cqn[i][r] = 0.f;
+      if constexpr (KN) ckn[i][r] = 0.f;
     }
 
   const char* yq = Ys + qt * BQ * ld_bytes;
@@ -103,15 +224,18 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
   XStream<NK> xs;
   u32x4 yf[4][NK];
   QlState ql;
+  SplitStream sst;
   if (t0 < t1) {
     if constexpr (ENG == 0) {
       stream_start(st, yq, Xs, ld_bytes, t0);
     } else if constexpr (ENG == 1) {
       ql_start(ql, yq, Xs, t0, lds);
-    } else {
+    } else if constexpr (ENG == 2) {
       yreg_load<NK>(yf, yq, ld_bytes, wq, lane);
       xs_load(xs, Xs + t0 * BN * ld_bytes, ld_bytes);
       xs.buf = 0;
+    } else {
+      split_start(sst, yq, Xs, ld_bytes, t0);
     }
   }
   // The data norms of a tile are fetched one tile ahead, one per thread, and
@@ -131,8 +255,10 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       stream_tile<T>(acc, st, yq, Xs, ld_bytes, nchunks, t, t1, lds, wq, wn, lane);
     else if constexpr (ENG == 1)
       ql_tile<T>(acc, ql, Xs, t, t1, lds, wq, wn, lane);
-    else
+    else if constexpr (ENG == 2)
       yreg_tile<T, NK>(acc, xs, yf, Xs, ld_bytes, t, t1, lds, wn, lane);
+    else
+      split_tile(acc, sst, yq, Xs, ld_bytes, nchunks, t, t1, lds, wq, wn, lane);
     // bit (4 i + j) * 4 + r of hm: element acc[i][j][r] of this lane is a
     // neighbour pair
     uint64_t hm = 0;
@@ -217,6 +343,7 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
               // padding columns: K = 0 times a finite norm term
               const float w = kv * (KERN == KERNEL_GAUSSIAN ? nl : fminf(nl, 3.0e38f));
               cqn[i][r] = __builtin_fmaf(w, w, cqn[i][r]);
+              if constexpr (KN) ckn[i][r] += fabsf(w);
             }
           }
           sum[i][r] += (double)part;
@@ -253,21 +380,24 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float a = csq[i][r], m = cmx[i][r], w = cqn[i][r];
+        float a = csq[i][r], m = cmx[i][r], w = cqn[i][r], kk = KN ? ckn[i][r] : 0.f;
 #pragma unroll
         for (int o = 1; o < 16; o <<= 1) {
           a += __shfl_xor(a, o, 64);
           w += __shfl_xor(w, o, 64);
+          if constexpr (KN) kk += __shfl_xor(kk, o, 64);
           const float mo = __shfl_xor(m, o, 64);
           m = KERN == KERNEL_GAUSSIAN ? m + mo : fmaxf(m, mo);
         }
         csq[i][r] = a;
         cmx[i][r] = m;
         cqn[i][r] = w;
+        if constexpr (KN) ckn[i][r] = kk;
       }
     __syncthreads();   // red is reused
     float2* cr = reinterpret_cast<float2*>(lds);   // [2][BQ]
     float* cw = reinterpret_cast<float*>(cr + 2 * BQ);   // [2][BQ]
+    float* ck = cw + 2 * BQ;                              // [2][BQ]
     if ((lane & 15) == 0) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -276,6 +406,7 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
           const int e = wn * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
           cr[e] = make_float2(csq[i][r], cmx[i][r]);
           cw[e] = cqn[i][r];
+          if constexpr (KN) ck[e] = ckn[i][r];
         }
     }
     __syncthreads();
@@ -284,6 +415,7 @@ kde_tile_kernel(const char* __restrict__ Ys, const char* __restrict__ Xs, int64_
       cert[split * qp + qt * BQ + threadIdx.x] =
           make_float2(a.x + b.x, KERN == KERNEL_GAUSSIAN ? a.y + b.y : fmaxf(a.y, b.y));
       certn[split * qp + qt * BQ + threadIdx.x] = cw[threadIdx.x] + cw[BQ + threadIdx.x];
+      if constexpr (KN) certk[split * qp + qt * BQ + threadIdx.x] = ck[threadIdx.x] + ck[BQ + threadIdx.x];
     }
   }
 }
@@ -440,7 +572,8 @@ kde_yres_kernel(TileProblem p, float Lf, double* __restrict__ partial, float2* _
 template <int KERN, int DPS, int NBI>
 __global__ void __launch_bounds__(YWG, NBI <= 2 ? 2 : 1)
 kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __restrict__ Ysp,
-                 float Lf, double* __restrict__ partial, float2* __restrict__ cert) {
+                 float Lf, double* __restrict__ partial, float2* __restrict__ cert,
+                 float* __restrict__ certk) {
   constexpr int TR = 16 * NBI;
   constexpr int KC = DPS / 32;                // 32-element k-chunks per plane
   constexpr int RB = 3 * DPS * 2;             // bytes per split row
@@ -496,8 +629,9 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
   };
 
   double sum = 0.0;
-  // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential: largest K
-  float csq = 0.f, cmx = 0.f;
+  // certificate: sum of K^2; Gaussian: sum of K times its exponent, exponential:
+  // largest K; sum of K N (the bfloat16 MFMA's truncation bias, see cert.h)
+  float csq = 0.f, cmx = 0.f, ckn = 0.f;
   if (u0 < u1) {
     gload(u0);
     lstore(0);
@@ -551,14 +685,17 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           float kv;
+          const float nl = yt + xt[r];   // -L N (Gaussian) or N; padding: huge
           if (KERN == KERNEL_GAUSSIAN) {
-            const float a = fminf(__builtin_fmaf(L2, acc[bi][r], yt + xt[r]), 0.f);
+            const float a = fminf(__builtin_fmaf(L2, acc[bi][r], nl), 0.f);
             kv = __builtin_amdgcn_exp2f(a);
             cmx = __builtin_fmaf(-kv, a, cmx);
+            ckn = __builtin_fmaf(kv, -nl, ckn);
           } else {
-            const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[bi][r], yt + xt[r]), 0.f);
+            const float d2 = fmaxf(__builtin_fmaf(-2.f, acc[bi][r], nl), 0.f);
             kv = __builtin_amdgcn_exp2f(-Lf * __builtin_sqrtf(d2));
             cmx = fmaxf(cmx, kv);
+            ckn = __builtin_fmaf(kv, fminf(nl, 3.0e38f), ckn);
           }
           part += kv;
           csq = __builtin_fmaf(kv, kv, csq);
@@ -579,9 +716,12 @@ kde_split_kernel(TileProblem p, const char* __restrict__ Xsp, const char* __rest
     cmx = fmaxf(cmx, __shfl_xor(cmx, 16, 64));
     cmx = fmaxf(cmx, __shfl_xor(cmx, 32, 64));
   }
+  ckn += __shfl_xor(ckn, 16, 64);
+  ckn += __shfl_xor(ckn, 32, 64);
   if (g == 0) {
     partial[split * p.qp + qt * BQ + wave * 16 + c] = sum;
     cert[split * p.qp + qt * BQ + wave * 16 + c] = make_float2(csq, cmx);
+    certk[split * p.qp + qt * BQ + wave * 16 + c] = ckn;
   }
 }
 
@@ -600,14 +740,19 @@ static hipError_t finish_fp32(const TileProblem& p, int kern, double h, float L,
 
 template <int KERN, int DPS>
 static void launch_split(const TileProblem& p, const void* Xsp, const void* Ysp, float L,
-                         double* partial, float2* cert, hipStream_t s) {
+                         double* partial, float2* cert, float* certk, hipStream_t s) {
   TileProblem q = p;
   q.map = make_tile_map(p.qtiles, p.splits, 1);
   constexpr int NBI = DPS == 64 ? 4 : SPLIT_NBI;   // whole 16-byte pieces per thread
   kde_split_kernel<KERN, DPS, NBI><<<dim3((unsigned)q.map.grid), dim3(YWG), 0, s>>>(
       q, reinterpret_cast<const char*>(Xsp), reinterpret_cast<const char*>(Ysp), L, partial,
-      cert);
+      cert, certk);
 }
+
+template <typename T, int KERN, int ENG, bool HYB = false>
+static void launch_kde_k(const TileProblem& p, float L, double* partial, hipStream_t s,
+                         const int32_t* hoff = nullptr, const uint16_t* hits = nullptr,
+                         float2* cert = nullptr, float* certn = nullptr, float* certk = nullptr);
 
 hipError_t launch_kde_exact_split(const TileProblem& p, const void* Xsp, const void* Ysp,
                                   int64_t dps, int kern, double h, double* partial, double* out,
@@ -619,21 +764,34 @@ hipError_t launch_kde_exact_split(const TileProblem& p, const void* Xsp, const v
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
   if (dps == 64) {
     if (kern == KERNEL_GAUSSIAN)
-      launch_split<KERNEL_GAUSSIAN, 64>(p, Xsp, Ysp, L, partial, ca.part, s);
+      launch_split<KERNEL_GAUSSIAN, 64>(p, Xsp, Ysp, L, partial, ca.part, ca.pk, s);
     else
-      launch_split<KERNEL_EXPONENTIAL, 64>(p, Xsp, Ysp, L, partial, ca.part, s);
+      launch_split<KERNEL_EXPONENTIAL, 64>(p, Xsp, Ysp, L, partial, ca.part, ca.pk, s);
   } else if (dps == 128) {
     if (kern == KERNEL_GAUSSIAN)
-      launch_split<KERNEL_GAUSSIAN, 128>(p, Xsp, Ysp, L, partial, ca.part, s);
+      launch_split<KERNEL_GAUSSIAN, 128>(p, Xsp, Ysp, L, partial, ca.part, ca.pk, s);
     else
-      launch_split<KERNEL_EXPONENTIAL, 128>(p, Xsp, Ysp, L, partial, ca.part, s);
+      launch_split<KERNEL_EXPONENTIAL, 128>(p, Xsp, Ysp, L, partial, ca.part, ca.pk, s);
+  } else if (dps > 128 && dps % 32 == 0) {
+    // wider rows: the generic tile kernel's split engine (query tiles streamed)
+    TileProblem q = p;
+    q.Ys = reinterpret_cast<const char*>(Ysp);
+    q.Xs = reinterpret_cast<const char*>(Xsp);
+    q.ld_bytes = 6 * dps;
+    q.nchunks = (int)(dps / 32);
+    if (kern == KERNEL_GAUSSIAN)
+      launch_kde_k<float, KERNEL_GAUSSIAN, 3>(q, L, partial, s, nullptr, nullptr, ca.part, ca.pn,
+                                              ca.pk);
+    else
+      launch_kde_k<float, KERNEL_EXPONENTIAL, 3>(q, L, partial, s, nullptr, nullptr, ca.part,
+                                                 ca.pn, ca.pk);
   } else {
     return hipErrorInvalidValue;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (th.stop && (e = hipEventRecord(th.stop, s)) != hipSuccess) return e;
   CertArgs cb = ca;
-  cb.pn = nullptr;   // the split kernel keeps no per-pair norm sums
+  if (dps <= 128) cb.pn = nullptr;   // the resident-query split kernel keeps no sums of (K N)^2
   return finish_fp32(p, kern, h, L, partial, out, s, cb, X, Y, d, fb_part);
 }
 
@@ -656,13 +814,13 @@ __global__ void kde_reduce_kernel(const double* __restrict__ partial, int64_t sp
   out[i] = s * inv_n;
 }
 
-template <typename T, int KERN, int ENG, bool HYB = false>
+template <typename T, int KERN, int ENG, bool HYB>
 static void launch_kde_k(const TileProblem& p, float L, double* partial, hipStream_t s,
-                         const int32_t* hoff = nullptr, const uint16_t* hits = nullptr,
-                         float2* cert = nullptr, float* certn = nullptr) {
+                         const int32_t* hoff, const uint16_t* hits, float2* cert, float* certn,
+                         float* certk) {
   kde_tile_kernel<T, KERN, ENG, HYB><<<dim3((unsigned)p.map.grid), dim3(WG), 0, s>>>(
       p.Ys, p.Xs, p.ld_bytes, p.nchunks, p.ynorm, p.xnorm, p.n, p.qtiles, p.splits, p.ntiles, L,
-      partial, p.qp, p.map, hoff, hits, cert, certn);
+      partial, p.qp, p.map, hoff, hits, cert, certn, certk);
 }
 
 template <typename T, int KERN>
@@ -758,6 +916,7 @@ hipError_t launch_kde_exact(int prec, const TileProblem& p, int kern, double h, 
   hipError_t e;
   if (th.start && (e = hipEventRecord(th.start, s)) != hipSuccess) return e;
   CertArgs cb = ca;
+  cb.pk = nullptr;   // float32 MFMAs round to nearest: no bias term
   switch (prec) {
     case PREC_FP32: e = launch_kde_t<float>(p, kern, L, partial, ca.part, &cb.pn, s); break;
     case PREC_BF16: e = launch_kde_t<__bf16>(p, kern, L, partial, nullptr, nullptr, s); break;

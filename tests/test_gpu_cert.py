@@ -93,12 +93,14 @@ def test_exact_small_bandwidth_values_and_gradients(c1, kern, scale, prec):
         assert st["exact_refined"] > 0   # this case does exercise the fallback
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp32_split"])
 @pytest.mark.parametrize("h", [2.5, 5.0])
 @pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
-def test_exact_wide_rows_certificate(kern, h):
-    # rows wider than 128 floats take the generic float32 tile kernel, whose
-    # certificate uses each pair's own norm term; a few far rows make the
-    # largest row norm much larger than the norms of the pairs that matter
+def test_exact_wide_rows_certificate(kern, h, prec):
+    # rows wider than 128 floats take the generic tile kernel (float32 or
+    # split operands), whose certificate uses each pair's own norm term; a few
+    # far rows make the largest row norm much larger than the norms of the
+    # pairs that matter
     import paper_2107_02736_amd as dk
     rng = np.random.default_rng(21)
     n, q, d = 4000, 200, 200
@@ -108,11 +110,11 @@ def test_exact_wide_rows_certificate(kern, h):
     Y = cen[rng.integers(0, 5, q)] + rng.normal(size=(q, d))
     X, Y = X.astype(np.float32), Y.astype(np.float32)
     dev = device()
-    got = dk.kde_exact(to_dev(X, dev), to_dev(Y, dev), h, KNAME[kern], "fp32").cpu().numpy()
+    got = dk.kde_exact(to_dev(X, dev), to_dev(Y, dev), h, KNAME[kern], prec).cpu().numpy()
     st = dk.last_stats(dev)
     ref = oracle.kde_exact(X, Y, h, kern)
     err, excluded = rel_err(got, ref)
-    print(f"{KNAME[kern]} h={h}: re-evaluated {st['exact_refined']} of {q}, max rel err "
+    print(f"{KNAME[kern]} {prec} h={h}: re-evaluated {st['exact_refined']} of {q}, max rel err "
           f"{err.max():.2e}, {excluded} below 1e-16")
     assert err.max() <= 1e-5
 

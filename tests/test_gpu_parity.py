@@ -126,25 +126,35 @@ def _small(n, q, d, seed=0):
     return X, Y
 
 
+@pytest.mark.parametrize("kern", [GAUSSIAN, EXPONENTIAL])
 @pytest.mark.parametrize("n,q,d", [(1000, 37, 9), (129, 1, 3), (1, 5, 2), (300, 130, 33),
-                                   (700, 50, 100), (500, 20, 128)])
-def test_edge_shapes_split_exact(dev, n, q, d):
+                                   (700, 50, 100), (500, 20, 128),
+                                   # wider rows: the split engine of the generic tile kernel
+                                   (300, 130, 129), (1000, 37, 300), (129, 3, 960),
+                                   (2500, 140, 500), (1, 2, 200)])
+def test_edge_shapes_split_exact(dev, n, q, d, kern):
     # the three-part bfloat16 form: every query within 1e-5, as the float32 path
     import paper_2107_02736_amd as dk
     X, Y = _small(n, q, d, seed=n + d)
     Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
-    h = 2.0 + 0.1 * d
-    ref = oracle.kde_exact(X, Y, h, GAUSSIAN)
-    got = dk.kde_exact(Xd, Yd, h, "gaussian", "fp32_split").cpu().numpy()
+    h = 2.0 + 0.1 * d if kern == GAUSSIAN else 1.0 + 0.05 * d
+    ref = oracle.kde_exact(X, Y, h, kern)
+    got = dk.kde_exact(Xd, Yd, h, KNAME[kern], "fp32_split").cpu().numpy()
     err, _ = rel_err(got, ref)
     assert err.max() <= 1e-5, err.max()
 
 
 def test_split_precision_width_limit(dev):
+    # the split form of the adjoint and of the fused value + gradient pass
+    # takes rows of at most 128 floats; kde_exact takes any width
     import paper_2107_02736_amd as dk
     X, Y = _small(200, 4, 129, seed=1)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
     with pytest.raises(dk.DeannError):
-        dk.kde_exact(to_dev(X, dev), to_dev(Y, dev), 3.0, "gaussian", "fp32_split")
+        dk.kde_exact_with_grad(Xd, Yd, 3.0, "gaussian", precision="fp32_split")
+    got = dk.kde_exact(Xd, Yd, 3.0, "gaussian", "fp32_split").cpu().numpy()
+    err, _ = rel_err(got, oracle.kde_exact(X, Y, 3.0, GAUSSIAN))
+    assert err.max() <= 1e-5
 
 
 @pytest.mark.parametrize("n,q,d", [(1000, 37, 9), (129, 1, 3), (1, 5, 2), (300, 130, 33),

@@ -1062,10 +1062,9 @@ hipError_t launch_kde_backward(const TileProblem& p, const float* X, const float
   // exact re-evaluation of the listed queries; its scratch reuses the sweep's
   // partials, which the reduction has consumed: value and h sums in the gh and
   // rw parts, the weighted row sums in gy_part ([splits][qp][dp] >= [fs][q][dp])
-  const int64_t fs = p.splits < 64 ? p.splits : 64;
-  e = launch_kde_direct_grad(X, Y, p.n, p.q, d, h, kern, ca.fb_ids, ca.fb_count, fs, gh_part,
-                             rw_part, gy_part, dp, grad_out, grad_Y, need_ghq ? ghq : nullptr, mu,
-                             s);
+  e = launch_kde_direct_grad(X, Y, p.n, p.q, d, h, kern, ca.fb_ids, ca.fb_count,
+                             p.splits * p.qp, gh_part, rw_part, gy_part, dp, grad_out, grad_Y,
+                             need_ghq ? ghq : nullptr, mu, s);
   if (e != hipSuccess) return e;
   if (!grad_h) return hipSuccess;
   sum_scalar_kernel<<<dim3(1), dim3(WG), 0, s>>>(ghq, p.q, grad_h);

@@ -80,6 +80,18 @@ constexpr int DQT = 16;      // queries per item
 constexpr int DROWS = 64;    // data rows per block (gradient kernel)
 constexpr int DG_MAXD = 128; // width limit of the gradient kernel
 
+// Row ranges of the gradient kernel for F listed queries: about one per 2048
+// rows (at most 512), as many as a scratch of cap entries per array holds
+// (entry sp * F + slot; the weighted row sums take ldg of them each), so that
+// a few listed queries still spread over the whole GPU.
+__host__ __device__ inline int64_t direct_grad_splits(int64_t F, int64_t cap, int64_t n) {
+  int64_t s = (n + 2047) / 2048;
+  if (s > 512) s = 512;
+  const int64_t room = F > 0 ? cap / F : cap;
+  if (s > room) s = room;
+  return s < 1 ? 1 : s;
+}
+
 // Value-only kernel: blocks of 256 rows, coordinates staged 32 at a time in
 // LDS transposed ([coordinate][row], float) so that thread (rb, g) =
 // (tid % 64, tid / 64) reads rows 4 rb .. 4 rb + 3 of one coordinate with one
@@ -217,13 +229,14 @@ template <int KERN>
 __global__ void __launch_bounds__(WG)
 kde_direct_grad_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t n,
                        int64_t d, double h, const int32_t* __restrict__ ids,
-                       const int32_t* __restrict__ count, int64_t splits, int64_t q,
+                       const int32_t* __restrict__ count, int64_t cap,
                        double* __restrict__ pval, double* __restrict__ pgh,
                        double* __restrict__ pG, int64_t ldg) {
   __shared__ float xs[DROWS][DG_MAXD + 1];
   __shared__ double ys[DQT][DG_MAXD];
   __shared__ double ws[DQT][DROWS];
   const int64_t F = *count;
+  const int64_t splits = direct_grad_splits(F, cap, n);
   const int64_t items = ceil_div(F, DQT) * splits;
   const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int qq = threadIdx.x >> 4, cl = threadIdx.x & 15;
@@ -296,8 +309,8 @@ kde_direct_grad_kernel(const float* __restrict__ X, const float* __restrict__ Y,
       }
       const int64_t slot = tile * DQT + 4 * g + j;
       if (r == 0 && slot < F) {
-        pval[sp * q + slot] = a;
-        pgh[sp * q + slot] = b;
+        pval[sp * F + slot] = a;
+        pgh[sp * F + slot] = b;
       }
     }
     const int64_t slot = tile * DQT + qq;
@@ -305,7 +318,7 @@ kde_direct_grad_kernel(const float* __restrict__ X, const float* __restrict__ Y,
 #pragma unroll
       for (int j = 0; j < NCT; ++j) {
         const int t = cl + 16 * j;
-        if (t < d) pG[(sp * q + slot) * ldg + t] = G[j];
+        if (t < d) pG[(sp * F + slot) * ldg + t] = G[j];
       }
   }
 }
@@ -316,21 +329,23 @@ __global__ void kde_direct_grad_reduce_kernel(const double* __restrict__ pval,
                                               const double* __restrict__ pgh,
                                               const double* __restrict__ pG, int64_t ldg,
                                               const int32_t* __restrict__ ids,
-                                              const int32_t* __restrict__ count, int64_t splits,
-                                              int64_t q, int64_t n, int64_t d, double c_y,
+                                              const int32_t* __restrict__ count, int64_t cap,
+                                              int64_t n, int64_t d, double c_y,
                                               double c_h, const double* __restrict__ grad_out,
                                               float* __restrict__ grad_Y,
                                               double* __restrict__ ghq, double* __restrict__ mu) {
   const int64_t slot = blockIdx.x;
-  if (slot >= *count) return;
+  const int64_t F = *count;
+  if (slot >= F) return;
+  const int64_t splits = direct_grad_splits(F, cap, n);
   const int64_t qi = ids[slot];
   const double g = grad_out ? grad_out[qi] : 1.0;
   const double inv_n = 1.0 / (double)n;
   if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
     for (int64_t sp = 0; sp < splits; ++sp) {
-      a += pval[sp * q + slot];
-      b += pgh[sp * q + slot];
+      a += pval[sp * F + slot];
+      b += pgh[sp * F + slot];
     }
     if (ghq) ghq[qi] = g * inv_n * c_h * b;
     if (mu) mu[qi] = a * inv_n;
@@ -338,7 +353,7 @@ __global__ void kde_direct_grad_reduce_kernel(const double* __restrict__ pval,
   if (!grad_Y) return;
   for (int64_t t = threadIdx.x; t < d; t += blockDim.x) {
     double s = 0.0;
-    for (int64_t sp = 0; sp < splits; ++sp) s += pG[(sp * q + slot) * ldg + t];
+    for (int64_t sp = 0; sp < splits; ++sp) s += pG[(sp * F + slot) * ldg + t];
     grad_Y[qi * d + t] = (float)(g * inv_n * c_y * s);
   }
 }
@@ -398,26 +413,27 @@ hipError_t launch_kde_direct(const float* X, const float* Y, int64_t n, int64_t 
 
 hipError_t launch_kde_direct_grad(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                                   double h, int kern, const int32_t* ids, const int32_t* count,
-                                  int64_t splits, double* pval, double* pgh, double* pG,
+                                  int64_t cap, double* pval, double* pgh, double* pG,
                                   int64_t ldg, const double* grad_out, float* grad_Y, double* ghq,
                                   double* mu, hipStream_t s) {
   if (q == 0) return hipSuccess;
-  if (d > DG_MAXD || ldg < d) return hipErrorInvalidValue;
-  const int64_t items = ceil_div(q, DQT) * splits;
-  const dim3 grid((unsigned)(items < kDirectGrid ? items : kDirectGrid)), block(WG);
+  if (d > DG_MAXD || ldg < d || cap < q) return hipErrorInvalidValue;
+  // the listed count is known on the device only: a grid-stride loop over the
+  // items it implies, as many as the scratch holds (see direct_grad_splits)
+  const dim3 grid((unsigned)kDirectGrid), block(WG);
   if (kern == KERNEL_GAUSSIAN)
     kde_direct_grad_kernel<KERNEL_GAUSSIAN><<<grid, block, 0, s>>>(X, Y, n, d, h, ids, count,
-                                                                   splits, q, pval, pgh, pG, ldg);
+                                                                   cap, pval, pgh, pG, ldg);
   else
     kde_direct_grad_kernel<KERNEL_EXPONENTIAL><<<grid, block, 0, s>>>(
-        X, Y, n, d, h, ids, count, splits, q, pval, pgh, pG, ldg);
+        X, Y, n, d, h, ids, count, cap, pval, pgh, pG, ldg);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // Gaussian: w = K, dh terms K d^2; exponential: w = K / r, dh terms K r
   const double c_y = kern == KERNEL_GAUSSIAN ? 1.0 / (h * h) : 1.0 / h;
   const double c_h = kern == KERNEL_GAUSSIAN ? 1.0 / (h * h * h) : 1.0 / (h * h);
   kde_direct_grad_reduce_kernel<<<dim3((unsigned)q), dim3(128), 0, s>>>(
-      pval, pgh, pG, ldg, ids, count, splits, q, n, d, c_y, c_h, grad_out, grad_Y, ghq, mu);
+      pval, pgh, pG, ldg, ids, count, cap, n, d, c_y, c_h, grad_out, grad_Y, ghq, mu);
   return hipGetLastError();
 }
 

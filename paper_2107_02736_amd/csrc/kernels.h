@@ -87,9 +87,10 @@ hipError_t launch_kde_direct(const float* X, const float* Y, int64_t n, int64_t 
 // Exact FP64 value, gradient and per-query d/dh of the listed queries (d <= 128):
 // pval, pgh [splits][q] and pG [splits][q][ldg] scratch; overwrites the
 // entries of grad_Y, ghq and mu (each may be NULL) of the listed queries.
+// cap: entries of each scratch array (pval, pgh; pG holds cap * ldg), at least q
 hipError_t launch_kde_direct_grad(const float* X, const float* Y, int64_t n, int64_t q, int64_t d,
                                   double h, int kern, const int32_t* ids, const int32_t* count,
-                                  int64_t splits, double* pval, double* pgh, double* pG,
+                                  int64_t cap, double* pval, double* pgh, double* pG,
                                   int64_t ldg, const double* grad_out, float* grad_Y, double* ghq,
                                   double* mu, hipStream_t s);
 

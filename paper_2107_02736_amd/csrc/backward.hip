@@ -182,9 +182,10 @@ deann_backward_vec_kernel(const float* __restrict__ X, const float* __restrict__
   // (one coalesced read instead of an index load in front of every row load),
   // and group g takes rows g, g + NG, ... of the chunk with the next rows in
   // flight behind the one it evaluates.
-  // wide rows (a wave per row) keep two rows in flight per group, 16-lane
-  // groups one (their extra registers would cost occupancy)
-  constexpr bool TWO = GW == 64;
+  // wide rows (a wave per row) and rows of up to 128 coordinates keep two rows
+  // in flight per group, other 16-lane groups one (their extra registers would
+  // cost occupancy)
+  constexpr bool TWO = GW == 64 || U <= 2;
   float xv[U][4], xa[U][4], xb[U][4];
   for (int64_t c0 = 0; c0 < R; c0 += BWD_IDX) {
     const int cnt = (int)(R - c0 < BWD_IDX ? R - c0 : BWD_IDX);

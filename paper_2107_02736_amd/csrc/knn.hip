@@ -810,7 +810,9 @@ knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   const int64_t qi = blockIdx.x;
   if (b.status[qi] != 1) return;
   const int C = b.cand2_cnt[qi];
-  if (C > b.cap2 || C > SORT_CAP) {
+  // the second pass collects at least the k rows its threshold came from, so
+  // C < k cannot occur; should it, the exhaustive scan answers the query
+  if (C > b.cap2 || C > SORT_CAP || C < a.k) {
     if (threadIdx.x == 0) b.status[qi] = 2;
     return;
   }

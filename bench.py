@@ -68,6 +68,9 @@ def parse():
                          "cluster counts and inspected clusters, then exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (counter calibration)")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="only measure the access patterns of the hot kernels without their "
+                         "arithmetic (libdeann_ceiling.so) and a library BF16 GEMM, then exit")
     return ap.parse_args()
 
 
@@ -82,6 +85,80 @@ def calibrate_copy():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 3}))
+
+
+def ceilings():
+    """What the hot kernels' own data movement reaches with their arithmetic
+    taken out, at the shapes of the two full-size workloads (random data):
+    random-row gathers of k + m rows per query as in the DEANN gather, and the
+    16-bit tile sweep of the k-NN passes with no epilogue; beside them a library
+    BF16 GEMM (torch.matmul) at the same inner dimension."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2107_02736_amd", "libdeann_ceiling.so"))
+    i64, vp = ctypes.c_int64, ctypes.c_void_p
+    lib.ceiling_gather.restype = ctypes.c_int
+    lib.ceiling_gather.argtypes = [vp, i64, i64, vp, i64, i64, vp, vp]
+    lib.ceiling_tile_sweep.restype = ctypes.c_int
+    lib.ceiling_tile_sweep.argtypes = [vp, i64, vp, i64, i64, i64, vp, vp]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    n, q = 1_000_000, 10_000
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {}
+    for d, (k, m) in ((960, KM["mix200_n1e6_d960"]), (128, KM["mix100_n1e6_d128"])):
+        X = torch.randn((n, d), device=dev, generator=gen)
+        idx = torch.randint(0, n, (q, k + m), device=dev, dtype=torch.int32, generator=gen)
+        out = torch.empty(q * 256, device=dev)
+
+        def gather():
+            st = lib.ceiling_gather(X.data_ptr(), n, d, idx.data_ptr(), q, k + m, out.data_ptr(),
+                                    stream)
+            if st != 0:
+                raise RuntimeError(f"ceiling_gather: hipError {st}")
+        ms = timed(gather)
+        gb = q * (k + m) * d * 4
+        res[f"gather_d{d}"] = {"rows_per_query": k + m, "ms": round(ms, 4),
+                               "TB_per_s": round(gb / ms / 1e9, 3),
+                               "frac_hbm": round(gb / ms / 1e9 / (PEAK_HBM / 1e12), 3)}
+        del X, idx
+        qp, np_, dp = (q + 127) // 128 * 128, (n + 127) // 128 * 128, (d + 63) // 64 * 64
+        Ys = torch.randn((qp, dp), device=dev, generator=gen).to(torch.bfloat16)
+        Xs = torch.randn((np_, dp), device=dev, generator=gen).to(torch.bfloat16)
+
+        def sweep():
+            st = lib.ceiling_tile_sweep(Ys.data_ptr(), qp, Xs.data_ptr(), np_, dp, 4096,
+                                        out.data_ptr(), stream)
+            if st != 0:
+                raise RuntimeError(f"ceiling_tile_sweep: hipError {st}")
+        ms = timed(sweep, reps=3)
+        fl = 2.0 * n * q * d
+        res[f"bf16_tile_sweep_d{d}"] = {"ms": round(ms, 3), "TFLOP_per_s": round(fl / ms / 1e9, 1),
+                                        "frac_bf16": round(fl / ms / 1e9 / (PEAK_BF16_MFMA / 1e12), 3)}
+        del Xs
+        B = torch.randn((262144, d), device=dev, generator=gen).to(torch.bfloat16)
+        A = Ys[:q, :d].contiguous()
+        ms = timed(lambda: torch.matmul(A, B.t()), reps=3)
+        fl = 2.0 * q * 262144 * d
+        res[f"library_bf16_gemm_k{d}"] = {"shape": [q, 262144, d], "ms": round(ms, 3),
+                                          "TFLOP_per_s": round(fl / ms / 1e9, 1),
+                                          "frac_bf16": round(fl / ms / 1e9 / (PEAK_BF16_MFMA / 1e12), 3)}
+        del A, B, Ys
+        torch.cuda.empty_cache()
+    print(json.dumps({"ceilings": res, "n": n, "q": q, "data": "synthetic random"}))
 
 
 def counters_path(workload):
@@ -132,6 +209,9 @@ def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.ceilings:
+        ceilings()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the query path needs no communication "

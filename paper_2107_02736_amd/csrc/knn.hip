@@ -477,6 +477,14 @@ struct RefineArgs {
   double h;
   int kern;
   int approx;   // candidates come from the cell pass: no certificate, always collect
+  // second refinement only: entries of its LDS sort and of its exact list (the
+  // dynamic LDS of the launch is sized from them), and whether this launch
+  // takes only the queries whose list fits (`small`: the others are left to a
+  // launch with the full capacity)
+  int sort_cap = SORT_CAP;   // keys of the sort of the list
+  int ex_cap = SORT_CAP;     // exact (distance, index) pairs after it
+  int kd_cap = K_MAX;
+  int small = 0;
 };
 
 // The K1 smallest of a query's `cells` cell candidates (packed key, index;
@@ -504,9 +512,12 @@ __device__ void cells_wave_select(const uint64_t* __restrict__ cand, int64_t qp,
     const int el = lane * EPL + r;
     if (el < K1) buf[wave * K1 + el] = v[r];
   }
+  // the bitonic sort takes a power of two: pad the waves' lists with empty cells
+  const int M = (WG / 64) * K1, N = next_pow2(M);
+  for (int i = M + threadIdx.x; i < N; i += WG) buf[i] = ~0ull;
   if (lane == 0) valid_w[wave] = valid;
   __syncthreads();
-  block_sort_u64(buf, (WG / 64) * K1);
+  block_sort_u64(buf, N);
   if (threadIdx.x == 0) {
     int tot = 0;
     for (int w = 0; w < WG / 64; ++w) tot += valid_w[w];
@@ -518,11 +529,13 @@ __device__ void cells_wave_select(const uint64_t* __restrict__ cand, int64_t qp,
 __global__ void __launch_bounds__(WG)
 knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  uint64_t* buf = reinterpret_cast<uint64_t*>(smem);                  // SORT_CAP
-  uint64_t* dkey = buf + SORT_CAP;                                     // K_MAX
-  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + K_MAX);         // K_MAX
-  uint32_t* tmp = didx + K_MAX;                                        // K_MAX
-  double* red = reinterpret_cast<double*>(tmp + K_MAX);               // WG
+  // sort_cap: merge buffer entries, kd_cap >= K1: exact candidates (even counts)
+  const int bcap = a.sort_cap, kcap = a.kd_cap;
+  uint64_t* buf = reinterpret_cast<uint64_t*>(smem);                  // bcap
+  uint64_t* dkey = buf + bcap;                                         // kcap
+  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + kcap);          // kcap
+  uint32_t* tmp = didx + kcap;                                         // kcap
+  double* red = reinterpret_cast<double*>(tmp + kcap);                // WG
   float* ys = reinterpret_cast<float*>(red + WG);                      // d
   __shared__ int fill_s;
   const int64_t qi = blockIdx.x;
@@ -543,8 +556,8 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
       cells_wave_select<16>(b.cand, a.qp, qi, cells, K1, buf, &fill_s);
   } else if (a.approx) {
     // cell candidates: CELLS per (split, query), contiguous; read in chunks of
-    // at most SORT_CAP - K1 entries whose loads are all in flight together
-    const int64_t total = a.splits * (int64_t)CELLS, chunk = SORT_CAP - K1;
+    // at most bcap - K1 entries whose loads are all in flight together
+    const int64_t total = a.splits * (int64_t)CELLS, chunk = bcap - K1;
     for (int64_t c0 = 0; c0 < total; c0 += chunk) {
       const int64_t c1 = c0 + chunk < total ? c0 + chunk : total;
       __syncthreads();   // every thread has read fill_s for the previous decision
@@ -558,7 +571,7 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
       // it is sorted whenever the K1-th key is used
       if ((last && fill_s >= K1) || (!last && fill_s > K1)) {
         const int F = fill_s;
-        const int N = next_pow2(F);   // <= SORT_CAP
+        const int N = next_pow2(F);   // <= bcap
         for (int i = F + threadIdx.x; i < N; i += WG) buf[i] = ~0ull;
         __syncthreads();
         block_sort_u64(buf, N);
@@ -578,10 +591,10 @@ knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
       if (v != ~0ull) buf[atomicAdd(&fill_s, 1)] = v;
     }
     __syncthreads();
-    const bool flush = (fill_s + K1 > SORT_CAP) || (s + 1 == a.splits);
+    const bool flush = (fill_s + K1 > bcap) || (s + 1 == a.splits);
     if (flush && fill_s >= K1) {   // sorted whenever the K1-th key is used
       const int F = fill_s;
-      const int N = next_pow2(F);   // <= SORT_CAP
+      const int N = next_pow2(F);   // <= bcap
       for (int i = F + threadIdx.x; i < N; i += WG) buf[i] = ~0ull;
       __syncthreads();
       block_sort_u64(buf, N);
@@ -800,11 +813,13 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
 __global__ void __launch_bounds__(WG)
 knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  uint64_t* dkey = reinterpret_cast<uint64_t*>(smem);                // SORT_CAP
-  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + SORT_CAP);      // SORT_CAP
-  uint64_t* kd = reinterpret_cast<uint64_t*>(didx + SORT_CAP);        // K_MAX
-  uint32_t* tmp = reinterpret_cast<uint32_t*>(kd + K_MAX);            // K_MAX
-  double* red = reinterpret_cast<double*>(tmp + K_MAX);               // WG
+  // even counts: 8-byte alignment holds; ecap <= cap
+  const int cap = a.sort_cap, ecap = a.ex_cap, kcap = a.kd_cap;
+  uint64_t* dkey = reinterpret_cast<uint64_t*>(smem);                // cap
+  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + cap);           // ecap
+  uint64_t* kd = reinterpret_cast<uint64_t*>(didx + ecap);            // kcap
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(kd + kcap);             // kcap
+  double* red = reinterpret_cast<double*>(tmp + kcap);                // WG
   float* ys = reinterpret_cast<float*>(red + WG);                      // d
   __shared__ int kept_s;
   const int64_t qi = blockIdx.x;
@@ -812,8 +827,8 @@ knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   const int C = b.cand2_cnt[qi];
   // the second pass collects at least the k rows its threshold came from, so
   // C < k cannot occur; should it, the exhaustive scan answers the query
-  if (C > b.cap2 || C > SORT_CAP || C < a.k) {
-    if (threadIdx.x == 0) b.status[qi] = 2;
+  if (C > b.cap2 || C > cap || C < a.k) {
+    if (threadIdx.x == 0 && !a.small) b.status[qi] = 2;
     return;
   }
   for (int64_t t = threadIdx.x; t < a.d; t += WG) ys[t] = a.Y[qi * a.d + t];
@@ -864,6 +879,9 @@ knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
     __syncthreads();
     cstar = P + kept_s;
   }
+  // (uniform) more exact pairs than this launch holds: the query stays listed
+  // for the launch with the full capacity
+  if (next_pow2(cstar > 1 ? cstar : 2) > ecap) return;
   // 4. the P evaluated entries in front, then the exact distances of [P, cstar)
   for (int c0 = P + g; c0 < cstar; c0 += 4 * (WG / 16)) {
     int64_t rr[4];
@@ -1095,6 +1113,38 @@ static int64_t seed_stride(int64_t ntiles, int64_t want) {
   return want < most ? want : (most > 1 ? most : 1);
 }
 
+// The second refinement in two launches: first with LDS for lists of at most
+// REFINE2_SORT entries of which at most REFINE2_EXACT are evaluated exactly
+// (five or six workgroups per CU), then with the full capacity for the queries
+// left (longer lists, and the ones for the exhaustive scan).
+constexpr int REFINE2_SORT = 2048, REFINE2_EXACT = 1024;
+
+hipError_t launch_refine2(RefineArgs a, const KnnBuffers& b, int32_t* nn_out, int64_t d,
+                          hipStream_t s) {
+  int kcap = 2;
+  while (kcap < (int)b.K1) kcap <<= 1;
+  if (kcap > K_MAX) kcap = K_MAX;
+  const dim3 g((unsigned)a.q), blk(WG);
+  RefineArgs sa = a;
+  sa.sort_cap = REFINE2_SORT;
+  sa.ex_cap = REFINE2_EXACT;
+  sa.kd_cap = kcap;
+  sa.small = 1;
+  const size_t sm_small = (size_t)REFINE2_SORT * 8 + (size_t)REFINE2_EXACT * 4 +
+                          (size_t)kcap * (8 + 4) + WG * 8 + d * 4;
+  knn_refine2_kernel<<<g, blk, sm_small, s>>>(sa, b, nn_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  RefineArgs la = a;
+  la.sort_cap = SORT_CAP;
+  la.ex_cap = SORT_CAP;
+  la.kd_cap = K_MAX;
+  la.small = 0;
+  const size_t sm = (size_t)SORT_CAP * (8 + 4) + (size_t)K_MAX * (8 + 4) + WG * 8 + d * 4;
+  knn_refine2_kernel<<<g, blk, sm, s>>>(la, b, nn_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, const KnnBuffers& b,
                       const float* X, const float* Y, int64_t d, int64_t k, double h, int kern,
                       int32_t* nn_out, hipStream_t s) {
@@ -1132,14 +1182,26 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
     e = launch_tiles_prec(prec, p, b, false, s);
     if (e != hipSuccess) return e;
   }
-  const size_t sm1 = SORT_CAP * 8 + K_MAX * (8 + 4 + 4) + WG * 8 + d * 4;
-  knn_refine_kernel<<<dim3((unsigned)p.q), dim3(WG), sm1, s>>>(a, bb, nn_out);
+  // the cell selection in registers needs 4 K1 merge entries (rounded up to a
+  // power of two) and K1 exact ones: several workgroups per CU; list merges
+  // take the full buffers
+  RefineArgs ra = a;
+  if (a.approx && a.splits * (int64_t)CELLS <= (WG / 64) * 64 * 16 && bb.K1 <= 512) {
+    int kcap = 2;
+    while (kcap < (int)bb.K1) kcap <<= 1;
+    ra.sort_cap = (WG / 64) * kcap;
+    ra.kd_cap = kcap;
+  } else {
+    ra.sort_cap = SORT_CAP;
+    ra.kd_cap = K_MAX;
+  }
+  const size_t sm1 = (size_t)ra.sort_cap * 8 + (size_t)ra.kd_cap * (8 + 4 + 4) + WG * 8 + d * 4;
+  knn_refine_kernel<<<dim3((unsigned)p.q), dim3(WG), sm1, s>>>(ra, bb, nn_out);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   e = launch_tiles_prec(prec, pc, b, true, s);
   if (e != hipSuccess) return e;
+  if ((e = launch_refine2(a, bb, nn_out, d, s)) != hipSuccess) return e;
   const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * (8 + 4) + WG * 8 + d * 4;
-  knn_refine2_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, bb, nn_out);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   knn_exhaustive_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, bb, nn_out);
   return hipGetLastError();
 }
@@ -1583,9 +1645,7 @@ hipError_t launch_ivf_knn(const IvfTiles& t, int64_t prow_cap, const KnnBuffers&
   if ((e = hipGetLastError()) != hipSuccess) return e;
   ivf_collect_kernel<<<g, blk, 0, s>>>(t, b);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t smr = SORT_CAP * (8 + 4) + K_MAX * (8 + 4) + WG * 8 + d * 4;
-  knn_refine2_kernel<<<dim3((unsigned)q), dim3(WG), smr, s>>>(a, b, nn_out);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_refine2(a, b, nn_out, d, s)) != hipSuccess) return e;
   const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * 4 + WG * 8 + ((d + 3) & ~3ll) * 4 +
                      (v.kp + 1) * 8;
   ivf_exhaustive_kernel<<<dim3((unsigned)q), dim3(WG), sm2, s>>>(a, b, v, nn_out);

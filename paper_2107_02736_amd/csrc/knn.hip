@@ -920,10 +920,11 @@ constexpr int EXH_CHUNK = 512;   // rows examined between checks of the candidat
 // back only when another chunk could overflow it (and after the last chunk),
 // so once the cut-off is tight almost every row is a compare and nothing else.
 struct ExhaustiveTop {
-  int kkeep;
+  int kkeep, cap;   // cap: buffer entries, a power of two >= kkeep + EXH_CHUNK
   uint64_t kth_key = ~0ull;
   uint32_t kth_idx = 0xffffffffu;
-  __device__ explicit ExhaustiveTop(int k) : kkeep(k + 32 < SORT_CAP / 2 ? k + 32 : SORT_CAP / 2) {}
+  __device__ ExhaustiveTop(int k, int cap_)
+      : kkeep(k + 32 < cap_ - EXH_CHUNK ? k + 32 : cap_ - EXH_CHUNK), cap(cap_) {}
   __device__ void offer(uint64_t kb, uint32_t id, uint64_t* dkey, uint32_t* didx, int* fill) {
     if (kb < kth_key || (kb == kth_key && id < kth_idx)) {
       const int slot = atomicAdd(fill, 1);
@@ -935,7 +936,7 @@ struct ExhaustiveTop {
   __device__ void settle(uint64_t* dkey, uint32_t* didx, int* fill, bool last) {
     __syncthreads();
     const int F = *fill;
-    if (F <= SORT_CAP - EXH_CHUNK && !last) return;   // uniform: F read after the barrier
+    if (F <= cap - EXH_CHUNK && !last) return;   // uniform: F read after the barrier
     const int N = next_pow2(F > 1 ? F : 2);
     for (int i = F + threadIdx.x; i < N; i += WG) { dkey[i] = ~0ull; didx[i] = 0xffffffffu; }
     __syncthreads();
@@ -949,10 +950,12 @@ struct ExhaustiveTop {
 __global__ void __launch_bounds__(WG)
 knn_exhaustive_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  uint64_t* dkey = reinterpret_cast<uint64_t*>(smem);
-  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + SORT_CAP);
-  uint32_t* tmp = didx + SORT_CAP;
-  double* red = reinterpret_cast<double*>(tmp + K_MAX);
+  // sort_cap: candidate buffer entries, kd_cap: next power of two >= k (even counts)
+  const int cap = a.sort_cap, kcap = a.kd_cap;
+  uint64_t* dkey = reinterpret_cast<uint64_t*>(smem);                // cap
+  uint32_t* didx = reinterpret_cast<uint32_t*>(dkey + cap);           // cap
+  uint32_t* tmp = didx + cap;                                          // kcap
+  double* red = reinterpret_cast<double*>(tmp + kcap);                // WG
   float* ys = reinterpret_cast<float*>(red + WG);
   __shared__ int fill_s;
   const int64_t qi = blockIdx.x;
@@ -962,12 +965,21 @@ knn_exhaustive_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) 
   if (threadIdx.x == 0) fill_s = 0;
   __syncthreads();
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
-  ExhaustiveTop top(k);
+  ExhaustiveTop top(k, cap);
   for (int64_t r0 = 0; r0 < a.n; r0 += EXH_CHUNK) {
     const int64_t r1 = r0 + EXH_CHUNK < a.n ? r0 + EXH_CHUNK : a.n;
-    for (int64_t r = r0 + g; r < r1; r += WG / 16) {
-      const double d2 = group16_d2(a.X, r, a.d, ys, l16);
-      if (l16 == 0) top.offer(__builtin_bit_cast(uint64_t, d2), (uint32_t)r, dkey, didx, &fill_s);
+    // four rows per 16-lane group at a time (their loads in flight together)
+    for (int64_t rb = r0 + g; rb < r1; rb += 4 * (WG / 16)) {
+      int64_t rr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) rr[i] = rb + i * (WG / 16) < r1 ? rb + i * (WG / 16) : -1;
+      double d2[4];
+      group16_d2_4(a.X, rr, a.d, ys, l16, d2);
+      if (l16 == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (rr[i] >= 0)
+            top.offer(__builtin_bit_cast(uint64_t, d2[i]), (uint32_t)rr[i], dkey, didx, &fill_s);
     }
     top.settle(dkey, didx, &fill_s, r1 == a.n);
   }
@@ -1201,8 +1213,16 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
   e = launch_tiles_prec(prec, pc, b, true, s);
   if (e != hipSuccess) return e;
   if ((e = launch_refine2(a, bb, nn_out, d, s)) != hipSuccess) return e;
-  const size_t sm2 = SORT_CAP * (8 + 4) + K_MAX * (8 + 4) + WG * 8 + d * 4;
-  knn_exhaustive_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(a, bb, nn_out);
+  // the exhaustive scan keeps k + 32 pairs plus a chunk of appends
+  RefineArgs ea = a;
+  int kcap = 2;
+  while (kcap < (int)k) kcap <<= 1;
+  int cap = 2;
+  while (cap < (int)k + 32 + EXH_CHUNK) cap <<= 1;
+  ea.sort_cap = cap < SORT_CAP ? cap : SORT_CAP;
+  ea.kd_cap = kcap;
+  const size_t sm2 = (size_t)ea.sort_cap * (8 + 4) + (size_t)kcap * 4 + WG * 8 + d * 4;
+  knn_exhaustive_kernel<<<dim3((unsigned)p.q), dim3(WG), sm2, s>>>(ea, bb, nn_out);
   return hipGetLastError();
 }
 
@@ -1538,7 +1558,7 @@ ivf_exhaustive_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restri
   __syncthreads();
   const int64_t R = st == 3 ? a.n : cum[np];
   const int g = threadIdx.x >> 4, l16 = threadIdx.x & 15;
-  ExhaustiveTop top(k);
+  ExhaustiveTop top(k, SORT_CAP);
   for (int64_t r0 = 0; r0 < R; r0 += EXH_CHUNK) {
     const int64_t r1 = r0 + EXH_CHUNK < R ? r0 + EXH_CHUNK : R;
     for (int64_t r = r0 + g; r < r1; r += WG / 16) {

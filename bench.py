@@ -100,7 +100,7 @@ def ceilings():
     lib.ceiling_gather.restype = ctypes.c_int
     lib.ceiling_gather.argtypes = [vp, i64, i64, vp, i64, i64, vp, vp]
     lib.ceiling_tile_sweep.restype = ctypes.c_int
-    lib.ceiling_tile_sweep.argtypes = [vp, i64, vp, i64, i64, i64, vp, vp]
+    lib.ceiling_tile_sweep.argtypes = [vp, i64, vp, i64, i64, i64, i64, vp, vp]
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev).cuda_stream
     gen = torch.Generator(device=dev)
@@ -140,7 +140,7 @@ def ceilings():
         Xs = torch.randn((np_, dp), device=dev, generator=gen).to(torch.bfloat16)
 
         def sweep():
-            st = lib.ceiling_tile_sweep(Ys.data_ptr(), qp, Xs.data_ptr(), np_, dp, 4096,
+            st = lib.ceiling_tile_sweep(Ys.data_ptr(), qp, Xs.data_ptr(), np_, dp, 4096, 0,
                                         out.data_ptr(), stream)
             if st != 0:
                 raise RuntimeError(f"ceiling_tile_sweep: hipError {st}")

@@ -114,11 +114,13 @@ extern "C" int ceiling_gather(const float* X, int64_t n, int64_t d, const int32_
 
 // Ys: [qp, dp] and Xs: [np, dp] bfloat16 device operands, qp and np multiples
 // of 128, dp a multiple of 64 (rows of dp * 2 bytes); split_target: workgroups
-// wanted (the k-NN passes use 4096); out: 256 floats of device scratch.
+// wanted (the k-NN passes use 4096); group: data splits per placement group
+// (0: the k-NN passes' choice); out: 256 floats of device scratch.
 extern "C" int ceiling_tile_sweep(const void* Ys, int64_t qp, const void* Xs, int64_t np,
-                                  int64_t dp, int64_t split_target, float* out, void* stream) {
+                                  int64_t dp, int64_t split_target, int64_t group, float* out,
+                                  void* stream) {
   if (!Ys || !Xs || !out || qp <= 0 || np <= 0 || qp % BQ || np % BN || dp <= 0 || dp % 64 ||
-      split_target <= 0)
+      split_target <= 0 || group < 0)
     return (int)hipErrorInvalidValue;
   TileProblem p{};
   p.Ys = static_cast<const char*>(Ys);
@@ -131,7 +133,7 @@ extern "C" int ceiling_tile_sweep(const void* Ys, int64_t qp, const void* Xs, in
   if (p.splits < 1) p.splits = 1;
   if (p.splits > p.ntiles) p.splits = p.ntiles;
   const bool resident_query = p.ld_bytes <= 2 * CHUNK_BYTES;
-  p.map = make_tile_map(p.qtiles, p.splits, resident_query ? 1 : 4);
+  p.map = make_tile_map(p.qtiles, p.splits, group > 0 ? group : (resident_query ? 1 : 4));
   p.tstride = 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 g((unsigned)p.map.grid), blk(WG);

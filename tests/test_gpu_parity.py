@@ -240,19 +240,23 @@ def test_knn_more_neighbours_than_cells(dev, n, k, prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-def test_second_pass_heavy_and_light_queries(dev, prec):
-    # half the queries sit in a blob of 1500 nearly equal rows that 16-bit keys
+@pytest.mark.parametrize("nb", [1500, 2500])
+def test_second_pass_heavy_and_light_queries(dev, prec, nb):
+    # half the queries sit in a blob of nb nearly equal rows that 16-bit keys
     # cannot tell apart (every blob row passes the second-pass threshold, far
     # more hits per tile than a wave stages: the rest go straight to the
     # lists), the other half in sparse data with few hits; all must equal the
-    # oracle's k-NN and estimate
+    # oracle's k-NN and estimate.  The second refinement's first launch takes
+    # the light queries; the blob ones go to its full-capacity launch (1500:
+    # the exact pairs exceed the first launch's 1024; 2500: the list exceeds
+    # its 2048 keys)
     import paper_2107_02736_amd as dk
     rng = np.random.default_rng(31)
     d = 24
     P = rng.uniform(-1, 1, size=d)
-    blob = P + 1e-3 * rng.normal(size=(1500, d))
+    blob = P + 1e-3 * rng.normal(size=(nb, d))
     rest = 3.0 * rng.normal(size=(1500, d))
-    X = np.concatenate([blob, rest])[rng.permutation(3000)].astype(np.float32)
+    X = np.concatenate([blob, rest])[rng.permutation(nb + 1500)].astype(np.float32)
     Y = np.concatenate([P + 1e-3 * rng.normal(size=(64, d)),
                         3.0 * rng.normal(size=(64, d))]).astype(np.float32)
     Xd, Yd = to_dev(X, dev), to_dev(Y, dev)

@@ -180,6 +180,49 @@ deann_status deann_query_with_grad(const float* X, int64_t n, const float* Y, in
                                    size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Prepared data set: the preprocessing of X that every call above performs
+ * (Algorithm 1 fits its estimator to X once and then answers queries; App. F
+ * keeps the row norms) -- X centred by its column mean (deann_options.center),
+ * stored in the scan precision with its norms and rounding bounds -- done once
+ * into caller-owned device memory and reused by the *_prepared calls, which
+ * then prepare only the queries.
+ *   deann_prepared_bytes  size for (n, d, precision); 0 for invalid arguments.
+ *   deann_prepare         fills `prepared` (prepared_bytes at least that size)
+ *                         from X[n, d]; asynchronous like every call.
+ *   *_prepared            as kde_exact, deann_query, deann_query_with_grad with
+ *                         the same arguments (X is still read: the exact
+ *                         re-evaluations and the gathers use its float32 rows),
+ *                         plus the prepared set and its size.  Results are
+ *                         bitwise those of the unprepared call.
+ * The prepared set must come from deann_prepare with the same X, n, d and
+ * precision (DEANN_FP32 for kde_exact_prepared with DEANN_FP32_SPLIT) and the
+ * same centring option; only its size is checked (DEANN_EWORKSPACE when it is
+ * too small for n, d and the precision).  It is read, never written, by the
+ * query calls, so several streams may share it; the workspaces stay per call.
+ * ------------------------------------------------------------------------- */
+size_t deann_prepared_bytes(int64_t n, int64_t d, deann_precision precision);
+deann_status deann_prepare(const float* X, int64_t n, int64_t d, deann_precision precision,
+                           void* prepared, size_t prepared_bytes, void* stream);
+deann_status kde_exact_prepared(const void* prepared, size_t prepared_bytes, const float* X,
+                                int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                                deann_kernel kernel, deann_precision precision, double* out,
+                                void* ws, size_t ws_bytes, void* stream);
+deann_status deann_query_prepared(const void* prepared, size_t prepared_bytes, const float* X,
+                                  int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                                  deann_kernel kernel, int64_t k, int64_t m, uint64_t seed,
+                                  uint64_t query_offset, uint64_t word2,
+                                  deann_precision precision, double* out, int32_t* nn_idx,
+                                  int32_t* sample_idx, void* ws, size_t ws_bytes, void* stream);
+deann_status deann_query_with_grad_prepared(const void* prepared, size_t prepared_bytes,
+                                            const float* X, int64_t n, const float* Y, int64_t q,
+                                            int64_t d, double h, deann_kernel kernel, int64_t k,
+                                            int64_t m, uint64_t seed, uint64_t query_offset,
+                                            uint64_t word2, deann_precision precision,
+                                            double* out, float* grad_Y, double* grad_h,
+                                            int32_t* nn_idx, int32_t* sample_idx, void* ws,
+                                            size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * DEANN with permuted random sampling (DEANNP; App. G, Algorithm 2): as
  * deann_query, but the sample of query i is the block of the data's permuted
  * order that starts at the running index l_i = (start + i m) mod n, with the

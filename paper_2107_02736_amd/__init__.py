@@ -9,5 +9,6 @@ from .api import (  # noqa: F401
     kde_exact, deann_query, deann_query_with_grad, deann_query_permuted, deann_query_backward, kde_exact_backward,
     kde_exact_with_grad, kde_hybrid, mean_shift_update, kernel_timing, kernel_times,
     ivf_build, IvfIndex, deann_ivf_query, PermutedIndex, get_options, set_options, default_options, last_stats,
+    prepare, Prepared,
 )
 from .autograd import ExactKDE, DeannKDE, exact_kde, deann_kde, mean_shift, bisect_h  # noqa: F401

@@ -51,9 +51,43 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
+class Prepared:
+    """A prepared data set (deann_prepare): X centred and stored in the scan
+    precision with its norms, computed once; pass it as `prepared=` to
+    kde_exact, deann_query and deann_query_with_grad with the same X."""
+
+    def __init__(self, X: torch.Tensor, precision="fp32"):
+        _check_xy(X, X[:0])
+        lib = _lib.load()
+        self.n, self.d = X.shape
+        self.precision = precision_id(precision)
+        self.device = X.device
+        self.x_ptr = X.data_ptr()
+        nbytes = lib.deann_prepared_bytes(self.n, self.d, self.precision)
+        if nbytes == 0:
+            raise ValueError("invalid size or precision for a prepared data set")
+        self.buf = _workspace(nbytes, X.device)
+        _lib.check(lib.deann_prepare(X.data_ptr(), self.n, self.d, self.precision,
+                                     self.buf.data_ptr(), self.buf.numel(), _stream(X.device)))
+
+    def args(self, X: torch.Tensor, precision: int):
+        """(pointer, bytes) after checking that the call matches this set."""
+        if (X.data_ptr() != self.x_ptr or tuple(X.shape) != (self.n, self.d)
+                or X.device != self.device or precision != self.precision):
+            raise ValueError("the prepared data set was made from another X or precision")
+        return self.buf.data_ptr(), self.buf.numel()
+
+
+def prepare(X: torch.Tensor, precision="fp32") -> Prepared:
+    """Prepare X once for repeated calls (deann_prepare)."""
+    return Prepared(X, precision)
+
+
 def kde_exact(X: torch.Tensor, Y: torch.Tensor, h: float, kernel="gaussian",
-              precision="fp32", out: torch.Tensor | None = None) -> torch.Tensor:
-    """Exact KDE of every query row (float64 [q])."""
+              precision="fp32", out: torch.Tensor | None = None,
+              prepared: Prepared | None = None) -> torch.Tensor:
+    """Exact KDE of every query row (float64 [q]); `prepared` (made with the
+    same X, in FP32 for the "fp32_split" precision) skips preparing X."""
     _check_xy(X, Y)
     lib = _lib.load()
     n, d = X.shape
@@ -62,15 +96,21 @@ def kde_exact(X: torch.Tensor, Y: torch.Tensor, h: float, kernel="gaussian",
     if out is None:
         out = torch.empty(q, dtype=torch.float64, device=X.device)
     ws = _workspace(lib.kde_exact_workspace(n, q, d, p), X.device)
-    _lib.check(lib.kde_exact(X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), p,
-                             out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(X.device)))
+    args = (X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), p,
+            out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(X.device))
+    if prepared is None:
+        _lib.check(lib.kde_exact(*args))
+    else:
+        pp = prepared.args(X, _lib.FP32 if p == _lib.FP32_SPLIT else p)
+        _lib.check(lib.kde_exact_prepared(*pp, *args))
     return out
 
 
 def deann_query(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int, kernel="gaussian",
                 seed: int = 0, query_offset: int = 0, word2: int = 0, precision="fp32",
-                return_indices: bool = True):
-    """DEANN estimate of every query: (out float64 [q], nn_idx int32 [q,k], sample_idx int32 [q,m])."""
+                return_indices: bool = True, prepared: Prepared | None = None):
+    """DEANN estimate of every query: (out float64 [q], nn_idx int32 [q,k], sample_idx int32 [q,m]);
+    `prepared` (made with the same X and precision) skips preparing X."""
     _check_xy(X, Y)
     lib = _lib.load()
     n, d = X.shape
@@ -81,17 +121,20 @@ def deann_query(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int, kern
     nn = torch.empty((q, k), dtype=torch.int32, device=dev) if return_indices else None
     sm = torch.empty((q, m), dtype=torch.int32, device=dev) if return_indices else None
     ws = _workspace(lib.deann_query_workspace(n, q, d, k, m, p), dev)
-    _lib.check(lib.deann_query(X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel),
-                               int(k), int(m), int(seed), int(query_offset), int(word2), p,
-                               out.data_ptr(), _ptr(nn), _ptr(sm), ws.data_ptr(), ws.numel(),
-                               _stream(dev)))
+    args = (X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), int(k), int(m),
+            int(seed), int(query_offset), int(word2), p, out.data_ptr(), _ptr(nn), _ptr(sm),
+            ws.data_ptr(), ws.numel(), _stream(dev))
+    if prepared is None:
+        _lib.check(lib.deann_query(*args))
+    else:
+        _lib.check(lib.deann_query_prepared(*prepared.args(X, p), *args))
     return out, nn, sm
 
 
 def deann_query_with_grad(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m: int,
                           kernel="gaussian", seed: int = 0, query_offset: int = 0, word2: int = 0,
                           precision="fp32", need_grad_y: bool = True, need_grad_h: bool = True,
-                          return_indices: bool = True):
+                          return_indices: bool = True, prepared: Prepared | None = None):
     """DEANN estimates with their gradients from one gather of each query's rows:
     (out float64 [q], grad_Y float32 [q,d] = d out_j / d y_j or None, grad_h
     float64 [q] = d out_j / d h or None, nn_idx int32 [q,k], sample_idx int32
@@ -108,10 +151,13 @@ def deann_query_with_grad(X: torch.Tensor, Y: torch.Tensor, h: float, k: int, m:
     nn = torch.empty((q, k), dtype=torch.int32, device=dev) if return_indices else None
     sm = torch.empty((q, m), dtype=torch.int32, device=dev) if return_indices else None
     ws = _workspace(lib.deann_query_with_grad_workspace(n, q, d, k, m, p), dev)
-    _lib.check(lib.deann_query_with_grad(
-        X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), int(k), int(m),
-        int(seed), int(query_offset), int(word2), p, out.data_ptr(), _ptr(gy), _ptr(gh), _ptr(nn),
-        _ptr(sm), ws.data_ptr(), ws.numel(), _stream(dev)))
+    args = (X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), int(k), int(m),
+            int(seed), int(query_offset), int(word2), p, out.data_ptr(), _ptr(gy), _ptr(gh),
+            _ptr(nn), _ptr(sm), ws.data_ptr(), ws.numel(), _stream(dev))
+    if prepared is None:
+        _lib.check(lib.deann_query_with_grad(*args))
+    else:
+        _lib.check(lib.deann_query_with_grad_prepared(*prepared.args(X, p), *args))
     return out, gy, gh, nn, sm
 
 

@@ -196,8 +196,10 @@ TileProblem make_problem(const Prep& p, int64_t n, int64_t q, int prec, int64_t 
   return t;
 }
 
-hipError_t run_prep(const Prep& p, const float* X, int64_t n, const float* Y, int64_t q,
-                    int64_t d, int prec, hipStream_t s) {
+// The data half of the preparation: centre, bounds (err_max[1], the queries'
+// bound, is left 0), the data rows in the scan type with their norms.
+hipError_t run_prep_x(const Prep& p, const float* X, int64_t n, int64_t d, int prec,
+                      hipStream_t s) {
   const int64_t R = n < kCenterRows ? n : kCenterRows;
   hipError_t e = g_opt.center ? launch_center(X, n, d, p.cpart, R, p.c, s)
                               : launch_fill_u32(reinterpret_cast<uint32_t*>(p.c), d, 0u, s);
@@ -207,9 +209,55 @@ hipError_t run_prep(const Prep& p, const float* X, int64_t n, const float* Y, in
   e = launch_prep_rows_prec(prec, X, n, p.np, d, p.dp, p.c, a, p.Xs, p.xnorm, p.xknorm, p.xerr,
                             p.err_max, s);
   if (e != hipSuccess) return e;
-  if ((e = launch_max_u32(p.xknorm, n, p.err_max + 2, s)) != hipSuccess) return e;
-  return launch_prep_rows_prec(prec, Y, q, p.qp, d, p.dp, p.c, a, p.Ys, p.ynorm, p.yknorm, p.yerr,
-                               p.err_max + 1, s);
+  return launch_max_u32(p.xknorm, n, p.err_max + 2, s);
+}
+
+hipError_t run_prep_y(const Prep& p, const float* Y, int64_t q, int64_t d, int prec,
+                      hipStream_t s) {
+  return launch_prep_rows_prec(prec, Y, q, p.qp, d, p.dp, p.c, key_scale(p.dp), p.Ys, p.ynorm,
+                               p.yknorm, p.yerr, p.err_max + 1, s);
+}
+
+hipError_t run_prep(const Prep& p, const float* X, int64_t n, const float* Y, int64_t q,
+                    int64_t d, int prec, hipStream_t s) {
+  hipError_t e = run_prep_x(p, X, n, d, prec, s);
+  if (e != hipSuccess) return e;
+  return run_prep_y(p, Y, q, d, prec, s);
+}
+
+// Prepared data set (deann_prepare), caller-owned device memory: the data half
+// of a Prep -- centre c[d], bounds err_max[3], centring partials, rows
+// Xs[np][dp] in the scan type, xnorm[np], xknorm[np], xerr[np].
+Prep carve_prepared(void* base, int64_t n, int64_t d, int prec, int64_t* bytes) {
+  Carve cv(base);
+  Prep p{};
+  p.dp = padded_d(d, prec);
+  p.np = round_up(n, BN);
+  p.c = cv.take<float>(d);
+  p.err_max = cv.take<uint32_t>(3);
+  p.cpart = cv.take<double>(kCenterRows * d);
+  p.Xs = cv.take<char>(p.np * p.dp * elem_bytes(prec));
+  p.xnorm = cv.take<double>(p.np);
+  p.xknorm = cv.take<float>(p.np);
+  p.xerr = cv.take<float>(p.np);
+  if (bytes) *bytes = cv.off + kAlign;
+  return p;
+}
+
+// A call's preparation from a prepared data set: the data rows are read where
+// they are; centre and bounds are copied into the call's workspace (the
+// queries' bound is formed there); then the queries are prepared.
+hipError_t run_prep_prepared(Prep& p, const Prep& h, const float* Y, int64_t q, int64_t d,
+                             int prec, hipStream_t s) {
+  p.Xs = h.Xs;
+  p.xnorm = h.xnorm;
+  p.xknorm = h.xknorm;
+  p.xerr = h.xerr;
+  hipError_t e = launch_copy_u32(reinterpret_cast<uint32_t*>(p.c),
+                                 reinterpret_cast<const uint32_t*>(h.c), d, s);
+  if (e != hipSuccess) return e;
+  if ((e = launch_copy_u32(p.err_max, h.err_max, 3, s)) != hipSuccess) return e;
+  return run_prep_y(p, Y, q, d, prec, s);
 }
 
 bool bad_prec(int prec) { return prec != DEANN_FP32 && prec != DEANN_BF16 && prec != DEANN_FP16; }
@@ -570,12 +618,35 @@ size_t kde_exact_workspace(int64_t n, int64_t q, int64_t d, deann_precision prec
   return (size_t)plan_kde(nullptr, n, q, d, precision).bytes;
 }
 
-deann_status kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-              deann_kernel kernel, deann_precision precision, double* out, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+// Size check of a prepared data set for (n, d, prec); DEANN_OK when it holds.
+static deann_status check_prepared(const void* prepared, size_t prepared_bytes, int64_t n,
+                                   int64_t d, int prec) {
+  int64_t need = 0;
+  carve_prepared(nullptr, n, d, prec, &need);
+  if (!prepared) return fail(DEANN_EINVAL, "prepared is NULL");
+  if ((int64_t)prepared_bytes < need)
+    return fail(DEANN_EWORKSPACE, "a prepared data set of %lld bytes is needed for n = %lld, "
+                "d = %lld in this precision", (long long)need, (long long)n, (long long)d);
+  return DEANN_OK;
+}
+
+static Prep prepared_of(const void* prepared, int64_t n, int64_t d, int prec) {
+  return carve_prepared(align_ws(const_cast<void*>(prepared)), n, d, prec, nullptr);
+}
+
+static deann_status kde_exact_impl(const void* prepared, size_t prepared_bytes, const float* X,
+                                   int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                                   int kernel, int precision, double* out, void* ws,
+                                   size_t ws_bytes, void* stream) {
   deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   const bool split = precision == DEANN_FP32_SPLIT;
   if (bad_prec(precision) && !split) return fail(DEANN_EINVAL, "unknown precision %d", precision);
+  const int prep_prec = split ? DEANN_FP32 : precision;
+  if (prepared && (st = check_prepared(prepared, prepared_bytes, n, d, prep_prec)) != DEANN_OK)
+    return st;
   if (q == 0) return DEANN_OK;
   if (!out) return fail(DEANN_EINVAL, "out is NULL");
   const int64_t need = plan_kde(nullptr, n, q, d, precision).bytes;
@@ -584,8 +655,9 @@ deann_status kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int
   hipStream_t s = static_cast<hipStream_t>(stream);
   KdePlan P = plan_kde(align_ws(ws), n, q, d, precision);
   record_last(P.cert.count, nullptr, q);   // null for 16-bit operands
-  const int prep_prec = split ? DEANN_FP32 : precision;
-  hipError_t e = run_prep(P.prep, X, n, Y, q, d, prep_prec, s);
+  hipError_t e = prepared ? run_prep_prepared(P.prep, prepared_of(prepared, n, d, prep_prec), Y,
+                                              q, d, prep_prec, s)
+                          : run_prep(P.prep, X, n, Y, q, d, prep_prec, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tp = make_problem(P.prep, n, q, prep_prec, kKdeSplitTarget);
   if (split) {
@@ -605,6 +677,45 @@ deann_status kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int
   }
   if (e != hipSuccess) return hip_fail(e, "kde_exact");
   return DEANN_OK;
+}
+
+extern "C" {
+
+deann_status kde_exact(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+              deann_kernel kernel, deann_precision precision, double* out, void* ws, size_t ws_bytes, void* stream) {
+  return kde_exact_impl(nullptr, 0, X, n, Y, q, d, h, kernel, precision, out, ws, ws_bytes,
+                        stream);
+}
+
+size_t deann_prepared_bytes(int64_t n, int64_t d, deann_precision precision) {
+  if (n < 1 || d < 1 || bad_prec(precision)) return 0;
+  int64_t need = 0;
+  carve_prepared(nullptr, n, d, precision, &need);
+  return (size_t)need;
+}
+
+deann_status deann_prepare(const float* X, int64_t n, int64_t d, deann_precision precision,
+                           void* prepared, size_t prepared_bytes, void* stream) {
+  if (n < 1) return fail(DEANN_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
+  if (d < 1) return fail(DEANN_EINVAL, "d must be >= 1 (got %lld)", (long long)d);
+  if (n >= (int64_t)1 << 31) return fail(DEANN_EINVAL, "n must be < 2^31");
+  if (!X) return fail(DEANN_EINVAL, "X is NULL");
+  if (bad_prec(precision)) return fail(DEANN_EINVAL, "unknown precision %d", precision);
+  deann_status st = check_prepared(prepared, prepared_bytes, n, d, precision);
+  if (st != DEANN_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = run_prep_x(prepared_of(prepared, n, d, precision), X, n, d, precision, s);
+  if (e != hipSuccess) return hip_fail(e, "prepare");
+  return DEANN_OK;
+}
+
+deann_status kde_exact_prepared(const void* prepared, size_t prepared_bytes, const float* X,
+                                int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                                deann_kernel kernel, deann_precision precision, double* out,
+                                void* ws, size_t ws_bytes, void* stream) {
+  if (!prepared) return fail(DEANN_EINVAL, "prepared is NULL");
+  return kde_exact_impl(prepared, prepared_bytes, X, n, Y, q, d, h, kernel, precision, out, ws,
+                        ws_bytes, stream);
 }
 
 size_t deann_query_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,
@@ -644,10 +755,13 @@ static deann_status deann_query_impl(const float* X, int64_t n, const float* Y, 
                             uint64_t query_offset, uint64_t word2, int permuted, uint64_t start,
                             int precision, double* out, int32_t* nn_idx, int32_t* sample_idx,
                             void* ws, size_t ws_bytes, void* stream,
-                            const PermIndex* pidx = nullptr, const DeannGradOut* grad = nullptr) {
+                            const PermIndex* pidx = nullptr, const DeannGradOut* grad = nullptr,
+                            const void* prepared = nullptr, size_t prepared_bytes = 0) {
   deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_prec(precision)) return fail(DEANN_EINVAL, "unknown precision %d", precision);
+  if (prepared && (st = check_prepared(prepared, prepared_bytes, n, d, precision)) != DEANN_OK)
+    return st;
   if (k < 0 || k > n) return fail(DEANN_EINVAL, "k must be in [0, n] (got %lld)", (long long)k);
   if (m < 0) return fail(DEANN_EINVAL, "m must be >= 0 (got %lld)", (long long)m);
   if (k > kMaxK && k != n)
@@ -678,7 +792,9 @@ static deann_status deann_query_impl(const float* X, int64_t n, const float* Y, 
     e = launch_knn_all(X, Y, n, q, d, h, kernel, P.kb.nn_work, P.kb.z1, s);
     if (e != hipSuccess) return hip_fail(e, "all-points sum");
   } else if (k > 0) {
-    e = run_prep(P.prep, X, n, Y, q, d, precision, s);
+    e = prepared ? run_prep_prepared(P.prep, prepared_of(prepared, n, d, precision), Y, q, d,
+                                     precision, s)
+                 : run_prep(P.prep, X, n, Y, q, d, precision, s);
     if (e != hipSuccess) return hip_fail(e, "prep");
     TileProblem tp = make_problem(P.prep, n, q, precision, kKnnSplitTarget);
     TileProblem tc = make_problem(P.prep, n, q, precision, kCollectSplitTarget);
@@ -723,6 +839,33 @@ deann_status deann_query_with_grad(const float* X, int64_t n, const float* Y, in
   const DeannGradOut g{grad_Y, grad_h};
   return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, query_offset, word2, 0, 0,
                           precision, out, nn_idx, sample_idx, ws, ws_bytes, stream, nullptr, &g);
+}
+
+deann_status deann_query_prepared(const void* prepared, size_t prepared_bytes, const float* X,
+                                  int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                                  deann_kernel kernel, int64_t k, int64_t m, uint64_t seed,
+                                  uint64_t query_offset, uint64_t word2,
+                                  deann_precision precision, double* out, int32_t* nn_idx,
+                                  int32_t* sample_idx, void* ws, size_t ws_bytes, void* stream) {
+  if (!prepared) return fail(DEANN_EINVAL, "prepared is NULL");
+  return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, query_offset, word2, 0, 0,
+                          precision, out, nn_idx, sample_idx, ws, ws_bytes, stream, nullptr,
+                          nullptr, prepared, prepared_bytes);
+}
+
+deann_status deann_query_with_grad_prepared(const void* prepared, size_t prepared_bytes,
+                                            const float* X, int64_t n, const float* Y, int64_t q,
+                                            int64_t d, double h, deann_kernel kernel, int64_t k,
+                                            int64_t m, uint64_t seed, uint64_t query_offset,
+                                            uint64_t word2, deann_precision precision,
+                                            double* out, float* grad_Y, double* grad_h,
+                                            int32_t* nn_idx, int32_t* sample_idx, void* ws,
+                                            size_t ws_bytes, void* stream) {
+  if (!prepared) return fail(DEANN_EINVAL, "prepared is NULL");
+  const DeannGradOut g{grad_Y, grad_h};
+  return deann_query_impl(X, n, Y, q, d, h, kernel, k, m, seed, query_offset, word2, 0, 0,
+                          precision, out, nn_idx, sample_idx, ws, ws_bytes, stream, nullptr, &g,
+                          prepared, prepared_bytes);
 }
 
 size_t deann_query_permuted_workspace(int64_t n, int64_t q, int64_t d, int64_t k, int64_t m,

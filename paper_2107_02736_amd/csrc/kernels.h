@@ -26,6 +26,7 @@ struct TileProblem {
 };
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, int64_t count, hipStream_t s);
 // Largest of count non-negative floats, as float bits, into *out (atomic max:
 // *out must hold a lower value first).
 hipError_t launch_max_u32(const float* v, int64_t count, uint32_t* out, hipStream_t s);

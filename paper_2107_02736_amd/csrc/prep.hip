@@ -193,6 +193,18 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s
   return hipGetLastError();
 }
 
+__global__ void copy_u32_kernel(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  copy_u32_kernel<<<dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s>>>(dst, src, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_max_u32(const float* v, int64_t count, uint32_t* out, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const int64_t mb = std::min<int64_t>(1024, ceil_div(count, WG));

@@ -218,3 +218,35 @@ def test_slack_enters_the_list_size_check(lib):
     finally:
         lib.deann_set_options(d)
 
+
+
+def test_prepared_sizes_and_validation(lib):
+    # sizes: 0 for invalid arguments, growing with n and d, the float32 set
+    # holding twice the 16-bit rows
+    assert lib.deann_prepared_bytes(0, 8, 0) == 0
+    assert lib.deann_prepared_bytes(10, 0, 0) == 0
+    assert lib.deann_prepared_bytes(10, 8, 3) == 0          # the split form prepares in FP32
+    small, big = lib.deann_prepared_bytes(1000, 64, 1), lib.deann_prepared_bytes(2000, 64, 1)
+    assert 0 < small < big
+    f32, b16 = lib.deann_prepared_bytes(100000, 960, 0), lib.deann_prepared_bytes(100000, 960, 1)
+    assert f32 - b16 >= 100000 * 960 * 2
+    # deann_prepare: host checks, nothing launched
+    need = lib.deann_prepared_bytes(100, 3, 1)
+    assert lib.deann_prepare(None, 100, 3, 1, FAKE, need, None) == _lib.EINVAL
+    assert lib.deann_prepare(FAKE, 100, 3, 7, FAKE, need, None) == _lib.EINVAL
+    assert lib.deann_prepare(FAKE, 100, 3, 1, None, need, None) == _lib.EINVAL
+    assert lib.deann_prepare(FAKE, 100, 3, 1, FAKE, need - 1, None) == _lib.EWORKSPACE
+    # the query calls check the set's size against their own n, d and precision
+    st = lib.kde_exact_prepared(None, need, FAKE, 100, FAKE, 4, 3, 1.0, 0, 1, FAKE, FAKE, 1 << 30,
+                                None)
+    assert st == _lib.EINVAL
+    need64 = lib.deann_prepared_bytes(100, 64, 1)
+    st = lib.kde_exact_prepared(FAKE, need64, FAKE, 100, FAKE, 4, 64, 1.0, 0, 0, FAKE, FAKE,
+                                1 << 30, None)
+    assert st == _lib.EWORKSPACE          # an FP32 call needs the larger FP32 set
+    st = lib.deann_query_prepared(FAKE, need, FAKE, 200, FAKE, 4, 3, 1.0, 0, 5, 10, 0, 0, 0, 1,
+                                  FAKE, FAKE, FAKE, FAKE, 1 << 34, None)
+    assert st == _lib.EWORKSPACE          # made for n = 100
+    st = lib.deann_query_with_grad_prepared(None, need, FAKE, 100, FAKE, 4, 3, 1.0, 0, 5, 10, 0, 0,
+                                            0, 1, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 34, None)
+    assert st == _lib.EINVAL

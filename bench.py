@@ -511,15 +511,14 @@ def run_workload(args, workload, with_cpu):
         ms_step_split = (time.perf_counter() - t0s) * 1e3 / args.steps
 
     # the step with X prepared once (deann_prepare; the data set fixed across
-    # calls, as when serving queries): the exact KDE (d > 128; the fused
-    # value + gradient call prepares X itself) and DEANN prepare only the
-    # queries.  Same outputs as the step.
-    pre32 = None if fused else dk.prepare(Xd, "fp32")
+    # calls, as when serving queries): the exact KDE (with its gradient for
+    # d <= 128) and DEANN prepare only the queries.  Same outputs as the step.
+    pre32 = dk.prepare(Xd, "fp32")
     pre16 = dk.prepare(Xd, "bf16")
 
     def step_prepared():
         if fused:
-            mu_p = dk.kde_exact_with_grad(Xd, Yd, h, KERNEL)[0]
+            mu_p = dk.kde_exact_with_grad(Xd, Yd, h, KERNEL, prepared=pre32)[0]
         else:
             mu_p = dk.kde_exact(Xd, Yd, h, KERNEL, "fp32", prepared=pre32)
         est_p = dk.deann_query_with_grad(Xd, Yd, h, K_NN, M_SAMPLES, KERNEL, seed=0,
@@ -689,8 +688,8 @@ def run_workload(args, workload, with_cpu):
                           "queries_per_s": q / (ms_step_prepared * 1e-3),
                           "same_outputs_as_step": prepared_same,
                           "note": "the step with X prepared once outside the timed region "
-                                  "(deann_prepare: FP32 set for the exact KDE when d > 128, "
-                                  "BF16 set for DEANN); queries prepared per call"},
+                                  "(deann_prepare: FP32 set for the exact KDE, BF16 set for "
+                                  "DEANN); queries prepared per call"},
         "mean_shift": {"steps": MEAN_SHIFT_STEPS,
                        "exact_ms": ms_shift_exact,
                        "exact_query_steps_per_s": (q * MEAN_SHIFT_STEPS / (ms_shift_exact * 1e-3)

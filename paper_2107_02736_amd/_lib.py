@@ -22,8 +22,8 @@ EXPORTS = (
     "kde_exact_workspace", "kde_exact",
     "deann_query_workspace", "deann_query",
     "deann_query_with_grad_workspace", "deann_query_with_grad",
-    "deann_prepared_bytes", "deann_prepare", "kde_exact_prepared", "deann_query_prepared",
-    "deann_query_with_grad_prepared",
+    "deann_prepared_bytes", "deann_prepare", "kde_exact_prepared", "kde_exact_with_grad_prepared",
+    "deann_query_prepared", "deann_query_with_grad_prepared",
     "deann_query_permuted_workspace", "deann_query_permuted",
     "deann_perm_index_bytes", "deann_perm_index_create", "deann_query_permuted_index",
     "deann_query_backward_workspace", "deann_query_backward", "deann_query_backward_noalloc",
@@ -90,16 +90,6 @@ def load(path: str = LIB_PATH):
     lib.deann_query_with_grad.argtypes = [_vp, _i64, _vp, _i64, _i64, _dbl, _int, _i64, _i64,
                                           _u64, _u64, _u64, _int, _vp, _vp, _vp, _vp, _vp, _vp,
                                           _sz, _vp]
-    lib.deann_prepared_bytes.restype = _sz
-    lib.deann_prepared_bytes.argtypes = [_i64, _i64, _int]
-    lib.deann_prepare.restype = _int
-    lib.deann_prepare.argtypes = [_vp, _i64, _i64, _int, _vp, _sz, _vp]
-    lib.kde_exact_prepared.restype = _int
-    lib.kde_exact_prepared.argtypes = [_vp, _sz] + lib.kde_exact.argtypes
-    lib.deann_query_prepared.restype = _int
-    lib.deann_query_prepared.argtypes = [_vp, _sz] + lib.deann_query.argtypes
-    lib.deann_query_with_grad_prepared.restype = _int
-    lib.deann_query_with_grad_prepared.argtypes = [_vp, _sz] + lib.deann_query_with_grad.argtypes
     lib.deann_query_permuted_workspace.restype = _sz
     lib.deann_query_permuted_workspace.argtypes = [_i64, _i64, _i64, _i64, _i64, _int]
     lib.deann_query_permuted.restype = _int
@@ -166,6 +156,19 @@ def load(path: str = LIB_PATH):
     lib.deann_kernel_timing.argtypes = [_int]
     lib.deann_kernel_times.restype = _int
     lib.deann_kernel_times.argtypes = [_int, ctypes.POINTER(ctypes.c_float), _int]
+    # prepared-set variants: the plain call's arguments after (prepared, bytes)
+    lib.deann_prepared_bytes.restype = _sz
+    lib.deann_prepared_bytes.argtypes = [_i64, _i64, _int]
+    lib.deann_prepare.restype = _int
+    lib.deann_prepare.argtypes = [_vp, _i64, _i64, _int, _vp, _sz, _vp]
+    lib.kde_exact_prepared.restype = _int
+    lib.kde_exact_prepared.argtypes = [_vp, _sz] + lib.kde_exact.argtypes
+    lib.kde_exact_with_grad_prepared.restype = _int
+    lib.kde_exact_with_grad_prepared.argtypes = [_vp, _sz] + lib.kde_exact_with_grad.argtypes
+    lib.deann_query_prepared.restype = _int
+    lib.deann_query_prepared.argtypes = [_vp, _sz] + lib.deann_query.argtypes
+    lib.deann_query_with_grad_prepared.restype = _int
+    lib.deann_query_with_grad_prepared.argtypes = [_vp, _sz] + lib.deann_query_with_grad.argtypes
     _lib = lib
     return lib
 

@@ -291,10 +291,11 @@ def kde_exact_backward(X, Y, h, grad_out, kernel="gaussian", need_grad_y: bool =
 
 
 def kde_exact_with_grad(X, Y, h, kernel="gaussian", need_grad_y: bool = True,
-                        need_grad_h: bool = True, precision="fp32"):
+                        need_grad_h: bool = True, precision="fp32",
+                        prepared: Prepared | None = None):
     """Exact KDE and its derivatives in one pass (d <= 128; precision "fp32" or
     "fp32_split"): (mu float64 [q], d mu/d y float32 [q,d] or None, d mu/d h
-    float64 [q] or None)."""
+    float64 [q] or None); `prepared`: an FP32 set of the same X."""
     _check_xy(X, Y)
     lib = _lib.load()
     n, d = X.shape
@@ -305,9 +306,12 @@ def kde_exact_with_grad(X, Y, h, kernel="gaussian", need_grad_y: bool = True,
     gh = torch.empty(q, dtype=torch.float64, device=dev) if need_grad_h else None
     p = precision_id(precision)
     ws = _workspace(lib.kde_exact_with_grad_workspace(n, q, d, p), dev)
-    _lib.check(lib.kde_exact_with_grad(X.data_ptr(), n, Y.data_ptr(), q, d, float(h),
-                                       kernel_id(kernel), p, mu.data_ptr(), _ptr(gy), _ptr(gh),
-                                       ws.data_ptr(), ws.numel(), _stream(dev)))
+    args = (X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), p, mu.data_ptr(),
+            _ptr(gy), _ptr(gh), ws.data_ptr(), ws.numel(), _stream(dev))
+    if prepared is None:
+        _lib.check(lib.kde_exact_with_grad(*args))
+    else:
+        _lib.check(lib.kde_exact_with_grad_prepared(*prepared.args(X, _lib.FP32), *args))
     return mu, gy, gh
 
 

@@ -491,9 +491,12 @@ bool bad_exact_grad_prec(int p) { return p != DEANN_FP32 && p != DEANN_FP32_SPLI
 
 // Float32 prep (and for DEANN_FP32_SPLIT the bfloat16 parts) of the exact
 // gradient paths; returns the split rows to use (X null: float32).
-hipError_t prep_exact_grad(const KdeBwdPlan& P, const float* X, int64_t n, const float* Y,
-                           int64_t q, int64_t d, int precision, SplitRows& sp, hipStream_t s) {
-  hipError_t e = run_prep(P.prep, X, n, Y, q, d, DEANN_FP32, s);
+// `pre`: a prepared float32 data set, or null to prepare X here.
+hipError_t prep_exact_grad(KdeBwdPlan& P, const float* X, int64_t n, const float* Y,
+                           int64_t q, int64_t d, int precision, SplitRows& sp, hipStream_t s,
+                           const Prep* pre = nullptr) {
+  hipError_t e = pre ? run_prep_prepared(P.prep, *pre, Y, q, d, DEANN_FP32, s)
+                     : run_prep(P.prep, X, n, Y, q, d, DEANN_FP32, s);
   if (e != hipSuccess || precision != DEANN_FP32_SPLIT) return e;
   e = launch_split_rows(reinterpret_cast<const float*>(P.prep.Xs), P.prep.np, P.prep.dp, P.dps,
                         P.Xsp, s);
@@ -1158,14 +1161,20 @@ size_t kde_exact_with_grad_workspace(int64_t n, int64_t q, int64_t d, deann_prec
   return kde_exact_backward_workspace(n, q, d, precision);
 }
 
-deann_status kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                        deann_kernel kernel, deann_precision precision, double* out, float* grad_Y, double* grad_h,
-                        void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+static deann_status kde_exact_with_grad_impl(const void* prepared, size_t prepared_bytes,
+                                             const float* X, int64_t n, const float* Y, int64_t q,
+                                             int64_t d, double h, int kernel, int precision,
+                                             double* out, float* grad_Y, double* grad_h, void* ws,
+                                             size_t ws_bytes, void* stream) {
   deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_exact_grad_prec(precision))
     return fail(DEANN_EINVAL, "precision must be DEANN_FP32 or DEANN_FP32_SPLIT");
   if (d > 128) return fail(DEANN_EUNSUPPORTED, "kde_exact_with_grad supports d <= 128");
+  if (prepared && (st = check_prepared(prepared, prepared_bytes, n, d, DEANN_FP32)) != DEANN_OK)
+    return st;
   if (q == 0) return DEANN_OK;
   if (!out) return fail(DEANN_EINVAL, "out is NULL");
   const int64_t need = plan_kde_bwd(nullptr, n, q, d, precision).bytes;
@@ -1175,7 +1184,8 @@ deann_status kde_exact_with_grad(const float* X, int64_t n, const float* Y, int6
   KdeBwdPlan P = plan_kde_bwd(align_ws(ws), n, q, d, precision);
   record_last(P.cert.count, nullptr, q);
   SplitRows sp;
-  hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s);
+  const Prep pre = prepared ? prepared_of(prepared, n, d, DEANN_FP32) : Prep{};
+  hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s, prepared ? &pre : nullptr);
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, bwd_split_target(P.prep.dp));
   tp.map = make_tile_map(tp.qtiles, tp.splits, 1);
@@ -1184,6 +1194,26 @@ deann_status kde_exact_with_grad(const float* X, int64_t n, const float* Y, int6
                           cert_args(P.cert, P.prep, sp.X ? P.dps + 4 : P.prep.dp, sp.X != nullptr));
   if (e != hipSuccess) return hip_fail(e, "kde value and gradient");
   return DEANN_OK;
+}
+
+extern "C" {
+
+deann_status kde_exact_with_grad(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                        deann_kernel kernel, deann_precision precision, double* out, float* grad_Y, double* grad_h,
+                        void* ws, size_t ws_bytes, void* stream) {
+  return kde_exact_with_grad_impl(nullptr, 0, X, n, Y, q, d, h, kernel, precision, out, grad_Y,
+                                  grad_h, ws, ws_bytes, stream);
+}
+
+deann_status kde_exact_with_grad_prepared(const void* prepared, size_t prepared_bytes,
+                                          const float* X, int64_t n, const float* Y, int64_t q,
+                                          int64_t d, double h, deann_kernel kernel,
+                                          deann_precision precision, double* out, float* grad_Y,
+                                          double* grad_h, void* ws, size_t ws_bytes,
+                                          void* stream) {
+  if (!prepared) return fail(DEANN_EINVAL, "prepared is NULL");
+  return kde_exact_with_grad_impl(prepared, prepared_bytes, X, n, Y, q, d, h, kernel, precision,
+                                  out, grad_Y, grad_h, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -45,6 +45,19 @@ def test_kde_exact_prepared_equals_unprepared(data, prec):
             assert torch.equal(a, b), (prec, kern)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp32_split"])
+def test_kde_exact_with_grad_prepared_equals_unprepared(data, prec):
+    import paper_2107_02736_amd as dk
+    X, Y1, Y2, Xd, Y1d, Y2d = data
+    pre = dk.prepare(Xd, "fp32")
+    for kern in ("gaussian", "exponential"):
+        for Yd in (Y2d, Y1d):
+            a = dk.kde_exact_with_grad(Xd, Yd, 9.0, kern, precision=prec)
+            b = dk.kde_exact_with_grad(Xd, Yd, 9.0, kern, precision=prec, prepared=pre)
+            for u, v in zip(a, b):
+                assert torch.equal(u, v), (prec, kern)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_deann_prepared_equals_unprepared(data, prec):
     import paper_2107_02736_amd as dk

@@ -87,15 +87,18 @@ def mean_shift(X, Y, h, steps, method="exact", k=0, m=0, seed=0, precision="fp32
     of the rows (with DEANN weights for method="deann").  Exact: density and
     gradient from one pass (kde_exact_with_grad).  DEANN: the estimate and its
     gradient from one gather (deann_query_with_grad); step t draws with counter
-    word 2 = t.  Returns the float32 end point [q, d]."""
+    word 2 = t.  X is prepared once for all steps (deann_prepare).  Returns the
+    float32 end point [q, d]."""
     Y = Y.detach().clone().contiguous()
+    pre = api.prepare(X, "fp32" if method == "exact" else precision) if steps > 0 else None
     for t in range(steps):
         if method == "exact":
-            mu, g, _ = api.kde_exact_with_grad(X, Y, float(h), "gaussian", True, False)
+            mu, g, _ = api.kde_exact_with_grad(X, Y, float(h), "gaussian", True, False,
+                                               prepared=pre)
         else:
             mu, g, _, _, _ = api.deann_query_with_grad(X, Y, float(h), k, m, "gaussian", seed, 0, t,
                                                        precision, need_grad_h=False,
-                                                       return_indices=False)
+                                                       return_indices=False, prepared=pre)
         api.mean_shift_update(Y, g, mu, float(h), out=Y)
     return Y
 
@@ -103,11 +106,12 @@ def mean_shift(X, Y, h, steps, method="exact", k=0, m=0, seed=0, precision="fp32
 def bisect_h(X, Y, target: float, kernel="gaussian", stat="mean", rel_tol=0.01,
              lo=-20.0, hi=20.0, max_iter=200) -> float:
     """Bandwidth whose mean (or median) exact KDE over Y is within rel_tol of target,
-    by bisection on log h with the FP32 exact path."""
+    by bisection on log h with the FP32 exact path (X prepared once)."""
+    pre = api.prepare(X, "fp32")
     for _ in range(max_iter):
         mid = 0.5 * (lo + hi)
         h = math.exp(mid)
-        v = api.kde_exact(X, Y, h, kernel, "fp32")
+        v = api.kde_exact(X, Y, h, kernel, "fp32", prepared=pre)
         val = float(v.mean() if stat == "mean" else v.median())
         if abs(val - target) <= rel_tol * target:
             return h

@@ -189,15 +189,16 @@ deann_status deann_query_with_grad(const float* X, int64_t n, const float* Y, in
  *   deann_prepared_bytes  size for (n, d, precision); 0 for invalid arguments.
  *   deann_prepare         fills `prepared` (prepared_bytes at least that size)
  *                         from X[n, d]; asynchronous like every call.
- *   *_prepared            as kde_exact, kde_exact_with_grad, deann_query,
- *                         deann_query_with_grad with
+ *   *_prepared            as kde_exact, kde_exact_backward, kde_exact_with_grad,
+ *                         deann_query, deann_query_with_grad with
  *                         the same arguments (X is still read: the exact
  *                         re-evaluations and the gathers use its float32 rows),
  *                         plus the prepared set and its size.  Results are
  *                         bitwise those of the unprepared call.
  * The prepared set must come from deann_prepare with the same X, n, d and
- * precision (DEANN_FP32 for kde_exact_with_grad_prepared, and for
- * kde_exact_prepared with DEANN_FP32_SPLIT) and the
+ * precision (DEANN_FP32 for kde_exact_backward_prepared and
+ * kde_exact_with_grad_prepared, and for kde_exact_prepared with
+ * DEANN_FP32_SPLIT) and the
  * same centring option; only its size is checked (DEANN_EWORKSPACE when it is
  * too small for n, d and the precision).  It is read, never written, by the
  * query calls, so several streams may share it; the workspaces stay per call.
@@ -215,6 +216,12 @@ deann_status deann_query_prepared(const void* prepared, size_t prepared_bytes, c
                                   uint64_t query_offset, uint64_t word2,
                                   deann_precision precision, double* out, int32_t* nn_idx,
                                   int32_t* sample_idx, void* ws, size_t ws_bytes, void* stream);
+deann_status kde_exact_backward_prepared(const void* prepared, size_t prepared_bytes,
+                                         const float* X, int64_t n, const float* Y, int64_t q,
+                                         int64_t d, double h, deann_kernel kernel,
+                                         deann_precision precision, const double* grad_out,
+                                         float* grad_Y, double* grad_h, void* ws,
+                                         size_t ws_bytes, void* stream);
 deann_status kde_exact_with_grad_prepared(const void* prepared, size_t prepared_bytes,
                                           const float* X, int64_t n, const float* Y, int64_t q,
                                           int64_t d, double h, deann_kernel kernel,

@@ -22,7 +22,8 @@ EXPORTS = (
     "kde_exact_workspace", "kde_exact",
     "deann_query_workspace", "deann_query",
     "deann_query_with_grad_workspace", "deann_query_with_grad",
-    "deann_prepared_bytes", "deann_prepare", "kde_exact_prepared", "kde_exact_with_grad_prepared",
+    "deann_prepared_bytes", "deann_prepare", "kde_exact_prepared", "kde_exact_backward_prepared",
+    "kde_exact_with_grad_prepared",
     "deann_query_prepared", "deann_query_with_grad_prepared",
     "deann_query_permuted_workspace", "deann_query_permuted",
     "deann_perm_index_bytes", "deann_perm_index_create", "deann_query_permuted_index",
@@ -163,6 +164,8 @@ def load(path: str = LIB_PATH):
     lib.deann_prepare.argtypes = [_vp, _i64, _i64, _int, _vp, _sz, _vp]
     lib.kde_exact_prepared.restype = _int
     lib.kde_exact_prepared.argtypes = [_vp, _sz] + lib.kde_exact.argtypes
+    lib.kde_exact_backward_prepared.restype = _int
+    lib.kde_exact_backward_prepared.argtypes = [_vp, _sz] + lib.kde_exact_backward.argtypes
     lib.kde_exact_with_grad_prepared.restype = _int
     lib.kde_exact_with_grad_prepared.argtypes = [_vp, _sz] + lib.kde_exact_with_grad.argtypes
     lib.deann_query_prepared.restype = _int

@@ -271,9 +271,11 @@ def deann_query_backward(X, Y, h, k, m, nn_idx, sample_idx, grad_out, kernel="ga
 
 
 def kde_exact_backward(X, Y, h, grad_out, kernel="gaussian", need_grad_y: bool = True,
-                       need_grad_h: bool = True, precision="fp32"):
+                       need_grad_h: bool = True, precision="fp32",
+                       prepared: Prepared | None = None):
     """(grad_Y float32 [q,d] or None, grad_h float64 [1] or None) of kde_exact;
-    precision "fp32" or "fp32_split" (distance product from bfloat16 parts)."""
+    precision "fp32" or "fp32_split" (distance product from bfloat16 parts);
+    `prepared`: an FP32 set of the same X."""
     _check_xy(X, Y)
     lib = _lib.load()
     n, d = X.shape
@@ -284,9 +286,12 @@ def kde_exact_backward(X, Y, h, grad_out, kernel="gaussian", need_grad_y: bool =
     gh = torch.empty(1, dtype=torch.float64, device=dev) if need_grad_h else None
     p = precision_id(precision)
     ws = _workspace(lib.kde_exact_backward_workspace(n, q, d, p), dev)
-    _lib.check(lib.kde_exact_backward(
-        X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), p, grad_out.data_ptr(),
-        _ptr(gy), _ptr(gh), ws.data_ptr(), ws.numel(), _stream(dev)))
+    args = (X.data_ptr(), n, Y.data_ptr(), q, d, float(h), kernel_id(kernel), p,
+            grad_out.data_ptr(), _ptr(gy), _ptr(gh), ws.data_ptr(), ws.numel(), _stream(dev))
+    if prepared is None:
+        _lib.check(lib.kde_exact_backward(*args))
+    else:
+        _lib.check(lib.kde_exact_backward_prepared(*prepared.args(X, _lib.FP32), *args))
     return gy, gh
 
 

@@ -16,14 +16,15 @@ def _h_value(h) -> float:
 
 
 class ExactKDE(torch.autograd.Function):
-    """out = exact KDE of Y against X; differentiable in Y and h (FP32 operands)."""
+    """out = exact KDE of Y against X; differentiable in Y and h (FP32 operands).
+    `prepared`: an FP32 prepared set of X (api.prepare), used by both passes."""
 
     @staticmethod
-    def forward(ctx, Y, h, X, kernel="gaussian"):
+    def forward(ctx, Y, h, X, kernel="gaussian", prepared=None):
         hv = _h_value(h)
-        out = api.kde_exact(X, Y.detach().contiguous(), hv, kernel, "fp32")
+        out = api.kde_exact(X, Y.detach().contiguous(), hv, kernel, "fp32", prepared=prepared)
         ctx.save_for_backward(X, Y)
-        ctx.hv, ctx.kernel = hv, kernel
+        ctx.hv, ctx.kernel, ctx.prepared = hv, kernel, prepared
         ctx.h_is_tensor = isinstance(h, torch.Tensor)
         ctx.h_device = h.device if ctx.h_is_tensor else None
         return out
@@ -33,9 +34,10 @@ class ExactKDE(torch.autograd.Function):
         X, Y = ctx.saved_tensors
         need_y, need_h = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         gy, gh = api.kde_exact_backward(X, Y.detach().contiguous(), ctx.hv, grad_out, ctx.kernel,
-                                        need_y, need_h and ctx.h_is_tensor)
+                                        need_y, need_h and ctx.h_is_tensor,
+                                        prepared=ctx.prepared)
         gh_out = gh.reshape(()).to(ctx.h_device) if gh is not None else None
-        return gy, gh_out, None, None
+        return gy, gh_out, None, None, None
 
 
 class DeannKDE(torch.autograd.Function):
@@ -43,11 +45,11 @@ class DeannKDE(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, Y, h, X, k, m, kernel="gaussian", seed=0, query_offset=0, word2=0,
-                precision="fp32", start=None, index=None):
+                precision="fp32", start=None, index=None, prepared=None):
         hv = _h_value(h)
         if start is None:   # draws with repetition (Algorithm 1)
             out, nn, sm = api.deann_query(X, Y.detach().contiguous(), hv, k, m, kernel, seed,
-                                          query_offset, word2, precision)
+                                          query_offset, word2, precision, prepared=prepared)
         else:               # permuted random sampling from running index `start`
             out, nn, sm = api.deann_query_permuted(X, Y.detach().contiguous(), hv, k, m, kernel,
                                                    seed, start, precision, index=index)
@@ -65,20 +67,22 @@ class DeannKDE(torch.autograd.Function):
         gy, gh = api.deann_query_backward(X, Y.detach().contiguous(), ctx.hv, ctx.k, ctx.m, nn, sm,
                                           grad_out, ctx.kernel, need_y, need_h and ctx.h_is_tensor)
         gh_out = gh.reshape(()).to(ctx.h_device) if gh is not None else None
-        return (gy, gh_out) + (None,) * 10
+        return (gy, gh_out) + (None,) * 11
 
 
-def exact_kde(Y, h, X, kernel="gaussian"):
-    return ExactKDE.apply(Y, h, X, kernel)
+def exact_kde(Y, h, X, kernel="gaussian", prepared=None):
+    """Exact KDE with autograd; `prepared`: an FP32 prepared set of X."""
+    return ExactKDE.apply(Y, h, X, kernel, prepared)
 
 
 def deann_kde(Y, h, X, k, m, kernel="gaussian", seed=0, query_offset=0, word2=0,
-              precision="fp32", start=None, index=None):
+              precision="fp32", start=None, index=None, prepared=None):
     """DEANN estimate with autograd; start (not None) selects permuted random
     sampling from that running index instead of draws with repetition, with
-    the rows of a PermutedIndex when one is given."""
+    the rows of a PermutedIndex when one is given; `prepared`: a prepared set
+    of X in `precision` (draws with repetition only)."""
     out, _, _ = DeannKDE.apply(Y, h, X, k, m, kernel, seed, query_offset, word2, precision, start,
-                               index)
+                               index, prepared)
     return out
 
 

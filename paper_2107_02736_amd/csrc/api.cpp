@@ -1035,14 +1035,20 @@ size_t kde_exact_backward_workspace(int64_t n, int64_t q, int64_t d, deann_preci
   return (size_t)plan_kde_bwd(nullptr, n, q, d, precision).bytes;
 }
 
-deann_status kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
-                       deann_kernel kernel, deann_precision precision, const double* grad_out, float* grad_Y,
-                       double* grad_h, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+static deann_status kde_exact_backward_impl(const void* prepared, size_t prepared_bytes,
+                                            const float* X, int64_t n, const float* Y, int64_t q,
+                                            int64_t d, double h, int kernel, int precision,
+                                            const double* grad_out, float* grad_Y, double* grad_h,
+                                            void* ws, size_t ws_bytes, void* stream) {
   deann_status st = check_common(X, n, Y, q, d, h, kernel);
   if (st != DEANN_OK) return st;
   if (bad_exact_grad_prec(precision))
     return fail(DEANN_EINVAL, "precision must be DEANN_FP32 or DEANN_FP32_SPLIT");
   if (d > 128) return fail(DEANN_EUNSUPPORTED, "kde_exact_backward supports d <= 128");
+  if (prepared && (st = check_prepared(prepared, prepared_bytes, n, d, DEANN_FP32)) != DEANN_OK)
+    return st;
   if (q == 0) return DEANN_OK;
   if (!grad_out) return fail(DEANN_EINVAL, "grad_out is NULL");
   const int64_t need = plan_kde_bwd(nullptr, n, q, d, precision).bytes;
@@ -1052,7 +1058,8 @@ deann_status kde_exact_backward(const float* X, int64_t n, const float* Y, int64
   KdeBwdPlan P = plan_kde_bwd(align_ws(ws), n, q, d, precision);
   record_last(P.cert.count, nullptr, q);
   SplitRows sp;
-  hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s);
+  const Prep pre = prepared ? prepared_of(prepared, n, d, DEANN_FP32) : Prep{};
+  hipError_t e = prep_exact_grad(P, X, n, Y, q, d, precision, sp, s, prepared ? &pre : nullptr);
   if (e != hipSuccess) return hip_fail(e, "prep");
   TileProblem tp = make_problem(P.prep, n, q, DEANN_FP32, bwd_split_target(P.prep.dp));
   // one 8-wave workgroup per CU: the query tiles of the split-major order
@@ -1063,6 +1070,26 @@ deann_status kde_exact_backward(const float* X, int64_t n, const float* Y, int64
                           cert_args(P.cert, P.prep, sp.X ? P.dps + 4 : P.prep.dp, sp.X != nullptr));
   if (e != hipSuccess) return hip_fail(e, "kde backward");
   return DEANN_OK;
+}
+
+extern "C" {
+
+deann_status kde_exact_backward(const float* X, int64_t n, const float* Y, int64_t q, int64_t d, double h,
+                       deann_kernel kernel, deann_precision precision, const double* grad_out, float* grad_Y,
+                       double* grad_h, void* ws, size_t ws_bytes, void* stream) {
+  return kde_exact_backward_impl(nullptr, 0, X, n, Y, q, d, h, kernel, precision, grad_out,
+                                 grad_Y, grad_h, ws, ws_bytes, stream);
+}
+
+deann_status kde_exact_backward_prepared(const void* prepared, size_t prepared_bytes,
+                                         const float* X, int64_t n, const float* Y, int64_t q,
+                                         int64_t d, double h, deann_kernel kernel,
+                                         deann_precision precision, const double* grad_out,
+                                         float* grad_Y, double* grad_h, void* ws,
+                                         size_t ws_bytes, void* stream) {
+  if (!prepared) return fail(DEANN_EINVAL, "prepared is NULL");
+  return kde_exact_backward_impl(prepared, prepared_bytes, X, n, Y, q, d, h, kernel, precision,
+                                 grad_out, grad_Y, grad_h, ws, ws_bytes, stream);
 }
 
 deann_status mean_shift_update(const float* Y, const float* grad_Y, const double* density, int64_t q,

@@ -106,3 +106,21 @@ def test_prepared_mismatch_is_refused(data, dev):
         dk.deann_query(Xd, Y1d, 9.0, 40, 100, precision="fp32", prepared=pre)
     with pytest.raises(ValueError):
         dk.kde_exact(Xd, Y1d, 9.0, precision="fp32", prepared=pre)
+
+
+def test_autograd_with_prepared_sets(data):
+    # the autograd wrappers: values and gradients equal with and without a
+    # prepared set of X
+    import paper_2107_02736_amd as dk
+    X, Y1, Y2, Xd, Y1d, Y2d = data
+    pre32, pre16 = dk.prepare(Xd, "fp32"), dk.prepare(Xd, "bf16")
+    res = []
+    for p32, p16 in ((None, None), (pre32, pre16)):
+        Y = Y2d.clone().requires_grad_(True)
+        h = torch.tensor(9.0, dtype=torch.float64, requires_grad=True)
+        v = dk.exact_kde(Y, h, Xd, prepared=p32).sum() + \
+            dk.deann_kde(Y, h, Xd, 40, 100, precision="bf16", prepared=p16).sum()
+        v.backward()
+        res.append((v.detach(), Y.grad.clone(), h.grad.clone()))
+    for u, w in zip(*res):
+        assert torch.equal(u, w)

@@ -534,6 +534,24 @@ def run_workload(args, workload, with_cpu):
     torch.cuda.synchronize()
     ms_step_prepared = (time.perf_counter() - t0p) * 1e3 / args.steps
     prepared_same = bool(torch.equal(mu_p, mu) and torch.equal(est_p, est))
+
+    # serving: small query batches against the fixed data set, DEANN (BF16
+    # scan, estimate and gradient) per batch with and without the prepared set
+    serving = {}
+    for qb in (128, 1024):
+        Yb = Yd[:qb].contiguous()
+        for name, kw in (("prepared", {"prepared": pre16}), ("unprepared", {})):
+            dk.deann_query_with_grad(Xd, Yb, h, K_NN, M_SAMPLES, KERNEL, seed=0, precision="bf16",
+                                     **kw)
+            torch.cuda.synchronize()
+            a.record()
+            for _ in range(10):
+                dk.deann_query_with_grad(Xd, Yb, h, K_NN, M_SAMPLES, KERNEL, seed=0,
+                                         precision="bf16", **kw)
+            b.record()
+            torch.cuda.synchronize()
+            ms_b = a.elapsed_time(b) / 10
+            serving[f"q{qb}_{name}"] = {"ms_per_batch": ms_b, "queries_per_s": qb / (ms_b * 1e-3)}
     del pre32, pre16
 
     # exact KDE with BF16 operands (not part of the step): speed and its error
@@ -690,6 +708,9 @@ def run_workload(args, workload, with_cpu):
                           "note": "the step with X prepared once outside the timed region "
                                   "(deann_prepare: FP32 set for the exact KDE, BF16 set for "
                                   "DEANN); queries prepared per call"},
+        "serving_deann_bf16_with_grad": dict(serving, note="batches of the first 128 / 1024 "
+                                             "queries, each call timed alone (HIP events, 10 "
+                                             "calls); with and without the prepared BF16 set"),
         "mean_shift": {"steps": MEAN_SHIFT_STEPS,
                        "exact_ms": ms_shift_exact,
                        "exact_query_steps_per_s": (q * MEAN_SHIFT_STEPS / (ms_shift_exact * 1e-3)

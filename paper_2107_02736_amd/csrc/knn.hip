@@ -1173,7 +1173,12 @@ hipError_t launch_knn(int prec, const TileProblem& p, const TileProblem& pc, con
     TileProblem ps = pc;
     ps.tstride = seed_stride(pc.ntiles, b.seed_stride);
     ps.ntiles = (pc.ntiles + ps.tstride - 1) / ps.tstride;
+    // at most as many splits as keep a query's cells (CELLS per split) within
+    // the refinement's in-register selection (4096 cells): small query batches
+    // would otherwise get thousands of splits and a slow merge of their cells
+    constexpr int64_t kMaxSeedSplits = (WG / 64) * 64 * 16 / CELLS;
     ps.splits = pc.splits < ps.ntiles ? pc.splits : ps.ntiles;
+    if (ps.splits > kMaxSeedSplits) ps.splits = kMaxSeedSplits;
     ps.map = make_tile_map(ps.qtiles, ps.splits, pc.map.group);
     const dim3 g((unsigned)ps.map.grid), blk(WG);
     const int eng = tile_engine<__bf16>(ps.ld_bytes);

@@ -245,3 +245,27 @@ def test_backward_rejects_bad_index_tensors(c1):
             dk.deann_query_backward(Xd, Yd, 2.0, 5, 7, bad_nn, bad_sm, g)
     with pytest.raises(ValueError):
         dk.deann_query_backward(Xd, Yd, 2.0, 5, 7, nn, sm, g[:-1])
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_small_batch_with_capped_seed_splits(prec):
+    # n = 200 000 rows and one query tile: the candidate pass's split count is
+    # capped (128 splits, 4096 cells per query) below the second pass's; the
+    # neighbours, draws and estimates equal the oracle's and those of the same
+    # queries inside a batch of 1024
+    import paper_2107_02736_amd as dk
+    dev = device()
+    spec, X, Y = synth.workload(WL, n=200_000, q=1024)
+    Xd, Yd = to_dev(X, dev), to_dev(Y, dev)
+    h, k, m = bandwidth(WL, "gaussian"), 50, 100
+    big = [t.cpu().numpy() for t in dk.deann_query(Xd, Yd, h, k, m, seed=4, precision=prec)]
+    small = [t.cpu().numpy() for t in dk.deann_query(Xd, Yd[:64].contiguous(), h, k, m, seed=4,
+                                                     precision=prec)]
+    for a, b in zip(small, big):
+        assert np.array_equal(a, b[:64])
+    out, nn, sm = small
+    for j in range(0, 64, 9):
+        est, nn_ref, s_ref = oracle.deann_estimate(X, Y[j], h, GAUSSIAN, k, m, 4, j)
+        assert np.array_equal(nn[j], nn_ref), j
+        assert np.array_equal(sm[j], s_ref), j
+        assert abs(out[j] - est) <= 1e-12 * max(est, 1e-300), j

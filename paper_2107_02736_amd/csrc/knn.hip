@@ -1566,19 +1566,31 @@ ivf_exhaustive_kernel(RefineArgs a, KnnBuffers b, IvfRefine v, int32_t* __restri
   ExhaustiveTop top(k, SORT_CAP);
   for (int64_t r0 = 0; r0 < R; r0 += EXH_CHUNK) {
     const int64_t r1 = r0 + EXH_CHUNK < R ? r0 + EXH_CHUNK : R;
-    for (int64_t r = r0 + g; r < r1; r += WG / 16) {
-      int64_t id = r;
-      if (st == 2) {   // r-th row of the inspected clusters
-        int64_t lo = 0, hi = np;   // cum[lo] <= r < cum[hi]
-        while (hi - lo > 1) {
-          const int64_t mid = (lo + hi) >> 1;
-          if (cum[mid] <= r) lo = mid; else hi = mid;
+    // four rows per 16-lane group at a time (their loads in flight together)
+    for (int64_t rb = r0 + g; rb < r1; rb += 4 * (WG / 16)) {
+      int64_t rr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = rb + i * (WG / 16);
+        int64_t id = r < r1 ? r : -1;
+        if (st == 2 && r < r1) {   // r-th row of the inspected clusters
+          int64_t lo = 0, hi = np;   // cum[lo] <= r < cum[hi]
+          while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (cum[mid] <= r) lo = mid; else hi = mid;
+          }
+          const int32_t l = v.probe[qi * v.kp + lo];
+          id = v.ids[v.off[l] + (r - cum[lo])];
         }
-        const int32_t l = v.probe[qi * v.kp + lo];
-        id = v.ids[v.off[l] + (r - cum[lo])];
+        rr[i] = id;
       }
-      const double d2 = group16_d2(a.X, id, a.d, ys, l16);
-      if (l16 == 0) top.offer(__builtin_bit_cast(uint64_t, d2), (uint32_t)id, dkey, didx, &fill_s);
+      double d2[4];
+      group16_d2_4(a.X, rr, a.d, ys, l16, d2);
+      if (l16 == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (rr[i] >= 0)
+            top.offer(__builtin_bit_cast(uint64_t, d2[i]), (uint32_t)rr[i], dkey, didx, &fill_s);
     }
     top.settle(dkey, didx, &fill_s, r1 == R);
   }

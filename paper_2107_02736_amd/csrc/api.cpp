@@ -164,8 +164,13 @@ double key_scale(int64_t dp) {
   return 2.0 * gamma + 16.0 * u;
 }
 
+// Data splits per query tile for a sweep of `target` workgroups, at most 512:
+// a batch of one query tile still fills the GPU (two workgroups per CU), and
+// the per-query reductions over the splits stay short.
 int64_t choose_splits(int64_t qtiles, int64_t ntiles, int64_t target) {
+  constexpr int64_t kMaxSplits = 512;
   int64_t s = target / (qtiles > 0 ? qtiles : 1);
+  if (s > kMaxSplits) s = kMaxSplits;
   if (s < 1) s = 1;
   if (s > ntiles) s = ntiles;
   return s;

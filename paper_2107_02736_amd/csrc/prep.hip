@@ -94,18 +94,43 @@ __global__ void __launch_bounds__(WG) prep_rows_kernel(const float* __restrict__
   }
   const float* in = src + row * d;
   double nn = 0.0, ee = 0.0;
-  for (int64_t t = lane; t < dp; t += 64) {
-    if (t < d) {
-      const float v = in[t];
-      const T r = to_elem<T>(v - c[t]);
-      out[t] = r;
-      const double rd = (double)(float)r;
-      nn += rd * rd;
-      const double exact = (double)v - (double)c[t];   // exact in FP64
-      const double dlt = rd - exact;
-      ee += dlt * dlt;
-    } else {
-      out[t] = to_elem<T>(0.f);
+  if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+    // four consecutive coordinates per lane and step (16-byte loads; dp and d
+    // are multiples of 4, the centre and the output rows 16- and 8-byte aligned)
+    for (int64_t t = 4 * lane; t < dp; t += 256) {
+      T r[4];
+      if (t < d) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(in + t);
+        const f32x4 cc = *reinterpret_cast<const f32x4*>(c + t);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          r[k] = to_elem<T>(v[k] - cc[k]);
+          const double rd = (double)(float)r[k];
+          nn += rd * rd;
+          const double dlt = rd - ((double)v[k] - (double)cc[k]);   // exact in FP64
+          ee += dlt * dlt;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = to_elem<T>(0.f);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) out[t + k] = r[k];
+    }
+  } else {
+    for (int64_t t = lane; t < dp; t += 64) {
+      if (t < d) {
+        const float v = in[t];
+        const T r = to_elem<T>(v - c[t]);
+        out[t] = r;
+        const double rd = (double)(float)r;
+        nn += rd * rd;
+        const double exact = (double)v - (double)c[t];   // exact in FP64
+        const double dlt = rd - exact;
+        ee += dlt * dlt;
+      } else {
+        out[t] = to_elem<T>(0.f);
+      }
     }
   }
   nn = wave_sum(nn);

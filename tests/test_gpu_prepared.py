@@ -124,3 +124,22 @@ def test_autograd_with_prepared_sets(data):
         res.append((v.detach(), Y.grad.clone(), h.grad.clone()))
     for u, w in zip(*res):
         assert torch.equal(u, w)
+
+
+@pytest.mark.parametrize("kern", ["gaussian", "exponential"])
+def test_prepared_degenerate_k_and_empty_batches(data, kern):
+    # k = 0 (plain random sampling), k = n (exact sum) and q = 0 with a prepared
+    # set: the same results as the unprepared calls
+    import paper_2107_02736_amd as dk
+    X, Y1, Y2, Xd, Y1d, Y2d = data
+    n = X.shape[0]
+    pre = dk.prepare(Xd, "bf16")
+    for k, m in ((0, 64), (n, 0), (7, 0)):
+        a = dk.deann_query_with_grad(Xd, Y2d, 9.0, k, m, kern, seed=5, precision="bf16")
+        b = dk.deann_query_with_grad(Xd, Y2d, 9.0, k, m, kern, seed=5, precision="bf16",
+                                     prepared=pre)
+        for u, v in zip(a, b):
+            assert (u is None and v is None) or torch.equal(u, v), (k, m)
+    empty = Y2d[:0]
+    out, _, _ = dk.deann_query(Xd, empty, 9.0, 7, 5, kern, precision="bf16", prepared=pre)
+    assert out.numel() == 0

@@ -682,18 +682,21 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
   const int64_t t0 = split * p.ntiles / p.splits, t1 = (split + 1) * p.ntiles / p.splits;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wq = wave >> 1, wn = wave & 1;
-  // key norms of the lane's 16 query rows (loop invariant, in registers) and
-  // the thresholds per query row (-inf: no second pass for that query),
-  // published by the first barrier of the sweep
-  float ykr[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) ykr[i][r] = p.yknorm[qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r];
-  __shared__ float ths[BQ];
+  // A column hits query row r when key = xk + yk - 2 x.y <= th_r.  The sweep
+  // tests xk - 2 x.y (one fma) against tq_r = th_r - yk_r (one subtraction
+  // per row, once): round-to-nearest is monotone, so whenever the exact key
+  // is <= th_r the rounded sides compare the same way, and the test admits
+  // every column the key bound requires.  th_r is -inf for a query without a
+  // second pass and +inf for one that collects every point.  tq and the key
+  // norms (for the key codes of the hits) of the tile's rows sit in LDS,
+  // published by the first barrier of the sweep.
+  __shared__ float tqs[BQ], yks[BQ];
   if (threadIdx.x < BQ) {
     const int64_t row = qt * BQ + threadIdx.x;
-    ths[threadIdx.x] = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
+    const float th = (row < p.q && b.status[row] == 1) ? b.thr2[row] : -__builtin_inff();
+    const float yk = p.yknorm[row];
+    tqs[threadIdx.x] = th == __builtin_inff() ? th : th - yk;
+    yks[threadIdx.x] = yk;
   }
   // Hits are staged per wave in LDS, (query row in the tile) << 57 | (key code
   // >> 7) << 32 | column, and appended to the global lists in bulk, so a wave
@@ -767,11 +770,10 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float yk = ykr[i][r];
-        float m = __builtin_fmaf(-2.f, acc[i][0][r], yk + xk[0]);
+        float m = __builtin_fmaf(-2.f, acc[i][0][r], xk[0]);
 #pragma unroll
-        for (int j = 1; j < 4; ++j) m = fminf(m, __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]));
-        hit |= m <= ths[wq * 64 + i * 16 + 4 * (lane >> 4) + r] ? 1u << (i * 4 + r) : 0u;
+        for (int j = 1; j < 4; ++j) m = fminf(m, __builtin_fmaf(-2.f, acc[i][j][r], xk[j]));
+        hit |= m <= tqs[wq * 64 + i * 16 + 4 * (lane >> 4) + r] ? 1u << (i * 4 + r) : 0u;
       }
     if (hit) {   // rare: append the hits, visiting only the rows that have one
 #pragma unroll
@@ -780,13 +782,16 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
         for (int r = 0; r < 4; ++r) {
           if (!(hit & (1u << (i * 4 + r)))) continue;
           const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
-          const float yk = ykr[i][r], th = ths[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
+          const float yk = yks[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
+          const float tq = tqs[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
-            const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]);
-            if (col < p.n && key <= th) {
-              const uint32_t code = float_key(key);
+            const float part = __builtin_fmaf(-2.f, acc[i][j][r], xk[j]);
+            if (col < p.n && part <= tq) {
+              // part + yk: two roundings, as fl(xk + yk) - 2 x.y has, within
+              // the slack of the pre-scaled norms, so still a lower bound
+              const uint32_t code = float_key(part + yk);
               const int e = atomicAdd(&nst[wave], 1);
               if (e < COLLECT_STAGE)
                 stage[wave][e] = ((uint64_t)(row - qt * BQ) << 57) | ((uint64_t)(code >> 7) << 32) |

@@ -380,12 +380,8 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
   // packed into its two low mantissa bits so that one min tracks both, and
   // the tile it came from.  The packing perturbs keys by at most 3 ulp; the
   // candidates only seed the second pass, which alone decides the result.
-  // key norms of the lane's 16 query rows, loop invariant
-  float ykr[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) ykr[i][r] = p.yknorm[qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r];
+  // The sweep tracks xk - 2 x.y; the query's key norm, the same for the whole
+  // row, is added once per cell at the end.
   float best[4][4];
   int32_t btile[4][4];
 #pragma unroll
@@ -440,12 +436,11 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float yk = ykr[i][r];
         float m = __builtin_inff();
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float key = __builtin_fmaf(-2.f, acc[i][j][r], yk + xk[j]);
-          m = fminf(m, __uint_as_float((__float_as_uint(key) & ~3u) | (uint32_t)j));
+          const float part = __builtin_fmaf(-2.f, acc[i][j][r], xk[j]);
+          m = fminf(m, __uint_as_float((__float_as_uint(part) & ~3u) | (uint32_t)j));
         }
         const bool better = m < best[i][r];
         best[i][r] = better ? m : best[i][r];
@@ -461,7 +456,7 @@ knn_cand_kernel(TileProblem p, uint64_t* __restrict__ cand, int32_t* __restrict_
                           (int64_t)(__float_as_uint(best[i][r]) & 3u) * 16 + (lane & 15);
       const uint64_t v = (btile[i][r] < 0 || col >= p.n)
                              ? ~0ull
-                             : ((uint64_t)float_key(best[i][r]) << 32) | (uint64_t)col;
+                             : ((uint64_t)float_key(best[i][r] + p.yknorm[row]) << 32) | (uint64_t)col;
       cand[(split * p.qp + row) * CELLS + wn * 16 + (lane & 15)] = v;
     }
   if (threadIdx.x < BQ) cand_cnt[split * p.qp + qt * BQ + threadIdx.x] = CELLS;

@@ -758,9 +758,9 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
       const int64_t col = t * BN + wn * 64 + j * 16 + (lane & 15);
       xk[j] = col < p.n ? xks[nb][wn * 64 + j * 16 + (lane & 15)] : __builtin_inff();
     }
-    // one bit per query row (i, r) of this lane that has a hit in this tile:
-    // some key of the row is <= its threshold
-    uint32_t hit = 0;
+    // per query row (i, r): the lanes of the wave whose row has a hit in this
+    // tile (some key of the row is <= its threshold), as a wave-wide mask
+    uint64_t hitm[4][4], any = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -768,14 +768,15 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
         float m = __builtin_fmaf(-2.f, acc[i][0][r], xk[0]);
 #pragma unroll
         for (int j = 1; j < 4; ++j) m = fminf(m, __builtin_fmaf(-2.f, acc[i][j][r], xk[j]));
-        hit |= m <= tqs[wq * 64 + i * 16 + 4 * (lane >> 4) + r] ? 1u << (i * 4 + r) : 0u;
+        hitm[i][r] = __builtin_amdgcn_ballot_w64(m <= tqs[wq * 64 + i * 16 + 4 * (lane >> 4) + r]);
+        any |= hitm[i][r];
       }
-    if (hit) {   // rare: append the hits, visiting only the rows that have one
+    if (any) {   // append the hits, visiting only the rows where some lane has one
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          if (!(hit & (1u << (i * 4 + r)))) continue;
+          if (!hitm[i][r]) continue;
           const int64_t row = qt * BQ + wq * 64 + i * 16 + 4 * (lane >> 4) + r;
           const float yk = yks[wq * 64 + i * 16 + 4 * (lane >> 4) + r];
           const float tq = tqs[wq * 64 + i * 16 + 4 * (lane >> 4) + r];

@@ -521,7 +521,7 @@ __device__ void cells_wave_select(const uint64_t* __restrict__ cand, int64_t qp,
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(WG)
+__global__ void __launch_bounds__(WG, 6)
 knn_refine_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   // sort_cap: merge buffer entries, kd_cap >= K1: exact candidates (even counts)
@@ -811,7 +811,7 @@ knn_collect_kernel(TileProblem p, KnnBuffers b) {
 // The refinement sorts them by key, evaluates the K1 smallest exactly, and
 // then only the entries that the k-th of those distances cannot exclude:
 // an entry whose key gives sqrt(key) - E - e_y above it is farther than d_k.
-__global__ void __launch_bounds__(WG)
+__global__ void __launch_bounds__(WG, 6)
 knn_refine2_kernel(RefineArgs a, KnnBuffers b, int32_t* __restrict__ nn_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   // even counts: 8-byte alignment holds; ecap <= cap

@@ -33,8 +33,11 @@ constexpr int K_MAX = 1024;      // largest K1 (and hence k) the refine kernels 
 // ---------------------------------------------------------------------------
 
 // Workgroup bitonic sort of N (power of two) packed uint64 keys, ascending.
-__device__ void block_sort_u64(uint64_t* a, int N) {
-  for (int kk = 2; kk <= N; kk <<= 1) {
+// k0 > 2 skips the levels below k0: it requires the aligned blocks of k0 / 2
+// entries to be sorted already, ascending in even blocks and descending in
+// odd ones (the state the sort itself reaches after those levels).
+__device__ void block_sort_u64(uint64_t* a, int N, int k0 = 2) {
+  for (int kk = k0; kk <= N; kk <<= 1) {
     for (int j = kk >> 1; j > 0; j >>= 1) {
       for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const int ixj = i ^ j;
@@ -486,7 +489,8 @@ struct RefineArgs {
 // empty cells are ~0), sorted ascending, in buf[0 .. min(K1, valid)), and
 // *fill = min(K1, number of non-empty cells).  Wave w takes cells
 // [w * 64 * EPL, (w + 1) * 64 * EPL) and sorts them in registers; K1 <= 64 * EPL
-// of each wave go to buf, which one workgroup sort then orders.  Whole block.
+// of each wave go to buf, where the upper levels of one workgroup bitonic sort
+// merge them.  Whole block.
 template <int EPL>
 __device__ void cells_wave_select(const uint64_t* __restrict__ cand, int64_t qp, int64_t qi,
                                   int64_t cells, int K1, uint64_t* buf, int* fill) {
@@ -502,17 +506,18 @@ __device__ void cells_wave_select(const uint64_t* __restrict__ cand, int64_t qp,
   }
   for (int off = 32; off > 0; off >>= 1) valid += __shfl_xor(valid, off, 64);
   wave_sort_u64<EPL>(v, lane);
+  // each wave's K1 smallest, padded with empty cells to a block of kc (a power
+  // of two), ascending in even waves' blocks and descending in odd ones: the
+  // merge then runs only the bitonic levels above kc
+  const int kc = next_pow2(K1), N = (WG / 64) * kc;
 #pragma unroll
   for (int r = 0; r < EPL; ++r) {
     const int el = lane * EPL + r;
-    if (el < K1) buf[wave * K1 + el] = v[r];
+    if (el < kc) buf[wave * kc + ((wave & 1) ? kc - 1 - el : el)] = el < K1 ? v[r] : ~0ull;
   }
-  // the bitonic sort takes a power of two: pad the waves' lists with empty cells
-  const int M = (WG / 64) * K1, N = next_pow2(M);
-  for (int i = M + threadIdx.x; i < N; i += WG) buf[i] = ~0ull;
   if (lane == 0) valid_w[wave] = valid;
   __syncthreads();
-  block_sort_u64(buf, N);
+  block_sort_u64(buf, N, 2 * kc);
   if (threadIdx.x == 0) {
     int tot = 0;
     for (int w = 0; w < WG / 64; ++w) tot += valid_w[w];
